@@ -1,0 +1,285 @@
+"""FP64 CPU oracle of the ETac tactile step (ctypes wrapper around etac_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the CPU-baseline
+leg of the benchmark are the only callers.  The product path never imports it.
+
+Every function takes the same FP32 input arrays the GPU library receives (see
+the ``scenes`` module for layouts), promotes them exactly to FP64 and returns
+FP64 results.  Parity status of each function is recorded in the test files
+that pin it (tests/test_oracle_*.py).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "etac_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+PHI_SIZE = 17411
+
+
+def build(force=True):
+    """Compile the oracle with gcc: FP64, SSE2 doubles, no FMA contraction, no
+    fast-math, OpenMP over environments."""
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+        return LIB
+    tmp = LIB + ".tmp"
+    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", "-msse2", "-mfpmath=sse", "-Wall", "-Wno-unknown-pragmas",
+           SRC, "-o", tmp, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        _lib = C.CDLL(LIB)
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def num_threads():
+    return int(_load().oracle_num_threads())
+
+
+def _mesh_args(mesh):
+    return (C.c_int(mesh.n_patches), C.c_int(mesh.n_nodes), _i32(mesh.patch_offset),
+            _f64(mesh.pos), _f64(mesh.nrm), _f64(mesh.origin))
+
+
+def _scene_args(scene):
+    return (C.c_int(scene.n_envs), C.c_int(scene.max_obj), _i32(scene.n_obj), _i32(scene.type),
+            _f64(scene.shape), _f64(scene.rot), _f64(scene.trans))
+
+
+def _call(fn, *args):
+    conv = [(_p(a) if isinstance(a, np.ndarray) else a) for a in args]
+    rc = fn(*conv)
+    if rc != 0:
+        raise RuntimeError(f"oracle call failed with {rc}")
+
+
+def contact(mesh, scene):
+    """Contact pass.  Returns contact_obj int8 [E][N], uhat f64 [3][E][N],
+    n_active int32 [E][K]."""
+    lib = _load()
+    K, N, off, pos, nrm, _ = _mesh_args(mesh)
+    E, O, n_obj, typ, shape, rot, trans = _scene_args(scene)
+    cobj = np.empty((E.value, N.value), np.int8)
+    uhat = np.empty((3, E.value, N.value), np.float64)
+    na = np.empty((E.value, K.value), np.int32)
+    _call(lib.oracle_contact, K, N, off, pos, nrm, E, O, n_obj, typ, shape, rot, trans, cobj, uhat, na)
+    return cobj, uhat, na
+
+
+def propagate(mesh, model, contact_obj, uhat, mode=None):
+    """Eqs. 1-2 on given contact results.  uhat may be FP32 or FP64."""
+    lib = _load()
+    K, N, off, pos, nrm, origin = _mesh_args(mesh)
+    cobj = np.ascontiguousarray(contact_obj, dtype=np.int8)
+    E = cobj.shape[0]
+    U = np.empty((3, E, N.value), np.float64)
+    m = model.mode if mode is None else mode
+    _call(lib.oracle_propagate, K, N, off, pos, nrm, origin, C.c_int(E), C.c_int(m),
+          _f64(model.alpha), _f64(model.phi), cobj, _f64(uhat), U)
+    return U
+
+
+def forward(mesh, scene, model, with_sig=False):
+    """Whole step.  Returns dict(u, contact_obj, uhat, n_active[, sig, margin])."""
+    lib = _load()
+    K, N, off, pos, nrm, origin = _mesh_args(mesh)
+    E, O, n_obj, typ, shape, rot, trans = _scene_args(scene)
+    e, n = E.value, N.value
+    U = np.empty((3, e, n), np.float64)
+    cobj = np.empty((e, n), np.int8)
+    uhat = np.empty((3, e, n), np.float64)
+    na = np.empty((e, K.value), np.int32)
+    sig = np.empty(e, np.uint64) if with_sig else None
+    margin = np.empty(e, np.float64) if with_sig else None
+    _call(lib.oracle_forward, K, N, off, pos, nrm, origin, E, O, n_obj, typ, shape, rot, trans,
+          C.c_int(model.mode), _f64(model.alpha), _f64(model.phi), U, cobj, uhat, na,
+          sig if sig is not None else None, margin if margin is not None else None)
+    out = dict(u=U, contact_obj=cobj, uhat=uhat, n_active=na)
+    if with_sig:
+        out.update(sig=sig, margin=margin)
+    return out
+
+
+def propagate_backward(mesh, model, contact_obj, uhat, grad_u):
+    lib = _load()
+    K, N, off, pos, nrm, origin = _mesh_args(mesh)
+    cobj = np.ascontiguousarray(contact_obj, dtype=np.int8)
+    E = cobj.shape[0]
+    guhat = np.empty((3, E, N.value), np.float64)
+    ga = np.empty(K.value, np.float64)
+    gp = np.empty(PHI_SIZE, np.float64)
+    _call(lib.oracle_propagate_backward, K, N, off, pos, nrm, origin, C.c_int(E), C.c_int(model.mode),
+          _f64(model.alpha), _f64(model.phi), cobj, _f64(uhat), _f64(grad_u), guhat, ga, gp)
+    return dict(grad_uhat=guhat, grad_alpha=ga, grad_phi=gp)
+
+
+def contact_backward(mesh, scene, grad_uhat):
+    lib = _load()
+    K, N, off, pos, nrm, _ = _mesh_args(mesh)
+    E, O, n_obj, typ, shape, rot, trans = _scene_args(scene)
+    grot = np.empty((E.value, O.value, 9), np.float64)
+    gt = np.empty((E.value, O.value, 3), np.float64)
+    _call(lib.oracle_contact_backward, K, N, off, pos, nrm, E, O, n_obj, typ, shape, rot, trans,
+          _f64(grad_uhat), grot, gt)
+    return dict(grad_rot=grot, grad_trans=gt)
+
+
+def backward(mesh, scene, model, grad_u):
+    """Adjoint of L = sum(grad_u * U) w.r.t. rot, trans, alpha, phi (and the
+    intermediate dL/du_hat)."""
+    lib = _load()
+    K, N, off, pos, nrm, origin = _mesh_args(mesh)
+    E, O, n_obj, typ, shape, rot, trans = _scene_args(scene)
+    grot = np.empty((E.value, O.value, 9), np.float64)
+    gt = np.empty((E.value, O.value, 3), np.float64)
+    ga = np.empty(K.value, np.float64)
+    gp = np.empty(PHI_SIZE, np.float64)
+    guhat = np.empty((3, E.value, N.value), np.float64)
+    _call(lib.oracle_backward, K, N, off, pos, nrm, origin, E, O, n_obj, typ, shape, rot, trans,
+          C.c_int(model.mode), _f64(model.alpha), _f64(model.phi), _f64(grad_u), grot, gt, ga, gp, guhat)
+    return dict(grad_rot=grot, grad_trans=gt, grad_alpha=ga, grad_phi=gp, grad_uhat=guhat)
+
+
+# ----------------------------------------------------------------------------
+# central finite differences on the FP64 oracle
+# ----------------------------------------------------------------------------
+
+class _F64Scene:
+    """FP64 copy of a scene so that FD perturbations are not rounded to FP32."""
+
+    def __init__(self, s):
+        self.n_obj = s.n_obj.copy()
+        self.type = s.type.copy()
+        self.shape = s.shape.astype(np.float64)
+        self.rot = s.rot.astype(np.float64)
+        self.trans = s.trans.astype(np.float64)
+
+    n_envs = property(lambda self: int(self.n_obj.shape[0]))
+    max_obj = property(lambda self: int(self.type.shape[1]))
+
+
+class _F64Model:
+    def __init__(self, m):
+        self.mode = m.mode
+        self.alpha = m.alpha.astype(np.float64)
+        self.phi = m.phi.astype(np.float64)
+
+
+def skew(w):
+    return np.array([[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]], dtype=np.float64)
+
+
+def expm_so3(w):
+    """Rodrigues' formula for exp([w]_x)."""
+    th = np.linalg.norm(w)
+    if th == 0.0:
+        return np.eye(3)
+    K = skew(w / th)
+    return np.eye(3) + np.sin(th) * K + (1.0 - np.cos(th)) * (K @ K)
+
+
+def loss_and_sig(mesh, scene, model, w):
+    out = forward(mesh, scene, model, with_sig=True)
+    return float(np.sum(out["u"] * w)), out["sig"]
+
+
+def fd_gradients(mesh, scene, model, w, env=0, obj=0, h=1e-4, phi_idx=(), shrink=(1e-5, 1e-6)):
+    """Central differences (L(theta+h) - L(theta-h)) / 2h of L = sum(w * U) in
+    FP64 for: the 3 translations and 3 twist components (R' = exp([+-h e_k]_x) R)
+    of object `obj` in env `env`, alpha of every patch, and the listed phi
+    entries.
+
+    The model is only piecewise smooth: a difference whose two sides take a
+    different discrete decision (active set, winner, face, clamp, ReLU
+    pattern, arg-max) is not a derivative.  Such a difference is retaken with
+    the smaller steps in `shrink`; if every step straddles a decision the
+    result is flagged.  Returns (dict of FD values, ok) where ok is False if
+    any entry stayed flagged."""
+    S = _F64Scene(scene)
+    M = _F64Model(model)
+    ok = True
+    res = {}
+
+    def central(perturb):
+        nonlocal ok
+        for step in (h,) + tuple(shrink):
+            Sp, Mp = _F64Scene(S), _F64Model(M)
+            Sm, Mm = _F64Scene(S), _F64Model(M)
+            perturb(Sp, Mp, step)
+            perturb(Sm, Mm, -step)
+            lp, sp = loss_and_sig(mesh, Sp, Mp, w)
+            lm, sm = loss_and_sig(mesh, Sm, Mm, w)
+            if np.array_equal(sp, sm):
+                return (lp - lm) / (2 * step)
+        ok = False
+        return (lp - lm) / (2 * step)
+
+    def shift_t(c):
+        def f(S_, M_, s):
+            S_.trans[env, obj, c] += s
+        return f
+
+    def twist(c):
+        def f(S_, M_, s):
+            e = np.zeros(3)
+            e[c] = s
+            R = S_.rot[env, obj].reshape(3, 3)
+            S_.rot[env, obj] = (expm_so3(e) @ R).ravel()
+        return f
+
+    def shift_alpha(k):
+        def f(S_, M_, s):
+            M_.alpha[k] += s
+        return f
+
+    def shift_phi(i):
+        def f(S_, M_, s):
+            M_.phi[i] += s
+        return f
+
+    res["trans"] = np.array([central(shift_t(c)) for c in range(3)])
+    res["twist"] = np.array([central(twist(c)) for c in range(3)])
+    res["alpha"] = np.array([central(shift_alpha(k)) for k in range(mesh.n_patches)])
+    res["phi"] = np.array([central(shift_phi(i)) for i in phi_idx])
+    return res, ok
+
+
+def twist_from_grad_rot(grad_rot, R):
+    """dL/dw_k = sum_ab G_ab ([e_k]_x R)_ab for R' = exp([w]_x) R, w -> 0."""
+    G = np.asarray(grad_rot, dtype=np.float64).reshape(3, 3)
+    R = np.asarray(R, dtype=np.float64).reshape(3, 3)
+    out = np.empty(3)
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = 1.0
+        out[k] = np.sum(G * (skew(e) @ R))
+    return out

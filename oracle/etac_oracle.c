@@ -1,0 +1,820 @@
+/*
+ * etac_oracle.c -- plain FP64 CPU oracle of the ETac tactile step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or constant with the GPU library.
+ *
+ * What it computes (ETac, Sec. III-A, "Lightweight Tactile Simulation
+ * Framework"):
+ *   1. contact: nodes of an elastomer patch that lie strictly inside a rigid
+ *      object are "active"; each gets the displacement that moves it to the
+ *      closest point of the object surface (the penalty-style local contact
+ *      displacement u_hat, Sec. III-A "Overview");
+ *   2. decay-based linear propagation (Eq. 1): a passive node i receives
+ *      sum_j exp(-alpha ||p_j - p_i||) u_hat_j over the active nodes j of its
+ *      patch, i.e. Omega U_a with Omega[i,j] = exp(-alpha ||p_j - p_i||);
+ *   3. residual correction Phi (Sec. III-A "Residual Displacement
+ *      Correction"): PointNet encoder on [P, N, U_hat] (n x 9) -> shared MLP ->
+ *      64-d per-node features, max-pool -> 64-d global feature, global MLP,
+ *      broadcast-concatenate -> n x 128, shared-MLP decoder -> n x 3, masked to
+ *      passive nodes;
+ *   4. Eq. 2: U_p = Omega U_a + Phi_p; active nodes keep u_hat.
+ * and the reverse-mode adjoint of all of it with respect to object poses
+ * (R, t), alpha and the network parameters.
+ *
+ * Readings where the paper is silent (all listed in the design notes):
+ *   - contact displacement = closest-point penetration vector; strict inside;
+ *     deepest object wins, lowest index on ties;
+ *   - FP64 predicate evaluated in the fixed order written below, no FMA
+ *     (build with -ffp-contract=off), so masks are reproducible bit for bit;
+ *   - Omega and the max-pool act per patch; alpha is one value per patch;
+ *   - a patch with no active node has U = 0;
+ *   - network widths 9-64-64 | 64 | 64 + [f;g'] 128-64-3, ReLU, linear
+ *     output; input position is p - o_k (o_k: per-patch origin).
+ *
+ * Inputs are FP64 (the Python side promotes the FP32 arrays exactly).
+ * Layouts: pos/nrm [3][N]; uhat/U/grad_u [3][E][N]; contact_obj [E][N];
+ * n_active [E][K]; object arrays [E][O][...]; phi packed as
+ * W1(64x9) b1 W2(64x64) b2 W3(64x64) b3 W4(64x128) b4 W5(3x64) b5.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define NF 64        /* per-node / global feature width */
+#define NIN 9        /* [p - o, n, u_hat] */
+#define PHI_N 17411
+
+enum { O_SPHERE = 0, O_BOX = 1, O_CAPSULE = 2 };
+enum { O_FULL = 0, O_DECAY_ONLY = 1, O_RESIDUAL_ONLY = 2 };
+
+/* ------------------------------------------------------------------------ */
+/* packed network parameters                                                */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const double *W1, *b1, *W2, *b2, *W3, *b3, *W4, *b4, *W5, *b5;
+} net_t;
+
+static net_t net_view(const double *phi) {
+    net_t n;
+    n.W1 = phi;            n.b1 = n.W1 + 64 * 9;
+    n.W2 = n.b1 + 64;      n.b2 = n.W2 + 64 * 64;
+    n.W3 = n.b2 + 64;      n.b3 = n.W3 + 64 * 64;
+    n.W4 = n.b3 + 64;      n.b4 = n.W4 + 64 * 128;
+    n.W5 = n.b4 + 64;      n.b5 = n.W5 + 3 * 64;
+    return n;
+}
+
+/* gradient views share the same packing */
+typedef struct {
+    double *W1, *b1, *W2, *b2, *W3, *b3, *W4, *b4, *W5, *b5;
+} dnet_t;
+
+static dnet_t dnet_view(double *g) {
+    dnet_t n;
+    n.W1 = g;              n.b1 = n.W1 + 64 * 9;
+    n.W2 = n.b1 + 64;      n.b2 = n.W2 + 64 * 64;
+    n.W3 = n.b2 + 64;      n.b3 = n.W3 + 64 * 64;
+    n.W4 = n.b3 + 64;      n.b4 = n.W4 + 64 * 128;
+    n.W5 = n.b4 + 64;      n.b5 = n.W5 + 3 * 64;
+    return n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 64-bit FNV-1a fingerprint of discrete decisions (for the FD harness)     */
+/* ------------------------------------------------------------------------ */
+static uint64_t fnv(uint64_t h, int64_t v) {
+    for (int b = 0; b < 8; ++b) {
+        h ^= (uint64_t)((v >> (8 * b)) & 0xff);
+        h *= 1099511628211ULL;
+    }
+    return h;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 1. contact: point vs rigid primitive                                     */
+/* ------------------------------------------------------------------------ */
+/* Discrete outcome of one node-object test. */
+typedef struct {
+    int inside;
+    double depth;     /* penetration depth (distance to the surface) */
+    double u[3];      /* displacement to the closest surface point */
+    int face;         /* box: face axis; capsule: 1 if the axial clamp is active */
+    int sign;         /* box: +1/-1 side of the face */
+    int degenerate;   /* sphere/capsule: node on the centre point/axis */
+} hit_t;
+
+/*
+ * Penetration of point p (normal nrm) into one object.  The frame transform
+ * and the inside tests use this exact operation order in FP64 with
+ * round-to-nearest-even and no fused multiply-add:
+ *   d_c = p_c - t_c
+ *   q_c = (R[0][c] d_0 + R[1][c] d_1) + R[2][c] d_2          (q = R^T d)
+ *   sphere : s = (d_0 d_0 + d_1 d_1) + d_2 d_2,   inside <=> s < r r
+ *   box    : inside <=> |q_c| < h_c for c = 0,1,2
+ *   capsule: z = clamp(q_2, -L, L), v = (q_0, q_1, q_2 - z),
+ *            s = (v_0 v_0 + v_1 v_1) + v_2 v_2,   inside <=> s < r r
+ * The closest surface point then gives u_hat:
+ *   sphere : depth = r - sqrt(s), u = (depth / sqrt(s)) d
+ *   box    : face c* = argmin_c (h_c - |q_c|) (lowest c on ties),
+ *            sign = +1 if q_c* >= 0 else -1, depth = h_c* - |q_c*|,
+ *            u = (sign depth) R[:, c*]
+ *   capsule: depth = r - sqrt(s), u = (depth / sqrt(s)) (R v)
+ * A node exactly on the centre point (sphere) or on the axis segment
+ * (capsule) has no unique closest point; it takes depth r and u = -r n.
+ */
+static hit_t penetrate(int type, const double *shape, const double *R, const double *t,
+                       const double p[3], const double nrm[3]) {
+    hit_t h;
+    memset(&h, 0, sizeof h);
+    double d0 = p[0] - t[0], d1 = p[1] - t[1], d2 = p[2] - t[2];
+    if (type == O_SPHERE) {
+        double r = shape[0];
+        double s = (d0 * d0 + d1 * d1) + d2 * d2;
+        if (!(s < r * r)) return h;
+        h.inside = 1;
+        if (s == 0.0) {
+            h.degenerate = 1;
+            h.depth = r;
+            for (int a = 0; a < 3; ++a) h.u[a] = -r * nrm[a];
+            return h;
+        }
+        double l = sqrt(s);
+        h.depth = r - l;
+        double sc = h.depth / l;
+        h.u[0] = sc * d0; h.u[1] = sc * d1; h.u[2] = sc * d2;
+        return h;
+    }
+    double q[3];
+    for (int c = 0; c < 3; ++c) q[c] = (R[0 * 3 + c] * d0 + R[1 * 3 + c] * d1) + R[2 * 3 + c] * d2;
+    if (type == O_BOX) {
+        for (int c = 0; c < 3; ++c)
+            if (!(fabs(q[c]) < shape[c])) return h;
+        h.inside = 1;
+        int cs = 0;
+        double best = shape[0] - fabs(q[0]);
+        for (int c = 1; c < 3; ++c) {
+            double sl = shape[c] - fabs(q[c]);
+            if (sl < best) { best = sl; cs = c; }
+        }
+        h.face = cs;
+        h.sign = (q[cs] >= 0.0) ? 1 : -1;
+        h.depth = best;
+        double a = (double)h.sign * best;
+        for (int r = 0; r < 3; ++r) h.u[r] = a * R[r * 3 + cs];
+        return h;
+    }
+    /* capsule: radius shape[0], half segment length shape[1] along object z */
+    double r = shape[0], L = shape[1];
+    double z = q[2];
+    int clamped = 0;
+    if (z < -L) { z = -L; clamped = 1; }
+    else if (z > L) { z = L; clamped = 1; }
+    double v0 = q[0], v1 = q[1], v2 = q[2] - z;
+    double s = (v0 * v0 + v1 * v1) + v2 * v2;
+    if (!(s < r * r)) return h;
+    h.inside = 1;
+    h.face = clamped;
+    if (s == 0.0) {
+        h.degenerate = 1;
+        h.depth = r;
+        for (int a = 0; a < 3; ++a) h.u[a] = -r * nrm[a];
+        return h;
+    }
+    double l = sqrt(s);
+    h.depth = r - l;
+    double sc = h.depth / l;
+    for (int a = 0; a < 3; ++a) {
+        double w = (R[a * 3 + 0] * v0 + R[a * 3 + 1] * v1) + R[a * 3 + 2] * v2;
+        h.u[a] = sc * w;
+    }
+    return h;
+}
+
+typedef struct {
+    int K, N;
+    const int32_t *offset;
+    const double *pos, *nrm, *origin;
+    int E, O;
+    const int32_t *n_obj, *type;
+    const double *shape, *rot, *trans;
+} problem_t;
+
+/* Contact for every node of env e.  Several objects: the deepest penetration
+ * wins (union of the objects' signed distance fields), ties to the lowest
+ * object index.  Passive nodes get contact_obj = -1 and u_hat = 0. */
+static void contact_env(const problem_t *P, int e, int8_t *cobj, double *uhat, int32_t *n_active,
+                        uint64_t *sig) {
+    const int N = P->N, E = P->E, O = P->O;
+    for (int k = 0; k < P->K; ++k) n_active[(size_t)e * P->K + k] = 0;
+    for (int k = 0; k < P->K; ++k) {
+        for (int i = P->offset[k]; i < P->offset[k + 1]; ++i) {
+            double p[3] = {P->pos[i], P->pos[N + i], P->pos[2 * N + i]};
+            double n[3] = {P->nrm[i], P->nrm[N + i], P->nrm[2 * N + i]};
+            int best = -1;
+            hit_t bh;
+            memset(&bh, 0, sizeof bh);
+            for (int o = 0; o < P->n_obj[e]; ++o) {
+                size_t eo = (size_t)e * O + o;
+                hit_t h = penetrate(P->type[eo], P->shape + 4 * eo, P->rot + 9 * eo,
+                                    P->trans + 3 * eo, p, n);
+                if (h.inside && (best < 0 || h.depth > bh.depth)) { best = o; bh = h; }
+            }
+            size_t en = (size_t)e * N + i;
+            cobj[en] = (int8_t)best;
+            for (int a = 0; a < 3; ++a) uhat[(size_t)a * E * N + en] = best >= 0 ? bh.u[a] : 0.0;
+            if (best >= 0) n_active[(size_t)e * P->K + k] += 1;
+            if (sig) {
+                *sig = fnv(*sig, best);
+                if (best >= 0) *sig = fnv(fnv(fnv(*sig, bh.face), bh.sign), bh.degenerate);
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* 2./3./4. propagation for one patch of one env                            */
+/* ------------------------------------------------------------------------ */
+static inline double relu(double x) { return x > 0.0 ? x : 0.0; }
+
+/* scratch for one patch (sized for the largest patch) */
+typedef struct {
+    int *act, *pas;
+    double *x;          /* [n][9]   */
+    double *pre1, *h1;  /* [n][64]  */
+    double *pre2, *f;   /* [n][64]  */
+    double *df;         /* [n][64]  */
+    int *argmax;        /* [64]     */
+    double g[NF], pre3[NF], gp[NF];
+} scratch_t;
+
+static scratch_t scratch_new(int nmax) {
+    scratch_t s;
+    s.act = malloc(sizeof(int) * nmax);
+    s.pas = malloc(sizeof(int) * nmax);
+    s.x = malloc(sizeof(double) * nmax * NIN);
+    s.pre1 = malloc(sizeof(double) * nmax * NF);
+    s.h1 = malloc(sizeof(double) * nmax * NF);
+    s.pre2 = malloc(sizeof(double) * nmax * NF);
+    s.f = malloc(sizeof(double) * nmax * NF);
+    s.df = malloc(sizeof(double) * nmax * NF);
+    s.argmax = malloc(sizeof(int) * NF);
+    return s;
+}
+
+static void scratch_free(scratch_t *s) {
+    free(s->act); free(s->pas); free(s->x); free(s->pre1); free(s->h1);
+    free(s->pre2); free(s->f); free(s->df); free(s->argmax);
+}
+
+static int max_patch(const problem_t *P) {
+    int m = 1;
+    for (int k = 0; k < P->K; ++k) {
+        int n = P->offset[k + 1] - P->offset[k];
+        if (n > m) m = n;
+    }
+    return m;
+}
+
+/* Encoder of the residual network for every node of the patch, then the
+ * max-pool over all n nodes (lowest node wins ties) and the global MLP.
+ * Network input x_i = [p_i - o_k, n_i, U_hat_i] with U_hat_i = 0 for passive
+ * nodes. */
+static void phi_encode(const problem_t *P, const net_t *W, int e, int k, const int8_t *cobj,
+                       const double *uhat, scratch_t *S, double *margin, uint64_t *sig) {
+    const int N = P->N, E = P->E;
+    const int o0 = P->offset[k], n = P->offset[k + 1] - o0;
+    for (int li = 0; li < n; ++li) {
+        int i = o0 + li;
+        size_t en = (size_t)e * N + i;
+        double *x = S->x + (size_t)li * NIN;
+        for (int a = 0; a < 3; ++a) {
+            x[a] = P->pos[(size_t)a * N + i] - P->origin[3 * k + a];
+            x[3 + a] = P->nrm[(size_t)a * N + i];
+            x[6 + a] = cobj[en] >= 0 ? uhat[(size_t)a * E * N + en] : 0.0;
+        }
+        double *pre1 = S->pre1 + (size_t)li * NF, *h1 = S->h1 + (size_t)li * NF;
+        for (int o = 0; o < NF; ++o) {
+            double acc = W->b1[o];
+            for (int c = 0; c < NIN; ++c) acc += W->W1[o * NIN + c] * x[c];
+            pre1[o] = acc;
+            h1[o] = relu(acc);
+        }
+        double *pre2 = S->pre2 + (size_t)li * NF, *f = S->f + (size_t)li * NF;
+        for (int o = 0; o < NF; ++o) {
+            double acc = W->b2[o];
+            for (int c = 0; c < NF; ++c) acc += W->W2[o * NF + c] * h1[c];
+            pre2[o] = acc;
+            f[o] = relu(acc);
+        }
+        if (margin)
+            for (int o = 0; o < NF; ++o) {
+                if (fabs(pre1[o]) < *margin) *margin = fabs(pre1[o]);
+                if (fabs(pre2[o]) < *margin) *margin = fabs(pre2[o]);
+            }
+        if (sig)
+            for (int o = 0; o < NF; ++o) *sig = fnv(fnv(*sig, pre1[o] > 0.0), pre2[o] > 0.0);
+    }
+    /* max-pool over all nodes of the patch */
+    for (int c = 0; c < NF; ++c) {
+        int am = 0;
+        double best = S->f[c];
+        for (int li = 1; li < n; ++li)
+            if (S->f[(size_t)li * NF + c] > best) { best = S->f[(size_t)li * NF + c]; am = li; }
+        S->g[c] = best;
+        S->argmax[c] = am;
+        if (margin && best > 0.0) {
+            /* gap to the runner-up: an FP32 evaluation may pick another node */
+            double second = -1.0;
+            for (int li = 0; li < n; ++li)
+                if (li != am && S->f[(size_t)li * NF + c] > second) second = S->f[(size_t)li * NF + c];
+            if (second >= 0.0 && best - second < *margin) *margin = best - second;
+        }
+        if (sig) *sig = fnv(*sig, am);
+    }
+    /* global MLP */
+    for (int o = 0; o < NF; ++o) {
+        double acc = W->b3[o];
+        for (int c = 0; c < NF; ++c) acc += W->W3[o * NF + c] * S->g[c];
+        S->pre3[o] = acc;
+        S->gp[o] = relu(acc);
+        if (margin && fabs(acc) < *margin) *margin = fabs(acc);
+        if (sig) *sig = fnv(*sig, acc > 0.0);
+    }
+}
+
+/* Decoder for one node: z = [f_i ; g'] (per-node features first),
+ * h4 = ReLU(W4 z + b4), r = W5 h4 + b5. */
+static void phi_decode(const net_t *W, const double *f, const double *gp, double *pre4, double *h4,
+                       double r[3]) {
+    for (int o = 0; o < NF; ++o) {
+        double acc = W->b4[o];
+        for (int c = 0; c < NF; ++c) acc += W->W4[o * 2 * NF + c] * f[c];
+        for (int c = 0; c < NF; ++c) acc += W->W4[o * 2 * NF + NF + c] * gp[c];
+        pre4[o] = acc;
+        h4[o] = relu(acc);
+    }
+    for (int a = 0; a < 3; ++a) {
+        double acc = W->b5[a];
+        for (int c = 0; c < NF; ++c) acc += W->W5[a * NF + c] * h4[c];
+        r[a] = acc;
+    }
+}
+
+/* Eq. 1 weight between two nodes: exp(-alpha ||p_j - p_i||_2). */
+static inline double decay_weight(const problem_t *P, double alpha, int i, int j, double *dist) {
+    const int N = P->N;
+    double dx = P->pos[j] - P->pos[i];
+    double dy = P->pos[N + j] - P->pos[N + i];
+    double dz = P->pos[2 * N + j] - P->pos[2 * N + i];
+    double d = sqrt(dx * dx + dy * dy + dz * dz);
+    if (dist) *dist = d;
+    return exp(-alpha * d);
+}
+
+static void split_sets(const problem_t *P, int e, int k, const int8_t *cobj, scratch_t *S, int *m,
+                       int *np) {
+    int a = 0, b = 0;
+    for (int i = P->offset[k]; i < P->offset[k + 1]; ++i) {
+        if (cobj[(size_t)e * P->N + i] >= 0) S->act[a++] = i;
+        else S->pas[b++] = i;
+    }
+    *m = a;
+    *np = b;
+}
+
+/* Forward propagation (Eqs. 1-2) for patch k of env e. */
+static void propagate_patch(const problem_t *P, const net_t *W, int mode, const double *alpha, int e,
+                            int k, const int8_t *cobj, const double *uhat, double *U, scratch_t *S,
+                            double *margin, uint64_t *sig) {
+    const int N = P->N, E = P->E;
+    int m, np;
+    split_sets(P, e, k, cobj, S, &m, &np);
+    for (int i = P->offset[k]; i < P->offset[k + 1]; ++i)
+        for (int a = 0; a < 3; ++a) U[(size_t)a * E * N + (size_t)e * N + i] = 0.0;
+    if (m == 0) return; /* no contact on this patch: no deformation */
+    /* active nodes keep their contact displacement */
+    for (int t = 0; t < m; ++t) {
+        size_t en = (size_t)e * N + S->act[t];
+        for (int a = 0; a < 3; ++a) U[(size_t)a * E * N + en] = uhat[(size_t)a * E * N + en];
+    }
+    /* Eq. 1: Omega U_a for every passive node */
+    if (mode != O_RESIDUAL_ONLY) {
+        for (int t = 0; t < np; ++t) {
+            int i = S->pas[t];
+            double acc[3] = {0, 0, 0};
+            for (int s = 0; s < m; ++s) {
+                int j = S->act[s];
+                double w = decay_weight(P, alpha[k], i, j, NULL);
+                size_t ej = (size_t)e * N + j;
+                for (int a = 0; a < 3; ++a) acc[a] += w * uhat[(size_t)a * E * N + ej];
+            }
+            for (int a = 0; a < 3; ++a) U[(size_t)a * E * N + (size_t)e * N + i] += acc[a];
+        }
+    }
+    /* residual network, kept for passive nodes only (mask M_p) */
+    if (mode != O_DECAY_ONLY) {
+        phi_encode(P, W, e, k, cobj, uhat, S, margin, sig);
+        double pre4[NF], h4[NF], r[3];
+        for (int t = 0; t < np; ++t) {
+            int i = S->pas[t];
+            int li = i - P->offset[k];
+            phi_decode(W, S->f + (size_t)li * NF, S->gp, pre4, h4, r);
+            if (margin)
+                for (int o = 0; o < NF; ++o)
+                    if (fabs(pre4[o]) < *margin) *margin = fabs(pre4[o]);
+            if (sig)
+                for (int o = 0; o < NF; ++o) *sig = fnv(*sig, pre4[o] > 0.0);
+            for (int a = 0; a < 3; ++a) U[(size_t)a * E * N + (size_t)e * N + i] += r[a];
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* adjoint of the propagation for one patch                                 */
+/* ------------------------------------------------------------------------ */
+/* L = sum_i g_i . U_i.  Accumulates dL/du_hat (active nodes only), dL/dalpha_k
+ * and dL/dphi.  Conventions: ReLU'(0) = 0; the max-pool routes its gradient
+ * to the arg-max node (lowest index on ties). */
+static void propagate_patch_backward(const problem_t *P, const net_t *W, int mode, const double *alpha,
+                                     int e, int k, const int8_t *cobj, const double *uhat,
+                                     const double *gu, double *guhat, double *galpha, dnet_t *dW,
+                                     scratch_t *S) {
+    const int N = P->N, E = P->E;
+    const size_t EN = (size_t)E * N;
+    int m, np;
+    split_sets(P, e, k, cobj, S, &m, &np);
+    for (int i = P->offset[k]; i < P->offset[k + 1]; ++i)
+        for (int a = 0; a < 3; ++a) guhat[a * EN + (size_t)e * N + i] = 0.0;
+    if (m == 0) return;
+    /* active nodes: U_j = u_hat_j */
+    for (int s = 0; s < m; ++s) {
+        size_t ej = (size_t)e * N + S->act[s];
+        for (int a = 0; a < 3; ++a) guhat[a * EN + ej] += gu[a * EN + ej];
+    }
+    /* Eq. 1 adjoint: d u_hat_j += w_ij g_i ; d alpha += -d_ij w_ij (g_i . u_hat_j) */
+    if (mode != O_RESIDUAL_ONLY) {
+        double da = 0.0;
+        for (int t = 0; t < np; ++t) {
+            int i = S->pas[t];
+            size_t ei = (size_t)e * N + i;
+            double gi[3] = {gu[ei], gu[EN + ei], gu[2 * EN + ei]};
+            for (int s = 0; s < m; ++s) {
+                int j = S->act[s];
+                size_t ej = (size_t)e * N + j;
+                double d;
+                double w = decay_weight(P, alpha[k], i, j, &d);
+                double dot = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    guhat[a * EN + ej] += w * gi[a];
+                    dot += gi[a] * uhat[a * EN + ej];
+                }
+                da += -d * w * dot;
+            }
+        }
+        *galpha += da;
+    }
+    if (mode == O_DECAY_ONLY) return;
+    /* residual network adjoint */
+    phi_encode(P, W, e, k, cobj, uhat, S, NULL, NULL);
+    const int o0 = P->offset[k], n = P->offset[k + 1] - o0;
+    memset(S->df, 0, sizeof(double) * (size_t)n * NF);
+    double dgp[NF];
+    memset(dgp, 0, sizeof dgp);
+    double pre4[NF], h4[NF], r[3], dh4[NF];
+    for (int t = 0; t < np; ++t) {
+        int i = S->pas[t];
+        int li = i - o0;
+        size_t ei = (size_t)e * N + i;
+        const double *f = S->f + (size_t)li * NF;
+        phi_decode(W, f, S->gp, pre4, h4, r);
+        double dr[3] = {gu[ei], gu[EN + ei], gu[2 * EN + ei]};
+        for (int a = 0; a < 3; ++a) {
+            dW->b5[a] += dr[a];
+            for (int c = 0; c < NF; ++c) dW->W5[a * NF + c] += dr[a] * h4[c];
+        }
+        for (int c = 0; c < NF; ++c) {
+            double acc = 0.0;
+            for (int a = 0; a < 3; ++a) acc += W->W5[a * NF + c] * dr[a];
+            dh4[c] = pre4[c] > 0.0 ? acc : 0.0;
+        }
+        for (int o = 0; o < NF; ++o) {
+            if (dh4[o] == 0.0) continue;
+            dW->b4[o] += dh4[o];
+            for (int c = 0; c < NF; ++c) {
+                dW->W4[o * 2 * NF + c] += dh4[o] * f[c];
+                dW->W4[o * 2 * NF + NF + c] += dh4[o] * S->gp[c];
+                S->df[(size_t)li * NF + c] += W->W4[o * 2 * NF + c] * dh4[o];
+                dgp[c] += W->W4[o * 2 * NF + NF + c] * dh4[o];
+            }
+        }
+    }
+    /* global MLP and max-pool */
+    double dpre3[NF], dg[NF];
+    for (int o = 0; o < NF; ++o) dpre3[o] = S->pre3[o] > 0.0 ? dgp[o] : 0.0;
+    for (int o = 0; o < NF; ++o) {
+        dW->b3[o] += dpre3[o];
+        for (int c = 0; c < NF; ++c) dW->W3[o * NF + c] += dpre3[o] * S->g[c];
+    }
+    for (int c = 0; c < NF; ++c) {
+        double acc = 0.0;
+        for (int o = 0; o < NF; ++o) acc += W->W3[o * NF + c] * dpre3[o];
+        dg[c] = acc;
+    }
+    for (int c = 0; c < NF; ++c) S->df[(size_t)S->argmax[c] * NF + c] += dg[c];
+    /* encoder adjoint for every node */
+    for (int li = 0; li < n; ++li) {
+        const double *df = S->df + (size_t)li * NF;
+        const double *pre2 = S->pre2 + (size_t)li * NF, *pre1 = S->pre1 + (size_t)li * NF;
+        const double *h1 = S->h1 + (size_t)li * NF, *x = S->x + (size_t)li * NIN;
+        double dpre2[NF], dpre1[NF];
+        int any = 0;
+        for (int o = 0; o < NF; ++o) {
+            dpre2[o] = pre2[o] > 0.0 ? df[o] : 0.0;
+            any |= dpre2[o] != 0.0;
+        }
+        if (!any) continue;
+        for (int o = 0; o < NF; ++o) {
+            dW->b2[o] += dpre2[o];
+            for (int c = 0; c < NF; ++c) dW->W2[o * NF + c] += dpre2[o] * h1[c];
+        }
+        for (int c = 0; c < NF; ++c) {
+            double acc = 0.0;
+            for (int o = 0; o < NF; ++o) acc += W->W2[o * NF + c] * dpre2[o];
+            dpre1[c] = pre1[c] > 0.0 ? acc : 0.0;
+        }
+        for (int o = 0; o < NF; ++o) {
+            dW->b1[o] += dpre1[o];
+            for (int c = 0; c < NIN; ++c) dW->W1[o * NIN + c] += dpre1[o] * x[c];
+        }
+        int i = o0 + li;
+        size_t ei = (size_t)e * N + i;
+        if (cobj[ei] >= 0) { /* only active nodes carry u_hat into the input */
+            for (int a = 0; a < 3; ++a) {
+                double acc = 0.0;
+                for (int o = 0; o < NF; ++o) acc += W->W1[o * NIN + 6 + a] * dpre1[o];
+                guhat[a * EN + ei] += acc;
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* adjoint of the contact displacement with respect to the object pose      */
+/* ------------------------------------------------------------------------ */
+/* Derivatives of u_hat as the function written in penetrate(), with R taken
+ * as nine free entries (the chosen face / clamp state held fixed):
+ *   sphere : u = phi(s) d, phi = r/sqrt(s) - 1, s = d.d, d = p - t
+ *            dL/dt = -(phi g + 2 phi'(s) (g.d) d),  dL/dR = 0
+ *   box    : u = (sg h_c - q_c) R[:,c],  q_c = R[:,c].d
+ *            dL/dt = (g.R[:,c]) R[:,c]
+ *            dL/dR[:,c] = (sg h_c - q_c) g - (g.R[:,c]) d, other columns 0
+ *   capsule: u = phi(s) R v, v = q - z e_3, q = R^T d, s = v.v
+ *            a = 2 phi'(s) (g.Rv) v + phi P R^T g   (P = diag(1,1,0) when the
+ *            axial clamp is inactive, else I)
+ *            dL/dR = d a^T + phi g v^T,  dL/dt = -R a
+ * Degenerate nodes (u = -r n) carry no pose dependence. */
+static void contact_node_backward(int type, const double *shape, const double *R, const double *t,
+                                  const double p[3], const double g[3], double *gR, double *gt) {
+    double d[3] = {p[0] - t[0], p[1] - t[1], p[2] - t[2]};
+    if (type == O_SPHERE) {
+        double r = shape[0];
+        double s = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        if (s == 0.0) return;
+        double l = sqrt(s);
+        double phi = r / l - 1.0;
+        double twophip = -r / (l * s);
+        double gd = g[0] * d[0] + g[1] * d[1] + g[2] * d[2];
+        for (int a = 0; a < 3; ++a) gt[a] += -(phi * g[a] + twophip * gd * d[a]);
+        return;
+    }
+    double q[3];
+    for (int c = 0; c < 3; ++c) q[c] = R[0 * 3 + c] * d[0] + R[1 * 3 + c] * d[1] + R[2 * 3 + c] * d[2];
+    if (type == O_BOX) {
+        int cs = 0;
+        double best = shape[0] - fabs(q[0]);
+        for (int c = 1; c < 3; ++c) {
+            double sl = shape[c] - fabs(q[c]);
+            if (sl < best) { best = sl; cs = c; }
+        }
+        double sg = (q[cs] >= 0.0) ? 1.0 : -1.0;
+        double rc[3] = {R[0 * 3 + cs], R[1 * 3 + cs], R[2 * 3 + cs]};
+        double grc = g[0] * rc[0] + g[1] * rc[1] + g[2] * rc[2];
+        double coef = sg * shape[cs] - q[cs];
+        for (int a = 0; a < 3; ++a) {
+            gt[a] += grc * rc[a];
+            gR[a * 3 + cs] += coef * g[a] - grc * d[a];
+        }
+        return;
+    }
+    double r = shape[0], L = shape[1];
+    double z = q[2];
+    int clamped = 0;
+    if (z < -L) { z = -L; clamped = 1; }
+    else if (z > L) { z = L; clamped = 1; }
+    double v[3] = {q[0], q[1], q[2] - z};
+    double s = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    if (s == 0.0) return;
+    double l = sqrt(s);
+    double phi = r / l - 1.0;
+    double twophip = -r / (l * s);
+    double Rv[3], RTg[3];
+    for (int a = 0; a < 3; ++a) Rv[a] = R[a * 3 + 0] * v[0] + R[a * 3 + 1] * v[1] + R[a * 3 + 2] * v[2];
+    for (int c = 0; c < 3; ++c) RTg[c] = R[0 * 3 + c] * g[0] + R[1 * 3 + c] * g[1] + R[2 * 3 + c] * g[2];
+    double gRv = g[0] * Rv[0] + g[1] * Rv[1] + g[2] * Rv[2];
+    double av[3];
+    for (int c = 0; c < 3; ++c) av[c] = twophip * gRv * v[c] + phi * RTg[c];
+    if (!clamped) av[2] = twophip * gRv * v[2]; /* P drops the axial row; v[2] = 0 here */
+    for (int a = 0; a < 3; ++a) {
+        for (int c = 0; c < 3; ++c) gR[a * 3 + c] += d[a] * av[c] + phi * g[a] * v[c];
+        gt[a] += -(R[a * 3 + 0] * av[0] + R[a * 3 + 1] * av[1] + R[a * 3 + 2] * av[2]);
+    }
+}
+
+/* pose gradients of env e from dL/du_hat of its active nodes */
+static void contact_env_backward(const problem_t *P, int e, const double *guhat, double *grot,
+                                 double *gtrans) {
+    const int N = P->N, E = P->E, O = P->O;
+    const size_t EN = (size_t)E * N;
+    for (int o = 0; o < O; ++o) {
+        for (int c = 0; c < 9; ++c) grot[((size_t)e * O + o) * 9 + c] = 0.0;
+        for (int c = 0; c < 3; ++c) gtrans[((size_t)e * O + o) * 3 + c] = 0.0;
+    }
+    for (int i = 0; i < N; ++i) {
+        double p[3] = {P->pos[i], P->pos[N + i], P->pos[2 * N + i]};
+        double n[3] = {P->nrm[i], P->nrm[N + i], P->nrm[2 * N + i]};
+        int best = -1;
+        hit_t bh;
+        memset(&bh, 0, sizeof bh);
+        for (int o = 0; o < P->n_obj[e]; ++o) {
+            size_t eo = (size_t)e * O + o;
+            hit_t h = penetrate(P->type[eo], P->shape + 4 * eo, P->rot + 9 * eo, P->trans + 3 * eo, p, n);
+            if (h.inside && (best < 0 || h.depth > bh.depth)) { best = o; bh = h; }
+        }
+        if (best < 0 || bh.degenerate) continue;
+        size_t ei = (size_t)e * N + i, eo = (size_t)e * O + best;
+        double g[3] = {guhat[ei], guhat[EN + ei], guhat[2 * EN + ei]};
+        contact_node_backward(P->type[eo], P->shape + 4 * eo, P->rot + 9 * eo, P->trans + 3 * eo, p, g,
+                              grot + 9 * eo, gtrans + 3 * eo);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* exported entry points (ctypes)                                           */
+/* ------------------------------------------------------------------------ */
+static problem_t mkprob(int K, int N, const int32_t *offset, const double *pos, const double *nrm,
+                        const double *origin, int E, int O, const int32_t *n_obj, const int32_t *type,
+                        const double *shape, const double *rot, const double *trans) {
+    problem_t P = {K, N, offset, pos, nrm, origin, E, O, n_obj, type, shape, rot, trans};
+    return P;
+}
+
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Contact only.  Outputs contact_obj [E][N], uhat [3][E][N], n_active [E][K]. */
+int oracle_contact(int K, int N, const int32_t *offset, const double *pos, const double *nrm, int E,
+                   int O, const int32_t *n_obj, const int32_t *type, const double *shape,
+                   const double *rot, const double *trans, int8_t *cobj, double *uhat,
+                   int32_t *n_active) {
+    problem_t P = mkprob(K, N, offset, pos, nrm, NULL, E, O, n_obj, type, shape, rot, trans);
+#pragma omp parallel for schedule(static)
+    for (int e = 0; e < E; ++e) contact_env(&P, e, cobj, uhat, n_active, NULL);
+    return 0;
+}
+
+/* Propagation of given contact results (Eqs. 1-2).  u [3][E][N]. */
+int oracle_propagate(int K, int N, const int32_t *offset, const double *pos, const double *nrm,
+                     const double *origin, int E, int mode, const double *alpha, const double *phi,
+                     const int8_t *cobj, const double *uhat, double *U) {
+    problem_t P = mkprob(K, N, offset, pos, nrm, origin, E, 0, NULL, NULL, NULL, NULL, NULL);
+    net_t W = net_view(phi);
+    int nmax = max_patch(&P);
+#pragma omp parallel
+    {
+        scratch_t S = scratch_new(nmax);
+#pragma omp for schedule(static)
+        for (int e = 0; e < E; ++e)
+            for (int k = 0; k < K; ++k) propagate_patch(&P, &W, mode, alpha, e, k, cobj, uhat, U, &S, NULL, NULL);
+        scratch_free(&S);
+    }
+    return 0;
+}
+
+/* Whole forward step.  Optional outputs (may be NULL): sig [E] fingerprint of
+ * every discrete decision, margin [E] smallest distance of a ReLU input or
+ * max-pool runner-up gap from its decision boundary. */
+int oracle_forward(int K, int N, const int32_t *offset, const double *pos, const double *nrm,
+                   const double *origin, int E, int O, const int32_t *n_obj, const int32_t *type,
+                   const double *shape, const double *rot, const double *trans, int mode,
+                   const double *alpha, const double *phi, double *U, int8_t *cobj, double *uhat,
+                   int32_t *n_active, uint64_t *sig, double *margin) {
+    problem_t P = mkprob(K, N, offset, pos, nrm, origin, E, O, n_obj, type, shape, rot, trans);
+    net_t W = net_view(phi);
+    int nmax = max_patch(&P);
+#pragma omp parallel
+    {
+        scratch_t S = scratch_new(nmax);
+#pragma omp for schedule(static)
+        for (int e = 0; e < E; ++e) {
+            uint64_t h = 1469598103934665603ULL;
+            double mg = INFINITY;
+            contact_env(&P, e, cobj, uhat, n_active, sig ? &h : NULL);
+            for (int k = 0; k < K; ++k)
+                propagate_patch(&P, &W, mode, alpha, e, k, cobj, uhat, U, &S, margin ? &mg : NULL,
+                                sig ? &h : NULL);
+            if (sig) sig[e] = h;
+            if (margin) margin[e] = mg;
+        }
+        scratch_free(&S);
+    }
+    return 0;
+}
+
+/* Adjoint of the propagation.  Outputs guhat [3][E][N] (zero on passive
+ * nodes), galpha [K], gphi [PHI_N] (both overwritten). */
+int oracle_propagate_backward(int K, int N, const int32_t *offset, const double *pos,
+                              const double *nrm, const double *origin, int E, int mode,
+                              const double *alpha, const double *phi, const int8_t *cobj,
+                              const double *uhat, const double *gu, double *guhat, double *galpha,
+                              double *gphi) {
+    problem_t P = mkprob(K, N, offset, pos, nrm, origin, E, 0, NULL, NULL, NULL, NULL, NULL);
+    net_t W = net_view(phi);
+    int nmax = max_patch(&P);
+    int nt = oracle_num_threads();
+    double *pa = calloc((size_t)nt * K, sizeof(double));
+    double *pp = calloc((size_t)nt * PHI_N, sizeof(double));
+#pragma omp parallel
+    {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        scratch_t S = scratch_new(nmax);
+        dnet_t dW = dnet_view(pp + (size_t)tid * PHI_N);
+#pragma omp for schedule(static)
+        for (int e = 0; e < E; ++e)
+            for (int k = 0; k < K; ++k)
+                propagate_patch_backward(&P, &W, mode, alpha, e, k, cobj, uhat, gu, guhat,
+                                         pa + (size_t)tid * K + k, &dW, &S);
+        scratch_free(&S);
+    }
+    for (int k = 0; k < K; ++k) {
+        double s = 0.0;
+        for (int t = 0; t < nt; ++t) s += pa[(size_t)t * K + k];
+        galpha[k] = s;
+    }
+    for (int c = 0; c < PHI_N; ++c) {
+        double s = 0.0;
+        for (int t = 0; t < nt; ++t) s += pp[(size_t)t * PHI_N + c];
+        gphi[c] = s;
+    }
+    free(pa);
+    free(pp);
+    return 0;
+}
+
+/* Adjoint of the contact pass: grot [E][O][9], gtrans [E][O][3]. */
+int oracle_contact_backward(int K, int N, const int32_t *offset, const double *pos, const double *nrm,
+                            int E, int O, const int32_t *n_obj, const int32_t *type,
+                            const double *shape, const double *rot, const double *trans,
+                            const double *guhat, double *grot, double *gtrans) {
+    problem_t P = mkprob(K, N, offset, pos, nrm, NULL, E, O, n_obj, type, shape, rot, trans);
+#pragma omp parallel for schedule(static)
+    for (int e = 0; e < E; ++e) contact_env_backward(&P, e, guhat, grot, gtrans);
+    return 0;
+}
+
+/* Whole adjoint of L = sum g . U: recomputes the contact pass, then the
+ * propagation adjoint, then the contact adjoint. */
+int oracle_backward(int K, int N, const int32_t *offset, const double *pos, const double *nrm,
+                    const double *origin, int E, int O, const int32_t *n_obj, const int32_t *type,
+                    const double *shape, const double *rot, const double *trans, int mode,
+                    const double *alpha, const double *phi, const double *gu, double *grot,
+                    double *gtrans, double *galpha, double *gphi, double *guhat_out) {
+    size_t EN = (size_t)E * N;
+    int8_t *cobj = malloc(EN);
+    double *uhat = malloc(sizeof(double) * 3 * EN);
+    int32_t *na = malloc(sizeof(int32_t) * (size_t)E * K);
+    double *guhat = guhat_out ? guhat_out : malloc(sizeof(double) * 3 * EN);
+    oracle_contact(K, N, offset, pos, nrm, E, O, n_obj, type, shape, rot, trans, cobj, uhat, na);
+    oracle_propagate_backward(K, N, offset, pos, nrm, origin, E, mode, alpha, phi, cobj, uhat, gu,
+                              guhat, galpha, gphi);
+    oracle_contact_backward(K, N, offset, pos, nrm, E, O, n_obj, type, shape, rot, trans, guhat, grot,
+                            gtrans);
+    if (!guhat_out) free(guhat);
+    free(cobj);
+    free(uhat);
+    free(na);
+    return 0;
+}
