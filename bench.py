@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Throughput of the ETac tactile step on one MI355X.
+
+One step = the whole hot path over one batch: the fused contact + propagation
+forward (etac_step) and its adjoint (etac_step_backward, which recomputes
+contact) for every env of the workload.  Workload: 4096 envs of a 16-patch
+hand (7232 surface nodes per env, patch sizes 64..1024) with 1-3 rigid
+primitives per env, FP32 with the FP64 contact predicate; inputs are resident
+in HBM before the timed region.
+
+Prints one JSON line (metric: sensor node-updates/s = envs x nodes / step time).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP32_MFMA_PEAK_TFLOPS = 157.3  # dense FP32 matrix
+FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (no packed FP32)
+ENC_MAC, DEC_MAC, GLOBAL_MAC = 9 * 64 + 64 * 64, 64 * 128 + 64 * 3, 2 * 64 * 64
+PAIR_FLOP = 20                 # decay pair: 3 sub, 5 for the squared distance, sqrt, scale, exp, 6 for w*u
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--envs", type=int, default=4096)
+    ap.add_argument("--mode", choices=["full", "decay", "residual"], default="full")
+    ap.add_argument("--cpu-envs", type=int, default=48, help="env sample for the CPU oracle baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph", action="store_true", help="replay the step from a captured HIP graph")
+    return ap.parse_args()
+
+
+def work_counts(mesh, n_active):
+    """Algorithmic work of one forward given the active counts [E][K]."""
+    n = mesh.patch_sizes()[None, :].astype(np.float64)
+    m = n_active.astype(np.float64)
+    hit = m > 0
+    pairs = float(np.sum(m * (n - m)))
+    enc_nodes = float(np.sum(np.where(hit, n, 0.0)))
+    dec_nodes = float(np.sum(np.where(hit, n - m, 0.0)))
+    items = float(np.sum(hit))
+    mlp_flop = 2.0 * (ENC_MAC * enc_nodes + DEC_MAC * dec_nodes + GLOBAL_MAC * items)
+    return dict(pairs=pairs, mlp_flop=mlp_flop, contacted_items=items, contacted_nodes=enc_nodes,
+                active=float(m.sum()))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the ETac step shards by env "
+              f"with no exchange in the forward, see the design notes.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import scenes
+    from paper_2604_20295_amd import _native
+
+    mode = {"full": scenes.MODE_FULL, "decay": scenes.MODE_DECAY_ONLY, "residual": scenes.MODE_RESIDUAL_ONLY}[args.mode]
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    mesh, scene, model = scenes.config2(n_envs=args.envs, mode=mode)
+    E, O, N, K = scene.n_envs, scene.max_obj, mesh.n_nodes, mesh.n_patches
+
+    def t(a, dtype):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).to(dev)
+
+    plan = _native.Plan.from_mesh(mesh, E, O, backward=True)
+    sc = plan.scene_struct(t(scene.n_obj, torch.int32), t(scene.type, torch.int32), t(scene.shape, torch.float32),
+                           t(scene.rot, torch.float32), t(scene.trans, torch.float32))
+    md = plan.model_struct(mode, t(model.alpha, torch.float32), t(model.phi, torch.float32))
+    grad_u = t(np.random.default_rng(7).standard_normal((3, E, N)), torch.float32)
+    u = torch.empty((3, E, N), dtype=torch.float32, device=dev)
+    cobj = torch.empty((E, N), dtype=torch.int8, device=dev)
+    na = torch.empty((E, K), dtype=torch.int32, device=dev)
+    grot = torch.empty((E, O, 9), dtype=torch.float32, device=dev)
+    gtr = torch.empty((E, O, 3), dtype=torch.float32, device=dev)
+    gal = torch.empty((K,), dtype=torch.float32, device=dev)
+    gph = torch.empty((17411,), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def fwd():
+        _native.etac_step(plan, sc, md, u, cobj, na)
+
+    def bwd():
+        _native.etac_step_backward(plan, sc, md, grad_u, grot, gtr, gal, gph)
+
+    graph = None
+    if args.graph:
+        fwd(); bwd()
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            fwd()
+            bwd()
+        stream = torch.cuda.current_stream(dev)
+
+    for _ in range(args.warmup):
+        if graph is not None:
+            graph.replay()
+        else:
+            fwd(); bwd()
+    torch.cuda.synchronize()
+    counts = work_counts(mesh, na.cpu().numpy())
+
+    # forward + backward steps, HIP events around each call on the launch stream
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        if graph is not None:
+            ev[s][0].record(stream); graph.replay(); ev[s][2].record(stream)
+        else:
+            ev[s][0].record(stream); fwd(); ev[s][1].record(stream); bwd(); ev[s][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = wall * 1e3 / args.steps
+    if graph is None:
+        fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+        bwd_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    else:
+        fwd_ms = bwd_ms = float("nan")
+    step_ev_ms = float(np.mean([e[0].elapsed_time(e[2]) for e in ev]))
+
+    # forward-only throughput
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        fwd()
+    torch.cuda.synchronize()
+    fwd_only_ms = (time.perf_counter() - t1) * 1e3 / args.steps
+
+    nodes = float(E) * N
+    value = nodes / (step_ms * 1e-3)
+    fwd_rate = nodes / (fwd_only_ms * 1e-3)
+    # HBM accounting of the metric: 13 B per node-update forward (U + contact
+    # id), 25 B with the backward (plus dL/dU read)
+    hbm_fwd_gbs = 13.0 * nodes / (fwd_only_ms * 1e-3) / 1e9
+    hbm_step_gbs = 25.0 * nodes / (step_ms * 1e-3) / 1e9
+
+    # dominant kernel of the step: the fused forward or the adjoint launch
+    kernel = "k_bwd" if bwd_ms >= fwd_ms else "k_step"
+    k_ms = bwd_ms if kernel == "k_bwd" else fwd_ms
+    flop = counts["mlp_flop"] * (2.0 if kernel == "k_bwd" else 1.0)
+    achieved = flop / (k_ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "kernel": kernel, "achieved": round(achieved, 3), "peak": FP32_MFMA_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": None,
+                "avg_ms": round(k_ms, 4)}
+
+    line = {
+        "metric": "sensor node-updates/s at 4096 envs (fwd+bwd step)",
+        "value": value,
+        "unit": "node-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{E} envs x 16-patch hand ({N} nodes/env, patches 64-1024 nodes), "
+                               f"1-3 sphere/box/capsule per env, mode {args.mode}",
+                   "envs": E, "nodes_per_env": N, "patches": K, "graph": bool(args.graph)},
+        "fwd_only": {"value": fwd_rate, "unit": "node-updates/s", "ms_per_step": fwd_only_ms,
+                     "hbm_gbs": hbm_fwd_gbs, "hbm_frac": hbm_fwd_gbs / HBM_PEAK_GBS},
+        "hbm_frac_step": hbm_step_gbs / HBM_PEAK_GBS,
+        "kernel_ms": {"etac_step": fwd_ms, "etac_step_backward": bwd_ms, "step_events": step_ev_ms},
+        "work": counts,
+        "roofline": roofline,
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        ne = min(args.cpu_envs, E)
+        sub = scene.select(np.arange(ne))
+        w = grad_u[:, :ne].cpu().numpy().astype(np.float64)
+        tc = time.perf_counter()
+        oracle.forward(mesh, sub, model)
+        oracle.backward(mesh, sub, model, w)
+        dt = time.perf_counter() - tc
+        line["cpu_baseline"] = {"value": ne * N / dt, "unit": "node-updates/s", "cores": oracle.num_threads(),
+                                "kind": "oracle",
+                                "sample": f"first {ne} envs of the workload, forward + adjoint, {dt:.1f} s"}
+    plan.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,194 @@
+/*
+ * etac.h -- C ABI of the MI355X ETac tactile step library (libetac.so).
+ *
+ * What the library computes (ETac, Sec. III-A):
+ *   contact   : surface nodes of an elastomer patch lying strictly inside a
+ *               rigid primitive are active; each gets the displacement u_hat
+ *               that moves it to the closest point of the primitive surface
+ *               (the local penalty-style contact displacement, Sec. III-A
+ *               "Overview"); the deepest object wins, lowest index on ties.
+ *   propagate : passive nodes get U_p = Omega U_a + Phi_p(P, U_hat, N)
+ *               (Eq. 2) with Omega[i,j] = exp(-alpha ||p_j - p_i||) (Eq. 1)
+ *               and Phi the PointNet residual network of Sec. III-A
+ *               "Residual Displacement Correction"; active nodes keep u_hat;
+ *               a patch with no active node has U = 0.
+ *   backward  : the adjoint of L = sum_i g_i . U_i with respect to object
+ *               poses (R, t), alpha and the network parameters (ETac is
+ *               differentiable, Table 1; Sec. III-A fits alpha and Phi by
+ *               gradient descent).
+ *
+ * Units: mm and 1/mm.  All float arrays are IEEE FP32.
+ *
+ * Layouts (row-major, "SoA" = component-major):
+ *   node arrays          [3][N]       x for all nodes, then y, then z
+ *   per-env node arrays  [3][E][N]    component, env, node
+ *   contact_obj          [E][N]       int8: -1 passive, else winning object
+ *   n_active             [E][K]       int32 active-node count per patch
+ *   object arrays        [E][O][...]  type int32; shape float[4]; rot float[9]
+ *                                     row-major R (world x = R q + t);
+ *                                     trans float[3]
+ *   primitive shapes     sphere (r); box (hx, hy, hz half extents);
+ *                        capsule (r, half segment length L along object z)
+ *   phi                  packed FP32 network parameters, ETAC_PHI_SIZE floats:
+ *                        W1[64][9] b1[64] W2[64][64] b2[64] W3[64][64] b3[64]
+ *                        W4[64][128] b4[64] W5[3][64] b5[3]
+ *                        network input x_i = [p_i - o_k, n_i, U_hat_i]
+ *                        (U_hat_i = 0 on passive nodes); h1 = relu(W1 x + b1);
+ *                        f = relu(W2 h1 + b2); g = max over the patch's nodes;
+ *                        g' = relu(W3 g + b3); h4 = relu(W4 [f; g'] + b4);
+ *                        r = W5 h4 + b5.
+ *
+ * Memory: every pointer marked DEVICE is a device pointer on the plan's
+ * device; HOST pointers are read during the call only.  The caller owns all
+ * inputs and outputs; outputs are overwritten, never accumulated.  The plan
+ * owns its copy of the mesh and all scratch memory; no call other than
+ * etac_plan_create / etac_plan_destroy allocates, frees or synchronises, so
+ * every other call may be captured in a HIP graph.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the default stream).  Every call
+ * only enqueues work on it.  A plan is used by one stream at a time.
+ *
+ * Errors: arguments are validated on the host before anything is enqueued;
+ * on error nothing is enqueued and an ETAC_ERR_* code is returned.  A failed
+ * kernel launch returns ETAC_ERR_HIP; etac_last_hip_error() gives the HIP
+ * code.  No C++ exception crosses this interface.
+ */
+#ifndef ETAC_H
+#define ETAC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t etac_status;
+
+#define ETAC_OK             0
+#define ETAC_ERR_NULL      -1   /* a required pointer is NULL                  */
+#define ETAC_ERR_SHAPE     -2   /* sizes negative, inconsistent or too large   */
+#define ETAC_ERR_VALUE     -3   /* bad mode / flags / primitive type           */
+#define ETAC_ERR_WORKSPACE -4   /* plan was created without what this call needs */
+#define ETAC_ERR_HIP       -5   /* HIP runtime error                           */
+#define ETAC_ERR_CAPTURE   -6   /* plan creation attempted during stream capture */
+
+#define ETAC_SPHERE  0
+#define ETAC_BOX     1
+#define ETAC_CAPSULE 2
+
+#define ETAC_FULL          0    /* Eq. 2: decay + residual (Table 2, full)     */
+#define ETAC_DECAY_ONLY    1    /* Eq. 1 only (Table 2, linear decay only)     */
+#define ETAC_RESIDUAL_ONLY 2    /* Phi only (Table 2, residual network only)   */
+
+#define ETAC_PHI_SIZE 17411
+#define ETAC_MAX_OBJ  8         /* objects per env                             */
+#define ETAC_MAX_PATCH_NODES 65536
+
+/* plan flags */
+#define ETAC_PLAN_BACKWARD 1u   /* reserve the scratch the backward calls need */
+
+typedef struct etac_plan etac_plan;
+
+/* Elastomer surfaces, shared by all envs (node positions P and normals N,
+ * Sec. III-A).  All pointers HOST; the plan keeps its own device copy. */
+typedef struct {
+    int32_t n_patches;            /* K >= 1                                    */
+    int32_t n_nodes;              /* N = patch_offset[K]                        */
+    const int32_t *patch_offset;  /* [K+1] ascending, [0] = 0, patch k owns
+                                     nodes patch_offset[k] .. patch_offset[k+1]-1,
+                                     every patch 1..ETAC_MAX_PATCH_NODES nodes  */
+    const float *pos;             /* [3][N] undeformed node positions, mm       */
+    const float *nrm;             /* [3][N] unit outward normals                */
+    const float *origin;          /* [K][3] per-patch origin o_k (network input)*/
+} etac_mesh;
+
+/* Rigid primitives of every env.  Array pointers DEVICE.  Objects
+ * o >= n_obj[e] are ignored.  n_envs may be smaller than the plan's. */
+typedef struct {
+    int32_t n_envs;               /* E, 0 <= E <= plan n_envs                  */
+    int32_t max_obj;              /* O, 1 <= O <= plan max_obj                 */
+    const int32_t *n_obj;         /* [E] values 0..O                           */
+    const int32_t *type;          /* [E][O] ETAC_SPHERE / BOX / CAPSULE        */
+    const float *shape;           /* [E][O][4]                                  */
+    const float *rot;             /* [E][O][9]                                  */
+    const float *trans;           /* [E][O][3]                                  */
+} etac_scene;
+
+/* Propagation model (Eqs. 1-2).  Pointers DEVICE. */
+typedef struct {
+    int32_t mode;                 /* ETAC_FULL / DECAY_ONLY / RESIDUAL_ONLY    */
+    const float *alpha;           /* [K] decay rate per patch, 1/mm            */
+    const float *phi;             /* [ETAC_PHI_SIZE]; may be NULL iff mode ==
+                                     ETAC_DECAY_ONLY                            */
+} etac_model;
+
+/* Create a plan for `mesh` and up to n_envs envs with up to max_obj objects.
+ * Validates the mesh, uploads it, computes per-patch bounding spheres and the
+ * longest-first item order, and allocates scratch (more with
+ * ETAC_PLAN_BACKWARD).  Synchronous; must not be called during stream
+ * capture (ETAC_ERR_CAPTURE). *out is set only on success. */
+etac_status etac_plan_create(const etac_mesh *mesh, int32_t n_envs, int32_t max_obj,
+                             uint32_t flags, etac_plan **out);
+
+/* Free a plan and its device memory (synchronises the device). NULL is OK. */
+etac_status etac_plan_destroy(etac_plan *plan);
+
+/* Contact pass only (Sec. III-A contact detection and local displacement).
+ * Outputs DEVICE: contact_obj [E][N], uhat [3][E][N] (0 on passive nodes),
+ * n_active [E][K].  uhat may be NULL to skip it. */
+etac_status etac_contact(etac_plan *plan, const etac_scene *scene, int8_t *contact_obj,
+                         float *uhat, int32_t *n_active, void *stream);
+
+/* Propagation of given contact results (Eqs. 1-2).  Inputs DEVICE:
+ * contact_obj [E][N] (any value >= 0 marks an active node), uhat [3][E][N]
+ * (read on active nodes only).  Output DEVICE: u [3][E][N].  E = n_envs. */
+etac_status etac_propagate(etac_plan *plan, const etac_model *model, int32_t n_envs,
+                           const int8_t *contact_obj, const float *uhat, float *u, void *stream);
+
+/* Whole step, contact + propagation, as one persistent fused launch.
+ * Outputs DEVICE: u [3][E][N], contact_obj [E][N], n_active [E][K]. */
+etac_status etac_step(etac_plan *plan, const etac_scene *scene, const etac_model *model,
+                      float *u, int8_t *contact_obj, int32_t *n_active, void *stream);
+
+/* Adjoint of the contact pass: given dL/du_hat [3][E][N] (DEVICE; read on
+ * active nodes only) returns dL/dR [E][O][9] and dL/dt [E][O][3] (DEVICE,
+ * overwritten, zero for absent objects).  dL/dR treats the nine entries of R
+ * as free inputs of the displacement formula.  Recomputes the contact pass. */
+etac_status etac_contact_backward(etac_plan *plan, const etac_scene *scene, const float *grad_uhat,
+                                  float *grad_rot, float *grad_trans, void *stream);
+
+/* Adjoint of the propagation: given contact_obj, uhat and dL/du [3][E][N]
+ * returns dL/du_hat [3][E][N] (0 on passive nodes), dL/dalpha [K] and
+ * dL/dphi [ETAC_PHI_SIZE] (all DEVICE, overwritten; grad_alpha / grad_phi may
+ * be NULL to skip).  Needs a plan created with ETAC_PLAN_BACKWARD. */
+etac_status etac_propagate_backward(etac_plan *plan, const etac_model *model, int32_t n_envs,
+                                    const int8_t *contact_obj, const float *uhat,
+                                    const float *grad_u, float *grad_uhat, float *grad_alpha,
+                                    float *grad_phi, void *stream);
+
+/* Adjoint of the whole step (recomputes contact; nothing from the forward
+ * call is needed).  Outputs as above.  Needs ETAC_PLAN_BACKWARD. */
+etac_status etac_step_backward(etac_plan *plan, const etac_scene *scene, const etac_model *model,
+                               const float *grad_u, float *grad_rot, float *grad_trans,
+                               float *grad_alpha, float *grad_phi, void *stream);
+
+/* Human-readable text of a status code (static storage). */
+const char *etac_status_string(etac_status status);
+
+/* HIP error code of the most recent ETAC_ERR_HIP in this thread (0 if none). */
+int32_t etac_last_hip_error(void);
+
+/* Plan introspection: number of (env, patch) items, persistent grid size,
+ * scratch bytes.  Any output pointer may be NULL. */
+etac_status etac_plan_info(const etac_plan *plan, int32_t *n_items, int32_t *grid,
+                           int64_t *scratch_bytes);
+
+/* Launch-shape override for the autotuner: persistent workgroups per CU for
+ * the fused kernels (0 = built-in default). */
+etac_status etac_plan_set_occupancy(etac_plan *plan, int32_t wg_per_cu);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ETAC_H */

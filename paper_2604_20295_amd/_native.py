@@ -1,0 +1,243 @@
+"""ctypes binding of libetac.so: the C ABI of include/etac.h, one Python
+function per exported symbol with the same name.  Argument marshalling only;
+every step of the computation runs in the library's HIP kernels.
+
+Tensors passed in must already live on the plan's GPU with the documented
+dtype, shape and contiguity; they are checked here and passed as raw device
+pointers.  Every call is enqueued on torch's current stream of that device.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libetac.so")
+
+ETAC_OK = 0
+ETAC_SPHERE, ETAC_BOX, ETAC_CAPSULE = 0, 1, 2
+ETAC_FULL, ETAC_DECAY_ONLY, ETAC_RESIDUAL_ONLY = 0, 1, 2
+ETAC_PHI_SIZE = 17411
+ETAC_MAX_OBJ = 8
+ETAC_PLAN_BACKWARD = 1
+
+EXPORTED = (
+    "etac_plan_create", "etac_plan_destroy", "etac_contact", "etac_propagate", "etac_step",
+    "etac_contact_backward", "etac_propagate_backward", "etac_step_backward",
+    "etac_status_string", "etac_last_hip_error", "etac_plan_info", "etac_plan_set_occupancy",
+)
+
+
+class etac_mesh(C.Structure):
+    _fields_ = [("n_patches", C.c_int32), ("n_nodes", C.c_int32), ("patch_offset", C.c_void_p),
+                ("pos", C.c_void_p), ("nrm", C.c_void_p), ("origin", C.c_void_p)]
+
+
+class etac_scene(C.Structure):
+    _fields_ = [("n_envs", C.c_int32), ("max_obj", C.c_int32), ("n_obj", C.c_void_p), ("type", C.c_void_p),
+                ("shape", C.c_void_p), ("rot", C.c_void_p), ("trans", C.c_void_p)]
+
+
+class etac_model(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("alpha", C.c_void_p), ("phi", C.c_void_p)]
+
+
+class EtacError(RuntimeError):
+    def __init__(self, fn, status):
+        msg = lib().etac_status_string(status).decode()
+        extra = ""
+        if status == -5:
+            extra = f" (HIP error {lib().etac_last_hip_error()})"
+        super().__init__(f"{fn} failed: {status} {msg}{extra}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libetac.so.  Fails loudly if the HIP library has not been built:
+    there is no fallback implementation."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2604_20295_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        P = C.POINTER
+        sig = {
+            "etac_plan_create": ([P(etac_mesh), i32, i32, C.c_uint32, P(vp)], i32),
+            "etac_plan_destroy": ([vp], i32),
+            "etac_contact": ([vp, P(etac_scene), vp, vp, vp, vp], i32),
+            "etac_propagate": ([vp, P(etac_model), i32, vp, vp, vp, vp], i32),
+            "etac_step": ([vp, P(etac_scene), P(etac_model), vp, vp, vp, vp], i32),
+            "etac_contact_backward": ([vp, P(etac_scene), vp, vp, vp, vp], i32),
+            "etac_propagate_backward": ([vp, P(etac_model), i32, vp, vp, vp, vp, vp, vp, vp], i32),
+            "etac_step_backward": ([vp, P(etac_scene), P(etac_model), vp, vp, vp, vp, vp, vp], i32),
+            "etac_status_string": ([i32], C.c_char_p),
+            "etac_last_hip_error": ([], i32),
+            "etac_plan_info": ([vp, P(i32), P(i32), P(i64)], i32),
+            "etac_plan_set_occupancy": ([vp, i32], i32),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(fn, status):
+    if status != ETAC_OK:
+        raise EtacError(fn, status)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    import torch
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _req(t, dtype, shape, name, device):
+    import torch
+    if t is None:
+        return
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous() or t.device != device:
+        raise ValueError(f"{name}: expected contiguous {dtype} {tuple(shape)} on {device}, "
+                         f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+
+
+class Plan:
+    """An etac_plan for one mesh (host arrays, scenes.Mesh layout) on the
+    current GPU, sized for up to n_envs envs with up to max_obj objects."""
+
+    def __init__(self, patch_offset, pos, nrm, origin, n_envs, max_obj, backward=False):
+        import torch
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self._off = np.ascontiguousarray(patch_offset, dtype=np.int32)
+        self._pos = np.ascontiguousarray(pos, dtype=np.float32)
+        self._nrm = np.ascontiguousarray(nrm, dtype=np.float32)
+        self._origin = np.ascontiguousarray(origin, dtype=np.float32)
+        self.K = int(self._off.shape[0] - 1)
+        self.N = int(self._pos.shape[1])
+        self.n_envs, self.max_obj = int(n_envs), int(max_obj)
+        m = etac_mesh(self.K, self.N, self._off.ctypes.data, self._pos.ctypes.data, self._nrm.ctypes.data,
+                      self._origin.ctypes.data)
+        h = C.c_void_p()
+        _check("etac_plan_create", lib().etac_plan_create(C.byref(m), self.n_envs, self.max_obj,
+                                                          ETAC_PLAN_BACKWARD if backward else 0, C.byref(h)))
+        self.handle = h
+
+    @classmethod
+    def from_mesh(cls, mesh, n_envs, max_obj, backward=False):
+        return cls(mesh.patch_offset, mesh.pos, mesh.nrm, mesh.origin, n_envs, max_obj, backward)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().etac_plan_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        n_items, grid, nbytes = C.c_int32(), C.c_int32(), C.c_int64()
+        _check("etac_plan_info", lib().etac_plan_info(self.handle, C.byref(n_items), C.byref(grid), C.byref(nbytes)))
+        return dict(n_items=n_items.value, grid=grid.value, scratch_bytes=nbytes.value)
+
+    def set_occupancy(self, wg_per_cu):
+        _check("etac_plan_set_occupancy", lib().etac_plan_set_occupancy(self.handle, int(wg_per_cu)))
+
+    # -- struct marshalling ---------------------------------------------------
+    def scene_struct(self, n_obj, type_, shape, rot, trans):
+        import torch
+        E, O = int(type_.shape[0]), int(type_.shape[1])
+        _req(n_obj, torch.int32, (E,), "n_obj", self.device)
+        _req(type_, torch.int32, (E, O), "type", self.device)
+        _req(shape, torch.float32, (E, O, 4), "shape", self.device)
+        _req(rot, torch.float32, (E, O, 9), "rot", self.device)
+        _req(trans, torch.float32, (E, O, 3), "trans", self.device)
+        return etac_scene(E, O, _ptr(n_obj), _ptr(type_), _ptr(shape), _ptr(rot), _ptr(trans))
+
+    def model_struct(self, mode, alpha, phi):
+        import torch
+        _req(alpha, torch.float32, (self.K,), "alpha", self.device)
+        _req(phi, torch.float32, (ETAC_PHI_SIZE,), "phi", self.device)
+        return etac_model(int(mode), _ptr(alpha), _ptr(phi))
+
+
+def etac_contact(plan, scene, contact_obj, uhat, n_active):
+    import torch
+    E = scene.n_envs
+    _req(contact_obj, torch.int8, (E, plan.N), "contact_obj", plan.device)
+    _req(uhat, torch.float32, (3, E, plan.N), "uhat", plan.device)
+    _req(n_active, torch.int32, (E, plan.K), "n_active", plan.device)
+    _check("etac_contact", lib().etac_contact(plan.handle, C.byref(scene), _ptr(contact_obj), _ptr(uhat),
+                                              _ptr(n_active), _stream(plan.device)))
+
+
+def etac_propagate(plan, model, n_envs, contact_obj, uhat, u):
+    import torch
+    E = int(n_envs)
+    _req(contact_obj, torch.int8, (E, plan.N), "contact_obj", plan.device)
+    _req(uhat, torch.float32, (3, E, plan.N), "uhat", plan.device)
+    _req(u, torch.float32, (3, E, plan.N), "u", plan.device)
+    _check("etac_propagate", lib().etac_propagate(plan.handle, C.byref(model), E, _ptr(contact_obj), _ptr(uhat),
+                                                  _ptr(u), _stream(plan.device)))
+
+
+def etac_step(plan, scene, model, u, contact_obj, n_active):
+    import torch
+    E = scene.n_envs
+    _req(u, torch.float32, (3, E, plan.N), "u", plan.device)
+    _req(contact_obj, torch.int8, (E, plan.N), "contact_obj", plan.device)
+    _req(n_active, torch.int32, (E, plan.K), "n_active", plan.device)
+    _check("etac_step", lib().etac_step(plan.handle, C.byref(scene), C.byref(model), _ptr(u), _ptr(contact_obj),
+                                        _ptr(n_active), _stream(plan.device)))
+
+
+def etac_contact_backward(plan, scene, grad_uhat, grad_rot, grad_trans):
+    import torch
+    E, O = scene.n_envs, scene.max_obj
+    _req(grad_uhat, torch.float32, (3, E, plan.N), "grad_uhat", plan.device)
+    _req(grad_rot, torch.float32, (E, O, 9), "grad_rot", plan.device)
+    _req(grad_trans, torch.float32, (E, O, 3), "grad_trans", plan.device)
+    _check("etac_contact_backward", lib().etac_contact_backward(plan.handle, C.byref(scene), _ptr(grad_uhat),
+                                                                _ptr(grad_rot), _ptr(grad_trans),
+                                                                _stream(plan.device)))
+
+
+def etac_propagate_backward(plan, model, n_envs, contact_obj, uhat, grad_u, grad_uhat, grad_alpha, grad_phi):
+    import torch
+    E = int(n_envs)
+    _req(contact_obj, torch.int8, (E, plan.N), "contact_obj", plan.device)
+    _req(uhat, torch.float32, (3, E, plan.N), "uhat", plan.device)
+    _req(grad_u, torch.float32, (3, E, plan.N), "grad_u", plan.device)
+    _req(grad_uhat, torch.float32, (3, E, plan.N), "grad_uhat", plan.device)
+    _req(grad_alpha, torch.float32, (plan.K,), "grad_alpha", plan.device)
+    _req(grad_phi, torch.float32, (ETAC_PHI_SIZE,), "grad_phi", plan.device)
+    _check("etac_propagate_backward",
+           lib().etac_propagate_backward(plan.handle, C.byref(model), E, _ptr(contact_obj), _ptr(uhat),
+                                         _ptr(grad_u), _ptr(grad_uhat), _ptr(grad_alpha), _ptr(grad_phi),
+                                         _stream(plan.device)))
+
+
+def etac_step_backward(plan, scene, model, grad_u, grad_rot, grad_trans, grad_alpha, grad_phi):
+    import torch
+    E, O = scene.n_envs, scene.max_obj
+    _req(grad_u, torch.float32, (3, E, plan.N), "grad_u", plan.device)
+    _req(grad_rot, torch.float32, (E, O, 9), "grad_rot", plan.device)
+    _req(grad_trans, torch.float32, (E, O, 3), "grad_trans", plan.device)
+    _req(grad_alpha, torch.float32, (plan.K,), "grad_alpha", plan.device)
+    _req(grad_phi, torch.float32, (ETAC_PHI_SIZE,), "grad_phi", plan.device)
+    _check("etac_step_backward",
+           lib().etac_step_backward(plan.handle, C.byref(scene), C.byref(model), _ptr(grad_u), _ptr(grad_rot),
+                                    _ptr(grad_trans), _ptr(grad_alpha), _ptr(grad_phi), _stream(plan.device)))

@@ -1,0 +1,332 @@
+// Host side of the C ABI declared in include/etac.h: plan creation (mesh
+// validation and upload, conservative per-patch bounding spheres, the
+// longest-patch-first item order, scratch allocation) and argument validation
+// for every call.  Nothing here computes the method; all arithmetic of the
+// step runs in the kernels.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <vector>
+
+#include "etac_internal.h"
+
+struct etac_plan {
+    etac::Plan p;
+};
+
+namespace {
+
+thread_local int32_t g_last_hip = 0;
+
+etac_status hip_fail(hipError_t e) {
+    g_last_hip = (int32_t)e;
+    return ETAC_ERR_HIP;
+}
+
+template <typename T>
+hipError_t plan_alloc(etac::Plan &p, T **ptr, size_t count) {
+    *ptr = nullptr;
+    if (count == 0) count = 1;
+    if (p.n_allocs >= (int)(sizeof(p.allocs) / sizeof(p.allocs[0]))) return hipErrorOutOfMemory;
+    void *v = nullptr;
+    hipError_t e = hipMalloc(&v, count * sizeof(T));
+    if (e != hipSuccess) return e;
+    p.allocs[p.n_allocs++] = v;
+    p.scratch_bytes += (int64_t)(count * sizeof(T));
+    *ptr = static_cast<T *>(v);
+    return hipSuccess;
+}
+
+void plan_free_all(etac::Plan &p) {
+    for (int i = 0; i < p.n_allocs; ++i) (void)hipFree(p.allocs[i]);
+    p.n_allocs = 0;
+}
+
+// Round a non-negative double up to the next float at or above it.
+float round_up_float(double v) {
+    float f = (float)v;
+    if ((double)f < v) f = std::nextafter(f, std::numeric_limits<float>::infinity());
+    return f;
+}
+
+etac_status check_scene(const etac::Plan &p, const etac_scene *s) {
+    if (!s) return ETAC_ERR_NULL;
+    if (s->n_envs < 0 || s->n_envs > p.n_envs) return ETAC_ERR_SHAPE;
+    if (s->max_obj < 1 || s->max_obj > p.max_obj) return ETAC_ERR_SHAPE;
+    if (s->n_envs > 0 && (!s->n_obj || !s->type || !s->shape || !s->rot || !s->trans)) return ETAC_ERR_NULL;
+    return ETAC_OK;
+}
+
+etac_status check_model(const etac_model *m) {
+    if (!m) return ETAC_ERR_NULL;
+    if (m->mode != ETAC_FULL && m->mode != ETAC_DECAY_ONLY && m->mode != ETAC_RESIDUAL_ONLY) return ETAC_ERR_VALUE;
+    if (!m->alpha) return ETAC_ERR_NULL;
+    if (!m->phi && m->mode != ETAC_DECAY_ONLY) return ETAC_ERR_VALUE;
+    return ETAC_OK;
+}
+
+etac::SceneDev scene_dev(const etac_scene *s) {
+    return etac::SceneDev{s->n_obj, s->type, s->shape, s->rot, s->trans, s->n_envs, s->max_obj};
+}
+
+etac::ModelDev model_dev(const etac_model *m) { return etac::ModelDev{m->mode, m->alpha, m->phi}; }
+
+}  // namespace
+
+extern "C" {
+
+const char *etac_status_string(etac_status s) {
+    switch (s) {
+        case ETAC_OK: return "ok";
+        case ETAC_ERR_NULL: return "required pointer is NULL";
+        case ETAC_ERR_SHAPE: return "sizes negative, inconsistent with the plan, or too large";
+        case ETAC_ERR_VALUE: return "invalid mode, flags or value";
+        case ETAC_ERR_WORKSPACE: return "plan lacks the scratch this call needs (create it with ETAC_PLAN_BACKWARD)";
+        case ETAC_ERR_HIP: return "HIP runtime error (see etac_last_hip_error)";
+        case ETAC_ERR_CAPTURE: return "plan creation is not allowed during stream capture";
+        default: return "unknown status";
+    }
+}
+
+int32_t etac_last_hip_error(void) { return g_last_hip; }
+
+etac_status etac_plan_create(const etac_mesh *mesh, int32_t n_envs, int32_t max_obj, uint32_t flags,
+                             etac_plan **out) {
+    if (!mesh || !out) return ETAC_ERR_NULL;
+    if (!mesh->patch_offset || !mesh->pos || !mesh->nrm || !mesh->origin) return ETAC_ERR_NULL;
+    const int K = mesh->n_patches, N = mesh->n_nodes;
+    if (K < 1 || K > etac::kMaxPatches || N < 1) return ETAC_ERR_SHAPE;
+    if (n_envs < 1 || max_obj < 1 || max_obj > ETAC_MAX_OBJ) return ETAC_ERR_SHAPE;
+    if (flags & ~ETAC_PLAN_BACKWARD) return ETAC_ERR_VALUE;
+    if (mesh->patch_offset[0] != 0 || mesh->patch_offset[K] != N) return ETAC_ERR_SHAPE;
+    int n_max = 0;
+    for (int k = 0; k < K; ++k) {
+        const int64_t n = (int64_t)mesh->patch_offset[k + 1] - mesh->patch_offset[k];
+        if (n < 1 || n > ETAC_MAX_PATCH_NODES) return ETAC_ERR_SHAPE;
+        n_max = std::max(n_max, (int)n);
+    }
+    if ((int64_t)n_envs * K > std::numeric_limits<int32_t>::max()) return ETAC_ERR_SHAPE;
+    if ((int64_t)n_envs * N > (std::numeric_limits<int64_t>::max() / 16)) return ETAC_ERR_SHAPE;
+    for (int64_t i = 0; i < 3 * (int64_t)N; ++i)
+        if (!std::isfinite(mesh->pos[i]) || !std::isfinite(mesh->nrm[i])) return ETAC_ERR_VALUE;
+    for (int i = 0; i < 3 * K; ++i)
+        if (!std::isfinite(mesh->origin[i])) return ETAC_ERR_VALUE;
+
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(nullptr, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return ETAC_ERR_CAPTURE;
+
+    etac_plan *h = new (std::nothrow) etac_plan();
+    if (!h) return ETAC_ERR_SHAPE;
+    etac::Plan &p = h->p;
+    std::memset(&p, 0, sizeof(p));
+    p.flags = flags;
+    p.n_envs = n_envs;
+    p.max_obj = max_obj;
+    p.K = K;
+    p.N = N;
+    p.n_max = n_max;
+    p.wg_per_cu = etac::kDefaultWgPerCu;
+    hipError_t e = hipGetDevice(&p.device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&p.cu_count, hipDeviceAttributeMultiprocessorCount, p.device);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e);
+    }
+    p.grid = p.cu_count * p.wg_per_cu;
+
+    // host-side tables
+    std::vector<float4> bound(K);
+    std::vector<int16_t> node_patch(N);
+    std::vector<int> order(K);
+    for (int k = 0; k < K; ++k) {
+        const int o0 = mesh->patch_offset[k], o1 = mesh->patch_offset[k + 1];
+        double lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) { lo[a] = 1e300; hi[a] = -1e300; }
+        for (int i = o0; i < o1; ++i)
+            for (int a = 0; a < 3; ++a) {
+                const double v = mesh->pos[(size_t)a * N + i];
+                lo[a] = std::min(lo[a], v);
+                hi[a] = std::max(hi[a], v);
+            }
+        double c[3];
+        for (int a = 0; a < 3; ++a) c[a] = 0.5 * (lo[a] + hi[a]);
+        float cf[3];
+        for (int a = 0; a < 3; ++a) cf[a] = (float)c[a];
+        double rad = 0.0;
+        for (int i = o0; i < o1; ++i) {
+            double d2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                const double d = (double)mesh->pos[(size_t)a * N + i] - (double)cf[a];
+                d2 += d * d;
+            }
+            rad = std::max(rad, std::sqrt(d2));
+            node_patch[i] = (int16_t)k;
+        }
+        bound[k] = make_float4(cf[0], cf[1], cf[2], round_up_float(rad * (1.0 + 1e-6) + 1e-4));
+        order[k] = k;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return (mesh->patch_offset[a + 1] - mesh->patch_offset[a]) > (mesh->patch_offset[b + 1] - mesh->patch_offset[b]);
+    });
+
+    float *pos = nullptr, *nrm = nullptr, *origin = nullptr;
+    int *offset = nullptr, *ord = nullptr;
+    float4 *bnd = nullptr;
+    int16_t *np = nullptr;
+    e = plan_alloc(p, &pos, 3 * (size_t)N);
+    if (e == hipSuccess) e = plan_alloc(p, &nrm, 3 * (size_t)N);
+    if (e == hipSuccess) e = plan_alloc(p, &origin, 3 * (size_t)K);
+    if (e == hipSuccess) e = plan_alloc(p, &offset, (size_t)K + 1);
+    if (e == hipSuccess) e = plan_alloc(p, &ord, (size_t)K);
+    if (e == hipSuccess) e = plan_alloc(p, &bnd, (size_t)K);
+    if (e == hipSuccess) e = plan_alloc(p, &np, (size_t)N);
+    if (e == hipSuccess) e = hipMemcpy(pos, mesh->pos, 3 * (size_t)N * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(nrm, mesh->nrm, 3 * (size_t)N * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(origin, mesh->origin, 3 * (size_t)K * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(offset, mesh->patch_offset, ((size_t)K + 1) * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ord, order.data(), (size_t)K * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(bnd, bound.data(), (size_t)K * sizeof(float4), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(np, node_patch.data(), (size_t)N * sizeof(int16_t), hipMemcpyHostToDevice);
+    p.mesh = etac::MeshDev{pos, nrm, origin, offset, bnd, np, ord, K, N, n_max};
+
+    // forward scratch, one slice per persistent workgroup
+    const size_t G = (size_t)p.cu_count * 8;  // enough for any occupancy override
+    p.scr.n_max = n_max;
+    if (e == hipSuccess) e = plan_alloc(p, &p.scr.uhat_node, G * 3 * n_max);
+    if (e == hipSuccess) e = plan_alloc(p, &p.scr.resid, G * 3 * n_max);
+    if (e == hipSuccess) e = plan_alloc(p, &p.scr.alist, G * n_max);
+    if (e == hipSuccess) e = plan_alloc(p, &p.scr.plist, G * n_max);
+    if (e == hipSuccess) e = plan_alloc(p, &p.scr.counter, 4);
+    if (e == hipSuccess) e = hipMemset(p.scr.counter, 0, 4 * sizeof(unsigned));
+
+    if (e == hipSuccess && (flags & ETAC_PLAN_BACKWARD)) {
+        const size_t items = (size_t)n_envs * K;
+        etac::BwdScratch &b = p.bwd;
+        e = plan_alloc(p, &b.gfeat, G * (size_t)n_max * 64);
+        if (e == hipSuccess) e = plan_alloc(p, &b.guhat, G * 3 * (size_t)n_max);
+        if (e == hipSuccess) e = plan_alloc(p, &b.phi_part, items * ETAC_PHI_SIZE);
+        if (e == hipSuccess) e = plan_alloc(p, &b.alpha_part, items);
+        if (e == hipSuccess) e = plan_alloc(p, &b.pose_part, items * (size_t)max_obj * 12);
+        if (e == hipSuccess) e = plan_alloc(p, &b.item_flag, items);
+        if (e == hipSuccess) e = plan_alloc(p, &b.item_list, items);
+        if (e == hipSuccess) e = plan_alloc(p, &b.n_list, 1);
+        if (e == hipSuccess) e = plan_alloc(p, &b.phi_seg, (size_t)64 * ETAC_PHI_SIZE);
+        p.has_bwd = (e == hipSuccess);
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        const etac_status st = (e == hipErrorStreamCaptureUnsupported || e == hipErrorStreamCaptureImplicit)
+                                   ? ETAC_ERR_CAPTURE : hip_fail(e);
+        plan_free_all(p);
+        delete h;
+        return st;
+    }
+    *out = h;
+    return ETAC_OK;
+}
+
+etac_status etac_plan_destroy(etac_plan *plan) {
+    if (!plan) return ETAC_OK;
+    (void)hipDeviceSynchronize();
+    plan_free_all(plan->p);
+    delete plan;
+    return ETAC_OK;
+}
+
+etac_status etac_plan_info(const etac_plan *plan, int32_t *n_items, int32_t *grid, int64_t *scratch_bytes) {
+    if (!plan) return ETAC_ERR_NULL;
+    if (n_items) *n_items = plan->p.n_envs * plan->p.K;
+    if (grid) *grid = plan->p.grid;
+    if (scratch_bytes) *scratch_bytes = plan->p.scratch_bytes;
+    return ETAC_OK;
+}
+
+etac_status etac_plan_set_occupancy(etac_plan *plan, int32_t wg_per_cu) {
+    if (!plan) return ETAC_ERR_NULL;
+    if (wg_per_cu < 0 || wg_per_cu > 8) return ETAC_ERR_VALUE;
+    plan->p.wg_per_cu = wg_per_cu == 0 ? etac::kDefaultWgPerCu : wg_per_cu;
+    plan->p.grid = plan->p.cu_count * plan->p.wg_per_cu;
+    return ETAC_OK;
+}
+
+etac_status etac_contact(etac_plan *plan, const etac_scene *scene, int8_t *contact_obj, float *uhat,
+                         int32_t *n_active, void *stream) {
+    if (!plan) return ETAC_ERR_NULL;
+    etac_status st = check_scene(plan->p, scene);
+    if (st != ETAC_OK) return st;
+    if (scene->n_envs > 0 && (!contact_obj || !n_active)) return ETAC_ERR_NULL;
+    hipError_t e = etac::launch_contact(plan->p, scene_dev(scene), contact_obj, uhat, n_active, (hipStream_t)stream);
+    return e == hipSuccess ? ETAC_OK : hip_fail(e);
+}
+
+etac_status etac_propagate(etac_plan *plan, const etac_model *model, int32_t n_envs, const int8_t *contact_obj,
+                           const float *uhat, float *u, void *stream) {
+    if (!plan) return ETAC_ERR_NULL;
+    etac_status st = check_model(model);
+    if (st != ETAC_OK) return st;
+    if (n_envs < 0 || n_envs > plan->p.n_envs) return ETAC_ERR_SHAPE;
+    if (n_envs > 0 && (!contact_obj || !uhat || !u)) return ETAC_ERR_NULL;
+    hipError_t e = etac::launch_step(plan->p, nullptr, model_dev(model), n_envs, contact_obj, uhat, u, nullptr,
+                                     nullptr, (hipStream_t)stream);
+    return e == hipSuccess ? ETAC_OK : hip_fail(e);
+}
+
+etac_status etac_step(etac_plan *plan, const etac_scene *scene, const etac_model *model, float *u,
+                      int8_t *contact_obj, int32_t *n_active, void *stream) {
+    if (!plan) return ETAC_ERR_NULL;
+    etac_status st = check_scene(plan->p, scene);
+    if (st != ETAC_OK) return st;
+    st = check_model(model);
+    if (st != ETAC_OK) return st;
+    if (scene->n_envs > 0 && (!u || !contact_obj || !n_active)) return ETAC_ERR_NULL;
+    const etac::SceneDev sd = scene_dev(scene);
+    hipError_t e = etac::launch_step(plan->p, &sd, model_dev(model), scene->n_envs, nullptr, nullptr, u,
+                                     contact_obj, n_active, (hipStream_t)stream);
+    return e == hipSuccess ? ETAC_OK : hip_fail(e);
+}
+
+etac_status etac_contact_backward(etac_plan *plan, const etac_scene *scene, const float *grad_uhat,
+                                  float *grad_rot, float *grad_trans, void *stream) {
+    if (!plan) return ETAC_ERR_NULL;
+    etac_status st = check_scene(plan->p, scene);
+    if (st != ETAC_OK) return st;
+    if (scene->n_envs > 0 && (!grad_uhat || !grad_rot || !grad_trans)) return ETAC_ERR_NULL;
+    if (!plan->p.has_bwd) return ETAC_ERR_WORKSPACE;
+    hipError_t e = etac::launch_contact_backward(plan->p, scene_dev(scene), grad_uhat, grad_rot, grad_trans,
+                                                 (hipStream_t)stream);
+    return e == hipSuccess ? ETAC_OK : hip_fail(e);
+}
+
+etac_status etac_propagate_backward(etac_plan *plan, const etac_model *model, int32_t n_envs,
+                                    const int8_t *contact_obj, const float *uhat, const float *grad_u,
+                                    float *grad_uhat, float *grad_alpha, float *grad_phi, void *stream) {
+    if (!plan) return ETAC_ERR_NULL;
+    etac_status st = check_model(model);
+    if (st != ETAC_OK) return st;
+    if (n_envs < 0 || n_envs > plan->p.n_envs) return ETAC_ERR_SHAPE;
+    if (n_envs > 0 && (!contact_obj || !uhat || !grad_u || !grad_uhat)) return ETAC_ERR_NULL;
+    if (!plan->p.has_bwd) return ETAC_ERR_WORKSPACE;
+    hipError_t e = etac::launch_backward(plan->p, nullptr, model_dev(model), n_envs, contact_obj, uhat, grad_u,
+                                         grad_uhat, nullptr, nullptr, grad_alpha, grad_phi, (hipStream_t)stream);
+    return e == hipSuccess ? ETAC_OK : hip_fail(e);
+}
+
+etac_status etac_step_backward(etac_plan *plan, const etac_scene *scene, const etac_model *model,
+                               const float *grad_u, float *grad_rot, float *grad_trans, float *grad_alpha,
+                               float *grad_phi, void *stream) {
+    if (!plan) return ETAC_ERR_NULL;
+    etac_status st = check_scene(plan->p, scene);
+    if (st != ETAC_OK) return st;
+    st = check_model(model);
+    if (st != ETAC_OK) return st;
+    if (scene->n_envs > 0 && (!grad_u || !grad_rot || !grad_trans)) return ETAC_ERR_NULL;
+    if (!plan->p.has_bwd) return ETAC_ERR_WORKSPACE;
+    const etac::SceneDev sd = scene_dev(scene);
+    hipError_t e = etac::launch_backward(plan->p, &sd, model_dev(model), scene->n_envs, nullptr, nullptr, grad_u,
+                                         nullptr, grad_rot, grad_trans, grad_alpha, grad_phi, (hipStream_t)stream);
+    return e == hipSuccess ? ETAC_OK : hip_fail(e);
+}
+
+}  // extern "C"

@@ -1,0 +1,411 @@
+// Device building blocks of the ETac step on gfx950: the pinned FP64 contact
+// predicate, the per-item active/passive compaction and the FP32-MFMA
+// residual network tiles.
+#pragma once
+
+#include "etac_internal.h"
+
+namespace etac {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Offsets of the packed network parameters (layout documented in etac.h).
+constexpr int kW1 = 0, kB1 = 576, kW2 = 640, kB2 = 4736, kW3 = 4800, kB3 = 8896;
+constexpr int kW4 = 8960, kB4 = 17152, kW5 = 17216, kB5 = 17408, kPhiN = 17411;
+
+// ---------------------------------------------------------------------------
+// contact (Sec. III-A: SDF contact of nodes with rigid objects)
+// ---------------------------------------------------------------------------
+
+struct Pen {
+    bool inside;
+    double depth, u0, u1, u2;
+};
+
+// Penetration of a node into one primitive.  FP64, every operation in the
+// order written and rounded to nearest-even, no contraction into FMA:
+//   d = p - t;  q_c = (R[0][c] d_0 + R[1][c] d_1) + R[2][c] d_2
+//   sphere  : s = (d_0^2 + d_1^2) + d_2^2 < r^2,  depth = r - sqrt(s),
+//             u = (depth / sqrt(s)) d
+//   box     : |q_c| < h_c for all c; face = first argmin (h_c - |q_c|);
+//             u = (sign(q_face) depth) R[:, face]  (sign(0) = +1)
+//   capsule : z = clamp(q_2, -L, L), v = (q_0, q_1, q_2 - z), s = v.v < r^2,
+//             u = (depth / sqrt(s)) R v
+// A node on the centre point / axis segment gets depth r and u = -r n.
+// Inside tests are sqrt-free; depth uses the correctly rounded FP64 sqrt, so
+// the inside set and the deepest-object choice are reproducible bit for bit.
+__device__ __forceinline__ Pen penetrate(int type, const float *sh, const float *R, const float *t,
+                                         float px, float py, float pz, float nx, float ny, float nz) {
+#pragma clang fp contract(off)
+    Pen h;
+    h.inside = false;
+    h.depth = 0.0;
+    h.u0 = h.u1 = h.u2 = 0.0;
+    const double d0 = (double)px - (double)t[0];
+    const double d1 = (double)py - (double)t[1];
+    const double d2 = (double)pz - (double)t[2];
+    if (type == ETAC_SPHERE) {
+        const double r = (double)sh[0];
+        const double s = (d0 * d0 + d1 * d1) + d2 * d2;
+        if (!(s < r * r)) return h;
+        h.inside = true;
+        if (s == 0.0) {
+            h.depth = r;
+            h.u0 = -r * (double)nx; h.u1 = -r * (double)ny; h.u2 = -r * (double)nz;
+            return h;
+        }
+        const double l = sqrt(s);
+        h.depth = r - l;
+        const double sc = h.depth / l;
+        h.u0 = sc * d0; h.u1 = sc * d1; h.u2 = sc * d2;
+        return h;
+    }
+    const double r00 = R[0], r01 = R[1], r02 = R[2];
+    const double r10 = R[3], r11 = R[4], r12 = R[5];
+    const double r20 = R[6], r21 = R[7], r22 = R[8];
+    const double q0 = (r00 * d0 + r10 * d1) + r20 * d2;
+    const double q1 = (r01 * d0 + r11 * d1) + r21 * d2;
+    const double q2 = (r02 * d0 + r12 * d1) + r22 * d2;
+    if (type == ETAC_BOX) {
+        const double h0 = sh[0], h1 = sh[1], h2 = sh[2];
+        if (!(fabs(q0) < h0)) return h;
+        if (!(fabs(q1) < h1)) return h;
+        if (!(fabs(q2) < h2)) return h;
+        h.inside = true;
+        double best = h0 - fabs(q0);
+        int cs = 0;
+        double qs = q0;
+        const double s1 = h1 - fabs(q1);
+        if (s1 < best) { best = s1; cs = 1; qs = q1; }
+        const double s2 = h2 - fabs(q2);
+        if (s2 < best) { best = s2; cs = 2; qs = q2; }
+        h.depth = best;
+        const double a = (qs >= 0.0) ? best : -best;
+        const double c0 = cs == 0 ? r00 : (cs == 1 ? r01 : r02);
+        const double c1 = cs == 0 ? r10 : (cs == 1 ? r11 : r12);
+        const double c2 = cs == 0 ? r20 : (cs == 1 ? r21 : r22);
+        h.u0 = a * c0; h.u1 = a * c1; h.u2 = a * c2;
+        return h;
+    }
+    const double r = sh[0], L = sh[1];
+    double z = q2;
+    if (z < -L) z = -L;
+    else if (z > L) z = L;
+    const double v0 = q0, v1 = q1, v2 = q2 - z;
+    const double s = (v0 * v0 + v1 * v1) + v2 * v2;
+    if (!(s < r * r)) return h;
+    h.inside = true;
+    if (s == 0.0) {
+        h.depth = r;
+        h.u0 = -r * (double)nx; h.u1 = -r * (double)ny; h.u2 = -r * (double)nz;
+        return h;
+    }
+    const double l = sqrt(s);
+    h.depth = r - l;
+    const double sc = h.depth / l;
+    h.u0 = sc * ((r00 * v0 + r01 * v1) + r02 * v2);
+    h.u1 = sc * ((r10 * v0 + r11 * v1) + r12 * v2);
+    h.u2 = sc * ((r20 * v0 + r21 * v1) + r22 * v2);
+    return h;
+}
+
+// Radius of a ball around the object's origin that contains the primitive.
+__device__ __forceinline__ float bounding_radius(int type, const float *sh) {
+    if (type == ETAC_SPHERE) return sh[0];
+    if (type == ETAC_BOX) return sqrtf(sh[0] * sh[0] + sh[1] * sh[1] + sh[2] * sh[2]);
+    return sh[0] + sh[1];
+}
+
+// Contact of one node with the candidate objects of env e (bit o of `cand`).
+// A cheap FP32 ball test with a relative margin of 1e-3 (far above FP32
+// rounding) skips objects that cannot contain the node; survivors take the
+// exact FP64 test.  Deepest penetration wins, lowest index on ties.
+// Returns the winning object or -1; u is the winner's u_hat rounded to FP32.
+__device__ __forceinline__ int contact_node(const SceneDev &S, int e, unsigned cand, float px, float py,
+                                            float pz, float nx, float ny, float nz, float &u0, float &u1,
+                                            float &u2) {
+    int best = -1;
+    double bd = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
+    const int no = min(S.n_obj[e], S.O);   // device contents are not validated on the host
+    for (int o = 0; o < no; ++o) {
+        if (!((cand >> o) & 1u)) continue;
+        const size_t eo = (size_t)e * S.O + o;
+        const int ty = S.type[eo];
+        const float *sh = S.shape + 4 * eo;
+        const float *R = S.rot + 9 * eo;
+        const float *t = S.trans + 3 * eo;
+        const float dx = px - t[0], dy = py - t[1], dz = pz - t[2];
+        const float rb = bounding_radius(ty, sh) * 1.001f + 1e-3f;
+        if (dx * dx + dy * dy + dz * dz > rb * rb) continue;
+        const Pen h = penetrate(ty, sh, R, t, px, py, pz, nx, ny, nz);
+        if (h.inside && (best < 0 || h.depth > bd)) {
+            best = o;
+            bd = h.depth;
+            b0 = h.u0; b1 = h.u1; b2 = h.u2;
+        }
+    }
+    u0 = (float)b0; u1 = (float)b1; u2 = (float)b2;
+    return best;
+}
+
+// Objects of env e whose bounding ball may reach patch k's bounding sphere.
+__device__ __forceinline__ unsigned cull_objects(const SceneDev &S, const MeshDev &M, int e, int k) {
+    unsigned cand = 0;
+    const int no = min(S.n_obj[e], S.O);
+    const float4 b = M.bound[k];
+    for (int o = 0; o < no; ++o) {
+        const size_t eo = (size_t)e * S.O + o;
+        const float *t = S.trans + 3 * eo;
+        const float dx = b.x - t[0], dy = b.y - t[1], dz = b.z - t[2];
+        const float reach = (b.w + bounding_radius(S.type[eo], S.shape + 4 * eo)) * 1.001f + 1e-3f;
+        const float d2 = dx * dx + dy * dy + dz * dz;
+        if (d2 * (1.0f - 1e-5f) <= reach * reach) cand |= 1u << o;
+    }
+    return cand;
+}
+
+// ---------------------------------------------------------------------------
+// wave helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Values that are equal across the workgroup but come from LDS must be made
+// visibly uniform before they steer control flow that contains barriers:
+// otherwise the compiler treats the branch as divergent and may split a wave
+// around a barrier (e.g. one lane leaving to finish a store while the others
+// re-enter the barrier and read stale LDS).
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ unsigned uniform(unsigned v) { return (unsigned)__builtin_amdgcn_readfirstlane((int)v); }
+
+__device__ __forceinline__ unsigned lanes_below(unsigned long long mask) {
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+// Contact (or given contact results) for every node of one (env, patch)
+// item, then the active and passive node lists in ascending node order
+// (wave ballots, prefix over waves).  Writes u_hat of every node into `uhn`
+// ([3][n_max], 0 on passive nodes), the winner into `wobj` when given, and
+// contact_obj into `cobj_out` when computing contact.  Returns m.
+template <bool FROM_INPUT>
+__device__ int contact_and_compact(const MeshDev &M, const SceneDev &Sc, int E, int n_max, const int8_t *cobj_in,
+                                   const float *uhat_in, int8_t *cobj_out, int (&wcnt)[2][kWaves], int e, int k,
+                                   int base, int n, unsigned cand, float *uhn, int *alist, int *plist,
+                                   int8_t *wobj) {
+    const int N = M.N;
+    const size_t EN = (size_t)E * N;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    int run_a = 0, run_p = 0;
+    for (int i0 = 0; i0 < n; i0 += kWG) {
+        const int i = i0 + threadIdx.x;
+        const bool valid = i < n;
+        int best = -1;
+        float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f;
+        if (valid) {
+            const int gi = base + i;
+            const size_t en = (size_t)e * N + gi;
+            if (FROM_INPUT) {
+                best = cobj_in[en] >= 0 ? (int)cobj_in[en] : -1;
+                if (best >= 0) {
+                    u0 = uhat_in[en];
+                    u1 = uhat_in[EN + en];
+                    u2 = uhat_in[2 * EN + en];
+                }
+            } else {
+                best = contact_node(Sc, e, cand, M.pos[gi], M.pos[N + gi], M.pos[2 * N + gi], M.nrm[gi],
+                                    M.nrm[N + gi], M.nrm[2 * N + gi], u0, u1, u2);
+                if (cobj_out) cobj_out[en] = (int8_t)best;
+            }
+            uhn[i] = u0;
+            uhn[n_max + i] = u1;
+            uhn[2 * n_max + i] = u2;
+            if (wobj) wobj[i] = (int8_t)best;
+        }
+        const bool act = valid && best >= 0, pas = valid && best < 0;
+        const unsigned long long ba = __ballot(act), bp = __ballot(pas);
+        // every lane stores the same wave counts (no single-lane block next to the barrier)
+        wcnt[0][wave] = __popcll(ba);
+        wcnt[1][wave] = __popcll(bp);
+        __syncthreads();
+        int oa = run_a, op = run_p, ta = 0, tp = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            if (w < wave) { oa += wcnt[0][w]; op += wcnt[1][w]; }
+            ta += wcnt[0][w];
+            tp += wcnt[1][w];
+        }
+        if (act) alist[oa + lanes_below(ba)] = i;
+        if (pas) plist[op + lanes_below(bp)] = i;
+        run_a += uniform(ta);
+        run_p += uniform(tp);
+        __syncthreads();
+    }
+    return uniform(run_a);
+}
+
+// ---------------------------------------------------------------------------
+// residual network Phi on FP32 MFMA (v_mfma_f32_16x16x4_f32)
+//
+// A 16-node tile is processed by one wave in transposed form, Y^T = W X^T:
+// the MFMA's M dimension is the layer's output features, N the 16 nodes, K the
+// input features.  Lane l holds node (l & 15); after a layer it holds output
+// features 16*ot + 4*(l >> 4) + r (r = 0..3) of out-tile ot in register r of
+// accumulator ot, which is exactly the B-operand layout the next layer needs
+// when its K steps are ordered (ot, r).  Weights are pre-arranged in LDS in
+// that fragment order, so every A operand is one conflict-free LDS read.
+// ---------------------------------------------------------------------------
+struct NetLds {
+    float w1f[4 * 3 * 64];       // [ot][s][lane]   W1, inputs padded 9 -> 12
+    floatx4 w2f[4 * 4 * 64];     // [ot2][ot][lane] W2 fragments, r in the vector
+    floatx4 w4f[4 * 4 * 64];     // [ot2][ot][lane] W4 columns 0..63 (per-node part)
+    float b1[64], b2[64];
+    float c4[64];                // W4[:, 64:] g' + b4, per item
+    float w5[3 * 64];
+    float b5[4];
+    float g[64], gp[64];         // pooled feature and global MLP output
+    float part[kWaves][64];      // per-wave partials
+};
+
+// Stage the network into LDS in fragment order (whole workgroup).
+__device__ void stage_net(NetLds &L, const float *phi) {
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < 4 * 3 * 64; idx += kWG) {
+        const int lane = idx & 63, s = (idx >> 6) % 3, ot = idx / 192;
+        const int in = 4 * s + (lane >> 4);
+        L.w1f[idx] = in < 9 ? phi[kW1 + (ot * 16 + (lane & 15)) * 9 + in] : 0.0f;
+    }
+    for (int idx = tid; idx < 4 * 4 * 64; idx += kWG) {
+        const int lane = idx & 63, ot = (idx >> 6) & 3, ot2 = idx >> 8;
+        const int out = ot2 * 16 + (lane & 15), in = ot * 16 + 4 * (lane >> 4);
+        floatx4 a, b;
+        #pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            a[r] = phi[kW2 + out * 64 + in + r];
+            b[r] = phi[kW4 + out * 128 + in + r];
+        }
+        L.w2f[idx] = a;
+        L.w4f[idx] = b;
+    }
+    for (int i = tid; i < 64; i += kWG) {
+        L.b1[i] = phi[kB1 + i];
+        L.b2[i] = phi[kB2 + i];
+    }
+    for (int i = tid; i < 192; i += kWG) L.w5[i] = phi[kW5 + i];
+    if (tid < 3) L.b5[tid] = phi[kB5 + tid];
+    if (tid == 3) L.b5[3] = 0.0f;
+}
+
+__device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ floatx4 relu4(floatx4 v) {
+    floatx4 o;
+    #pragma unroll
+    for (int r = 0; r < 4; ++r) o[r] = fmaxf(v[r], 0.0f);
+    return o;
+}
+
+// Network input of this lane's node for the three K steps of layer 1: lane
+// group gq = lane >> 4 supplies input feature 4 s + gq of node (lane & 15).
+// Inputs: [p - o_k (3), n (3), U_hat (3)], padded with zeros to 12.
+__device__ __forceinline__ void load_x(const MeshDev &M, int k, int gnode, bool valid,
+                                       const float *uhn, int n_max, int lnode, float xs[3]) {
+    const int gq = lane_id() >> 4;
+    const int N = M.N;
+    xs[0] = xs[1] = xs[2] = 0.0f;
+    if (!valid) return;
+    if (gq < 3) xs[0] = M.pos[(size_t)gq * N + gnode] - M.origin[3 * k + gq];
+    else xs[0] = M.nrm[gnode];
+    if (gq < 2) xs[1] = M.nrm[(size_t)(gq + 1) * N + gnode];
+    else xs[1] = uhn[(size_t)(gq - 2) * n_max + lnode];
+    if (gq == 0) xs[2] = uhn[(size_t)2 * n_max + lnode];
+}
+
+// Encoder: h1 = relu(W1 x + b1), f = relu(W2 h1 + b2) for a 16-node tile.
+__device__ __forceinline__ void encoder_tile(const NetLds &L, const float xs[3], floatx4 h1[4],
+                                             floatx4 f[4]) {
+    const int lane = lane_id(), gq = lane >> 4;
+#pragma unroll
+    for (int ot = 0; ot < 4; ++ot) {
+        floatx4 acc = *reinterpret_cast<const floatx4 *>(&L.b1[ot * 16 + 4 * gq]);
+#pragma unroll
+        for (int s = 0; s < 3; ++s) acc = mfma4(L.w1f[(ot * 3 + s) * 64 + lane], xs[s], acc);
+        h1[ot] = acc;
+    }
+#pragma unroll
+    for (int ot = 0; ot < 4; ++ot) h1[ot] = relu4(h1[ot]);
+#pragma unroll
+    for (int ot2 = 0; ot2 < 4; ++ot2) {
+        floatx4 acc = *reinterpret_cast<const floatx4 *>(&L.b2[ot2 * 16 + 4 * gq]);
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot) {
+            const floatx4 w = L.w2f[(ot2 * 4 + ot) * 64 + lane];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc = mfma4(w[r], h1[ot][r], acc);
+        }
+        f[ot2] = acc;
+    }
+#pragma unroll
+    for (int ot = 0; ot < 4; ++ot) f[ot] = relu4(f[ot]);
+}
+
+// Decoder: h4 = relu(W4 [f; g'] + b4) with the g' part folded into c4, then
+// r = W5 h4 + b5.  Every lane returns r of its node (lane & 15).
+__device__ __forceinline__ void decoder_tile(const NetLds &L, const floatx4 f[4], floatx4 h4[4],
+                                             float r_out[3]) {
+    const int lane = lane_id(), gq = lane >> 4;
+#pragma unroll
+    for (int ot2 = 0; ot2 < 4; ++ot2) {
+        floatx4 acc = *reinterpret_cast<const floatx4 *>(&L.c4[ot2 * 16 + 4 * gq]);
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot) {
+            const floatx4 w = L.w4f[(ot2 * 4 + ot) * 64 + lane];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc = mfma4(w[r], f[ot][r], acc);
+        }
+        h4[ot2] = acc;
+    }
+#pragma unroll
+    for (int ot = 0; ot < 4; ++ot) h4[ot] = relu4(h4[ot]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float s = 0.0f;
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot) {
+            const floatx4 w = *reinterpret_cast<const floatx4 *>(&L.w5[c * 64 + ot * 16 + 4 * gq]);
+            s += w[0] * h4[ot][0] + w[1] * h4[ot][1] + w[2] * h4[ot][2] + w[3] * h4[ot][3];
+        }
+        s += __shfl_xor(s, 16);
+        s += __shfl_xor(s, 32);
+        r_out[c] = s + L.b5[c];
+    }
+}
+
+// Global MLP of one item from the pooled feature in L.g:
+// g' = relu(W3 g + b3) and c4 = W4[:, 64:] g' + b4.  Whole workgroup; each
+// wave sums 16 input features and the four partials are added in wave order.
+__device__ void global_mlp(NetLds &L, const float *phi) {
+    const int tid = threadIdx.x, o = tid & 63, w = tid >> 6;
+    float acc = 0.0f;
+    for (int c = 16 * w; c < 16 * w + 16; ++c) acc += phi[kW3 + o * 64 + c] * L.g[c];
+    L.part[w][o] = acc;
+    __syncthreads();
+    if (tid < 64) {
+        float s = phi[kB3 + o];
+        for (int q = 0; q < kWaves; ++q) s += L.part[q][o];
+        L.gp[o] = fmaxf(s, 0.0f);
+    }
+    __syncthreads();
+    acc = 0.0f;
+    for (int c = 16 * w; c < 16 * w + 16; ++c) acc += phi[kW4 + o * 128 + 64 + c] * L.gp[c];
+    L.part[w][o] = acc;
+    __syncthreads();
+    if (tid < 64) {
+        float s = phi[kB4 + o];
+        for (int q = 0; q < kWaves; ++q) s += L.part[q][o];
+        L.c4[o] = s;
+    }
+    __syncthreads();
+}
+
+}  // namespace etac

@@ -1,0 +1,363 @@
+// Forward kernels of the ETac step on gfx950:
+//   k_contact : contact pass alone, one workgroup per env (HBM-write bound)
+//   k_step    : persistent fused contact + propagation, one (env, patch) item
+//               at a time per workgroup, items taken from a device work queue
+//               in longest-patch-first order.  The same kernel, templated,
+//               propagates given contact results (etac_propagate).
+#include "etac_device.h"
+
+namespace etac {
+
+constexpr int kChunk = 1536;      // active nodes staged in LDS per pass of the decay loop
+
+// ---------------------------------------------------------------------------
+// contact pass alone
+// ---------------------------------------------------------------------------
+struct ContactParams {
+    MeshDev mesh;
+    SceneDev scene;
+    int8_t *cobj;      // [E][N]
+    float *uhat;       // [3][E][N] or null
+    int32_t *n_active; // [E][K]
+};
+
+__global__ __launch_bounds__(kWG) void k_contact(ContactParams p) {
+    __shared__ int cnt[kMaxPatches];
+    const int e = blockIdx.x;
+    const MeshDev &M = p.mesh;
+    const int N = M.N, K = M.K;
+    const size_t EN = (size_t)p.scene.E * N;
+    for (int k = threadIdx.x; k < K; k += kWG) cnt[k] = 0;
+    __syncthreads();
+    const unsigned all = 0xffu;
+    for (int i = threadIdx.x; i < N; i += kWG) {
+        float u0, u1, u2;
+        const int best = contact_node(p.scene, e, all, M.pos[i], M.pos[N + i], M.pos[2 * N + i], M.nrm[i],
+                                      M.nrm[N + i], M.nrm[2 * N + i], u0, u1, u2);
+        const size_t en = (size_t)e * N + i;
+        p.cobj[en] = (int8_t)best;
+        if (p.uhat) {
+            p.uhat[en] = u0;
+            p.uhat[EN + en] = u1;
+            p.uhat[2 * EN + en] = u2;
+        }
+        if (best >= 0) atomicAdd(&cnt[M.node_patch[i]], 1);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += kWG) p.n_active[(size_t)e * K + k] = cnt[k];
+}
+
+hipError_t launch_contact(const Plan &p, const SceneDev &s, int8_t *cobj, float *uhat, int32_t *n_active,
+                          hipStream_t st) {
+    if (s.E == 0) return hipSuccess;
+    ContactParams cp{p.mesh, s, cobj, uhat, n_active};
+    hipLaunchKernelGGL(k_contact, dim3(s.E), dim3(kWG), 0, st, cp);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// persistent fused step
+// ---------------------------------------------------------------------------
+struct StepParams {
+    MeshDev mesh;
+    SceneDev scene;
+    ModelDev model;
+    Scratch scr;
+    int E;
+    int n_items;
+    const int8_t *cobj_in;   // propagate-only: given contact results
+    const float *uhat_in;
+    float *u;                // [3][E][N]
+    int8_t *cobj_out;        // [E][N] (fused step)
+    int32_t *n_active;       // [E][K] (fused step)
+};
+
+struct StepLds {
+    NetLds net;
+    float4 act_a[kChunk];    // (px, py, pz, ux) of staged active nodes
+    float2 act_b[kChunk];    // (uy, uz)
+    int wcnt[2][kWaves];
+    int item;
+    unsigned cand;
+};
+
+// Work queue: counter[0] hands out items, counter[1] counts finished
+// workgroups; the last workgroup resets both so the next launch (or graph
+// replay) starts from zero without a host-side clear.
+//
+// Every block that only part of the workgroup executes is a whole wave (wave
+// 0, storing identical values), and every item ends at a barrier: a block
+// taken by single lanes next to a barrier lets the compiler thread the other
+// lanes of the wave past it into the barrier, which deadlocks the queue.
+__device__ __forceinline__ int next_item(unsigned *counter, StepLds &S) {
+    if (threadIdx.x < 64) {
+        // one atomic for the wave (lane 0 adds 1), every lane learns the result
+        const unsigned old = atomicAdd(&counter[0], lane_id() == 0 ? 1u : 0u);
+        S.item = __shfl((int)old, 0);
+    }
+    __syncthreads();
+    const int it = uniform(S.item);
+    __syncthreads();
+    return it;
+}
+
+__device__ __forceinline__ void retire(unsigned *counter) {
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned done = atomicAdd(&counter[1], 1u);
+        if (done == gridDim.x - 1) {
+            atomicExch(&counter[0], 0u);
+            atomicExch(&counter[1], 0u);
+        }
+    }
+}
+
+// Zero deformation for a patch without contact.
+__device__ __forceinline__ void write_zero_item(const StepParams &p, int e, int base, int n, bool write_cobj) {
+    const size_t EN = (size_t)p.E * p.mesh.N;
+    const size_t row = (size_t)e * p.mesh.N + base;
+    for (int i = threadIdx.x; i < n; i += kWG) {
+        p.u[row + i] = 0.0f;
+        p.u[EN + row + i] = 0.0f;
+        p.u[2 * EN + row + i] = 0.0f;
+        if (write_cobj) p.cobj_out[row + i] = -1;
+    }
+}
+
+// Residual network over the whole patch: max-pool pass, global MLP, then the
+// decoder pass writing r for every node into `resid` ([3][n_max]).  The
+// encoder is recomputed in the decoder pass instead of keeping n x 64
+// features.
+__device__ void residual_item(const StepParams &p, StepLds &S, int k, int base, int n, const float *uhn,
+                              float *resid) {
+    NetLds &L = S.net;
+    const int lane = lane_id(), wave = threadIdx.x >> 6, gq = lane >> 4;
+    const int n_max = p.scr.n_max;
+    const int ntiles = (n + 15) >> 4;
+    floatx4 mx[4];
+    #pragma unroll
+    for (int ot = 0; ot < 4; ++ot) mx[ot] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int t = wave; t < ntiles; t += kWaves) {
+        const int ln = t * 16 + (lane & 15);
+        const bool valid = ln < n;
+        float xs[3];
+        load_x(p.mesh, k, base + ln, valid, uhn, n_max, ln, xs);
+        floatx4 h1[4], f[4];
+        encoder_tile(L, xs, h1, f);
+        // f >= 0, so padding nodes with 0 leaves the max-pool unchanged
+        if (valid)
+            #pragma unroll
+            for (int ot = 0; ot < 4; ++ot)
+                #pragma unroll
+                for (int r = 0; r < 4; ++r) mx[ot][r] = fmaxf(mx[ot][r], f[ot][r]);
+    }
+    #pragma unroll
+    for (int ot = 0; ot < 4; ++ot)
+        #pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float v = mx[ot][r];
+            v = fmaxf(v, __shfl_xor(v, 1));
+            v = fmaxf(v, __shfl_xor(v, 2));
+            v = fmaxf(v, __shfl_xor(v, 4));
+            v = fmaxf(v, __shfl_xor(v, 8));
+            mx[ot][r] = v;
+        }
+    // after the row reduction all 16 lanes of a row hold the same maxima (identical stores)
+        #pragma unroll
+        for (int ot = 0; ot < 4; ++ot)
+            #pragma unroll
+            for (int r = 0; r < 4; ++r) L.part[wave][ot * 16 + 4 * gq + r] = mx[ot][r];
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        float v = L.part[0][threadIdx.x];
+        for (int w = 1; w < kWaves; ++w) v = fmaxf(v, L.part[w][threadIdx.x]);
+        L.g[threadIdx.x] = v;
+    }
+    __syncthreads();
+    global_mlp(L, p.model.phi);
+    for (int t = wave; t < ntiles; t += kWaves) {
+        const int ln = t * 16 + (lane & 15);
+        const bool valid = ln < n;
+        float xs[3];
+        load_x(p.mesh, k, base + ln, valid, uhn, n_max, ln, xs);
+        floatx4 h1[4], f[4], h4[4];
+        encoder_tile(L, xs, h1, f);
+        float r[3];
+        decoder_tile(L, f, h4, r);
+        if (valid && gq < 3) resid[gq * n_max + ln] = r[gq];
+    }
+    __syncthreads();
+}
+
+// Stage active nodes [c0, c0 + cnt) of the item into LDS.
+__device__ __forceinline__ void stage_active(const StepParams &p, StepLds &S, int base, const int *alist,
+                                             const float *uhn, int c0, int cnt) {
+    const MeshDev &M = p.mesh;
+    const int N = M.N, n_max = p.scr.n_max;
+    for (int t = threadIdx.x; t < cnt; t += kWG) {
+        const int j = alist[c0 + t];
+        const int gj = base + j;
+        S.act_a[t] = make_float4(M.pos[gj], M.pos[N + gj], M.pos[2 * N + gj], uhn[j]);
+        S.act_b[t] = make_float2(uhn[n_max + j], uhn[2 * n_max + j]);
+    }
+}
+
+// Eq. 1 over one staged chunk for two passive nodes per thread.  FP32 terms
+// are summed in blocks of 32 and the block sums are accumulated in FP64.
+__device__ __forceinline__ void decay_chunk(const StepLds &S, int cnt, float nbeta, float px0, float py0,
+                                            float pz0, float px1, float py1, float pz1, double acc0[3],
+                                            double acc1[3]) {
+    for (int j0 = 0; j0 < cnt; j0 += 32) {
+        const int j1 = min(cnt, j0 + 32);
+        float s0x = 0.f, s0y = 0.f, s0z = 0.f, s1x = 0.f, s1y = 0.f, s1z = 0.f;
+        for (int j = j0; j < j1; ++j) {
+            const float4 a = S.act_a[j];
+            const float2 b = S.act_b[j];
+            const float dx0 = a.x - px0, dy0 = a.y - py0, dz0 = a.z - pz0;
+            const float dx1 = a.x - px1, dy1 = a.y - py1, dz1 = a.z - pz1;
+            const float d0 = __builtin_amdgcn_sqrtf(dx0 * dx0 + dy0 * dy0 + dz0 * dz0);
+            const float d1 = __builtin_amdgcn_sqrtf(dx1 * dx1 + dy1 * dy1 + dz1 * dz1);
+            const float w0 = __builtin_amdgcn_exp2f(nbeta * d0);
+            const float w1 = __builtin_amdgcn_exp2f(nbeta * d1);
+            s0x += w0 * a.w; s0y += w0 * b.x; s0z += w0 * b.y;
+            s1x += w1 * a.w; s1y += w1 * b.x; s1z += w1 * b.y;
+        }
+        acc0[0] += s0x; acc0[1] += s0y; acc0[2] += s0z;
+        acc1[0] += s1x; acc1[1] += s1y; acc1[2] += s1z;
+    }
+}
+
+template <bool FROM_INPUT>
+__device__ void process_item(const StepParams &p, StepLds &S, int e, int k, float *uhn, float *resid,
+                             int *alist, int *plist) {
+    const MeshDev &M = p.mesh;
+    const int N = M.N, n_max = p.scr.n_max;
+    const size_t EN = (size_t)p.E * N;
+    const int base = M.offset[k];
+    const int n = M.offset[k + 1] - base;
+    const int mode = p.model.mode;
+    unsigned cand = 0xffu;
+    if (!FROM_INPUT) {
+        if (threadIdx.x < 64) S.cand = cull_objects(p.scene, M, e, k);
+        __syncthreads();
+        cand = uniform(S.cand);
+        __syncthreads();
+        if (cand == 0u) {
+            write_zero_item(p, e, base, n, true);
+            if (threadIdx.x < 64) p.n_active[(size_t)e * M.K + k] = 0;
+            __syncthreads();
+            return;
+        }
+    }
+    const int m = contact_and_compact<FROM_INPUT>(M, p.scene, p.E, p.scr.n_max, p.cobj_in, p.uhat_in, p.cobj_out,
+                                                  S.wcnt, e, k, base, n, cand, uhn, alist, plist, nullptr);
+    if (!FROM_INPUT && threadIdx.x < 64) p.n_active[(size_t)e * M.K + k] = m;
+    if (m == 0) {
+        write_zero_item(p, e, base, n, false);
+        __syncthreads();
+        return;
+    }
+    const size_t row = (size_t)e * N + base;
+    // active nodes keep their contact displacement
+    for (int t = threadIdx.x; t < m; t += kWG) {
+        const int i = alist[t];
+        p.u[row + i] = uhn[i];
+        p.u[EN + row + i] = uhn[n_max + i];
+        p.u[2 * EN + row + i] = uhn[2 * n_max + i];
+    }
+    const bool use_res = mode != ETAC_DECAY_ONLY, use_dec = mode != ETAC_RESIDUAL_ONLY;
+    if (use_res) residual_item(p, S, k, base, n, uhn, resid);
+    const int np = n - m;
+    // exp(-alpha d) = exp2(-alpha log2(e) d)
+    const float nbeta = (float)(-(double)p.model.alpha[k] * 1.4426950408889634);
+    const bool one_chunk = m <= kChunk;
+    if (use_dec && one_chunk) {
+        stage_active(p, S, base, alist, uhn, 0, m);
+        __syncthreads();
+    }
+    for (int pb = 0; pb < np; pb += 2 * kWG) {
+        const int t0 = pb + threadIdx.x, t1 = t0 + kWG;
+        const bool v0 = t0 < np, v1 = t1 < np;
+        const int i0 = v0 ? plist[t0] : 0, i1 = v1 ? plist[t1] : 0;
+        const int g0 = base + i0, g1 = base + i1;
+        double a0[3] = {0.0, 0.0, 0.0}, a1[3] = {0.0, 0.0, 0.0};
+        if (use_dec) {
+            const float px0 = M.pos[g0], py0 = M.pos[N + g0], pz0 = M.pos[2 * N + g0];
+            const float px1 = M.pos[g1], py1 = M.pos[N + g1], pz1 = M.pos[2 * N + g1];
+            if (one_chunk) {
+                decay_chunk(S, m, nbeta, px0, py0, pz0, px1, py1, pz1, a0, a1);
+            } else {
+                for (int c0 = 0; c0 < m; c0 += kChunk) {
+                    const int cnt = min(kChunk, m - c0);
+                    __syncthreads();
+                    stage_active(p, S, base, alist, uhn, c0, cnt);
+                    __syncthreads();
+                    decay_chunk(S, cnt, nbeta, px0, py0, pz0, px1, py1, pz1, a0, a1);
+                }
+            }
+        }
+        if (use_res) {
+            if (v0) for (int c = 0; c < 3; ++c) a0[c] += (double)resid[c * n_max + i0];
+            if (v1) for (int c = 0; c < 3; ++c) a1[c] += (double)resid[c * n_max + i1];
+        }
+        if (v0) {
+            p.u[row + i0] = (float)a0[0];
+            p.u[EN + row + i0] = (float)a0[1];
+            p.u[2 * EN + row + i0] = (float)a0[2];
+        }
+        if (v1) {
+            p.u[row + i1] = (float)a1[0];
+            p.u[EN + row + i1] = (float)a1[1];
+            p.u[2 * EN + row + i1] = (float)a1[2];
+        }
+    }
+    __syncthreads();
+}
+
+template <bool FROM_INPUT>
+__global__ __launch_bounds__(kWG) void k_step(StepParams p) {
+    __shared__ StepLds S;
+    const int wg = blockIdx.x;
+    const int n_max = p.scr.n_max;
+    float *uhn = p.scr.uhat_node + (size_t)wg * 3 * n_max;
+    float *resid = p.scr.resid + (size_t)wg * 3 * n_max;
+    int *alist = p.scr.alist + (size_t)wg * n_max;
+    int *plist = p.scr.plist + (size_t)wg * n_max;
+    if (p.model.mode != ETAC_DECAY_ONLY) {
+        stage_net(S.net, p.model.phi);
+        __syncthreads();
+    }
+    for (;;) {
+        const int item = next_item(p.scr.counter, S);
+        if (item >= p.n_items) break;
+        const int kk = item / p.E, e = item - kk * p.E;
+        const int k = p.mesh.order[kk];
+        process_item<FROM_INPUT>(p, S, e, k, uhn, resid, alist, plist);
+    }
+    retire(p.scr.counter);
+}
+
+hipError_t launch_step(const Plan &pl, const SceneDev *s, const ModelDev &m, int n_envs,
+                       const int8_t *cobj_in, const float *uhat_in, float *u, int8_t *cobj_out,
+                       int32_t *n_active, hipStream_t st) {
+    if (n_envs == 0) return hipSuccess;
+    StepParams p;
+    p.mesh = pl.mesh;
+    if (s) p.scene = *s;
+    else p.scene = SceneDev{nullptr, nullptr, nullptr, nullptr, nullptr, 0, 1};
+    p.model = m;
+    p.scr = pl.scr;
+    p.E = n_envs;
+    p.n_items = n_envs * pl.K;
+    p.cobj_in = cobj_in;
+    p.uhat_in = uhat_in;
+    p.u = u;
+    p.cobj_out = cobj_out;
+    p.n_active = n_active;
+    const int grid = p.n_items < pl.grid ? p.n_items : pl.grid;
+    if (s) hipLaunchKernelGGL(k_step<false>, dim3(grid), dim3(kWG), 0, st, p);
+    else hipLaunchKernelGGL(k_step<true>, dim3(grid), dim3(kWG), 0, st, p);
+    return hipGetLastError();
+}
+
+}  // namespace etac

@@ -1,0 +1,96 @@
+// Internal declarations shared by the host API and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/etac.h"
+
+namespace etac {
+
+constexpr int kWG = 256;           // threads per workgroup: 4 waves of 64
+constexpr int kWaves = kWG / 64;
+constexpr int kMaxPatches = 1024;  // per-patch counters of the contact kernel live in LDS
+constexpr int kDefaultWgPerCu = 2;
+
+// Device view of the plan's mesh copy.
+struct MeshDev {
+    const float *pos;      // [3][N]
+    const float *nrm;      // [3][N]
+    const float *origin;   // [K][3]
+    const int *offset;     // [K+1]
+    const float4 *bound;   // [K] conservative bounding sphere (cx, cy, cz, radius)
+    const int16_t *node_patch;  // [N] patch of each node
+    const int *order;      // [K] patches sorted by node count, largest first
+    int K, N, n_max;
+};
+
+struct SceneDev {
+    const int *n_obj;      // [E]
+    const int *type;       // [E][O]
+    const float *shape;    // [E][O][4]
+    const float *rot;      // [E][O][9]
+    const float *trans;    // [E][O][3]
+    int E, O;
+};
+
+struct ModelDev {
+    int mode;
+    const float *alpha;    // [K]
+    const float *phi;      // [17411] or null in decay-only mode
+};
+
+// Per-workgroup scratch of the persistent kernels (device memory).
+struct Scratch {
+    float *uhat_node;      // [G][3][n_max] u_hat of every node of the current item (0 passive)
+    float *resid;          // [G][3][n_max] residual-network output
+    int *alist;            // [G][n_max]    active node indices (patch-local, ascending)
+    int *plist;            // [G][n_max]    passive node indices (patch-local, ascending)
+    unsigned *counter;     // [4]           work-queue counters (self-resetting)
+    int n_max;
+};
+
+// Backward scratch (plan flag ETAC_PLAN_BACKWARD).
+struct BwdScratch {
+    float *gfeat;          // [G][n_max][64]   dL/df per node of the current item
+    float *guhat;          // [G][3][n_max]    dL/du_hat per node of the current item
+    float *phi_part;       // [E*K][17411]     per-item parameter-gradient partials
+    float *alpha_part;     // [E*K]            per-item dL/dalpha partials
+    float *pose_part;      // [E*K][O][12]     per-item pose-gradient partials
+    int *item_flag;        // [E*K]            1 if the item wrote partials
+    int *item_list;        // [E*K]            compacted list of flagged items
+    int *n_list;           // [1]
+    double *phi_seg;       // [kPhiSegs][17411] segment sums of the parameter reduction
+};
+
+struct Plan {
+    int device;
+    int cu_count;
+    int wg_per_cu;
+    int grid;              // persistent workgroups
+    int n_envs, max_obj, K, N, n_max;
+    uint32_t flags;
+    MeshDev mesh;
+    Scratch scr;
+    BwdScratch bwd;
+    bool has_bwd;
+    // device allocations owned by the plan
+    void *allocs[32];
+    int n_allocs;
+    int64_t scratch_bytes;
+};
+
+// Launchers (return hipError_t of the launch).
+hipError_t launch_contact(const Plan &p, const SceneDev &s, int8_t *cobj, float *uhat, int32_t *n_active,
+                          hipStream_t st);
+hipError_t launch_step(const Plan &p, const SceneDev *s, const ModelDev &m, int n_envs,
+                       const int8_t *cobj_in, const float *uhat_in, float *u, int8_t *cobj_out,
+                       int32_t *n_active, hipStream_t st);
+hipError_t launch_backward(const Plan &p, const SceneDev *s, const ModelDev &m, int n_envs,
+                           const int8_t *cobj_in, const float *uhat_in, const float *grad_u,
+                           float *grad_uhat, float *grad_rot, float *grad_trans, float *grad_alpha,
+                           float *grad_phi, hipStream_t st);
+hipError_t launch_contact_backward(const Plan &p, const SceneDev &s, const float *grad_uhat,
+                                   float *grad_rot, float *grad_trans, hipStream_t st);
+
+}  // namespace etac

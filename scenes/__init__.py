@@ -252,12 +252,12 @@ HAND_SIZES = (64, 128, 256, 512, 1024)
 HAND_GRIDS = {64: (8, 8), 128: (16, 8), 256: (16, 16), 512: (32, 16), 1024: (32, 32)}
 
 
-def hand_mesh(seed=0, n_patches=16, spacing=45.0):
+def hand_mesh(seed=0, n_patches=16, spacing=45.0, sizes=HAND_SIZES):
     """16 patches, sizes i.i.d. from {64..1024} nodes, 1 mm pitch, half flat and
     half wrapped on a cylinder of radius U(8, 15) mm about the long axis, laid
     out on a 4x4 grid 45 mm apart so that patches never overlap."""
     rng = np.random.default_rng([seed, 7])
-    sizes = rng.choice(HAND_SIZES, size=n_patches)
+    sizes = rng.choice(sizes, size=n_patches)
     curved = np.zeros(n_patches, bool)
     curved[rng.permutation(n_patches)[: n_patches // 2]] = True
     radii = rng.uniform(8.0, 15.0, size=n_patches)
@@ -273,10 +273,10 @@ def hand_mesh(seed=0, n_patches=16, spacing=45.0):
     return _assemble_mesh(patches, [1.0] * n_patches, centres, grids)
 
 
-def draw_primitive(rng):
+def draw_primitive(rng, scale=1.0):
     """Type uniform over sphere (r U(10,40)), box (sides U(20,60)), capsule
     (r U(8,20), length U(30,80)); orientation uniform on SO(3), R = I for a
-    sphere.  Returns (type, shape[4], R)."""
+    sphere.  All lengths are multiplied by `scale`.  Returns (type, shape[4], R)."""
     ptype = int(rng.integers(0, 3))
     shape = np.zeros(4)
     if ptype == SPHERE:
@@ -289,7 +289,7 @@ def draw_primitive(rng):
         shape[0] = rng.uniform(8.0, 20.0)
         shape[1] = rng.uniform(30.0, 80.0) / 2.0
         R = random_rotation(rng)
-    return ptype, shape, R
+    return ptype, shape * scale, R
 
 
 # Depth of a primitive's extreme point below the touched node, mm (objects
@@ -311,18 +311,19 @@ def place_primitive(rng, mesh, ptype, shape, R, offset=HAND_OFFSET):
     return p + (h - s) * n
 
 
-def hand_scene(mesh, n_envs, seed=1, max_obj=3, offset=HAND_OFFSET):
+def hand_scene(mesh, n_envs, seed=1, max_obj=3, offset=HAND_OFFSET, scale=1.0):
     """Per env: object count U{1,2,3}, then per object type/shape/rotation and
     placement.  Env e draws from its own stream (seed, e) so that any subset
-    of envs can be regenerated alone."""
+    of envs can be regenerated alone.  `scale` shrinks objects and press
+    depths together (small-patch hands)."""
     scene = _empty_scene(n_envs, max_obj)
     for e in range(n_envs):
         rng = np.random.default_rng([seed, e])
         cnt = int(rng.integers(1, max_obj + 1))
         scene.n_obj[e] = cnt
         for o in range(cnt):
-            ptype, shape, R = draw_primitive(rng)
-            t = place_primitive(rng, mesh, ptype, shape, R, offset)
+            ptype, shape, R = draw_primitive(rng, scale)
+            t = place_primitive(rng, mesh, ptype, shape, R, (offset[0] * scale, offset[1] * scale))
             scene.type[e, o] = ptype
             scene.shape[e, o] = shape
             scene.rot[e, o] = R.ravel()
@@ -330,10 +331,12 @@ def hand_scene(mesh, n_envs, seed=1, max_obj=3, offset=HAND_OFFSET):
     return scene
 
 
-def config2(n_envs=4096, hand_seed=0, env_seed=1, mode=MODE_FULL):
-    """Batched forward: n_envs envs of a 16-patch hand with 1-3 primitives."""
-    mesh = hand_mesh(hand_seed)
-    scene = hand_scene(mesh, n_envs, env_seed)
+def config2(n_envs=4096, hand_seed=0, env_seed=1, mode=MODE_FULL, sizes=HAND_SIZES, scale=1.0):
+    """Batched forward: n_envs envs of a 16-patch hand with 1-3 primitives.
+    `sizes` narrows the patch-size draw (small-patch hands for the gradient
+    checks)."""
+    mesh = hand_mesh(hand_seed, sizes=sizes)
+    scene = hand_scene(mesh, n_envs, env_seed, scale=scale)
     model = draw_model(np.random.default_rng([hand_seed, 1]), mesh.pitch, mode)
     return mesh, scene, model
 

@@ -1,0 +1,202 @@
+"""GPU parity of the adjoint (etac_step_backward, etac_propagate_backward,
+etac_contact_backward) against the FP64 oracle's adjoint and against FP64
+central finite differences of the oracle.
+
+The model is piecewise smooth: ReLU gates and the max-pool arg-max are
+discrete decisions.  FP32 pre-activations differ from FP64 by up to ~2e-6 on
+these workloads, so where a decision lies within that distance of its boundary
+both branches are valid and the FP32 and FP64 gradients may legitimately take
+different ones.  The oracle reports, per env, the smallest distance of any
+such decision from its boundary; envs below MARGIN are left out (their objects
+are removed, so their items carry no gradient) and the rest must match to
+|dG| <= 1e-4 max|G| + 1e-6 per gradient block.  Decay-only mode has no such
+decisions and is compared on every env.  Contact decisions are bit-exact and
+never excluded."""
+import numpy as np
+import pytest
+
+import scenes
+from scenes import MODE_FULL, MODE_DECAY_ONLY, MODE_RESIDUAL_ONLY
+from tests.gpu_util import DevModel, DevScene, log, make_plan, to_dev, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+MARGIN = 5e-6
+SMALL = dict(sizes=(64, 128, 256), scale=0.2)   # small-patch hand: many envs clear the margin
+
+
+def _close(gpu, ref, name, rel=1e-4, atol=1e-6):
+    gpu = np.asarray(gpu, np.float64)
+    ref = np.asarray(ref, np.float64)
+    err = float(np.max(np.abs(gpu - ref))) if ref.size else 0.0
+    mx = float(np.max(np.abs(ref))) if ref.size else 0.0
+    bound = rel * mx + atol
+    log(f"[gpu]   {name}: max err {err:.3e}  bound {bound:.3e}  max|ref| {mx:.3e}")
+    assert np.all(np.isfinite(gpu)), name
+    assert err <= bound, name
+
+
+def gpu_step_backward(plan, scene, model, grad_u):
+    from paper_2604_20295_amd import _native
+    torch, dev = torch_dev()
+    ds, dm = DevScene(scene), DevModel(model)
+    E, O = ds.E, ds.O
+    gu = to_dev(grad_u.astype(np.float32))
+    grot = torch.full((E, O, 9), float("nan"), device=dev)
+    gt = torch.full((E, O, 3), float("nan"), device=dev)
+    ga = torch.full((plan.K,), float("nan"), device=dev)
+    gp = torch.full((17411,), float("nan"), device=dev)
+    _native.etac_step_backward(plan, ds.struct(plan), dm.struct(plan), gu, grot, gt, ga, gp)
+    torch.cuda.synchronize()
+    return dict(grad_rot=grot.cpu().numpy(), grad_trans=gt.cpu().numpy(), grad_alpha=ga.cpu().numpy(),
+                grad_phi=gp.cpu().numpy())
+
+
+def clean_scene(oracle_lib, mesh, scene, model):
+    """Scene restricted to envs whose decisions all clear MARGIN."""
+    if model.mode == MODE_DECAY_ONLY:
+        return scene, scene.n_envs
+    out = oracle_lib.forward(mesh, scene, model, with_sig=True)
+    keep = out["margin"] > MARGIN
+    s = scene.copy()
+    s.n_obj[~keep] = 0
+    hit = keep & (out["n_active"].sum(axis=1) > 0)
+    return s, int(hit.sum())
+
+
+def _compare_all(g, ref, mode):
+    _close(g["grad_trans"], ref["grad_trans"], "grad_trans")
+    _close(g["grad_rot"], ref["grad_rot"], "grad_rot")
+    if mode != MODE_RESIDUAL_ONLY:
+        _close(g["grad_alpha"], ref["grad_alpha"], "grad_alpha")
+    else:
+        assert np.all(g["grad_alpha"] == 0.0)
+    if mode != MODE_DECAY_ONLY:
+        _close(g["grad_phi"], ref["grad_phi"], "grad_phi")
+    else:
+        assert np.all(g["grad_phi"] == 0.0)
+
+
+@pytest.mark.parametrize("mode", [MODE_DECAY_ONLY, MODE_FULL])
+def test_step_backward_pads(oracle_lib, mode):
+    # 8 envs of the 32x32 pad (config-3 geometry), loss weights N(0,1)
+    mesh, scene, model, w = scenes.config3()
+    model = model.with_mode(mode)
+    sc, n_clean = clean_scene(oracle_lib, mesh, scene, model)
+    log(f"[gpu] step backward pads mode={mode} envs compared {n_clean}/8")
+    assert n_clean >= 1
+    plan = make_plan(mesh, 8, 1, backward=True)
+    g = gpu_step_backward(plan, sc, model, w)
+    _compare_all(g, oracle_lib.backward(mesh, sc, model, w), mode)
+
+
+@pytest.mark.parametrize("mode", [MODE_DECAY_ONLY, MODE_FULL])
+def test_step_backward_hand(oracle_lib, mode):
+    mesh, scene, model = scenes.config2(n_envs=48, mode=mode)
+    sc, n_clean = clean_scene(oracle_lib, mesh, scene, model)
+    log(f"[gpu] step backward hand mode={mode} envs compared {n_clean}/48")
+    assert n_clean >= 8
+    w = np.random.default_rng(9).standard_normal((3, 48, mesh.n_nodes))
+    plan = make_plan(mesh, 48, 3, backward=True)
+    g = gpu_step_backward(plan, sc, model, w)
+    _compare_all(g, oracle_lib.backward(mesh, sc, model, w), mode)
+
+
+@pytest.mark.parametrize("mode", [MODE_FULL, MODE_RESIDUAL_ONLY])
+def test_step_backward_small_hand(oracle_lib, mode):
+    mesh, scene, model = scenes.config2(n_envs=96, mode=mode, **SMALL)
+    sc, n_clean = clean_scene(oracle_lib, mesh, scene, model)
+    log(f"[gpu] step backward small hand mode={mode} envs compared {n_clean}/96")
+    assert n_clean >= 20
+    w = np.random.default_rng(4).standard_normal((3, 96, mesh.n_nodes))
+    plan = make_plan(mesh, 96, 3, backward=True)
+    g = gpu_step_backward(plan, sc, model, w)
+    _compare_all(g, oracle_lib.backward(mesh, sc, model, w), mode)
+
+
+def test_propagate_and_contact_backward(oracle_lib):
+    from paper_2604_20295_amd import _native
+    torch, dev = torch_dev()
+    mesh, scene, model = scenes.config2(n_envs=32, **SMALL)
+    sc, n_clean = clean_scene(oracle_lib, mesh, scene, model)
+    log(f"[gpu] propagate/contact backward envs compared {n_clean}/32")
+    rc, ru, _ = oracle_lib.contact(mesh, sc)
+    ru32 = ru.astype(np.float32)
+    w = np.random.default_rng(5).standard_normal((3, 32, mesh.n_nodes))
+    plan = make_plan(mesh, 32, 3, backward=True)
+    dm = DevModel(model)
+    guh = torch.full((3, 32, mesh.n_nodes), float("nan"), device=dev)
+    ga = torch.zeros(plan.K, device=dev)
+    gp = torch.zeros(17411, device=dev)
+    _native.etac_propagate_backward(plan, dm.struct(plan), 32, to_dev(rc), to_dev(ru32), to_dev(w.astype(np.float32)),
+                                    guh, ga, gp)
+    torch.cuda.synchronize()
+    ref = oracle_lib.propagate_backward(mesh, model, rc, ru32.astype(np.float64), w)
+    _close(guh.cpu().numpy(), ref["grad_uhat"], "grad_uhat")
+    _close(ga.cpu().numpy(), ref["grad_alpha"], "grad_alpha")
+    _close(gp.cpu().numpy(), ref["grad_phi"], "grad_phi")
+    # contact adjoint from the oracle's dL/du_hat (same FP32 values on both sides)
+    g_uh = ref["grad_uhat"].astype(np.float32)
+    ds = DevScene(sc)
+    grot = torch.full((32, 3, 9), float("nan"), device=dev)
+    gt = torch.full((32, 3, 3), float("nan"), device=dev)
+    _native.etac_contact_backward(plan, ds.struct(plan), to_dev(g_uh), grot, gt)
+    torch.cuda.synchronize()
+    refc = oracle_lib.contact_backward(mesh, sc, g_uh.astype(np.float64))
+    _close(grot.cpu().numpy(), refc["grad_rot"], "contact grad_rot")
+    _close(gt.cpu().numpy(), refc["grad_trans"], "contact grad_trans")
+
+
+def _fd_vs_gpu(oracle_lib, mesh, sc, model, w, plan, o=0):
+    g = gpu_step_backward(plan, sc, model, w)
+    fd, ok = oracle_lib.fd_gradients(mesh, sc, model, w, obj=o)
+    if not ok:
+        return False
+    tw = oracle_lib.twist_from_grad_rot(g["grad_rot"][0, o], sc.rot[0, o])
+    scale = max(np.abs(fd["trans"]).max(), np.abs(fd["twist"]).max(), 1e-3)
+    log(f"[gpu]   fd trans {g['grad_trans'][0, o]} vs {fd['trans']}; twist {tw} vs {fd['twist']}")
+    assert np.max(np.abs(g["grad_trans"][0, o] - fd["trans"])) <= 1e-4 * scale + 1e-6
+    assert np.max(np.abs(tw - fd["twist"])) <= 1e-4 * scale + 1e-6
+    if model.mode != MODE_RESIDUAL_ONLY:
+        assert np.max(np.abs(g["grad_alpha"] - fd["alpha"])) <= 1e-4 * np.abs(fd["alpha"]).max() + 1e-6
+    return True
+
+
+def test_step_backward_vs_central_fd_pads(oracle_lib):
+    # GPU adjoint against FP64 central differences (h = 1e-4) of the oracle:
+    # 6-DoF twist / translation gradients and dL/dalpha, 8 pad envs.
+    mesh, scene, model, w = scenes.config3()
+    model = model.with_mode(MODE_DECAY_ONLY)
+    plan = make_plan(mesh, 1, 1, backward=True)
+    checked = 0
+    for e in range(8):
+        log(f"[gpu] fd pad env {e}")
+        checked += _fd_vs_gpu(oracle_lib, mesh, scene.select([e]), model, w[:, e:e + 1], plan)
+    assert checked >= 6
+
+
+def test_step_backward_vs_central_fd_small_hand(oracle_lib):
+    mesh, scene, model = scenes.config2(n_envs=64, **SMALL)
+    out = oracle_lib.forward(mesh, scene, model, with_sig=True)
+    plan = make_plan(mesh, 1, 3, backward=True)
+    rng = np.random.default_rng(6)
+    checked = 0
+    for e in range(64):
+        if out["margin"][e] <= MARGIN or out["n_active"][e].sum() == 0 or checked >= 4:
+            continue
+        o = int(out["contact_obj"][e][out["contact_obj"][e] >= 0][0])
+        log(f"[gpu] fd small hand env {e} obj {o}")
+        w = rng.standard_normal((3, 1, mesh.n_nodes))
+        checked += _fd_vs_gpu(oracle_lib, mesh, scene.select([e]), model, w, plan, o)
+    assert checked >= 3
+
+
+def test_backward_is_deterministic(oracle_lib):
+    mesh, scene, model = scenes.config2(n_envs=32)
+    w = np.random.default_rng(1).standard_normal((3, 32, mesh.n_nodes))
+    plan = make_plan(mesh, 32, 3, backward=True)
+    log("[gpu] backward determinism")
+    a = gpu_step_backward(plan, scene, model, w)
+    b = gpu_step_backward(plan, scene, model, w)
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
