@@ -36,7 +36,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--envs", type=int, default=4096)
     ap.add_argument("--mode", choices=["full", "decay", "residual"], default="full")
-    ap.add_argument("--cpu-envs", type=int, default=48, help="env sample for the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="time budget of the CPU oracle baseline (envs are added in blocks until it is spent)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay the step from a captured HIP graph")
     return ap.parse_args()
@@ -182,17 +183,22 @@ def main():
     }
 
     if not args.no_cpu_baseline:
+        # the FP64 oracle (forward + adjoint) on blocks of the same envs until
+        # the time budget is spent
         import oracle
-        ne = min(args.cpu_envs, E)
-        sub = scene.select(np.arange(ne))
-        w = grad_u[:, :ne].cpu().numpy().astype(np.float64)
-        tc = time.perf_counter()
-        oracle.forward(mesh, sub, model)
-        oracle.backward(mesh, sub, model, w)
-        dt = time.perf_counter() - tc
+        gu_host = grad_u.cpu().numpy().astype(np.float64)
+        ne, dt, block = 0, 0.0, 256
+        while ne < E and dt < args.cpu_seconds:
+            envs = np.arange(ne, min(E, ne + block))
+            sub = scene.select(envs)
+            tc = time.perf_counter()
+            oracle.forward(mesh, sub, model)
+            oracle.backward(mesh, sub, model, np.ascontiguousarray(gu_host[:, envs]))
+            dt += time.perf_counter() - tc
+            ne += len(envs)
         line["cpu_baseline"] = {"value": ne * N / dt, "unit": "node-updates/s", "cores": oracle.num_threads(),
                                 "kind": "oracle",
-                                "sample": f"first {ne} envs of the workload, forward + adjoint, {dt:.1f} s"}
+                                "sample": f"first {ne} of {E} envs, FP64 forward + adjoint, {dt:.1f} s"}
     plan.close()
     print(json.dumps(line), flush=True)
 

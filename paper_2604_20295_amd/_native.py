@@ -165,13 +165,17 @@ class Plan:
         _req(shape, torch.float32, (E, O, 4), "shape", self.device)
         _req(rot, torch.float32, (E, O, 9), "rot", self.device)
         _req(trans, torch.float32, (E, O, 3), "trans", self.device)
-        return etac_scene(E, O, _ptr(n_obj), _ptr(type_), _ptr(shape), _ptr(rot), _ptr(trans))
+        st = etac_scene(E, O, _ptr(n_obj), _ptr(type_), _ptr(shape), _ptr(rot), _ptr(trans))
+        st._keep = (n_obj, type_, shape, rot, trans)   # the struct holds raw pointers: keep the tensors alive
+        return st
 
     def model_struct(self, mode, alpha, phi):
         import torch
         _req(alpha, torch.float32, (self.K,), "alpha", self.device)
         _req(phi, torch.float32, (ETAC_PHI_SIZE,), "phi", self.device)
-        return etac_model(int(mode), _ptr(alpha), _ptr(phi))
+        st = etac_model(int(mode), _ptr(alpha), _ptr(phi))
+        st._keep = (alpha, phi)
+        return st
 
 
 def etac_contact(plan, scene, contact_obj, uhat, n_active):

@@ -1,0 +1,62 @@
+"""torch.autograd binding of the ETac step.
+
+ETacStep.apply(plan, n_obj, type, shape, rot, trans, alpha, phi, mode)
+returns (u [3][E][N], contact_obj [E][N], n_active [E][K]); gradients flow to
+rot [E][O][9], trans [E][O][3], alpha [K] and phi [17411].  The forward runs
+etac_step, the backward runs etac_step_backward, which recomputes the contact
+pass (nothing but the inputs is saved).  Argument marshalling only.
+"""
+import torch
+
+from . import _native
+
+
+class ETacStep(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, plan, n_obj, type_, shape, rot, trans, alpha, phi, mode):
+        rot, trans = rot.contiguous(), trans.contiguous()
+        alpha, phi = alpha.contiguous(), phi.contiguous()
+        sc = plan.scene_struct(n_obj, type_, shape, rot, trans)
+        md = plan.model_struct(mode, alpha, phi)
+        E = int(type_.shape[0])
+        dev = rot.device
+        u = torch.empty((3, E, plan.N), dtype=torch.float32, device=dev)
+        cobj = torch.empty((E, plan.N), dtype=torch.int8, device=dev)
+        na = torch.empty((E, plan.K), dtype=torch.int32, device=dev)
+        _native.etac_step(plan, sc, md, u, cobj, na)
+        ctx.plan, ctx.mode = plan, int(mode)
+        ctx.save_for_backward(n_obj, type_, shape, rot, trans, alpha, phi)
+        ctx.mark_non_differentiable(cobj, na)
+        return u, cobj, na
+
+    @staticmethod
+    def backward(ctx, grad_u, _grad_cobj, _grad_na):
+        n_obj, type_, shape, rot, trans, alpha, phi = ctx.saved_tensors
+        plan = ctx.plan
+        sc = plan.scene_struct(n_obj, type_, shape, rot, trans)
+        md = plan.model_struct(ctx.mode, alpha, phi)
+        gu = grad_u.to(torch.float32).contiguous()
+        grot = torch.empty_like(rot)
+        gtr = torch.empty_like(trans)
+        gal = torch.empty_like(alpha)
+        gph = torch.empty_like(phi)
+        _native.etac_step_backward(plan, sc, md, gu, grot, gtr, gal, gph)
+        return None, None, None, None, grot, gtr, gal, gph, None
+
+
+def etac_step(plan, n_obj, type_, shape, rot, trans, alpha, phi, mode=_native.ETAC_FULL):
+    return ETacStep.apply(plan, n_obj, type_, shape, rot, trans, alpha, phi, mode)
+
+
+def rotation_from_axis_angle(w):
+    """Rodrigues' formula, differentiable: w [..., 3] -> row-major R [..., 9]."""
+    th = torch.linalg.norm(w, dim=-1, keepdim=True).clamp_min(1e-12)
+    k = w / th
+    kx, ky, kz = k.unbind(-1)
+    z = torch.zeros_like(kx)
+    K = torch.stack([z, -kz, ky, kz, z, -kx, -ky, kx, z], dim=-1).reshape(*w.shape[:-1], 3, 3)
+    eye = torch.eye(3, dtype=w.dtype, device=w.device).expand_as(K)
+    s = torch.sin(th)[..., None]
+    c = (1.0 - torch.cos(th))[..., None]
+    R = eye + s * K + c * (K @ K)
+    return R.reshape(*w.shape[:-1], 9)

@@ -204,8 +204,7 @@ etac_status etac_plan_create(const etac_mesh *mesh, int32_t n_envs, int32_t max_
     if (e == hipSuccess && (flags & ETAC_PLAN_BACKWARD)) {
         const size_t items = (size_t)n_envs * K;
         etac::BwdScratch &b = p.bwd;
-        e = plan_alloc(p, &b.gfeat, G * (size_t)n_max * 64);
-        if (e == hipSuccess) e = plan_alloc(p, &b.guhat, G * 3 * (size_t)n_max);
+        e = plan_alloc(p, &b.guhat, G * 3 * (size_t)n_max);
         if (e == hipSuccess) e = plan_alloc(p, &b.phi_part, items * ETAC_PHI_SIZE);
         if (e == hipSuccess) e = plan_alloc(p, &b.alpha_part, items);
         if (e == hipSuccess) e = plan_alloc(p, &b.pose_part, items * (size_t)max_obj * 12);

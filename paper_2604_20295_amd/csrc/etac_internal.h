@@ -52,7 +52,6 @@ struct Scratch {
 
 // Backward scratch (plan flag ETAC_PLAN_BACKWARD).
 struct BwdScratch {
-    float *gfeat;          // [G][n_max][64]   dL/df per node of the current item
     float *guhat;          // [G][3][n_max]    dL/du_hat per node of the current item
     float *phi_part;       // [E*K][17411]     per-item parameter-gradient partials
     float *alpha_part;     // [E*K]            per-item dL/dalpha partials

@@ -396,25 +396,32 @@ def config4(n_envs=4096, seed=3, mode=MODE_FULL):
 # config 5: smooth random trajectories of the config-2 objects
 # ----------------------------------------------------------------------------
 
-def _rodrigues(w):
-    th = np.linalg.norm(w)
-    if th < 1e-15:
-        return np.eye(3)
-    k = w / th
-    Kx = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
-    return np.eye(3) + np.sin(th) * Kx + (1 - np.cos(th)) * (Kx @ Kx)
+def _rodrigues_batch(w):
+    """exp([w]_x) for w [..., 3] (Rodrigues' formula, FP64)."""
+    th = np.linalg.norm(w, axis=-1)[..., None, None]
+    safe = np.where(th > 1e-15, th, 1.0)
+    k = w / safe[..., 0]
+    z = np.zeros_like(k[..., 0])
+    K = np.stack([z, -k[..., 2], k[..., 1], k[..., 2], z, -k[..., 0], -k[..., 1], k[..., 0], z],
+                 axis=-1).reshape(*w.shape[:-1], 3, 3)
+    eye = np.broadcast_to(np.eye(3), K.shape)
+    R = eye + np.sin(th) * K + (1.0 - np.cos(th)) * (K @ K)
+    return np.where(th > 1e-15, R, eye)
 
 
 def trajectory(scene, n_steps, seed=5, v_std=5.0, w_std=0.05, rho=0.9, box=10.0):
-    """AR(1) translational (std v_std mm/step) and angular (std w_std
-    rad/step) velocities per object; the displacement from the initial pose is
-    reflected to stay within +-box mm per axis.  Returns rot [T][E][O][9] and
-    trans [T][E][O][3] in FP32."""
+    """Smooth random object motion for a graph-captured rollout.
+
+    Per object: AR(1) translational velocity (stationary std v_std mm/step)
+    and angular velocity (std w_std rad/step); the displacement from the
+    initial pose is reflected to stay within +-box mm per axis.  Spheres keep
+    R = I.  Returns rot [T][E][O][9] and trans [T][E][O][3] in FP32."""
     E, O = scene.type.shape
     rng = np.random.default_rng(seed)
     sig = np.sqrt(1.0 - rho * rho)
     t0 = scene.trans.astype(np.float64)
     R = scene.rot.astype(np.float64).reshape(E, O, 3, 3).copy()
+    spin = (scene.type != SPHERE)[..., None]
     off = np.zeros((E, O, 3))
     v = rng.normal(0.0, v_std, size=(E, O, 3))
     w = rng.normal(0.0, w_std, size=(E, O, 3))
@@ -432,8 +439,5 @@ def trajectory(scene, n_steps, seed=5, v_std=5.0, w_std=0.05, rho=0.9, box=10.0)
         under = off < -box
         off[under] = -2 * box - off[under]
         v[under] = -v[under]
-        for e in range(E):
-            for o in range(O):
-                if scene.type[e, o] != SPHERE:
-                    R[e, o] = _rodrigues(w[e, o]) @ R[e, o]
+        R = np.where(spin[..., None], _rodrigues_batch(w) @ R, R)
     return rots, trans

@@ -1,0 +1,102 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each mutant is a copy of oracle/etac_oracle.c with one planted mistake (a
+flipped inequality, a dropped term, a wrong sign or index, a transposed
+concatenation).  It is compiled on the CPU and loaded in place of the oracle,
+and the pin tests are run against it: at least one pin must fail.  The real
+oracle is restored afterwards."""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import test_oracle_adjoint as TA
+from tests import test_oracle_contact as TC
+from tests import test_oracle_propagate as TP
+
+SRC = oracle.SRC
+
+# (name, original text, mutated text)
+MUTANTS = [
+    ("surface nodes active", "if (!(s < r * r)) return h;\n        h.inside = 1;\n        if (s == 0.0) {\n            h.degenerate = 1;\n            h.depth = r;\n            for (int a = 0; a < 3; ++a) h.u[a] = -r * nrm[a];\n            return h;\n        }\n        double l = sqrt(s);\n        h.depth = r - l;\n        double sc = h.depth / l;\n        h.u[0]",
+     "if (!(s <= r * r)) return h;\n        h.inside = 1;\n        if (s == 0.0) {\n            h.degenerate = 1;\n            h.depth = r;\n            for (int a = 0; a < 3; ++a) h.u[a] = -r * nrm[a];\n            return h;\n        }\n        double l = sqrt(s);\n        h.depth = r - l;\n        double sc = h.depth / l;\n        h.u[0]"),
+    ("box face tie to highest axis", "if (sl < best) { best = sl; cs = c; }\n        }\n        h.face = cs;",
+     "if (sl <= best) { best = sl; cs = c; }\n        }\n        h.face = cs;"),
+    ("capsule ignores clamp", "double v0 = q[0], v1 = q[1], v2 = q[2] - z;", "double v0 = q[0], v1 = q[1], v2 = q[2];"),
+    ("shallowest object wins", "if (h.inside && (best < 0 || h.depth > bh.depth)) { best = o; bh = h; }\n            }\n            size_t en",
+     "if (h.inside && (best < 0 || h.depth < bh.depth)) { best = o; bh = h; }\n            }\n            size_t en"),
+    ("decay uses squared distance", "return exp(-alpha * d);", "return exp(-alpha * d * d);"),
+    ("decay sums the passive node", "for (int a = 0; a < 3; ++a) acc[a] += w * uhat[(size_t)a * E * N + ej];",
+     "for (int a = 0; a < 3; ++a) acc[a] += w * uhat[(size_t)a * E * N + (size_t)e * N + i];"),
+    ("network input p + o", "x[a] = P->pos[(size_t)a * N + i] - P->origin[3 * k + a];",
+     "x[a] = P->pos[(size_t)a * N + i] + P->origin[3 * k + a];"),
+    ("concat [g'; f]", "for (int c = 0; c < NF; ++c) acc += W->W4[o * 2 * NF + c] * f[c];\n        for (int c = 0; c < NF; ++c) acc += W->W4[o * 2 * NF + NF + c] * gp[c];",
+     "for (int c = 0; c < NF; ++c) acc += W->W4[o * 2 * NF + c] * gp[c];\n        for (int c = 0; c < NF; ++c) acc += W->W4[o * 2 * NF + NF + c] * f[c];"),
+    ("min-pool", "if (S->f[(size_t)li * NF + c] > best) { best = S->f[(size_t)li * NF + c]; am = li; }",
+     "if (S->f[(size_t)li * NF + c] < best) { best = S->f[(size_t)li * NF + c]; am = li; }"),
+    ("residual on active nodes", "int i = S->pas[t];\n            int li = i - P->offset[k];\n            phi_decode",
+     "int i = S->pas[t] == P->offset[k] ? S->act[0] : S->pas[t];\n            int li = i - P->offset[k];\n            phi_decode"),
+    ("alpha gradient sign", "da += -d * w * dot;", "da += d * w * dot;"),
+    ("sphere pose gradient sign", "for (int a = 0; a < 3; ++a) gt[a] += -(phi * g[a] + twophip * gd * d[a]);",
+     "for (int a = 0; a < 3; ++a) gt[a] += (phi * g[a] + twophip * gd * d[a]);"),
+    ("box rotation gradient term", "gR[a * 3 + cs] += coef * g[a] - grc * d[a];", "gR[a * 3 + cs] += coef * g[a] + grc * d[a];"),
+    ("capsule drops the axial projection", "if (!clamped) av[2] = twophip * gRv * v[2];", ""),
+    ("max-pool routes to node 0", "S->df[(size_t)S->argmax[c] * NF + c] += dg[c];", "S->df[(size_t)0 * NF + c] += dg[c];"),
+    ("decoder gradient misses W4 g' part", "dW->W4[o * 2 * NF + NF + c] += dh4[o] * S->gp[c];", "dW->W4[o * 2 * NF + NF + c] += dh4[o] * S->g[c];"),
+    ("encoder gate uses h1 instead of pre1", "dpre1[c] = pre1[c] > 0.0 ? acc : 0.0;", "dpre1[c] = acc;"),
+    ("u_hat gradient from passive input", "if (cobj[ei] >= 0) { /* only active nodes carry u_hat into the input */",
+     "if (cobj[ei] < 0) { /* only active nodes carry u_hat into the input */"),
+]
+
+
+def _pins():
+    """Quick pins, each a zero-argument callable raising on failure."""
+    P = pytest.mark.parametrize
+    return [
+        lambda o: TC.test_sphere_worked_example_node_below_centre(o),
+        lambda o: TC.test_sphere_active_set_exact_rational(o, 0),
+        lambda o: [TC.test_penetration_vs_brute_force_surface_sampling(o, t) for t in (0, 1, 2)],
+        lambda o: TC.test_deepest_object_wins_and_ties_to_lowest_index(o),
+        lambda o: TC.test_box_face_tie_goes_to_lowest_axis_and_zero_is_positive(o),
+        lambda o: TC.test_surface_nodes_are_passive(o),
+        lambda o: TP.test_decay_equals_explicit_omega_matmul(o, 0),
+        lambda o: TP.test_golden_two_node_hand_example(o),
+        lambda o: TP.test_full_is_sum_of_ablations_on_passive_nodes(o),
+        lambda o: [TP.test_forward_vs_independent_torch_float64(o, m) for m in (0, 1, 2)],
+        lambda o: TA.test_contact_adjoint_vs_torch_autograd(o),
+        lambda o: [TA.test_propagation_adjoint_vs_torch_autograd(o, m) for m in (0, 1, 2)],
+        lambda o: TA.test_raw_rotation_entries_vs_fd(o),
+    ]
+
+
+def _caught(lib_path):
+    saved = oracle._lib
+    oracle._lib = C.CDLL(lib_path)
+    try:
+        for pin in _pins():
+            try:
+                pin(oracle)
+            except (AssertionError, ValueError, RuntimeError, IndexError):
+                return True
+        return False
+    finally:
+        oracle._lib = saved
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_planted_mistake_is_caught(tmp_path, oracle_lib, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutant anchor not unique: {name}"
+    path = tmp_path / "mutant.c"
+    path.write_text(src.replace(old, new))
+    lib = tmp_path / "libmutant.so"
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+                           "-fno-fast-math", "-w", str(path), "-o", str(lib), "-lm"])
+    assert _caught(str(lib)), f"no pin caught the planted mistake: {name}"
+
+
+def test_unmutated_oracle_passes_the_same_pins(oracle_lib):
+    assert not _caught(oracle.LIB)
