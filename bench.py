@@ -40,7 +40,85 @@ def parse():
                     help="time budget of the CPU oracle baseline (envs are added in blocks until it is spent)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay the step from a captured HIP graph")
+    ap.add_argument("--rollout", action="store_true",
+                    help="also run the graph-captured rollout: 16384 envs, 200 steps of smooth object motion")
+    ap.add_argument("--rollout-envs", type=int, default=16384)
+    ap.add_argument("--rollout-steps", type=int, default=200)
     return ap.parse_args()
+
+
+def rollout(args, mode):
+    """Graph-captured rollout: per-step poses come from trajectories resident
+    in HBM, selected inside the graph by a device step counter; the whole step
+    (pose select, etac_step, optionally etac_step_backward) is one HIP graph
+    replayed once per step.  Returns steps/s and per-step latency p50/p99 for
+    the forward-only and forward+adjoint graphs."""
+    import torch
+    import scenes
+    from paper_2604_20295_amd import _native
+    dev = torch.device("cuda", 0)
+    mesh = scenes.hand_mesh(0)
+    scene = scenes.hand_scene(mesh, args.rollout_envs, 1)
+    model = scenes.draw_model(np.random.default_rng([0, 1]), mesh.pitch, mode)
+    T = args.rollout_steps
+    traj_rot, traj_trans = scenes.trajectory(scene, T, seed=5)
+    E, O, N, K = scene.n_envs, scene.max_obj, mesh.n_nodes, mesh.n_patches
+
+    def t(a, dtype):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).to(dev)
+
+    plan = _native.Plan.from_mesh(mesh, E, O, backward=True)
+    rot, trans = t(scene.rot, torch.float32), t(scene.trans, torch.float32)
+    sc = plan.scene_struct(t(scene.n_obj, torch.int32), t(scene.type, torch.int32), t(scene.shape, torch.float32),
+                           rot, trans)
+    md = plan.model_struct(mode, t(model.alpha, torch.float32), t(model.phi, torch.float32))
+    trot, ttr = t(traj_rot, torch.float32), t(traj_trans, torch.float32)
+    step_idx = torch.zeros(1, dtype=torch.long, device=dev)
+    u = torch.empty((3, E, N), device=dev)
+    cobj = torch.empty((E, N), dtype=torch.int8, device=dev)
+    na = torch.empty((E, K), dtype=torch.int32, device=dev)
+    gu = t(np.random.default_rng(11).standard_normal((3, E, N)), torch.float32)
+    grot, gtr = torch.empty((E, O, 9), device=dev), torch.empty((E, O, 3), device=dev)
+    gal, gph = torch.empty((K,), device=dev), torch.empty((17411,), device=dev)
+
+    def body(with_bwd):
+        rot.copy_(torch.index_select(trot, 0, step_idx)[0])
+        trans.copy_(torch.index_select(ttr, 0, step_idx)[0])
+        _native.etac_step(plan, sc, md, u, cobj, na)
+        if with_bwd:
+            _native.etac_step_backward(plan, sc, md, gu, grot, gtr, gal, gph)
+        step_idx.add_(1).remainder_(T)
+
+    out = {"envs": E, "steps": T, "workload": f"{E} envs x 16-patch hand, {T} steps of AR(1) object motion "
+                                            f"(5 mm/step velocity std), whole step in one HIP graph"}
+    for with_bwd in (False, True):
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            body(with_bwd)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            body(with_bwd)
+        step_idx.zero_()
+        torch.cuda.synchronize()
+        st = torch.cuda.current_stream()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(T + 1)]
+        t0 = time.perf_counter()
+        ev[0].record(st)
+        for s in range(T):
+            g.replay()
+            ev[s + 1].record(st)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        lat = np.array([ev[s].elapsed_time(ev[s + 1]) for s in range(T)])
+        key = "fwd_bwd" if with_bwd else "fwd"
+        out[key] = {"steps_per_s": T / wall, "node_updates_per_s": E * N * T / wall,
+                    "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))}
+        del g
+    plan.close()
+    return out
 
 
 def work_counts(mesh, n_active):
@@ -200,6 +278,8 @@ def main():
                                 "kind": "oracle",
                                 "sample": f"first {ne} of {E} envs, FP64 forward + adjoint, {dt:.1f} s"}
     plan.close()
+    if args.rollout:
+        line["rollout"] = rollout(args, mode)
     print(json.dumps(line), flush=True)
 
 

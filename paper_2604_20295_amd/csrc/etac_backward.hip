@@ -40,19 +40,29 @@ struct BwdParams {
     float *grad_uhat_out;         // [3][E][N]   BWD_PROP
 };
 
+constexpr int kRS = 80;        // row stride (floats) of the 64-feature round tiles: rows 16 banks apart
+
+// One round of the network adjoint: 4 tiles x 16 nodes (one tile per wave),
+// stored as rows [node][feature] so that every wave can contract over all 64
+// nodes for the weight-gradient slice it owns.
+struct RoundBuf {
+    float a[64 * kRS];         // phase A: dL/dpre4   | phase B: dL/dpre2
+    float b[64 * kRS];         // phase A: f          | phase B: h1
+    float c[64 * kRS];         // phase A: h4         | phase B: dL/dpre1
+    float d[64 * 16];          // phase A: dL/dr      | phase B: x (inputs padded to 16)
+};
+
 struct BwdLds {
     NetLds net;
     floatx4 w2t[4 * 4 * 64];      // [it][ot][lane] fragments of W2^T
     floatx4 w4t[4 * 4 * 64];      // [it][ot][lane] fragments of W4[:, :64]^T
     floatx4 w1t[4 * 64];          // [ot][lane]     fragments of W1^T (inputs padded to 16)
-    float ta[kWaves][16 * kTS];   // per-wave transpose tiles
-    float tb[kWaves][16 * kTS];
     union {
         struct {
             float4 a[kBChunk];    // (px, py, pz, gx) of staged passive nodes
             float2 b[kBChunk];    // (gy, gz)
         } st;
-        float red[4096];          // cross-wave reduction buffer
+        RoundBuf rb;
     } u;
     float s4[64];                 // sum_i dL/dpre4_i  (= db4)
     float dgp[64], dpre3[64], dg[64];
@@ -108,6 +118,7 @@ __device__ void stage_net_t(BwdLds &S, const float *phi) {
 // Y^T = W^T X^T for a 16-node tile with X in D layout (the input-gradient
 // chain of a 64 -> 64 layer).  wt: fragments [it][ot][lane].
 __device__ __forceinline__ void matT_tile(const floatx4 *wt, const floatx4 x[4], floatx4 y[4]) {
+    reload_fence();
     const int lane = lane_id();
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
@@ -122,103 +133,130 @@ __device__ __forceinline__ void matT_tile(const floatx4 *wt, const floatx4 x[4],
     }
 }
 
-// Store a D-layout tile (16 nodes x 64 features) as rows [node][feature].
-__device__ __forceinline__ void store_rows(float *t, const floatx4 v[4]) {
+// Store a D-layout tile (16 nodes x 64 features) as round rows row0 .. row0 + 15.
+__device__ __forceinline__ void store_rows(float *t, int row0, const floatx4 v[4]) {
     const int lane = lane_id(), node = lane & 15, gq = lane >> 4;
 #pragma unroll
-    for (int ot = 0; ot < 4; ++ot) *reinterpret_cast<floatx4 *>(&t[node * kTS + ot * 16 + 4 * gq]) = v[ot];
+    for (int ot = 0; ot < 4; ++ot)
+        *reinterpret_cast<floatx4 *>(&t[(row0 + node) * kRS + ot * 16 + 4 * gq]) = v[ot];
 }
 
-// acc[ot][it] += A^T B over the 16 nodes of a tile: A = rows ta (16 x 16*nat
-// features), B = rows tb (16 x 16*nbt features).  The result is in the MFMA
-// output layout: lane l, register r holds (out 16 ot + 4 (l >> 4) + r,
-// in 16 it + (l & 15)).
-template <int NAT, int NBT>
-__device__ __forceinline__ void wgrad_tile(const float *ta, const float *tb, floatx4 (&acc)[NAT][NBT]) {
+// acc[it] += sum over the 64 nodes of a round of A[node][acol + i] B[node][bcol + 16 it + j]
+// (i, j = 0..15).  Result in the MFMA output layout: lane l, register r holds
+// (i = 4 (l >> 4) + r, j = l & 15).
+template <int NB>
+__device__ __forceinline__ void round_wgrad(const float *A, int sa, int acol, const float *B, int sb, int bcol,
+                                            floatx4 (&acc)[NB]) {
     const int lane = lane_id(), col = lane & 15, kq = lane >> 4;
+#pragma unroll 4
+    for (int s = 0; s < 16; ++s) {
+        const int row = 4 * s + kq;
+        const float a = A[row * sa + acol + col];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int row = (4 * s + kq) * kTS;
-        float a[NAT], b[NBT];
-#pragma unroll
-        for (int ot = 0; ot < NAT; ++ot) a[ot] = ta[row + ot * 16 + col];
-#pragma unroll
-        for (int it = 0; it < NBT; ++it) b[it] = tb[row + it * 16 + col];
-#pragma unroll
-        for (int ot = 0; ot < NAT; ++ot)
-#pragma unroll
-            for (int it = 0; it < NBT; ++it) acc[ot][it] = mfma4(a[ot], b[it], acc[ot][it]);
+        for (int it = 0; it < NB; ++it) acc[it] = mfma4(a, B[row * sb + bcol + 16 * it + col], acc[it]);
     }
 }
 
+// Sum over the 64 round nodes of A[node][acol + i]; every lane returns the
+// sum for i = lane & 15 (lane groups sum 16 nodes each, then a butterfly).
+__device__ __forceinline__ float round_colsum(const float *A, int sa, int acol) {
+    const int lane = lane_id(), col = lane & 15, q = lane >> 4;
+    float s = 0.0f;
+    for (int r = 0; r < 16; ++r) s += A[(q * 16 + r) * sa + acol + col];
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    return s;
+}
+
+// This wave's slices of the parameter gradients: output rows 16 wave .. 16 wave + 15.
 struct WaveGrads {
-    floatx4 w4[4][4];    // dW4[:, :64]
-    floatx4 w2[4][4];    // dW2
-    floatx4 w1[4][1];    // dW1 (inputs padded to 16)
-    floatx4 w5[1][4];    // dW5 (outputs padded to 16)
-    floatx4 b2[4];       // per-lane partial sums over nodes (D layout)
-    floatx4 b1[4];
-    floatx4 b4[4];
-    float b5[3];
+    floatx4 w4[4];       // dW4[:, :64]
+    floatx4 w2[4];       // dW2
+    floatx4 w1[1];       // dW1 (inputs padded to 16)
+    floatx4 w5[1];       // dW5 columns 16 wave + j (outputs padded to 16)
+    float b4, b2, b1;    // bias sums of output 16 wave + (lane & 15)
+    float b5[3];         // db5 partial (lane group 0 only)
 };
 
 __device__ __forceinline__ void zero_grads(WaveGrads &G) {
     const floatx4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-    #pragma unroll
-    for (int a = 0; a < 4; ++a)
-        #pragma unroll
-        for (int b = 0; b < 4; ++b) { G.w4[a][b] = z; G.w2[a][b] = z; }
-    #pragma unroll
-    for (int a = 0; a < 4; ++a) { G.w1[a][0] = z; G.w5[0][a] = z; G.b2[a] = z; G.b1[a] = z; G.b4[a] = z; }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) { G.w4[a] = z; G.w2[a] = z; }
+    G.w1[0] = z;
+    G.w5[0] = z;
+    G.b4 = G.b2 = G.b1 = 0.0f;
     G.b5[0] = G.b5[1] = G.b5[2] = 0.0f;
 }
 
-// Adjoint of the encoder of one tile given dL/df (D layout): accumulates dW2,
-// db2, dW1, db1; when want_dx, returns dL/dx in D layout (features 0..15).
-__device__ __forceinline__ void encoder_adjoint(BwdLds &S, WaveGrads &G, const float xs[3], const floatx4 h1[4],
-                                                const floatx4 f[4], const floatx4 df[4], bool want_dx,
-                                                floatx4 *dx) {
+// Decoder adjoint of one round (phase A).  Each wave passes its tile's f, h4
+// and dL/dr; returns dL/dpre4 of its tile and accumulates its dW4 / dW5 / db4
+// slices over the round.
+__device__ void round_decoder_adjoint(BwdLds &S, WaveGrads &G, const floatx4 f[4], const floatx4 h4[4],
+                                      const float dr[3], floatx4 dh4[4]) {
+    reload_fence();
     const int wave = threadIdx.x >> 6, lane = lane_id(), gq = lane >> 4, node = lane & 15;
-    float *ta = S.ta[wave], *tb = S.tb[wave];
+    const NetLds &L = S.net;
+    RoundBuf &R = S.u.rb;
+#pragma unroll
+    for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int feat = ot * 16 + 4 * gq + r;
+            const float v = L.w5[feat] * dr[0] + L.w5[64 + feat] * dr[1] + L.w5[128 + feat] * dr[2];
+            dh4[ot][r] = h4[ot][r] > 0.0f ? v : 0.0f;
+        }
+    if (gq == 0) { G.b5[0] += dr[0]; G.b5[1] += dr[1]; G.b5[2] += dr[2]; }
+    __syncthreads();                       // previous users of the round buffer are done
+    store_rows(R.a, 16 * wave, dh4);
+    store_rows(R.b, 16 * wave, f);
+    store_rows(R.c, 16 * wave, h4);
+#pragma unroll
+    for (int c = gq; c < 16; c += 4) R.d[(16 * wave + node) * 16 + c] = c < 3 ? dr[c] : 0.0f;
+    __syncthreads();
+    round_wgrad<4>(R.a, kRS, 16 * wave, R.b, kRS, 0, G.w4);
+    round_wgrad<1>(R.d, 16, 0, R.c, kRS, 16 * wave, G.w5);
+    G.b4 += round_colsum(R.a, kRS, 16 * wave);
+}
+
+// Encoder adjoint of one round (phase B) given dL/df of each wave's tile:
+// accumulates the dW2 / dW1 / db2 / db1 slices and returns dL/dx of the tile
+// (D layout, inputs 0..15).
+__device__ void round_encoder_adjoint(BwdLds &S, WaveGrads &G, const float xs[3], const floatx4 h1[4],
+                                      const floatx4 f[4], const floatx4 df[4], floatx4 &dx) {
+    reload_fence();
+    const int wave = threadIdx.x >> 6, lane = lane_id(), gq = lane >> 4, node = lane & 15;
+    RoundBuf &R = S.u.rb;
     floatx4 dpre2[4], dh1[4];
 #pragma unroll
     for (int ot = 0; ot < 4; ++ot)
 #pragma unroll
         for (int r = 0; r < 4; ++r) dpre2[ot][r] = f[ot][r] > 0.0f ? df[ot][r] : 0.0f;
-#pragma unroll
-    for (int ot = 0; ot < 4; ++ot) G.b2[ot] += dpre2[ot];
-    // dW2 += dpre2 (x) h1
-    wave_sync();
-    store_rows(ta, dpre2);
-    store_rows(tb, h1);
-    wave_sync();
-    wgrad_tile<4, 4>(ta, tb, G.w2);
-    // dh1 = W2^T dpre2, gated by h1 > 0
     matT_tile(S.w2t, dpre2, dh1);
 #pragma unroll
     for (int ot = 0; ot < 4; ++ot)
 #pragma unroll
         for (int r = 0; r < 4; ++r) dh1[ot][r] = h1[ot][r] > 0.0f ? dh1[ot][r] : 0.0f;
+    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    reload_fence();
 #pragma unroll
-    for (int ot = 0; ot < 4; ++ot) G.b1[ot] += dh1[ot];
-    // dW1 += dpre1 (x) x: x rows hold features 4 s + gq, padded to 16
-    wave_sync();
-    store_rows(ta, dh1);
+    for (int ot = 0; ot < 4; ++ot) {
+        const floatx4 w = S.w1t[ot * 64 + lane];
 #pragma unroll
-    for (int s = 0; s < 3; ++s) tb[node * kTS + 4 * s + gq] = xs[s];
-    tb[node * kTS + 12 + gq] = 0.0f;
-    wave_sync();
-    wgrad_tile<4, 1>(ta, tb, G.w1);
-    if (want_dx) {
-        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int ot = 0; ot < 4; ++ot) {
-            const floatx4 w = S.w1t[ot * 64 + lane];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) acc = mfma4(w[r], dh1[ot][r], acc);
-        }
-        *dx = acc;
+        for (int r = 0; r < 4; ++r) acc = mfma4(w[r], dh1[ot][r], acc);
     }
+    dx = acc;
+    __syncthreads();
+    store_rows(R.a, 16 * wave, dpre2);
+    store_rows(R.b, 16 * wave, h1);
+    store_rows(R.c, 16 * wave, dh1);
+#pragma unroll
+    for (int s = 0; s < 3; ++s) R.d[(16 * wave + node) * 16 + 4 * s + gq] = xs[s];
+    R.d[(16 * wave + node) * 16 + 12 + gq] = 0.0f;
+    __syncthreads();
+    round_wgrad<4>(R.a, kRS, 16 * wave, R.b, kRS, 0, G.w2);
+    round_wgrad<1>(R.c, kRS, 16 * wave, R.d, 16, 0, G.w1);
+    G.b2 += round_colsum(R.a, kRS, 16 * wave);
+    G.b1 += round_colsum(R.c, kRS, 16 * wave);
 }
 
 // ---------------------------------------------------------------------------
@@ -419,70 +457,6 @@ __device__ void contact_adjoint_item(const BwdParams &p, BwdLds &S, int e, int i
     }
 }
 
-// Cross-wave sum of a wave's 16 accumulator tiles in fixed wave order and
-// store of the result (wave 0 writes).  dst(ot, it, r, col) maps an MFMA
-// output element to a packed-parameter index or -1.
-template <int NA, int NB, typename Dst>
-__device__ void reduce_store_tiles(BwdLds &S, floatx4 (&acc)[NA][NB], float *out, Dst dst) {
-    const int wave = threadIdx.x >> 6, lane = lane_id();
-    for (int w = 1; w < kWaves; ++w) {
-        __syncthreads();
-        if (wave == w)
-            #pragma unroll
-            for (int a = 0; a < NA; ++a)
-                #pragma unroll
-                for (int b = 0; b < NB; ++b) *reinterpret_cast<floatx4 *>(&S.u.red[((a * NB + b) * 64 + lane) * 4]) = acc[a][b];
-        __syncthreads();
-        if (wave == 0)
-            #pragma unroll
-            for (int a = 0; a < NA; ++a)
-                #pragma unroll
-                for (int b = 0; b < NB; ++b) acc[a][b] += *reinterpret_cast<const floatx4 *>(&S.u.red[((a * NB + b) * 64 + lane) * 4]);
-    }
-    if (wave == 0) {
-        const int gq = lane >> 4, col = lane & 15;
-        #pragma unroll
-        for (int a = 0; a < NA; ++a)
-            #pragma unroll
-            for (int b = 0; b < NB; ++b)
-                #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int idx = dst(16 * a + 4 * gq + r, 16 * b + col);
-                    if (idx >= 0) out[idx] = acc[a][b][r];
-                }
-    }
-}
-
-// Row sums of a D-layout vector accumulator over the 16 nodes, then over the
-// waves in order; result [64] in `dst` (LDS), valid after the call.
-__device__ void reduce_vec(BwdLds &S, floatx4 (&v)[4], float *dst) {
-    const int wave = threadIdx.x >> 6, lane = lane_id(), gq = lane >> 4;
-    #pragma unroll
-    for (int ot = 0; ot < 4; ++ot)
-        #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            float x = v[ot][r];
-            x += __shfl_xor(x, 1);
-            x += __shfl_xor(x, 2);
-            x += __shfl_xor(x, 4);
-            x += __shfl_xor(x, 8);
-            v[ot][r] = x;
-        }
-    __syncthreads();
-    // all 16 lanes of a row hold the reduced values: identical stores
-        #pragma unroll
-        for (int ot = 0; ot < 4; ++ot)
-            #pragma unroll
-            for (int r = 0; r < 4; ++r) S.vred[wave][ot * 16 + 4 * gq + r] = v[ot][r];
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        float s = S.vred[0][threadIdx.x];
-        for (int w = 1; w < kWaves; ++w) s += S.vred[w][threadIdx.x];
-        dst[threadIdx.x] = s;
-    }
-    __syncthreads();
-}
-
 // Residual-network adjoint of one item; writes its parameter-gradient
 // partial and adds dL/du_hat of active arg-max nodes into gh.
 __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, int item, int base, int n,
@@ -557,15 +531,16 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
     __syncthreads();
     global_mlp(L, phi);
 
-    // (b) decoder + encoder adjoint over the passive nodes of every tile
+    // (b) rounds of four tiles: decoder adjoint (phase A), then encoder
+    //     adjoint (phase B) of every tile's passive nodes
     WaveGrads G;
     zero_grads(G);
-    for (int t = wave; t < ntiles; t += kWaves) {
-        const int ln = t * 16 + (lane & 15);
+    for (int t0 = 0; t0 < ntiles; t0 += kWaves) {
+        const int ln = (t0 + wave) * 16 + (lane & 15);
         const bool valid = ln < n;
         const bool passive = valid && wobj[ln] < 0;
         float xs[3];
-        load_x(M, k, base + ln, valid, uhn, n_max, ln, xs);
+        load_x(M, k, base + (valid ? ln : 0), valid, uhn, n_max, valid ? ln : 0, xs);
         floatx4 h1[4], f[4], h4[4];
         encoder_tile(L, xs, h1, f);
         float r_unused[3];
@@ -576,65 +551,47 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
             dr[1] = p.grad_u[EN + row + ln];
             dr[2] = p.grad_u[2 * EN + row + ln];
         }
-        if (gq == 0) { G.b5[0] += dr[0]; G.b5[1] += dr[1]; G.b5[2] += dr[2]; }
-        // dW5 += dr (x) h4 ; dh4 = (W5^T dr) gated by h4 > 0
-        float *ta = S.ta[wave], *tb = S.tb[wave];
-        wave_sync();
-        {
-            const int node = lane & 15;
-            ta[node * kTS + gq] = gq < 3 ? dr[gq] : 0.0f;
-            for (int c = 4 + gq; c < 16; c += 4) ta[node * kTS + c] = 0.0f;
-        }
-        store_rows(tb, h4);
-        wave_sync();
-        wgrad_tile<1, 4>(ta, tb, G.w5);
-        floatx4 dh4[4];
-#pragma unroll
-        for (int ot = 0; ot < 4; ++ot) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int feat = ot * 16 + 4 * gq + r;
-                const float v = L.w5[feat] * dr[0] + L.w5[64 + feat] * dr[1] + L.w5[128 + feat] * dr[2];
-                dh4[ot][r] = h4[ot][r] > 0.0f ? v : 0.0f;
-            }
-            G.b4[ot] += dh4[ot];
-        }
-        // dW4[:, :64] += dh4 (x) f ; df = W4[:, :64]^T dh4
-        wave_sync();
-        store_rows(ta, dh4);
-        store_rows(tb, f);
-        wave_sync();
-        wgrad_tile<4, 4>(ta, tb, G.w4);
-        floatx4 df[4];
+        floatx4 dh4[4], df[4], dx;
+        round_decoder_adjoint(S, G, f, h4, dr, dh4);
         matT_tile(S.w4t, dh4, df);
-        encoder_adjoint(S, G, xs, h1, f, df, false, nullptr);
-    }
-
-    // (c) global MLP adjoint: s4 = sum_i dh4_i, dg' = W4[:, 64:]^T s4,
-    //     dpre3 = dg' gated by g' > 0, dg = W3^T dpre3
-    reduce_vec(S, G.b4, S.s4);
-    if (threadIdx.x < 64) {
-        const int c = threadIdx.x;
-        float s = 0.0f;
-        for (int o = 0; o < 64; ++o) s += phi[kW4 + o * 128 + 64 + c] * S.s4[o];
-        S.dgp[c] = s;
+        round_encoder_adjoint(S, G, xs, h1, f, df, dx);
     }
     __syncthreads();
-    if (threadIdx.x < 64) {
-        const int o = threadIdx.x;
-        S.dpre3[o] = L.gp[o] > 0.0f ? S.dgp[o] : 0.0f;
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        const int c = threadIdx.x;
-        float s = 0.0f;
-        for (int o = 0; o < 64; ++o) s += phi[kW3 + o * 64 + c] * S.dpre3[o];
-        S.dg[c] = s;
-    }
+    S.s4[16 * wave + (lane & 15)] = G.b4;    // identical values in the 4 lane groups
     __syncthreads();
 
-    // (d) max-pool routing: 64 slots, slot c carries dL/df = dg[c] e_c at the
-    //     arg-max node of channel c; four 16-slot tiles, one per wave
+    // (c) global MLP adjoint: dg' = W4[:, 64:]^T s4, dpre3 = dg' gated by
+    //     g' > 0, dg = W3^T dpre3
+    {
+        // each wave sums 16 of the 64 terms, the partials are added in wave order
+        const int c = lane;
+        float s = 0.0f;
+#pragma unroll 4
+        for (int o = 16 * wave; o < 16 * wave + 16; ++o) s += phi[kW4 + o * 128 + 64 + c] * S.s4[o];
+        S.vred[wave][c] = s;
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            float t = S.vred[0][c];
+            for (int w = 1; w < kWaves; ++w) t += S.vred[w][c];
+            S.dgp[c] = t;
+            S.dpre3[c] = L.gp[c] > 0.0f ? t : 0.0f;
+        }
+        __syncthreads();
+        s = 0.0f;
+#pragma unroll 4
+        for (int o = 16 * wave; o < 16 * wave + 16; ++o) s += phi[kW3 + o * 64 + c] * S.dpre3[o];
+        S.vred[wave][c] = s;
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            float t = S.vred[0][c];
+            for (int w = 1; w < kWaves; ++w) t += S.vred[w][c];
+            S.dg[c] = t;
+        }
+        __syncthreads();
+    }
+
+    // (d) max-pool routing round: slot c carries dL/df = dg[c] e_c at the
+    //     arg-max node of channel c; wave w holds slots 16 w .. 16 w + 15
     {
         const int slot = wave * 16 + (lane & 15);
         const int ln = S.argmax[slot];
@@ -643,14 +600,14 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
         load_x(M, k, base + (valid ? ln : 0), valid, uhn, n_max, valid ? ln : 0, xs);
         floatx4 h1[4], f[4], df[4], dx;
         encoder_tile(L, xs, h1, f);
-        #pragma unroll
+#pragma unroll
         for (int ot = 0; ot < 4; ++ot)
-            #pragma unroll
+#pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int feat = ot * 16 + 4 * gq + r;
                 df[ot][r] = (valid && feat == slot) ? S.dg[slot] : 0.0f;
             }
-        encoder_adjoint(S, G, xs, h1, f, df, true, &dx);
+        round_encoder_adjoint(S, G, xs, h1, f, df, dx);
         S.dxs[slot][gq] = dx;   // input features 4 gq + r of this slot's node
     }
     __syncthreads();
@@ -666,26 +623,34 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
             }
         }
 
-    // (e) item partial of every parameter gradient
-    reduce_store_tiles(S, G.w4, out, [](int o, int i) { return kW4 + o * 128 + i; });
-    reduce_store_tiles(S, G.w2, out, [](int o, int i) { return kW2 + o * 64 + i; });
-    reduce_store_tiles(S, G.w1, out, [](int o, int i) { return i < 9 ? kW1 + o * 9 + i : -1; });
-    reduce_store_tiles(S, G.w5, out, [](int o, int i) { return o < 3 ? kW5 + o * 64 + i : -1; });
-    reduce_vec(S, G.b2, S.vred[0] + 0);   // uses vred as scratch; copy out below
-    if (threadIdx.x < 64) out[kB2 + threadIdx.x] = S.vred[0][threadIdx.x];
-    __syncthreads();
-    reduce_vec(S, G.b1, S.dgp);
-    if (threadIdx.x < 64) out[kB1 + threadIdx.x] = S.dgp[threadIdx.x];
-    __syncthreads();
+    // (e) item partial of every parameter gradient; each wave writes its slices
+    {
+        const int col = lane & 15, o16 = 16 * wave;
+#pragma unroll
+        for (int it = 0; it < 4; ++it)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int o = o16 + 4 * gq + r, i = 16 * it + col;
+                out[kW4 + o * 128 + i] = G.w4[it][r];
+                out[kW2 + o * 64 + i] = G.w2[it][r];
+            }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int o = o16 + 4 * gq + r;
+            if (col < 9) out[kW1 + o * 9 + col] = G.w1[0][r];
+            const int o5 = 4 * gq + r;
+            if (o5 < 3) out[kW5 + o5 * 64 + o16 + col] = G.w5[0][r];
+        }
+        out[kB4 + o16 + col] = G.b4;
+        out[kB2 + o16 + col] = G.b2;
+        out[kB1 + o16 + col] = G.b1;
+    }
     for (int idx = threadIdx.x; idx < 64 * 64; idx += kWG) {
         const int o = idx >> 6, c = idx & 63;
         out[kW4 + o * 128 + 64 + c] = S.s4[o] * L.gp[c];     // dW4[:, 64:] = s4 (x) g'
         out[kW3 + o * 64 + c] = S.dpre3[o] * L.g[c];          // dW3 = dpre3 (x) g
     }
-    if (threadIdx.x < 64) {
-        out[kB4 + threadIdx.x] = S.s4[threadIdx.x];
-        out[kB3 + threadIdx.x] = S.dpre3[threadIdx.x];
-    }
+    if (threadIdx.x < 64) out[kB3 + threadIdx.x] = S.dpre3[threadIdx.x];
     // db5: wave sums (only lane group 0 accumulated), then the waves in order
 #pragma unroll
     for (int c = 0; c < 3; ++c) {

@@ -294,6 +294,11 @@ __device__ void stage_net(NetLds &L, const float *phi) {
     if (tid == 3) L.b5[3] = 0.0f;
 }
 
+// Keeps the compiler from hoisting the (loop-invariant) LDS weight-fragment
+// loads of a tile out of the node loops: hoisted, they would need ~280 extra
+// registers per lane and spill.  Emits no instruction.
+__device__ __forceinline__ void reload_fence() { asm volatile("" ::: "memory"); }
+
 __device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
@@ -324,6 +329,7 @@ __device__ __forceinline__ void load_x(const MeshDev &M, int k, int gnode, bool 
 // Encoder: h1 = relu(W1 x + b1), f = relu(W2 h1 + b2) for a 16-node tile.
 __device__ __forceinline__ void encoder_tile(const NetLds &L, const float xs[3], floatx4 h1[4],
                                              floatx4 f[4]) {
+    reload_fence();
     const int lane = lane_id(), gq = lane >> 4;
 #pragma unroll
     for (int ot = 0; ot < 4; ++ot) {
@@ -353,6 +359,7 @@ __device__ __forceinline__ void encoder_tile(const NetLds &L, const float xs[3],
 // r = W5 h4 + b5.  Every lane returns r of its node (lane & 15).
 __device__ __forceinline__ void decoder_tile(const NetLds &L, const floatx4 f[4], floatx4 h4[4],
                                              float r_out[3]) {
+    reload_fence();
     const int lane = lane_id(), gq = lane >> 4;
 #pragma unroll
     for (int ot2 = 0; ot2 < 4; ++ot2) {
