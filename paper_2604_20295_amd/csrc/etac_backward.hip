@@ -40,7 +40,10 @@ struct BwdParams {
     float *grad_uhat_out;         // [3][E][N]   BWD_PROP
 };
 
-constexpr int kRS = 80;        // row stride (floats) of the 64-feature round tiles: rows 16 banks apart
+constexpr int kRS = 82;        // row stride (floats) of the 64-feature round tiles
+constexpr int kDS = 34;        // row stride of the 16-feature round tiles
+// Both strides put rows 8 apart 16 LDS banks apart, so the four lane groups of
+// an MFMA operand read (rows 8 q + e) hit different banks.
 
 // One round of the network adjoint: 4 tiles x 16 nodes (one tile per wave),
 // stored as rows [node][feature] so that every wave can contract over all 64
@@ -49,18 +52,19 @@ struct RoundBuf {
     float a[64 * kRS];         // phase A: dL/dpre4   | phase B: dL/dpre2
     float b[64 * kRS];         // phase A: f          | phase B: h1
     float c[64 * kRS];         // phase A: h4         | phase B: dL/dpre1
-    float d[64 * 16];          // phase A: dL/dr      | phase B: x (inputs padded to 16)
+    float d[64 * kDS];         // phase A: dL/dr      | phase B: x (inputs 0..15; 16..31 scratch)
 };
 
 struct BwdLds {
     NetLds net;
-    floatx4 w2t[4 * 4 * 64];      // [it][ot][lane] fragments of W2^T
-    floatx4 w4t[4 * 4 * 64];      // [it][ot][lane] fragments of W4[:, :64]^T
-    floatx4 w1t[4 * 64];          // [ot][lane]     fragments of W1^T (inputs padded to 16)
+    half8 w2th[4 * 2 * 64], w2tl[4 * 2 * 64];   // [it][s][lane] split fragments of W2^T
+    half8 w4th[4 * 2 * 64], w4tl[4 * 2 * 64];   // [it][s][lane] split fragments of W4[:, :64]^T
+    float w1u[3][64];                           // W1[:, 6..8]: the u_hat inputs
     union {
         struct {
             float4 a[kBChunk];    // (px, py, pz, gx) of staged passive nodes
             float2 b[kBChunk];    // (gy, gz)
+            double part[kWG][6];  // per-thread partial dL/du_hat of its two active nodes
         } st;
         RoundBuf rb;
     } u;
@@ -69,7 +73,7 @@ struct BwdLds {
     float vred[kWaves][64];
     int ired[kWaves][64];
     int argmax[64];
-    floatx4 dxs[64][4];           // dL/dx of the routed arg-max node of each channel, per lane group
+    float dxs[64][3];             // dL/du_hat of the routed arg-max node of each channel
     double dred[kWaves][12];
     int wcnt[2][kWaves];
     int item;
@@ -82,33 +86,24 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Transposed weight fragments for the adjoint layers.
+// Transposed weight fragments for the adjoint layers, in the chain order of
+// etac_device.h (K step s, lane group q, element e <-> output chain_k(s, q, e)).
 __device__ void stage_net_t(BwdLds &S, const float *phi) {
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < 4 * 4 * 64; idx += kWG) {
-        const int lane = idx & 63, ot = (idx >> 6) & 3, it = idx >> 8;
+    for (int idx = tid; idx < 4 * 2 * 64; idx += kWG) {
+        const int lane = idx & 63, s = (idx >> 6) & 1, it = idx >> 7, q = lane >> 4;
         const int in = it * 16 + (lane & 15);
-        floatx4 a, b;
-        #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int out = ot * 16 + 4 * (lane >> 4) + r;
-            a[r] = phi[kW2 + out * 64 + in];
-            b[r] = phi[kW4 + out * 128 + in];
+        float a[8], b[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int out = chain_k(s, q, e);
+            a[e] = phi[kW2 + out * 64 + in];
+            b[e] = phi[kW4 + out * 128 + in];
         }
-        S.w2t[idx] = a;
-        S.w4t[idx] = b;
+        split8(a, S.w2th[idx], S.w2tl[idx]);
+        split8(b, S.w4th[idx], S.w4tl[idx]);
     }
-    for (int idx = tid; idx < 4 * 64; idx += kWG) {
-        const int lane = idx & 63, ot = idx >> 6;
-        const int in = lane & 15;
-        floatx4 a;
-        #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int out = ot * 16 + 4 * (lane >> 4) + r;
-            a[r] = in < 9 ? phi[kW1 + out * 9 + in] : 0.0f;
-        }
-        S.w1t[idx] = a;
-    }
+    for (int idx = tid; idx < 3 * 64; idx += kWG) S.w1u[idx >> 6][idx & 63] = phi[kW1 + (idx & 63) * 9 + 6 + (idx >> 6)];
 }
 
 // ---------------------------------------------------------------------------
@@ -116,18 +111,19 @@ __device__ void stage_net_t(BwdLds &S, const float *phi) {
 // ---------------------------------------------------------------------------
 
 // Y^T = W^T X^T for a 16-node tile with X in D layout (the input-gradient
-// chain of a 64 -> 64 layer).  wt: fragments [it][ot][lane].
-__device__ __forceinline__ void matT_tile(const floatx4 *wt, const floatx4 x[4], floatx4 y[4]) {
+// chain of a 64 -> 64 layer); wth / wtl: split fragments [it][s][lane].
+__device__ __forceinline__ void matT_tile(const half8 *wth, const half8 *wtl, const floatx4 x[4], floatx4 y[4]) {
     reload_fence();
     const int lane = lane_id();
+    half8 bh[2], bl[2];
+    split_chain(x, bh, bl);
 #pragma unroll
     for (int it = 0; it < 4; ++it) {
         floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int ot = 0; ot < 4; ++ot) {
-            const floatx4 w = wt[(it * 4 + ot) * 64 + lane];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) acc = mfma4(w[r], x[ot][r], acc);
+        for (int s = 0; s < 2; ++s) {
+            const int fi = (it * 2 + s) * 64 + lane;
+            acc = mfma_split(wth[fi], wtl[fi], bh[s], bl[s], acc);
         }
         y[it] = acc;
     }
@@ -137,23 +133,38 @@ __device__ __forceinline__ void matT_tile(const floatx4 *wt, const floatx4 x[4],
 __device__ __forceinline__ void store_rows(float *t, int row0, const floatx4 v[4]) {
     const int lane = lane_id(), node = lane & 15, gq = lane >> 4;
 #pragma unroll
-    for (int ot = 0; ot < 4; ++ot)
-        *reinterpret_cast<floatx4 *>(&t[(row0 + node) * kRS + ot * 16 + 4 * gq]) = v[ot];
+    for (int ot = 0; ot < 4; ++ot) {
+        float *dst = &t[(row0 + node) * kRS + ot * 16 + 4 * gq];
+        *reinterpret_cast<float2 *>(dst) = make_float2(v[ot][0], v[ot][1]);
+        *reinterpret_cast<float2 *>(dst + 2) = make_float2(v[ot][2], v[ot][3]);
+    }
 }
 
 // acc[it] += sum over the 64 nodes of a round of A[node][acol + i] B[node][bcol + 16 it + j]
-// (i, j = 0..15).  Result in the MFMA output layout: lane l, register r holds
-// (i = 4 (l >> 4) + r, j = l & 15).
+// (i, j = 0..15), with split-FP16 operands: K = nodes, two K steps of 32 in
+// which lane group q supplies nodes 32 s + 8 q .. 32 s + 8 q + 7.  Result in
+// the MFMA output layout: lane l, register r holds (i = 4 (l >> 4) + r, j = l & 15).
 template <int NB>
 __device__ __forceinline__ void round_wgrad(const float *A, int sa, int acol, const float *B, int sb, int bcol,
                                             floatx4 (&acc)[NB]) {
-    const int lane = lane_id(), col = lane & 15, kq = lane >> 4;
-#pragma unroll 4
-    for (int s = 0; s < 16; ++s) {
-        const int row = 4 * s + kq;
-        const float a = A[row * sa + acol + col];
+    const int lane = lane_id(), col = lane & 15, q = lane >> 4;
 #pragma unroll
-        for (int it = 0; it < NB; ++it) acc[it] = mfma4(a, B[row * sb + bcol + 16 * it + col], acc[it]);
+    for (int s = 0; s < 2; ++s) {
+        const int row0 = 32 * s + 8 * q;
+        float av[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) av[e] = A[(row0 + e) * sa + acol + col];
+        half8 ah, al;
+        split8(av, ah, al);
+#pragma unroll
+        for (int it = 0; it < NB; ++it) {
+            float bv[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) bv[e] = B[(row0 + e) * sb + bcol + 16 * it + col];
+            half8 bh, bl;
+            split8(bv, bh, bl);
+            acc[it] = mfma_split(ah, al, bh, bl, acc[it]);
+        }
     }
 }
 
@@ -211,18 +222,19 @@ __device__ void round_decoder_adjoint(BwdLds &S, WaveGrads &G, const floatx4 f[4
     store_rows(R.b, 16 * wave, f);
     store_rows(R.c, 16 * wave, h4);
 #pragma unroll
-    for (int c = gq; c < 16; c += 4) R.d[(16 * wave + node) * 16 + c] = c < 3 ? dr[c] : 0.0f;
+    for (int c = gq; c < 16; c += 4) R.d[(16 * wave + node) * kDS + c] = c < 3 ? dr[c] : 0.0f;
     __syncthreads();
     round_wgrad<4>(R.a, kRS, 16 * wave, R.b, kRS, 0, G.w4);
-    round_wgrad<1>(R.d, 16, 0, R.c, kRS, 16 * wave, G.w5);
+    round_wgrad<1>(R.d, kDS, 0, R.c, kRS, 16 * wave, G.w5);
     G.b4 += round_colsum(R.a, kRS, 16 * wave);
 }
 
 // Encoder adjoint of one round (phase B) given dL/df of each wave's tile:
-// accumulates the dW2 / dW1 / db2 / db1 slices and returns dL/dx of the tile
-// (D layout, inputs 0..15).
-__device__ void round_encoder_adjoint(BwdLds &S, WaveGrads &G, const float xs[3], const floatx4 h1[4],
-                                      const floatx4 f[4], const floatx4 df[4], floatx4 &dx) {
+// accumulates the dW2 / dW1 / db2 / db1 slices and returns dL/du_hat of the
+// tile's nodes (the gradient of inputs 6..8), valid in every lane for node
+// (lane & 15).  xf: this lane's 8 network inputs (features 8 (lane >> 4) + e).
+__device__ void round_encoder_adjoint(BwdLds &S, WaveGrads &G, const float xf[8], const floatx4 h1[4],
+                                      const floatx4 f[4], const floatx4 df[4], float du[3]) {
     reload_fence();
     const int wave = threadIdx.x >> 6, lane = lane_id(), gq = lane >> 4, node = lane & 15;
     RoundBuf &R = S.u.rb;
@@ -231,30 +243,33 @@ __device__ void round_encoder_adjoint(BwdLds &S, WaveGrads &G, const float xs[3]
     for (int ot = 0; ot < 4; ++ot)
 #pragma unroll
         for (int r = 0; r < 4; ++r) dpre2[ot][r] = f[ot][r] > 0.0f ? df[ot][r] : 0.0f;
-    matT_tile(S.w2t, dpre2, dh1);
+    matT_tile(S.w2th, S.w2tl, dpre2, dh1);
 #pragma unroll
     for (int ot = 0; ot < 4; ++ot)
 #pragma unroll
         for (int r = 0; r < 4; ++r) dh1[ot][r] = h1[ot][r] > 0.0f ? dh1[ot][r] : 0.0f;
-    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-    reload_fence();
+    // dL/du_hat = W1[:, 6..8]^T dpre1: partial over this lane's 16 features, then the 4 lane groups
 #pragma unroll
-    for (int ot = 0; ot < 4; ++ot) {
-        const floatx4 w = S.w1t[ot * 64 + lane];
+    for (int c = 0; c < 3; ++c) {
+        float t = 0.0f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc = mfma4(w[r], dh1[ot][r], acc);
+        for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) t += S.w1u[c][ot * 16 + 4 * gq + r] * dh1[ot][r];
+        t += __shfl_xor(t, 16);
+        t += __shfl_xor(t, 32);
+        du[c] = t;
     }
-    dx = acc;
     __syncthreads();
     store_rows(R.a, 16 * wave, dpre2);
     store_rows(R.b, 16 * wave, h1);
     store_rows(R.c, 16 * wave, dh1);
+    // x rows: groups 0 and 1 hold inputs 0..15; groups 2 and 3 write zeros to the padding
 #pragma unroll
-    for (int s = 0; s < 3; ++s) R.d[(16 * wave + node) * 16 + 4 * s + gq] = xs[s];
-    R.d[(16 * wave + node) * 16 + 12 + gq] = 0.0f;
+    for (int e = 0; e < 8; ++e) R.d[(16 * wave + node) * kDS + 8 * gq + e] = gq < 2 ? xf[e] : 0.0f;
     __syncthreads();
     round_wgrad<4>(R.a, kRS, 16 * wave, R.b, kRS, 0, G.w2);
-    round_wgrad<1>(R.c, kRS, 16 * wave, R.d, 16, 0, G.w1);
+    round_wgrad<1>(R.c, kRS, 16 * wave, R.d, kDS, 0, G.w1);
     G.b2 += round_colsum(R.a, kRS, 16 * wave);
     G.b1 += round_colsum(R.c, kRS, 16 * wave);
 }
@@ -267,9 +282,13 @@ __device__ __forceinline__ bool uses_residual(const BwdParams &p) {
     return p.model.mode != ETAC_DECAY_ONLY;
 }
 
-// Eq. 1 adjoint of one item.  Threads own active nodes (two each), passive
-// nodes (position, g) are staged through LDS.  Adds into gh ([3][n_max]) of
-// active nodes; returns this thread's dL/dalpha contribution.
+// Eq. 1 adjoint of one item.  Pairs (active j, passive i) are split over
+// (active slot, passive segment): every thread owns two active nodes of a
+// pass and one segment of each staged chunk of passive nodes (position, g);
+// with few active nodes the passive list is cut into 2 or 4 segments so that
+// all threads work.  Slots are whole waves, so LDS reads stay broadcasts.  The
+// segment partials of dL/du_hat_j are combined in segment order; the thread's
+// dL/dalpha contribution is returned.
 __device__ double decay_adjoint(const BwdParams &p, BwdLds &S, int e, int k, int base, int m, int np,
                                 const int *alist, const int *plist, const float *uhn, float *gh) {
     const MeshDev &M = p.mesh;
@@ -277,9 +296,12 @@ __device__ double decay_adjoint(const BwdParams &p, BwdLds &S, int e, int k, int
     const size_t EN = (size_t)p.E * N;
     const size_t row = (size_t)e * N + base;
     const float nbeta = (float)(-(double)p.model.alpha[k] * 1.4426950408889634);
+    const int slots = m <= 128 ? 64 : (m <= 256 ? 128 : kWG);     // threads per segment
+    const int nseg = kWG / slots;
+    const int slot = threadIdx.x % slots, seg = threadIdx.x / slots;
     double dalpha = 0.0;
-    for (int ab = 0; ab < m; ab += 2 * kWG) {
-        const int t0 = ab + threadIdx.x, t1 = t0 + kWG;
+    for (int ab = 0; ab < m; ab += 2 * slots) {
+        const int t0 = ab + slot, t1 = t0 + slots;
         const bool v0 = t0 < m, v1 = t1 < m;
         const int j0 = v0 ? alist[t0] : alist[0], j1 = v1 ? alist[t1] : alist[0];
         const int g0 = base + j0, g1 = base + j1;
@@ -299,8 +321,10 @@ __device__ double decay_adjoint(const BwdParams &p, BwdLds &S, int e, int k, int
                 S.u.st.b[t] = make_float2(p.grad_u[EN + row + i], p.grad_u[2 * EN + row + i]);
             }
             __syncthreads();
-            for (int i0 = 0; i0 < cnt; i0 += 32) {
-                const int i1 = min(cnt, i0 + 32);
+            const int per = (cnt + nseg - 1) / nseg;
+            const int lo = seg * per, hi = min(cnt, lo + per);
+            for (int i0 = lo; i0 < hi; i0 += 32) {
+                const int i1 = min(hi, i0 + 32);
                 float s0x = 0.f, s0y = 0.f, s0z = 0.f, s1x = 0.f, s1y = 0.f, s1z = 0.f, q0 = 0.f, q1 = 0.f;
                 for (int i = i0; i < i1; ++i) {
                     const float4 a = S.u.st.a[i];
@@ -322,17 +346,30 @@ __device__ double decay_adjoint(const BwdParams &p, BwdLds &S, int e, int k, int
                 da1 -= q1;
             }
         }
-        if (v0) {
-            gh[j0] = (float)((double)gh[j0] + a0[0]);
-            gh[n_max + j0] = (float)((double)gh[n_max + j0] + a0[1]);
-            gh[2 * n_max + j0] = (float)((double)gh[2 * n_max + j0] + a0[2]);
-            dalpha += da0;
-        }
-        if (v1) {
-            gh[j1] = (float)((double)gh[j1] + a1[0]);
-            gh[n_max + j1] = (float)((double)gh[n_max + j1] + a1[1]);
-            gh[2 * n_max + j1] = (float)((double)gh[2 * n_max + j1] + a1[2]);
-            dalpha += da1;
+        if (v0) dalpha += da0;
+        if (v1) dalpha += da1;
+        // combine the segments of each active node in segment order
+        __syncthreads();
+        double *mine = S.u.st.part[threadIdx.x];
+        mine[0] = a0[0]; mine[1] = a0[1]; mine[2] = a0[2];
+        mine[3] = a1[0]; mine[4] = a1[1]; mine[5] = a1[2];
+        __syncthreads();
+        if (seg == 0) {
+            for (int q = 1; q < nseg; ++q) {
+                const double *o = S.u.st.part[q * slots + slot];
+                a0[0] += o[0]; a0[1] += o[1]; a0[2] += o[2];
+                a1[0] += o[3]; a1[1] += o[4]; a1[2] += o[5];
+            }
+            if (v0) {
+                gh[j0] = (float)((double)gh[j0] + a0[0]);
+                gh[n_max + j0] = (float)((double)gh[n_max + j0] + a0[1]);
+                gh[2 * n_max + j0] = (float)((double)gh[2 * n_max + j0] + a0[2]);
+            }
+            if (v1) {
+                gh[j1] = (float)((double)gh[j1] + a1[0]);
+                gh[n_max + j1] = (float)((double)gh[n_max + j1] + a1[1]);
+                gh[2 * n_max + j1] = (float)((double)gh[2 * n_max + j1] + a1[2]);
+            }
         }
     }
     __syncthreads();
@@ -481,10 +518,10 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
     for (int t = wave; t < ntiles; t += kWaves) {
         const int ln = t * 16 + (lane & 15);
         const bool valid = ln < n;
-        float xs[3];
-        load_x(M, k, base + ln, valid, uhn, n_max, ln, xs);
+        half8 xh, xl;
+        load_x(M, k, base + ln, valid, uhn, n_max, ln, xh, xl);
         floatx4 h1[4], f[4];
-        encoder_tile(L, xs, h1, f);
+        encoder_tile(L, xh, xl, h1, f);
         if (valid)
             #pragma unroll
             for (int ot = 0; ot < 4; ++ot)
@@ -539,10 +576,11 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
         const int ln = (t0 + wave) * 16 + (lane & 15);
         const bool valid = ln < n;
         const bool passive = valid && wobj[ln] < 0;
-        float xs[3];
-        load_x(M, k, base + (valid ? ln : 0), valid, uhn, n_max, valid ? ln : 0, xs);
+        half8 xh, xl;
+        float xf[8];
+        load_x(M, k, base + (valid ? ln : 0), valid, uhn, n_max, valid ? ln : 0, xh, xl, xf);
         floatx4 h1[4], f[4], h4[4];
-        encoder_tile(L, xs, h1, f);
+        encoder_tile(L, xh, xl, h1, f);
         float r_unused[3];
         decoder_tile(L, f, h4, r_unused);
         float dr[3] = {0.0f, 0.0f, 0.0f};
@@ -551,10 +589,11 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
             dr[1] = p.grad_u[EN + row + ln];
             dr[2] = p.grad_u[2 * EN + row + ln];
         }
-        floatx4 dh4[4], df[4], dx;
+        floatx4 dh4[4], df[4];
+        float du[3];
         round_decoder_adjoint(S, G, f, h4, dr, dh4);
-        matT_tile(S.w4t, dh4, df);
-        round_encoder_adjoint(S, G, xs, h1, f, df, dx);
+        matT_tile(S.w4th, S.w4tl, dh4, df);
+        round_encoder_adjoint(S, G, xf, h1, f, df, du);
     }
     __syncthreads();
     S.s4[16 * wave + (lane & 15)] = G.b4;    // identical values in the 4 lane groups
@@ -596,10 +635,11 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
         const int slot = wave * 16 + (lane & 15);
         const int ln = S.argmax[slot];
         const bool valid = ln < n;
-        float xs[3];
-        load_x(M, k, base + (valid ? ln : 0), valid, uhn, n_max, valid ? ln : 0, xs);
-        floatx4 h1[4], f[4], df[4], dx;
-        encoder_tile(L, xs, h1, f);
+        half8 xh, xl;
+        float xf[8];
+        load_x(M, k, base + (valid ? ln : 0), valid, uhn, n_max, valid ? ln : 0, xh, xl, xf);
+        floatx4 h1[4], f[4], df[4];
+        encoder_tile(L, xh, xl, h1, f);
 #pragma unroll
         for (int ot = 0; ot < 4; ++ot)
 #pragma unroll
@@ -607,19 +647,20 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
                 const int feat = ot * 16 + 4 * gq + r;
                 df[ot][r] = (valid && feat == slot) ? S.dg[slot] : 0.0f;
             }
-        round_encoder_adjoint(S, G, xs, h1, f, df, dx);
-        S.dxs[slot][gq] = dx;   // input features 4 gq + r of this slot's node
+        float du[3];
+        round_encoder_adjoint(S, G, xf, h1, f, df, du);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) S.dxs[slot][c] = du[c];   // identical in the 4 lane groups
     }
     __syncthreads();
-    // u_hat channels are inputs 6, 7, 8 (group 1 r = 2, 3; group 2 r = 0).
-    // Wave 0 adds them in slot order; all its lanes do the same update.
+    // Wave 0 adds the routed dL/du_hat in slot order; all its lanes do the same update.
     if (threadIdx.x < 64)
         for (int c = 0; c < 64; ++c) {
             const int ln = S.argmax[c];
             if (ln < n && wobj[ln] >= 0) {
-                gh[ln] += S.dxs[c][1][2];
-                gh[n_max + ln] += S.dxs[c][1][3];
-                gh[2 * n_max + ln] += S.dxs[c][2][0];
+                gh[ln] += S.dxs[c][0];
+                gh[n_max + ln] += S.dxs[c][1];
+                gh[2 * n_max + ln] += S.dxs[c][2];
             }
         }
 
@@ -887,10 +928,13 @@ hipError_t launch_backward(const Plan &pl, const SceneDev *s, const ModelDev &m,
     p.grad_uhat_in = nullptr;
     p.grad_uhat_out = grad_uhat;
     const int grid = min(p.n_items, pl.cu_count);
+    int slot = timer_begin(pl, ETAC_TIMER_BACKWARD, st);
     if (s) hipLaunchKernelGGL(k_bwd<BWD_STEP>, dim3(grid), dim3(kWG), 0, st, p);
     else hipLaunchKernelGGL(k_bwd<BWD_PROP>, dim3(grid), dim3(kWG), 0, st, p);
     hipError_t e = hipGetLastError();
+    timer_end(pl, ETAC_TIMER_BACKWARD, slot, st);
     if (e != hipSuccess) return e;
+    slot = timer_begin(pl, ETAC_TIMER_REDUCE, st);
     if (grad_phi) {
         hipLaunchKernelGGL(k_list_items, dim3(1), dim3(1024), 0, st, pl.bwd.item_flag, p.n_items, pl.bwd.item_list,
                            pl.bwd.n_list);
@@ -904,7 +948,9 @@ hipError_t launch_backward(const Plan &pl, const SceneDev *s, const ModelDev &m,
         hipLaunchKernelGGL(k_pose, dim3((nt + 255) / 256), dim3(256), 0, st, pl.bwd.pose_part, n_envs, pl.K, s->O,
                            grad_rot, grad_trans);
     }
-    return hipGetLastError();
+    e = hipGetLastError();
+    timer_end(pl, ETAC_TIMER_REDUCE, slot, st);
+    return e;
 }
 
 hipError_t launch_contact_backward(const Plan &pl, const SceneDev &s, const float *grad_uhat, float *grad_rot,

@@ -243,55 +243,82 @@ __device__ int contact_and_compact(const MeshDev &M, const SceneDev &Sc, int E, 
 }
 
 // ---------------------------------------------------------------------------
-// residual network Phi on FP32 MFMA (v_mfma_f32_16x16x4_f32)
+// residual network Phi on MFMA with split-FP16 operands
+//
+// Every FP32 operand x is split as x = hi + lo with hi = fp16(x) and
+// lo = fp16(x - hi) (22 significant bits together), and a product is taken as
+// hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_f16 with FP32 accumulation.
+// The dropped lo*lo term is ~2^-22 relative, so a layer keeps FP32-level
+// accuracy at the FP16 matrix rate (about 5x the FP32 matrix rate).
 //
 // A 16-node tile is processed by one wave in transposed form, Y^T = W X^T:
 // the MFMA's M dimension is the layer's output features, N the 16 nodes, K the
-// input features.  Lane l holds node (l & 15); after a layer it holds output
-// features 16*ot + 4*(l >> 4) + r (r = 0..3) of out-tile ot in register r of
-// accumulator ot, which is exactly the B-operand layout the next layer needs
-// when its K steps are ordered (ot, r).  Weights are pre-arranged in LDS in
-// that fragment order, so every A operand is one conflict-free LDS read.
+// input features.  Lane l holds node (l & 15).  After a layer it holds output
+// features 16 ot + 4 (l >> 4) + r (r = 0..3) of out-tile ot in register r of
+// accumulator ot.  The next layer's K dimension is ordered so that these same
+// registers are its B operand: in K step s, lane group q = l >> 4 supplies
+// inputs 16 (2 s + (e >> 2)) + 4 q + (e & 3) for e = 0..7.  Weight fragments
+// are pre-arranged in LDS in that order (hi and lo halves), so every A
+// operand is one 16-byte LDS read.
 // ---------------------------------------------------------------------------
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+
 struct NetLds {
-    float w1f[4 * 3 * 64];       // [ot][s][lane]   W1, inputs padded 9 -> 12
-    floatx4 w2f[4 * 4 * 64];     // [ot2][ot][lane] W2 fragments, r in the vector
-    floatx4 w4f[4 * 4 * 64];     // [ot2][ot][lane] W4 columns 0..63 (per-node part)
+    half8 w1h[4 * 64], w1l[4 * 64];          // [ot][lane]    W1, inputs padded 9 -> 32 (one K step)
+    half8 w2h[4 * 2 * 64], w2l[4 * 2 * 64];  // [ot2][s][lane] W2
+    half8 w4h[4 * 2 * 64], w4l[4 * 2 * 64];  // [ot2][s][lane] W4 columns 0..63 (per-node part)
     float b1[64], b2[64];
-    float c4[64];                // W4[:, 64:] g' + b4, per item
+    float c4[64];                            // W4[:, 64:] g' + b4, per item
     float w5[3 * 64];
     float b5[4];
-    float g[64], gp[64];         // pooled feature and global MLP output
-    float part[kWaves][64];      // per-wave partials
+    float g[64], gp[64];                     // pooled feature and global MLP output
+    float part[kWaves][64];                  // per-wave partials
 };
+
+__device__ __forceinline__ void split8(const float v[8], half8 &hi, half8 &lo) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const _Float16 h = (_Float16)v[e];
+        hi[e] = h;
+        lo[e] = (_Float16)(v[e] - (float)h);
+    }
+}
+
+// Input feature of K step s, lane group q, element e of a 64 -> 64 layer.
+__device__ __forceinline__ int chain_k(int s, int q, int e) { return 16 * (2 * s + (e >> 2)) + 4 * q + (e & 3); }
 
 // Stage the network into LDS in fragment order (whole workgroup).
 __device__ void stage_net(NetLds &L, const float *phi) {
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < 4 * 3 * 64; idx += kWG) {
-        const int lane = idx & 63, s = (idx >> 6) % 3, ot = idx / 192;
-        const int in = 4 * s + (lane >> 4);
-        L.w1f[idx] = in < 9 ? phi[kW1 + (ot * 16 + (lane & 15)) * 9 + in] : 0.0f;
-    }
-    for (int idx = tid; idx < 4 * 4 * 64; idx += kWG) {
-        const int lane = idx & 63, ot = (idx >> 6) & 3, ot2 = idx >> 8;
-        const int out = ot2 * 16 + (lane & 15), in = ot * 16 + 4 * (lane >> 4);
-        floatx4 a, b;
-        #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            a[r] = phi[kW2 + out * 64 + in + r];
-            b[r] = phi[kW4 + out * 128 + in + r];
+    for (int idx = tid; idx < 4 * 64; idx += kWG) {
+        const int lane = idx & 63, ot = idx >> 6, q = lane >> 4;
+        float v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int in = 8 * q + e;
+            v[e] = in < 9 ? phi[kW1 + (ot * 16 + (lane & 15)) * 9 + in] : 0.0f;
         }
-        L.w2f[idx] = a;
-        L.w4f[idx] = b;
+        split8(v, L.w1h[idx], L.w1l[idx]);
+    }
+    for (int idx = tid; idx < 4 * 2 * 64; idx += kWG) {
+        const int lane = idx & 63, s = (idx >> 6) & 1, ot2 = idx >> 7, q = lane >> 4;
+        const int out = ot2 * 16 + (lane & 15);
+        float a[8], b[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int in = chain_k(s, q, e);
+            a[e] = phi[kW2 + out * 64 + in];
+            b[e] = phi[kW4 + out * 128 + in];
+        }
+        split8(a, L.w2h[idx], L.w2l[idx]);
+        split8(b, L.w4h[idx], L.w4l[idx]);
     }
     for (int i = tid; i < 64; i += kWG) {
         L.b1[i] = phi[kB1 + i];
         L.b2[i] = phi[kB2 + i];
     }
     for (int i = tid; i < 192; i += kWG) L.w5[i] = phi[kW5 + i];
-    if (tid < 3) L.b5[tid] = phi[kB5 + tid];
-    if (tid == 3) L.b5[3] = 0.0f;
+    for (int i = tid; i < 4; i += kWG) L.b5[i] = i < 3 ? phi[kB5 + i] : 0.0f;
 }
 
 // Keeps the compiler from hoisting the (loop-invariant) LDS weight-fragment
@@ -299,81 +326,104 @@ __device__ void stage_net(NetLds &L, const float *phi) {
 // registers per lane and spill.  Emits no instruction.
 __device__ __forceinline__ void reload_fence() { asm volatile("" ::: "memory"); }
 
-__device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+__device__ __forceinline__ floatx4 mfma16(const half8 &a, const half8 &b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+// acc += A B with split operands (hi*hi + hi*lo + lo*hi)
+__device__ __forceinline__ floatx4 mfma_split(const half8 &ah, const half8 &al, const half8 &bh, const half8 &bl,
+                                              floatx4 acc) {
+    acc = mfma16(ah, bh, acc);
+    acc = mfma16(ah, bl, acc);
+    return mfma16(al, bh, acc);
 }
 
 __device__ __forceinline__ floatx4 relu4(floatx4 v) {
     floatx4 o;
-    #pragma unroll
+#pragma unroll
     for (int r = 0; r < 4; ++r) o[r] = fmaxf(v[r], 0.0f);
     return o;
 }
 
-// Network input of this lane's node for the three K steps of layer 1: lane
-// group gq = lane >> 4 supplies input feature 4 s + gq of node (lane & 15).
-// Inputs: [p - o_k (3), n (3), U_hat (3)], padded with zeros to 12.
-__device__ __forceinline__ void load_x(const MeshDev &M, int k, int gnode, bool valid,
-                                       const float *uhn, int n_max, int lnode, float xs[3]) {
-    const int gq = lane_id() >> 4;
+// Split a D-layout 64-feature tile into the B operands of the two K steps of
+// the next 64 -> 64 layer.
+__device__ __forceinline__ void split_chain(const floatx4 x[4], half8 bh[2], half8 bl[2]) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        float v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = x[2 * s + (e >> 2)][e & 3];
+        split8(v, bh[s], bl[s]);
+    }
+}
+
+// Network input of this lane's node: lane group q = lane >> 4 supplies input
+// features 8 q .. 8 q + 7 of [p - o_k (3), n (3), U_hat (3)], zero padded to 32.
+__device__ __forceinline__ void load_x(const MeshDev &M, int k, int gnode, bool valid, const float *uhn, int n_max,
+                                       int lnode, half8 &xh, half8 &xl, float *xf = nullptr) {
+    const int q = lane_id() >> 4;
     const int N = M.N;
-    xs[0] = xs[1] = xs[2] = 0.0f;
-    if (!valid) return;
-    if (gq < 3) xs[0] = M.pos[(size_t)gq * N + gnode] - M.origin[3 * k + gq];
-    else xs[0] = M.nrm[gnode];
-    if (gq < 2) xs[1] = M.nrm[(size_t)(gq + 1) * N + gnode];
-    else xs[1] = uhn[(size_t)(gq - 2) * n_max + lnode];
-    if (gq == 0) xs[2] = uhn[(size_t)2 * n_max + lnode];
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = 0.0f;
+    if (valid && q == 0) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            v[a] = M.pos[(size_t)a * N + gnode] - M.origin[3 * k + a];
+            v[3 + a] = M.nrm[(size_t)a * N + gnode];
+        }
+        v[6] = uhn[lnode];
+        v[7] = uhn[(size_t)n_max + lnode];
+    } else if (valid && q == 1) {
+        v[0] = uhn[(size_t)2 * n_max + lnode];
+    }
+    if (xf)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xf[e] = v[e];
+    split8(v, xh, xl);
 }
 
 // Encoder: h1 = relu(W1 x + b1), f = relu(W2 h1 + b2) for a 16-node tile.
-__device__ __forceinline__ void encoder_tile(const NetLds &L, const float xs[3], floatx4 h1[4],
+__device__ __forceinline__ void encoder_tile(const NetLds &L, const half8 &xh, const half8 &xl, floatx4 h1[4],
                                              floatx4 f[4]) {
     reload_fence();
     const int lane = lane_id(), gq = lane >> 4;
 #pragma unroll
     for (int ot = 0; ot < 4; ++ot) {
-        floatx4 acc = *reinterpret_cast<const floatx4 *>(&L.b1[ot * 16 + 4 * gq]);
-#pragma unroll
-        for (int s = 0; s < 3; ++s) acc = mfma4(L.w1f[(ot * 3 + s) * 64 + lane], xs[s], acc);
-        h1[ot] = acc;
+        const floatx4 acc = *reinterpret_cast<const floatx4 *>(&L.b1[ot * 16 + 4 * gq]);
+        h1[ot] = relu4(mfma_split(L.w1h[ot * 64 + lane], L.w1l[ot * 64 + lane], xh, xl, acc));
     }
-#pragma unroll
-    for (int ot = 0; ot < 4; ++ot) h1[ot] = relu4(h1[ot]);
+    half8 bh[2], bl[2];
+    split_chain(h1, bh, bl);
 #pragma unroll
     for (int ot2 = 0; ot2 < 4; ++ot2) {
         floatx4 acc = *reinterpret_cast<const floatx4 *>(&L.b2[ot2 * 16 + 4 * gq]);
 #pragma unroll
-        for (int ot = 0; ot < 4; ++ot) {
-            const floatx4 w = L.w2f[(ot2 * 4 + ot) * 64 + lane];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) acc = mfma4(w[r], h1[ot][r], acc);
+        for (int s = 0; s < 2; ++s) {
+            const int fi = (ot2 * 2 + s) * 64 + lane;
+            acc = mfma_split(L.w2h[fi], L.w2l[fi], bh[s], bl[s], acc);
         }
-        f[ot2] = acc;
+        f[ot2] = relu4(acc);
     }
-#pragma unroll
-    for (int ot = 0; ot < 4; ++ot) f[ot] = relu4(f[ot]);
 }
 
 // Decoder: h4 = relu(W4 [f; g'] + b4) with the g' part folded into c4, then
 // r = W5 h4 + b5.  Every lane returns r of its node (lane & 15).
-__device__ __forceinline__ void decoder_tile(const NetLds &L, const floatx4 f[4], floatx4 h4[4],
-                                             float r_out[3]) {
+__device__ __forceinline__ void decoder_tile(const NetLds &L, const floatx4 f[4], floatx4 h4[4], float r_out[3]) {
     reload_fence();
     const int lane = lane_id(), gq = lane >> 4;
+    half8 bh[2], bl[2];
+    split_chain(f, bh, bl);
 #pragma unroll
     for (int ot2 = 0; ot2 < 4; ++ot2) {
         floatx4 acc = *reinterpret_cast<const floatx4 *>(&L.c4[ot2 * 16 + 4 * gq]);
 #pragma unroll
-        for (int ot = 0; ot < 4; ++ot) {
-            const floatx4 w = L.w4f[(ot2 * 4 + ot) * 64 + lane];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) acc = mfma4(w[r], f[ot][r], acc);
+        for (int s = 0; s < 2; ++s) {
+            const int fi = (ot2 * 2 + s) * 64 + lane;
+            acc = mfma_split(L.w4h[fi], L.w4l[fi], bh[s], bl[s], acc);
         }
-        h4[ot2] = acc;
+        h4[ot2] = relu4(acc);
     }
-#pragma unroll
-    for (int ot = 0; ot < 4; ++ot) h4[ot] = relu4(h4[ot]);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         float s = 0.0f;

@@ -51,8 +51,11 @@ hipError_t launch_contact(const Plan &p, const SceneDev &s, int8_t *cobj, float 
                           hipStream_t st) {
     if (s.E == 0) return hipSuccess;
     ContactParams cp{p.mesh, s, cobj, uhat, n_active};
+    const int slot = timer_begin(p, ETAC_TIMER_CONTACT, st);
     hipLaunchKernelGGL(k_contact, dim3(s.E), dim3(kWG), 0, st, cp);
-    return hipGetLastError();
+    const hipError_t e = hipGetLastError();
+    timer_end(p, ETAC_TIMER_CONTACT, slot, st);
+    return e;
 }
 
 // ---------------------------------------------------------------------------
@@ -140,10 +143,10 @@ __device__ void residual_item(const StepParams &p, StepLds &S, int k, int base, 
     for (int t = wave; t < ntiles; t += kWaves) {
         const int ln = t * 16 + (lane & 15);
         const bool valid = ln < n;
-        float xs[3];
-        load_x(p.mesh, k, base + ln, valid, uhn, n_max, ln, xs);
+        half8 xh, xl;
+        load_x(p.mesh, k, base + ln, valid, uhn, n_max, ln, xh, xl);
         floatx4 h1[4], f[4];
-        encoder_tile(L, xs, h1, f);
+        encoder_tile(L, xh, xl, h1, f);
         // f >= 0, so padding nodes with 0 leaves the max-pool unchanged
         if (valid)
             #pragma unroll
@@ -178,10 +181,10 @@ __device__ void residual_item(const StepParams &p, StepLds &S, int k, int base, 
     for (int t = wave; t < ntiles; t += kWaves) {
         const int ln = t * 16 + (lane & 15);
         const bool valid = ln < n;
-        float xs[3];
-        load_x(p.mesh, k, base + ln, valid, uhn, n_max, ln, xs);
+        half8 xh, xl;
+        load_x(p.mesh, k, base + ln, valid, uhn, n_max, ln, xh, xl);
         floatx4 h1[4], f[4], h4[4];
-        encoder_tile(L, xs, h1, f);
+        encoder_tile(L, xh, xl, h1, f);
         float r[3];
         decoder_tile(L, f, h4, r);
         if (valid && gq < 3) resid[gq * n_max + ln] = r[gq];
@@ -355,9 +358,12 @@ hipError_t launch_step(const Plan &pl, const SceneDev *s, const ModelDev &m, int
     p.cobj_out = cobj_out;
     p.n_active = n_active;
     const int grid = p.n_items < pl.grid ? p.n_items : pl.grid;
+    const int slot = timer_begin(pl, ETAC_TIMER_STEP, st);
     if (s) hipLaunchKernelGGL(k_step<false>, dim3(grid), dim3(kWG), 0, st, p);
     else hipLaunchKernelGGL(k_step<true>, dim3(grid), dim3(kWG), 0, st, p);
-    return hipGetLastError();
+    const hipError_t e = hipGetLastError();
+    timer_end(pl, ETAC_TIMER_STEP, slot, st);
+    return e;
 }
 
 }  // namespace etac

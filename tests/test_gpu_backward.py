@@ -230,3 +230,16 @@ def test_autograd_function_matches_direct_call(oracle_lib):
     (u2 * w).sum().backward()
     assert torch.isfinite(w6.grad).all()
     assert float(w6.grad.abs().sum()) > 0.0
+
+
+def test_hires_pads_backward_full_size_sampled(oracle_lib):
+    # decay-only adjoint at full size: pose gradients of sampled envs
+    mesh, scene, model = scenes.config4(n_envs=4096, mode=MODE_DECAY_ONLY)
+    w = np.random.default_rng(12).standard_normal((3, 4096, mesh.n_nodes)).astype(np.float32)
+    plan = make_plan(mesh, 4096, 4, backward=True)
+    log("[gpu] hires pads backward E=4096")
+    g = gpu_step_backward(plan, scene, model, w)
+    envs = np.random.default_rng(2).choice(4096, size=4, replace=False)
+    ref = oracle_lib.backward(mesh, scene.select(envs), model, w[:, envs].astype(np.float64))
+    _close(g["grad_trans"][envs], ref["grad_trans"], "grad_trans")
+    _close(g["grad_rot"][envs], ref["grad_rot"], "grad_rot")

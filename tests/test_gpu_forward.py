@@ -189,3 +189,22 @@ def test_config2_full_size_sampled(oracle_lib):
     err = max_err(u[:, envs], ref["u"])
     log(f"[gpu]   sampled max|dU| = {err:.3e}")
     assert err <= TOL_U
+
+
+def test_hires_pads_full_size_sampled(oracle_lib):
+    # 4096 envs x 4 pads of 128 x 128 nodes at 0.125 mm pitch (65536 nodes per
+    # env, 2.7e8 per step), one sphere or box per pad: contact of 8 sampled envs
+    # and their displacements against the oracle.  Active sets reach several
+    # thousand nodes, so the decay loop streams several LDS chunks.
+    mesh, scene, model = scenes.config4(n_envs=4096)
+    plan = make_plan(mesh, 4096, 4)
+    log("[gpu] hires pads E=4096 full size")
+    u, cobj, na = gpu_step(plan, scene, model)
+    envs = np.random.default_rng(1).choice(4096, size=8, replace=False)
+    ref = oracle_lib.forward(mesh, scene.select(envs), model)
+    assert np.array_equal(cobj[envs], ref["contact_obj"])
+    assert np.array_equal(na[envs], ref["n_active"])
+    assert na[envs].max() > 1536
+    err = max_err(u[:, envs], ref["u"])
+    log(f"[gpu]   sampled max|dU| = {err:.3e}")
+    assert err <= TOL_U
