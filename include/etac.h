@@ -42,8 +42,9 @@
  * device; HOST pointers are read during the call only.  The caller owns all
  * inputs and outputs; outputs are overwritten, never accumulated.  The plan
  * owns its copy of the mesh and all scratch memory; no call other than
- * etac_plan_create / etac_plan_destroy allocates, frees or synchronises, so
- * every other call may be captured in a HIP graph.
+ * etac_plan_create / etac_plan_destroy and the two kernel-timing calls
+ * allocates, frees or synchronises, so every compute call may be captured in
+ * a HIP graph.
  *
  * Streams: `stream` is a hipStream_t (NULL = the default stream).  Every call
  * only enqueues work on it.  A plan is used by one stream at a time.
@@ -186,6 +187,32 @@ etac_status etac_plan_info(const etac_plan *plan, int32_t *n_items, int32_t *gri
 /* Launch-shape override for the autotuner: persistent workgroups per CU for
  * the fused kernels (0 = built-in default). */
 etac_status etac_plan_set_occupancy(etac_plan *plan, int32_t wg_per_cu);
+
+/* Kernel timing (diagnostics, not part of the method).  With timing on, every
+ * launch of a timed kernel made outside stream capture is bracketed by a pair
+ * of HIP events recorded on the stream the kernel is launched on, so the
+ * measured span is that kernel's own execution on the device.  The plan keeps
+ * the most recent ETAC_TIMER_SLOTS pairs per timer. */
+#define ETAC_TIMER_SLOTS 256
+typedef enum {
+    ETAC_TIMER_CONTACT = 0,   /* k_contact: contact only (etac_contact)                  */
+    ETAC_TIMER_STEP = 1,      /* k_step: the fused persistent forward                    */
+    ETAC_TIMER_BACKWARD = 2,  /* k_bwd: the fused persistent adjoint                     */
+    ETAC_TIMER_REDUCE = 3,    /* the fixed-order reductions that follow k_bwd, as one span */
+    ETAC_TIMER_COUNT = 4
+} etac_timer;
+
+/* Turn timing on (enable != 0) or off.  The first call that turns it on
+ * creates the plan's events (host-side objects, freed by etac_plan_destroy);
+ * turning it on resets every timer.  ETAC_ERR_HIP if event creation fails. */
+etac_status etac_plan_set_timing(etac_plan *plan, int32_t enable);
+
+/* Waits for the recorded launches of `timer` (blocks the host), writes how
+ * many were recorded (at most ETAC_TIMER_SLOTS, the latest ones) and their
+ * summed device time in ms, and resets that timer.  Both outputs are HOST
+ * pointers.  ETAC_ERR_VALUE for an unknown timer; zero launches if timing was
+ * never turned on. */
+etac_status etac_plan_kernel_time(etac_plan *plan, int32_t timer, int32_t *launches, double *total_ms);
 
 #ifdef __cplusplus
 }

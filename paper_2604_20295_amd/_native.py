@@ -22,11 +22,14 @@ ETAC_FULL, ETAC_DECAY_ONLY, ETAC_RESIDUAL_ONLY = 0, 1, 2
 ETAC_PHI_SIZE = 17411
 ETAC_MAX_OBJ = 8
 ETAC_PLAN_BACKWARD = 1
+ETAC_TIMER_CONTACT, ETAC_TIMER_STEP, ETAC_TIMER_BACKWARD, ETAC_TIMER_REDUCE = 0, 1, 2, 3
+ETAC_TIMER_SLOTS = 256
 
 EXPORTED = (
     "etac_plan_create", "etac_plan_destroy", "etac_contact", "etac_propagate", "etac_step",
     "etac_contact_backward", "etac_propagate_backward", "etac_step_backward",
     "etac_status_string", "etac_last_hip_error", "etac_plan_info", "etac_plan_set_occupancy",
+    "etac_plan_set_timing", "etac_plan_kernel_time",
 )
 
 
@@ -80,6 +83,8 @@ def lib():
             "etac_last_hip_error": ([], i32),
             "etac_plan_info": ([vp, P(i32), P(i32), P(i64)], i32),
             "etac_plan_set_occupancy": ([vp, i32], i32),
+            "etac_plan_set_timing": ([vp, i32], i32),
+            "etac_plan_kernel_time": ([vp, i32, P(i32), P(C.c_double)], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -155,6 +160,16 @@ class Plan:
 
     def set_occupancy(self, wg_per_cu):
         _check("etac_plan_set_occupancy", lib().etac_plan_set_occupancy(self.handle, int(wg_per_cu)))
+
+    def set_timing(self, enable):
+        _check("etac_plan_set_timing", lib().etac_plan_set_timing(self.handle, 1 if enable else 0))
+
+    def kernel_time(self, timer):
+        """(launches, total device ms) of the latest launches of one timed
+        kernel since timing was turned on or last read; resets that timer."""
+        n, ms = C.c_int32(), C.c_double()
+        _check("etac_plan_kernel_time", lib().etac_plan_kernel_time(self.handle, int(timer), C.byref(n), C.byref(ms)))
+        return n.value, ms.value
 
     # -- struct marshalling ---------------------------------------------------
     def scene_struct(self, n_obj, type_, shape, rot, trans):

@@ -42,6 +42,14 @@ hipError_t plan_alloc(etac::Plan &p, T **ptr, size_t count) {
 void plan_free_all(etac::Plan &p) {
     for (int i = 0; i < p.n_allocs; ++i) (void)hipFree(p.allocs[i]);
     p.n_allocs = 0;
+    if (p.timers) {
+        for (int k = 0; k < ETAC_TIMER_COUNT; ++k)
+            for (int i = 0; i < ETAC_TIMER_SLOTS; ++i)
+                for (int j = 0; j < 2; ++j)
+                    if (p.timers->ev[k][i][j]) (void)hipEventDestroy(p.timers->ev[k][i][j]);
+        delete p.timers;
+        p.timers = nullptr;
+    }
 }
 
 // Round a non-negative double up to the next float at or above it.
@@ -247,6 +255,55 @@ etac_status etac_plan_set_occupancy(etac_plan *plan, int32_t wg_per_cu) {
     if (wg_per_cu < 0 || wg_per_cu > 8) return ETAC_ERR_VALUE;
     plan->p.wg_per_cu = wg_per_cu == 0 ? etac::kDefaultWgPerCu : wg_per_cu;
     plan->p.grid = plan->p.cu_count * plan->p.wg_per_cu;
+    return ETAC_OK;
+}
+
+etac_status etac_plan_set_timing(etac_plan *plan, int32_t enable) {
+    if (!plan) return ETAC_ERR_NULL;
+    etac::Plan &p = plan->p;
+    if (!enable) {
+        if (p.timers) p.timers->on = false;
+        return ETAC_OK;
+    }
+    if (!p.timers) {
+        etac::Timers *t = new (std::nothrow) etac::Timers();
+        if (!t) return ETAC_ERR_SHAPE;
+        std::memset(t, 0, sizeof(*t));
+        p.timers = t;
+        for (int k = 0; k < ETAC_TIMER_COUNT; ++k)
+            for (int i = 0; i < ETAC_TIMER_SLOTS; ++i)
+                for (int j = 0; j < 2; ++j) {
+                    hipError_t e = hipEventCreate(&t->ev[k][i][j]);
+                    if (e != hipSuccess) {
+                        t->ev[k][i][j] = nullptr;
+                        return hip_fail(e);
+                    }
+                }
+    }
+    for (int k = 0; k < ETAC_TIMER_COUNT; ++k) p.timers->n[k] = 0;
+    p.timers->on = true;
+    return ETAC_OK;
+}
+
+etac_status etac_plan_kernel_time(etac_plan *plan, int32_t timer, int32_t *launches, double *total_ms) {
+    if (!plan || !launches || !total_ms) return ETAC_ERR_NULL;
+    if (timer < 0 || timer >= ETAC_TIMER_COUNT) return ETAC_ERR_VALUE;
+    *launches = 0;
+    *total_ms = 0.0;
+    etac::Timers *t = plan->p.timers;
+    if (!t) return ETAC_OK;
+    const int n = std::min(t->n[timer], ETAC_TIMER_SLOTS);
+    double sum = 0.0;
+    for (int i = 0; i < n; ++i) {
+        hipError_t e = hipEventSynchronize(t->ev[timer][i][1]);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t->ev[timer][i][0], t->ev[timer][i][1]);
+        if (e != hipSuccess) return hip_fail(e);
+        sum += ms;
+    }
+    t->n[timer] = 0;
+    *launches = n;
+    *total_ms = sum;
     return ETAC_OK;
 }
 

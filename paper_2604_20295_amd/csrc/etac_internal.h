@@ -62,6 +62,13 @@ struct BwdScratch {
     double *phi_seg;       // [kPhiSegs][17411] segment sums of the parameter reduction
 };
 
+// Event pairs bracketing kernel launches (etac_plan_set_timing).
+struct Timers {
+    bool on;
+    hipEvent_t ev[ETAC_TIMER_COUNT][ETAC_TIMER_SLOTS][2];
+    int n[ETAC_TIMER_COUNT];
+};
+
 struct Plan {
     int device;
     int cu_count;
@@ -77,7 +84,24 @@ struct Plan {
     void *allocs[32];
     int n_allocs;
     int64_t scratch_bytes;
+    Timers *timers;        // null until timing is first turned on
 };
+
+// Open a timed span of timer k on stream st; returns the slot, or -1 when
+// timing is off or the stream is being captured.
+inline int timer_begin(const Plan &p, int k, hipStream_t st) {
+    Timers *t = p.timers;
+    if (!t || !t->on) return -1;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return -1;
+    const int slot = t->n[k] % ETAC_TIMER_SLOTS;
+    return hipEventRecord(t->ev[k][slot][0], st) == hipSuccess ? slot : -1;
+}
+
+inline void timer_end(const Plan &p, int k, int slot, hipStream_t st) {
+    if (slot < 0) return;
+    if (hipEventRecord(p.timers->ev[k][slot][1], st) == hipSuccess) p.timers->n[k]++;
+}
 
 // Launchers (return hipError_t of the launch).
 hipError_t launch_contact(const Plan &p, const SceneDev &s, int8_t *cobj, float *uhat, int32_t *n_active,

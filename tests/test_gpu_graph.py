@@ -67,3 +67,41 @@ def test_graph_replay_matches_eager(oracle_lib):
         s2 = scene.copy()
         s2.rot, s2.trans = traj_rot[t], traj_trans[t]
         assert np.array_equal(got["cobj"], oracle_lib.contact(mesh, s2)[0])
+
+
+def test_kernel_timer_counts_eager_launches_only(oracle_lib):
+    from paper_2604_20295_amd import _native
+    torch, dev = torch_dev()
+    mesh, scene, model = scenes.config2(n_envs=32)
+    plan = make_plan(mesh, 32, 3, backward=True)
+    ds, dm = DevScene(scene), DevModel(model)
+    sc, md = ds.struct(plan), dm.struct(plan)
+    E, N, K = 32, mesh.n_nodes, mesh.n_patches
+    u = torch.empty((3, E, N), device=dev)
+    cobj = torch.empty((E, N), dtype=torch.int8, device=dev)
+    na = torch.empty((E, K), dtype=torch.int32, device=dev)
+    log("[gpu] kernel timer")
+    assert plan.kernel_time(_native.ETAC_TIMER_STEP) == (0, 0.0)     # never turned on
+    plan.set_timing(True)
+    for _ in range(5):
+        _native.etac_step(plan, sc, md, u, cobj, na)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        _native.etac_step(plan, sc, md, u, cobj, na)          # 6th eager launch (side stream)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        _native.etac_step(plan, sc, md, u, cobj, na)          # captured: not timed
+    g.replay()
+    n, ms = plan.kernel_time(_native.ETAC_TIMER_STEP)
+    assert n == 6 and 0.0 < ms < 1e4
+    assert plan.kernel_time(_native.ETAC_TIMER_STEP) == (0, 0.0)    # reading resets
+    assert plan.kernel_time(_native.ETAC_TIMER_BACKWARD) == (0, 0.0)
+    plan.set_timing(False)
+    _native.etac_step(plan, sc, md, u, cobj, na)
+    assert plan.kernel_time(_native.ETAC_TIMER_STEP) == (0, 0.0)
+    ref = oracle_lib.forward(mesh, scene, model)
+    torch.cuda.synchronize()
+    assert np.array_equal(cobj.cpu().numpy(), ref["contact_obj"])
