@@ -23,10 +23,14 @@ if ROOT not in sys.path:
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-FP32_MFMA_PEAK_TFLOPS = 157.3  # dense FP32 matrix
-FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (no packed FP32)
+F16_MFMA_PEAK_TFLOPS = 2500.0  # dense FP16 matrix (the MFMA the network kernels issue)
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+MFMA_PASSES = 3                # split-FP16 products per FP32-equivalent product (hi*hi + hi*lo + lo*hi)
 ENC_MAC, DEC_MAC, GLOBAL_MAC = 9 * 64 + 64 * 64, 64 * 128 + 64 * 3, 2 * 64 * 64
 PAIR_FLOP = 20                 # decay pair: 3 sub, 5 for the squared distance, sqrt, scale, exp, 6 for w*u
+PAIR_FLOP_BWD = 30             # adjoint pair: the above without u, plus d*w and the g.u_hat dot product
+PHI_SIZE = 17411
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def parse():
@@ -135,6 +139,81 @@ def work_counts(mesh, n_active):
                 active=float(m.sum()))
 
 
+def algorithmic_work(kernel, counts, E, N, K, O, mode):
+    """Algorithmic work of one launch of the dominant kernel: FP32-equivalent
+    network flops (2 per multiply-add), decay-pair flops and the HBM bytes
+    that must move (inputs read once, outputs written once).  The adjoint
+    reads dL/dU only on patches in contact (elsewhere U = 0 whatever the
+    inputs) and writes one partial per item of alpha, the poses and, on
+    contacted items, the network parameters."""
+    nodes = float(E) * N
+    items = counts["contacted_items"]
+    decay = mode != 2     # not residual-only
+    net = mode != 1       # not decay-only
+    if kernel == "k_step":
+        return dict(mfma_flop=counts["mlp_flop"] if net else 0.0,
+                    valu_flop=PAIR_FLOP * counts["pairs"] if decay else 0.0,
+                    hbm_bytes=13.0 * nodes + 4.0 * E * K)
+    # adjoint: the network's forward is recomputed (no state is kept from the
+    # forward call) and both adjoint products run: 3x the forward flops
+    return dict(mfma_flop=3.0 * counts["mlp_flop"] if net else 0.0,
+                valu_flop=PAIR_FLOP_BWD * counts["pairs"] if decay else 0.0,
+                hbm_bytes=12.0 * counts["contacted_nodes"] + float(E) * K * (4.0 + 48.0 * O)
+                + (4.0 * PHI_SIZE * items if net else 0.0))
+
+
+def source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_2604_20295_amd", "csrc")
+    for f in sorted(os.listdir(src)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(open(os.path.join(src, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary, if it was taken on the current kernel sources."""
+    path = os.path.join(PROFILES, f"{kernel}_hand4096_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for ln in open(path):
+        if ":" in ln and not ln.startswith("#"):
+            a, b = ln.split(":", 1)
+            kv[a.strip()] = b.strip()
+    if kv.get("source_digest") != source_digest():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def roofline_of(kernel, avg_ms, work):
+    """Roofline of the dominant kernel: the resource whose lower-bound time
+    (work / peak) is largest names the bound; achieved = algorithmic work of
+    one launch / its average device time."""
+    t = avg_ms * 1e-3
+    lb = {"mfma": MFMA_PASSES * work["mfma_flop"] / (F16_MFMA_PEAK_TFLOPS * 1e12),
+          "alu": work["valu_flop"] / (FP32_VECTOR_PEAK_TFLOPS * 1e12),
+          "hbm": work["hbm_bytes"] / (HBM_PEAK_GBS * 1e9)}
+    bound = max(lb, key=lb.get)
+    if bound == "mfma":
+        achieved, peak, unit = work["mfma_flop"] / t / 1e12, F16_MFMA_PEAK_TFLOPS, "TFLOP/s"
+    elif bound == "alu":
+        achieved, peak, unit = work["valu_flop"] / t / 1e12, FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
+    else:
+        achieved, peak, unit = work["hbm_bytes"] / t / 1e9, HBM_PEAK_GBS, "GB/s"
+    traffic = measured_traffic(kernel)
+    return {"bound": bound, "kernel": kernel, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+            "frac": round(achieved / peak, 5), "traffic": traffic, "avg_ms": round(avg_ms, 4),
+            "mfma_passes": MFMA_PASSES if bound == "mfma" else None,
+            "lower_bound_ms": {k: round(v * 1e3, 4) for k, v in lb.items()},
+            "work_per_launch": work}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -192,9 +271,12 @@ def main():
     torch.cuda.synchronize()
     counts = work_counts(mesh, na.cpu().numpy())
 
-    # forward + backward steps, HIP events around each call on the launch stream
+    # forward + backward steps: HIP events around each call on the launch
+    # stream, and the library's per-kernel event pairs (same stream)
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()
+    if graph is None:
+        plan.set_timing(True)
     t0 = time.perf_counter()
     for s in range(args.steps):
         if graph is not None:
@@ -204,9 +286,15 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     step_ms = wall * 1e3 / args.steps
+    kernel_avg = {}
     if graph is None:
         fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
         bwd_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+        for name, tid in (("k_step", _native.ETAC_TIMER_STEP), ("k_bwd", _native.ETAC_TIMER_BACKWARD),
+                          ("bwd_reductions", _native.ETAC_TIMER_REDUCE)):
+            n, ms = plan.kernel_time(tid)
+            kernel_avg[name] = ms / n if n else float("nan")
+        plan.set_timing(False)
     else:
         fwd_ms = bwd_ms = float("nan")
     step_ev_ms = float(np.mean([e[0].elapsed_time(e[2]) for e in ev]))
@@ -227,14 +315,10 @@ def main():
     hbm_fwd_gbs = 13.0 * nodes / (fwd_only_ms * 1e-3) / 1e9
     hbm_step_gbs = 25.0 * nodes / (step_ms * 1e-3) / 1e9
 
-    # dominant kernel of the step: the fused forward or the adjoint launch
-    kernel = "k_bwd" if bwd_ms >= fwd_ms else "k_step"
-    k_ms = bwd_ms if kernel == "k_bwd" else fwd_ms
-    flop = counts["mlp_flop"] * (2.0 if kernel == "k_bwd" else 1.0)
-    achieved = flop / (k_ms * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "kernel": kernel, "achieved": round(achieved, 3), "peak": FP32_MFMA_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP32_MFMA_PEAK_TFLOPS, 4), "traffic": None,
-                "avg_ms": round(k_ms, 4)}
+    roofline = None
+    if kernel_avg:
+        kernel = max(("k_step", "k_bwd"), key=lambda k: kernel_avg[k])
+        roofline = roofline_of(kernel, kernel_avg[kernel], algorithmic_work(kernel, counts, E, N, K, O, mode))
 
     line = {
         "metric": "sensor node-updates/s at 4096 envs (fwd+bwd step)",
@@ -255,7 +339,8 @@ def main():
         "fwd_only": {"value": fwd_rate, "unit": "node-updates/s", "ms_per_step": fwd_only_ms,
                      "hbm_gbs": hbm_fwd_gbs, "hbm_frac": hbm_fwd_gbs / HBM_PEAK_GBS},
         "hbm_frac_step": hbm_step_gbs / HBM_PEAK_GBS,
-        "kernel_ms": {"etac_step": fwd_ms, "etac_step_backward": bwd_ms, "step_events": step_ev_ms},
+        "kernel_ms": {"etac_step": fwd_ms, "etac_step_backward": bwd_ms, "step_events": step_ev_ms,
+                      **{f"{k}_avg": v for k, v in kernel_avg.items()}},
         "work": counts,
         "roofline": roofline,
     }
