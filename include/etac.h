@@ -188,6 +188,11 @@ etac_status etac_plan_info(const etac_plan *plan, int32_t *n_items, int32_t *gri
  * the fused kernels (0 = built-in default). */
 etac_status etac_plan_set_occupancy(etac_plan *plan, int32_t wg_per_cu);
 
+/* Work-queue granularity for the autotuner: (env, patch) items claimed per
+ * queue atomic by the persistent kernels, 1 .. 64 (0 = built-in default).
+ * Results do not depend on it.  ETAC_ERR_VALUE outside 0 .. 64. */
+etac_status etac_plan_set_batch(etac_plan *plan, int32_t items);
+
 /* Kernel timing (diagnostics, not part of the method).  With timing on, every
  * launch of a timed kernel made outside stream capture is bracketed by a pair
  * of HIP events recorded on the stream the kernel is launched on, so the

@@ -29,7 +29,7 @@ EXPORTED = (
     "etac_plan_create", "etac_plan_destroy", "etac_contact", "etac_propagate", "etac_step",
     "etac_contact_backward", "etac_propagate_backward", "etac_step_backward",
     "etac_status_string", "etac_last_hip_error", "etac_plan_info", "etac_plan_set_occupancy",
-    "etac_plan_set_timing", "etac_plan_kernel_time",
+    "etac_plan_set_timing", "etac_plan_kernel_time", "etac_plan_set_batch",
 )
 
 
@@ -84,6 +84,7 @@ def lib():
             "etac_plan_info": ([vp, P(i32), P(i32), P(i64)], i32),
             "etac_plan_set_occupancy": ([vp, i32], i32),
             "etac_plan_set_timing": ([vp, i32], i32),
+            "etac_plan_set_batch": ([vp, i32], i32),
             "etac_plan_kernel_time": ([vp, i32, P(i32), P(C.c_double)], i32),
         }
         for name, (args, res) in sig.items():
@@ -160,6 +161,9 @@ class Plan:
 
     def set_occupancy(self, wg_per_cu):
         _check("etac_plan_set_occupancy", lib().etac_plan_set_occupancy(self.handle, int(wg_per_cu)))
+
+    def set_batch(self, items):
+        _check("etac_plan_set_batch", lib().etac_plan_set_batch(self.handle, int(items)))
 
     def set_timing(self, enable):
         _check("etac_plan_set_timing", lib().etac_plan_set_timing(self.handle, 1 if enable else 0))

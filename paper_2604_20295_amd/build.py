@@ -10,6 +10,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libetac.so")
 SOURCES = ["etac_api.cpp", "etac_forward.hip", "etac_backward.hip"]
+# The adjoint kernel keeps ~500 registers per lane live (one wave per SIMD);
+# letting MFMA results live in VGPRs as well as AGPRs avoids spills there.
+EXTRA = {"etac_backward.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -25,7 +28,7 @@ def build(verbose=False):
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
-        cmd = [HIPCC, "-x", "hip", *FLAGS, "-c", path, "-o", obj]
+        cmd = [HIPCC, "-x", "hip", *FLAGS, *EXTRA.get(src, []), "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)

@@ -136,6 +136,7 @@ etac_status etac_plan_create(const etac_mesh *mesh, int32_t n_envs, int32_t max_
     p.N = N;
     p.n_max = n_max;
     p.wg_per_cu = etac::kDefaultWgPerCu;
+    p.batch = etac::kDefaultBatch;
     hipError_t e = hipGetDevice(&p.device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&p.cu_count, hipDeviceAttributeMultiprocessorCount, p.device);
     if (e != hipSuccess) {
@@ -255,6 +256,13 @@ etac_status etac_plan_set_occupancy(etac_plan *plan, int32_t wg_per_cu) {
     if (wg_per_cu < 0 || wg_per_cu > 8) return ETAC_ERR_VALUE;
     plan->p.wg_per_cu = wg_per_cu == 0 ? etac::kDefaultWgPerCu : wg_per_cu;
     plan->p.grid = plan->p.cu_count * plan->p.wg_per_cu;
+    return ETAC_OK;
+}
+
+etac_status etac_plan_set_batch(etac_plan *plan, int32_t items) {
+    if (!plan) return ETAC_ERR_NULL;
+    if (items < 0 || items > 64) return ETAC_ERR_VALUE;
+    plan->p.batch = items == 0 ? etac::kDefaultBatch : items;
     return ETAC_OK;
 }
 

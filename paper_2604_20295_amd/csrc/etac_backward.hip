@@ -7,10 +7,12 @@
 //   2. Eq. 1 adjoint, transposed pair loop over passive nodes i:
 //        dL/du_hat_j += sum_i w_ij g_i,
 //        dL/dalpha_k += sum_ij (-d_ij w_ij) (g_i . u_hat_j)
-//   3. residual-network adjoint on FP32 MFMA (weight gradients are node
-//      contractions, fed through per-wave LDS transposes); the max-pool routes
-//      its gradient to the arg-max node of each channel (lowest index on
-//      ties), which reaches u_hat of active arg-max nodes through W1;
+//   3. residual-network adjoint on split-FP16 MFMA over the passive nodes
+//      (the only nodes whose residual is used); every layer is evaluated in
+//      both register layouts, so the weight gradients (contractions over
+//      nodes) take their operands straight from registers; the max-pool
+//      routes its gradient to the arg-max node of each channel (lowest index
+//      on ties), which reaches u_hat of active arg-max nodes through W1;
 //   4. contact adjoint: dL/d(R, t) of every winning object from dL/du_hat
 //      of its active nodes, in FP64.
 // Per-item partials (network parameters, alpha, poses) go to plan scratch and
@@ -21,7 +23,6 @@
 namespace etac {
 
 constexpr int kBChunk = 1024;  // passive nodes staged per pass of the decay adjoint
-constexpr int kTS = 68;        // row stride (floats) of the per-wave transpose tiles
 constexpr int kPhiSegs = 64;   // segments of the parameter-gradient reduction
 
 enum BwdKind { BWD_STEP = 0, BWD_PROP = 1, BWD_CONTACT = 2 };
@@ -33,6 +34,7 @@ struct BwdParams {
     Scratch scr;
     BwdScratch bwd;
     int E, n_items;
+    int batch;                    // queue positions claimed per atomic
     const int8_t *cobj_in;        // BWD_PROP
     const float *uhat_in;         // BWD_PROP
     const float *grad_u;          // [3][E][N]   BWD_STEP, BWD_PROP
@@ -40,20 +42,7 @@ struct BwdParams {
     float *grad_uhat_out;         // [3][E][N]   BWD_PROP
 };
 
-constexpr int kRS = 82;        // row stride (floats) of the 64-feature round tiles
-constexpr int kDS = 34;        // row stride of the 16-feature round tiles
-// Both strides put rows 8 apart 16 LDS banks apart, so the four lane groups of
-// an MFMA operand read (rows 8 q + e) hit different banks.
-
-// One round of the network adjoint: 4 tiles x 16 nodes (one tile per wave),
-// stored as rows [node][feature] so that every wave can contract over all 64
-// nodes for the weight-gradient slice it owns.
-struct RoundBuf {
-    float a[64 * kRS];         // phase A: dL/dpre4   | phase B: dL/dpre2
-    float b[64 * kRS];         // phase A: f          | phase B: h1
-    float c[64 * kRS];         // phase A: h4         | phase B: dL/dpre1
-    float d[64 * kDS];         // phase A: dL/dr      | phase B: x (inputs 0..15; 16..31 scratch)
-};
+constexpr int kRedRegs = 32;   // accumulator registers per lane summed per pass of the item reduction
 
 struct BwdLds {
     NetLds net;
@@ -66,18 +55,19 @@ struct BwdLds {
             float2 b[kBChunk];    // (gy, gz)
             double part[kWG][6];  // per-thread partial dL/du_hat of its two active nodes
         } st;
-        RoundBuf rb;
+        float red[kWaves][kRedRegs][64];   // one chunk of every wave's gradient accumulators
     } u;
+    floatx4 acc15[kWaves][8 * 64]; // per-wave dW1 (blocks 0-3) and dW5 (4-7) accumulators [block][lane]
     float s4[64];                 // sum_i dL/dpre4_i  (= db4)
     float dgp[64], dpre3[64], dg[64];
+    float vroute[64];             // dL/dpre2 routed to the arg-max node of channel c: dg[c] [g[c] > 0]
     float vred[kWaves][64];
     int ired[kWaves][64];
     int argmax[64];
     float dxs[64][3];             // dL/du_hat of the routed arg-max node of each channel
     double dred[kWaves][12];
     int wcnt[2][kWaves];
-    int item;
-    unsigned cand;
+    ItemBatch batch;
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -107,171 +97,360 @@ __device__ void stage_net_t(BwdLds &S, const float *phi) {
 }
 
 // ---------------------------------------------------------------------------
-// wave-level tile algebra
+// wave-level tile algebra in two register layouts
+//
+// T form (the forward's): lane l holds node (l & 15) of a 16-node tile;
+// register r of block b holds feature 16 b + 4 (l >> 4) + r.  It is the
+// output of W X^T with the tile as the MFMA's B operand, and chains into the
+// next layer as B.
+// N form: lane l holds feature 16 b + (l & 15) of block b; register r holds
+// node 4 (l >> 4) + r.  Feeding the split T-form tile as the A operand instead
+// (M = nodes, K = input features) and the same weight fragment as the B
+// operand gives X W^T in this layout.  In N form the nodes sit in registers,
+// so a weight gradient dW = sum_n a_n (x) b_n is one v_mfma_f32_16x16x16_f16
+// per 16 x 16 block with K = the tile's 16 nodes and both operands taken
+// straight from the N-form registers.
 // ---------------------------------------------------------------------------
+typedef _Float16 half4 __attribute__((ext_vector_type(4)));
 
-// Y^T = W^T X^T for a 16-node tile with X in D layout (the input-gradient
-// chain of a 64 -> 64 layer); wth / wtl: split fragments [it][s][lane].
-__device__ __forceinline__ void matT_tile(const half8 *wth, const half8 *wtl, const floatx4 x[4], floatx4 y[4]) {
-    reload_fence();
-    const int lane = lane_id();
-    half8 bh[2], bl[2];
-    split_chain(x, bh, bl);
+__device__ __forceinline__ void split4(const floatx4 &v, half4 &hi, half4 &lo) {
 #pragma unroll
-    for (int it = 0; it < 4; ++it) {
-        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int e = 0; e < 4; ++e) {
+        const _Float16 h = (_Float16)v[e];
+        hi[e] = h;
+        lo[e] = (_Float16)(v[e] - (float)h);
+    }
+}
+
+__device__ __forceinline__ floatx4 mfma_k16(const half4 &a, const half4 &b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+}
+
+// acc += A B over the tile's 16 nodes with split operands (hi*hi + hi*lo + lo*hi)
+__device__ __forceinline__ floatx4 mfma_k16_split(const half4 &ah, const half4 &al, const half4 &bh, const half4 &bl,
+                                                  floatx4 acc) {
+    acc = mfma_k16(ah, bh, acc);
+    acc = mfma_k16(ah, bl, acc);
+    return mfma_k16(al, bh, acc);
+}
+
+// Input layer (9 -> 64, inputs padded to one K step of 32) in both forms:
+// h1T = relu(W1 x + b1), h1N = relu(x W1^T + b1).
+__device__ __forceinline__ void layer1_dual(const NetLds &L, const half8 &xh, const half8 &xl, floatx4 h1T[4],
+                                            floatx4 h1N[4]) {
+    reload_fence();
+    const int lane = lane_id(), gq = lane >> 4, col = lane & 15;
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+        const half8 wh = L.w1h[ob * 64 + lane], wl = L.w1l[ob * 64 + lane];
+        const floatx4 bT = *reinterpret_cast<const floatx4 *>(&L.b1[ob * 16 + 4 * gq]);
+        const float bn = L.b1[ob * 16 + col];
+        h1T[ob] = relu4(mfma_split(wh, wl, xh, xl, bT));
+        h1N[ob] = relu4(mfma_split(xh, xl, wh, wl, floatx4{bn, bn, bn, bn}));
+    }
+}
+
+// A 64 -> 64 layer from a split T-form input (xh, xl: the two K steps):
+// yT = W x (+ bias), yN = x W^T (+ bias), each only if requested; relu if
+// RELU.  wh / wl: fragments [ob][s][lane] of W (or of a transposed weight).
+template <bool WANT_T, bool WANT_N, bool RELU>
+__device__ __forceinline__ void layer64(const half8 *wh, const half8 *wl, const half8 xh[2], const half8 xl[2],
+                                        const float *bias, floatx4 yT[4], floatx4 yN[4]) {
+    reload_fence();
+    const int lane = lane_id(), gq = lane >> 4, col = lane & 15;
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+        reload_fence();   // one block's fragments in flight at a time
+        floatx4 aT = {0.0f, 0.0f, 0.0f, 0.0f}, aN = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (bias) {
+            aT = *reinterpret_cast<const floatx4 *>(&bias[ob * 16 + 4 * gq]);
+            const float bn = bias[ob * 16 + col];
+            aN = floatx4{bn, bn, bn, bn};
+        }
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
-            const int fi = (it * 2 + s) * 64 + lane;
-            acc = mfma_split(wth[fi], wtl[fi], bh[s], bl[s], acc);
+            const int fi = (ob * 2 + s) * 64 + lane;
+            const half8 h = wh[fi], l = wl[fi];
+            if (WANT_T) aT = mfma_split(h, l, xh[s], xl[s], aT);
+            if (WANT_N) aN = mfma_split(xh[s], xl[s], h, l, aN);
         }
-        y[it] = acc;
+        if (WANT_T) yT[ob] = RELU ? relu4(aT) : aT;
+        if (WANT_N) yN[ob] = RELU ? relu4(aN) : aN;
     }
 }
 
-// Store a D-layout tile (16 nodes x 64 features) as round rows row0 .. row0 + 15.
-__device__ __forceinline__ void store_rows(float *t, int row0, const floatx4 v[4]) {
-    const int lane = lane_id(), node = lane & 15, gq = lane >> 4;
+// Network inputs in N form: lane l supplies input feature (l & 15) of nodes
+// 4 (l >> 4) + r: [p - o_k (3), n (3), U_hat (3)], a constant 1 at input 9
+// (its weight-gradient column is the bias gradient db1), zeros above.
+__device__ __forceinline__ floatx4 load_xn(const MeshDev &M, int k, int base, const int ln[4], const bool v[4],
+                                           const float *uhn, int n_max) {
+    const int col = lane_id() & 15, N = M.N;
+    floatx4 x;
 #pragma unroll
-    for (int ot = 0; ot < 4; ++ot) {
-        float *dst = &t[(row0 + node) * kRS + ot * 16 + 4 * gq];
-        *reinterpret_cast<float2 *>(dst) = make_float2(v[ot][0], v[ot][1]);
-        *reinterpret_cast<float2 *>(dst + 2) = make_float2(v[ot][2], v[ot][3]);
-    }
-}
-
-// acc[it] += sum over the 64 nodes of a round of A[node][acol + i] B[node][bcol + 16 it + j]
-// (i, j = 0..15), with split-FP16 operands: K = nodes, two K steps of 32 in
-// which lane group q supplies nodes 32 s + 8 q .. 32 s + 8 q + 7.  Result in
-// the MFMA output layout: lane l, register r holds (i = 4 (l >> 4) + r, j = l & 15).
-template <int NB>
-__device__ __forceinline__ void round_wgrad(const float *A, int sa, int acol, const float *B, int sb, int bcol,
-                                            floatx4 (&acc)[NB]) {
-    const int lane = lane_id(), col = lane & 15, q = lane >> 4;
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        const int row0 = 32 * s + 8 * q;
-        float av[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) av[e] = A[(row0 + e) * sa + acol + col];
-        half8 ah, al;
-        split8(av, ah, al);
-#pragma unroll
-        for (int it = 0; it < NB; ++it) {
-            float bv[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) bv[e] = B[(row0 + e) * sb + bcol + 16 * it + col];
-            half8 bh, bl;
-            split8(bv, bh, bl);
-            acc[it] = mfma_split(ah, al, bh, bl, acc[it]);
+    for (int r = 0; r < 4; ++r) {
+        float val = 0.0f;
+        if (v[r]) {
+            const int g = base + ln[r];
+            if (col < 3) val = M.pos[(size_t)col * N + g] - M.origin[3 * k + col];
+            else if (col < 6) val = M.nrm[(size_t)(col - 3) * N + g];
+            else if (col < 9) val = uhn[(size_t)(col - 6) * n_max + ln[r]];
+            else if (col == 9) val = 1.0f;
         }
+        x[r] = val;
     }
+    return x;
 }
 
-// Sum over the 64 round nodes of A[node][acol + i]; every lane returns the
-// sum for i = lane & 15 (lane groups sum 16 nodes each, then a butterfly).
-__device__ __forceinline__ float round_colsum(const float *A, int sa, int acol) {
-    const int lane = lane_id(), col = lane & 15, q = lane >> 4;
-    float s = 0.0f;
-    for (int r = 0; r < 16; ++r) s += A[(q * 16 + r) * sa + acol + col];
-    s += __shfl_xor(s, 16);
-    s += __shfl_xor(s, 32);
-    return s;
-}
-
-// This wave's slices of the parameter gradients: output rows 16 wave .. 16 wave + 15.
-struct WaveGrads {
-    floatx4 w4[4];       // dW4[:, :64]
-    floatx4 w2[4];       // dW2
-    floatx4 w1[1];       // dW1 (inputs padded to 16)
-    floatx4 w5[1];       // dW5 columns 16 wave + j (outputs padded to 16)
-    float b4, b2, b1;    // bias sums of output 16 wave + (lane & 15)
-    float b5[3];         // db5 partial (lane group 0 only)
+// This wave's accumulators of the item's parameter gradients.  Blocks are
+// 16 x 16 in MFMA output layout: lane l, register r holds row 4 (l >> 4) + r,
+// column l & 15 of the block.
+// dW1 (row blocks 0-3; columns = 16 padded inputs, column 9 = db1) and dW5
+// (column blocks 4-7; rows = the 3 outputs padded to 16) accumulate in the
+// wave's own LDS region S.acc15[wave] in the same layout.
+struct WGrad {
+    floatx4 w4[4][4];    // dW4[:, :64]   [row block][column block]
+    floatx4 w2[4][4];    // dW2
+    floatx4 b4, b2;      // per-lane partial sums of dpre4 / dpre2 for feature 16 b + (l & 15), b = component
+    float b5;            // lanes with (l & 15) < 3: partial db5[l & 15]
 };
 
-__device__ __forceinline__ void zero_grads(WaveGrads &G) {
+// acc15[wave][blk] += a b over the tile's nodes (split operands)
+__device__ __forceinline__ void acc15_add(floatx4 *acc, int blk, const half4 &ah, const half4 &al, const half4 &bh,
+                                          const half4 &bl) {
+    const int lane = lane_id();
+    const floatx4 t = mfma_k16_split(ah, al, bh, bl, floatx4{0.0f, 0.0f, 0.0f, 0.0f});
+    floatx4 v = acc[blk * 64 + lane];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] += t[r];
+    acc[blk * 64 + lane] = v;
+}
+
+__device__ __forceinline__ void zero_wgrad(WGrad &G) {
     const floatx4 z = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int a = 0; a < 4; ++a) { G.w4[a] = z; G.w2[a] = z; }
-    G.w1[0] = z;
-    G.w5[0] = z;
-    G.b4 = G.b2 = G.b1 = 0.0f;
-    G.b5[0] = G.b5[1] = G.b5[2] = 0.0f;
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) { G.w4[a][b] = z; G.w2[a][b] = z; }
+    G.b4 = z;
+    G.b2 = z;
+    G.b5 = 0.0f;
 }
 
-// Decoder adjoint of one round (phase A).  Each wave passes its tile's f, h4
-// and dL/dr; returns dL/dpre4 of its tile and accumulates its dW4 / dW5 / db4
-// slices over the round.
-__device__ void round_decoder_adjoint(BwdLds &S, WaveGrads &G, const floatx4 f[4], const floatx4 h4[4],
-                                      const float dr[3], floatx4 dh4[4]) {
-    reload_fence();
-    const int wave = threadIdx.x >> 6, lane = lane_id(), gq = lane >> 4, node = lane & 15;
+// Adjoint of one tile of 16 passive nodes (positions 16 t .. 16 t + 15 of the
+// passive list): forward recomputation, decoder and encoder adjoints, all
+// accumulated into this wave's parameter gradients.  Passive nodes have
+// U_hat = 0 and need no dL/du_hat.
+__device__ void passive_tile(const BwdParams &p, BwdLds &S, WGrad &G, int k, int base, int np,
+                             const int *plist, int t, size_t row, size_t EN, const float *uhn) {
     const NetLds &L = S.net;
-    RoundBuf &R = S.u.rb;
+    const MeshDev &M = p.mesh;
+    const int lane = lane_id(), gq = lane >> 4, col = lane & 15, n_max = p.scr.n_max;
+    // T form: this lane's node; N form: nodes 4 gq + r
+    const int li = 16 * t + col;
+    const bool valid = li < np;
+    const int ln = valid ? plist[li] : 0;
+    int lnr[4];
+    bool vr[4];
 #pragma unroll
-    for (int ot = 0; ot < 4; ++ot)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int feat = ot * 16 + 4 * gq + r;
-            const float v = L.w5[feat] * dr[0] + L.w5[64 + feat] * dr[1] + L.w5[128 + feat] * dr[2];
-            dh4[ot][r] = h4[ot][r] > 0.0f ? v : 0.0f;
-        }
-    if (gq == 0) { G.b5[0] += dr[0]; G.b5[1] += dr[1]; G.b5[2] += dr[2]; }
-    __syncthreads();                       // previous users of the round buffer are done
-    store_rows(R.a, 16 * wave, dh4);
-    store_rows(R.b, 16 * wave, f);
-    store_rows(R.c, 16 * wave, h4);
-#pragma unroll
-    for (int c = gq; c < 16; c += 4) R.d[(16 * wave + node) * kDS + c] = c < 3 ? dr[c] : 0.0f;
-    __syncthreads();
-    round_wgrad<4>(R.a, kRS, 16 * wave, R.b, kRS, 0, G.w4);
-    round_wgrad<1>(R.d, kDS, 0, R.c, kRS, 16 * wave, G.w5);
-    G.b4 += round_colsum(R.a, kRS, 16 * wave);
-}
-
-// Encoder adjoint of one round (phase B) given dL/df of each wave's tile:
-// accumulates the dW2 / dW1 / db2 / db1 slices and returns dL/du_hat of the
-// tile's nodes (the gradient of inputs 6..8), valid in every lane for node
-// (lane & 15).  xf: this lane's 8 network inputs (features 8 (lane >> 4) + e).
-__device__ void round_encoder_adjoint(BwdLds &S, WaveGrads &G, const float xf[8], const floatx4 h1[4],
-                                      const floatx4 f[4], const floatx4 df[4], float du[3]) {
-    reload_fence();
-    const int wave = threadIdx.x >> 6, lane = lane_id(), gq = lane >> 4, node = lane & 15;
-    RoundBuf &R = S.u.rb;
-    floatx4 dpre2[4], dh1[4];
-#pragma unroll
-    for (int ot = 0; ot < 4; ++ot)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) dpre2[ot][r] = f[ot][r] > 0.0f ? df[ot][r] : 0.0f;
-    matT_tile(S.w2th, S.w2tl, dpre2, dh1);
-#pragma unroll
-    for (int ot = 0; ot < 4; ++ot)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) dh1[ot][r] = h1[ot][r] > 0.0f ? dh1[ot][r] : 0.0f;
-    // dL/du_hat = W1[:, 6..8]^T dpre1: partial over this lane's 16 features, then the 4 lane groups
+    for (int r = 0; r < 4; ++r) {
+        const int q = 16 * t + 4 * gq + r;
+        vr[r] = q < np;
+        lnr[r] = vr[r] ? plist[q] : 0;
+    }
+    // dL/dr of the tile's nodes in both forms (zero on padding); loaded first
+    float dr[3], drn[3][4];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        float t = 0.0f;
+        dr[c] = valid ? p.grad_u[c * EN + row + ln] : 0.0f;
 #pragma unroll
-        for (int ot = 0; ot < 4; ++ot)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) t += S.w1u[c][ot * 16 + 4 * gq + r] * dh1[ot][r];
-        t += __shfl_xor(t, 16);
-        t += __shfl_xor(t, 32);
-        du[c] = t;
+        for (int r = 0; r < 4; ++r) drn[c][r] = vr[r] ? p.grad_u[c * EN + row + lnr[r]] : 0.0f;
     }
-    __syncthreads();
-    store_rows(R.a, 16 * wave, dpre2);
-    store_rows(R.b, 16 * wave, h1);
-    store_rows(R.c, 16 * wave, dh1);
-    // x rows: groups 0 and 1 hold inputs 0..15; groups 2 and 3 write zeros to the padding
+    // forward recomputation in both forms; T-form values that only gate a
+    // later step are kept as bit masks (bit 4 block + register)
+    half8 xh, xl;
+    load_x(M, k, base + ln, valid, uhn, n_max, ln, xh, xl);
+    floatx4 h1T[4], h1N[4];
+    layer1_dual(L, xh, xl, h1T, h1N);
+    half8 sh[2], sl[2];
+    split_chain(h1T, sh, sl);
+    floatx4 fT[4], fN[4];
+    layer64<true, true, true>(L.w2h, L.w2l, sh, sl, L.b2, fT, fN);
+    split_chain(fT, sh, sl);
+    unsigned fmask = 0;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) R.d[(16 * wave + node) * kDS + 8 * gq + e] = gq < 2 ? xf[e] : 0.0f;
-    __syncthreads();
-    round_wgrad<4>(R.a, kRS, 16 * wave, R.b, kRS, 0, G.w2);
-    round_wgrad<1>(R.c, kRS, 16 * wave, R.d, kDS, 0, G.w1);
-    G.b2 += round_colsum(R.a, kRS, 16 * wave);
-    G.b1 += round_colsum(R.c, kRS, 16 * wave);
+    for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) fmask |= (fT[ob][r] > 0.0f ? 1u : 0u) << (4 * ob + r);
+    floatx4 h4T[4], h4N[4];
+    layer64<true, true, true>(L.w4h, L.w4l, sh, sl, L.c4, h4T, h4N);
+    // dL/dpre4 = (W5^T dr) [h4 > 0] in both forms
+    floatx4 d4T[4], d4N[4];
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+        const int fn = ob * 16 + col;
+        const float w0 = L.w5[fn], w1 = L.w5[64 + fn], w2 = L.w5[128 + fn];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ft = ob * 16 + 4 * gq + r;
+            const float vt = L.w5[ft] * dr[0] + L.w5[64 + ft] * dr[1] + L.w5[128 + ft] * dr[2];
+            d4T[ob][r] = h4T[ob][r] > 0.0f ? vt : 0.0f;
+            const float vn = w0 * drn[0][r] + w1 * drn[1][r] + w2 * drn[2][r];
+            d4N[ob][r] = h4N[ob][r] > 0.0f ? vn : 0.0f;
+        }
+    }
+
+    // dW5 += dr (x) h4 (lane col < 3 supplies output col), db5
+    {
+        floatx4 a;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[r] = col == 0 ? drn[0][r] : (col == 1 ? drn[1][r] : (col == 2 ? drn[2][r] : 0.0f));
+        G.b5 += (a[0] + a[1]) + (a[2] + a[3]);
+        half4 ah, al;
+        split4(a, ah, al);
+        floatx4 *acc = S.acc15[threadIdx.x >> 6];
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) {
+            half4 bh, bl;
+            split4(h4N[ib], bh, bl);
+            acc15_add(acc, 4 + ib, ah, al, bh, bl);
+        }
+    }
+    // dL/df = W4[:, :64]^T dpre4 in both forms
+    split_chain(d4T, sh, sl);
+    floatx4 dfT[4], dfN[4];
+    layer64<true, true, false>(S.w4th, S.w4tl, sh, sl, nullptr, dfT, dfN);
+    // dW4[:, :64] += dpre4 (x) f, db4
+    {
+        half4 fh[4], fl[4];
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) split4(fN[ib], fh[ib], fl[ib]);
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) {
+            G.b4[ob] += (d4N[ob][0] + d4N[ob][1]) + (d4N[ob][2] + d4N[ob][3]);
+            half4 ah, al;
+            split4(d4N[ob], ah, al);
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib) G.w4[ob][ib] = mfma_k16_split(ah, al, fh[ib], fl[ib], G.w4[ob][ib]);
+        }
+    }
+    // dL/dpre2 = df [f > 0]; dL/dh1 = W2^T dpre2 (N form only: no dL/du_hat here)
+    floatx4 d2T[4], d2N[4];
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            d2T[ob][r] = ((fmask >> (4 * ob + r)) & 1u) ? dfT[ob][r] : 0.0f;
+            d2N[ob][r] = fN[ob][r] > 0.0f ? dfN[ob][r] : 0.0f;
+        }
+    split_chain(d2T, sh, sl);
+    floatx4 dh1N[4];
+    layer64<false, true, false>(S.w2th, S.w2tl, sh, sl, nullptr, nullptr, dh1N);
+    // dW2 += dpre2 (x) h1, db2
+    {
+        half4 hh[4], hl[4];
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) split4(h1N[ib], hh[ib], hl[ib]);
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) {
+            G.b2[ob] += (d2N[ob][0] + d2N[ob][1]) + (d2N[ob][2] + d2N[ob][3]);
+            half4 ah, al;
+            split4(d2N[ob], ah, al);
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib) G.w2[ob][ib] = mfma_k16_split(ah, al, hh[ib], hl[ib], G.w2[ob][ib]);
+        }
+    }
+    // dW1 += dpre1 (x) x (db1 through input 9)
+    {
+        half4 xnh, xnl;
+        split4(load_xn(M, k, base, lnr, vr, uhn, n_max), xnh, xnl);
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) {
+            floatx4 d1;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) d1[r] = h1N[ob][r] > 0.0f ? dh1N[ob][r] : 0.0f;
+            half4 ah, al;
+            split4(d1, ah, al);
+            acc15_add(S.acc15[threadIdx.x >> 6], ob, ah, al, xnh, xnl);
+        }
+    }
+}
+
+// Max-pool routing for the wave's 16 channels c = 16 wave + j: the
+// gradient dL/dpre2 = vroute[c] e_c at the arg-max node of channel c.  Its
+// dL/dh1 is vroute[c] W2[c, :] (exact FP32 products); adds the dW2 rows,
+// dW1 and db1 contributions and leaves dL/du_hat of each channel's node in
+// S.dxs (identical in the four lane groups).
+__device__ void routing_tile(const BwdParams &p, BwdLds &S, WGrad &G, int k, int base, int n, const float *uhn) {
+    const NetLds &L = S.net;
+    const MeshDev &M = p.mesh;
+    const float *phi = p.model.phi;
+    const int lane = lane_id(), wave = threadIdx.x >> 6, gq = lane >> 4, col = lane & 15, n_max = p.scr.n_max;
+    // T form: channel 16 wave + col; N form: channels 16 wave + 4 gq + r
+    const int cT = 16 * wave + col;
+    const int lnT = S.argmax[cT];
+    const bool vT = lnT < n;
+    int lnr[4], cr[4];
+    bool vr[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        cr[r] = 16 * wave + 4 * gq + r;
+        lnr[r] = S.argmax[cr[r]];
+        vr[r] = lnr[r] < n;
+        if (!vr[r]) lnr[r] = 0;
+    }
+    half8 xh, xl;
+    load_x(M, k, base + (vT ? lnT : 0), vT, uhn, n_max, vT ? lnT : 0, xh, xl);
+    floatx4 h1T[4], h1N[4];
+    layer1_dual(L, xh, xl, h1T, h1N);
+    const float vt = vT ? S.vroute[cT] : 0.0f;
+    float vn[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) vn[r] = vr[r] ? S.vroute[cr[r]] : 0.0f;
+    // dL/du_hat of the channel's node: W1[:, 6..8]^T (dh1 [h1 > 0]) in T form
+    float du[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+        const float *wrow = &phi[kW2 + cT * 64 + ob * 16 + 4 * gq];   // caller memory: scalar loads
+        const float wv[4] = {wrow[0], wrow[1], wrow[2], wrow[3]};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int f = ob * 16 + 4 * gq + r;
+            const float d1 = h1T[ob][r] > 0.0f ? vt * wv[r] : 0.0f;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) du[c] += S.w1u[c][f] * d1;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        du[c] += __shfl_xor(du[c], 16);
+        du[c] += __shfl_xor(du[c], 32);
+        S.dxs[cT][c] = du[c];
+    }
+    // dW2 rows 16 wave + 4 gq + r += vroute h1 (FP32): row block `wave`; the
+    // other blocks add exact zeros (no register indexed by the wave number)
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+        const bool mine = ob == wave;
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) G.w2[ob][ib][r] += (mine ? vn[r] : 0.0f) * h1N[ib][r];
+    }
+    // dW1 += dpre1 (x) x with dpre1 = vroute W2[c, :] [h1 > 0] in N form
+    half4 xnh, xnl;
+    split4(load_xn(M, k, base, lnr, vr, uhn, n_max), xnh, xnl);
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+        floatx4 d1;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const float w = phi[kW2 + cr[r] * 64 + ob * 16 + col];
+            d1[r] = h1N[ob][r] > 0.0f ? vn[r] * w : 0.0f;
+        }
+        half4 ah, al;
+        split4(d1, ah, al);
+        acc15_add(S.acc15[wave], ob, ah, al, xnh, xnl);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -494,10 +673,55 @@ __device__ void contact_adjoint_item(const BwdParams &p, BwdLds &S, int e, int i
     }
 }
 
+// Sum accumulator chunk C over the four waves (in wave order) and store it
+// into the item's parameter-gradient partial.
+template <int C>
+__device__ __forceinline__ void store_partials(BwdLds &S, const WGrad &G, float *out) {
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    __syncthreads();    // previous users of the buffer are done
+    // chunks 0-1: dW4[:, :64] row blocks 0-1 / 2-3; chunks 2-3: the same of
+    // dW2; chunk 4: dW1 then dW5 (every register named statically, so the
+    // accumulators never leave registers)
+#define ETAC_ST(j, blk)                                                          \
+    {                                                                            \
+        const floatx4 v_ = (blk);                                                \
+        for (int r = 0; r < 4; ++r) S.u.red[wave][4 * (j) + r][lane] = v_[r];    \
+    }
+#define ETAC_ST4(j0, arr) ETAC_ST(j0, arr[0]) ETAC_ST(j0 + 1, arr[1]) ETAC_ST(j0 + 2, arr[2]) ETAC_ST(j0 + 3, arr[3])
+    if (C == 0) { ETAC_ST4(0, G.w4[0]) ETAC_ST4(4, G.w4[1]) }
+    if (C == 1) { ETAC_ST4(0, G.w4[2]) ETAC_ST4(4, G.w4[3]) }
+    if (C == 2) { ETAC_ST4(0, G.w2[0]) ETAC_ST4(4, G.w2[1]) }
+    if (C == 3) { ETAC_ST4(0, G.w2[2]) ETAC_ST4(4, G.w2[3]) }
+    if (C == 4)
+        for (int j = 0; j < 8; ++j) ETAC_ST(j, S.acc15[wave][j * 64 + lane])
+#undef ETAC_ST4
+#undef ETAC_ST
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kRedRegs * 64; idx += kWG) {
+        const int reg = idx >> 6, ln = idx & 63;
+        float v = S.u.red[0][reg][ln];
+        for (int w = 1; w < kWaves; ++w) v += S.u.red[w][reg][ln];
+        const int j = reg >> 2, r = reg & 3, cl = ln & 15;
+        const int lrow = 4 * (ln >> 4) + r;      // row within the 16 x 16 block
+        if (C < 4) {
+            const int ob = 2 * (C & 1) + (j >> 2), ib = j & 3;
+            const int o = 16 * ob + lrow, i = 16 * ib + cl;
+            if (C < 2) out[kW4 + o * 128 + i] = v;
+            else out[kW2 + o * 64 + i] = v;
+        } else if (j < 4) {
+            const int o = 16 * j + lrow;
+            if (cl < 9) out[kW1 + o * 9 + cl] = v;
+            else if (cl == 9) out[kB1 + o] = v;
+        } else if (lrow < 3) {
+            out[kW5 + lrow * 64 + 16 * (j - 4) + cl] = v;
+        }
+    }
+}
+
 // Residual-network adjoint of one item; writes its parameter-gradient
 // partial and adds dL/du_hat of active arg-max nodes into gh.
-__device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, int item, int base, int n,
-                                 const float *uhn, const int8_t *wobj, float *gh) {
+__device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, int item, int base, int n, int np,
+                                 const int *plist, const float *uhn, const int8_t *wobj, float *gh) {
     NetLds &L = S.net;
     const MeshDev &M = p.mesh;
     const float *phi = p.model.phi;
@@ -568,39 +792,29 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
     __syncthreads();
     global_mlp(L, phi);
 
-    // (b) rounds of four tiles: decoder adjoint (phase A), then encoder
-    //     adjoint (phase B) of every tile's passive nodes
-    WaveGrads G;
-    zero_grads(G);
-    for (int t0 = 0; t0 < ntiles; t0 += kWaves) {
-        const int ln = (t0 + wave) * 16 + (lane & 15);
-        const bool valid = ln < n;
-        const bool passive = valid && wobj[ln] < 0;
-        half8 xh, xl;
-        float xf[8];
-        load_x(M, k, base + (valid ? ln : 0), valid, uhn, n_max, valid ? ln : 0, xh, xl, xf);
-        floatx4 h1[4], f[4], h4[4];
-        encoder_tile(L, xh, xl, h1, f);
-        float r_unused[3];
-        decoder_tile(L, f, h4, r_unused);
-        float dr[3] = {0.0f, 0.0f, 0.0f};
-        if (passive) {
-            dr[0] = p.grad_u[row + ln];
-            dr[1] = p.grad_u[EN + row + ln];
-            dr[2] = p.grad_u[2 * EN + row + ln];
-        }
-        floatx4 dh4[4], df[4];
-        float du[3];
-        round_decoder_adjoint(S, G, f, h4, dr, dh4);
-        matT_tile(S.w4th, S.w4tl, dh4, df);
-        round_encoder_adjoint(S, G, xf, h1, f, df, du);
+    // (b) decoder and encoder adjoints over the passive nodes, tile t on wave t % 4
+    WGrad G;
+    zero_wgrad(G);
+    for (int j = 0; j < 8; ++j) S.acc15[wave][j * 64 + lane] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int ptiles = (np + 15) >> 4;
+    for (int t = wave; t < ptiles; t += kWaves) passive_tile(p, S, G, k, base, np, plist, t, row, EN, uhn);
+
+    // (c) db4 = s4 = sum_i dpre4_i; global MLP adjoint: dg' = W4[:, 64:]^T s4,
+    //     dpre3 = dg' [g' > 0], dg = W3^T dpre3
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+        float v = G.b4[ob];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        S.vred[wave][ob * 16 + (lane & 15)] = v;     // identical in the 4 lane groups
     }
     __syncthreads();
-    S.s4[16 * wave + (lane & 15)] = G.b4;    // identical values in the 4 lane groups
+    if (threadIdx.x < 64) {
+        float t = S.vred[0][threadIdx.x];
+        for (int w = 1; w < kWaves; ++w) t += S.vred[w][threadIdx.x];
+        S.s4[threadIdx.x] = t;
+    }
     __syncthreads();
-
-    // (c) global MLP adjoint: dg' = W4[:, 64:]^T s4, dpre3 = dg' gated by
-    //     g' > 0, dg = W3^T dpre3
     {
         // each wave sums 16 of the 64 terms, the partials are added in wave order
         const int c = lane;
@@ -625,35 +839,16 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
             float t = S.vred[0][c];
             for (int w = 1; w < kWaves; ++w) t += S.vred[w][c];
             S.dg[c] = t;
+            // f = relu(pre2) >= 0 and f at the arg-max node is g, so its gate is g > 0
+            S.vroute[c] = L.g[c] > 0.0f ? t : 0.0f;
         }
         __syncthreads();
     }
 
-    // (d) max-pool routing round: slot c carries dL/df = dg[c] e_c at the
-    //     arg-max node of channel c; wave w holds slots 16 w .. 16 w + 15
-    {
-        const int slot = wave * 16 + (lane & 15);
-        const int ln = S.argmax[slot];
-        const bool valid = ln < n;
-        half8 xh, xl;
-        float xf[8];
-        load_x(M, k, base + (valid ? ln : 0), valid, uhn, n_max, valid ? ln : 0, xh, xl, xf);
-        floatx4 h1[4], f[4], df[4];
-        encoder_tile(L, xh, xl, h1, f);
-#pragma unroll
-        for (int ot = 0; ot < 4; ++ot)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int feat = ot * 16 + 4 * gq + r;
-                df[ot][r] = (valid && feat == slot) ? S.dg[slot] : 0.0f;
-            }
-        float du[3];
-        round_encoder_adjoint(S, G, xf, h1, f, df, du);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) S.dxs[slot][c] = du[c];   // identical in the 4 lane groups
-    }
+    // (d) max-pool routing: wave w takes channels 16 w .. 16 w + 15
+    routing_tile(p, S, G, k, base, n, uhn);
     __syncthreads();
-    // Wave 0 adds the routed dL/du_hat in slot order; all its lanes do the same update.
+    // Wave 0 adds the routed dL/du_hat in channel order; all its lanes do the same update.
     if (threadIdx.x < 64)
         for (int c = 0; c < 64; ++c) {
             const int ln = S.argmax[c];
@@ -664,27 +859,39 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
             }
         }
 
-    // (e) item partial of every parameter gradient; each wave writes its slices
+    // (e) item partial of every parameter gradient: the four waves'
+    //     accumulators summed in wave order, kRedRegs registers per pass
+    store_partials<0>(S, G, out);
+    store_partials<1>(S, G, out);
+    store_partials<2>(S, G, out);
+    store_partials<3>(S, G, out);
+    store_partials<4>(S, G, out);
+    // db2 (passive sums plus the routed one-hots) and db5
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+        float v = G.b2[ob];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        S.vred[wave][ob * 16 + (lane & 15)] = v;
+    }
     {
-        const int col = lane & 15, o16 = 16 * wave;
-#pragma unroll
-        for (int it = 0; it < 4; ++it)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int o = o16 + 4 * gq + r, i = 16 * it + col;
-                out[kW4 + o * 128 + i] = G.w4[it][r];
-                out[kW2 + o * 64 + i] = G.w2[it][r];
-            }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int o = o16 + 4 * gq + r;
-            if (col < 9) out[kW1 + o * 9 + col] = G.w1[0][r];
-            const int o5 = 4 * gq + r;
-            if (o5 < 3) out[kW5 + o5 * 64 + o16 + col] = G.w5[0][r];
+        float v = G.b5;
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        S.ired[wave][lane & 15] = __float_as_int(v);      // lanes (l & 15) < 3 carry db5
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int c = threadIdx.x;
+        float t = S.vred[0][c];
+        for (int w = 1; w < kWaves; ++w) t += S.vred[w][c];
+        out[kB2 + c] = t + S.vroute[c];
+        out[kB4 + c] = S.s4[c];
+        if (c < 3) {
+            float b = __int_as_float(S.ired[0][c]);
+            for (int w = 1; w < kWaves; ++w) b += __int_as_float(S.ired[w][c]);
+            out[kB5 + c] = b;
         }
-        out[kB4 + o16 + col] = G.b4;
-        out[kB2 + o16 + col] = G.b2;
-        out[kB1 + o16 + col] = G.b1;
     }
     for (int idx = threadIdx.x; idx < 64 * 64; idx += kWG) {
         const int o = idx >> 6, c = idx & 63;
@@ -692,48 +899,40 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
         out[kW3 + o * 64 + c] = S.dpre3[o] * L.g[c];          // dW3 = dpre3 (x) g
     }
     if (threadIdx.x < 64) out[kB3 + threadIdx.x] = S.dpre3[threadIdx.x];
-    // db5: wave sums (only lane group 0 accumulated), then the waves in order
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        float x = G.b5[c];
-        for (int off = 1; off <= 32; off <<= 1) x += __shfl_xor(x, off);
-        G.b5[c] = x;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < 3; ++c) S.vred[wave][c] = G.b5[c];
-    __syncthreads();
-    if (threadIdx.x < 64)
-        for (int c = 0; c < 3; ++c) {
-            float s = S.vred[0][c];
-            for (int w = 1; w < kWaves; ++w) s += S.vred[w][c];
-            out[kB5 + c] = s;
-        }
     __syncthreads();
 }
 
+// Zero partials of the batch's items that no object can reach (wave w takes
+// items w, w + 4, ...; no barrier needed).
+__device__ void zero_fill_batch_bwd(const BwdParams &p, const ItemBatch &B, int b0) {
+    const MeshDev &M = p.mesh;
+    const int wave = threadIdx.x >> 6, lane = lane_id(), O = p.scene.O;
+    const unsigned long long live = batch_mask(B);
+    for (int j = wave; j < p.batch; j += kWaves) {
+        const int q = b0 + j;
+        if (q >= p.n_items || ((live >> j) & 1ull)) continue;
+        int e, k;
+        queue_item(M, p.E, q, e, k);
+        const size_t item = (size_t)e * M.K + k;
+        for (int c = lane; c < O * 12; c += 64) p.bwd.pose_part[item * O * 12 + c] = 0.0f;
+        p.bwd.alpha_part[item] = 0.0f;
+        p.bwd.item_flag[item] = 0;
+    }
+}
+
+// One item (item = e K + k indexes the partials) with candidate objects cand
+// (all bits set when contact results are given).
 template <int KIND>
-__device__ void process_item_bwd(const BwdParams &p, BwdLds &S, int item, int e, int k, float *uhn, float *gh,
-                                 int *alist, int *plist, int8_t *wobj) {
+__device__ void process_item_bwd(const BwdParams &p, BwdLds &S, int item, int e, int k, unsigned cand, float *uhn,
+                                 float *gh, int *alist, int *plist, int8_t *wobj) {
     const MeshDev &M = p.mesh;
     const int N = M.N, n_max = p.scr.n_max, O = p.scene.O;
     const size_t EN = (size_t)p.E * N;
     const int base = M.offset[k];
     const int n = M.offset[k + 1] - base;
     const size_t row = (size_t)e * N + base;
-    unsigned cand = 0xffu;
-    int m = 0;
-    bool has = true;
-    if (KIND != BWD_PROP) {
-        if (threadIdx.x < 64) S.cand = cull_objects(p.scene, M, e, k);
-        __syncthreads();
-        cand = uniform(S.cand);
-        __syncthreads();
-        has = cand != 0u;
-    }
-    if (has)
-        m = contact_and_compact<KIND == BWD_PROP>(M, p.scene, p.E, n_max, p.cobj_in, p.uhat_in, nullptr, S.wcnt, e, k,
-                                                  base, n, cand, uhn, alist, plist, wobj);
+    const int m = contact_and_compact<KIND == BWD_PROP>(M, p.scene, p.E, n_max, p.cobj_in, p.uhat_in, nullptr, S.wcnt,
+                                                        e, k, base, n, cand, uhn, alist, plist, wobj);
     if (m == 0) {
         if (threadIdx.x < 64) {
             p.bwd.alpha_part[item] = 0.0f;
@@ -764,7 +963,7 @@ __device__ void process_item_bwd(const BwdParams &p, BwdLds &S, int item, int e,
         const int np = n - m;
         if (p.model.mode != ETAC_RESIDUAL_ONLY && np > 0)
             dalpha = decay_adjoint(p, S, e, k, base, m, np, alist, plist, uhn, gh);
-        if (uses_residual(p)) residual_adjoint(p, S, e, k, item, base, n, uhn, wobj, gh);
+        if (uses_residual(p)) residual_adjoint(p, S, e, k, item, base, n, n - m, plist, uhn, wobj, gh);
     }
     // dL/dalpha partial of the item
     {
@@ -791,17 +990,6 @@ __device__ void process_item_bwd(const BwdParams &p, BwdLds &S, int item, int e,
     __syncthreads();
 }
 
-__device__ __forceinline__ int next_item_bwd(unsigned *counter, BwdLds &S) {
-    if (threadIdx.x < 64) {
-        const unsigned old = atomicAdd(&counter[2], lane_id() == 0 ? 1u : 0u);
-        S.item = __shfl((int)old, 0);
-    }
-    __syncthreads();
-    const int it = uniform(S.item);
-    __syncthreads();
-    return it;
-}
-
 template <int KIND>
 __global__ __launch_bounds__(kWG) void k_bwd(BwdParams p) {
     __shared__ BwdLds S;
@@ -818,10 +1006,18 @@ __global__ __launch_bounds__(kWG) void k_bwd(BwdParams p) {
         __syncthreads();
     }
     for (;;) {
-        const int item = next_item_bwd(p.scr.counter, S);
-        if (item >= p.n_items) break;
-        const int e = item / p.mesh.K, k = item - e * p.mesh.K;
-        process_item_bwd<KIND>(p, S, item, e, k, uhn, gh, alist, plist, wobj);
+        const int b0 = next_batch<KIND != BWD_PROP>(p.scr.counter + 2, S.batch, p.mesh, p.scene, p.E, p.n_items,
+                                                     p.batch);
+        if (b0 >= p.n_items) break;
+        if (KIND != BWD_PROP) zero_fill_batch_bwd(p, S.batch, b0);
+        const int nb = uniform(S.batch.n);
+        for (int q = 0; q < nb; ++q) {
+            const int pos = uniform(S.batch.item[q]);
+            const unsigned cand = uniform((unsigned)S.batch.cand[q]);
+            int e, k;
+            queue_item(p.mesh, p.E, pos, e, k);
+            process_item_bwd<KIND>(p, S, e * p.mesh.K + k, e, k, cand, uhn, gh, alist, plist, wobj);
+        }
     }
     if (threadIdx.x == 0) {
         __threadfence();
@@ -922,6 +1118,7 @@ hipError_t launch_backward(const Plan &pl, const SceneDev *s, const ModelDev &m,
     p.bwd = pl.bwd;
     p.E = n_envs;
     p.n_items = n_envs * pl.K;
+    p.batch = pl.batch;
     p.cobj_in = cobj_in;
     p.uhat_in = uhat_in;
     p.grad_u = grad_u;
@@ -964,6 +1161,7 @@ hipError_t launch_contact_backward(const Plan &pl, const SceneDev &s, const floa
     p.bwd = pl.bwd;
     p.E = s.E;
     p.n_items = s.E * pl.K;
+    p.batch = pl.batch;
     p.cobj_in = nullptr;
     p.uhat_in = nullptr;
     p.grad_u = nullptr;

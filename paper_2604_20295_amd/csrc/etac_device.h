@@ -182,6 +182,74 @@ __device__ __forceinline__ unsigned lanes_below(unsigned long long mask) {
                                      __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
 
+// ---------------------------------------------------------------------------
+// batched work queue
+//
+// The persistent kernels claim `batch` (1 .. kBatch) consecutive queue
+// positions per atomic.
+// Queue position q maps to patch order[q / E] (patches by node count, largest
+// first) and env q % E.  Wave 0 culls the whole batch at once, one item per
+// lane; only items that some object may reach are processed one by one, the
+// rest only need their zero outputs.
+// ---------------------------------------------------------------------------
+constexpr int kBatch = 64;
+
+struct ItemBatch {
+    int item[kBatch];          // queue positions of the live items, ascending
+    uint8_t cand[kBatch];      // their candidate-object masks
+    unsigned mask_lo, mask_hi; // live items as a bit mask over the batch
+    int n;                     // number of live items
+    int b0;                    // first queue position of the batch
+};
+
+__device__ __forceinline__ void queue_item(const MeshDev &M, int E, int q, int &e, int &k) {
+    const int kk = q / E;
+    e = q - kk * E;
+    k = M.order[kk];
+}
+
+__device__ __forceinline__ unsigned long long batch_mask(const ItemBatch &B) {
+    return ((unsigned long long)uniform(B.mask_hi) << 32) | (unsigned long long)uniform(B.mask_lo);
+}
+
+// Claim the next batch and cull it (CULL false: every item is live).  Returns
+// the batch's first queue position (>= n_items when the queue is empty).
+template <bool CULL>
+__device__ int next_batch(unsigned *counter, ItemBatch &B, const MeshDev &M, const SceneDev &Sc, int E,
+                          int n_items, int batch) {
+    __syncthreads();   // every wave is done with the previous batch
+    if (threadIdx.x < 64) {
+        const int lane = lane_id();
+        // one atomic for the wave (lane 0 adds `batch`), every lane learns the result
+        const unsigned old = atomicAdd(&counter[0], lane == 0 ? (unsigned)batch : 0u);
+        const int b0 = __shfl((int)old, 0);
+        const int q = b0 + lane;
+        unsigned cand = 0;
+        if (lane < batch && q < n_items) {
+            if (CULL) {
+                int e, k;
+                queue_item(M, E, q, e, k);
+                cand = cull_objects(Sc, M, e, k);
+            } else {
+                cand = 0xffu;
+            }
+        }
+        const unsigned long long live = __ballot(cand != 0u);
+        if (cand != 0u) {
+            const int slot = (int)lanes_below(live);
+            B.item[slot] = q;
+            B.cand[slot] = (uint8_t)cand;
+        }
+        // identical values from every lane
+        B.mask_lo = (unsigned)live;
+        B.mask_hi = (unsigned)(live >> 32);
+        B.n = __popcll(live);
+        B.b0 = b0;
+    }
+    __syncthreads();
+    return uniform(B.b0);
+}
+
 // Contact (or given contact results) for every node of one (env, patch)
 // item, then the active and passive node lists in ascending node order
 // (wave ballots, prefix over waves).  Writes u_hat of every node into `uhn`
@@ -194,7 +262,7 @@ __device__ int contact_and_compact(const MeshDev &M, const SceneDev &Sc, int E, 
                                    int8_t *wobj) {
     const int N = M.N;
     const size_t EN = (size_t)E * N;
-    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    const int wave = threadIdx.x >> 6;
     int run_a = 0, run_p = 0;
     for (int i0 = 0; i0 < n; i0 += kWG) {
         const int i = i0 + threadIdx.x;

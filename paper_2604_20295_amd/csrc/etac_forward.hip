@@ -68,6 +68,7 @@ struct StepParams {
     Scratch scr;
     int E;
     int n_items;
+    int batch;               // queue positions claimed per atomic
     const int8_t *cobj_in;   // propagate-only: given contact results
     const float *uhat_in;
     float *u;                // [3][E][N]
@@ -80,30 +81,18 @@ struct StepLds {
     float4 act_a[kChunk];    // (px, py, pz, ux) of staged active nodes
     float2 act_b[kChunk];    // (uy, uz)
     int wcnt[2][kWaves];
-    int item;
-    unsigned cand;
+    ItemBatch batch;
 };
 
-// Work queue: counter[0] hands out items, counter[1] counts finished
-// workgroups; the last workgroup resets both so the next launch (or graph
-// replay) starts from zero without a host-side clear.
+// Work queue: counter[0] hands out batches of kBatch items in queue order
+// (patches by size, largest first; envs within a patch), counter[1] counts
+// finished workgroups; the last workgroup resets both so the next launch (or
+// graph replay) starts from zero without a host-side clear.
 //
 // Every block that only part of the workgroup executes is a whole wave (wave
 // 0, storing identical values), and every item ends at a barrier: a block
 // taken by single lanes next to a barrier lets the compiler thread the other
 // lanes of the wave past it into the barrier, which deadlocks the queue.
-__device__ __forceinline__ int next_item(unsigned *counter, StepLds &S) {
-    if (threadIdx.x < 64) {
-        // one atomic for the wave (lane 0 adds 1), every lane learns the result
-        const unsigned old = atomicAdd(&counter[0], lane_id() == 0 ? 1u : 0u);
-        S.item = __shfl((int)old, 0);
-    }
-    __syncthreads();
-    const int it = uniform(S.item);
-    __syncthreads();
-    return it;
-}
-
 __device__ __forceinline__ void retire(unsigned *counter) {
     if (threadIdx.x == 0) {
         __threadfence();
@@ -115,7 +104,7 @@ __device__ __forceinline__ void retire(unsigned *counter) {
     }
 }
 
-// Zero deformation for a patch without contact.
+// Zero deformation for a patch without contact (whole workgroup).
 __device__ __forceinline__ void write_zero_item(const StepParams &p, int e, int base, int n, bool write_cobj) {
     const size_t EN = (size_t)p.E * p.mesh.N;
     const size_t row = (size_t)e * p.mesh.N + base;
@@ -127,12 +116,38 @@ __device__ __forceinline__ void write_zero_item(const StepParams &p, int e, int 
     }
 }
 
-// Residual network over the whole patch: max-pool pass, global MLP, then the
-// decoder pass writing r for every node into `resid` ([3][n_max]).  The
-// encoder is recomputed in the decoder pass instead of keeping n x 64
+// Outputs of the batch's items that no object can reach: U = 0, no contact,
+// m = 0.  Wave w takes items w, w + 4, ...; no barrier is needed.
+__device__ void zero_fill_batch(const StepParams &p, const ItemBatch &B, int b0) {
+    const int batch = p.batch;
+    const MeshDev &M = p.mesh;
+    const int wave = threadIdx.x >> 6, lane = lane_id();
+    const unsigned long long live = batch_mask(B);
+    const size_t EN = (size_t)p.E * M.N;
+    for (int j = wave; j < batch; j += kWaves) {
+        const int item = b0 + j;
+        if (item >= p.n_items || ((live >> j) & 1ull)) continue;
+        int e, k;
+        queue_item(M, p.E, item, e, k);
+        const int base = M.offset[k], n = M.offset[k + 1] - base;
+        const size_t row = (size_t)e * M.N + base;
+        for (int i = lane; i < n; i += 64) {
+            p.u[row + i] = 0.0f;
+            p.u[EN + row + i] = 0.0f;
+            p.u[2 * EN + row + i] = 0.0f;
+            p.cobj_out[row + i] = -1;
+        }
+        p.n_active[(size_t)e * M.K + k] = 0;
+    }
+}
+
+// Residual network over the whole patch: max-pool pass over every node,
+// global MLP, then the decoder pass writing r into `resid` ([3][n_max]) for
+// the passive nodes (plist[0 .. np)), the only ones whose residual is used.
+// The encoder is recomputed in the decoder pass instead of keeping n x 64
 // features.
 __device__ void residual_item(const StepParams &p, StepLds &S, int k, int base, int n, const float *uhn,
-                              float *resid) {
+                              const int *plist, int np, float *resid) {
     NetLds &L = S.net;
     const int lane = lane_id(), wave = threadIdx.x >> 6, gq = lane >> 4;
     const int n_max = p.scr.n_max;
@@ -178,9 +193,11 @@ __device__ void residual_item(const StepParams &p, StepLds &S, int k, int base, 
     }
     __syncthreads();
     global_mlp(L, p.model.phi);
-    for (int t = wave; t < ntiles; t += kWaves) {
-        const int ln = t * 16 + (lane & 15);
-        const bool valid = ln < n;
+    const int ptiles = (np + 15) >> 4;
+    for (int t = wave; t < ptiles; t += kWaves) {
+        const int li = t * 16 + (lane & 15);
+        const bool valid = li < np;
+        const int ln = valid ? plist[li] : 0;
         half8 xh, xl;
         load_x(p.mesh, k, base + ln, valid, uhn, n_max, ln, xh, xl);
         floatx4 h1[4], f[4], h4[4];
@@ -230,28 +247,17 @@ __device__ __forceinline__ void decay_chunk(const StepLds &S, int cnt, float nbe
     }
 }
 
+// One item with at least one candidate object (cand: objects that may reach
+// the patch; all bits set when contact results are given).
 template <bool FROM_INPUT>
-__device__ void process_item(const StepParams &p, StepLds &S, int e, int k, float *uhn, float *resid,
-                             int *alist, int *plist) {
+__device__ void process_item(const StepParams &p, StepLds &S, int e, int k, unsigned cand, float *uhn,
+                             float *resid, int *alist, int *plist) {
     const MeshDev &M = p.mesh;
     const int N = M.N, n_max = p.scr.n_max;
     const size_t EN = (size_t)p.E * N;
     const int base = M.offset[k];
     const int n = M.offset[k + 1] - base;
     const int mode = p.model.mode;
-    unsigned cand = 0xffu;
-    if (!FROM_INPUT) {
-        if (threadIdx.x < 64) S.cand = cull_objects(p.scene, M, e, k);
-        __syncthreads();
-        cand = uniform(S.cand);
-        __syncthreads();
-        if (cand == 0u) {
-            write_zero_item(p, e, base, n, true);
-            if (threadIdx.x < 64) p.n_active[(size_t)e * M.K + k] = 0;
-            __syncthreads();
-            return;
-        }
-    }
     const int m = contact_and_compact<FROM_INPUT>(M, p.scene, p.E, p.scr.n_max, p.cobj_in, p.uhat_in, p.cobj_out,
                                                   S.wcnt, e, k, base, n, cand, uhn, alist, plist, nullptr);
     if (!FROM_INPUT && threadIdx.x < 64) p.n_active[(size_t)e * M.K + k] = m;
@@ -269,8 +275,8 @@ __device__ void process_item(const StepParams &p, StepLds &S, int e, int k, floa
         p.u[2 * EN + row + i] = uhn[2 * n_max + i];
     }
     const bool use_res = mode != ETAC_DECAY_ONLY, use_dec = mode != ETAC_RESIDUAL_ONLY;
-    if (use_res) residual_item(p, S, k, base, n, uhn, resid);
     const int np = n - m;
+    if (use_res) residual_item(p, S, k, base, n, uhn, plist, np, resid);
     // exp(-alpha d) = exp2(-alpha log2(e) d)
     const float nbeta = (float)(-(double)p.model.alpha[k] * 1.4426950408889634);
     const bool one_chunk = m <= kChunk;
@@ -331,11 +337,17 @@ __global__ __launch_bounds__(kWG) void k_step(StepParams p) {
         __syncthreads();
     }
     for (;;) {
-        const int item = next_item(p.scr.counter, S);
-        if (item >= p.n_items) break;
-        const int kk = item / p.E, e = item - kk * p.E;
-        const int k = p.mesh.order[kk];
-        process_item<FROM_INPUT>(p, S, e, k, uhn, resid, alist, plist);
+        const int b0 = next_batch<!FROM_INPUT>(p.scr.counter, S.batch, p.mesh, p.scene, p.E, p.n_items, p.batch);
+        if (b0 >= p.n_items) break;
+        if (!FROM_INPUT) zero_fill_batch(p, S.batch, b0);
+        const int nb = uniform(S.batch.n);
+        for (int q = 0; q < nb; ++q) {
+            const int item = uniform(S.batch.item[q]);
+            const unsigned cand = uniform((unsigned)S.batch.cand[q]);
+            int e, k;
+            queue_item(p.mesh, p.E, item, e, k);
+            process_item<FROM_INPUT>(p, S, e, k, cand, uhn, resid, alist, plist);
+        }
     }
     retire(p.scr.counter);
 }
@@ -352,6 +364,7 @@ hipError_t launch_step(const Plan &pl, const SceneDev *s, const ModelDev &m, int
     p.scr = pl.scr;
     p.E = n_envs;
     p.n_items = n_envs * pl.K;
+    p.batch = pl.batch;
     p.cobj_in = cobj_in;
     p.uhat_in = uhat_in;
     p.u = u;

@@ -12,6 +12,7 @@ constexpr int kWG = 256;           // threads per workgroup: 4 waves of 64
 constexpr int kWaves = kWG / 64;
 constexpr int kMaxPatches = 1024;  // per-patch counters of the contact kernel live in LDS
 constexpr int kDefaultWgPerCu = 2;
+constexpr int kDefaultBatch = 4;   // work-queue positions claimed per atomic
 
 // Device view of the plan's mesh copy.
 struct MeshDev {
@@ -74,6 +75,7 @@ struct Plan {
     int cu_count;
     int wg_per_cu;
     int grid;              // persistent workgroups
+    int batch;             // work-queue positions claimed per atomic (1 .. 64)
     int n_envs, max_obj, K, N, n_max;
     uint32_t flags;
     MeshDev mesh;
