@@ -56,6 +56,7 @@ struct BwdLds {
             double part[kWG][6];  // per-thread partial dL/du_hat of its two active nodes
         } st;
         float red[kWaves][kRedRegs][64];   // one chunk of every wave's gradient accumulators
+        StageBuf xs;                       // node inputs of the network passes
     } u;
     floatx4 acc15[kWaves][8 * 64]; // per-wave dW1 (blocks 0-3) and dW5 (4-7) accumulators [block][lane]
     float s4[64];                 // sum_i dL/dpre4_i  (= db4)
@@ -126,56 +127,142 @@ __device__ __forceinline__ floatx4 mfma_k16(const half4 &a, const half4 &b, floa
     return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
 }
 
-// acc += A B over the tile's 16 nodes with split operands (hi*hi + hi*lo + lo*hi)
-__device__ __forceinline__ floatx4 mfma_k16_split(const half4 &ah, const half4 &al, const half4 &bh, const half4 &bl,
-                                                  floatx4 acc) {
-    acc = mfma_k16(ah, bh, acc);
-    acc = mfma_k16(ah, bl, acc);
-    return mfma_k16(al, bh, acc);
-}
 
 // Input layer (9 -> 64, inputs padded to one K step of 32) in both forms:
-// h1T = relu(W1 x + b1), h1N = relu(x W1^T + b1).
+// h1T = relu(W1 x + b1), h1N = relu(x W1^T + b1).  The three split passes
+// run pass-outermost over the eight independent accumulators, so no MFMA
+// waits on the one before it (each accumulator sees the same sequence).
 __device__ __forceinline__ void layer1_dual(const NetLds &L, const half8 &xh, const half8 &xl, floatx4 h1T[4],
                                             floatx4 h1N[4]) {
     reload_fence();
     const int lane = lane_id(), gq = lane >> 4, col = lane & 15;
+    half8 wh[4], wl[4];
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob) {
-        const half8 wh = L.w1h[ob * 64 + lane], wl = L.w1l[ob * 64 + lane];
-        const floatx4 bT = *reinterpret_cast<const floatx4 *>(&L.b1[ob * 16 + 4 * gq]);
+        wh[ob] = L.w1h[ob * 64 + lane];
+        wl[ob] = L.w1l[ob * 64 + lane];
+        h1T[ob] = *reinterpret_cast<const floatx4 *>(&L.b1[ob * 16 + 4 * gq]);
         const float bn = L.b1[ob * 16 + col];
-        h1T[ob] = relu4(mfma_split(wh, wl, xh, xl, bT));
-        h1N[ob] = relu4(mfma_split(xh, xl, wh, wl, floatx4{bn, bn, bn, bn}));
+        h1N[ob] = floatx4{bn, bn, bn, bn};
+    }
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) { h1T[ob] = mfma16(wh[ob], xh, h1T[ob]); h1N[ob] = mfma16(xh, wh[ob], h1N[ob]); }
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) { h1T[ob] = mfma16(wh[ob], xl, h1T[ob]); h1N[ob] = mfma16(xh, wl[ob], h1N[ob]); }
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+        h1T[ob] = relu4(mfma16(wl[ob], xh, h1T[ob]));
+        h1N[ob] = relu4(mfma16(xl, wh[ob], h1N[ob]));
     }
 }
 
 // A 64 -> 64 layer from a split T-form input (xh, xl: the two K steps):
 // yT = W x (+ bias), yN = x W^T (+ bias), each only if requested; relu if
 // RELU.  wh / wl: fragments [ob][s][lane] of W (or of a transposed weight).
+// Split passes run pass-outermost over the independent accumulators.
 template <bool WANT_T, bool WANT_N, bool RELU>
 __device__ __forceinline__ void layer64(const half8 *wh, const half8 *wl, const half8 xh[2], const half8 xl[2],
                                         const float *bias, floatx4 yT[4], floatx4 yN[4]) {
     reload_fence();
     const int lane = lane_id(), gq = lane >> 4, col = lane & 15;
+    floatx4 aT[4], aN[4];
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob) {
-        reload_fence();   // one block's fragments in flight at a time
-        floatx4 aT = {0.0f, 0.0f, 0.0f, 0.0f}, aN = {0.0f, 0.0f, 0.0f, 0.0f};
+        aT[ob] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        aN[ob] = aT[ob];
         if (bias) {
-            aT = *reinterpret_cast<const floatx4 *>(&bias[ob * 16 + 4 * gq]);
+            aT[ob] = *reinterpret_cast<const floatx4 *>(&bias[ob * 16 + 4 * gq]);
             const float bn = bias[ob * 16 + col];
-            aN = floatx4{bn, bn, bn, bn};
+            aN[ob] = floatx4{bn, bn, bn, bn};
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        half8 h[4], l[4];
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) {
+            h[ob] = wh[(ob * 2 + s) * 64 + lane];
+            l[ob] = wl[(ob * 2 + s) * 64 + lane];
         }
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int fi = (ob * 2 + s) * 64 + lane;
-            const half8 h = wh[fi], l = wl[fi];
-            if (WANT_T) aT = mfma_split(h, l, xh[s], xl[s], aT);
-            if (WANT_N) aN = mfma_split(xh[s], xl[s], h, l, aN);
+        for (int ob = 0; ob < 4; ++ob) {
+            if (WANT_T) aT[ob] = mfma16(h[ob], xh[s], aT[ob]);
+            if (WANT_N) aN[ob] = mfma16(xh[s], h[ob], aN[ob]);
         }
-        if (WANT_T) yT[ob] = RELU ? relu4(aT) : aT;
-        if (WANT_N) yN[ob] = RELU ? relu4(aN) : aN;
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) {
+            if (WANT_T) aT[ob] = mfma16(h[ob], xl[s], aT[ob]);
+            if (WANT_N) aN[ob] = mfma16(xh[s], l[ob], aN[ob]);
+        }
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) {
+            if (WANT_T) aT[ob] = mfma16(l[ob], xh[s], aT[ob]);
+            if (WANT_N) aN[ob] = mfma16(xl[s], h[ob], aN[ob]);
+        }
+    }
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+        if (WANT_T) yT[ob] = RELU ? relu4(aT[ob]) : aT[ob];
+        if (WANT_N) yN[ob] = RELU ? relu4(aN[ob]) : aN[ob];
+    }
+}
+
+// acc[ob][ib] += A[ob] B[ib] over the tile's nodes for NO x NI blocks, split
+// passes outermost (every accumulator sees hi*hi, hi*lo, lo*hi in order).
+template <int NO, int NI>
+__device__ __forceinline__ void wgrad_blocks(const half4 (&ah)[NO], const half4 (&al)[NO], const half4 (&bh)[NI],
+                                             const half4 (&bl)[NI], floatx4 (&acc)[NO][NI]) {
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+#pragma unroll
+        for (int i = 0; i < NI; ++i) acc[o][i] = mfma_k16(ah[o], bh[i], acc[o][i]);
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+#pragma unroll
+        for (int i = 0; i < NI; ++i) acc[o][i] = mfma_k16(ah[o], bl[i], acc[o][i]);
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+#pragma unroll
+        for (int i = 0; i < NI; ++i) acc[o][i] = mfma_k16(al[o], bh[i], acc[o][i]);
+}
+
+// acc15[wave][blk0 + j] += A[j] B (j < 4) or A B[j]: four blocks from fresh
+// accumulators, then one LDS read-modify-write each.
+template <bool A_VARIES>
+__device__ __forceinline__ void acc15_add4(floatx4 *acc, int blk0, const half4 *ah, const half4 *al,
+                                           const half4 *bh, const half4 *bl) {
+    const int lane = lane_id();
+    floatx4 t[1][4];
+    half4 h1[1], l1[1], h4[4], l4[4];
+    if (A_VARIES) {
+        h1[0] = bh[0]; l1[0] = bl[0];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) { h4[j] = ah[j]; l4[j] = al[j]; }
+    } else {
+        h1[0] = ah[0]; l1[0] = al[0];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) { h4[j] = bh[j]; l4[j] = bl[j]; }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) t[0][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    // the products are symmetric in which operand is A here only through the
+    // layout: A[j] B means MFMA A operand = the varying block
+    if (A_VARIES) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) t[0][j] = mfma_k16(h4[j], h1[0], t[0][j]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) t[0][j] = mfma_k16(h4[j], l1[0], t[0][j]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) t[0][j] = mfma_k16(l4[j], h1[0], t[0][j]);
+    } else {
+        wgrad_blocks<1, 4>(h1, l1, h4, l4, t);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        floatx4 v = acc[(blk0 + j) * 64 + lane];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] += t[0][j][r];
+        acc[(blk0 + j) * 64 + lane] = v;
     }
 }
 
@@ -214,16 +301,6 @@ struct WGrad {
     float b5;            // lanes with (l & 15) < 3: partial db5[l & 15]
 };
 
-// acc15[wave][blk] += a b over the tile's nodes (split operands)
-__device__ __forceinline__ void acc15_add(floatx4 *acc, int blk, const half4 &ah, const half4 &al, const half4 &bh,
-                                          const half4 &bl) {
-    const int lane = lane_id();
-    const floatx4 t = mfma_k16_split(ah, al, bh, bl, floatx4{0.0f, 0.0f, 0.0f, 0.0f});
-    floatx4 v = acc[blk * 64 + lane];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) v[r] += t[r];
-    acc[blk * 64 + lane] = v;
-}
 
 __device__ __forceinline__ void zero_wgrad(WGrad &G) {
     const floatx4 z = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -236,39 +313,42 @@ __device__ __forceinline__ void zero_wgrad(WGrad &G) {
     G.b5 = 0.0f;
 }
 
-// Adjoint of one tile of 16 passive nodes (positions 16 t .. 16 t + 15 of the
-// passive list): forward recomputation, decoder and encoder adjoints, all
-// accumulated into this wave's parameter gradients.  Passive nodes have
-// U_hat = 0 and need no dL/du_hat.
-__device__ void passive_tile(const BwdParams &p, BwdLds &S, WGrad &G, int k, int base, int np,
-                             const int *plist, int t, size_t row, size_t EN, const float *uhn) {
+// Adjoint of one tile of 16 passive nodes (staged nodes 16 t .. 16 t + 15 of
+// the current chunk of cnt): forward recomputation, decoder and encoder
+// adjoints, all accumulated into this wave's parameter gradients.  Passive
+// nodes have U_hat = 0 and need no dL/du_hat; the stage holds dL/dU in its
+// third triple.
+__device__ void passive_tile(BwdLds &S, WGrad &G, int cnt, int t) {
     const NetLds &L = S.net;
-    const MeshDev &M = p.mesh;
-    const int lane = lane_id(), gq = lane >> 4, col = lane & 15, n_max = p.scr.n_max;
+    const StageBuf &xs = S.u.xs;
+    const int lane = lane_id(), gq = lane >> 4, col = lane & 15;
     // T form: this lane's node; N form: nodes 4 gq + r
     const int li = 16 * t + col;
-    const bool valid = li < np;
-    const int ln = valid ? plist[li] : 0;
-    int lnr[4];
+    const bool valid = li < cnt;
+    int lj[4];
     bool vr[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int q = 16 * t + 4 * gq + r;
-        vr[r] = q < np;
-        lnr[r] = vr[r] ? plist[q] : 0;
+        lj[r] = 16 * t + 4 * gq + r;
+        vr[r] = lj[r] < cnt;
     }
-    // dL/dr of the tile's nodes in both forms (zero on padding); loaded first
+    // N-form network inputs: feature col of nodes lj[r] (U_hat = 0; input 9 = 1)
+    floatx4 xn;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        xn[r] = !vr[r] ? 0.0f : (col < 6 ? xs[col][lj[r]] : (col == 9 ? 1.0f : 0.0f));
+    // dL/dr of the tile's nodes in both forms (zero on padding)
     float dr[3], drn[3][4];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        dr[c] = valid ? p.grad_u[c * EN + row + ln] : 0.0f;
+        dr[c] = valid ? xs[6 + c][li] : 0.0f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) drn[c][r] = vr[r] ? p.grad_u[c * EN + row + lnr[r]] : 0.0f;
+        for (int r = 0; r < 4; ++r) drn[c][r] = vr[r] ? xs[6 + c][lj[r]] : 0.0f;
     }
+    half8 xh, xl;
+    stage_x<true>(xs, li, valid, xh, xl);
     // forward recomputation in both forms; T-form values that only gate a
     // later step are kept as bit masks (bit 4 block + register)
-    half8 xh, xl;
-    load_x(M, k, base + ln, valid, uhn, n_max, ln, xh, xl);
     floatx4 h1T[4], h1N[4];
     layer1_dual(L, xh, xl, h1T, h1N);
     half8 sh[2], sl[2];
@@ -305,15 +385,11 @@ __device__ void passive_tile(const BwdParams &p, BwdLds &S, WGrad &G, int k, int
 #pragma unroll
         for (int r = 0; r < 4; ++r) a[r] = col == 0 ? drn[0][r] : (col == 1 ? drn[1][r] : (col == 2 ? drn[2][r] : 0.0f));
         G.b5 += (a[0] + a[1]) + (a[2] + a[3]);
-        half4 ah, al;
+        half4 ah, al, bh[4], bl[4];
         split4(a, ah, al);
-        floatx4 *acc = S.acc15[threadIdx.x >> 6];
 #pragma unroll
-        for (int ib = 0; ib < 4; ++ib) {
-            half4 bh, bl;
-            split4(h4N[ib], bh, bl);
-            acc15_add(acc, 4 + ib, ah, al, bh, bl);
-        }
+        for (int ib = 0; ib < 4; ++ib) split4(h4N[ib], bh[ib], bl[ib]);
+        acc15_add4<false>(S.acc15[threadIdx.x >> 6], 4, &ah, &al, bh, bl);
     }
     // dL/df = W4[:, :64]^T dpre4 in both forms
     split_chain(d4T, sh, sl);
@@ -321,17 +397,15 @@ __device__ void passive_tile(const BwdParams &p, BwdLds &S, WGrad &G, int k, int
     layer64<true, true, false>(S.w4th, S.w4tl, sh, sl, nullptr, dfT, dfN);
     // dW4[:, :64] += dpre4 (x) f, db4
     {
-        half4 fh[4], fl[4];
+        half4 fh[4], fl[4], ah[4], al[4];
 #pragma unroll
         for (int ib = 0; ib < 4; ++ib) split4(fN[ib], fh[ib], fl[ib]);
 #pragma unroll
         for (int ob = 0; ob < 4; ++ob) {
             G.b4[ob] += (d4N[ob][0] + d4N[ob][1]) + (d4N[ob][2] + d4N[ob][3]);
-            half4 ah, al;
-            split4(d4N[ob], ah, al);
-#pragma unroll
-            for (int ib = 0; ib < 4; ++ib) G.w4[ob][ib] = mfma_k16_split(ah, al, fh[ib], fl[ib], G.w4[ob][ib]);
+            split4(d4N[ob], ah[ob], al[ob]);
         }
+        wgrad_blocks<4, 4>(ah, al, fh, fl, G.w4);
     }
     // dL/dpre2 = df [f > 0]; dL/dh1 = W2^T dpre2 (N form only: no dL/du_hat here)
     floatx4 d2T[4], d2N[4];
@@ -347,79 +421,81 @@ __device__ void passive_tile(const BwdParams &p, BwdLds &S, WGrad &G, int k, int
     layer64<false, true, false>(S.w2th, S.w2tl, sh, sl, nullptr, nullptr, dh1N);
     // dW2 += dpre2 (x) h1, db2
     {
-        half4 hh[4], hl[4];
+        half4 hh[4], hl[4], ah[4], al[4];
 #pragma unroll
         for (int ib = 0; ib < 4; ++ib) split4(h1N[ib], hh[ib], hl[ib]);
 #pragma unroll
         for (int ob = 0; ob < 4; ++ob) {
             G.b2[ob] += (d2N[ob][0] + d2N[ob][1]) + (d2N[ob][2] + d2N[ob][3]);
-            half4 ah, al;
-            split4(d2N[ob], ah, al);
-#pragma unroll
-            for (int ib = 0; ib < 4; ++ib) G.w2[ob][ib] = mfma_k16_split(ah, al, hh[ib], hl[ib], G.w2[ob][ib]);
+            split4(d2N[ob], ah[ob], al[ob]);
         }
+        wgrad_blocks<4, 4>(ah, al, hh, hl, G.w2);
     }
     // dW1 += dpre1 (x) x (db1 through input 9)
     {
-        half4 xnh, xnl;
-        split4(load_xn(M, k, base, lnr, vr, uhn, n_max), xnh, xnl);
+        half4 xnh, xnl, ah[4], al[4];
+        split4(xn, xnh, xnl);
 #pragma unroll
         for (int ob = 0; ob < 4; ++ob) {
             floatx4 d1;
 #pragma unroll
             for (int r = 0; r < 4; ++r) d1[r] = h1N[ob][r] > 0.0f ? dh1N[ob][r] : 0.0f;
-            half4 ah, al;
-            split4(d1, ah, al);
-            acc15_add(S.acc15[threadIdx.x >> 6], ob, ah, al, xnh, xnl);
+            split4(d1, ah[ob], al[ob]);
         }
+        acc15_add4<true>(S.acc15[threadIdx.x >> 6], 0, ah, al, &xnh, &xnl);
     }
 }
 
 // Max-pool routing for the wave's 16 channels c = 16 wave + j: the
 // gradient dL/dpre2 = vroute[c] e_c at the arg-max node of channel c.  Its
-// dL/dh1 is vroute[c] W2[c, :] (exact FP32 products); adds the dW2 rows,
-// dW1 and db1 contributions and leaves dL/du_hat of each channel's node in
-// S.dxs (identical in the four lane groups).
+// dL/dh1 = W2^T dpre2 comes from the W2^T fragments in both forms; adds the
+// dW2 rows, dW1 and db1 contributions and leaves dL/du_hat of each channel's
+// node in S.dxs (identical in the four lane groups).
 __device__ void routing_tile(const BwdParams &p, BwdLds &S, WGrad &G, int k, int base, int n, const float *uhn) {
     const NetLds &L = S.net;
     const MeshDev &M = p.mesh;
-    const float *phi = p.model.phi;
     const int lane = lane_id(), wave = threadIdx.x >> 6, gq = lane >> 4, col = lane & 15, n_max = p.scr.n_max;
     // T form: channel 16 wave + col; N form: channels 16 wave + 4 gq + r
     const int cT = 16 * wave + col;
     const int lnT = S.argmax[cT];
     const bool vT = lnT < n;
-    int lnr[4], cr[4];
+    int lnr[4];
     bool vr[4];
+    float vn[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        cr[r] = 16 * wave + 4 * gq + r;
-        lnr[r] = S.argmax[cr[r]];
+        const int c = 16 * wave + 4 * gq + r;
+        lnr[r] = S.argmax[c];
         vr[r] = lnr[r] < n;
         if (!vr[r]) lnr[r] = 0;
+        vn[r] = vr[r] ? S.vroute[c] : 0.0f;
     }
     half8 xh, xl;
     load_x(M, k, base + (vT ? lnT : 0), vT, uhn, n_max, vT ? lnT : 0, xh, xl);
     floatx4 h1T[4], h1N[4];
     layer1_dual(L, xh, xl, h1T, h1N);
+    // one-hot dL/dpre2 in T form, then dL/dh1 in both forms
     const float vt = vT ? S.vroute[cT] : 0.0f;
-    float vn[4];
+    floatx4 d2T[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) vn[r] = vr[r] ? S.vroute[cr[r]] : 0.0f;
-    // dL/du_hat of the channel's node: W1[:, 6..8]^T (dh1 [h1 > 0]) in T form
+    for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) d2T[ob][r] = (ob * 16 + 4 * gq + r == cT) ? vt : 0.0f;
+    half8 sh[2], sl[2];
+    split_chain(d2T, sh, sl);
+    floatx4 dh1T[4], dh1N[4];
+    layer64<true, true, false>(S.w2th, S.w2tl, sh, sl, nullptr, dh1T, dh1N);
+    // dL/du_hat of the channel's node: W1[:, 6..8]^T dpre1 in T form
     float du[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-    for (int ob = 0; ob < 4; ++ob) {
-        const float *wrow = &phi[kW2 + cT * 64 + ob * 16 + 4 * gq];   // caller memory: scalar loads
-        const float wv[4] = {wrow[0], wrow[1], wrow[2], wrow[3]};
+    for (int ob = 0; ob < 4; ++ob)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int f = ob * 16 + 4 * gq + r;
-            const float d1 = h1T[ob][r] > 0.0f ? vt * wv[r] : 0.0f;
+            const float d1 = h1T[ob][r] > 0.0f ? dh1T[ob][r] : 0.0f;
 #pragma unroll
             for (int c = 0; c < 3; ++c) du[c] += S.w1u[c][f] * d1;
         }
-    }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         du[c] += __shfl_xor(du[c], 16);
@@ -436,21 +512,17 @@ __device__ void routing_tile(const BwdParams &p, BwdLds &S, WGrad &G, int k, int
 #pragma unroll
             for (int r = 0; r < 4; ++r) G.w2[ob][ib][r] += (mine ? vn[r] : 0.0f) * h1N[ib][r];
     }
-    // dW1 += dpre1 (x) x with dpre1 = vroute W2[c, :] [h1 > 0] in N form
-    half4 xnh, xnl;
+    // dW1 += dpre1 (x) x (db1 through input 9)
+    half4 xnh, xnl, ah[4], al[4];
     split4(load_xn(M, k, base, lnr, vr, uhn, n_max), xnh, xnl);
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob) {
         floatx4 d1;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const float w = phi[kW2 + cr[r] * 64 + ob * 16 + col];
-            d1[r] = h1N[ob][r] > 0.0f ? vn[r] * w : 0.0f;
-        }
-        half4 ah, al;
-        split4(d1, ah, al);
-        acc15_add(S.acc15[wave], ob, ah, al, xnh, xnl);
+        for (int r = 0; r < 4; ++r) d1[r] = h1N[ob][r] > 0.0f ? dh1N[ob][r] : 0.0f;
+        split4(d1, ah[ob], al[ob]);
     }
+    acc15_add4<true>(S.acc15[wave], 0, ah, al, &xnh, &xnl);
 }
 
 // ---------------------------------------------------------------------------
@@ -461,35 +533,39 @@ __device__ __forceinline__ bool uses_residual(const BwdParams &p) {
     return p.model.mode != ETAC_DECAY_ONLY;
 }
 
-// Eq. 1 adjoint of one item.  Pairs (active j, passive i) are split over
-// (active slot, passive segment): every thread owns two active nodes of a
-// pass and one segment of each staged chunk of passive nodes (position, g);
-// with few active nodes the passive list is cut into 2 or 4 segments so that
-// all threads work.  Slots are whole waves, so LDS reads stay broadcasts.  The
-// segment partials of dL/du_hat_j are combined in segment order; the thread's
-// dL/dalpha contribution is returned.
-__device__ double decay_adjoint(const BwdParams &p, BwdLds &S, int e, int k, int base, int m, int np,
-                                const int *alist, const int *plist, const float *uhn, float *gh) {
+// Eq. 1 adjoint of one item.  Pairs (active j, passive i) are split over a
+// grid of SLOTS active slots x (kWG / SLOTS) passive segments: every thread
+// owns A active nodes per pass and one segment of each staged chunk of
+// passive nodes (position, g).  Slots are whole waves, so LDS reads stay
+// broadcasts.  The segment partials of dL/du_hat_j are combined in segment
+// order; the thread's dL/dalpha contribution is returned.
+template <int SLOTS, int A>
+__device__ double decay_adjoint_grid(const BwdParams &p, BwdLds &S, int e, int k, int base, int m, int np,
+                                     const int *alist, const int *plist, const float *uhn, float *gh) {
     const MeshDev &M = p.mesh;
     const int N = M.N, n_max = p.scr.n_max;
     const size_t EN = (size_t)p.E * N;
     const size_t row = (size_t)e * N + base;
     const float nbeta = (float)(-(double)p.model.alpha[k] * 1.4426950408889634);
-    const int slots = m <= 128 ? 64 : (m <= 256 ? 128 : kWG);     // threads per segment
-    const int nseg = kWG / slots;
-    const int slot = threadIdx.x % slots, seg = threadIdx.x / slots;
+    constexpr int nseg = kWG / SLOTS;
+    const int slot = threadIdx.x % SLOTS, seg = threadIdx.x / SLOTS;
     double dalpha = 0.0;
-    for (int ab = 0; ab < m; ab += 2 * slots) {
-        const int t0 = ab + slot, t1 = t0 + slots;
-        const bool v0 = t0 < m, v1 = t1 < m;
-        const int j0 = v0 ? alist[t0] : alist[0], j1 = v1 ? alist[t1] : alist[0];
-        const int g0 = base + j0, g1 = base + j1;
-        const float px0 = M.pos[g0], py0 = M.pos[N + g0], pz0 = M.pos[2 * N + g0];
-        const float px1 = M.pos[g1], py1 = M.pos[N + g1], pz1 = M.pos[2 * N + g1];
-        const float ux0 = uhn[j0], uy0 = uhn[n_max + j0], uz0 = uhn[2 * n_max + j0];
-        const float ux1 = uhn[j1], uy1 = uhn[n_max + j1], uz1 = uhn[2 * n_max + j1];
-        double a0[3] = {0.0, 0.0, 0.0}, a1[3] = {0.0, 0.0, 0.0};
-        double da0 = 0.0, da1 = 0.0;
+    for (int ab = 0; ab < m; ab += A * SLOTS) {
+        bool v[A];
+        int j[A];
+        float px[A], py[A], pz[A], ux[A], uy[A], uz[A];
+        double acc[A][3], da[A];
+#pragma unroll
+        for (int a = 0; a < A; ++a) {
+            const int t = ab + slot + a * SLOTS;
+            v[a] = t < m;
+            j[a] = v[a] ? alist[t] : alist[0];
+            const int g = base + j[a];
+            px[a] = M.pos[g]; py[a] = M.pos[N + g]; pz[a] = M.pos[2 * N + g];
+            ux[a] = uhn[j[a]]; uy[a] = uhn[n_max + j[a]]; uz[a] = uhn[2 * n_max + j[a]];
+            acc[a][0] = acc[a][1] = acc[a][2] = 0.0;
+            da[a] = 0.0;
+        }
         for (int c0 = 0; c0 < np; c0 += kBChunk) {
             const int cnt = min(kBChunk, np - c0);
             __syncthreads();
@@ -504,55 +580,85 @@ __device__ double decay_adjoint(const BwdParams &p, BwdLds &S, int e, int k, int
             const int lo = seg * per, hi = min(cnt, lo + per);
             for (int i0 = lo; i0 < hi; i0 += 32) {
                 const int i1 = min(hi, i0 + 32);
-                float s0x = 0.f, s0y = 0.f, s0z = 0.f, s1x = 0.f, s1y = 0.f, s1z = 0.f, q0 = 0.f, q1 = 0.f;
+                float sx[A], sy[A], sz[A], q[A];
+#pragma unroll
+                for (int a = 0; a < A; ++a) sx[a] = sy[a] = sz[a] = q[a] = 0.0f;
+#pragma unroll 2
                 for (int i = i0; i < i1; ++i) {
-                    const float4 a = S.u.st.a[i];
-                    const float2 b = S.u.st.b[i];
-                    const float dx0 = a.x - px0, dy0 = a.y - py0, dz0 = a.z - pz0;
-                    const float dx1 = a.x - px1, dy1 = a.y - py1, dz1 = a.z - pz1;
-                    const float d0 = __builtin_amdgcn_sqrtf(dx0 * dx0 + dy0 * dy0 + dz0 * dz0);
-                    const float d1 = __builtin_amdgcn_sqrtf(dx1 * dx1 + dy1 * dy1 + dz1 * dz1);
-                    const float w0 = __builtin_amdgcn_exp2f(nbeta * d0);
-                    const float w1 = __builtin_amdgcn_exp2f(nbeta * d1);
-                    s0x += w0 * a.w; s0y += w0 * b.x; s0z += w0 * b.y;
-                    s1x += w1 * a.w; s1y += w1 * b.x; s1z += w1 * b.y;
-                    q0 += d0 * w0 * (a.w * ux0 + b.x * uy0 + b.y * uz0);
-                    q1 += d1 * w1 * (a.w * ux1 + b.x * uy1 + b.y * uz1);
+                    const float4 pa = S.u.st.a[i];
+                    const float2 pb = S.u.st.b[i];
+#pragma unroll
+                    for (int a = 0; a < A; ++a) {
+                        const float dx = pa.x - px[a], dy = pa.y - py[a], dz = pa.z - pz[a];
+                        const float d = __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
+                        const float w = __builtin_amdgcn_exp2f(nbeta * d);
+                        sx[a] += w * pa.w; sy[a] += w * pb.x; sz[a] += w * pb.y;
+                        q[a] += d * w * (pa.w * ux[a] + pb.x * uy[a] + pb.y * uz[a]);
+                    }
                 }
-                a0[0] += s0x; a0[1] += s0y; a0[2] += s0z;
-                a1[0] += s1x; a1[1] += s1y; a1[2] += s1z;
-                da0 -= q0;
-                da1 -= q1;
+#pragma unroll
+                for (int a = 0; a < A; ++a) {
+                    acc[a][0] += sx[a]; acc[a][1] += sy[a]; acc[a][2] += sz[a];
+                    da[a] -= q[a];
+                }
             }
         }
-        if (v0) dalpha += da0;
-        if (v1) dalpha += da1;
+#pragma unroll
+        for (int a = 0; a < A; ++a)
+            if (v[a]) dalpha += da[a];
         // combine the segments of each active node in segment order
-        __syncthreads();
-        double *mine = S.u.st.part[threadIdx.x];
-        mine[0] = a0[0]; mine[1] = a0[1]; mine[2] = a0[2];
-        mine[3] = a1[0]; mine[4] = a1[1]; mine[5] = a1[2];
-        __syncthreads();
-        if (seg == 0) {
-            for (int q = 1; q < nseg; ++q) {
-                const double *o = S.u.st.part[q * slots + slot];
-                a0[0] += o[0]; a0[1] += o[1]; a0[2] += o[2];
-                a1[0] += o[3]; a1[1] += o[4]; a1[2] += o[5];
-            }
-            if (v0) {
-                gh[j0] = (float)((double)gh[j0] + a0[0]);
-                gh[n_max + j0] = (float)((double)gh[n_max + j0] + a0[1]);
-                gh[2 * n_max + j0] = (float)((double)gh[2 * n_max + j0] + a0[2]);
-            }
-            if (v1) {
-                gh[j1] = (float)((double)gh[j1] + a1[0]);
-                gh[n_max + j1] = (float)((double)gh[n_max + j1] + a1[1]);
-                gh[2 * n_max + j1] = (float)((double)gh[2 * n_max + j1] + a1[2]);
-            }
+        if (nseg > 1) {
+            __syncthreads();
+            double *mine = S.u.st.part[threadIdx.x];
+#pragma unroll
+            for (int a = 0; a < A; ++a) { mine[3 * a] = acc[a][0]; mine[3 * a + 1] = acc[a][1]; mine[3 * a + 2] = acc[a][2]; }
+            __syncthreads();
+            if (seg == 0)
+                for (int q = 1; q < nseg; ++q) {
+                    const double *o = S.u.st.part[q * SLOTS + slot];
+#pragma unroll
+                    for (int a = 0; a < A; ++a) { acc[a][0] += o[3 * a]; acc[a][1] += o[3 * a + 1]; acc[a][2] += o[3 * a + 2]; }
+                }
         }
+        if (seg == 0)
+#pragma unroll
+            for (int a = 0; a < A; ++a)
+                if (v[a]) {
+                    gh[j[a]] = (float)((double)gh[j[a]] + acc[a][0]);
+                    gh[n_max + j[a]] = (float)((double)gh[n_max + j[a]] + acc[a][1]);
+                    gh[2 * n_max + j[a]] = (float)((double)gh[2 * n_max + j[a]] + acc[a][2]);
+                }
     }
     __syncthreads();
     return dalpha;
+}
+
+// Grid shape for m x np pairs: the (slots, nodes per thread) pair with the
+// fewest thread iterations, two nodes per thread weighted as 1.75 (they
+// share the LDS reads).  Returns 0..5 for (64|128|256) x (1|2).
+__device__ __forceinline__ int decay_grid_shape(int m, int np) {
+    int best = 5;
+    float bc = 3.0e38f;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const int slots = 64 << (c % 3), a = 1 + c / 3, nseg = kWG / slots;
+        const float cost = (float)((m + a * slots - 1) / (a * slots)) * (float)((np + nseg - 1) / nseg) *
+                           (a == 2 ? 1.75f : 1.0f);
+        if (cost < bc) { bc = cost; best = c; }
+    }
+    return best;
+}
+
+__device__ double decay_adjoint(const BwdParams &p, BwdLds &S, int e, int k, int base, int m, int np,
+                                const int *alist, const int *plist, const float *uhn, float *gh) {
+    switch (uniform(decay_grid_shape(m, np))) {
+        case 0: return decay_adjoint_grid<64, 1>(p, S, e, k, base, m, np, alist, plist, uhn, gh);
+        case 1: return decay_adjoint_grid<128, 1>(p, S, e, k, base, m, np, alist, plist, uhn, gh);
+        case 2: return decay_adjoint_grid<256, 1>(p, S, e, k, base, m, np, alist, plist, uhn, gh);
+        case 3: return decay_adjoint_grid<64, 2>(p, S, e, k, base, m, np, alist, plist, uhn, gh);
+        case 4: return decay_adjoint_grid<128, 2>(p, S, e, k, base, m, np, alist, plist, uhn, gh);
+        default: return decay_adjoint_grid<256, 2>(p, S, e, k, base, m, np, alist, plist, uhn, gh);
+    }
 }
 
 // Deterministic workgroup sum of 12 doubles per thread (butterfly within the
@@ -729,7 +835,6 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
     const size_t EN = (size_t)p.E * N;
     const size_t row = (size_t)e * N + base;
     const int lane = lane_id(), wave = threadIdx.x >> 6, gq = lane >> 4;
-    const int ntiles = (n + 15) >> 4;
     float *out = p.bwd.phi_part + (size_t)item * kPhiN;
 
     // (a) encoder pass: max-pool with arg-max (lowest node on ties)
@@ -739,19 +844,26 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
     for (int ot = 0; ot < 4; ++ot)
         #pragma unroll
         for (int r = 0; r < 4; ++r) { mx[ot][r] = -1.0f; mi[ot][r] = 0x7fffffff; }
-    for (int t = wave; t < ntiles; t += kWaves) {
-        const int ln = t * 16 + (lane & 15);
-        const bool valid = ln < n;
-        half8 xh, xl;
-        load_x(M, k, base + ln, valid, uhn, n_max, ln, xh, xl);
-        floatx4 h1[4], f[4];
-        encoder_tile(L, xh, xl, h1, f);
-        if (valid)
-            #pragma unroll
-            for (int ot = 0; ot < 4; ++ot)
+    for (int c0 = 0; c0 < n; c0 += kStage) {
+        const int cnt = min(kStage, n - c0);
+        __syncthreads();
+        stage_nodes(M, k, base, nullptr, c0, cnt, uhn, n_max, 0, S.u.xs);
+        __syncthreads();
+        const int ntl = (cnt + 15) >> 4;
+        for (int t = wave; t < ntl; t += kWaves) {
+            const int lj = t * 16 + (lane & 15);
+            const bool valid = lj < cnt;
+            half8 xh, xl;
+            stage_x<false>(S.u.xs, lj, valid, xh, xl);
+            floatx4 h1[4], f[4];
+            encoder_tile(L, xh, xl, h1, f);
+            if (valid)
                 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (f[ot][r] > mx[ot][r]) { mx[ot][r] = f[ot][r]; mi[ot][r] = ln; }
+                for (int ot = 0; ot < 4; ++ot)
+                    #pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (f[ot][r] > mx[ot][r]) { mx[ot][r] = f[ot][r]; mi[ot][r] = c0 + lj; }
+        }
     }
     #pragma unroll
     for (int ot = 0; ot < 4; ++ot)
@@ -796,8 +908,14 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
     WGrad G;
     zero_wgrad(G);
     for (int j = 0; j < 8; ++j) S.acc15[wave][j * 64 + lane] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-    const int ptiles = (np + 15) >> 4;
-    for (int t = wave; t < ptiles; t += kWaves) passive_tile(p, S, G, k, base, np, plist, t, row, EN, uhn);
+    for (int c0 = 0; c0 < np; c0 += kStage) {
+        const int cnt = min(kStage, np - c0);
+        __syncthreads();
+        stage_nodes(M, k, base, plist, c0, cnt, p.grad_u, EN, row, S.u.xs);
+        __syncthreads();
+        const int ptl = (cnt + 15) >> 4;
+        for (int t = wave; t < ptl; t += kWaves) passive_tile(S, G, cnt, t);
+    }
 
     // (c) db4 = s4 = sum_i dpre4_i; global MLP adjoint: dg' = W4[:, 64:]^T s4,
     //     dpre3 = dg' [g' > 0], dg = W3^T dpre3
@@ -848,16 +966,30 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
     // (d) max-pool routing: wave w takes channels 16 w .. 16 w + 15
     routing_tile(p, S, G, k, base, n, uhn);
     __syncthreads();
-    // Wave 0 adds the routed dL/du_hat in channel order; all its lanes do the same update.
-    if (threadIdx.x < 64)
-        for (int c = 0; c < 64; ++c) {
-            const int ln = S.argmax[c];
-            if (ln < n && wobj[ln] >= 0) {
-                gh[ln] += S.dxs[c][0];
-                gh[n_max + ln] += S.dxs[c][1];
-                gh[2 * n_max + ln] += S.dxs[c][2];
-            }
+    // Routed dL/du_hat of active arg-max nodes: lane c of wave 0 owns channel
+    // c's node if c is the lowest channel routed there; the owner sums the
+    // node's channels in channel order and updates gh once.
+    if (threadIdx.x < 64) {
+        const int c = threadIdx.x;
+        const int ln = S.argmax[c];
+        const float x0 = S.dxs[c][0], x1 = S.dxs[c][1], x2 = S.dxs[c][2];
+        bool owner = ln < n;
+        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+        for (int c2 = 0; c2 < 64; ++c2) {   // channel c2's node and values, read from its lane
+            const int l2 = __builtin_amdgcn_readlane(ln, c2);
+            const float y0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x0), c2));
+            const float y1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x1), c2));
+            const float y2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x2), c2));
+            const bool same = l2 == ln;
+            owner = owner && !(same && c2 < c);
+            if (same && c2 >= c) { s0 += y0; s1 += y1; s2 += y2; }
         }
+        if (owner && wobj[ln] >= 0) {
+            gh[ln] += s0;
+            gh[n_max + ln] += s1;
+            gh[2 * n_max + ln] += s2;
+        }
+    }
 
     // (e) item partial of every parameter gradient: the four waves'
     //     accumulators summed in wave order, kRedRegs registers per pass

@@ -451,28 +451,105 @@ __device__ __forceinline__ void load_x(const MeshDev &M, int k, int gnode, bool 
     split8(v, xh, xl);
 }
 
+// y = W x + acc over the two K steps of a 64 -> 64 layer in T form; the three
+// split passes run pass-outermost over the four output blocks, so no MFMA
+// waits on the one before it (each block sees hi*hi, hi*lo, lo*hi per step).
+__device__ __forceinline__ void layer64_t(const half8 *wh, const half8 *wl, const half8 bh[2], const half8 bl[2],
+                                          floatx4 acc[4]) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        half8 h[4], l[4];
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot) {
+            h[ot] = wh[(ot * 2 + s) * 64 + lane];
+            l[ot] = wl[(ot * 2 + s) * 64 + lane];
+        }
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot) acc[ot] = mfma16(h[ot], bh[s], acc[ot]);
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot) acc[ot] = mfma16(h[ot], bl[s], acc[ot]);
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot) acc[ot] = mfma16(l[ot], bh[s], acc[ot]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// node inputs staged in LDS for the network passes
+//
+// xs[f][j], f = 0..8: [p - o_k (3), n (3), a third triple] of staged node j.
+// The third triple is U_hat (network input) or, in the adjoint's pass over
+// passive nodes, dL/dU (U_hat is 0 there).  One parallel gather per chunk of
+// kStage nodes replaces dependent global loads per 16-node tile.
+// ---------------------------------------------------------------------------
+constexpr int kStage = 1024;
+typedef float StageBuf[9][kStage];
+
+// Stage nodes c0 + j (list == nullptr) or list[c0 + j], j < cnt; the third
+// triple is third[c * stride + off + node] (zeros when third is null).
+// Whole workgroup; the caller brackets it with barriers.
+__device__ __forceinline__ void stage_nodes(const MeshDev &M, int k, int base, const int *list, int c0, int cnt,
+                                            const float *third, size_t stride, size_t off, StageBuf &xs) {
+    const int N = M.N;
+    const float o0 = M.origin[3 * k], o1 = M.origin[3 * k + 1], o2 = M.origin[3 * k + 2];
+    for (int j = threadIdx.x; j < cnt; j += kWG) {
+        const int i = list ? list[c0 + j] : c0 + j;
+        const int g = base + i;
+        xs[0][j] = M.pos[g] - o0;
+        xs[1][j] = M.pos[N + g] - o1;
+        xs[2][j] = M.pos[2 * N + g] - o2;
+        xs[3][j] = M.nrm[g];
+        xs[4][j] = M.nrm[N + g];
+        xs[5][j] = M.nrm[2 * N + g];
+        xs[6][j] = third ? third[off + i] : 0.0f;
+        xs[7][j] = third ? third[stride + off + i] : 0.0f;
+        xs[8][j] = third ? third[2 * stride + off + i] : 0.0f;
+    }
+}
+
+// T-form network input of staged node j (lane group q supplies features
+// 8 q .. 8 q + 7, zero padded to 32); with ZERO_U the U_hat features are 0.
+template <bool ZERO_U>
+__device__ __forceinline__ void stage_x(const StageBuf &xs, int j, bool valid, half8 &xh, half8 &xl) {
+    const int q = lane_id() >> 4;
+    float v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = 0.0f;
+    if (valid && q == 0) {
+#pragma unroll
+        for (int e = 0; e < 6; ++e) v[e] = xs[e][j];
+        if (!ZERO_U) { v[6] = xs[6][j]; v[7] = xs[7][j]; }
+    } else if (valid && q == 1 && !ZERO_U) {
+        v[0] = xs[8][j];
+    }
+    split8(v, xh, xl);
+}
+
 // Encoder: h1 = relu(W1 x + b1), f = relu(W2 h1 + b2) for a 16-node tile.
 __device__ __forceinline__ void encoder_tile(const NetLds &L, const half8 &xh, const half8 &xl, floatx4 h1[4],
                                              floatx4 f[4]) {
     reload_fence();
     const int lane = lane_id(), gq = lane >> 4;
+    half8 wh[4], wl[4];
 #pragma unroll
     for (int ot = 0; ot < 4; ++ot) {
-        const floatx4 acc = *reinterpret_cast<const floatx4 *>(&L.b1[ot * 16 + 4 * gq]);
-        h1[ot] = relu4(mfma_split(L.w1h[ot * 64 + lane], L.w1l[ot * 64 + lane], xh, xl, acc));
+        wh[ot] = L.w1h[ot * 64 + lane];
+        wl[ot] = L.w1l[ot * 64 + lane];
+        h1[ot] = *reinterpret_cast<const floatx4 *>(&L.b1[ot * 16 + 4 * gq]);
     }
+#pragma unroll
+    for (int ot = 0; ot < 4; ++ot) h1[ot] = mfma16(wh[ot], xh, h1[ot]);
+#pragma unroll
+    for (int ot = 0; ot < 4; ++ot) h1[ot] = mfma16(wh[ot], xl, h1[ot]);
+#pragma unroll
+    for (int ot = 0; ot < 4; ++ot) h1[ot] = relu4(mfma16(wl[ot], xh, h1[ot]));
     half8 bh[2], bl[2];
     split_chain(h1, bh, bl);
 #pragma unroll
-    for (int ot2 = 0; ot2 < 4; ++ot2) {
-        floatx4 acc = *reinterpret_cast<const floatx4 *>(&L.b2[ot2 * 16 + 4 * gq]);
+    for (int ot = 0; ot < 4; ++ot) f[ot] = *reinterpret_cast<const floatx4 *>(&L.b2[ot * 16 + 4 * gq]);
+    layer64_t(L.w2h, L.w2l, bh, bl, f);
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int fi = (ot2 * 2 + s) * 64 + lane;
-            acc = mfma_split(L.w2h[fi], L.w2l[fi], bh[s], bl[s], acc);
-        }
-        f[ot2] = relu4(acc);
-    }
+    for (int ot = 0; ot < 4; ++ot) f[ot] = relu4(f[ot]);
 }
 
 // Decoder: h4 = relu(W4 [f; g'] + b4) with the g' part folded into c4, then
@@ -483,15 +560,10 @@ __device__ __forceinline__ void decoder_tile(const NetLds &L, const floatx4 f[4]
     half8 bh[2], bl[2];
     split_chain(f, bh, bl);
 #pragma unroll
-    for (int ot2 = 0; ot2 < 4; ++ot2) {
-        floatx4 acc = *reinterpret_cast<const floatx4 *>(&L.c4[ot2 * 16 + 4 * gq]);
+    for (int ot = 0; ot < 4; ++ot) h4[ot] = *reinterpret_cast<const floatx4 *>(&L.c4[ot * 16 + 4 * gq]);
+    layer64_t(L.w4h, L.w4l, bh, bl, h4);
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int fi = (ot2 * 2 + s) * 64 + lane;
-            acc = mfma_split(L.w4h[fi], L.w4l[fi], bh[s], bl[s], acc);
-        }
-        h4[ot2] = relu4(acc);
-    }
+    for (int ot = 0; ot < 4; ++ot) h4[ot] = relu4(h4[ot]);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         float s = 0.0f;

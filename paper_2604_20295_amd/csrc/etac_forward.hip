@@ -8,7 +8,7 @@
 
 namespace etac {
 
-constexpr int kChunk = 1536;      // active nodes staged in LDS per pass of the decay loop
+constexpr int kChunk = 1024;      // active nodes staged in LDS per pass of the decay loop
 
 // ---------------------------------------------------------------------------
 // contact pass alone
@@ -78,8 +78,14 @@ struct StepParams {
 
 struct StepLds {
     NetLds net;
-    float4 act_a[kChunk];    // (px, py, pz, ux) of staged active nodes
-    float2 act_b[kChunk];    // (uy, uz)
+    union {
+        struct {
+            float4 act_a[kChunk];    // (px, py, pz, ux) of staged active nodes
+            float2 act_b[kChunk];    // (uy, uz)
+            double part[kWG][6];     // per-thread partial sums of its passive nodes (segment combine)
+        };
+        StageBuf xs;                 // node inputs of the network passes (before the decay)
+    };
     int wcnt[2][kWaves];
     ItemBatch batch;
 };
@@ -151,23 +157,29 @@ __device__ void residual_item(const StepParams &p, StepLds &S, int k, int base, 
     NetLds &L = S.net;
     const int lane = lane_id(), wave = threadIdx.x >> 6, gq = lane >> 4;
     const int n_max = p.scr.n_max;
-    const int ntiles = (n + 15) >> 4;
     floatx4 mx[4];
     #pragma unroll
     for (int ot = 0; ot < 4; ++ot) mx[ot] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int t = wave; t < ntiles; t += kWaves) {
-        const int ln = t * 16 + (lane & 15);
-        const bool valid = ln < n;
-        half8 xh, xl;
-        load_x(p.mesh, k, base + ln, valid, uhn, n_max, ln, xh, xl);
-        floatx4 h1[4], f[4];
-        encoder_tile(L, xh, xl, h1, f);
-        // f >= 0, so padding nodes with 0 leaves the max-pool unchanged
-        if (valid)
-            #pragma unroll
-            for (int ot = 0; ot < 4; ++ot)
+    for (int c0 = 0; c0 < n; c0 += kStage) {
+        const int cnt = min(kStage, n - c0);
+        __syncthreads();
+        stage_nodes(p.mesh, k, base, nullptr, c0, cnt, uhn, n_max, 0, S.xs);
+        __syncthreads();
+        const int ntl = (cnt + 15) >> 4;
+        for (int t = wave; t < ntl; t += kWaves) {
+            const int lj = t * 16 + (lane & 15);
+            const bool valid = lj < cnt;
+            half8 xh, xl;
+            stage_x<false>(S.xs, lj, valid, xh, xl);
+            floatx4 h1[4], f[4];
+            encoder_tile(L, xh, xl, h1, f);
+            // f >= 0, so padding nodes with 0 leaves the max-pool unchanged
+            if (valid)
                 #pragma unroll
-                for (int r = 0; r < 4; ++r) mx[ot][r] = fmaxf(mx[ot][r], f[ot][r]);
+                for (int ot = 0; ot < 4; ++ot)
+                    #pragma unroll
+                    for (int r = 0; r < 4; ++r) mx[ot][r] = fmaxf(mx[ot][r], f[ot][r]);
+        }
     }
     #pragma unroll
     for (int ot = 0; ot < 4; ++ot)
@@ -193,18 +205,23 @@ __device__ void residual_item(const StepParams &p, StepLds &S, int k, int base, 
     }
     __syncthreads();
     global_mlp(L, p.model.phi);
-    const int ptiles = (np + 15) >> 4;
-    for (int t = wave; t < ptiles; t += kWaves) {
-        const int li = t * 16 + (lane & 15);
-        const bool valid = li < np;
-        const int ln = valid ? plist[li] : 0;
-        half8 xh, xl;
-        load_x(p.mesh, k, base + ln, valid, uhn, n_max, ln, xh, xl);
-        floatx4 h1[4], f[4], h4[4];
-        encoder_tile(L, xh, xl, h1, f);
-        float r[3];
-        decoder_tile(L, f, h4, r);
-        if (valid && gq < 3) resid[gq * n_max + ln] = r[gq];
+    for (int c0 = 0; c0 < np; c0 += kStage) {
+        const int cnt = min(kStage, np - c0);
+        __syncthreads();
+        stage_nodes(p.mesh, k, base, plist, c0, cnt, nullptr, 0, 0, S.xs);   // passive: U_hat = 0
+        __syncthreads();
+        const int ptl = (cnt + 15) >> 4;
+        for (int t = wave; t < ptl; t += kWaves) {
+            const int lj = t * 16 + (lane & 15);
+            const bool valid = lj < cnt;
+            half8 xh, xl;
+            stage_x<true>(S.xs, lj, valid, xh, xl);
+            floatx4 h1[4], f[4], h4[4];
+            encoder_tile(L, xh, xl, h1, f);
+            float r[3];
+            decoder_tile(L, f, h4, r);
+            if (valid && gq < 3) resid[gq * n_max + plist[c0 + lj]] = r[gq];
+        }
     }
     __syncthreads();
 }
@@ -222,29 +239,117 @@ __device__ __forceinline__ void stage_active(const StepParams &p, StepLds &S, in
     }
 }
 
-// Eq. 1 over one staged chunk for two passive nodes per thread.  FP32 terms
-// are summed in blocks of 32 and the block sums are accumulated in FP64.
-__device__ __forceinline__ void decay_chunk(const StepLds &S, int cnt, float nbeta, float px0, float py0,
-                                            float pz0, float px1, float py1, float pz1, double acc0[3],
-                                            double acc1[3]) {
-    for (int j0 = 0; j0 < cnt; j0 += 32) {
-        const int j1 = min(cnt, j0 + 32);
-        float s0x = 0.f, s0y = 0.f, s0z = 0.f, s1x = 0.f, s1y = 0.f, s1z = 0.f;
+// Eq. 1 over staged active nodes [lo, hi) for P passive nodes per thread.
+// FP32 terms are summed in blocks of 32 and the block sums are accumulated
+// in FP64.
+template <int P>
+__device__ __forceinline__ void decay_range(const StepLds &S, int lo, int hi, float nbeta, const float (&px)[P],
+                                            const float (&py)[P], const float (&pz)[P], double (&acc)[P][3]) {
+    for (int j0 = lo; j0 < hi; j0 += 32) {
+        const int j1 = min(hi, j0 + 32);
+        float sx[P], sy[P], sz[P];
+#pragma unroll
+        for (int a = 0; a < P; ++a) sx[a] = sy[a] = sz[a] = 0.0f;
         for (int j = j0; j < j1; ++j) {
-            const float4 a = S.act_a[j];
-            const float2 b = S.act_b[j];
-            const float dx0 = a.x - px0, dy0 = a.y - py0, dz0 = a.z - pz0;
-            const float dx1 = a.x - px1, dy1 = a.y - py1, dz1 = a.z - pz1;
-            const float d0 = __builtin_amdgcn_sqrtf(dx0 * dx0 + dy0 * dy0 + dz0 * dz0);
-            const float d1 = __builtin_amdgcn_sqrtf(dx1 * dx1 + dy1 * dy1 + dz1 * dz1);
-            const float w0 = __builtin_amdgcn_exp2f(nbeta * d0);
-            const float w1 = __builtin_amdgcn_exp2f(nbeta * d1);
-            s0x += w0 * a.w; s0y += w0 * b.x; s0z += w0 * b.y;
-            s1x += w1 * a.w; s1y += w1 * b.x; s1z += w1 * b.y;
+            const float4 pa = S.act_a[j];
+            const float2 pb = S.act_b[j];
+#pragma unroll
+            for (int a = 0; a < P; ++a) {
+                const float dx = pa.x - px[a], dy = pa.y - py[a], dz = pa.z - pz[a];
+                const float d = __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
+                const float w = __builtin_amdgcn_exp2f(nbeta * d);
+                sx[a] += w * pa.w; sy[a] += w * pb.x; sz[a] += w * pb.y;
+            }
         }
-        acc0[0] += s0x; acc0[1] += s0y; acc0[2] += s0z;
-        acc1[0] += s1x; acc1[1] += s1y; acc1[2] += s1z;
+#pragma unroll
+        for (int a = 0; a < P; ++a) { acc[a][0] += sx[a]; acc[a][1] += sy[a]; acc[a][2] += sz[a]; }
     }
+}
+
+// Passive nodes of one item: U = Omega U_a (Eq. 1) + residual.  Pairs are
+// split over a grid of SLOTS passive slots x (kWG / SLOTS) active segments:
+// every thread owns P passive nodes per pass and one segment of each staged
+// chunk of active nodes; segment partials are combined in segment order.
+// Active nodes are already staged when the item has one chunk.
+template <int SLOTS, int P>
+__device__ void decay_item(const StepParams &p, StepLds &S, int base, int m, int np, const int *alist,
+                           const int *plist, const float *uhn, const float *resid, bool use_dec, bool use_res,
+                           float nbeta, size_t row) {
+    const MeshDev &M = p.mesh;
+    const int N = M.N, n_max = p.scr.n_max;
+    const size_t EN = (size_t)p.E * N;
+    constexpr int nseg = kWG / SLOTS;
+    const int slot = threadIdx.x % SLOTS, seg = threadIdx.x / SLOTS;
+    const bool one_chunk = m <= kChunk;
+    for (int pb = 0; pb < np; pb += P * SLOTS) {
+        bool v[P];
+        int ii[P];
+        float px[P], py[P], pz[P];
+        double acc[P][3];
+#pragma unroll
+        for (int a = 0; a < P; ++a) {
+            const int t = pb + slot + a * SLOTS;
+            v[a] = t < np;
+            ii[a] = v[a] ? plist[t] : 0;
+            const int g = base + ii[a];
+            px[a] = M.pos[g]; py[a] = M.pos[N + g]; pz[a] = M.pos[2 * N + g];
+            acc[a][0] = acc[a][1] = acc[a][2] = 0.0;
+        }
+        if (use_dec) {
+            if (one_chunk) {
+                const int per = (m + nseg - 1) / nseg, lo = seg * per;
+                decay_range<P>(S, lo, min(m, lo + per), nbeta, px, py, pz, acc);
+            } else {
+                for (int c0 = 0; c0 < m; c0 += kChunk) {
+                    const int cnt = min(kChunk, m - c0);
+                    __syncthreads();
+                    stage_active(p, S, base, alist, uhn, c0, cnt);
+                    __syncthreads();
+                    const int per = (cnt + nseg - 1) / nseg, lo = seg * per;
+                    decay_range<P>(S, lo, min(cnt, lo + per), nbeta, px, py, pz, acc);
+                }
+            }
+            if (nseg > 1) {
+                __syncthreads();
+                double *mine = S.part[threadIdx.x];
+#pragma unroll
+                for (int a = 0; a < P; ++a) { mine[3 * a] = acc[a][0]; mine[3 * a + 1] = acc[a][1]; mine[3 * a + 2] = acc[a][2]; }
+                __syncthreads();
+                if (seg == 0)
+                    for (int q = 1; q < nseg; ++q) {
+                        const double *o = S.part[q * SLOTS + slot];
+#pragma unroll
+                        for (int a = 0; a < P; ++a) { acc[a][0] += o[3 * a]; acc[a][1] += o[3 * a + 1]; acc[a][2] += o[3 * a + 2]; }
+                    }
+            }
+        }
+        if (seg == 0)
+#pragma unroll
+            for (int a = 0; a < P; ++a)
+                if (v[a]) {
+                    const int i = ii[a];
+                    if (use_res)
+                        for (int c = 0; c < 3; ++c) acc[a][c] += (double)resid[c * n_max + i];
+                    p.u[row + i] = (float)acc[a][0];
+                    p.u[EN + row + i] = (float)acc[a][1];
+                    p.u[2 * EN + row + i] = (float)acc[a][2];
+                }
+    }
+}
+
+// Same shape choice as the adjoint: fewest thread iterations over the
+// np x m pairs, two nodes per thread weighted 1.75.  0..5 = (64|128|256) x (1|2).
+__device__ __forceinline__ int decay_grid_shape(int np, int m) {
+    int best = 5;
+    float bc = 3.0e38f;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const int slots = 64 << (c % 3), a = 1 + c / 3, nseg = kWG / slots;
+        const float cost = (float)((np + a * slots - 1) / (a * slots)) * (float)((m + nseg - 1) / nseg) *
+                           (a == 2 ? 1.75f : 1.0f);
+        if (cost < bc) { bc = cost; best = c; }
+    }
+    return best;
 }
 
 // One item with at least one candidate object (cand: objects that may reach
@@ -279,46 +384,19 @@ __device__ void process_item(const StepParams &p, StepLds &S, int e, int k, unsi
     if (use_res) residual_item(p, S, k, base, n, uhn, plist, np, resid);
     // exp(-alpha d) = exp2(-alpha log2(e) d)
     const float nbeta = (float)(-(double)p.model.alpha[k] * 1.4426950408889634);
-    const bool one_chunk = m <= kChunk;
-    if (use_dec && one_chunk) {
+    if (use_dec && m <= kChunk) {
         stage_active(p, S, base, alist, uhn, 0, m);
         __syncthreads();
     }
-    for (int pb = 0; pb < np; pb += 2 * kWG) {
-        const int t0 = pb + threadIdx.x, t1 = t0 + kWG;
-        const bool v0 = t0 < np, v1 = t1 < np;
-        const int i0 = v0 ? plist[t0] : 0, i1 = v1 ? plist[t1] : 0;
-        const int g0 = base + i0, g1 = base + i1;
-        double a0[3] = {0.0, 0.0, 0.0}, a1[3] = {0.0, 0.0, 0.0};
-        if (use_dec) {
-            const float px0 = M.pos[g0], py0 = M.pos[N + g0], pz0 = M.pos[2 * N + g0];
-            const float px1 = M.pos[g1], py1 = M.pos[N + g1], pz1 = M.pos[2 * N + g1];
-            if (one_chunk) {
-                decay_chunk(S, m, nbeta, px0, py0, pz0, px1, py1, pz1, a0, a1);
-            } else {
-                for (int c0 = 0; c0 < m; c0 += kChunk) {
-                    const int cnt = min(kChunk, m - c0);
-                    __syncthreads();
-                    stage_active(p, S, base, alist, uhn, c0, cnt);
-                    __syncthreads();
-                    decay_chunk(S, cnt, nbeta, px0, py0, pz0, px1, py1, pz1, a0, a1);
-                }
-            }
-        }
-        if (use_res) {
-            if (v0) for (int c = 0; c < 3; ++c) a0[c] += (double)resid[c * n_max + i0];
-            if (v1) for (int c = 0; c < 3; ++c) a1[c] += (double)resid[c * n_max + i1];
-        }
-        if (v0) {
-            p.u[row + i0] = (float)a0[0];
-            p.u[EN + row + i0] = (float)a0[1];
-            p.u[2 * EN + row + i0] = (float)a0[2];
-        }
-        if (v1) {
-            p.u[row + i1] = (float)a1[0];
-            p.u[EN + row + i1] = (float)a1[1];
-            p.u[2 * EN + row + i1] = (float)a1[2];
-        }
+    // with the decay off (residual only) every shape does the same work
+    const int shape = use_dec ? uniform(decay_grid_shape(np, m)) : 5;
+    switch (shape) {
+        case 0: decay_item<64, 1>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, nbeta, row); break;
+        case 1: decay_item<128, 1>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, nbeta, row); break;
+        case 2: decay_item<256, 1>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, nbeta, row); break;
+        case 3: decay_item<64, 2>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, nbeta, row); break;
+        case 4: decay_item<128, 2>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, nbeta, row); break;
+        default: decay_item<256, 2>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, nbeta, row); break;
     }
     __syncthreads();
 }
