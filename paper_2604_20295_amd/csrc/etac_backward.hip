@@ -115,12 +115,14 @@ __device__ void stage_net_t(BwdLds &S, const float *phi) {
 typedef _Float16 half4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void split4(const floatx4 &v, half4 &hi, half4 &lo) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const _Float16 h = (_Float16)v[e];
-        hi[e] = h;
-        lo[e] = (_Float16)(v[e] - (float)h);
-    }
+    uint2t h, l;
+    unsigned a, b, c, d;
+    split2(v[0], v[1], a, b);
+    split2(v[2], v[3], c, d);
+    h[0] = a; h[1] = c;
+    l[0] = b; l[1] = d;
+    hi = __builtin_bit_cast(half4, h);
+    lo = __builtin_bit_cast(half4, l);
 }
 
 __device__ __forceinline__ floatx4 mfma_k16(const half4 &a, const half4 &b, floatx4 c) {
@@ -332,18 +334,25 @@ __device__ void passive_tile(BwdLds &S, WGrad &G, int cnt, int t) {
         lj[r] = 16 * t + 4 * gq + r;
         vr[r] = lj[r] < cnt;
     }
-    // N-form network inputs: feature col of nodes lj[r] (U_hat = 0; input 9 = 1)
+    // N-form network inputs: feature col of nodes lj[r] (U_hat = 0; input 9 =
+    // 1).  Reads stay inside the stage (tile rows < kStage) and are masked
+    // afterwards, so no lane branches.
+    const int fcol = col < 6 ? col : 0;
+    const float fsel = col < 6 ? 1.0f : 0.0f, fone = col == 9 ? 1.0f : 0.0f;
     floatx4 xn;
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-        xn[r] = !vr[r] ? 0.0f : (col < 6 ? xs[col][lj[r]] : (col == 9 ? 1.0f : 0.0f));
+    for (int r = 0; r < 4; ++r) xn[r] = vr[r] ? xs[fcol][lj[r]] * fsel + fone : 0.0f;
     // dL/dr of the tile's nodes in both forms (zero on padding)
     float dr[3], drn[3][4];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        dr[c] = valid ? xs[6 + c][li] : 0.0f;
+        const float v = xs[6 + c][li];
+        dr[c] = valid ? v : 0.0f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) drn[c][r] = vr[r] ? xs[6 + c][lj[r]] : 0.0f;
+        for (int r = 0; r < 4; ++r) {
+            const float w = xs[6 + c][lj[r]];
+            drn[c][r] = vr[r] ? w : 0.0f;
+        }
     }
     half8 xh, xl;
     stage_x<true>(xs, li, valid, xh, xl);
@@ -382,8 +391,12 @@ __device__ void passive_tile(BwdLds &S, WGrad &G, int cnt, int t) {
     // dW5 += dr (x) h4 (lane col < 3 supplies output col), db5
     {
         floatx4 a;
+        const int ccol = col < 3 ? col : 0;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) a[r] = col == 0 ? drn[0][r] : (col == 1 ? drn[1][r] : (col == 2 ? drn[2][r] : 0.0f));
+        for (int r = 0; r < 4; ++r) {
+            const float v = xs[6 + ccol][lj[r]];
+            a[r] = (vr[r] && col < 3) ? v : 0.0f;
+        }
         G.b5 += (a[0] + a[1]) + (a[2] + a[3]);
         half4 ah, al, bh[4], bl[4];
         split4(a, ah, al);

@@ -343,13 +343,41 @@ struct NetLds {
     float part[kWaves][64];                  // per-wave partials
 };
 
+typedef _Float16 half2t __attribute__((ext_vector_type(2)));
+typedef unsigned uint2t __attribute__((ext_vector_type(2)));
+typedef unsigned uint4t __attribute__((ext_vector_type(4)));
+
+// x - (float)h exactly, for h the FP16 value in the low (HI_HALF false) or
+// high half of a packed register: one v_fma_mix_f32 (-h * 1.0 + x with the
+// FP16 operand converted inside the instruction).
+template <bool HI_HALF>
+__device__ __forceinline__ float sub_f16(float x, unsigned h2) {
+    float r;
+    if (HI_HALF) asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(h2), "v"(x));
+    else asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(h2), "v"(x));
+    return r;
+}
+
+// Split two floats: hi = fp16(a), fp16(b) packed; lo = fp16 of the exact
+// remainders.  Four instructions per pair.
+__device__ __forceinline__ void split2(float a, float b, unsigned &hi, unsigned &lo) {
+    const half2t h = {(_Float16)a, (_Float16)b};
+    hi = __builtin_bit_cast(unsigned, h);
+    const half2t l = {(_Float16)sub_f16<false>(a, hi), (_Float16)sub_f16<true>(b, hi)};
+    lo = __builtin_bit_cast(unsigned, l);
+}
+
 __device__ __forceinline__ void split8(const float v[8], half8 &hi, half8 &lo) {
+    uint4t h, l;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const _Float16 h = (_Float16)v[e];
-        hi[e] = h;
-        lo[e] = (_Float16)(v[e] - (float)h);
+    for (int e = 0; e < 4; ++e) {
+        unsigned a, b;
+        split2(v[2 * e], v[2 * e + 1], a, b);
+        h[e] = a;
+        l[e] = b;
     }
+    hi = __builtin_bit_cast(half8, h);
+    lo = __builtin_bit_cast(half8, l);
 }
 
 // Input feature of K step s, lane group q, element e of a 64 -> 64 layer.
@@ -406,10 +434,14 @@ __device__ __forceinline__ floatx4 mfma_split(const half8 &ah, const half8 &al, 
     return mfma16(al, bh, acc);
 }
 
+// max(x, 0) as a signed-integer max of the bits: negative floats (and -0)
+// have negative bit patterns; one instruction, no NaN canonicalisation.
+__device__ __forceinline__ float relu1(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+
 __device__ __forceinline__ floatx4 relu4(floatx4 v) {
     floatx4 o;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) o[r] = fmaxf(v[r], 0.0f);
+    for (int r = 0; r < 4; ++r) o[r] = relu1(v[r]);
     return o;
 }
 
@@ -512,16 +544,18 @@ __device__ __forceinline__ void stage_nodes(const MeshDev &M, int k, int base, c
 template <bool ZERO_U>
 __device__ __forceinline__ void stage_x(const StageBuf &xs, int j, bool valid, half8 &xh, half8 &xl) {
     const int q = lane_id() >> 4;
+    // every lane reads inside the stage (j < kStage) and masks: no branches
+    const bool g0 = valid && q == 0, g1 = valid && q == 1 && !ZERO_U;
     float v[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = 0.0f;
-    if (valid && q == 0) {
-#pragma unroll
-        for (int e = 0; e < 6; ++e) v[e] = xs[e][j];
-        if (!ZERO_U) { v[6] = xs[6][j]; v[7] = xs[7][j]; }
-    } else if (valid && q == 1 && !ZERO_U) {
-        v[0] = xs[8][j];
+    for (int e = 0; e < 6; ++e) {
+        const float x = xs[e][j];
+        v[e] = g0 ? x : 0.0f;
     }
+    const float u0 = xs[6][j], u1 = xs[7][j], u2 = xs[8][j];
+    v[6] = (g0 && !ZERO_U) ? u0 : 0.0f;
+    v[7] = (g0 && !ZERO_U) ? u1 : 0.0f;
+    v[0] = g1 ? u2 : v[0];
     split8(v, xh, xl);
 }
 
