@@ -290,8 +290,8 @@ def main():
     if graph is None:
         fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
         bwd_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
-        for name, tid in (("k_step", _native.ETAC_TIMER_STEP), ("k_bwd", _native.ETAC_TIMER_BACKWARD),
-                          ("bwd_reductions", _native.ETAC_TIMER_REDUCE)):
+        for name, tid in (("k_step", _native.ETAC_TIMER_STEP), ("k_bwd_decay", _native.ETAC_TIMER_BWD_DECAY),
+                          ("k_bwd", _native.ETAC_TIMER_BACKWARD), ("bwd_reductions", _native.ETAC_TIMER_REDUCE)):
             n, ms = plan.kernel_time(tid)
             kernel_avg[name] = ms / n if n else float("nan")
         plan.set_timing(False)

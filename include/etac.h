@@ -202,9 +202,10 @@ etac_status etac_plan_set_batch(etac_plan *plan, int32_t items);
 typedef enum {
     ETAC_TIMER_CONTACT = 0,   /* k_contact: contact only (etac_contact)                  */
     ETAC_TIMER_STEP = 1,      /* k_step: the fused persistent forward                    */
-    ETAC_TIMER_BACKWARD = 2,  /* k_bwd: the fused persistent adjoint                     */
+    ETAC_TIMER_BACKWARD = 2,  /* k_bwd: network and contact adjoint of contacted items   */
     ETAC_TIMER_REDUCE = 3,    /* the fixed-order reductions that follow k_bwd, as one span */
-    ETAC_TIMER_COUNT = 4
+    ETAC_TIMER_BWD_DECAY = 4, /* k_bwd_decay: contact and Eq. 1 adjoint, before k_bwd     */
+    ETAC_TIMER_COUNT = 5
 } etac_timer;
 
 /* Turn timing on (enable != 0) or off.  The first call that turns it on

@@ -22,7 +22,7 @@ ETAC_FULL, ETAC_DECAY_ONLY, ETAC_RESIDUAL_ONLY = 0, 1, 2
 ETAC_PHI_SIZE = 17411
 ETAC_MAX_OBJ = 8
 ETAC_PLAN_BACKWARD = 1
-ETAC_TIMER_CONTACT, ETAC_TIMER_STEP, ETAC_TIMER_BACKWARD, ETAC_TIMER_REDUCE = 0, 1, 2, 3
+ETAC_TIMER_CONTACT, ETAC_TIMER_STEP, ETAC_TIMER_BACKWARD, ETAC_TIMER_REDUCE, ETAC_TIMER_BWD_DECAY = 0, 1, 2, 3, 4
 ETAC_TIMER_SLOTS = 256
 
 EXPORTED = (

@@ -221,6 +221,11 @@ etac_status etac_plan_create(const etac_mesh *mesh, int32_t n_envs, int32_t max_
         if (e == hipSuccess) e = plan_alloc(p, &b.item_list, items);
         if (e == hipSuccess) e = plan_alloc(p, &b.n_list, 1);
         if (e == hipSuccess) e = plan_alloc(p, &b.phi_seg, (size_t)64 * ETAC_PHI_SIZE);
+        const size_t EN = (size_t)n_envs * N;
+        if (e == hipSuccess) e = plan_alloc(p, &b.cobj_st, EN);
+        if (e == hipSuccess) e = plan_alloc(p, &b.uhat_st, 3 * EN);
+        if (e == hipSuccess) e = plan_alloc(p, &b.gh_st, 3 * EN);
+        if (e == hipSuccess) e = plan_alloc(p, &b.m_st, items);
         p.has_bwd = (e == hipSuccess);
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();

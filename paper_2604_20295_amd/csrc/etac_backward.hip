@@ -1,8 +1,10 @@
 // Adjoint of the ETac step on gfx950.
 //
-// k_bwd is a persistent kernel over (env, patch) items like the forward step.
-// For every item it recomputes the contact pass (nothing is kept from the
-// forward call), then for L = sum_i g_i . U_i:
+// Two persistent kernels over (env, patch) items, like the forward step:
+// k_bwd_decay recomputes contact (nothing is kept from the forward call) and
+// runs steps 1-2 below with a small LDS footprint, several workgroups per
+// CU; k_bwd takes the contacted items and runs steps 3-4.  For
+// L = sum_i g_i . U_i:
 //   1. active nodes: dL/du_hat_j = g_j                        (U_j = u_hat_j)
 //   2. Eq. 1 adjoint, transposed pair loop over passive nodes i:
 //        dL/du_hat_j += sum_i w_ij g_i,
@@ -22,7 +24,7 @@
 
 namespace etac {
 
-constexpr int kBChunk = 1024;  // passive nodes staged per pass of the decay adjoint
+constexpr int kBChunk = 512;   // passive nodes staged per pass of the decay adjoint
 constexpr int kPhiSegs = 64;   // segments of the parameter-gradient reduction
 
 enum BwdKind { BWD_STEP = 0, BWD_PROP = 1, BWD_CONTACT = 2 };
@@ -44,17 +46,27 @@ struct BwdParams {
 
 constexpr int kRedRegs = 32;   // accumulator registers per lane summed per pass of the item reduction
 
+// Staging area of the decay adjoint.
+struct DecayStage {
+    float4 a[kBChunk];            // (px, py, pz, gx) of staged passive nodes
+    float2 b[kBChunk];            // (gy, gz)
+    double part[kWG][12];         // per-thread partial dL/du_hat of its (up to four) active nodes
+};
+
+// LDS of the decay kernel (contact, decay adjoint, hand-over).
+struct DecayLds {
+    DecayStage st;
+    double dred[kWaves][12];
+    int wcnt[2][kWaves];
+    ItemBatch batch;
+};
+
 struct BwdLds {
     NetLds net;
     half8 w2th[4 * 2 * 64], w2tl[4 * 2 * 64];   // [it][s][lane] split fragments of W2^T
     half8 w4th[4 * 2 * 64], w4tl[4 * 2 * 64];   // [it][s][lane] split fragments of W4[:, :64]^T
     float w1u[3][64];                           // W1[:, 6..8]: the u_hat inputs
     union {
-        struct {
-            float4 a[kBChunk];    // (px, py, pz, gx) of staged passive nodes
-            float2 b[kBChunk];    // (gy, gz)
-            double part[kWG][6];  // per-thread partial dL/du_hat of its two active nodes
-        } st;
         float red[kWaves][kRedRegs][64];   // one chunk of every wave's gradient accumulators
         StageBuf xs;                       // node inputs of the network passes
     } u;
@@ -553,7 +565,7 @@ __device__ __forceinline__ bool uses_residual(const BwdParams &p) {
 // broadcasts.  The segment partials of dL/du_hat_j are combined in segment
 // order; the thread's dL/dalpha contribution is returned.
 template <int SLOTS, int A>
-__device__ double decay_adjoint_grid(const BwdParams &p, BwdLds &S, int e, int k, int base, int m, int np,
+__device__ double decay_adjoint_grid(const BwdParams &p, DecayStage &st, int e, int k, int base, int m, int np,
                                      const int *alist, const int *plist, const float *uhn, float *gh) {
     const MeshDev &M = p.mesh;
     const int N = M.N, n_max = p.scr.n_max;
@@ -585,8 +597,8 @@ __device__ double decay_adjoint_grid(const BwdParams &p, BwdLds &S, int e, int k
             for (int t = threadIdx.x; t < cnt; t += kWG) {
                 const int i = plist[c0 + t];
                 const int gi = base + i;
-                S.u.st.a[t] = make_float4(M.pos[gi], M.pos[N + gi], M.pos[2 * N + gi], p.grad_u[row + i]);
-                S.u.st.b[t] = make_float2(p.grad_u[EN + row + i], p.grad_u[2 * EN + row + i]);
+                st.a[t] = make_float4(M.pos[gi], M.pos[N + gi], M.pos[2 * N + gi], p.grad_u[row + i]);
+                st.b[t] = make_float2(p.grad_u[EN + row + i], p.grad_u[2 * EN + row + i]);
             }
             __syncthreads();
             const int per = (cnt + nseg - 1) / nseg;
@@ -598,8 +610,8 @@ __device__ double decay_adjoint_grid(const BwdParams &p, BwdLds &S, int e, int k
                 for (int a = 0; a < A; ++a) sx[a] = sy[a] = sz[a] = q[a] = 0.0f;
 #pragma unroll 2
                 for (int i = i0; i < i1; ++i) {
-                    const float4 pa = S.u.st.a[i];
-                    const float2 pb = S.u.st.b[i];
+                    const float4 pa = st.a[i];
+                    const float2 pb = st.b[i];
 #pragma unroll
                     for (int a = 0; a < A; ++a) {
                         const float dx = pa.x - px[a], dy = pa.y - py[a], dz = pa.z - pz[a];
@@ -622,13 +634,13 @@ __device__ double decay_adjoint_grid(const BwdParams &p, BwdLds &S, int e, int k
         // combine the segments of each active node in segment order
         if (nseg > 1) {
             __syncthreads();
-            double *mine = S.u.st.part[threadIdx.x];
+            double *mine = st.part[threadIdx.x];
 #pragma unroll
             for (int a = 0; a < A; ++a) { mine[3 * a] = acc[a][0]; mine[3 * a + 1] = acc[a][1]; mine[3 * a + 2] = acc[a][2]; }
             __syncthreads();
             if (seg == 0)
                 for (int q = 1; q < nseg; ++q) {
-                    const double *o = S.u.st.part[q * SLOTS + slot];
+                    const double *o = st.part[q * SLOTS + slot];
 #pragma unroll
                     for (int a = 0; a < A; ++a) { acc[a][0] += o[3 * a]; acc[a][1] += o[3 * a + 1]; acc[a][2] += o[3 * a + 2]; }
                 }
@@ -647,22 +659,23 @@ __device__ double decay_adjoint_grid(const BwdParams &p, BwdLds &S, int e, int k
 }
 
 // Grid shape for m x np pairs: the (slots, nodes per thread) pair with the
-// fewest thread iterations, two nodes per thread weighted as 1.75 (they
-// share the LDS reads).  Returns 0..5 for (64|128|256) x (1|2).
+// fewest thread iterations; a nodes per thread cost less than a times one
+// (shared LDS reads, independent chains to hide latency).  Returns 0..8
+// for (64|128|256) x (1|2|4).
 __device__ __forceinline__ int decay_grid_shape(int m, int np) {
     int best = 5;
     float bc = 3.0e38f;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        const int slots = 64 << (c % 3), a = 1 + c / 3, nseg = kWG / slots;
-        const float cost = (float)((m + a * slots - 1) / (a * slots)) * (float)((np + nseg - 1) / nseg) *
-                           (a == 2 ? 1.75f : 1.0f);
+    for (int c = 0; c < 9; ++c) {
+        const int slots = 64 << (c % 3), a = 1 << (c / 3), nseg = kWG / slots;
+        const float w = a == 1 ? 1.0f : (a == 2 ? 1.75f : 3.3f);
+        const float cost = (float)((m + a * slots - 1) / (a * slots)) * (float)((np + nseg - 1) / nseg) * w;
         if (cost < bc) { bc = cost; best = c; }
     }
     return best;
 }
 
-__device__ double decay_adjoint(const BwdParams &p, BwdLds &S, int e, int k, int base, int m, int np,
+__device__ double decay_adjoint(const BwdParams &p, DecayStage &S, int e, int k, int base, int m, int np,
                                 const int *alist, const int *plist, const float *uhn, float *gh) {
     switch (uniform(decay_grid_shape(m, np))) {
         case 0: return decay_adjoint_grid<64, 1>(p, S, e, k, base, m, np, alist, plist, uhn, gh);
@@ -670,7 +683,10 @@ __device__ double decay_adjoint(const BwdParams &p, BwdLds &S, int e, int k, int
         case 2: return decay_adjoint_grid<256, 1>(p, S, e, k, base, m, np, alist, plist, uhn, gh);
         case 3: return decay_adjoint_grid<64, 2>(p, S, e, k, base, m, np, alist, plist, uhn, gh);
         case 4: return decay_adjoint_grid<128, 2>(p, S, e, k, base, m, np, alist, plist, uhn, gh);
-        default: return decay_adjoint_grid<256, 2>(p, S, e, k, base, m, np, alist, plist, uhn, gh);
+        case 5: return decay_adjoint_grid<256, 2>(p, S, e, k, base, m, np, alist, plist, uhn, gh);
+        case 6: return decay_adjoint_grid<64, 4>(p, S, e, k, base, m, np, alist, plist, uhn, gh);
+        case 7: return decay_adjoint_grid<128, 4>(p, S, e, k, base, m, np, alist, plist, uhn, gh);
+        default: return decay_adjoint_grid<256, 4>(p, S, e, k, base, m, np, alist, plist, uhn, gh);
     }
 }
 
@@ -679,7 +695,7 @@ __device__ double decay_adjoint(const BwdParams &p, BwdLds &S, int e, int k, int
 // Blocks that only part of the workgroup executes are whole waves and every
 // lane stores the same value, so no single-lane region sits next to a
 // barrier (the compiler may otherwise thread the rest of a wave past it).
-__device__ void wg_sum12(BwdLds &S, double v[12]) {
+__device__ void wg_sum12(double (&dred)[kWaves][12], double v[12]) {
     const int wave = threadIdx.x >> 6;
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
@@ -689,12 +705,12 @@ __device__ void wg_sum12(BwdLds &S, double v[12]) {
     }
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < 12; ++c) S.dred[wave][c] = v[c];
+    for (int c = 0; c < 12; ++c) dred[wave][c] = v[c];
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < 12; ++c) {
-        double s = S.dred[0][c];
-        for (int w = 1; w < kWaves; ++w) s += S.dred[w][c];
+        double s = dred[0][c];
+        for (int w = 1; w < kWaves; ++w) s += dred[w][c];
         v[c] = s;
     }
     __syncthreads();
@@ -786,7 +802,7 @@ __device__ void contact_adjoint_item(const BwdParams &p, BwdLds &S, int e, int i
                 contact_adjoint_node(ty, sh, R, t, M.pos[gj], M.pos[N + gj], M.pos[2 * N + gj], g, acc);
             }
         }
-        wg_sum12(S, acc);
+        wg_sum12(S.dred, acc);
         if (threadIdx.x < 12) out[o * 12 + threadIdx.x] = (float)acc[threadIdx.x];
         __syncthreads();
     }
@@ -1062,28 +1078,38 @@ __device__ void zero_fill_batch_bwd(const BwdParams &p, const ItemBatch &B, int 
         for (int c = lane; c < O * 12; c += 64) p.bwd.pose_part[item * O * 12 + c] = 0.0f;
         p.bwd.alpha_part[item] = 0.0f;
         p.bwd.item_flag[item] = 0;
+        p.bwd.m_st[item] = 0;
     }
 }
 
-// One item (item = e K + k indexes the partials) with candidate objects cand
-// (all bits set when contact results are given).
+// ---------------------------------------------------------------------------
+// k_bwd_decay: contact and the Eq. 1 adjoint of every item
+//
+// Runs before k_bwd with a small LDS footprint, so several workgroups share
+// a CU.  For every item it recomputes (or reads) contact, writes the active
+// count, the alpha partial and, for items without contact, every zero
+// partial; for contacted items it hands dL/du_hat (own U plus the decay
+// adjoint) and, in the step adjoint, the contact results to k_bwd.
+// ---------------------------------------------------------------------------
 template <int KIND>
-__device__ void process_item_bwd(const BwdParams &p, BwdLds &S, int item, int e, int k, unsigned cand, float *uhn,
-                                 float *gh, int *alist, int *plist, int8_t *wobj) {
+__device__ void decay_item_bwd(const BwdParams &p, DecayLds &S, int item, int e, int k, unsigned cand, float *uhn,
+                               float *gh, int *alist, int *plist) {
     const MeshDev &M = p.mesh;
     const int N = M.N, n_max = p.scr.n_max, O = p.scene.O;
     const size_t EN = (size_t)p.E * N;
     const int base = M.offset[k];
     const int n = M.offset[k + 1] - base;
     const size_t row = (size_t)e * N + base;
-    const int m = contact_and_compact<KIND == BWD_PROP>(M, p.scene, p.E, n_max, p.cobj_in, p.uhat_in, nullptr, S.wcnt,
-                                                        e, k, base, n, cand, uhn, alist, plist, wobj);
+    const int m = contact_and_compact<KIND == BWD_PROP>(M, p.scene, p.E, n_max, p.cobj_in, p.uhat_in,
+                                                        KIND == BWD_STEP ? p.bwd.cobj_st : nullptr, S.wcnt, e, k,
+                                                        base, n, cand, uhn, alist, plist, nullptr);
+    if (threadIdx.x < 64) p.bwd.m_st[item] = m;     // identical stores
     if (m == 0) {
         if (threadIdx.x < 64) {
             p.bwd.alpha_part[item] = 0.0f;
             p.bwd.item_flag[item] = 0;
         }
-        if (KIND != BWD_PROP)
+        if (KIND == BWD_STEP)
             for (int c = threadIdx.x; c < O * 12; c += kWG) p.bwd.pose_part[(size_t)item * O * 12 + c] = 0.0f;
         if (KIND == BWD_PROP)
             for (int i = threadIdx.x; i < n; i += kWG) {
@@ -1094,8 +1120,100 @@ __device__ void process_item_bwd(const BwdParams &p, BwdLds &S, int item, int e,
         __syncthreads();
         return;
     }
-    // dL/du_hat of active nodes starts from their own U (or the given gradient)
-    const float *g0 = KIND == BWD_CONTACT ? p.grad_uhat_in : p.grad_u;
+    // dL/du_hat of active nodes starts from their own U
+    for (int q = threadIdx.x; q < m; q += kWG) {
+        const int j = alist[q];
+        gh[j] = p.grad_u[row + j];
+        gh[n_max + j] = p.grad_u[EN + row + j];
+        gh[2 * n_max + j] = p.grad_u[2 * EN + row + j];
+    }
+    __syncthreads();
+    double dalpha = 0.0;
+    const int np = n - m;
+    if (p.model.mode != ETAC_RESIDUAL_ONLY && np > 0)
+        dalpha = decay_adjoint(p, S.st, e, k, base, m, np, alist, plist, uhn, gh);
+    {
+        double v[12];
+        v[0] = dalpha;
+        for (int c = 1; c < 12; ++c) v[c] = 0.0;
+        wg_sum12(S.dred, v);
+        if (threadIdx.x < 64) p.bwd.alpha_part[item] = (float)v[0];
+    }
+    // hand-over of the active nodes to k_bwd
+    for (int q = threadIdx.x; q < m; q += kWG) {
+        const int j = alist[q];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            p.bwd.gh_st[c * EN + row + j] = gh[c * n_max + j];
+            if (KIND == BWD_STEP) p.bwd.uhat_st[c * EN + row + j] = uhn[c * n_max + j];
+        }
+    }
+    __syncthreads();
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kWG) void k_bwd_decay(BwdParams p) {
+    __shared__ DecayLds S;
+    const int wg = blockIdx.x;
+    const int n_max = p.scr.n_max;
+    float *uhn = p.scr.uhat_node + (size_t)wg * 3 * n_max;
+    float *gh = p.bwd.guhat + (size_t)wg * 3 * n_max;
+    int *alist = p.scr.alist + (size_t)wg * n_max;
+    int *plist = p.scr.plist + (size_t)wg * n_max;
+    for (;;) {
+        const int b0 = next_batch<KIND == BWD_PROP ? CULL_NONE : CULL_OBJECTS>(p.scr.counter + 2, S.batch, p.mesh,
+                                                                              p.scene, p.E, p.n_items, p.batch);
+        if (b0 >= p.n_items) break;
+        if (KIND != BWD_PROP) zero_fill_batch_bwd(p, S.batch, b0);
+        const int nb = uniform(S.batch.n);
+        for (int q = 0; q < nb; ++q) {
+            const int pos = uniform(S.batch.item[q]);
+            const unsigned cand = uniform((unsigned)S.batch.cand[q]);
+            int e, k;
+            queue_item(p.mesh, p.E, pos, e, k);
+            decay_item_bwd<KIND>(p, S, e * p.mesh.K + k, e, k, cand, uhn, gh, alist, plist);
+        }
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned done = atomicAdd(&p.scr.counter[3], 1u);
+        if (done == gridDim.x - 1) {
+            atomicExch(&p.scr.counter[2], 0u);
+            atomicExch(&p.scr.counter[3], 0u);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_bwd: network and contact adjoint
+// ---------------------------------------------------------------------------
+
+// One item (item = e K + k indexes the partials).  Step / propagate adjoint:
+// only items with active nodes reach here; contact comes from the hand-over
+// (step) or the caller (propagate), dL/du_hat of active nodes from the decay
+// kernel.  Contact adjoint: contact is recomputed (cand: candidate objects)
+// and dL/du_hat is the caller's.
+template <int KIND>
+__device__ void process_item_bwd(const BwdParams &p, BwdLds &S, int item, int e, int k, unsigned cand, float *uhn,
+                                 float *gh, int *alist, int *plist, int8_t *wobj) {
+    const MeshDev &M = p.mesh;
+    const int N = M.N, n_max = p.scr.n_max, O = p.scene.O;
+    const size_t EN = (size_t)p.E * N;
+    const int base = M.offset[k];
+    const int n = M.offset[k + 1] - base;
+    const size_t row = (size_t)e * N + base;
+    const int8_t *cin = KIND == BWD_STEP ? p.bwd.cobj_st : p.cobj_in;
+    const float *uin = KIND == BWD_STEP ? p.bwd.uhat_st : p.uhat_in;
+    const int m = contact_and_compact<KIND != BWD_CONTACT>(M, p.scene, p.E, n_max, cin, uin, nullptr, S.wcnt, e, k,
+                                                           base, n, cand, uhn, alist, plist, wobj);
+    if (m == 0) {
+        // contact adjoint only: the other kinds never queue items without contact
+        if (threadIdx.x < 64) p.bwd.item_flag[item] = 0;
+        for (int c = threadIdx.x; c < O * 12; c += kWG) p.bwd.pose_part[(size_t)item * O * 12 + c] = 0.0f;
+        __syncthreads();
+        return;
+    }
+    const float *g0 = KIND == BWD_CONTACT ? p.grad_uhat_in : p.bwd.gh_st;
     for (int q = threadIdx.x; q < m; q += kWG) {
         const int j = alist[q];
         gh[j] = g0[row + j];
@@ -1103,24 +1221,8 @@ __device__ void process_item_bwd(const BwdParams &p, BwdLds &S, int item, int e,
         gh[2 * n_max + j] = g0[2 * EN + row + j];
     }
     __syncthreads();
-    double dalpha = 0.0;
-    if (KIND != BWD_CONTACT) {
-        const int np = n - m;
-        if (p.model.mode != ETAC_RESIDUAL_ONLY && np > 0)
-            dalpha = decay_adjoint(p, S, e, k, base, m, np, alist, plist, uhn, gh);
-        if (uses_residual(p)) residual_adjoint(p, S, e, k, item, base, n, n - m, plist, uhn, wobj, gh);
-    }
-    // dL/dalpha partial of the item
-    {
-        double v[12];
-        v[0] = dalpha;
-        for (int c = 1; c < 12; ++c) v[c] = 0.0;
-        wg_sum12(S, v);
-        if (threadIdx.x < 64) {
-            p.bwd.alpha_part[item] = (float)v[0];
-            p.bwd.item_flag[item] = (KIND != BWD_CONTACT && uses_residual(p)) ? 1 : 0;
-        }
-    }
+    if (KIND != BWD_CONTACT && uses_residual(p)) residual_adjoint(p, S, e, k, item, base, n, n - m, plist, uhn, wobj, gh);
+    if (threadIdx.x < 64) p.bwd.item_flag[item] = (KIND != BWD_CONTACT && uses_residual(p)) ? 1 : 0;
     __syncthreads();
     if (KIND == BWD_PROP) {
         for (int i = threadIdx.x; i < n; i += kWG) {
@@ -1151,10 +1253,10 @@ __global__ __launch_bounds__(kWG) void k_bwd(BwdParams p) {
         __syncthreads();
     }
     for (;;) {
-        const int b0 = next_batch<KIND != BWD_PROP>(p.scr.counter + 2, S.batch, p.mesh, p.scene, p.E, p.n_items,
-                                                     p.batch);
+        const int b0 = next_batch<KIND == BWD_CONTACT ? CULL_OBJECTS : CULL_ACTIVE>(
+            p.scr.counter + 2, S.batch, p.mesh, p.scene, p.E, p.n_items, p.batch, p.bwd.m_st);
         if (b0 >= p.n_items) break;
-        if (KIND != BWD_PROP) zero_fill_batch_bwd(p, S.batch, b0);
+        if (KIND == BWD_CONTACT) zero_fill_batch_bwd(p, S.batch, b0);
         const int nb = uniform(S.batch.n);
         for (int q = 0; q < nb; ++q) {
             const int pos = uniform(S.batch.item[q]);
@@ -1269,11 +1371,20 @@ hipError_t launch_backward(const Plan &pl, const SceneDev *s, const ModelDev &m,
     p.grad_u = grad_u;
     p.grad_uhat_in = nullptr;
     p.grad_uhat_out = grad_uhat;
+    // contact and the decay adjoint, several workgroups per CU
+    const int grid_d = min(p.n_items, pl.cu_count * kDecayWgPerCu);
+    int slot = timer_begin(pl, ETAC_TIMER_BWD_DECAY, st);
+    if (s) hipLaunchKernelGGL(k_bwd_decay<BWD_STEP>, dim3(grid_d), dim3(kWG), 0, st, p);
+    else hipLaunchKernelGGL(k_bwd_decay<BWD_PROP>, dim3(grid_d), dim3(kWG), 0, st, p);
+    hipError_t e = hipGetLastError();
+    timer_end(pl, ETAC_TIMER_BWD_DECAY, slot, st);
+    if (e != hipSuccess) return e;
+    // network and contact adjoint of the contacted items, one workgroup per CU
     const int grid = min(p.n_items, pl.cu_count);
-    int slot = timer_begin(pl, ETAC_TIMER_BACKWARD, st);
+    slot = timer_begin(pl, ETAC_TIMER_BACKWARD, st);
     if (s) hipLaunchKernelGGL(k_bwd<BWD_STEP>, dim3(grid), dim3(kWG), 0, st, p);
     else hipLaunchKernelGGL(k_bwd<BWD_PROP>, dim3(grid), dim3(kWG), 0, st, p);
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     timer_end(pl, ETAC_TIMER_BACKWARD, slot, st);
     if (e != hipSuccess) return e;
     slot = timer_begin(pl, ETAC_TIMER_REDUCE, st);

@@ -212,11 +212,18 @@ __device__ __forceinline__ unsigned long long batch_mask(const ItemBatch &B) {
     return ((unsigned long long)uniform(B.mask_hi) << 32) | (unsigned long long)uniform(B.mask_lo);
 }
 
-// Claim the next batch and cull it (CULL false: every item is live).  Returns
-// the batch's first queue position (>= n_items when the queue is empty).
-template <bool CULL>
+// How a claimed batch is culled.
+enum CullMode {
+    CULL_NONE = 0,      // every item is live (contact results are given)
+    CULL_OBJECTS = 1,   // live if some object's bounding ball may reach the patch
+    CULL_ACTIVE = 2     // live if a previous kernel found active nodes (live[e K + k] > 0)
+};
+
+// Claim the next batch and cull it.  Returns the batch's first queue
+// position (>= n_items when the queue is empty).
+template <int CULL>
 __device__ int next_batch(unsigned *counter, ItemBatch &B, const MeshDev &M, const SceneDev &Sc, int E,
-                          int n_items, int batch) {
+                          int n_items, int batch, const int *live = nullptr) {
     __syncthreads();   // every wave is done with the previous batch
     if (threadIdx.x < 64) {
         const int lane = lane_id();
@@ -226,10 +233,14 @@ __device__ int next_batch(unsigned *counter, ItemBatch &B, const MeshDev &M, con
         const int q = b0 + lane;
         unsigned cand = 0;
         if (lane < batch && q < n_items) {
-            if (CULL) {
+            if (CULL == CULL_OBJECTS) {
                 int e, k;
                 queue_item(M, E, q, e, k);
                 cand = cull_objects(Sc, M, e, k);
+            } else if (CULL == CULL_ACTIVE) {
+                int e, k;
+                queue_item(M, E, q, e, k);
+                cand = live[(size_t)e * M.K + k] > 0 ? 0xffu : 0u;
             } else {
                 cand = 0xffu;
             }

@@ -415,7 +415,8 @@ __global__ __launch_bounds__(kWG) void k_step(StepParams p) {
         __syncthreads();
     }
     for (;;) {
-        const int b0 = next_batch<!FROM_INPUT>(p.scr.counter, S.batch, p.mesh, p.scene, p.E, p.n_items, p.batch);
+        const int b0 = next_batch<FROM_INPUT ? CULL_NONE : CULL_OBJECTS>(p.scr.counter, S.batch, p.mesh, p.scene, p.E,
+                                                                        p.n_items, p.batch);
         if (b0 >= p.n_items) break;
         if (!FROM_INPUT) zero_fill_batch(p, S.batch, b0);
         const int nb = uniform(S.batch.n);

@@ -13,6 +13,7 @@ constexpr int kWaves = kWG / 64;
 constexpr int kMaxPatches = 1024;  // per-patch counters of the contact kernel live in LDS
 constexpr int kDefaultWgPerCu = 2;
 constexpr int kDefaultBatch = 4;   // work-queue positions claimed per atomic
+constexpr int kDecayWgPerCu = 3;   // workgroups per CU of the decay-adjoint kernel
 
 // Device view of the plan's mesh copy.
 struct MeshDev {
@@ -61,6 +62,11 @@ struct BwdScratch {
     int *item_list;        // [E*K]            compacted list of flagged items
     int *n_list;           // [1]
     double *phi_seg;       // [kPhiSegs][17411] segment sums of the parameter reduction
+    // hand-over from the decay kernel to the network / contact kernel
+    int8_t *cobj_st;       // [E][N]    contact winners of every candidate item (step adjoint)
+    float *uhat_st;        // [3][E][N] u_hat of active nodes (step adjoint)
+    float *gh_st;          // [3][E][N] dL/du_hat of active nodes after the decay adjoint
+    int *m_st;             // [E*K]     active-node count of every item
 };
 
 // Event pairs bracketing kernel launches (etac_plan_set_timing).
