@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--envs", type=int, default=4096)
+    ap.add_argument("--workload", choices=["hand", "hires"], default="hand",
+                    help="hand: 16-patch hands (the metric's workload); hires: four 128x128 pads per env")
     ap.add_argument("--mode", choices=["full", "decay", "residual"], default="full")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="time budget of the CPU oracle baseline (envs are added in blocks until it is spent)")
@@ -140,25 +142,32 @@ def work_counts(mesh, n_active):
 
 
 def algorithmic_work(kernel, counts, E, N, K, O, mode):
-    """Algorithmic work of one launch of the dominant kernel: FP32-equivalent
-    network flops (2 per multiply-add), decay-pair flops and the HBM bytes
-    that must move (inputs read once, outputs written once).  The adjoint
-    reads dL/dU only on patches in contact (elsewhere U = 0 whatever the
-    inputs) and writes one partial per item of alpha, the poses and, on
-    contacted items, the network parameters."""
+    """Algorithmic work of one launch of a kernel: FP32-equivalent network
+    flops (2 per multiply-add), decay-pair flops and the HBM bytes that must
+    move (inputs read once, outputs written once).  The adjoint reads dL/dU
+    only on patches in contact (elsewhere U = 0 whatever the inputs)."""
     nodes = float(E) * N
     items = counts["contacted_items"]
     decay = mode != 2     # not residual-only
     net = mode != 1       # not decay-only
+    if kernel == "k_contact":
+        # contact winner (1 B) and u_hat (12 B) per node, active count per item
+        return dict(mfma_flop=0.0, valu_flop=0.0, hbm_bytes=13.0 * nodes + 4.0 * E * K)
     if kernel == "k_step":
         return dict(mfma_flop=counts["mlp_flop"] if net else 0.0,
                     valu_flop=PAIR_FLOP * counts["pairs"] if decay else 0.0,
                     hbm_bytes=13.0 * nodes + 4.0 * E * K)
-    # adjoint: the network's forward is recomputed (no state is kept from the
+    if kernel == "k_bwd_decay":
+        # dL/dU of contacted patches in; alpha partials, active counts and, for
+        # contacted items, winners (1 B per node) and u_hat, dL/du_hat (24 B per
+        # active node) handed to k_bwd
+        return dict(mfma_flop=0.0, valu_flop=PAIR_FLOP_BWD * counts["pairs"] if decay else 0.0,
+                    hbm_bytes=12.0 * counts["contacted_nodes"] + 8.0 * E * K
+                    + counts["contacted_nodes"] + 24.0 * counts["active"])
+    # k_bwd: the network's forward is recomputed (no state is kept from the
     # forward call) and both adjoint products run: 3x the forward flops
-    return dict(mfma_flop=3.0 * counts["mlp_flop"] if net else 0.0,
-                valu_flop=PAIR_FLOP_BWD * counts["pairs"] if decay else 0.0,
-                hbm_bytes=12.0 * counts["contacted_nodes"] + float(E) * K * (4.0 + 48.0 * O)
+    return dict(mfma_flop=3.0 * counts["mlp_flop"] if net else 0.0, valu_flop=0.0,
+                hbm_bytes=counts["contacted_nodes"] + 24.0 * counts["active"] + 48.0 * O * items
                 + (4.0 * PHI_SIZE * items if net else 0.0))
 
 
@@ -172,10 +181,11 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary, if it was taken on the current kernel sources."""
-    path = os.path.join(PROFILES, f"{kernel}_hand4096_hbm_traffic.txt")
+    tag = "hand4096" if workload == "hand" else "hires4096"
+    path = os.path.join(PROFILES, f"{kernel}_{tag}_hbm_traffic.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -191,7 +201,7 @@ def measured_traffic(kernel):
         return None
 
 
-def roofline_of(kernel, avg_ms, work):
+def roofline_of(kernel, avg_ms, work, workload="hand"):
     """Roofline of the dominant kernel: the resource whose lower-bound time
     (work / peak) is largest names the bound; achieved = algorithmic work of
     one launch / its average device time."""
@@ -206,7 +216,7 @@ def roofline_of(kernel, avg_ms, work):
         achieved, peak, unit = work["valu_flop"] / t / 1e12, FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
     else:
         achieved, peak, unit = work["hbm_bytes"] / t / 1e9, HBM_PEAK_GBS, "GB/s"
-    traffic = measured_traffic(kernel)
+    traffic = measured_traffic(kernel, workload)
     return {"bound": bound, "kernel": kernel, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
             "frac": round(achieved / peak, 5), "traffic": traffic, "avg_ms": round(avg_ms, 4),
             "mfma_passes": MFMA_PASSES if bound == "mfma" else None,
@@ -227,7 +237,10 @@ def main():
     mode = {"full": scenes.MODE_FULL, "decay": scenes.MODE_DECAY_ONLY, "residual": scenes.MODE_RESIDUAL_ONLY}[args.mode]
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
-    mesh, scene, model = scenes.config2(n_envs=args.envs, mode=mode)
+    if args.workload == "hand":
+        mesh, scene, model = scenes.config2(n_envs=args.envs, mode=mode)
+    else:
+        mesh, scene, model = scenes.config4(n_envs=args.envs, mode=mode)
     E, O, N, K = scene.n_envs, scene.max_obj, mesh.n_nodes, mesh.n_patches
 
     def t(a, dtype):
@@ -307,6 +320,19 @@ def main():
     torch.cuda.synchronize()
     fwd_only_ms = (time.perf_counter() - t1) * 1e3 / args.steps
 
+    # contact pass alone (etac_contact: winners, u_hat and active counts)
+    uhat = torch.empty((3, E, N), dtype=torch.float32, device=dev)
+    for _ in range(2):
+        _native.etac_contact(plan, sc, cobj, uhat, na)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    for _ in range(args.steps):
+        _native.etac_contact(plan, sc, cobj, uhat, na)
+    torch.cuda.synchronize()
+    n_c, ms_c = plan.kernel_time(_native.ETAC_TIMER_CONTACT)
+    plan.set_timing(False)
+    kernel_avg["k_contact"] = ms_c / n_c
+
     nodes = float(E) * N
     value = nodes / (step_ms * 1e-3)
     fwd_rate = nodes / (fwd_only_ms * 1e-3)
@@ -315,13 +341,16 @@ def main():
     hbm_fwd_gbs = 13.0 * nodes / (fwd_only_ms * 1e-3) / 1e9
     hbm_step_gbs = 25.0 * nodes / (step_ms * 1e-3) / 1e9
 
-    roofline = None
-    if kernel_avg:
-        kernel = max(("k_step", "k_bwd"), key=lambda k: kernel_avg[k])
-        roofline = roofline_of(kernel, kernel_avg[kernel], algorithmic_work(kernel, counts, E, N, K, O, mode))
+    roofline, by_kernel = None, {}
+    if "k_step" in kernel_avg:
+        for kern in ("k_contact", "k_step", "k_bwd_decay", "k_bwd"):
+            by_kernel[kern] = roofline_of(kern, kernel_avg[kern], algorithmic_work(kern, counts, E, N, K, O, mode),
+                                          args.workload)
+        kernel = max(("k_step", "k_bwd_decay", "k_bwd"), key=lambda k: kernel_avg[k])
+        roofline = dict(by_kernel[kernel])
 
     line = {
-        "metric": "sensor node-updates/s at 4096 envs (fwd+bwd step)",
+        "metric": "sensor node-updates/s at 4096 envs, fwd and fwd+bwd; % of HBM roofline",
         "value": value,
         "unit": "node-updates/s",
         "n_gpus": 1,
@@ -333,8 +362,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{E} envs x 16-patch hand ({N} nodes/env, patches 64-1024 nodes), "
-                               f"1-3 sphere/box/capsule per env, mode {args.mode}",
+        "config": {"workload": (f"{E} envs x 16-patch hand ({N} nodes/env, patches 64-1024 nodes), "
+                                f"1-3 sphere/box/capsule per env, mode {args.mode}") if args.workload == "hand" else
+                               (f"{E} envs x 4 pads of 128x128 nodes at 0.125 mm ({N} nodes/env), one sphere or box "
+                                f"per pad, mode {args.mode}"),
                    "envs": E, "nodes_per_env": N, "patches": K, "graph": bool(args.graph)},
         "fwd_only": {"value": fwd_rate, "unit": "node-updates/s", "ms_per_step": fwd_only_ms,
                      "hbm_gbs": hbm_fwd_gbs, "hbm_frac": hbm_fwd_gbs / HBM_PEAK_GBS},
@@ -343,6 +374,9 @@ def main():
                       **{f"{k}_avg": v for k, v in kernel_avg.items()}},
         "work": counts,
         "roofline": roofline,
+        "roofline_by_kernel": by_kernel,
+        "contact_only": {"value": nodes / (kernel_avg.get("k_contact", float("nan")) * 1e-3), "unit": "node-updates/s",
+                         "ms": kernel_avg.get("k_contact")},
     }
 
     if not args.no_cpu_baseline:
@@ -350,7 +384,7 @@ def main():
         # the time budget is spent
         import oracle
         gu_host = grad_u.cpu().numpy().astype(np.float64)
-        ne, dt, block = 0, 0.0, 256
+        ne, dt, block = 0, 0.0, (256 if N < 20000 else 1)
         while ne < E and dt < args.cpu_seconds:
             envs = np.arange(ne, min(E, ne + block))
             sub = scene.select(envs)

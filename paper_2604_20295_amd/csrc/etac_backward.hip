@@ -780,27 +780,42 @@ __device__ void contact_adjoint_node(int type, const float *sh, const float *Rf,
     }
 }
 
-// Pose partials of one item: for every object, the sum over its active nodes.
+// Pose partials of one item: for every object, the sum over its active
+// nodes.  Objects that win no active node of the item get exact zeros
+// without a reduction (usually one object reaches a patch).
 __device__ void contact_adjoint_item(const BwdParams &p, BwdLds &S, int e, int item, int base, int m,
                                      const int *alist, const int8_t *wobj, const float *gh) {
     const MeshDev &M = p.mesh;
     const int N = M.N, n_max = p.scr.n_max, O = p.scene.O;
     const int no = min(p.scene.n_obj[e], O);
     float *out = p.bwd.pose_part + (size_t)item * O * 12;
+    // objects present among the active nodes (an OR, independent of order)
+    int mask = 0;
+    for (int q = threadIdx.x; q < m; q += kWG) mask |= 1 << wobj[alist[q]];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) mask |= __shfl_xor(mask, off);
+    S.ired[threadIdx.x >> 6][lane_id()] = mask;     // identical in every lane of the wave
+    __syncthreads();
+    int present = 0;
+    for (int w = 0; w < kWaves; ++w) present |= S.ired[w][0];
+    present = uniform(present);
+    __syncthreads();
     for (int o = 0; o < O; ++o) {
+        if (!((present >> o) & 1) || o >= no) {
+            if (threadIdx.x < 64 && lane_id() < 12) out[o * 12 + lane_id()] = 0.0f;
+            continue;
+        }
         double acc[12];
         for (int c = 0; c < 12; ++c) acc[c] = 0.0;
-        if (o < no) {
-            const size_t eo = (size_t)e * O + o;
-            const int ty = p.scene.type[eo];
-            const float *sh = p.scene.shape + 4 * eo, *R = p.scene.rot + 9 * eo, *t = p.scene.trans + 3 * eo;
-            for (int q = threadIdx.x; q < m; q += kWG) {
-                const int j = alist[q];
-                if (wobj[j] != o) continue;
-                const int gj = base + j;
-                const double g[3] = {gh[j], gh[n_max + j], gh[2 * n_max + j]};
-                contact_adjoint_node(ty, sh, R, t, M.pos[gj], M.pos[N + gj], M.pos[2 * N + gj], g, acc);
-            }
+        const size_t eo = (size_t)e * O + o;
+        const int ty = p.scene.type[eo];
+        const float *sh = p.scene.shape + 4 * eo, *R = p.scene.rot + 9 * eo, *t = p.scene.trans + 3 * eo;
+        for (int q = threadIdx.x; q < m; q += kWG) {
+            const int j = alist[q];
+            if (wobj[j] != o) continue;
+            const int gj = base + j;
+            const double g[3] = {gh[j], gh[n_max + j], gh[2 * n_max + j]};
+            contact_adjoint_node(ty, sh, R, t, M.pos[gj], M.pos[N + gj], M.pos[2 * N + gj], g, acc);
         }
         wg_sum12(S.dred, acc);
         if (threadIdx.x < 12) out[o * 12 + threadIdx.x] = (float)acc[threadIdx.x];
