@@ -30,6 +30,7 @@ ENC_MAC, DEC_MAC, GLOBAL_MAC = 9 * 64 + 64 * 64, 64 * 128 + 64 * 3, 2 * 64 * 64
 PAIR_FLOP = 20                 # decay pair: 3 sub, 5 for the squared distance, sqrt, scale, exp, 6 for w*u
 PAIR_FLOP_BWD = 30             # adjoint pair: the above without u, plus d*w and the g.u_hat dot product
 PHI_SIZE = 17411
+TRANS_PAIR_CEILING = 4.9e12    # pairs/s: two quarter-rate transcendentals per pair (256 CU x 64 lanes x 2.4 GHz / 4 / 2)
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -332,6 +333,18 @@ def main():
     n_c, ms_c = plan.kernel_time(_native.ETAC_TIMER_CONTACT)
     plan.set_timing(False)
     kernel_avg["k_contact"] = ms_c / n_c
+    # plain forward: contact, then propagation from the stored contact (two launches)
+    uo = torch.empty_like(u)
+    for _ in range(2):
+        _native.etac_contact(plan, sc, cobj, uhat, na)
+        _native.etac_propagate(plan, md, E, cobj, uhat, uo)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        _native.etac_contact(plan, sc, cobj, uhat, na)
+        _native.etac_propagate(plan, md, E, cobj, uhat, uo)
+    torch.cuda.synchronize()
+    plain_fwd_ms = (time.perf_counter() - t2) * 1e3 / args.steps
 
     nodes = float(E) * N
     value = nodes / (step_ms * 1e-3)
@@ -377,6 +390,12 @@ def main():
         "roofline_by_kernel": by_kernel,
         "contact_only": {"value": nodes / (kernel_avg.get("k_contact", float("nan")) * 1e-3), "unit": "node-updates/s",
                          "ms": kernel_avg.get("k_contact")},
+        "plain_forward": {"ms_per_step": plain_fwd_ms, "value": nodes / (plain_fwd_ms * 1e-3),
+                          "unit": "node-updates/s", "what": "etac_contact then etac_propagate (two launches)",
+                          "fwd_bwd_over_plain_forward": step_ms / plain_fwd_ms},
+        "decay_pairs_per_s": {"k_step": counts["pairs"] / (kernel_avg.get("k_step", float("nan")) * 1e-3),
+                              "k_bwd_decay": counts["pairs"] / (kernel_avg.get("k_bwd_decay", float("nan")) * 1e-3),
+                              "transcendental_ceiling": TRANS_PAIR_CEILING},
     }
 
     if not args.no_cpu_baseline:
