@@ -24,7 +24,7 @@
 
 namespace etac {
 
-constexpr int kBChunk = 512;   // passive nodes staged per pass of the decay adjoint
+constexpr int kBChunk = 1024;  // passive nodes staged per pass of the decay adjoint
 constexpr int kPhiSegs = 64;   // segments of the parameter-gradient reduction
 
 enum BwdKind { BWD_STEP = 0, BWD_PROP = 1, BWD_CONTACT = 2 };
@@ -50,6 +50,7 @@ constexpr int kRedRegs = 32;   // accumulator registers per lane summed per pass
 struct DecayStage {
     float4 a[kBChunk];            // (px, py, pz, gx) of staged passive nodes
     float2 b[kBChunk];            // (gy, gz)
+    float4 bb[2 * (kBChunk / 32)]; // boxes of the blocks of 32 staged passive nodes
     double part[kWG][12];         // per-thread partial dL/du_hat of its (up to four) active nodes
 };
 
@@ -558,6 +559,27 @@ __device__ __forceinline__ bool uses_residual(const BwdParams &p) {
     return p.model.mode != ETAC_DECAY_ONLY;
 }
 
+// Stage passive nodes plist[c0 .. c0 + cnt) (position, dL/dU) and, with the
+// cutoff on, their block boxes.  Whole workgroup, barriers included.
+__device__ __forceinline__ void stage_passive_chunk(const BwdParams &p, DecayStage &st, int base, size_t row,
+                                                    const int *plist, int c0, int cnt, bool boxes) {
+    const MeshDev &M = p.mesh;
+    const int N = M.N;
+    const size_t EN = (size_t)p.E * N;
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt; t += kWG) {
+        const int i = plist[c0 + t];
+        const int gi = base + i;
+        st.a[t] = make_float4(M.pos[gi], M.pos[N + gi], M.pos[2 * N + gi], p.grad_u[row + i]);
+        st.b[t] = make_float2(p.grad_u[EN + row + i], p.grad_u[2 * EN + row + i]);
+    }
+    __syncthreads();
+    if (boxes) {
+        block_boxes(st.a, cnt, st.bb);
+        __syncthreads();
+    }
+}
+
 // Eq. 1 adjoint of one item.  Pairs (active j, passive i) are split over a
 // grid of SLOTS active slots x (kWG / SLOTS) passive segments: every thread
 // owns A active nodes per pass and one segment of each staged chunk of
@@ -569,11 +591,15 @@ __device__ double decay_adjoint_grid(const BwdParams &p, DecayStage &st, int e, 
                                      const int *alist, const int *plist, const float *uhn, float *gh) {
     const MeshDev &M = p.mesh;
     const int N = M.N, n_max = p.scr.n_max;
-    const size_t EN = (size_t)p.E * N;
     const size_t row = (size_t)e * N + base;
     const float nbeta = (float)(-(double)p.model.alpha[k] * 1.4426950408889634);
+    float cut2 = cutoff_d2(p.model.alpha[k]);
+    if (!cutoff_useful(M, k, cut2)) cut2 = -1.0f;     // off: no boxes, no tests
     constexpr int nseg = kWG / SLOTS;
     const int slot = threadIdx.x % SLOTS, seg = threadIdx.x / SLOTS;
+    // a passive set that fits one chunk is staged once for every pass
+    const bool one_chunk = np <= kBChunk;
+    if (one_chunk) stage_passive_chunk(p, st, base, row, plist, 0, np, cut2 >= 0.0f);
     double dalpha = 0.0;
     for (int ab = 0; ab < m; ab += A * SLOTS) {
         bool v[A];
@@ -593,18 +619,24 @@ __device__ double decay_adjoint_grid(const BwdParams &p, DecayStage &st, int e, 
         }
         for (int c0 = 0; c0 < np; c0 += kBChunk) {
             const int cnt = min(kBChunk, np - c0);
-            __syncthreads();
-            for (int t = threadIdx.x; t < cnt; t += kWG) {
-                const int i = plist[c0 + t];
-                const int gi = base + i;
-                st.a[t] = make_float4(M.pos[gi], M.pos[N + gi], M.pos[2 * N + gi], p.grad_u[row + i]);
-                st.b[t] = make_float2(p.grad_u[EN + row + i], p.grad_u[2 * EN + row + i]);
-            }
-            __syncthreads();
+            if (!one_chunk) stage_passive_chunk(p, st, base, row, plist, c0, cnt, cut2 >= 0.0f);
             const int per = (cnt + nseg - 1) / nseg;
             const int lo = seg * per, hi = min(cnt, lo + per);
             for (int i0 = lo; i0 < hi; i0 += 32) {
                 const int i1 = min(hi, i0 + 32);
+                if (cut2 >= 0.0f) {   // uniform: the cutoff is on for this item
+                    // skip a run no valid active node of the wave reaches within the cutoff
+                    // (wave-uniform; the run overlaps boxes b0 and b1)
+                    const int b0 = i0 >> 5, b1 = (i1 - 1) >> 5;
+                    const float4 lo0 = st.bb[2 * b0], hi0 = st.bb[2 * b0 + 1];
+                    const float4 lo1 = st.bb[2 * b1], hi1 = st.bb[2 * b1 + 1];
+                    bool need = false;
+#pragma unroll
+                    for (int a = 0; a < A; ++a)
+                        need = need || (v[a] && (box_d2(lo0, hi0, px[a], py[a], pz[a]) < cut2 ||
+                                                 box_d2(lo1, hi1, px[a], py[a], pz[a]) < cut2));
+                    if (__ballot(need) == 0ull) continue;
+                }
                 float sx[A], sy[A], sz[A], q[A];
 #pragma unroll
                 for (int a = 0; a < A; ++a) sx[a] = sy[a] = sz[a] = q[a] = 0.0f;

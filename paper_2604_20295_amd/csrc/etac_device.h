@@ -183,6 +183,63 @@ __device__ __forceinline__ unsigned lanes_below(unsigned long long mask) {
 }
 
 // ---------------------------------------------------------------------------
+// certified cutoff of the Eq. 1 pair sums
+//
+// Staged points are grouped in blocks of 32 consecutive list entries (node
+// order, so spatially compact strips) with a bounding box each.  A wave skips
+// a block when none of its own nodes lies within D of the box, where
+// exp(-alpha D) = 2^-50: every skipped weight is below 2^-50, so a skipped
+// block changes a sum by less than 2^-50 times the sum of its |terms|, far
+// below FP32 rounding of the sums themselves.
+// ---------------------------------------------------------------------------
+constexpr double kCutLog2 = 50.0;
+
+// D^2 for the item's alpha, rounded up (no cutoff when alpha <= 0).
+__device__ __forceinline__ float cutoff_d2(float alpha) {
+    if (!(alpha > 0.0f)) return __builtin_inff();
+    const double d = kCutLog2 / ((double)alpha * 1.4426950408889634);
+    return (float)(d * d * (1.0 + 1e-6));
+}
+
+// Boxes of the blocks of 32 among staged points pts[0 .. cnt): bb[2 b] =
+// lower corner, bb[2 b + 1] = upper corner.  Thread t loads point t and each
+// aligned group of 32 lanes reduces by shuffles.  The caller brackets it with
+// barriers.
+__device__ __forceinline__ void block_boxes(const float4 *pts, int cnt, float4 *bb) {
+    for (int t0 = 0; t0 < cnt; t0 += kWG) {
+        const int t = t0 + threadIdx.x;
+        const bool ok = t < cnt;
+        const float4 q = pts[ok ? t : 0];
+        float lx = ok ? q.x : 3.0e38f, ly = ok ? q.y : 3.0e38f, lz = ok ? q.z : 3.0e38f;
+        float hx = ok ? q.x : -3.0e38f, hy = ok ? q.y : -3.0e38f, hz = ok ? q.z : -3.0e38f;
+#pragma unroll
+        for (int off = 16; off >= 1; off >>= 1) {
+            lx = fminf(lx, __shfl_xor(lx, off)); ly = fminf(ly, __shfl_xor(ly, off)); lz = fminf(lz, __shfl_xor(lz, off));
+            hx = fmaxf(hx, __shfl_xor(hx, off)); hy = fmaxf(hy, __shfl_xor(hy, off)); hz = fmaxf(hz, __shfl_xor(hz, off));
+        }
+        if ((t & 31) == 0 && ok) {
+            bb[2 * (t >> 5)] = make_float4(lx, ly, lz, 0.0f);
+            bb[2 * (t >> 5) + 1] = make_float4(hx, hy, hz, 0.0f);
+        }
+    }
+}
+
+// Whether the cutoff can skip anything in patch k: only if the patch is wider
+// than D (its bounding sphere's diameter exceeds the cutoff radius).
+__device__ __forceinline__ bool cutoff_useful(const MeshDev &M, int k, float cut2) {
+    const float d = 2.0f * M.bound[k].w;
+    return d * d > cut2;
+}
+
+// Squared distance from (x, y, z) to the box [lo, hi].
+__device__ __forceinline__ float box_d2(const float4 &lo, const float4 &hi, float x, float y, float z) {
+    const float dx = fmaxf(fmaxf(lo.x - x, x - hi.x), 0.0f);
+    const float dy = fmaxf(fmaxf(lo.y - y, y - hi.y), 0.0f);
+    const float dz = fmaxf(fmaxf(lo.z - z, z - hi.z), 0.0f);
+    return dx * dx + dy * dy + dz * dz;
+}
+
+// ---------------------------------------------------------------------------
 // batched work queue
 //
 // The persistent kernels claim `batch` (1 .. kBatch) consecutive queue

@@ -21,6 +21,19 @@ struct ContactParams {
     int32_t *n_active; // [E][K]
 };
 
+// Contact of one node of env e; returns the winner and adds it to the patch count.
+__device__ __forceinline__ int contact_one(const ContactParams &p, int e, int i, float &u0, float &u1, float &u2,
+                                           int *cnt) {
+    const MeshDev &M = p.mesh;
+    const int N = M.N;
+    const int best = contact_node(p.scene, e, 0xffu, M.pos[i], M.pos[N + i], M.pos[2 * N + i], M.nrm[i],
+                                  M.nrm[N + i], M.nrm[2 * N + i], u0, u1, u2);
+    if (best >= 0) atomicAdd(&cnt[M.node_patch[i]], 1);
+    return best;
+}
+
+// One workgroup per env; consecutive threads take consecutive nodes, so every
+// store of a wave is one contiguous run.
 __global__ __launch_bounds__(kWG) void k_contact(ContactParams p) {
     __shared__ int cnt[kMaxPatches];
     const int e = blockIdx.x;
@@ -29,19 +42,16 @@ __global__ __launch_bounds__(kWG) void k_contact(ContactParams p) {
     const size_t EN = (size_t)p.scene.E * N;
     for (int k = threadIdx.x; k < K; k += kWG) cnt[k] = 0;
     __syncthreads();
-    const unsigned all = 0xffu;
+    const size_t row = (size_t)e * N;
     for (int i = threadIdx.x; i < N; i += kWG) {
         float u0, u1, u2;
-        const int best = contact_node(p.scene, e, all, M.pos[i], M.pos[N + i], M.pos[2 * N + i], M.nrm[i],
-                                      M.nrm[N + i], M.nrm[2 * N + i], u0, u1, u2);
-        const size_t en = (size_t)e * N + i;
-        p.cobj[en] = (int8_t)best;
+        const int best = contact_one(p, e, i, u0, u1, u2, cnt);
+        p.cobj[row + i] = (int8_t)best;
         if (p.uhat) {
-            p.uhat[en] = u0;
-            p.uhat[EN + en] = u1;
-            p.uhat[2 * EN + en] = u2;
+            p.uhat[row + i] = u0;
+            p.uhat[EN + row + i] = u1;
+            p.uhat[2 * EN + row + i] = u2;
         }
-        if (best >= 0) atomicAdd(&cnt[M.node_patch[i]], 1);
     }
     __syncthreads();
     for (int k = threadIdx.x; k < K; k += kWG) p.n_active[(size_t)e * K + k] = cnt[k];
@@ -242,11 +252,26 @@ __device__ __forceinline__ void stage_active(const StepParams &p, StepLds &S, in
 // Eq. 1 over staged active nodes [lo, hi) for P passive nodes per thread.
 // FP32 terms are summed in blocks of 32 and the block sums are accumulated
 // in FP64.
+// Runs of 32 staged actives that no valid passive node of the wave can reach
+// within the cutoff are skipped (a run overlaps at most two boxes); cut2 < 0
+// turns the cutoff off.
 template <int P>
-__device__ __forceinline__ void decay_range(const StepLds &S, int lo, int hi, float nbeta, const float (&px)[P],
+__device__ __forceinline__ void decay_range(const StepLds &S, const float4 *bb, float cut2, int lo, int hi,
+                                            float nbeta, const bool (&v)[P], const float (&px)[P],
                                             const float (&py)[P], const float (&pz)[P], double (&acc)[P][3]) {
     for (int j0 = lo; j0 < hi; j0 += 32) {
         const int j1 = min(hi, j0 + 32);
+        if (cut2 >= 0.0f) {   // uniform: the cutoff is on for this item
+            // [j0, j1) overlaps boxes b0 and b1 (equal when aligned)
+            const int b0 = j0 >> 5, b1 = (j1 - 1) >> 5;
+            const float4 lo0 = bb[2 * b0], hi0 = bb[2 * b0 + 1], lo1 = bb[2 * b1], hi1 = bb[2 * b1 + 1];
+            bool need = false;
+#pragma unroll
+            for (int a = 0; a < P; ++a)
+                need = need || (v[a] && (box_d2(lo0, hi0, px[a], py[a], pz[a]) < cut2 ||
+                                         box_d2(lo1, hi1, px[a], py[a], pz[a]) < cut2));
+            if (__ballot(need) == 0ull) continue;   // wave-uniform
+        }
         float sx[P], sy[P], sz[P];
 #pragma unroll
         for (int a = 0; a < P; ++a) sx[a] = sy[a] = sz[a] = 0.0f;
@@ -274,13 +299,14 @@ __device__ __forceinline__ void decay_range(const StepLds &S, int lo, int hi, fl
 template <int SLOTS, int P>
 __device__ void decay_item(const StepParams &p, StepLds &S, int base, int m, int np, const int *alist,
                            const int *plist, const float *uhn, const float *resid, bool use_dec, bool use_res,
-                           float nbeta, size_t row) {
+                           float nbeta, float cut2, size_t row) {
     const MeshDev &M = p.mesh;
     const int N = M.N, n_max = p.scr.n_max;
     const size_t EN = (size_t)p.E * N;
     constexpr int nseg = kWG / SLOTS;
     const int slot = threadIdx.x % SLOTS, seg = threadIdx.x / SLOTS;
     const bool one_chunk = m <= kChunk;
+    const float4 *bb = reinterpret_cast<const float4 *>(&S.net.part[0][0]);   // block boxes (free during the decay)
     for (int pb = 0; pb < np; pb += P * SLOTS) {
         bool v[P];
         int ii[P];
@@ -298,15 +324,19 @@ __device__ void decay_item(const StepParams &p, StepLds &S, int base, int m, int
         if (use_dec) {
             if (one_chunk) {
                 const int per = (m + nseg - 1) / nseg, lo = seg * per;
-                decay_range<P>(S, lo, min(m, lo + per), nbeta, px, py, pz, acc);
+                decay_range<P>(S, bb, cut2, lo, min(m, lo + per), nbeta, v, px, py, pz, acc);
             } else {
                 for (int c0 = 0; c0 < m; c0 += kChunk) {
                     const int cnt = min(kChunk, m - c0);
                     __syncthreads();
                     stage_active(p, S, base, alist, uhn, c0, cnt);
                     __syncthreads();
+                    if (cut2 >= 0.0f) {
+                        block_boxes(S.act_a, cnt, reinterpret_cast<float4 *>(&S.net.part[0][0]));
+                        __syncthreads();
+                    }
                     const int per = (cnt + nseg - 1) / nseg, lo = seg * per;
-                    decay_range<P>(S, lo, min(cnt, lo + per), nbeta, px, py, pz, acc);
+                    decay_range<P>(S, bb, cut2, lo, min(cnt, lo + per), nbeta, v, px, py, pz, acc);
                 }
             }
             if (nseg > 1) {
@@ -384,19 +414,25 @@ __device__ void process_item(const StepParams &p, StepLds &S, int e, int k, unsi
     if (use_res) residual_item(p, S, k, base, n, uhn, plist, np, resid);
     // exp(-alpha d) = exp2(-alpha log2(e) d)
     const float nbeta = (float)(-(double)p.model.alpha[k] * 1.4426950408889634);
+    float cut2 = cutoff_d2(p.model.alpha[k]);
+    if (!cutoff_useful(M, k, cut2)) cut2 = -1.0f;     // off: no boxes, no tests
     if (use_dec && m <= kChunk) {
         stage_active(p, S, base, alist, uhn, 0, m);
         __syncthreads();
+        if (cut2 >= 0.0f) {
+            block_boxes(S.act_a, m, reinterpret_cast<float4 *>(&S.net.part[0][0]));
+            __syncthreads();
+        }
     }
     // with the decay off (residual only) every shape does the same work
     const int shape = use_dec ? uniform(decay_grid_shape(np, m)) : 5;
     switch (shape) {
-        case 0: decay_item<64, 1>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, nbeta, row); break;
-        case 1: decay_item<128, 1>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, nbeta, row); break;
-        case 2: decay_item<256, 1>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, nbeta, row); break;
-        case 3: decay_item<64, 2>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, nbeta, row); break;
-        case 4: decay_item<128, 2>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, nbeta, row); break;
-        default: decay_item<256, 2>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, nbeta, row); break;
+        case 0: decay_item<64, 1>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, nbeta, cut2, row); break;
+        case 1: decay_item<128, 1>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, nbeta, cut2, row); break;
+        case 2: decay_item<256, 1>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, nbeta, cut2, row); break;
+        case 3: decay_item<64, 2>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, nbeta, cut2, row); break;
+        case 4: decay_item<128, 2>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, nbeta, cut2, row); break;
+        default: decay_item<256, 2>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, nbeta, cut2, row); break;
     }
     __syncthreads();
 }

@@ -208,3 +208,28 @@ def test_hires_pads_full_size_sampled(oracle_lib):
     err = max_err(u[:, envs], ref["u"])
     log(f"[gpu]   sampled max|dU| = {err:.3e}")
     assert err <= TOL_U
+
+
+def test_contact_pass_ragged_node_count(oracle_lib):
+    # N not a multiple of 4: the contact kernel's scalar store path
+    mesh = _ragged_mesh()
+    assert mesh.n_nodes % 4 != 0
+    E = 6
+    scene = scenes._empty_scene(E, 2)
+    rng = np.random.default_rng(5)
+    for e in range(E):
+        scene.n_obj[e] = 2
+        for o in range(2):
+            k = (e + 2 * o) % mesh.n_patches
+            c = mesh.origin[k].astype(np.float64)
+            r = rng.uniform(3.0, 9.0)
+            scene.type[e, o] = SPHERE
+            scene.shape[e, o, 0] = r
+            scene.trans[e, o] = c + np.array([rng.uniform(-2, 2), rng.uniform(-2, 2), r - rng.uniform(0.5, 3.0)])
+    plan = make_plan(mesh, E, 2)
+    log("[gpu] contact ragged N")
+    cobj, uhat, na = gpu_contact(plan, scene)
+    rc, ru, rn = oracle_lib.contact(mesh, scene)
+    assert np.array_equal(cobj, rc) and np.array_equal(na, rn)
+    assert max_err(uhat, ru) <= 1e-6
+    assert int(na.sum()) > 0
