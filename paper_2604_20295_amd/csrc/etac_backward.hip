@@ -925,20 +925,29 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
         __syncthreads();
         stage_nodes(M, k, base, nullptr, c0, cnt, uhn, n_max, 0, S.u.xs);
         __syncthreads();
+        // two tiles per wave step (t and t + kWaves); the second may be padding
         const int ntl = (cnt + 15) >> 4;
-        for (int t = wave; t < ntl; t += kWaves) {
-            const int lj = t * 16 + (lane & 15);
-            const bool valid = lj < cnt;
-            half8 xh, xl;
-            stage_x<false>(S.u.xs, lj, valid, xh, xl);
-            floatx4 h1[4], f[4];
-            encoder_tile(L, xh, xl, h1, f);
-            if (valid)
-                #pragma unroll
-                for (int ot = 0; ot < 4; ++ot)
+        for (int t = wave; t < ntl; t += 2 * kWaves) {
+            int lj[2];
+            bool valid[2];
+            half8 xh[2], xl[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                lj[u] = (t + u * kWaves) * 16 + (lane & 15);
+                valid[u] = lj[u] < cnt;
+                stage_x<false>(S.u.xs, valid[u] ? lj[u] : 0, valid[u], xh[u], xl[u]);
+            }
+            floatx4 f[2][4];
+            encoder_tile2(L, xh, xl, f);
+            // tile order keeps the lowest node on ties (tile t's nodes precede tile t + kWaves's)
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (valid[u])
                     #pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (f[ot][r] > mx[ot][r]) { mx[ot][r] = f[ot][r]; mi[ot][r] = c0 + lj; }
+                    for (int ot = 0; ot < 4; ++ot)
+                        #pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (f[u][ot][r] > mx[ot][r]) { mx[ot][r] = f[u][ot][r]; mi[ot][r] = c0 + lj[u]; }
         }
     }
     #pragma unroll

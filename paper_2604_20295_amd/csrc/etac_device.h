@@ -654,6 +654,72 @@ __device__ __forceinline__ void encoder_tile(const NetLds &L, const half8 &xh, c
     for (int ot = 0; ot < 4; ++ot) f[ot] = relu4(f[ot]);
 }
 
+// Encoder of two independent 16-node tiles at once: the weight fragments are
+// read once and the two tiles' MFMA chains interleave.
+__device__ __forceinline__ void encoder_tile2(const NetLds &L, const half8 (&xh)[2], const half8 (&xl)[2],
+                                              floatx4 (&f)[2][4]) {
+    reload_fence();
+    const int lane = lane_id(), gq = lane >> 4;
+    floatx4 h1[2][4];
+    {
+        half8 wh[4], wl[4];
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot) {
+            wh[ot] = L.w1h[ot * 64 + lane];
+            wl[ot] = L.w1l[ot * 64 + lane];
+            const floatx4 b = *reinterpret_cast<const floatx4 *>(&L.b1[ot * 16 + 4 * gq]);
+            h1[0][ot] = b;
+            h1[1][ot] = b;
+        }
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) h1[u][ot] = mfma16(wh[ot], xh[u], h1[u][ot]);
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) h1[u][ot] = mfma16(wh[ot], xl[u], h1[u][ot]);
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) h1[u][ot] = relu4(mfma16(wl[ot], xh[u], h1[u][ot]));
+    }
+    half8 bh[2][2], bl[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) split_chain(h1[u], bh[u], bl[u]);
+#pragma unroll
+    for (int ot = 0; ot < 4; ++ot) {
+        const floatx4 b = *reinterpret_cast<const floatx4 *>(&L.b2[ot * 16 + 4 * gq]);
+        f[0][ot] = b;
+        f[1][ot] = b;
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        half8 h[4], l[4];
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot) {
+            h[ot] = L.w2h[(ot * 2 + s) * 64 + lane];
+            l[ot] = L.w2l[(ot * 2 + s) * 64 + lane];
+        }
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) f[u][ot] = mfma16(h[ot], bh[u][s], f[u][ot]);
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) f[u][ot] = mfma16(h[ot], bl[u][s], f[u][ot]);
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) f[u][ot] = mfma16(l[ot], bh[u][s], f[u][ot]);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot) f[u][ot] = relu4(f[u][ot]);
+}
+
 // Decoder: h4 = relu(W4 [f; g'] + b4) with the g' part folded into c4, then
 // r = W5 h4 + b5.  Every lane returns r of its node (lane & 15).
 __device__ __forceinline__ void decoder_tile(const NetLds &L, const floatx4 f[4], floatx4 h4[4], float r_out[3]) {

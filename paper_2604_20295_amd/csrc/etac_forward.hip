@@ -175,20 +175,27 @@ __device__ void residual_item(const StepParams &p, StepLds &S, int k, int base, 
         __syncthreads();
         stage_nodes(p.mesh, k, base, nullptr, c0, cnt, uhn, n_max, 0, S.xs);
         __syncthreads();
+        // two tiles per wave step (t and t + kWaves); the second may be padding
         const int ntl = (cnt + 15) >> 4;
-        for (int t = wave; t < ntl; t += kWaves) {
-            const int lj = t * 16 + (lane & 15);
-            const bool valid = lj < cnt;
-            half8 xh, xl;
-            stage_x<false>(S.xs, lj, valid, xh, xl);
-            floatx4 h1[4], f[4];
-            encoder_tile(L, xh, xl, h1, f);
+        for (int t = wave; t < ntl; t += 2 * kWaves) {
+            bool valid[2];
+            half8 xh[2], xl[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int lj = (t + u * kWaves) * 16 + (lane & 15);
+                valid[u] = lj < cnt;
+                stage_x<false>(S.xs, valid[u] ? lj : 0, valid[u], xh[u], xl[u]);
+            }
+            floatx4 f[2][4];
+            encoder_tile2(L, xh, xl, f);
             // f >= 0, so padding nodes with 0 leaves the max-pool unchanged
-            if (valid)
-                #pragma unroll
-                for (int ot = 0; ot < 4; ++ot)
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (valid[u])
                     #pragma unroll
-                    for (int r = 0; r < 4; ++r) mx[ot][r] = fmaxf(mx[ot][r], f[ot][r]);
+                    for (int ot = 0; ot < 4; ++ot)
+                        #pragma unroll
+                        for (int r = 0; r < 4; ++r) mx[ot][r] = fmaxf(mx[ot][r], f[u][ot][r]);
         }
     }
     #pragma unroll
