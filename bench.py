@@ -47,6 +47,7 @@ def parse():
                     help="time budget of the CPU oracle baseline (envs are added in blocks until it is spent)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay the step from a captured HIP graph")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the built-in launch shapes")
     ap.add_argument("--rollout", action="store_true",
                     help="also run the graph-captured rollout: 16384 envs, 200 steps of smooth object motion")
     ap.add_argument("--rollout-envs", type=int, default=16384)
@@ -88,6 +89,9 @@ def rollout(args, mode):
     grot, gtr = torch.empty((E, O, 9), device=dev), torch.empty((E, O, 3), device=dev)
     gal, gph = torch.empty((K,), device=dev), torch.empty((17411,), device=dev)
 
+    if not args.no_autotune:
+        _native.etac_plan_autotune(plan, sc, md, u, cobj, na, gu, grot, gtr, gal, gph, reps=2)
+
     def body(with_bwd):
         rot.copy_(torch.index_select(trot, 0, step_idx)[0])
         trans.copy_(torch.index_select(ttr, 0, step_idx)[0])
@@ -97,7 +101,8 @@ def rollout(args, mode):
         step_idx.add_(1).remainder_(T)
 
     out = {"envs": E, "steps": T, "workload": f"{E} envs x 16-patch hand, {T} steps of AR(1) object motion "
-                                            f"(5 mm/step velocity std), whole step in one HIP graph"}
+                                            f"(5 mm/step velocity std), whole step in one HIP graph",
+           "launch_shape": list(plan.launch())}
     for with_bwd in (False, True):
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
@@ -267,6 +272,11 @@ def main():
     def bwd():
         _native.etac_step_backward(plan, sc, md, grad_u, grot, gtr, gal, gph)
 
+    # launch shapes chosen by the library's autotuner on this workload
+    if not args.no_autotune:
+        _native.etac_plan_autotune(plan, sc, md, u, cobj, na, grad_u, grot, gtr, gal, gph, reps=2)
+    launch_shape = plan.launch()
+
     graph = None
     if args.graph:
         fwd(); bwd()
@@ -379,7 +389,10 @@ def main():
                                 f"1-3 sphere/box/capsule per env, mode {args.mode}") if args.workload == "hand" else
                                (f"{E} envs x 4 pads of 128x128 nodes at 0.125 mm ({N} nodes/env), one sphere or box "
                                 f"per pad, mode {args.mode}"),
-                   "envs": E, "nodes_per_env": N, "patches": K, "graph": bool(args.graph)},
+                   "envs": E, "nodes_per_env": N, "patches": K, "graph": bool(args.graph),
+                   "launch_shape": {"fwd_wg_per_cu": launch_shape[0], "fwd_batch": launch_shape[1],
+                                    "bwd_batch": launch_shape[2], "decay_wg_per_cu": launch_shape[3],
+                                    "autotuned": not args.no_autotune}},
         "fwd_only": {"value": fwd_rate, "unit": "node-updates/s", "ms_per_step": fwd_only_ms,
                      "hbm_gbs": hbm_fwd_gbs, "hbm_frac": hbm_fwd_gbs / HBM_PEAK_GBS},
         "hbm_frac_step": hbm_step_gbs / HBM_PEAK_GBS,

@@ -42,9 +42,9 @@
  * device; HOST pointers are read during the call only.  The caller owns all
  * inputs and outputs; outputs are overwritten, never accumulated.  The plan
  * owns its copy of the mesh and all scratch memory; no call other than
- * etac_plan_create / etac_plan_destroy and the two kernel-timing calls
- * allocates, frees or synchronises, so every compute call may be captured in
- * a HIP graph.
+ * etac_plan_create / etac_plan_destroy, etac_plan_autotune and the two
+ * kernel-timing calls allocates, frees or synchronises, so every compute
+ * call may be captured in a HIP graph.
  *
  * Streams: `stream` is a hipStream_t (NULL = the default stream).  Every call
  * only enqueues work on it.  A plan is used by one stream at a time.
@@ -192,6 +192,32 @@ etac_status etac_plan_set_occupancy(etac_plan *plan, int32_t wg_per_cu);
  * queue atomic by the persistent kernels, 1 .. 64 (0 = built-in default).
  * Results do not depend on it.  ETAC_ERR_VALUE outside 0 .. 64. */
 etac_status etac_plan_set_batch(etac_plan *plan, int32_t items);
+
+/* Launch shape of the persistent kernels (autotuner knobs; 0 keeps the
+ * current value): forward workgroups per CU (1 .. 8), forward work-queue
+ * batch (1 .. 64), adjoint work-queue batch (1 .. 64), workgroups per CU of
+ * the decay-adjoint kernel (1 .. 8).  Results do not depend on them.
+ * ETAC_ERR_VALUE outside those ranges. */
+etac_status etac_plan_set_launch(etac_plan *plan, int32_t fwd_wg_per_cu, int32_t fwd_batch,
+                                 int32_t bwd_batch, int32_t decay_wg_per_cu);
+
+/* The current launch shape, in the order of etac_plan_set_launch (HOST int32[4]). */
+etac_status etac_plan_get_launch(const etac_plan *plan, int32_t *shape);
+
+/* Autotuner.  Times every candidate launch shape of the persistent kernels
+ * on the caller's inputs (as for etac_step and etac_step_backward; all
+ * DEVICE pointers, outputs overwritten) with HIP events over `reps` calls
+ * (1 .. 1000) after a warm-up call, and keeps the fastest: forward
+ * workgroups per CU in {1, 2} x batch in {1, 2, 4, 8, 16}; with grad_u
+ * non-NULL also decay-kernel workgroups per CU in {2, 3, 4} x adjoint batch
+ * in {2, 4, 8, 16}.  Every candidate gives identical results.  `best` (HOST
+ * int32[4], may be NULL) receives the chosen shape as in
+ * etac_plan_get_launch.  Blocks the host and creates two HIP events, so it
+ * must not be called during stream capture (ETAC_ERR_CAPTURE). */
+etac_status etac_plan_autotune(etac_plan *plan, const etac_scene *scene, const etac_model *model,
+                               const float *grad_u, float *u, int8_t *contact_obj, int32_t *n_active,
+                               float *grad_rot, float *grad_trans, float *grad_alpha, float *grad_phi,
+                               int32_t reps, int32_t *best, void *stream);
 
 /* Kernel timing (diagnostics, not part of the method).  With timing on, every
  * launch of a timed kernel made outside stream capture is bracketed by a pair

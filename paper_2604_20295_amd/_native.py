@@ -30,6 +30,7 @@ EXPORTED = (
     "etac_contact_backward", "etac_propagate_backward", "etac_step_backward",
     "etac_status_string", "etac_last_hip_error", "etac_plan_info", "etac_plan_set_occupancy",
     "etac_plan_set_timing", "etac_plan_kernel_time", "etac_plan_set_batch",
+    "etac_plan_set_launch", "etac_plan_get_launch", "etac_plan_autotune",
 )
 
 
@@ -85,6 +86,10 @@ def lib():
             "etac_plan_set_occupancy": ([vp, i32], i32),
             "etac_plan_set_timing": ([vp, i32], i32),
             "etac_plan_set_batch": ([vp, i32], i32),
+            "etac_plan_set_launch": ([vp, i32, i32, i32, i32], i32),
+            "etac_plan_get_launch": ([vp, P(i32)], i32),
+            "etac_plan_autotune": ([vp, P(etac_scene), P(etac_model), vp, vp, vp, vp, vp, vp, vp, vp, i32, P(i32),
+                                    vp], i32),
             "etac_plan_kernel_time": ([vp, i32, P(i32), P(C.c_double)], i32),
         }
         for name, (args, res) in sig.items():
@@ -164,6 +169,16 @@ class Plan:
 
     def set_batch(self, items):
         _check("etac_plan_set_batch", lib().etac_plan_set_batch(self.handle, int(items)))
+
+    def set_launch(self, fwd_wg_per_cu=0, fwd_batch=0, bwd_batch=0, decay_wg_per_cu=0):
+        _check("etac_plan_set_launch", lib().etac_plan_set_launch(self.handle, int(fwd_wg_per_cu), int(fwd_batch),
+                                                                  int(bwd_batch), int(decay_wg_per_cu)))
+
+    def launch(self):
+        """(fwd workgroups per CU, fwd batch, adjoint batch, decay workgroups per CU)"""
+        out = (C.c_int32 * 4)()
+        _check("etac_plan_get_launch", lib().etac_plan_get_launch(self.handle, out))
+        return tuple(out)
 
     def set_timing(self, enable):
         _check("etac_plan_set_timing", lib().etac_plan_set_timing(self.handle, 1 if enable else 0))
@@ -264,3 +279,27 @@ def etac_step_backward(plan, scene, model, grad_u, grad_rot, grad_trans, grad_al
     _check("etac_step_backward",
            lib().etac_step_backward(plan.handle, C.byref(scene), C.byref(model), _ptr(grad_u), _ptr(grad_rot),
                                     _ptr(grad_trans), _ptr(grad_alpha), _ptr(grad_phi), _stream(plan.device)))
+
+
+def etac_plan_autotune(plan, scene, model, u, contact_obj, n_active, grad_u=None, grad_rot=None, grad_trans=None,
+                       grad_alpha=None, grad_phi=None, reps=3):
+    """Time the candidate launch shapes on these inputs, keep the fastest and
+    return it as (fwd workgroups per CU, fwd batch, adjoint batch, decay
+    workgroups per CU).  With grad_u None only the forward is tuned."""
+    import torch
+    E, O = scene.n_envs, scene.max_obj
+    _req(u, torch.float32, (3, E, plan.N), "u", plan.device)
+    _req(contact_obj, torch.int8, (E, plan.N), "contact_obj", plan.device)
+    _req(n_active, torch.int32, (E, plan.K), "n_active", plan.device)
+    if grad_u is not None:
+        _req(grad_u, torch.float32, (3, E, plan.N), "grad_u", plan.device)
+        _req(grad_rot, torch.float32, (E, O, 9), "grad_rot", plan.device)
+        _req(grad_trans, torch.float32, (E, O, 3), "grad_trans", plan.device)
+        _req(grad_alpha, torch.float32, (plan.K,), "grad_alpha", plan.device)
+        _req(grad_phi, torch.float32, (ETAC_PHI_SIZE,), "grad_phi", plan.device)
+    best = (C.c_int32 * 4)()
+    _check("etac_plan_autotune",
+           lib().etac_plan_autotune(plan.handle, C.byref(scene), C.byref(model), _ptr(grad_u), _ptr(u),
+                                    _ptr(contact_obj), _ptr(n_active), _ptr(grad_rot), _ptr(grad_trans),
+                                    _ptr(grad_alpha), _ptr(grad_phi), int(reps), best, _stream(plan.device)))
+    return tuple(best)

@@ -137,6 +137,8 @@ etac_status etac_plan_create(const etac_mesh *mesh, int32_t n_envs, int32_t max_
     p.n_max = n_max;
     p.wg_per_cu = etac::kDefaultWgPerCu;
     p.batch = etac::kDefaultBatch;
+    p.bwd_batch = etac::kDefaultBatch;
+    p.decay_wg_per_cu = etac::kDefaultDecayWgPerCu;
     hipError_t e = hipGetDevice(&p.device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&p.cu_count, hipDeviceAttributeMultiprocessorCount, p.device);
     if (e != hipSuccess) {
@@ -267,7 +269,33 @@ etac_status etac_plan_set_occupancy(etac_plan *plan, int32_t wg_per_cu) {
 etac_status etac_plan_set_batch(etac_plan *plan, int32_t items) {
     if (!plan) return ETAC_ERR_NULL;
     if (items < 0 || items > 64) return ETAC_ERR_VALUE;
-    plan->p.batch = items == 0 ? etac::kDefaultBatch : items;
+    plan->p.batch = plan->p.bwd_batch = items == 0 ? etac::kDefaultBatch : items;
+    return ETAC_OK;
+}
+
+etac_status etac_plan_set_launch(etac_plan *plan, int32_t fwd_wg_per_cu, int32_t fwd_batch, int32_t bwd_batch,
+                                 int32_t decay_wg_per_cu) {
+    if (!plan) return ETAC_ERR_NULL;
+    if (fwd_wg_per_cu < 0 || fwd_wg_per_cu > 8 || fwd_batch < 0 || fwd_batch > 64 || bwd_batch < 0 ||
+        bwd_batch > 64 || decay_wg_per_cu < 0 || decay_wg_per_cu > 8)
+        return ETAC_ERR_VALUE;
+    etac::Plan &p = plan->p;
+    if (fwd_wg_per_cu) {
+        p.wg_per_cu = fwd_wg_per_cu;
+        p.grid = p.cu_count * p.wg_per_cu;
+    }
+    if (fwd_batch) p.batch = fwd_batch;
+    if (bwd_batch) p.bwd_batch = bwd_batch;
+    if (decay_wg_per_cu) p.decay_wg_per_cu = decay_wg_per_cu;
+    return ETAC_OK;
+}
+
+etac_status etac_plan_get_launch(const etac_plan *plan, int32_t *shape) {
+    if (!plan || !shape) return ETAC_ERR_NULL;
+    shape[0] = plan->p.wg_per_cu;
+    shape[1] = plan->p.batch;
+    shape[2] = plan->p.bwd_batch;
+    shape[3] = plan->p.decay_wg_per_cu;
     return ETAC_OK;
 }
 
@@ -396,6 +424,85 @@ etac_status etac_step_backward(etac_plan *plan, const etac_scene *scene, const e
     hipError_t e = etac::launch_backward(plan->p, &sd, model_dev(model), scene->n_envs, nullptr, nullptr, grad_u,
                                          nullptr, grad_rot, grad_trans, grad_alpha, grad_phi, (hipStream_t)stream);
     return e == hipSuccess ? ETAC_OK : hip_fail(e);
+}
+
+etac_status etac_plan_autotune(etac_plan *plan, const etac_scene *scene, const etac_model *model,
+                               const float *grad_u, float *u, int8_t *contact_obj, int32_t *n_active,
+                               float *grad_rot, float *grad_trans, float *grad_alpha, float *grad_phi,
+                               int32_t reps, int32_t *best, void *stream) {
+    if (!plan) return ETAC_ERR_NULL;
+    if (reps < 1 || reps > 1000) return ETAC_ERR_VALUE;
+    etac::Plan &p = plan->p;
+    const hipStream_t st = (hipStream_t)stream;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return ETAC_ERR_CAPTURE;
+    // one validated call of each before any timing (argument errors come back here)
+    etac_status s = etac_step(plan, scene, model, u, contact_obj, n_active, stream);
+    if (s != ETAC_OK) return s;
+    if (grad_u) {
+        s = etac_step_backward(plan, scene, model, grad_u, grad_rot, grad_trans, grad_alpha, grad_phi, stream);
+        if (s != ETAC_OK) return s;
+    }
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipEventCreate(&ev[0]);
+    if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+    // time `reps` calls after one warm-up call of the current shape
+    auto timed = [&](bool fwd, float &ms) -> etac_status {
+        for (int r = 0; r <= reps; ++r) {
+            if (r == 1 && hipEventRecord(ev[0], st) != hipSuccess) return ETAC_ERR_HIP;
+            const etac_status q = fwd ? etac_step(plan, scene, model, u, contact_obj, n_active, stream)
+                                      : etac_step_backward(plan, scene, model, grad_u, grad_rot, grad_trans,
+                                                           grad_alpha, grad_phi, stream);
+            if (q != ETAC_OK) return q;
+        }
+        hipError_t h = hipEventRecord(ev[1], st);
+        if (h == hipSuccess) h = hipEventSynchronize(ev[1]);
+        if (h == hipSuccess) h = hipEventElapsedTime(&ms, ev[0], ev[1]);
+        return h == hipSuccess ? ETAC_OK : hip_fail(h);
+    };
+    etac_status out = e == hipSuccess ? ETAC_OK : hip_fail(e);
+    // forward: workgroups per CU x work-queue batch
+    int bf_occ = p.wg_per_cu, bf_batch = p.batch;
+    float bf_ms = 3.0e38f;
+    static const int kOcc[] = {1, 2};
+    static const int kBatch[] = {1, 2, 4, 8, 16};
+    for (int oi = 0; out == ETAC_OK && oi < 2; ++oi)
+        for (int bi = 0; out == ETAC_OK && bi < 5; ++bi) {
+            p.wg_per_cu = kOcc[oi];
+            p.grid = p.cu_count * p.wg_per_cu;
+            p.batch = kBatch[bi];
+            float ms = 0.0f;
+            out = timed(true, ms);
+            if (out == ETAC_OK && ms < bf_ms) { bf_ms = ms; bf_occ = p.wg_per_cu; bf_batch = p.batch; }
+        }
+    p.wg_per_cu = bf_occ;
+    p.grid = p.cu_count * p.wg_per_cu;
+    p.batch = bf_batch;
+    // adjoint: decay-kernel workgroups per CU x work-queue batch
+    if (grad_u) {
+        int bb_dec = p.decay_wg_per_cu, bb_batch = p.bwd_batch;
+        float bb_ms = 3.0e38f;
+        static const int kDec[] = {2, 3, 4};
+        for (int di = 0; out == ETAC_OK && di < 3; ++di)
+            for (int bi = 1; out == ETAC_OK && bi < 5; ++bi) {
+                p.decay_wg_per_cu = kDec[di];
+                p.bwd_batch = kBatch[bi];
+                float ms = 0.0f;
+                out = timed(false, ms);
+                if (out == ETAC_OK && ms < bb_ms) { bb_ms = ms; bb_dec = p.decay_wg_per_cu; bb_batch = p.bwd_batch; }
+            }
+        p.decay_wg_per_cu = bb_dec;
+        p.bwd_batch = bb_batch;
+    }
+    for (int i = 0; i < 2; ++i)
+        if (ev[i]) (void)hipEventDestroy(ev[i]);
+    if (best) {
+        best[0] = p.wg_per_cu;
+        best[1] = p.batch;
+        best[2] = p.bwd_batch;
+        best[3] = p.decay_wg_per_cu;
+    }
+    return out;
 }
 
 }  // extern "C"

@@ -1421,14 +1421,14 @@ hipError_t launch_backward(const Plan &pl, const SceneDev *s, const ModelDev &m,
     p.bwd = pl.bwd;
     p.E = n_envs;
     p.n_items = n_envs * pl.K;
-    p.batch = pl.batch;
+    p.batch = pl.bwd_batch;
     p.cobj_in = cobj_in;
     p.uhat_in = uhat_in;
     p.grad_u = grad_u;
     p.grad_uhat_in = nullptr;
     p.grad_uhat_out = grad_uhat;
     // contact and the decay adjoint, several workgroups per CU
-    const int grid_d = min(p.n_items, pl.cu_count * kDecayWgPerCu);
+    const int grid_d = min(p.n_items, pl.cu_count * pl.decay_wg_per_cu);
     int slot = timer_begin(pl, ETAC_TIMER_BWD_DECAY, st);
     if (s) hipLaunchKernelGGL(k_bwd_decay<BWD_STEP>, dim3(grid_d), dim3(kWG), 0, st, p);
     else hipLaunchKernelGGL(k_bwd_decay<BWD_PROP>, dim3(grid_d), dim3(kWG), 0, st, p);
@@ -1473,7 +1473,7 @@ hipError_t launch_contact_backward(const Plan &pl, const SceneDev &s, const floa
     p.bwd = pl.bwd;
     p.E = s.E;
     p.n_items = s.E * pl.K;
-    p.batch = pl.batch;
+    p.batch = pl.bwd_batch;
     p.cobj_in = nullptr;
     p.uhat_in = nullptr;
     p.grad_u = nullptr;

@@ -13,7 +13,7 @@ constexpr int kWaves = kWG / 64;
 constexpr int kMaxPatches = 1024;  // per-patch counters of the contact kernel live in LDS
 constexpr int kDefaultWgPerCu = 2;
 constexpr int kDefaultBatch = 4;   // work-queue positions claimed per atomic
-constexpr int kDecayWgPerCu = 3;   // workgroups per CU of the decay-adjoint kernel
+constexpr int kDefaultDecayWgPerCu = 3;   // workgroups per CU of the decay-adjoint kernel
 
 // Device view of the plan's mesh copy.
 struct MeshDev {
@@ -81,7 +81,9 @@ struct Plan {
     int cu_count;
     int wg_per_cu;
     int grid;              // persistent workgroups
-    int batch;             // work-queue positions claimed per atomic (1 .. 64)
+    int batch;             // forward work-queue positions claimed per atomic (1 .. 64)
+    int bwd_batch;         // adjoint work-queue positions claimed per atomic (1 .. 64)
+    int decay_wg_per_cu;   // workgroups per CU of the decay-adjoint kernel (1 .. 8)
     int n_envs, max_obj, K, N, n_max;
     uint32_t flags;
     MeshDev mesh;

@@ -105,3 +105,37 @@ def test_kernel_timer_counts_eager_launches_only(oracle_lib):
     ref = oracle_lib.forward(mesh, scene, model)
     torch.cuda.synchronize()
     assert np.array_equal(cobj.cpu().numpy(), ref["contact_obj"])
+
+
+def test_autotune_picks_a_candidate_and_keeps_results(oracle_lib):
+    from paper_2604_20295_amd import _native
+    torch, dev = torch_dev()
+    mesh, scene, model = scenes.config2(n_envs=64)
+    E, O, N, K = 64, 3, mesh.n_nodes, mesh.n_patches
+    plan = make_plan(mesh, E, O, backward=True)
+    ds, dm = DevScene(scene), DevModel(model)
+    sc, md = ds.struct(plan), dm.struct(plan)
+    gu = to_dev(np.random.default_rng(4).standard_normal((3, E, N)).astype(np.float32))
+    outs = dict(u=torch.empty((3, E, N), device=dev), cobj=torch.empty((E, N), dtype=torch.int8, device=dev),
+                na=torch.empty((E, K), dtype=torch.int32, device=dev), grot=torch.empty((E, O, 9), device=dev),
+                gt=torch.empty((E, O, 3), device=dev), ga=torch.empty((K,), device=dev),
+                gp=torch.empty((17411,), device=dev))
+
+    def step():
+        _native.etac_step(plan, sc, md, outs["u"], outs["cobj"], outs["na"])
+        _native.etac_step_backward(plan, sc, md, gu, outs["grot"], outs["gt"], outs["ga"], outs["gp"])
+        torch.cuda.synchronize()
+        return {k: v.cpu().numpy().copy() for k, v in outs.items()}
+
+    log("[gpu] autotune")
+    assert plan.launch() == (2, 4, 4, 3)                     # built-in defaults
+    ref = step()
+    best = _native.etac_plan_autotune(plan, sc, md, outs["u"], outs["cobj"], outs["na"], gu, outs["grot"],
+                                      outs["gt"], outs["ga"], outs["gp"], reps=2)
+    log(f"[gpu]   chosen launch shape {best}")
+    assert best == plan.launch()
+    assert best[0] in (1, 2) and best[1] in (1, 2, 4, 8, 16) and best[2] in (2, 4, 8, 16) and best[3] in (2, 3, 4)
+    got = step()
+    for k in ref:
+        assert np.array_equal(got[k], ref[k]), k
+    assert np.array_equal(got["cobj"], oracle_lib.contact(mesh, scene)[0])
