@@ -21,31 +21,33 @@ struct ContactParams {
     int32_t *n_active; // [E][K]
 };
 
-// Contact of one node of env e; returns the winner and adds it to the patch count.
-__device__ __forceinline__ int contact_one(const ContactParams &p, int e, int i, float &u0, float &u1, float &u2,
-                                           int *cnt) {
-    const MeshDev &M = p.mesh;
-    const int N = M.N;
-    const int best = contact_node(p.scene, e, 0xffu, M.pos[i], M.pos[N + i], M.pos[2 * N + i], M.nrm[i],
-                                  M.nrm[N + i], M.nrm[2 * N + i], u0, u1, u2);
-    if (best >= 0) atomicAdd(&cnt[M.node_patch[i]], 1);
-    return best;
-}
-
-// One workgroup per env; consecutive threads take consecutive nodes, so every
-// store of a wave is one contiguous run.
+// One workgroup per env.  The patches' candidate objects are culled first
+// (one mask per patch in LDS), so nodes of patches no object reaches only
+// store their empty result; the others are tested one node per thread,
+// consecutive threads on consecutive nodes.
 __global__ __launch_bounds__(kWG) void k_contact(ContactParams p) {
     __shared__ int cnt[kMaxPatches];
+    __shared__ uint8_t cand[kMaxPatches];
     const int e = blockIdx.x;
     const MeshDev &M = p.mesh;
     const int N = M.N, K = M.K;
     const size_t EN = (size_t)p.scene.E * N;
-    for (int k = threadIdx.x; k < K; k += kWG) cnt[k] = 0;
+    for (int k = threadIdx.x; k < K; k += kWG) {
+        cnt[k] = 0;
+        cand[k] = (uint8_t)cull_objects(p.scene, M, e, k);
+    }
     __syncthreads();
     const size_t row = (size_t)e * N;
     for (int i = threadIdx.x; i < N; i += kWG) {
-        float u0, u1, u2;
-        const int best = contact_one(p, e, i, u0, u1, u2, cnt);
+        int best = -1;
+        float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f;
+        const int k = M.node_patch[i];
+        const unsigned c = cand[k];
+        if (c) {
+            best = contact_node(p.scene, e, c, M.pos[i], M.pos[N + i], M.pos[2 * N + i], M.nrm[i], M.nrm[N + i],
+                                M.nrm[2 * N + i], u0, u1, u2);
+            if (best >= 0) atomicAdd(&cnt[k], 1);
+        }
         p.cobj[row + i] = (int8_t)best;
         if (p.uhat) {
             p.uhat[row + i] = u0;
