@@ -44,6 +44,7 @@ struct BwdParams {
     float *grad_uhat_out;         // [3][E][N]   BWD_PROP
 };
 
+constexpr int kTrRow = 20;     // padded row of the block transpose buffer: conflict-free stores, aligned loads
 constexpr int kRedRegs = 32;   // accumulator registers per lane summed per pass of the item reduction
 
 // Staging area of the decay adjoint.
@@ -72,6 +73,7 @@ struct BwdLds {
         StageBuf xs;                       // node inputs of the network passes
     } u;
     floatx4 acc15[kWaves][8 * 64]; // per-wave dW1 (blocks 0-3) and dW5 (4-7) accumulators [block][lane]
+    floatx4 tr[kWaves][16 * kTrRow / 4]; // per-wave 16 x 16 block transpose buffer (rows of kTrRow floats)
     float s4[64];                 // sum_i dL/dpre4_i  (= db4)
     float dgp[64], dpre3[64], dg[64];
     float vroute[64];             // dL/dpre2 routed to the arg-max node of channel c: dg[c] [g[c] > 0]
@@ -328,14 +330,35 @@ __device__ __forceinline__ void zero_wgrad(WGrad &G) {
     G.b5 = 0.0f;
 }
 
+// N form of a T-form tile through the wave's LDS buffer, one 16 x 16 block
+// at a time: value (feature 4 q + r, node c) of a block is stored at row
+// 4 q + r, column c and read back as four consecutive columns of row c.  The
+// wave's LDS operations execute in order, so the buffer is reused per block
+// with no wait between blocks.
+__device__ __forceinline__ void to_n_form(floatx4 *buf, const floatx4 t[4], floatx4 n[4]) {
+    float *b = reinterpret_cast<float *>(buf);
+    const int lane = lane_id(), gq = lane >> 4, col = lane & 15;
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) b[(4 * gq + r) * kTrRow + col] = t[ob][r];
+        wave_sync();
+        n[ob] = *reinterpret_cast<const floatx4 *>(&b[col * kTrRow + 4 * gq]);
+        wave_sync();
+    }
+}
+
 // Adjoint of one tile of 16 passive nodes (staged nodes 16 t .. 16 t + 15 of
 // the current chunk of cnt): forward recomputation, decoder and encoder
 // adjoints, all accumulated into this wave's parameter gradients.  Passive
 // nodes have U_hat = 0 and need no dL/du_hat; the stage holds dL/dU in its
-// third triple.
+// third triple.  Every layer runs in T form on MFMA; the N forms the weight
+// gradients need are block transposes of the T-form values.
 __device__ void passive_tile(BwdLds &S, WGrad &G, int cnt, int t) {
     const NetLds &L = S.net;
     const StageBuf &xs = S.u.xs;
+    const int wave = threadIdx.x >> 6;
+    floatx4 *tb = S.tr[wave];
     const int lane = lane_id(), gq = lane >> 4, col = lane & 15;
     // T form: this lane's node; N form: nodes 4 gq + r
     const int li = 16 * t + col;
@@ -355,54 +378,36 @@ __device__ void passive_tile(BwdLds &S, WGrad &G, int cnt, int t) {
     floatx4 xn;
 #pragma unroll
     for (int r = 0; r < 4; ++r) xn[r] = vr[r] ? xs[fcol][lj[r]] * fsel + fone : 0.0f;
-    // dL/dr of the tile's nodes in both forms (zero on padding)
-    float dr[3], drn[3][4];
+    // dL/dr of this lane's node (zero on padding)
+    float dr[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const float v = xs[6 + c][li];
         dr[c] = valid ? v : 0.0f;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const float w = xs[6 + c][lj[r]];
-            drn[c][r] = vr[r] ? w : 0.0f;
-        }
     }
     half8 xh, xl;
     stage_x<true>(xs, li, valid, xh, xl);
-    // forward recomputation in both forms; T-form values that only gate a
-    // later step are kept as bit masks (bit 4 block + register)
-    floatx4 h1T[4], h1N[4];
-    layer1_dual(L, xh, xl, h1T, h1N);
+    // forward recomputation (T form)
+    floatx4 h1T[4], fT[4];
+    encoder_tile(L, xh, xl, h1T, fT);
     half8 sh[2], sl[2];
-    split_chain(h1T, sh, sl);
-    floatx4 fT[4], fN[4];
-    layer64<true, true, true>(L.w2h, L.w2l, sh, sl, L.b2, fT, fN);
     split_chain(fT, sh, sl);
-    unsigned fmask = 0;
+    floatx4 h4T[4];
+    layer64<true, false, true>(L.w4h, L.w4l, sh, sl, L.c4, h4T, nullptr);
+    // dL/dpre4 = (W5^T dr) [h4 > 0]
+    floatx4 d4T[4];
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) fmask |= (fT[ob][r] > 0.0f ? 1u : 0u) << (4 * ob + r);
-    floatx4 h4T[4], h4N[4];
-    layer64<true, true, true>(L.w4h, L.w4l, sh, sl, L.c4, h4T, h4N);
-    // dL/dpre4 = (W5^T dr) [h4 > 0] in both forms
-    floatx4 d4T[4], d4N[4];
-#pragma unroll
-    for (int ob = 0; ob < 4; ++ob) {
-        const int fn = ob * 16 + col;
-        const float w0 = L.w5[fn], w1 = L.w5[64 + fn], w2 = L.w5[128 + fn];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int ft = ob * 16 + 4 * gq + r;
             const float vt = L.w5[ft] * dr[0] + L.w5[64 + ft] * dr[1] + L.w5[128 + ft] * dr[2];
             d4T[ob][r] = h4T[ob][r] > 0.0f ? vt : 0.0f;
-            const float vn = w0 * drn[0][r] + w1 * drn[1][r] + w2 * drn[2][r];
-            d4N[ob][r] = h4N[ob][r] > 0.0f ? vn : 0.0f;
         }
-    }
-
     // dW5 += dr (x) h4 (lane col < 3 supplies output col), db5
     {
+        floatx4 h4N[4];
+        to_n_form(tb, h4T, h4N);
         floatx4 a;
         const int ccol = col < 3 ? col : 0;
 #pragma unroll
@@ -415,14 +420,17 @@ __device__ void passive_tile(BwdLds &S, WGrad &G, int cnt, int t) {
         split4(a, ah, al);
 #pragma unroll
         for (int ib = 0; ib < 4; ++ib) split4(h4N[ib], bh[ib], bl[ib]);
-        acc15_add4<false>(S.acc15[threadIdx.x >> 6], 4, &ah, &al, bh, bl);
+        acc15_add4<false>(S.acc15[wave], 4, &ah, &al, bh, bl);
     }
-    // dL/df = W4[:, :64]^T dpre4 in both forms
+    // dL/df = W4[:, :64]^T dpre4
     split_chain(d4T, sh, sl);
-    floatx4 dfT[4], dfN[4];
-    layer64<true, true, false>(S.w4th, S.w4tl, sh, sl, nullptr, dfT, dfN);
+    floatx4 dfT[4];
+    layer64<true, false, false>(S.w4th, S.w4tl, sh, sl, nullptr, dfT, nullptr);
     // dW4[:, :64] += dpre4 (x) f, db4
     {
+        floatx4 d4N[4], fN[4];
+        to_n_form(tb, d4T, d4N);
+        to_n_form(tb, fT, fN);
         half4 fh[4], fl[4], ah[4], al[4];
 #pragma unroll
         for (int ib = 0; ib < 4; ++ib) split4(fN[ib], fh[ib], fl[ib]);
@@ -434,19 +442,20 @@ __device__ void passive_tile(BwdLds &S, WGrad &G, int cnt, int t) {
         wgrad_blocks<4, 4>(ah, al, fh, fl, G.w4);
     }
     // dL/dpre2 = df [f > 0]; dL/dh1 = W2^T dpre2 (N form only: no dL/du_hat here)
-    floatx4 d2T[4], d2N[4];
+    floatx4 d2T[4];
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            d2T[ob][r] = ((fmask >> (4 * ob + r)) & 1u) ? dfT[ob][r] : 0.0f;
-            d2N[ob][r] = fN[ob][r] > 0.0f ? dfN[ob][r] : 0.0f;
-        }
+        for (int r = 0; r < 4; ++r) d2T[ob][r] = fT[ob][r] > 0.0f ? dfT[ob][r] : 0.0f;
     split_chain(d2T, sh, sl);
     floatx4 dh1N[4];
     layer64<false, true, false>(S.w2th, S.w2tl, sh, sl, nullptr, nullptr, dh1N);
+    floatx4 h1N[4];
+    to_n_form(tb, h1T, h1N);
     // dW2 += dpre2 (x) h1, db2
     {
+        floatx4 d2N[4];
+        to_n_form(tb, d2T, d2N);
         half4 hh[4], hl[4], ah[4], al[4];
 #pragma unroll
         for (int ib = 0; ib < 4; ++ib) split4(h1N[ib], hh[ib], hl[ib]);
@@ -468,7 +477,7 @@ __device__ void passive_tile(BwdLds &S, WGrad &G, int cnt, int t) {
             for (int r = 0; r < 4; ++r) d1[r] = h1N[ob][r] > 0.0f ? dh1N[ob][r] : 0.0f;
             split4(d1, ah[ob], al[ob]);
         }
-        acc15_add4<true>(S.acc15[threadIdx.x >> 6], 0, ah, al, &xnh, &xnl);
+        acc15_add4<true>(S.acc15[wave], 0, ah, al, &xnh, &xnl);
     }
 }
 
