@@ -123,9 +123,12 @@ __device__ void stage_net_t(BwdLds &S, const float *phi) {
 // node 4 (l >> 4) + r.  Feeding the split T-form tile as the A operand instead
 // (M = nodes, K = input features) and the same weight fragment as the B
 // operand gives X W^T in this layout.  In N form the nodes sit in registers,
-// so a weight gradient dW = sum_n a_n (x) b_n is one v_mfma_f32_16x16x16_f16
-// per 16 x 16 block with K = the tile's 16 nodes and both operands taken
-// straight from the N-form registers.
+// so a weight gradient dW = sum_n a_n (x) b_n per 16 x 16 block takes both
+// operands straight from the N-form registers: two v_mfma_f32_16x16x32_f16
+// whose K = 32 runs over the tile's 16 nodes twice (hi and lo parts).
+// Every accumulator here sees only that one MFMA shape: chaining an
+// accumulator from the 16x16x32 shape into the 16x16x16 one gave wrong
+// gradients in this build, so the 16x16x16 shape is not used.
 // ---------------------------------------------------------------------------
 typedef _Float16 half4 __attribute__((ext_vector_type(4)));
 
@@ -140,9 +143,6 @@ __device__ __forceinline__ void split4(const floatx4 &v, half4 &hi, half4 &lo) {
     lo = __builtin_bit_cast(half4, l);
 }
 
-__device__ __forceinline__ floatx4 mfma_k16(const half4 &a, const half4 &b, floatx4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
-}
 
 
 // Input layer (9 -> 64, inputs padded to one K step of 32) in both forms:
@@ -224,23 +224,40 @@ __device__ __forceinline__ void layer64(const half8 *wh, const half8 *wl, const 
     }
 }
 
+// Two N-form operands side by side as one K = 32 operand: lane group q then
+// holds k = 8 q .. 8 q + 7 = (first: nodes 4 q .. 4 q + 3, second: the same
+// nodes).  Any k order contracts correctly as long as both operands use it.
+__device__ __forceinline__ half8 cat4(const half4 &a, const half4 &b) {
+    return __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7);
+}
+
+// Split weight-gradient product over the tile's 16 nodes as two K = 32
+// MFMAs sharing the B operand [bh bl]: [ah ah] gives hi*hi + hi*lo, [al 0]
+// gives lo*hi.  Every accumulator sees only this one MFMA shape.
+__device__ __forceinline__ floatx4 wgrad_hh_hl(const half4 &ah, const half8 &b, floatx4 acc) {
+    return mfma16(cat4(ah, ah), b, acc);
+}
+__device__ __forceinline__ floatx4 wgrad_lh(const half4 &al, const half8 &b, floatx4 acc) {
+    const half4 z = {0, 0, 0, 0};
+    return mfma16(cat4(al, z), b, acc);
+}
+
 // acc[ob][ib] += A[ob] B[ib] over the tile's nodes for NO x NI blocks, split
-// passes outermost (every accumulator sees hi*hi, hi*lo, lo*hi in order).
+// passes outermost (every accumulator sees hi*hi + hi*lo, then lo*hi).
 template <int NO, int NI>
 __device__ __forceinline__ void wgrad_blocks(const half4 (&ah)[NO], const half4 (&al)[NO], const half4 (&bh)[NI],
                                              const half4 (&bl)[NI], floatx4 (&acc)[NO][NI]) {
+    half8 b[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) b[i] = cat4(bh[i], bl[i]);
 #pragma unroll
     for (int o = 0; o < NO; ++o)
 #pragma unroll
-        for (int i = 0; i < NI; ++i) acc[o][i] = mfma_k16(ah[o], bh[i], acc[o][i]);
+        for (int i = 0; i < NI; ++i) acc[o][i] = wgrad_hh_hl(ah[o], b[i], acc[o][i]);
 #pragma unroll
     for (int o = 0; o < NO; ++o)
 #pragma unroll
-        for (int i = 0; i < NI; ++i) acc[o][i] = mfma_k16(ah[o], bl[i], acc[o][i]);
-#pragma unroll
-    for (int o = 0; o < NO; ++o)
-#pragma unroll
-        for (int i = 0; i < NI; ++i) acc[o][i] = mfma_k16(al[o], bh[i], acc[o][i]);
+        for (int i = 0; i < NI; ++i) acc[o][i] = wgrad_lh(al[o], b[i], acc[o][i]);
 }
 
 // acc15[wave][blk0 + j] += A[j] B (j < 4) or A B[j]: four blocks from fresh
@@ -250,28 +267,19 @@ __device__ __forceinline__ void acc15_add4(floatx4 *acc, int blk0, const half4 *
                                            const half4 *bh, const half4 *bl) {
     const int lane = lane_id();
     floatx4 t[1][4];
-    half4 h1[1], l1[1], h4[4], l4[4];
-    if (A_VARIES) {
-        h1[0] = bh[0]; l1[0] = bl[0];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) { h4[j] = ah[j]; l4[j] = al[j]; }
-    } else {
-        h1[0] = ah[0]; l1[0] = al[0];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) { h4[j] = bh[j]; l4[j] = bl[j]; }
-    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) t[0][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-    // the products are symmetric in which operand is A here only through the
-    // layout: A[j] B means MFMA A operand = the varying block
     if (A_VARIES) {
+        // MFMA A operand = the varying block
+        const half8 b = cat4(bh[0], bl[0]);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) t[0][j] = mfma_k16(h4[j], h1[0], t[0][j]);
+        for (int j = 0; j < 4; ++j) t[0][j] = wgrad_hh_hl(ah[j], b, t[0][j]);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) t[0][j] = mfma_k16(h4[j], l1[0], t[0][j]);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) t[0][j] = mfma_k16(l4[j], h1[0], t[0][j]);
+        for (int j = 0; j < 4; ++j) t[0][j] = wgrad_lh(al[j], b, t[0][j]);
     } else {
+        half4 h1[1] = {ah[0]}, l1[1] = {al[0]}, h4[4], l4[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) { h4[j] = bh[j]; l4[j] = bl[j]; }
         wgrad_blocks<1, 4>(h1, l1, h4, l4, t);
     }
 #pragma unroll
