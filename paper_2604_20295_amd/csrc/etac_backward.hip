@@ -224,71 +224,80 @@ __device__ __forceinline__ void layer64(const half8 *wh, const half8 *wl, const 
     }
 }
 
-// Two N-form operands side by side as one K = 32 operand: lane group q then
-// holds k = 8 q .. 8 q + 7 = (first: nodes 4 q .. 4 q + 3, second: the same
-// nodes).  Any k order contracts correctly as long as both operands use it.
-__device__ __forceinline__ half8 cat4(const half4 &a, const half4 &b) {
-    return __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7);
-}
+// Weight-gradient operands: NB N-form blocks of NT tiles, split and packed as
+// K = 32 MFMA operands (lane group q holds k = 8 q .. 8 q + 7; any k order
+// contracts correctly as long as both operands use it).
+//   NT = 2: h = [hi of tile 0, hi of tile 1], l = the lo parts; the three
+//           split products hi*hi, hi*lo, lo*hi take one MFMA each.
+//   NT = 1: A operand h = [hi hi], l = [lo 0]; B operand h = [hi lo]; then
+//           A.h B.h = hi*hi + hi*lo and A.l B.h = lo*hi.
+// Every accumulator sees only the 16x16x32 MFMA shape: chaining an
+// accumulator from that shape into the 16x16x16 one gave wrong gradients in
+// this build, so the 16x16x16 shape is not used.
+template <int NT, int NB, bool A_ROLE>
+struct WOp {
+    static_assert(NT == 1 || NT == 2, "one or two tiles");
+    half8 h[NB], l[NB];
+    __device__ __forceinline__ void set(int u, int j, const floatx4 &v) {
+        half4 hi, lo;
+        split4(v, hi, lo);
+        if constexpr (NT == 2) {
+            if (u == 0) { h[j].lo = hi; l[j].lo = lo; }
+            else { h[j].hi = hi; l[j].hi = lo; }
+        } else if constexpr (A_ROLE) {
+            h[j].lo = hi; h[j].hi = hi;
+            l[j].lo = lo; l[j].hi = half4{0, 0, 0, 0};
+        } else {
+            h[j].lo = hi; h[j].hi = lo;
+        }
+    }
+};
 
-// Split weight-gradient product over the tile's 16 nodes as two K = 32
-// MFMAs sharing the B operand [bh bl]: [ah ah] gives hi*hi + hi*lo, [al 0]
-// gives lo*hi.  Every accumulator sees only this one MFMA shape.
-__device__ __forceinline__ floatx4 wgrad_hh_hl(const half4 &ah, const half8 &b, floatx4 acc) {
-    return mfma16(cat4(ah, ah), b, acc);
-}
-__device__ __forceinline__ floatx4 wgrad_lh(const half4 &al, const half8 &b, floatx4 acc) {
-    const half4 z = {0, 0, 0, 0};
-    return mfma16(cat4(al, z), b, acc);
-}
-
-// acc[ob][ib] += A[ob] B[ib] over the tile's nodes for NO x NI blocks, split
-// passes outermost (every accumulator sees hi*hi + hi*lo, then lo*hi).
-template <int NO, int NI>
-__device__ __forceinline__ void wgrad_blocks(const half4 (&ah)[NO], const half4 (&al)[NO], const half4 (&bh)[NI],
-                                             const half4 (&bl)[NI], floatx4 (&acc)[NO][NI]) {
-    half8 b[NI];
-#pragma unroll
-    for (int i = 0; i < NI; ++i) b[i] = cat4(bh[i], bl[i]);
+// acc[o][i] += sum over the tiles' nodes of A[o] (x) B[i], split passes
+// outermost.
+template <int NT, int NO, int NI>
+__device__ __forceinline__ void wgrad_tiles(const WOp<NT, NO, true> &A, const WOp<NT, NI, false> &B,
+                                            floatx4 (&acc)[NO][NI]) {
 #pragma unroll
     for (int o = 0; o < NO; ++o)
 #pragma unroll
-        for (int i = 0; i < NI; ++i) acc[o][i] = wgrad_hh_hl(ah[o], b[i], acc[o][i]);
+        for (int i = 0; i < NI; ++i) acc[o][i] = mfma16(A.h[o], B.h[i], acc[o][i]);
+    if constexpr (NT == 2) {
+#pragma unroll
+        for (int o = 0; o < NO; ++o)
+#pragma unroll
+            for (int i = 0; i < NI; ++i) acc[o][i] = mfma16(A.h[o], B.l[i], acc[o][i]);
+    }
 #pragma unroll
     for (int o = 0; o < NO; ++o)
 #pragma unroll
-        for (int i = 0; i < NI; ++i) acc[o][i] = wgrad_lh(al[o], b[i], acc[o][i]);
+        for (int i = 0; i < NI; ++i) acc[o][i] = mfma16(A.l[o], B.h[i], acc[o][i]);
 }
 
-// acc15[wave][blk0 + j] += A[j] B (j < 4) or A B[j]: four blocks from fresh
-// accumulators, then one LDS read-modify-write each.
-template <bool A_VARIES>
-__device__ __forceinline__ void acc15_add4(floatx4 *acc, int blk0, const half4 *ah, const half4 *al,
-                                           const half4 *bh, const half4 *bl) {
+// acc15[wave][blk0 + o NI + i] += sum over the tiles' nodes of A[o] (x) B[i]
+// (NO x NI = 4 blocks): products from fresh accumulators, then one LDS
+// read-modify-write per block.
+template <int NT, int NO, int NI>
+__device__ __forceinline__ void acc15_add(floatx4 *acc, int blk0, const WOp<NT, NO, true> &A,
+                                          const WOp<NT, NI, false> &B) {
+    static_assert(NO * NI == 4, "four blocks");
     const int lane = lane_id();
-    floatx4 t[1][4];
+    floatx4 t[NO][NI];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) t[0][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-    if (A_VARIES) {
-        // MFMA A operand = the varying block
-        const half8 b = cat4(bh[0], bl[0]);
+    for (int o = 0; o < NO; ++o)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) t[0][j] = wgrad_hh_hl(ah[j], b, t[0][j]);
+        for (int i = 0; i < NI; ++i) t[o][i] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    wgrad_tiles<NT, NO, NI>(A, B, t);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) t[0][j] = wgrad_lh(al[j], b, t[0][j]);
-    } else {
-        half4 h1[1] = {ah[0]}, l1[1] = {al[0]}, h4[4], l4[4];
+    for (int o = 0; o < NO; ++o)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) { h4[j] = bh[j]; l4[j] = bl[j]; }
-        wgrad_blocks<1, 4>(h1, l1, h4, l4, t);
-    }
+        for (int i = 0; i < NI; ++i) {
+            const int j = blk0 + o * NI + i;
+            floatx4 v = acc[j * 64 + lane];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        floatx4 v = acc[(blk0 + j) * 64 + lane];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) v[r] += t[0][j][r];
-        acc[(blk0 + j) * 64 + lane] = v;
-    }
+            for (int r = 0; r < 4; ++r) v[r] += t[o][i][r];
+            acc[j * 64 + lane] = v;
+        }
 }
 
 // Network inputs in N form: lane l supplies input feature (l & 15) of nodes
@@ -356,136 +365,263 @@ __device__ __forceinline__ void to_n_form(floatx4 *buf, const floatx4 t[4], floa
     }
 }
 
-// Adjoint of one tile of 16 passive nodes (staged nodes 16 t .. 16 t + 15 of
-// the current chunk of cnt): forward recomputation, decoder and encoder
+// T-form layers over NT tiles; each weight fragment is read from LDS once
+// for all tiles.  Per tile and block the MFMA sequence is that of layer64:
+// per K step hi*hi, hi*lo, lo*hi.
+template <int NT>
+__device__ __forceinline__ void layer1_tiles(const NetLds &L, const half8 (&xh)[NT], const half8 (&xl)[NT],
+                                             floatx4 (&h1)[NT][4]) {
+    reload_fence();
+    const int lane = lane_id(), gq = lane >> 4;
+    half8 wh[4], wl[4];
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+        wh[ob] = L.w1h[ob * 64 + lane];
+        wl[ob] = L.w1l[ob * 64 + lane];
+        const floatx4 b = *reinterpret_cast<const floatx4 *>(&L.b1[ob * 16 + 4 * gq]);
+#pragma unroll
+        for (int u = 0; u < NT; ++u) h1[u][ob] = b;
+    }
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+        for (int u = 0; u < NT; ++u) h1[u][ob] = mfma16(wh[ob], xh[u], h1[u][ob]);
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+        for (int u = 0; u < NT; ++u) h1[u][ob] = mfma16(wh[ob], xl[u], h1[u][ob]);
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+        for (int u = 0; u < NT; ++u) h1[u][ob] = relu4(mfma16(wl[ob], xh[u], h1[u][ob]));
+}
+
+// y[u] = W x[u] (+ bias), relu if RELU (T form in and out).
+template <int NT, bool RELU>
+__device__ __forceinline__ void layer64_tiles(const half8 *wh, const half8 *wl, const half8 (&xh)[NT][2],
+                                              const half8 (&xl)[NT][2], const float *bias, floatx4 (&y)[NT][4]) {
+    reload_fence();
+    const int lane = lane_id(), gq = lane >> 4;
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob) {
+        const floatx4 b = bias ? *reinterpret_cast<const floatx4 *>(&bias[ob * 16 + 4 * gq])
+                               : floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int u = 0; u < NT; ++u) y[u][ob] = b;
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        half8 h[4], l[4];
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) {
+            h[ob] = wh[(ob * 2 + s) * 64 + lane];
+            l[ob] = wl[(ob * 2 + s) * 64 + lane];
+        }
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+            for (int u = 0; u < NT; ++u) y[u][ob] = mfma16(h[ob], xh[u][s], y[u][ob]);
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+            for (int u = 0; u < NT; ++u) y[u][ob] = mfma16(h[ob], xl[u][s], y[u][ob]);
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+            for (int u = 0; u < NT; ++u) y[u][ob] = mfma16(l[ob], xh[u][s], y[u][ob]);
+    }
+    if (RELU)
+#pragma unroll
+        for (int u = 0; u < NT; ++u)
+#pragma unroll
+            for (int ob = 0; ob < 4; ++ob) y[u][ob] = relu4(y[u][ob]);
+}
+
+// y[u] = x[u] W^T in N form from a split T-form input (no bias, no relu).
+template <int NT>
+__device__ __forceinline__ void layer64_tiles_n(const half8 *wh, const half8 *wl, const half8 (&xh)[NT][2],
+                                                const half8 (&xl)[NT][2], floatx4 (&y)[NT][4]) {
+    reload_fence();
+    const int lane = lane_id();
+#pragma unroll
+    for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+        for (int u = 0; u < NT; ++u) y[u][ob] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        half8 h[4], l[4];
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob) {
+            h[ob] = wh[(ob * 2 + s) * 64 + lane];
+            l[ob] = wl[(ob * 2 + s) * 64 + lane];
+        }
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+            for (int u = 0; u < NT; ++u) y[u][ob] = mfma16(xh[u][s], h[ob], y[u][ob]);
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+            for (int u = 0; u < NT; ++u) y[u][ob] = mfma16(xh[u][s], l[ob], y[u][ob]);
+#pragma unroll
+        for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+            for (int u = 0; u < NT; ++u) y[u][ob] = mfma16(xl[u][s], h[ob], y[u][ob]);
+    }
+}
+
+// Adjoint of NT tiles of 16 passive nodes (staged nodes 16 t[u] .. 16 t[u] +
+// 15 of the current chunk of cnt): forward recomputation, decoder and encoder
 // adjoints, all accumulated into this wave's parameter gradients.  Passive
 // nodes have U_hat = 0 and need no dL/du_hat; the stage holds dL/dU in its
 // third triple.  Every layer runs in T form on MFMA; the N forms the weight
 // gradients need are block transposes of the T-form values.
-__device__ void passive_tile(BwdLds &S, WGrad &G, int cnt, int t) {
+template <int NT>
+__device__ void passive_tiles(BwdLds &S, WGrad &G, int cnt, const int (&t)[NT]) {
     const NetLds &L = S.net;
     const StageBuf &xs = S.u.xs;
     const int wave = threadIdx.x >> 6;
     floatx4 *tb = S.tr[wave];
     const int lane = lane_id(), gq = lane >> 4, col = lane & 15;
     // T form: this lane's node; N form: nodes 4 gq + r
-    const int li = 16 * t + col;
-    const bool valid = li < cnt;
-    int lj[4];
-    bool vr[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        lj[r] = 16 * t + 4 * gq + r;
-        vr[r] = lj[r] < cnt;
-    }
+    int lj[NT][4];
+    bool vr[NT][4];
+    floatx4 xn[NT];
+    float dr[NT][3];
+    half8 xh[NT], xl[NT];
     // N-form network inputs: feature col of nodes lj[r] (U_hat = 0; input 9 =
     // 1).  Reads stay inside the stage (tile rows < kStage) and are masked
     // afterwards, so no lane branches.
     const int fcol = col < 6 ? col : 0;
     const float fsel = col < 6 ? 1.0f : 0.0f, fone = col == 9 ? 1.0f : 0.0f;
-    floatx4 xn;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) xn[r] = vr[r] ? xs[fcol][lj[r]] * fsel + fone : 0.0f;
-    // dL/dr of this lane's node (zero on padding)
-    float dr[3];
+    for (int u = 0; u < NT; ++u) {
+        const int li = 16 * t[u] + col;
+        const bool valid = li < cnt;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const float v = xs[6 + c][li];
-        dr[c] = valid ? v : 0.0f;
+        for (int r = 0; r < 4; ++r) {
+            lj[u][r] = 16 * t[u] + 4 * gq + r;
+            vr[u][r] = lj[u][r] < cnt;
+            xn[u][r] = vr[u][r] ? xs[fcol][lj[u][r]] * fsel + fone : 0.0f;
+        }
+        // dL/dr of this lane's node (zero on padding)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float v = xs[6 + c][li];
+            dr[u][c] = valid ? v : 0.0f;
+        }
+        stage_x<true>(xs, li, valid, xh[u], xl[u]);
     }
-    half8 xh, xl;
-    stage_x<true>(xs, li, valid, xh, xl);
     // forward recomputation (T form)
-    floatx4 h1T[4], fT[4];
-    encoder_tile(L, xh, xl, h1T, fT);
-    half8 sh[2], sl[2];
-    split_chain(fT, sh, sl);
-    floatx4 h4T[4];
-    layer64<true, false, true>(L.w4h, L.w4l, sh, sl, L.c4, h4T, nullptr);
+    floatx4 h1T[NT][4], fT[NT][4], h4T[NT][4];
+    half8 sh[NT][2], sl[NT][2];
+    layer1_tiles<NT>(L, xh, xl, h1T);
+#pragma unroll
+    for (int u = 0; u < NT; ++u) split_chain(h1T[u], sh[u], sl[u]);
+    layer64_tiles<NT, true>(L.w2h, L.w2l, sh, sl, L.b2, fT);
+#pragma unroll
+    for (int u = 0; u < NT; ++u) split_chain(fT[u], sh[u], sl[u]);
+    layer64_tiles<NT, true>(L.w4h, L.w4l, sh, sl, L.c4, h4T);
     // dL/dpre4 = (W5^T dr) [h4 > 0]
-    floatx4 d4T[4];
+    floatx4 d4T[NT][4];
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int ft = ob * 16 + 4 * gq + r;
-            const float vt = L.w5[ft] * dr[0] + L.w5[64 + ft] * dr[1] + L.w5[128 + ft] * dr[2];
-            d4T[ob][r] = h4T[ob][r] > 0.0f ? vt : 0.0f;
+            const float w0 = L.w5[ft], w1 = L.w5[64 + ft], w2 = L.w5[128 + ft];
+#pragma unroll
+            for (int u = 0; u < NT; ++u) {
+                const float vt = w0 * dr[u][0] + w1 * dr[u][1] + w2 * dr[u][2];
+                d4T[u][ob][r] = h4T[u][ob][r] > 0.0f ? vt : 0.0f;
+            }
         }
     // dW5 += dr (x) h4 (lane col < 3 supplies output col), db5
     {
-        floatx4 h4N[4];
-        to_n_form(tb, h4T, h4N);
-        floatx4 a;
+        WOp<NT, 1, true> A;
+        WOp<NT, 4, false> B;
         const int ccol = col < 3 ? col : 0;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const float v = xs[6 + ccol][lj[r]];
-            a[r] = (vr[r] && col < 3) ? v : 0.0f;
-        }
-        G.b5 += (a[0] + a[1]) + (a[2] + a[3]);
-        half4 ah, al, bh[4], bl[4];
-        split4(a, ah, al);
+        for (int u = 0; u < NT; ++u) {
+            floatx4 h4N[4];
+            to_n_form(tb, h4T[u], h4N);
+            floatx4 a;
 #pragma unroll
-        for (int ib = 0; ib < 4; ++ib) split4(h4N[ib], bh[ib], bl[ib]);
-        acc15_add4<false>(S.acc15[wave], 4, &ah, &al, bh, bl);
+            for (int r = 0; r < 4; ++r) {
+                const float v = xs[6 + ccol][lj[u][r]];
+                a[r] = (vr[u][r] && col < 3) ? v : 0.0f;
+            }
+            G.b5 += (a[0] + a[1]) + (a[2] + a[3]);
+            A.set(u, 0, a);
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib) B.set(u, ib, h4N[ib]);
+        }
+        acc15_add<NT, 1, 4>(S.acc15[wave], 4, A, B);
+    }
+    // dW4[:, :64] += dpre4 (x) f, db4; f > 0 kept as bits (4 block + register)
+    unsigned fmask[NT];
+    {
+        WOp<NT, 4, true> A;
+        WOp<NT, 4, false> B;
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+            floatx4 d4N[4], fN[4];
+            to_n_form(tb, d4T[u], d4N);
+            to_n_form(tb, fT[u], fN);
+            fmask[u] = 0u;
+#pragma unroll
+            for (int ob = 0; ob < 4; ++ob) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) fmask[u] |= (fT[u][ob][r] > 0.0f ? 1u : 0u) << (4 * ob + r);
+                B.set(u, ob, fN[ob]);
+                G.b4[ob] += (d4N[ob][0] + d4N[ob][1]) + (d4N[ob][2] + d4N[ob][3]);
+                A.set(u, ob, d4N[ob]);
+            }
+        }
+        wgrad_tiles<NT, 4, 4>(A, B, G.w4);
     }
     // dL/df = W4[:, :64]^T dpre4
-    split_chain(d4T, sh, sl);
-    floatx4 dfT[4];
-    layer64<true, false, false>(S.w4th, S.w4tl, sh, sl, nullptr, dfT, nullptr);
-    // dW4[:, :64] += dpre4 (x) f, db4
-    {
-        floatx4 d4N[4], fN[4];
-        to_n_form(tb, d4T, d4N);
-        to_n_form(tb, fT, fN);
-        half4 fh[4], fl[4], ah[4], al[4];
 #pragma unroll
-        for (int ib = 0; ib < 4; ++ib) split4(fN[ib], fh[ib], fl[ib]);
-#pragma unroll
-        for (int ob = 0; ob < 4; ++ob) {
-            G.b4[ob] += (d4N[ob][0] + d4N[ob][1]) + (d4N[ob][2] + d4N[ob][3]);
-            split4(d4N[ob], ah[ob], al[ob]);
-        }
-        wgrad_blocks<4, 4>(ah, al, fh, fl, G.w4);
-    }
+    for (int u = 0; u < NT; ++u) split_chain(d4T[u], sh[u], sl[u]);
+    floatx4 dfT[NT][4];
+    layer64_tiles<NT, false>(S.w4th, S.w4tl, sh, sl, nullptr, dfT);
     // dL/dpre2 = df [f > 0]; dL/dh1 = W2^T dpre2 (N form only: no dL/du_hat here)
-    floatx4 d2T[4];
+    floatx4 d2T[NT][4];
 #pragma unroll
-    for (int ob = 0; ob < 4; ++ob)
+    for (int u = 0; u < NT; ++u)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) d2T[ob][r] = fT[ob][r] > 0.0f ? dfT[ob][r] : 0.0f;
-    split_chain(d2T, sh, sl);
-    floatx4 dh1N[4];
-    layer64<false, true, false>(S.w2th, S.w2tl, sh, sl, nullptr, nullptr, dh1N);
-    floatx4 h1N[4];
-    to_n_form(tb, h1T, h1N);
-    // dW2 += dpre2 (x) h1, db2
+        for (int ob = 0; ob < 4; ++ob)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                d2T[u][ob][r] = ((fmask[u] >> (4 * ob + r)) & 1u) ? dfT[u][ob][r] : 0.0f;
+#pragma unroll
+    for (int u = 0; u < NT; ++u) split_chain(d2T[u], sh[u], sl[u]);
+    floatx4 dh1N[NT][4];
+    layer64_tiles_n<NT>(S.w2th, S.w2tl, sh, sl, dh1N);
+    // dW2 += dpre2 (x) h1, db2; dW1 += dpre1 (x) x (db1 through input 9)
     {
-        floatx4 d2N[4];
-        to_n_form(tb, d2T, d2N);
-        half4 hh[4], hl[4], ah[4], al[4];
+        WOp<NT, 4, true> A2, A1;
+        WOp<NT, 4, false> B2;
+        WOp<NT, 1, false> B1;
 #pragma unroll
-        for (int ib = 0; ib < 4; ++ib) split4(h1N[ib], hh[ib], hl[ib]);
+        for (int u = 0; u < NT; ++u) {
+            floatx4 h1N[4], d2N[4];
+            to_n_form(tb, h1T[u], h1N);
+            to_n_form(tb, d2T[u], d2N);
 #pragma unroll
-        for (int ob = 0; ob < 4; ++ob) {
-            G.b2[ob] += (d2N[ob][0] + d2N[ob][1]) + (d2N[ob][2] + d2N[ob][3]);
-            split4(d2N[ob], ah[ob], al[ob]);
+            for (int ob = 0; ob < 4; ++ob) {
+                B2.set(u, ob, h1N[ob]);
+                G.b2[ob] += (d2N[ob][0] + d2N[ob][1]) + (d2N[ob][2] + d2N[ob][3]);
+                A2.set(u, ob, d2N[ob]);
+                floatx4 d1;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) d1[r] = h1N[ob][r] > 0.0f ? dh1N[u][ob][r] : 0.0f;
+                A1.set(u, ob, d1);
+            }
+            B1.set(u, 0, xn[u]);
         }
-        wgrad_blocks<4, 4>(ah, al, hh, hl, G.w2);
-    }
-    // dW1 += dpre1 (x) x (db1 through input 9)
-    {
-        half4 xnh, xnl, ah[4], al[4];
-        split4(xn, xnh, xnl);
-#pragma unroll
-        for (int ob = 0; ob < 4; ++ob) {
-            floatx4 d1;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) d1[r] = h1N[ob][r] > 0.0f ? dh1N[ob][r] : 0.0f;
-            split4(d1, ah[ob], al[ob]);
-        }
-        acc15_add4<true>(S.acc15[wave], 0, ah, al, &xnh, &xnl);
+        wgrad_tiles<NT, 4, 4>(A2, B2, G.w2);
+        acc15_add<NT, 4, 1>(S.acc15[wave], 0, A1, B1);
     }
 }
 
@@ -556,16 +692,17 @@ __device__ void routing_tile(const BwdParams &p, BwdLds &S, WGrad &G, int k, int
             for (int r = 0; r < 4; ++r) G.w2[ob][ib][r] += (mine ? vn[r] : 0.0f) * h1N[ib][r];
     }
     // dW1 += dpre1 (x) x (db1 through input 9)
-    half4 xnh, xnl, ah[4], al[4];
-    split4(load_xn(M, k, base, lnr, vr, uhn, n_max), xnh, xnl);
+    WOp<1, 4, true> A;
+    WOp<1, 1, false> B;
+    B.set(0, 0, load_xn(M, k, base, lnr, vr, uhn, n_max));
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob) {
         floatx4 d1;
 #pragma unroll
         for (int r = 0; r < 4; ++r) d1[r] = h1N[ob][r] > 0.0f ? dh1N[ob][r] : 0.0f;
-        split4(d1, ah[ob], al[ob]);
+        A.set(0, ob, d1);
     }
-    acc15_add4<true>(S.acc15[wave], 0, ah, al, &xnh, &xnl);
+    acc15_add<1, 4, 1>(S.acc15[wave], 0, A, B);
 }
 
 // ---------------------------------------------------------------------------
@@ -1015,8 +1152,18 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
         __syncthreads();
         stage_nodes(M, k, base, plist, c0, cnt, p.grad_u, EN, row, S.u.xs);
         __syncthreads();
+        // pairs of tiles (t, t + 4) per wave while every wave gets a pair,
+        // then single tiles
         const int ptl = (cnt + 15) >> 4;
-        for (int t = wave; t < ptl; t += kWaves) passive_tile(S, G, cnt, t);
+        int t0 = 0;
+        for (; ptl - t0 >= 2 * kWaves; t0 += 2 * kWaves) {
+            const int tt[2] = {t0 + wave, t0 + kWaves + wave};
+            passive_tiles<2>(S, G, cnt, tt);
+        }
+        for (int t = t0 + wave; t < ptl; t += kWaves) {
+            const int tt[1] = {t};
+            passive_tiles<1>(S, G, cnt, tt);
+        }
     }
 
     // (c) db4 = s4 = sum_i dpre4_i; global MLP adjoint: dg' = W4[:, 64:]^T s4,
