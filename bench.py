@@ -88,16 +88,17 @@ def rollout(args, mode):
     gu = t(np.random.default_rng(11).standard_normal((3, E, N)), torch.float32)
     grot, gtr = torch.empty((E, O, 9), device=dev), torch.empty((E, O, 3), device=dev)
     gal, gph = torch.empty((K,), device=dev), torch.empty((17411,), device=dev)
+    saved = _native.saved_buffer(plan, E)
 
     if not args.no_autotune:
-        _native.etac_plan_autotune(plan, sc, md, u, cobj, na, gu, grot, gtr, gal, gph, reps=2)
+        _native.etac_plan_autotune(plan, sc, md, u, cobj, na, gu, grot, gtr, gal, gph, reps=2, saved=saved)
 
     def body(with_bwd):
         rot.copy_(torch.index_select(trot, 0, step_idx)[0])
         trans.copy_(torch.index_select(ttr, 0, step_idx)[0])
-        _native.etac_step(plan, sc, md, u, cobj, na)
+        _native.etac_step(plan, sc, md, u, cobj, na, saved=saved if with_bwd else None)
         if with_bwd:
-            _native.etac_step_backward(plan, sc, md, gu, grot, gtr, gal, gph)
+            _native.etac_step_backward(plan, sc, md, gu, grot, gtr, gal, gph, saved=saved)
         step_idx.add_(1).remainder_(T)
 
     out = {"envs": E, "steps": T, "workload": f"{E} envs x 16-patch hand, {T} steps of AR(1) object motion "
@@ -144,7 +145,7 @@ def work_counts(mesh, n_active):
     items = float(np.sum(hit))
     mlp_flop = 2.0 * (ENC_MAC * enc_nodes + DEC_MAC * dec_nodes + GLOBAL_MAC * items)
     return dict(pairs=pairs, mlp_flop=mlp_flop, contacted_items=items, contacted_nodes=enc_nodes,
-                active=float(m.sum()))
+                active=float(m.sum()), passive=dec_nodes)
 
 
 def algorithmic_work(kernel, counts, E, N, K, O, mode):
@@ -170,11 +171,14 @@ def algorithmic_work(kernel, counts, E, N, K, O, mode):
         return dict(mfma_flop=0.0, valu_flop=PAIR_FLOP_BWD * counts["pairs"] if decay else 0.0,
                     hbm_bytes=12.0 * counts["contacted_nodes"] + 8.0 * E * K
                     + counts["contacted_nodes"] + 24.0 * counts["active"])
-    # k_bwd: the network's forward is recomputed (no state is kept from the
-    # forward call) and both adjoint products run: 3x the forward flops
-    return dict(mfma_flop=3.0 * counts["mlp_flop"] if net else 0.0, valu_flop=0.0,
+    # k_bwd, given the forward's pooling record: on the passive nodes of
+    # contacted patches the network's forward is recomputed (encoder and
+    # decoder) and both adjoint products run, 3x those forward flops; the
+    # global MLP likewise per item.  Reads the record (512 B per item).
+    bwd_flop = 3.0 * 2.0 * ((ENC_MAC + DEC_MAC) * counts["passive"] + GLOBAL_MAC * items)
+    return dict(mfma_flop=bwd_flop if net else 0.0, valu_flop=0.0,
                 hbm_bytes=counts["contacted_nodes"] + 24.0 * counts["active"] + 48.0 * O * items
-                + (4.0 * PHI_SIZE * items if net else 0.0))
+                + ((4.0 * PHI_SIZE + 512.0) * items if net else 0.0))
 
 
 def source_digest():
@@ -264,17 +268,20 @@ def main():
     gtr = torch.empty((E, O, 3), dtype=torch.float32, device=dev)
     gal = torch.empty((K,), dtype=torch.float32, device=dev)
     gph = torch.empty((17411,), dtype=torch.float32, device=dev)
+    # the forward's pooling record, handed to the adjoint (as the autograd
+    # binding does); the forward-only figure is taken without it
+    saved = _native.saved_buffer(plan, E)
     stream = torch.cuda.current_stream(dev)
 
-    def fwd():
-        _native.etac_step(plan, sc, md, u, cobj, na)
+    def fwd(rec=saved):
+        _native.etac_step(plan, sc, md, u, cobj, na, saved=rec)
 
     def bwd():
-        _native.etac_step_backward(plan, sc, md, grad_u, grot, gtr, gal, gph)
+        _native.etac_step_backward(plan, sc, md, grad_u, grot, gtr, gal, gph, saved=saved)
 
     # launch shapes chosen by the library's autotuner on this workload
     if not args.no_autotune:
-        _native.etac_plan_autotune(plan, sc, md, u, cobj, na, grad_u, grot, gtr, gal, gph, reps=2)
+        _native.etac_plan_autotune(plan, sc, md, u, cobj, na, grad_u, grot, gtr, gal, gph, reps=2, saved=saved)
     launch_shape = plan.launch()
 
     graph = None
@@ -327,7 +334,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for _ in range(args.steps):
-        fwd()
+        fwd(None)
     torch.cuda.synchronize()
     fwd_only_ms = (time.perf_counter() - t1) * 1e3 / args.steps
 

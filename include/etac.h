@@ -140,16 +140,37 @@ etac_status etac_plan_destroy(etac_plan *plan);
 etac_status etac_contact(etac_plan *plan, const etac_scene *scene, int8_t *contact_obj,
                          float *uhat, int32_t *n_active, void *stream);
 
+/* Pooling record of a forward call, for the adjoint (optional).  The
+ * residual network (Eq. 2) max-pools its per-node encoder features over the
+ * patch; the adjoint needs the pooled features and, per channel, the node
+ * that attains the maximum.  A forward call given `saved` writes, for every
+ * (env e, patch k) item with at least one active node and a model that uses
+ * the residual, ETAC_SAVED_WORDS 32-bit words at word offset
+ * (e K + k) ETAC_SAVED_WORDS: words 0..63 the pooled features (float),
+ * words 64..127 the arg-max node of each channel (int32, index within the
+ * patch, lowest index on ties).  Other items are not written.  An adjoint
+ * call given the same buffer reads these records instead of repeating the
+ * encoder pass over every node of the contacted patches; it must come from
+ * the forward call on the same inputs (same scene or contact results, same
+ * model, same n_envs), which nothing can check.  With saved = NULL the
+ * adjoint recomputes them; both give identical results.  Size:
+ * n_envs K ETAC_SAVED_WORDS 4 bytes. */
+#define ETAC_SAVED_WORDS 128
+
 /* Propagation of given contact results (Eqs. 1-2).  Inputs DEVICE:
  * contact_obj [E][N] (any value >= 0 marks an active node), uhat [3][E][N]
- * (read on active nodes only).  Output DEVICE: u [3][E][N].  E = n_envs. */
+ * (read on active nodes only).  Output DEVICE: u [3][E][N].  E = n_envs.
+ * saved (DEVICE, may be NULL): the pooling record for the adjoint. */
 etac_status etac_propagate(etac_plan *plan, const etac_model *model, int32_t n_envs,
-                           const int8_t *contact_obj, const float *uhat, float *u, void *stream);
+                           const int8_t *contact_obj, const float *uhat, float *u, void *saved,
+                           void *stream);
 
 /* Whole step, contact + propagation, as one persistent fused launch.
- * Outputs DEVICE: u [3][E][N], contact_obj [E][N], n_active [E][K]. */
+ * Outputs DEVICE: u [3][E][N], contact_obj [E][N], n_active [E][K].
+ * saved (DEVICE, may be NULL): the pooling record for the adjoint, see
+ * ETAC_SAVED_WORDS. */
 etac_status etac_step(etac_plan *plan, const etac_scene *scene, const etac_model *model,
-                      float *u, int8_t *contact_obj, int32_t *n_active, void *stream);
+                      float *u, int8_t *contact_obj, int32_t *n_active, void *saved, void *stream);
 
 /* Adjoint of the contact pass: given dL/du_hat [3][E][N] (DEVICE; read on
  * active nodes only) returns dL/dR [E][O][9] and dL/dt [E][O][3] (DEVICE,
@@ -161,17 +182,21 @@ etac_status etac_contact_backward(etac_plan *plan, const etac_scene *scene, cons
 /* Adjoint of the propagation: given contact_obj, uhat and dL/du [3][E][N]
  * returns dL/du_hat [3][E][N] (0 on passive nodes), dL/dalpha [K] and
  * dL/dphi [ETAC_PHI_SIZE] (all DEVICE, overwritten; grad_alpha / grad_phi may
- * be NULL to skip).  Needs a plan created with ETAC_PLAN_BACKWARD. */
+ * be NULL to skip).  saved: NULL, or the pooling record written by
+ * etac_propagate on the same inputs.  Needs a plan created with
+ * ETAC_PLAN_BACKWARD. */
 etac_status etac_propagate_backward(etac_plan *plan, const etac_model *model, int32_t n_envs,
                                     const int8_t *contact_obj, const float *uhat,
-                                    const float *grad_u, float *grad_uhat, float *grad_alpha,
-                                    float *grad_phi, void *stream);
+                                    const float *grad_u, const void *saved, float *grad_uhat,
+                                    float *grad_alpha, float *grad_phi, void *stream);
 
-/* Adjoint of the whole step (recomputes contact; nothing from the forward
- * call is needed).  Outputs as above.  Needs ETAC_PLAN_BACKWARD. */
+/* Adjoint of the whole step.  It recomputes the contact pass; the only thing
+ * it can take from the forward call is the optional pooling record `saved`
+ * (NULL, or written by etac_step on the same inputs).  Outputs as above.
+ * Needs ETAC_PLAN_BACKWARD. */
 etac_status etac_step_backward(etac_plan *plan, const etac_scene *scene, const etac_model *model,
-                               const float *grad_u, float *grad_rot, float *grad_trans,
-                               float *grad_alpha, float *grad_phi, void *stream);
+                               const float *grad_u, const void *saved, float *grad_rot,
+                               float *grad_trans, float *grad_alpha, float *grad_phi, void *stream);
 
 /* Human-readable text of a status code (static storage). */
 const char *etac_status_string(etac_status status);
@@ -206,7 +231,8 @@ etac_status etac_plan_get_launch(const etac_plan *plan, int32_t *shape);
 
 /* Autotuner.  Times every candidate launch shape of the persistent kernels
  * on the caller's inputs (as for etac_step and etac_step_backward; all
- * DEVICE pointers, outputs overwritten) with HIP events over `reps` calls
+ * DEVICE pointers, outputs overwritten; `saved` may be NULL and is passed to
+ * both calls) with HIP events over `reps` calls
  * (1 .. 1000) after a warm-up call, and keeps the fastest: forward
  * workgroups per CU in {1, 2} x batch in {1, 2, 4, 8, 16}; with grad_u
  * non-NULL also decay-kernel workgroups per CU in {2, 3, 4} x adjoint batch
@@ -216,8 +242,8 @@ etac_status etac_plan_get_launch(const etac_plan *plan, int32_t *shape);
  * must not be called during stream capture (ETAC_ERR_CAPTURE). */
 etac_status etac_plan_autotune(etac_plan *plan, const etac_scene *scene, const etac_model *model,
                                const float *grad_u, float *u, int8_t *contact_obj, int32_t *n_active,
-                               float *grad_rot, float *grad_trans, float *grad_alpha, float *grad_phi,
-                               int32_t reps, int32_t *best, void *stream);
+                               void *saved, float *grad_rot, float *grad_trans, float *grad_alpha,
+                               float *grad_phi, int32_t reps, int32_t *best, void *stream);
 
 /* Kernel timing (diagnostics, not part of the method).  With timing on, every
  * launch of a timed kernel made outside stream capture is bracketed by a pair

@@ -20,6 +20,7 @@ ETAC_OK = 0
 ETAC_SPHERE, ETAC_BOX, ETAC_CAPSULE = 0, 1, 2
 ETAC_FULL, ETAC_DECAY_ONLY, ETAC_RESIDUAL_ONLY = 0, 1, 2
 ETAC_PHI_SIZE = 17411
+ETAC_SAVED_WORDS = 128     # 32-bit words of the pooling record per (env, patch) item
 ETAC_MAX_OBJ = 8
 ETAC_PLAN_BACKWARD = 1
 ETAC_TIMER_CONTACT, ETAC_TIMER_STEP, ETAC_TIMER_BACKWARD, ETAC_TIMER_REDUCE, ETAC_TIMER_BWD_DECAY = 0, 1, 2, 3, 4
@@ -75,11 +76,11 @@ def lib():
             "etac_plan_create": ([P(etac_mesh), i32, i32, C.c_uint32, P(vp)], i32),
             "etac_plan_destroy": ([vp], i32),
             "etac_contact": ([vp, P(etac_scene), vp, vp, vp, vp], i32),
-            "etac_propagate": ([vp, P(etac_model), i32, vp, vp, vp, vp], i32),
-            "etac_step": ([vp, P(etac_scene), P(etac_model), vp, vp, vp, vp], i32),
+            "etac_propagate": ([vp, P(etac_model), i32, vp, vp, vp, vp, vp], i32),
+            "etac_step": ([vp, P(etac_scene), P(etac_model), vp, vp, vp, vp, vp], i32),
             "etac_contact_backward": ([vp, P(etac_scene), vp, vp, vp, vp], i32),
-            "etac_propagate_backward": ([vp, P(etac_model), i32, vp, vp, vp, vp, vp, vp, vp], i32),
-            "etac_step_backward": ([vp, P(etac_scene), P(etac_model), vp, vp, vp, vp, vp, vp], i32),
+            "etac_propagate_backward": ([vp, P(etac_model), i32, vp, vp, vp, vp, vp, vp, vp, vp], i32),
+            "etac_step_backward": ([vp, P(etac_scene), P(etac_model), vp, vp, vp, vp, vp, vp, vp], i32),
             "etac_status_string": ([i32], C.c_char_p),
             "etac_last_hip_error": ([], i32),
             "etac_plan_info": ([vp, P(i32), P(i32), P(i64)], i32),
@@ -88,8 +89,8 @@ def lib():
             "etac_plan_set_batch": ([vp, i32], i32),
             "etac_plan_set_launch": ([vp, i32, i32, i32, i32], i32),
             "etac_plan_get_launch": ([vp, P(i32)], i32),
-            "etac_plan_autotune": ([vp, P(etac_scene), P(etac_model), vp, vp, vp, vp, vp, vp, vp, vp, i32, P(i32),
-                                    vp], i32),
+            "etac_plan_autotune": ([vp, P(etac_scene), P(etac_model), vp, vp, vp, vp, vp, vp, vp, vp, vp, i32,
+                                    P(i32), vp], i32),
             "etac_plan_kernel_time": ([vp, i32, P(i32), P(C.c_double)], i32),
         }
         for name, (args, res) in sig.items():
@@ -222,24 +223,33 @@ def etac_contact(plan, scene, contact_obj, uhat, n_active):
                                               _ptr(n_active), _stream(plan.device)))
 
 
-def etac_propagate(plan, model, n_envs, contact_obj, uhat, u):
+def saved_buffer(plan, n_envs):
+    """A pooling-record buffer for n_envs envs (int32 [E K][ETAC_SAVED_WORDS],
+    contents written by a forward call given it)."""
+    import torch
+    return torch.empty((int(n_envs) * plan.K, ETAC_SAVED_WORDS), dtype=torch.int32, device=plan.device)
+
+
+def etac_propagate(plan, model, n_envs, contact_obj, uhat, u, saved=None):
     import torch
     E = int(n_envs)
     _req(contact_obj, torch.int8, (E, plan.N), "contact_obj", plan.device)
     _req(uhat, torch.float32, (3, E, plan.N), "uhat", plan.device)
     _req(u, torch.float32, (3, E, plan.N), "u", plan.device)
+    _req(saved, torch.int32, (E * plan.K, ETAC_SAVED_WORDS), "saved", plan.device)
     _check("etac_propagate", lib().etac_propagate(plan.handle, C.byref(model), E, _ptr(contact_obj), _ptr(uhat),
-                                                  _ptr(u), _stream(plan.device)))
+                                                  _ptr(u), _ptr(saved), _stream(plan.device)))
 
 
-def etac_step(plan, scene, model, u, contact_obj, n_active):
+def etac_step(plan, scene, model, u, contact_obj, n_active, saved=None):
     import torch
     E = scene.n_envs
     _req(u, torch.float32, (3, E, plan.N), "u", plan.device)
     _req(contact_obj, torch.int8, (E, plan.N), "contact_obj", plan.device)
     _req(n_active, torch.int32, (E, plan.K), "n_active", plan.device)
+    _req(saved, torch.int32, (E * plan.K, ETAC_SAVED_WORDS), "saved", plan.device)
     _check("etac_step", lib().etac_step(plan.handle, C.byref(scene), C.byref(model), _ptr(u), _ptr(contact_obj),
-                                        _ptr(n_active), _stream(plan.device)))
+                                        _ptr(n_active), _ptr(saved), _stream(plan.device)))
 
 
 def etac_contact_backward(plan, scene, grad_uhat, grad_rot, grad_trans):
@@ -253,9 +263,11 @@ def etac_contact_backward(plan, scene, grad_uhat, grad_rot, grad_trans):
                                                                 _stream(plan.device)))
 
 
-def etac_propagate_backward(plan, model, n_envs, contact_obj, uhat, grad_u, grad_uhat, grad_alpha, grad_phi):
+def etac_propagate_backward(plan, model, n_envs, contact_obj, uhat, grad_u, grad_uhat, grad_alpha, grad_phi,
+                            saved=None):
     import torch
     E = int(n_envs)
+    _req(saved, torch.int32, (E * plan.K, ETAC_SAVED_WORDS), "saved", plan.device)
     _req(contact_obj, torch.int8, (E, plan.N), "contact_obj", plan.device)
     _req(uhat, torch.float32, (3, E, plan.N), "uhat", plan.device)
     _req(grad_u, torch.float32, (3, E, plan.N), "grad_u", plan.device)
@@ -264,25 +276,27 @@ def etac_propagate_backward(plan, model, n_envs, contact_obj, uhat, grad_u, grad
     _req(grad_phi, torch.float32, (ETAC_PHI_SIZE,), "grad_phi", plan.device)
     _check("etac_propagate_backward",
            lib().etac_propagate_backward(plan.handle, C.byref(model), E, _ptr(contact_obj), _ptr(uhat),
-                                         _ptr(grad_u), _ptr(grad_uhat), _ptr(grad_alpha), _ptr(grad_phi),
-                                         _stream(plan.device)))
+                                         _ptr(grad_u), _ptr(saved), _ptr(grad_uhat), _ptr(grad_alpha),
+                                         _ptr(grad_phi), _stream(plan.device)))
 
 
-def etac_step_backward(plan, scene, model, grad_u, grad_rot, grad_trans, grad_alpha, grad_phi):
+def etac_step_backward(plan, scene, model, grad_u, grad_rot, grad_trans, grad_alpha, grad_phi, saved=None):
     import torch
     E, O = scene.n_envs, scene.max_obj
+    _req(saved, torch.int32, (E * plan.K, ETAC_SAVED_WORDS), "saved", plan.device)
     _req(grad_u, torch.float32, (3, E, plan.N), "grad_u", plan.device)
     _req(grad_rot, torch.float32, (E, O, 9), "grad_rot", plan.device)
     _req(grad_trans, torch.float32, (E, O, 3), "grad_trans", plan.device)
     _req(grad_alpha, torch.float32, (plan.K,), "grad_alpha", plan.device)
     _req(grad_phi, torch.float32, (ETAC_PHI_SIZE,), "grad_phi", plan.device)
     _check("etac_step_backward",
-           lib().etac_step_backward(plan.handle, C.byref(scene), C.byref(model), _ptr(grad_u), _ptr(grad_rot),
-                                    _ptr(grad_trans), _ptr(grad_alpha), _ptr(grad_phi), _stream(plan.device)))
+           lib().etac_step_backward(plan.handle, C.byref(scene), C.byref(model), _ptr(grad_u), _ptr(saved),
+                                    _ptr(grad_rot), _ptr(grad_trans), _ptr(grad_alpha), _ptr(grad_phi),
+                                    _stream(plan.device)))
 
 
 def etac_plan_autotune(plan, scene, model, u, contact_obj, n_active, grad_u=None, grad_rot=None, grad_trans=None,
-                       grad_alpha=None, grad_phi=None, reps=3):
+                       grad_alpha=None, grad_phi=None, reps=3, saved=None):
     """Time the candidate launch shapes on these inputs, keep the fastest and
     return it as (fwd workgroups per CU, fwd batch, adjoint batch, decay
     workgroups per CU).  With grad_u None only the forward is tuned."""
@@ -291,6 +305,7 @@ def etac_plan_autotune(plan, scene, model, u, contact_obj, n_active, grad_u=None
     _req(u, torch.float32, (3, E, plan.N), "u", plan.device)
     _req(contact_obj, torch.int8, (E, plan.N), "contact_obj", plan.device)
     _req(n_active, torch.int32, (E, plan.K), "n_active", plan.device)
+    _req(saved, torch.int32, (E * plan.K, ETAC_SAVED_WORDS), "saved", plan.device)
     if grad_u is not None:
         _req(grad_u, torch.float32, (3, E, plan.N), "grad_u", plan.device)
         _req(grad_rot, torch.float32, (E, O, 9), "grad_rot", plan.device)
@@ -300,6 +315,6 @@ def etac_plan_autotune(plan, scene, model, u, contact_obj, n_active, grad_u=None
     best = (C.c_int32 * 4)()
     _check("etac_plan_autotune",
            lib().etac_plan_autotune(plan.handle, C.byref(scene), C.byref(model), _ptr(grad_u), _ptr(u),
-                                    _ptr(contact_obj), _ptr(n_active), _ptr(grad_rot), _ptr(grad_trans),
+                                    _ptr(contact_obj), _ptr(n_active), _ptr(saved), _ptr(grad_rot), _ptr(grad_trans),
                                     _ptr(grad_alpha), _ptr(grad_phi), int(reps), best, _stream(plan.device)))
     return tuple(best)

@@ -4,7 +4,9 @@ ETacStep.apply(plan, n_obj, type, shape, rot, trans, alpha, phi, mode)
 returns (u [3][E][N], contact_obj [E][N], n_active [E][K]); gradients flow to
 rot [E][O][9], trans [E][O][3], alpha [K] and phi [17411].  The forward runs
 etac_step, the backward runs etac_step_backward, which recomputes the contact
-pass (nothing but the inputs is saved).  Argument marshalling only.
+pass; besides the inputs only the network's pooling record (pooled features
+and their arg-max nodes, 512 bytes per (env, patch) item) is saved.  Argument
+marshalling only.
 """
 import torch
 
@@ -23,15 +25,16 @@ class ETacStep(torch.autograd.Function):
         u = torch.empty((3, E, plan.N), dtype=torch.float32, device=dev)
         cobj = torch.empty((E, plan.N), dtype=torch.int8, device=dev)
         na = torch.empty((E, plan.K), dtype=torch.int32, device=dev)
-        _native.etac_step(plan, sc, md, u, cobj, na)
+        saved = _native.saved_buffer(plan, E)
+        _native.etac_step(plan, sc, md, u, cobj, na, saved=saved)
         ctx.plan, ctx.mode = plan, int(mode)
-        ctx.save_for_backward(n_obj, type_, shape, rot, trans, alpha, phi)
+        ctx.save_for_backward(n_obj, type_, shape, rot, trans, alpha, phi, saved)
         ctx.mark_non_differentiable(cobj, na)
         return u, cobj, na
 
     @staticmethod
     def backward(ctx, grad_u, _grad_cobj, _grad_na):
-        n_obj, type_, shape, rot, trans, alpha, phi = ctx.saved_tensors
+        n_obj, type_, shape, rot, trans, alpha, phi, saved = ctx.saved_tensors
         plan = ctx.plan
         sc = plan.scene_struct(n_obj, type_, shape, rot, trans)
         md = plan.model_struct(ctx.mode, alpha, phi)
@@ -40,7 +43,7 @@ class ETacStep(torch.autograd.Function):
         gtr = torch.empty_like(trans)
         gal = torch.empty_like(alpha)
         gph = torch.empty_like(phi)
-        _native.etac_step_backward(plan, sc, md, gu, grot, gtr, gal, gph)
+        _native.etac_step_backward(plan, sc, md, gu, grot, gtr, gal, gph, saved=saved)
         return None, None, None, None, grot, gtr, gal, gph, None
 
 

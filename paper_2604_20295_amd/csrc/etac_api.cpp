@@ -359,19 +359,19 @@ etac_status etac_contact(etac_plan *plan, const etac_scene *scene, int8_t *conta
 }
 
 etac_status etac_propagate(etac_plan *plan, const etac_model *model, int32_t n_envs, const int8_t *contact_obj,
-                           const float *uhat, float *u, void *stream) {
+                           const float *uhat, float *u, void *saved, void *stream) {
     if (!plan) return ETAC_ERR_NULL;
     etac_status st = check_model(model);
     if (st != ETAC_OK) return st;
     if (n_envs < 0 || n_envs > plan->p.n_envs) return ETAC_ERR_SHAPE;
     if (n_envs > 0 && (!contact_obj || !uhat || !u)) return ETAC_ERR_NULL;
     hipError_t e = etac::launch_step(plan->p, nullptr, model_dev(model), n_envs, contact_obj, uhat, u, nullptr,
-                                     nullptr, (hipStream_t)stream);
+                                     nullptr, static_cast<uint32_t *>(saved), (hipStream_t)stream);
     return e == hipSuccess ? ETAC_OK : hip_fail(e);
 }
 
 etac_status etac_step(etac_plan *plan, const etac_scene *scene, const etac_model *model, float *u,
-                      int8_t *contact_obj, int32_t *n_active, void *stream) {
+                      int8_t *contact_obj, int32_t *n_active, void *saved, void *stream) {
     if (!plan) return ETAC_ERR_NULL;
     etac_status st = check_scene(plan->p, scene);
     if (st != ETAC_OK) return st;
@@ -380,7 +380,7 @@ etac_status etac_step(etac_plan *plan, const etac_scene *scene, const etac_model
     if (scene->n_envs > 0 && (!u || !contact_obj || !n_active)) return ETAC_ERR_NULL;
     const etac::SceneDev sd = scene_dev(scene);
     hipError_t e = etac::launch_step(plan->p, &sd, model_dev(model), scene->n_envs, nullptr, nullptr, u,
-                                     contact_obj, n_active, (hipStream_t)stream);
+                                     contact_obj, n_active, static_cast<uint32_t *>(saved), (hipStream_t)stream);
     return e == hipSuccess ? ETAC_OK : hip_fail(e);
 }
 
@@ -398,7 +398,8 @@ etac_status etac_contact_backward(etac_plan *plan, const etac_scene *scene, cons
 
 etac_status etac_propagate_backward(etac_plan *plan, const etac_model *model, int32_t n_envs,
                                     const int8_t *contact_obj, const float *uhat, const float *grad_u,
-                                    float *grad_uhat, float *grad_alpha, float *grad_phi, void *stream) {
+                                    const void *saved, float *grad_uhat, float *grad_alpha, float *grad_phi,
+                                    void *stream) {
     if (!plan) return ETAC_ERR_NULL;
     etac_status st = check_model(model);
     if (st != ETAC_OK) return st;
@@ -406,13 +407,14 @@ etac_status etac_propagate_backward(etac_plan *plan, const etac_model *model, in
     if (n_envs > 0 && (!contact_obj || !uhat || !grad_u || !grad_uhat)) return ETAC_ERR_NULL;
     if (!plan->p.has_bwd) return ETAC_ERR_WORKSPACE;
     hipError_t e = etac::launch_backward(plan->p, nullptr, model_dev(model), n_envs, contact_obj, uhat, grad_u,
-                                         grad_uhat, nullptr, nullptr, grad_alpha, grad_phi, (hipStream_t)stream);
+                                         static_cast<const uint32_t *>(saved), grad_uhat, nullptr, nullptr,
+                                         grad_alpha, grad_phi, (hipStream_t)stream);
     return e == hipSuccess ? ETAC_OK : hip_fail(e);
 }
 
 etac_status etac_step_backward(etac_plan *plan, const etac_scene *scene, const etac_model *model,
-                               const float *grad_u, float *grad_rot, float *grad_trans, float *grad_alpha,
-                               float *grad_phi, void *stream) {
+                               const float *grad_u, const void *saved, float *grad_rot, float *grad_trans,
+                               float *grad_alpha, float *grad_phi, void *stream) {
     if (!plan) return ETAC_ERR_NULL;
     etac_status st = check_scene(plan->p, scene);
     if (st != ETAC_OK) return st;
@@ -422,14 +424,15 @@ etac_status etac_step_backward(etac_plan *plan, const etac_scene *scene, const e
     if (!plan->p.has_bwd) return ETAC_ERR_WORKSPACE;
     const etac::SceneDev sd = scene_dev(scene);
     hipError_t e = etac::launch_backward(plan->p, &sd, model_dev(model), scene->n_envs, nullptr, nullptr, grad_u,
-                                         nullptr, grad_rot, grad_trans, grad_alpha, grad_phi, (hipStream_t)stream);
+                                         static_cast<const uint32_t *>(saved), nullptr, grad_rot, grad_trans,
+                                         grad_alpha, grad_phi, (hipStream_t)stream);
     return e == hipSuccess ? ETAC_OK : hip_fail(e);
 }
 
 etac_status etac_plan_autotune(etac_plan *plan, const etac_scene *scene, const etac_model *model,
                                const float *grad_u, float *u, int8_t *contact_obj, int32_t *n_active,
-                               float *grad_rot, float *grad_trans, float *grad_alpha, float *grad_phi,
-                               int32_t reps, int32_t *best, void *stream) {
+                               void *saved, float *grad_rot, float *grad_trans, float *grad_alpha,
+                               float *grad_phi, int32_t reps, int32_t *best, void *stream) {
     if (!plan) return ETAC_ERR_NULL;
     if (reps < 1 || reps > 1000) return ETAC_ERR_VALUE;
     etac::Plan &p = plan->p;
@@ -437,10 +440,11 @@ etac_status etac_plan_autotune(etac_plan *plan, const etac_scene *scene, const e
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return ETAC_ERR_CAPTURE;
     // one validated call of each before any timing (argument errors come back here)
-    etac_status s = etac_step(plan, scene, model, u, contact_obj, n_active, stream);
+    etac_status s = etac_step(plan, scene, model, u, contact_obj, n_active, saved, stream);
     if (s != ETAC_OK) return s;
     if (grad_u) {
-        s = etac_step_backward(plan, scene, model, grad_u, grad_rot, grad_trans, grad_alpha, grad_phi, stream);
+        s = etac_step_backward(plan, scene, model, grad_u, saved, grad_rot, grad_trans, grad_alpha, grad_phi,
+                               stream);
         if (s != ETAC_OK) return s;
     }
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -450,9 +454,9 @@ etac_status etac_plan_autotune(etac_plan *plan, const etac_scene *scene, const e
     auto timed = [&](bool fwd, float &ms) -> etac_status {
         for (int r = 0; r <= reps; ++r) {
             if (r == 1 && hipEventRecord(ev[0], st) != hipSuccess) return ETAC_ERR_HIP;
-            const etac_status q = fwd ? etac_step(plan, scene, model, u, contact_obj, n_active, stream)
-                                      : etac_step_backward(plan, scene, model, grad_u, grad_rot, grad_trans,
-                                                           grad_alpha, grad_phi, stream);
+            const etac_status q = fwd ? etac_step(plan, scene, model, u, contact_obj, n_active, saved, stream)
+                                      : etac_step_backward(plan, scene, model, grad_u, saved, grad_rot,
+                                                           grad_trans, grad_alpha, grad_phi, stream);
             if (q != ETAC_OK) return q;
         }
         hipError_t h = hipEventRecord(ev[1], st);

@@ -42,6 +42,7 @@ struct BwdParams {
     const float *grad_u;          // [3][E][N]   BWD_STEP, BWD_PROP
     const float *grad_uhat_in;    // [3][E][N]   BWD_CONTACT
     float *grad_uhat_out;         // [3][E][N]   BWD_PROP
+    const uint32_t *saved;        // [E K][kSavedWords] pooling record of the forward, or null
 };
 
 constexpr int kTrRow = 20;     // padded row of the block transpose buffer: conflict-free stores, aligned loads
@@ -1054,20 +1055,13 @@ __device__ __forceinline__ void store_partials(BwdLds &S, const WGrad &G, float 
     }
 }
 
-// Residual-network adjoint of one item; writes its parameter-gradient
-// partial and adds dL/du_hat of active arg-max nodes into gh.
-__device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, int item, int base, int n, int np,
-                                 const int *plist, const float *uhn, const int8_t *wobj, float *gh) {
+// Max-pool of the item's encoder features with, per channel, the arg-max
+// node (lowest index on ties) recomputed over every node: L.g, S.argmax.
+__device__ void pool_argmax(const BwdParams &p, BwdLds &S, int k, int base, int n, const float *uhn) {
     NetLds &L = S.net;
     const MeshDev &M = p.mesh;
-    const float *phi = p.model.phi;
-    const int N = M.N, n_max = p.scr.n_max;
-    const size_t EN = (size_t)p.E * N;
-    const size_t row = (size_t)e * N + base;
+    const int n_max = p.scr.n_max;
     const int lane = lane_id(), wave = threadIdx.x >> 6, gq = lane >> 4;
-    float *out = p.bwd.phi_part + (size_t)item * kPhiN;
-
-    // (a) encoder pass: max-pool with arg-max (lowest node on ties)
     floatx4 mx[4];
     int mi[4][4];
     #pragma unroll
@@ -1141,6 +1135,36 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
         S.argmax[c] = ix;
     }
     __syncthreads();
+}
+
+// Residual-network adjoint of one item; writes its parameter-gradient
+// partial and adds dL/du_hat of active arg-max nodes into gh.
+__device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, int item, int base, int n, int np,
+                                 const int *plist, const float *uhn, const int8_t *wobj, float *gh) {
+    NetLds &L = S.net;
+    const MeshDev &M = p.mesh;
+    const float *phi = p.model.phi;
+    const int N = M.N, n_max = p.scr.n_max;
+    const size_t EN = (size_t)p.E * N;
+    const size_t row = (size_t)e * N + base;
+    const int lane = lane_id(), wave = threadIdx.x >> 6;
+    float *out = p.bwd.phi_part + (size_t)item * kPhiN;
+
+    // (a) max-pool with arg-max (lowest node on ties): from the forward's
+    //     record, else an encoder pass over every node of the item
+    if (p.saved) {
+        if (threadIdx.x < 64) {
+            const uint32_t *rec = p.saved + (size_t)item * kSavedWords;
+            L.g[threadIdx.x] = __uint_as_float(rec[threadIdx.x]);
+            // a node outside the patch (a record not written for this item)
+            // becomes "no node": wrong gradients, never an access outside it
+            const int a = (int)rec[64 + threadIdx.x];
+            S.argmax[threadIdx.x] = (a >= 0 && a < n) ? a : n;
+        }
+        __syncthreads();
+    } else {
+        pool_argmax(p, S, k, base, n, uhn);
+    }
     global_mlp(L, phi);
 
     // (b) decoder and encoder adjoints over the passive nodes, tile t on wave t % 4
@@ -1574,8 +1598,9 @@ __global__ __launch_bounds__(256) void k_pose(const float *part, int E, int K, i
 }
 
 hipError_t launch_backward(const Plan &pl, const SceneDev *s, const ModelDev &m, int n_envs, const int8_t *cobj_in,
-                           const float *uhat_in, const float *grad_u, float *grad_uhat, float *grad_rot,
-                           float *grad_trans, float *grad_alpha, float *grad_phi, hipStream_t st) {
+                           const float *uhat_in, const float *grad_u, const uint32_t *saved, float *grad_uhat,
+                           float *grad_rot, float *grad_trans, float *grad_alpha, float *grad_phi,
+                           hipStream_t st) {
     if (n_envs == 0) return hipSuccess;
     BwdParams p;
     p.mesh = pl.mesh;
@@ -1591,6 +1616,7 @@ hipError_t launch_backward(const Plan &pl, const SceneDev *s, const ModelDev &m,
     p.grad_u = grad_u;
     p.grad_uhat_in = nullptr;
     p.grad_uhat_out = grad_uhat;
+    p.saved = saved;
     // contact and the decay adjoint, several workgroups per CU
     const int grid_d = min(p.n_items, pl.cu_count * pl.decay_wg_per_cu);
     int slot = timer_begin(pl, ETAC_TIMER_BWD_DECAY, st);
@@ -1643,6 +1669,7 @@ hipError_t launch_contact_backward(const Plan &pl, const SceneDev &s, const floa
     p.grad_u = nullptr;
     p.grad_uhat_in = grad_uhat;
     p.grad_uhat_out = nullptr;
+    p.saved = nullptr;
     const int grid = min(p.n_items, pl.cu_count);
     hipLaunchKernelGGL(k_bwd<BWD_CONTACT>, dim3(grid), dim3(kWG), 0, st, p);
     hipError_t e = hipGetLastError();

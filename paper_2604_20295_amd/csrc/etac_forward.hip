@@ -86,6 +86,7 @@ struct StepParams {
     float *u;                // [3][E][N]
     int8_t *cobj_out;        // [E][N] (fused step)
     int32_t *n_active;       // [E][K] (fused step)
+    uint32_t *saved;         // [E K][kSavedWords] pooling record for the adjoint, or null
 };
 
 struct StepLds {
@@ -164,14 +165,18 @@ __device__ void zero_fill_batch(const StepParams &p, const ItemBatch &B, int b0)
 // the passive nodes (plist[0 .. np)), the only ones whose residual is used.
 // The encoder is recomputed in the decoder pass instead of keeping n x 64
 // features.
-__device__ void residual_item(const StepParams &p, StepLds &S, int k, int base, int n, const float *uhn,
+__device__ void residual_item(const StepParams &p, StepLds &S, int item, int k, int base, int n, const float *uhn,
                               const int *plist, int np, float *resid) {
     NetLds &L = S.net;
     const int lane = lane_id(), wave = threadIdx.x >> 6, gq = lane >> 4;
     const int n_max = p.scr.n_max;
+    // max-pool with arg-max (lowest node on ties); f >= 0 beats the initial -1
     floatx4 mx[4];
+    int mi[4][4];
     #pragma unroll
-    for (int ot = 0; ot < 4; ++ot) mx[ot] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int ot = 0; ot < 4; ++ot)
+        #pragma unroll
+        for (int r = 0; r < 4; ++r) { mx[ot][r] = -1.0f; mi[ot][r] = 0x7fffffff; }
     for (int c0 = 0; c0 < n; c0 += kStage) {
         const int cnt = min(kStage, n - c0);
         __syncthreads();
@@ -190,14 +195,17 @@ __device__ void residual_item(const StepParams &p, StepLds &S, int k, int base, 
             }
             floatx4 f[2][4];
             encoder_tile2(L, xh, xl, f);
-            // f >= 0, so padding nodes with 0 leaves the max-pool unchanged
+            // a lane meets its nodes in increasing order (tile t before t + kWaves)
 #pragma unroll
-            for (int u = 0; u < 2; ++u)
+            for (int u = 0; u < 2; ++u) {
+                const int node = c0 + (t + u * kWaves) * 16 + (lane & 15);
                 if (valid[u])
                     #pragma unroll
                     for (int ot = 0; ot < 4; ++ot)
                         #pragma unroll
-                        for (int r = 0; r < 4; ++r) mx[ot][r] = fmaxf(mx[ot][r], f[u][ot][r]);
+                        for (int r = 0; r < 4; ++r)
+                            if (f[u][ot][r] > mx[ot][r]) { mx[ot][r] = f[u][ot][r]; mi[ot][r] = node; }
+            }
         }
     }
     #pragma unroll
@@ -205,22 +213,43 @@ __device__ void residual_item(const StepParams &p, StepLds &S, int k, int base, 
         #pragma unroll
         for (int r = 0; r < 4; ++r) {
             float v = mx[ot][r];
-            v = fmaxf(v, __shfl_xor(v, 1));
-            v = fmaxf(v, __shfl_xor(v, 2));
-            v = fmaxf(v, __shfl_xor(v, 4));
-            v = fmaxf(v, __shfl_xor(v, 8));
+            int ix = mi[ot][r];
+            #pragma unroll
+            for (int off = 1; off <= 8; off <<= 1) {
+                const float v2 = __shfl_xor(v, off);
+                const int i2 = __shfl_xor(ix, off);
+                if (v2 > v || (v2 == v && i2 < ix)) { v = v2; ix = i2; }
+            }
             mx[ot][r] = v;
+            mi[ot][r] = ix;
         }
-    // after the row reduction all 16 lanes of a row hold the same maxima (identical stores)
+    // the per-wave arg-maxes go to the node stage, free once every wave is done with it
+    __syncthreads();
+    int (*ipart)[64] = reinterpret_cast<int (*)[64]>(&S.xs[0][0]);
+    // after the row reduction all 16 lanes of a row hold the same values (identical stores)
         #pragma unroll
         for (int ot = 0; ot < 4; ++ot)
             #pragma unroll
-            for (int r = 0; r < 4; ++r) L.part[wave][ot * 16 + 4 * gq + r] = mx[ot][r];
+            for (int r = 0; r < 4; ++r) {
+                L.part[wave][ot * 16 + 4 * gq + r] = mx[ot][r];
+                ipart[wave][ot * 16 + 4 * gq + r] = mi[ot][r];
+            }
     __syncthreads();
     if (threadIdx.x < 64) {
-        float v = L.part[0][threadIdx.x];
-        for (int w = 1; w < kWaves; ++w) v = fmaxf(v, L.part[w][threadIdx.x]);
-        L.g[threadIdx.x] = v;
+        const int c = threadIdx.x;
+        float v = L.part[0][c];
+        int ix = ipart[0][c];
+        for (int w = 1; w < kWaves; ++w) {
+            const float v2 = L.part[w][c];
+            const int i2 = ipart[w][c];
+            if (v2 > v || (v2 == v && i2 < ix)) { v = v2; ix = i2; }
+        }
+        L.g[c] = v;
+        if (p.saved) {
+            uint32_t *rec = p.saved + (size_t)item * kSavedWords;
+            rec[c] = __float_as_uint(v);
+            rec[64 + c] = (uint32_t)ix;
+        }
     }
     __syncthreads();
     global_mlp(L, p.model.phi);
@@ -420,7 +449,7 @@ __device__ void process_item(const StepParams &p, StepLds &S, int e, int k, unsi
     }
     const bool use_res = mode != ETAC_DECAY_ONLY, use_dec = mode != ETAC_RESIDUAL_ONLY;
     const int np = n - m;
-    if (use_res) residual_item(p, S, k, base, n, uhn, plist, np, resid);
+    if (use_res) residual_item(p, S, e * M.K + k, k, base, n, uhn, plist, np, resid);
     // exp(-alpha d) = exp2(-alpha log2(e) d)
     const float nbeta = (float)(-(double)p.model.alpha[k] * 1.4426950408889634);
     float cut2 = cutoff_d2(p.model.alpha[k]);
@@ -478,7 +507,7 @@ __global__ __launch_bounds__(kWG) void k_step(StepParams p) {
 
 hipError_t launch_step(const Plan &pl, const SceneDev *s, const ModelDev &m, int n_envs,
                        const int8_t *cobj_in, const float *uhat_in, float *u, int8_t *cobj_out,
-                       int32_t *n_active, hipStream_t st) {
+                       int32_t *n_active, uint32_t *saved, hipStream_t st) {
     if (n_envs == 0) return hipSuccess;
     StepParams p;
     p.mesh = pl.mesh;
@@ -494,6 +523,7 @@ hipError_t launch_step(const Plan &pl, const SceneDev *s, const ModelDev &m, int
     p.u = u;
     p.cobj_out = cobj_out;
     p.n_active = n_active;
+    p.saved = saved;
     const int grid = p.n_items < pl.grid ? p.n_items : pl.grid;
     const int slot = timer_begin(pl, ETAC_TIMER_STEP, st);
     if (s) hipLaunchKernelGGL(k_step<false>, dim3(grid), dim3(kWG), 0, st, p);

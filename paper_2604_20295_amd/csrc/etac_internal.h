@@ -10,6 +10,7 @@ namespace etac {
 
 constexpr int kWG = 256;           // threads per workgroup: 4 waves of 64
 constexpr int kWaves = kWG / 64;
+constexpr int kSavedWords = ETAC_SAVED_WORDS;   // pooling record per (env, patch) item
 constexpr int kMaxPatches = 1024;  // per-patch counters of the contact kernel live in LDS
 constexpr int kDefaultWgPerCu = 2;
 constexpr int kDefaultBatch = 4;   // work-queue positions claimed per atomic
@@ -118,11 +119,11 @@ hipError_t launch_contact(const Plan &p, const SceneDev &s, int8_t *cobj, float 
                           hipStream_t st);
 hipError_t launch_step(const Plan &p, const SceneDev *s, const ModelDev &m, int n_envs,
                        const int8_t *cobj_in, const float *uhat_in, float *u, int8_t *cobj_out,
-                       int32_t *n_active, hipStream_t st);
+                       int32_t *n_active, uint32_t *saved, hipStream_t st);
 hipError_t launch_backward(const Plan &p, const SceneDev *s, const ModelDev &m, int n_envs,
                            const int8_t *cobj_in, const float *uhat_in, const float *grad_u,
-                           float *grad_uhat, float *grad_rot, float *grad_trans, float *grad_alpha,
-                           float *grad_phi, hipStream_t st);
+                           const uint32_t *saved, float *grad_uhat, float *grad_rot, float *grad_trans,
+                           float *grad_alpha, float *grad_phi, hipStream_t st);
 hipError_t launch_contact_backward(const Plan &p, const SceneDev &s, const float *grad_uhat,
                                    float *grad_rot, float *grad_trans, hipStream_t st);
 

@@ -85,11 +85,11 @@ def test_calls_reject_null_plan():
     sc = _native.etac_scene()
     md = _native.etac_model()
     assert lib.etac_contact(None, C.byref(sc), None, None, None, None) == -1
-    assert lib.etac_propagate(None, C.byref(md), 1, None, None, None, None) == -1
-    assert lib.etac_step(None, C.byref(sc), C.byref(md), None, None, None, None) == -1
+    assert lib.etac_propagate(None, C.byref(md), 1, None, None, None, None, None) == -1
+    assert lib.etac_step(None, C.byref(sc), C.byref(md), None, None, None, None, None) == -1
     assert lib.etac_contact_backward(None, C.byref(sc), None, None, None, None) == -1
-    assert lib.etac_propagate_backward(None, C.byref(md), 1, None, None, None, None, None, None, None) == -1
-    assert lib.etac_step_backward(None, C.byref(sc), C.byref(md), None, None, None, None, None, None) == -1
+    assert lib.etac_propagate_backward(None, C.byref(md), 1, None, None, None, None, None, None, None, None) == -1
+    assert lib.etac_step_backward(None, C.byref(sc), C.byref(md), None, None, None, None, None, None, None) == -1
     assert lib.etac_plan_destroy(None) == 0
     assert lib.etac_plan_info(None, None, None, None) == -1
     assert lib.etac_plan_set_occupancy(None, 1) == -1
@@ -97,8 +97,8 @@ def test_calls_reject_null_plan():
     assert lib.etac_plan_set_batch(None, 4) == -1
     assert lib.etac_plan_set_launch(None, 0, 0, 0, 0) == -1
     assert lib.etac_plan_get_launch(None, None) == -1
-    assert lib.etac_plan_autotune(None, None, None, None, None, None, None, None, None, None, None, 1, None,
-                                  None) == -1
+    assert lib.etac_plan_autotune(None, None, None, None, None, None, None, None, None, None, None, None, 1,
+                                  None, None) == -1
     n, ms = C.c_int32(), C.c_double()
     assert lib.etac_plan_kernel_time(None, 0, C.byref(n), C.byref(ms)) == -1
 

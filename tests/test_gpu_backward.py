@@ -36,17 +36,26 @@ def _close(gpu, ref, name, rel=1e-4, atol=1e-6):
     assert err <= bound, name
 
 
-def gpu_step_backward(plan, scene, model, grad_u):
+def gpu_step_backward(plan, scene, model, grad_u, saved=False):
+    """etac_step_backward; with saved=True the forward's pooling record is
+    taken first (etac_step with a saved buffer) and handed to the adjoint."""
     from paper_2604_20295_amd import _native
     torch, dev = torch_dev()
     ds, dm = DevScene(scene), DevModel(model)
     E, O = ds.E, ds.O
+    rec = None
+    if saved:
+        rec = torch.full((E * plan.K, _native.ETAC_SAVED_WORDS), -1, dtype=torch.int32, device=dev)
+        u = torch.empty((3, E, plan.N), device=dev)
+        cobj = torch.empty((E, plan.N), dtype=torch.int8, device=dev)
+        na = torch.empty((E, plan.K), dtype=torch.int32, device=dev)
+        _native.etac_step(plan, ds.struct(plan), dm.struct(plan), u, cobj, na, saved=rec)
     gu = to_dev(grad_u.astype(np.float32))
     grot = torch.full((E, O, 9), float("nan"), device=dev)
     gt = torch.full((E, O, 3), float("nan"), device=dev)
     ga = torch.full((plan.K,), float("nan"), device=dev)
     gp = torch.full((17411,), float("nan"), device=dev)
-    _native.etac_step_backward(plan, ds.struct(plan), dm.struct(plan), gu, grot, gt, ga, gp)
+    _native.etac_step_backward(plan, ds.struct(plan), dm.struct(plan), gu, grot, gt, ga, gp, saved=rec)
     torch.cuda.synchronize()
     return dict(grad_rot=grot.cpu().numpy(), grad_trans=gt.cpu().numpy(), grad_alpha=ga.cpu().numpy(),
                 grad_phi=gp.cpu().numpy())
@@ -243,3 +252,138 @@ def test_hires_pads_backward_full_size_sampled(oracle_lib):
     ref = oracle_lib.backward(mesh, scene.select(envs), model, w[:, envs].astype(np.float64))
     _close(g["grad_trans"][envs], ref["grad_trans"], "grad_trans")
     _close(g["grad_rot"][envs], ref["grad_rot"], "grad_rot")
+
+
+# ---------------------------------------------------------------------------
+# the forward's pooling record (ETAC_SAVED_WORDS per (env, patch) item)
+# ---------------------------------------------------------------------------
+
+def _pool_f64(mesh, model, cobj, uhat, e, k):
+    """Max-pooled encoder features and their arg-max nodes of one item in
+    float64 (the independent torch formulation's encoder), plus per channel
+    the gap to the runner-up value."""
+    import torch
+    from tests.torch_ref import unpack_phi
+    W = unpack_phi(torch.tensor(model.phi.astype(np.float64)))
+    a, b = int(mesh.patch_offset[k]), int(mesh.patch_offset[k + 1])
+    P = torch.tensor(mesh.pos[:, a:b].T.astype(np.float64))
+    Nn = torch.tensor(mesh.nrm[:, a:b].T.astype(np.float64))
+    act = torch.tensor(cobj[e, a:b] >= 0)
+    Uh = torch.tensor(np.moveaxis(uhat[:, e, a:b], 0, 1).astype(np.float64))
+    Uh = torch.where(act[:, None], Uh, torch.zeros_like(Uh))
+    x = torch.cat([P - torch.tensor(mesh.origin[k].astype(np.float64)), Nn, Uh], dim=1)
+    f = torch.relu(torch.relu(x @ W["W1"].T + W["b1"]) @ W["W2"].T + W["b2"])
+    g = f.amax(dim=0)
+    arg = f.argmax(dim=0)              # first maximal node on ties
+    top2 = torch.topk(f, min(2, f.shape[0]), dim=0).values
+    gap = (top2[0] - top2[-1]) if f.shape[0] > 1 else torch.full_like(g, float("inf"))
+    return g.numpy(), arg.numpy(), gap.numpy()
+
+
+@pytest.mark.parametrize("which", ["pads", "small_hand"])
+def test_saved_pool_record_contents(oracle_lib, which):
+    # pooled features within FP32 rounding of a float64 evaluation; arg-max
+    # nodes equal wherever the runner-up is further than that rounding
+    from paper_2604_20295_amd import _native
+    torch, dev = torch_dev()
+    if which == "pads":
+        mesh, scene, model, _ = scenes.config3()
+        model = model.with_mode(MODE_FULL)
+    else:
+        mesh, scene, model = scenes.config2(n_envs=24, mode=MODE_FULL, **SMALL)
+    E = scene.n_envs
+    plan = make_plan(mesh, E, scene.max_obj, backward=True)
+    ds, dm = DevScene(scene), DevModel(model)
+    rec = torch.full((E * plan.K, _native.ETAC_SAVED_WORDS), -1, dtype=torch.int32, device=dev)
+    u = torch.empty((3, E, plan.N), device=dev)
+    cobj = torch.empty((E, plan.N), dtype=torch.int8, device=dev)
+    na = torch.empty((E, plan.K), dtype=torch.int32, device=dev)
+    _native.etac_step(plan, ds.struct(plan), dm.struct(plan), u, cobj, na, saved=rec)
+    torch.cuda.synchronize()
+    rec = rec.cpu().numpy()
+    ref = oracle_lib.forward(mesh, scene, model)
+    n_items = 0
+    for e in range(E):
+        for k in range(plan.K):
+            item = e * plan.K + k
+            if ref["n_active"][e, k] == 0:
+                assert np.all(rec[item] == -1), "items without contact are not written"
+                continue
+            g, arg, gap = _pool_f64(mesh, model, ref["contact_obj"], ref["uhat"], e, k)
+            gg = rec[item, :64].view(np.float32).astype(np.float64)
+            ga = rec[item, 64:]
+            assert np.max(np.abs(gg - g)) <= 1e-5 * max(1.0, np.abs(g).max()), (e, k)
+            n = int(mesh.patch_offset[k + 1] - mesh.patch_offset[k])
+            assert np.all((ga >= 0) & (ga < n)), (e, k)
+            sure = gap > 1e-4
+            assert np.array_equal(ga[sure], arg[sure]), (e, k)
+            n_items += 1
+    log(f"[gpu] pooling records checked: {n_items} items ({which})")
+    assert n_items >= 4
+
+
+@pytest.mark.parametrize("mode", [MODE_FULL, MODE_RESIDUAL_ONLY])
+def test_saved_pool_record_gives_identical_gradients(oracle_lib, mode):
+    # the adjoint given the forward's record equals the one that recomputes it, bit for bit
+    mesh, scene, model = scenes.config2(n_envs=96, mode=mode, **SMALL)
+    w = np.random.default_rng(4).standard_normal((3, 96, mesh.n_nodes))
+    plan = make_plan(mesh, 96, 3, backward=True)
+    log(f"[gpu] saved pooling record vs recompute, small hand mode={mode}")
+    g0 = gpu_step_backward(plan, scene, model, w)
+    g1 = gpu_step_backward(plan, scene, model, w, saved=True)
+    for k in g0:
+        assert np.array_equal(g0[k], g1[k]), k
+
+
+def test_saved_pool_record_propagate_adjoint(oracle_lib):
+    from paper_2604_20295_amd import _native
+    torch, dev = torch_dev()
+    mesh, scene, model = scenes.config2(n_envs=32, **SMALL)
+    rc, ru, _ = oracle_lib.contact(mesh, scene)
+    c, uh = to_dev(rc), to_dev(ru.astype(np.float32))
+    gu = to_dev(np.random.default_rng(5).standard_normal((3, 32, mesh.n_nodes)).astype(np.float32))
+    plan = make_plan(mesh, 32, 3, backward=True)
+    dm = DevModel(model)
+    rec = _native.saved_buffer(plan, 32)
+    u = torch.empty((3, 32, plan.N), device=dev)
+    _native.etac_propagate(plan, dm.struct(plan), 32, c, uh, u, saved=rec)
+    out = []
+    for r in (None, rec):
+        guh = torch.full((3, 32, plan.N), float("nan"), device=dev)
+        ga = torch.zeros(plan.K, device=dev)
+        gp = torch.zeros(17411, device=dev)
+        _native.etac_propagate_backward(plan, dm.struct(plan), 32, c, uh, gu, guh, ga, gp, saved=r)
+        torch.cuda.synchronize()
+        out.append((guh.cpu().numpy(), ga.cpu().numpy(), gp.cpu().numpy()))
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
+def test_config2_full_size_backward_sampled(oracle_lib):
+    # the 4096-env hand, full model, in the launch configuration the benchmark
+    # times (forward with the pooling record, then the adjoint given it):
+    # gradients identical to the recomputing adjoint, and pose gradients of
+    # sampled envs (all decisions clear of the margin) against the oracle
+    mesh, scene, model = scenes.config2(n_envs=4096)
+    w = np.random.default_rng(21).standard_normal((3, 4096, mesh.n_nodes)).astype(np.float32)
+    plan = make_plan(mesh, 4096, scene.max_obj, backward=True)
+    log("[gpu] hand backward E=4096 (saved record vs recompute)")
+    g1 = gpu_step_backward(plan, scene, model, w, saved=True)
+    g0 = gpu_step_backward(plan, scene, model, w)
+    for k in g0:
+        assert np.array_equal(g0[k], g1[k]), k
+    rng = np.random.default_rng(3)
+    envs = []
+    for e in rng.permutation(4096):
+        sub = scene.select([int(e)])
+        out = oracle_lib.forward(mesh, sub, model, with_sig=True)
+        if out["margin"][0] > MARGIN and out["n_active"].sum() > 0:
+            envs.append(int(e))
+        if len(envs) == 6:
+            break
+    log(f"[gpu]   sampled envs {envs}")
+    assert len(envs) == 6
+    envs = np.array(envs)
+    ref = oracle_lib.backward(mesh, scene.select(envs), model, w[:, envs].astype(np.float64))
+    _close(g1["grad_trans"][envs], ref["grad_trans"], "grad_trans")
+    _close(g1["grad_rot"][envs], ref["grad_rot"], "grad_rot")
