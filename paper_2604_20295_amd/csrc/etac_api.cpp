@@ -220,8 +220,6 @@ etac_status etac_plan_create(const etac_mesh *mesh, int32_t n_envs, int32_t max_
         if (e == hipSuccess) e = plan_alloc(p, &b.alpha_part, items);
         if (e == hipSuccess) e = plan_alloc(p, &b.pose_part, items * (size_t)max_obj * 12);
         if (e == hipSuccess) e = plan_alloc(p, &b.item_flag, items);
-        if (e == hipSuccess) e = plan_alloc(p, &b.item_list, items);
-        if (e == hipSuccess) e = plan_alloc(p, &b.n_list, 1);
         if (e == hipSuccess) e = plan_alloc(p, &b.phi_seg, (size_t)64 * ETAC_PHI_SIZE);
         const size_t EN = (size_t)n_envs * N;
         if (e == hipSuccess) e = plan_alloc(p, &b.cobj_st, EN);

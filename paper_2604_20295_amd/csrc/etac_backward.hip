@@ -1524,44 +1524,59 @@ __global__ __launch_bounds__(kWG) void k_bwd(BwdParams p) {
 // fixed-order reductions of the per-item partials
 // ---------------------------------------------------------------------------
 
-// Ascending list of items that wrote a parameter-gradient partial.
-__global__ __launch_bounds__(1024) void k_list_items(const int *flag, int n_items, int *list, int *n_list) {
-    __shared__ int wsum[16];
-    const int wave = threadIdx.x >> 6;
-    int run = 0;   // identical in every thread
-    for (int i0 = 0; i0 < n_items; i0 += 1024) {
-        const int i = i0 + threadIdx.x;
-        const bool f = i < n_items && flag[i] != 0;
-        const unsigned long long b = __ballot(f);
-        wsum[wave] = __popcll(b);
-        __syncthreads();
-        int off = run;
-        int tot = 0;
-        for (int w = 0; w < 16; ++w) {
-            if (w < wave) off += wsum[w];
-            tot += wsum[w];
-        }
-        if (f) list[off + lanes_below(b)] = i;
-        run += uniform(tot);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *n_list = run;
-}
-
-// Segment sums of the parameter partials in list order (FP64).
-__global__ __launch_bounds__(256) void k_phi_segments(const float *part, const int *list, const int *n_list,
+// Segment sums of the parameter partials (FP64).  Segment s covers items
+// [s R, (s + 1) R), R = ceil(n_items / kPhiSegs), and adds the partials of
+// the items that wrote one (flag set) in ascending item order.  The block
+// compacts its segment's flags into an LDS list 1024 items at a time (wave
+// ballots, waves in order), then every thread sums its column over the list
+// with four loads in flight.
+__global__ __launch_bounds__(256) void k_phi_segments(const float *part, const int *flag, int n_items,
                                                       double *seg) {
+    __shared__ int list[1024];
+    __shared__ int wsum[kWaves];
     const int c = blockIdx.x * 256 + threadIdx.x;
     const int s = blockIdx.y;
-    const int nl = *n_list;
-    const int per = (nl + kPhiSegs - 1) / kPhiSegs;
-    const int a = s * per, b = min(nl, a + per);
-    if (c >= kPhiN) return;
+    const int wave = threadIdx.x >> 6;
+    const int per = (n_items + kPhiSegs - 1) / kPhiSegs;
+    const int a = min(n_items, s * per), b = min(n_items, a + per);
+    const int cc = c < kPhiN ? c : 0;   // out-of-range columns read column 0, store nothing
     double acc = 0.0;
-    for (int q = a; q < b; ++q) acc += (double)part[(size_t)list[q] * kPhiN + c];
-    seg[(size_t)s * kPhiN + c] = acc;
+    for (int c0 = a; c0 < b; c0 += 1024) {
+        int cnt = 0;   // identical in every thread
+        for (int j = 0; j < 4; ++j) {
+            const int i = c0 + j * 256 + threadIdx.x;
+            const bool f = i < b && flag[i] != 0;
+            const unsigned long long bal = __ballot(f);
+            __syncthreads();   // the previous round's wsum reads are done
+            wsum[wave] = __popcll(bal);
+            __syncthreads();
+            int off = cnt, tot = 0;
+            for (int w = 0; w < kWaves; ++w) {
+                if (w < wave) off += wsum[w];
+                tot += wsum[w];
+            }
+            if (f) list[off + lanes_below(bal)] = i;
+            cnt += uniform(tot);
+        }
+        __syncthreads();
+        int q = 0;
+        for (; q + 4 <= cnt; q += 4) {
+            const float v0 = part[(size_t)list[q] * kPhiN + cc];
+            const float v1 = part[(size_t)list[q + 1] * kPhiN + cc];
+            const float v2 = part[(size_t)list[q + 2] * kPhiN + cc];
+            const float v3 = part[(size_t)list[q + 3] * kPhiN + cc];
+            acc += (double)v0;
+            acc += (double)v1;
+            acc += (double)v2;
+            acc += (double)v3;
+        }
+        for (; q < cnt; ++q) acc += (double)part[(size_t)list[q] * kPhiN + cc];
+        __syncthreads();   // the list is rewritten by the next chunk
+    }
+    if (c < kPhiN) seg[(size_t)s * kPhiN + c] = acc;
 }
 
+// dL/dphi: the segment sums added in segment order.
 __global__ __launch_bounds__(256) void k_phi_final(const double *seg, float *grad_phi) {
     const int c = blockIdx.x * 256 + threadIdx.x;
     if (c >= kPhiN) return;
@@ -1635,10 +1650,8 @@ hipError_t launch_backward(const Plan &pl, const SceneDev *s, const ModelDev &m,
     if (e != hipSuccess) return e;
     slot = timer_begin(pl, ETAC_TIMER_REDUCE, st);
     if (grad_phi) {
-        hipLaunchKernelGGL(k_list_items, dim3(1), dim3(1024), 0, st, pl.bwd.item_flag, p.n_items, pl.bwd.item_list,
-                           pl.bwd.n_list);
         hipLaunchKernelGGL(k_phi_segments, dim3((kPhiN + 255) / 256, kPhiSegs), dim3(256), 0, st, pl.bwd.phi_part,
-                           pl.bwd.item_list, pl.bwd.n_list, pl.bwd.phi_seg);
+                           pl.bwd.item_flag, p.n_items, pl.bwd.phi_seg);
         hipLaunchKernelGGL(k_phi_final, dim3((kPhiN + 255) / 256), dim3(256), 0, st, pl.bwd.phi_seg, grad_phi);
     }
     if (grad_alpha) hipLaunchKernelGGL(k_alpha, dim3(pl.K), dim3(256), 0, st, pl.bwd.alpha_part, n_envs, pl.K, grad_alpha);

@@ -60,8 +60,6 @@ struct BwdScratch {
     float *alpha_part;     // [E*K]            per-item dL/dalpha partials
     float *pose_part;      // [E*K][O][12]     per-item pose-gradient partials
     int *item_flag;        // [E*K]            1 if the item wrote partials
-    int *item_list;        // [E*K]            compacted list of flagged items
-    int *n_list;           // [1]
     double *phi_seg;       // [kPhiSegs][17411] segment sums of the parameter reduction
     // hand-over from the decay kernel to the network / contact kernel
     int8_t *cobj_st;       // [E][N]    contact winners of every candidate item (step adjoint)
