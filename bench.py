@@ -399,6 +399,7 @@ def main():
                    "envs": E, "nodes_per_env": N, "patches": K, "graph": bool(args.graph),
                    "launch_shape": {"fwd_wg_per_cu": launch_shape[0], "fwd_batch": launch_shape[1],
                                     "bwd_batch": launch_shape[2], "decay_wg_per_cu": launch_shape[3],
+                                    "net_batch": launch_shape[4],
                                     "autotuned": not args.no_autotune}},
         "fwd_only": {"value": fwd_rate, "unit": "node-updates/s", "ms_per_step": fwd_only_ms,
                      "hbm_gbs": hbm_fwd_gbs, "hbm_frac": hbm_fwd_gbs / HBM_PEAK_GBS},

@@ -220,13 +220,15 @@ etac_status etac_plan_set_batch(etac_plan *plan, int32_t items);
 
 /* Launch shape of the persistent kernels (autotuner knobs; 0 keeps the
  * current value): forward workgroups per CU (1 .. 8), forward work-queue
- * batch (1 .. 64), adjoint work-queue batch (1 .. 64), workgroups per CU of
- * the decay-adjoint kernel (1 .. 8).  Results do not depend on them.
- * ETAC_ERR_VALUE outside those ranges. */
+ * batch (1 .. 64), work-queue batch of the decay-adjoint kernel (1 .. 64),
+ * workgroups per CU of the decay-adjoint kernel (1 .. 8), and items claimed
+ * at a time by the network-adjoint kernel from its list of items with
+ * contact (1 .. 64).  Results do not depend on them.  ETAC_ERR_VALUE outside
+ * those ranges. */
 etac_status etac_plan_set_launch(etac_plan *plan, int32_t fwd_wg_per_cu, int32_t fwd_batch,
-                                 int32_t bwd_batch, int32_t decay_wg_per_cu);
+                                 int32_t bwd_batch, int32_t decay_wg_per_cu, int32_t net_batch);
 
-/* The current launch shape, in the order of etac_plan_set_launch (HOST int32[4]). */
+/* The current launch shape, in the order of etac_plan_set_launch (HOST int32[5]). */
 etac_status etac_plan_get_launch(const etac_plan *plan, int32_t *shape);
 
 /* Autotuner.  Times every candidate launch shape of the persistent kernels
@@ -235,10 +237,10 @@ etac_status etac_plan_get_launch(const etac_plan *plan, int32_t *shape);
  * both calls) with HIP events over `reps` calls
  * (1 .. 1000) after a warm-up call, and keeps the fastest: forward
  * workgroups per CU in {1, 2} x batch in {1, 2, 4, 8, 16}; with grad_u
- * non-NULL also decay-kernel workgroups per CU in {2, 3, 4} x adjoint batch
- * in {2, 4, 8, 16}.  Every candidate gives identical results.  `best` (HOST
- * int32[4], may be NULL) receives the chosen shape as in
- * etac_plan_get_launch.  Blocks the host and creates two HIP events, so it
+ * non-NULL also decay-kernel workgroups per CU in {2, 3, 4} x its batch in
+ * {2, 4, 8, 16}, then the network-adjoint claim in {1, 2, 4}.  Every
+ * candidate gives identical results.  `best` (HOST int32[5], may be NULL)
+ * receives the chosen shape as in etac_plan_get_launch.  Blocks the host and creates two HIP events, so it
  * must not be called during stream capture (ETAC_ERR_CAPTURE). */
 etac_status etac_plan_autotune(etac_plan *plan, const etac_scene *scene, const etac_model *model,
                                const float *grad_u, float *u, int8_t *contact_obj, int32_t *n_active,

@@ -87,7 +87,7 @@ def lib():
             "etac_plan_set_occupancy": ([vp, i32], i32),
             "etac_plan_set_timing": ([vp, i32], i32),
             "etac_plan_set_batch": ([vp, i32], i32),
-            "etac_plan_set_launch": ([vp, i32, i32, i32, i32], i32),
+            "etac_plan_set_launch": ([vp, i32, i32, i32, i32, i32], i32),
             "etac_plan_get_launch": ([vp, P(i32)], i32),
             "etac_plan_autotune": ([vp, P(etac_scene), P(etac_model), vp, vp, vp, vp, vp, vp, vp, vp, vp, i32,
                                     P(i32), vp], i32),
@@ -171,13 +171,15 @@ class Plan:
     def set_batch(self, items):
         _check("etac_plan_set_batch", lib().etac_plan_set_batch(self.handle, int(items)))
 
-    def set_launch(self, fwd_wg_per_cu=0, fwd_batch=0, bwd_batch=0, decay_wg_per_cu=0):
+    def set_launch(self, fwd_wg_per_cu=0, fwd_batch=0, bwd_batch=0, decay_wg_per_cu=0, net_batch=0):
         _check("etac_plan_set_launch", lib().etac_plan_set_launch(self.handle, int(fwd_wg_per_cu), int(fwd_batch),
-                                                                  int(bwd_batch), int(decay_wg_per_cu)))
+                                                                  int(bwd_batch), int(decay_wg_per_cu),
+                                                                  int(net_batch)))
 
     def launch(self):
-        """(fwd workgroups per CU, fwd batch, adjoint batch, decay workgroups per CU)"""
-        out = (C.c_int32 * 4)()
+        """(fwd workgroups per CU, fwd batch, decay-adjoint batch, decay
+        workgroups per CU, network-adjoint claim)"""
+        out = (C.c_int32 * 5)()
         _check("etac_plan_get_launch", lib().etac_plan_get_launch(self.handle, out))
         return tuple(out)
 
@@ -298,8 +300,8 @@ def etac_step_backward(plan, scene, model, grad_u, grad_rot, grad_trans, grad_al
 def etac_plan_autotune(plan, scene, model, u, contact_obj, n_active, grad_u=None, grad_rot=None, grad_trans=None,
                        grad_alpha=None, grad_phi=None, reps=3, saved=None):
     """Time the candidate launch shapes on these inputs, keep the fastest and
-    return it as (fwd workgroups per CU, fwd batch, adjoint batch, decay
-    workgroups per CU).  With grad_u None only the forward is tuned."""
+    return it as in Plan.launch().  With grad_u None only the forward is
+    tuned."""
     import torch
     E, O = scene.n_envs, scene.max_obj
     _req(u, torch.float32, (3, E, plan.N), "u", plan.device)
@@ -312,7 +314,7 @@ def etac_plan_autotune(plan, scene, model, u, contact_obj, n_active, grad_u=None
         _req(grad_trans, torch.float32, (E, O, 3), "grad_trans", plan.device)
         _req(grad_alpha, torch.float32, (plan.K,), "grad_alpha", plan.device)
         _req(grad_phi, torch.float32, (ETAC_PHI_SIZE,), "grad_phi", plan.device)
-    best = (C.c_int32 * 4)()
+    best = (C.c_int32 * 5)()
     _check("etac_plan_autotune",
            lib().etac_plan_autotune(plan.handle, C.byref(scene), C.byref(model), _ptr(grad_u), _ptr(u),
                                     _ptr(contact_obj), _ptr(n_active), _ptr(saved), _ptr(grad_rot), _ptr(grad_trans),

@@ -139,6 +139,7 @@ etac_status etac_plan_create(const etac_mesh *mesh, int32_t n_envs, int32_t max_
     p.batch = etac::kDefaultBatch;
     p.bwd_batch = etac::kDefaultBatch;
     p.decay_wg_per_cu = etac::kDefaultDecayWgPerCu;
+    p.net_batch = etac::kDefaultNetBatch;
     hipError_t e = hipGetDevice(&p.device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&p.cu_count, hipDeviceAttributeMultiprocessorCount, p.device);
     if (e != hipSuccess) {
@@ -226,6 +227,8 @@ etac_status etac_plan_create(const etac_mesh *mesh, int32_t n_envs, int32_t max_
         if (e == hipSuccess) e = plan_alloc(p, &b.uhat_st, 3 * EN);
         if (e == hipSuccess) e = plan_alloc(p, &b.gh_st, 3 * EN);
         if (e == hipSuccess) e = plan_alloc(p, &b.m_st, items);
+        if (e == hipSuccess) e = plan_alloc(p, &b.live, items);
+        if (e == hipSuccess) e = plan_alloc(p, &b.seg_cnt, (items + 1023) / 1024 + 1);
         p.has_bwd = (e == hipSuccess);
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -272,10 +275,10 @@ etac_status etac_plan_set_batch(etac_plan *plan, int32_t items) {
 }
 
 etac_status etac_plan_set_launch(etac_plan *plan, int32_t fwd_wg_per_cu, int32_t fwd_batch, int32_t bwd_batch,
-                                 int32_t decay_wg_per_cu) {
+                                 int32_t decay_wg_per_cu, int32_t net_batch) {
     if (!plan) return ETAC_ERR_NULL;
     if (fwd_wg_per_cu < 0 || fwd_wg_per_cu > 8 || fwd_batch < 0 || fwd_batch > 64 || bwd_batch < 0 ||
-        bwd_batch > 64 || decay_wg_per_cu < 0 || decay_wg_per_cu > 8)
+        bwd_batch > 64 || decay_wg_per_cu < 0 || decay_wg_per_cu > 8 || net_batch < 0 || net_batch > 64)
         return ETAC_ERR_VALUE;
     etac::Plan &p = plan->p;
     if (fwd_wg_per_cu) {
@@ -285,6 +288,7 @@ etac_status etac_plan_set_launch(etac_plan *plan, int32_t fwd_wg_per_cu, int32_t
     if (fwd_batch) p.batch = fwd_batch;
     if (bwd_batch) p.bwd_batch = bwd_batch;
     if (decay_wg_per_cu) p.decay_wg_per_cu = decay_wg_per_cu;
+    if (net_batch) p.net_batch = net_batch;
     return ETAC_OK;
 }
 
@@ -294,6 +298,7 @@ etac_status etac_plan_get_launch(const etac_plan *plan, int32_t *shape) {
     shape[1] = plan->p.batch;
     shape[2] = plan->p.bwd_batch;
     shape[3] = plan->p.decay_wg_per_cu;
+    shape[4] = plan->p.net_batch;
     return ETAC_OK;
 }
 
@@ -480,7 +485,8 @@ etac_status etac_plan_autotune(etac_plan *plan, const etac_scene *scene, const e
     p.wg_per_cu = bf_occ;
     p.grid = p.cu_count * p.wg_per_cu;
     p.batch = bf_batch;
-    // adjoint: decay-kernel workgroups per CU x work-queue batch
+    // adjoint: decay-kernel workgroups per CU x its work-queue batch, then
+    // the network kernel's claim size
     if (grad_u) {
         int bb_dec = p.decay_wg_per_cu, bb_batch = p.bwd_batch;
         float bb_ms = 3.0e38f;
@@ -495,6 +501,15 @@ etac_status etac_plan_autotune(etac_plan *plan, const etac_scene *scene, const e
             }
         p.decay_wg_per_cu = bb_dec;
         p.bwd_batch = bb_batch;
+        int bn = p.net_batch;
+        float bn_ms = 3.0e38f;
+        for (int ni = 0; out == ETAC_OK && ni < 3; ++ni) {
+            p.net_batch = kBatch[ni];
+            float ms = 0.0f;
+            out = timed(false, ms);
+            if (out == ETAC_OK && ms < bn_ms) { bn_ms = ms; bn = p.net_batch; }
+        }
+        p.net_batch = bn;
     }
     for (int i = 0; i < 2; ++i)
         if (ev[i]) (void)hipEventDestroy(ev[i]);
@@ -503,6 +518,7 @@ etac_status etac_plan_autotune(etac_plan *plan, const etac_scene *scene, const e
         best[1] = p.batch;
         best[2] = p.bwd_batch;
         best[3] = p.decay_wg_per_cu;
+        best[4] = p.net_batch;
     }
     return out;
 }

@@ -36,7 +36,9 @@ struct BwdParams {
     Scratch scr;
     BwdScratch bwd;
     int E, n_items;
-    int batch;                    // queue positions claimed per atomic
+    int batch;                    // queue positions claimed per atomic (all items)
+    int net_batch;                // live-list positions claimed per atomic (k_bwd)
+    int n_seg;                    // 1024-position segments of the queue
     const int8_t *cobj_in;        // BWD_PROP
     const float *uhat_in;         // BWD_PROP
     const float *grad_u;          // [3][E][N]   BWD_STEP, BWD_PROP
@@ -1429,6 +1431,56 @@ __global__ __launch_bounds__(kWG) void k_bwd_decay(BwdParams p) {
 }
 
 // ---------------------------------------------------------------------------
+// list of the items with contact, in queue order, for k_bwd's work queue
+//
+// k_live_count counts them per segment of 1024 queue positions; k_live_list
+// writes each segment's positions after the counts of the segments before it
+// (wave ballots, waves in order) and the last segment writes the total.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool item_live(const BwdParams &p, int q) {
+    int e, k;
+    queue_item(p.mesh, p.E, q, e, k);
+    return p.bwd.m_st[(size_t)e * p.mesh.K + k] > 0;
+}
+
+__global__ __launch_bounds__(256) void k_live_count(BwdParams p) {
+    __shared__ int wsum[kWaves];
+    const int s = blockIdx.x, wave = threadIdx.x >> 6;
+    int cnt = 0;
+    for (int j = 0; j < 4; ++j) {
+        const int q = s * 1024 + j * 256 + threadIdx.x;
+        cnt += (q < p.n_items && item_live(p, q)) ? 1 : 0;
+    }
+    for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off);
+    wsum[wave] = cnt;   // identical in every lane
+    __syncthreads();
+    if (threadIdx.x < 64) p.bwd.seg_cnt[s] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+__global__ __launch_bounds__(256) void k_live_list(BwdParams p) {
+    __shared__ int wsum[kWaves];
+    const int s = blockIdx.x, wave = threadIdx.x >> 6;
+    int run = 0;   // identical in every thread
+    for (int t = 0; t < s; ++t) run += p.bwd.seg_cnt[t];
+    for (int j = 0; j < 4; ++j) {
+        const int q = s * 1024 + j * 256 + threadIdx.x;
+        const bool f = q < p.n_items && item_live(p, q);
+        const unsigned long long bal = __ballot(f);
+        __syncthreads();   // the previous round's wsum reads are done
+        wsum[wave] = __popcll(bal);
+        __syncthreads();
+        int off = run, tot = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            if (w < wave) off += wsum[w];
+            tot += wsum[w];
+        }
+        if (f) p.bwd.live[off + lanes_below(bal)] = q;
+        run += uniform(tot);
+    }
+    if (s == (int)gridDim.x - 1 && threadIdx.x < 64) p.bwd.seg_cnt[gridDim.x] = run;
+}
+
+// ---------------------------------------------------------------------------
 // k_bwd: network and contact adjoint
 // ---------------------------------------------------------------------------
 
@@ -1496,10 +1548,15 @@ __global__ __launch_bounds__(kWG) void k_bwd(BwdParams p) {
         stage_net_t(S, p.model.phi);
         __syncthreads();
     }
+    // step / propagate adjoint: positions of the list of items with contact;
+    // contact adjoint: every queue position, culled by the objects' reach
+    const int n_pos = KIND == BWD_CONTACT ? p.n_items : uniform(p.bwd.seg_cnt[p.n_seg]);
     for (;;) {
-        const int b0 = next_batch<KIND == BWD_CONTACT ? CULL_OBJECTS : CULL_ACTIVE>(
-            p.scr.counter + 2, S.batch, p.mesh, p.scene, p.E, p.n_items, p.batch, p.bwd.m_st);
-        if (b0 >= p.n_items) break;
+        const int b0 = KIND == BWD_CONTACT
+                           ? next_batch<CULL_OBJECTS>(p.scr.counter + 2, S.batch, p.mesh, p.scene, p.E, n_pos, p.batch)
+                           : next_batch<CULL_LIST>(p.scr.counter + 2, S.batch, p.mesh, p.scene, p.E, n_pos,
+                                                   p.net_batch, p.bwd.live);
+        if (b0 >= n_pos) break;
         if (KIND == BWD_CONTACT) zero_fill_batch_bwd(p, S.batch, b0);
         const int nb = uniform(S.batch.n);
         for (int q = 0; q < nb; ++q) {
@@ -1632,6 +1689,8 @@ hipError_t launch_backward(const Plan &pl, const SceneDev *s, const ModelDev &m,
     p.grad_uhat_in = nullptr;
     p.grad_uhat_out = grad_uhat;
     p.saved = saved;
+    p.net_batch = pl.net_batch;
+    p.n_seg = (p.n_items + 1023) / 1024;
     // contact and the decay adjoint, several workgroups per CU
     const int grid_d = min(p.n_items, pl.cu_count * pl.decay_wg_per_cu);
     int slot = timer_begin(pl, ETAC_TIMER_BWD_DECAY, st);
@@ -1640,6 +1699,9 @@ hipError_t launch_backward(const Plan &pl, const SceneDev *s, const ModelDev &m,
     hipError_t e = hipGetLastError();
     timer_end(pl, ETAC_TIMER_BWD_DECAY, slot, st);
     if (e != hipSuccess) return e;
+    // the items with contact, in queue order
+    hipLaunchKernelGGL(k_live_count, dim3(p.n_seg), dim3(256), 0, st, p);
+    hipLaunchKernelGGL(k_live_list, dim3(p.n_seg), dim3(256), 0, st, p);
     // network and contact adjoint of the contacted items, one workgroup per CU
     const int grid = min(p.n_items, pl.cu_count);
     slot = timer_begin(pl, ETAC_TIMER_BACKWARD, st);
@@ -1683,6 +1745,8 @@ hipError_t launch_contact_backward(const Plan &pl, const SceneDev &s, const floa
     p.grad_uhat_in = grad_uhat;
     p.grad_uhat_out = nullptr;
     p.saved = nullptr;
+    p.net_batch = pl.net_batch;
+    p.n_seg = (p.n_items + 1023) / 1024;
     const int grid = min(p.n_items, pl.cu_count);
     hipLaunchKernelGGL(k_bwd<BWD_CONTACT>, dim3(grid), dim3(kWG), 0, st, p);
     hipError_t e = hipGetLastError();

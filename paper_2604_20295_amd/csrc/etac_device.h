@@ -273,14 +273,15 @@ __device__ __forceinline__ unsigned long long batch_mask(const ItemBatch &B) {
 enum CullMode {
     CULL_NONE = 0,      // every item is live (contact results are given)
     CULL_OBJECTS = 1,   // live if some object's bounding ball may reach the patch
-    CULL_ACTIVE = 2     // live if a previous kernel found active nodes (live[e K + k] > 0)
+    CULL_LIST = 2       // positions index a list of live queue positions (live[q])
 };
 
-// Claim the next batch and cull it.  Returns the batch's first queue
-// position (>= n_items when the queue is empty).
+// Claim the next batch and cull it.  Returns the batch's first position
+// (>= n_items when the queue is empty); B.item holds the live items' queue
+// positions.
 template <int CULL>
 __device__ int next_batch(unsigned *counter, ItemBatch &B, const MeshDev &M, const SceneDev &Sc, int E,
-                          int n_items, int batch, const int *live = nullptr) {
+                          int n_items, int batch, const int *list = nullptr) {
     __syncthreads();   // every wave is done with the previous batch
     if (threadIdx.x < 64) {
         const int lane = lane_id();
@@ -294,10 +295,6 @@ __device__ int next_batch(unsigned *counter, ItemBatch &B, const MeshDev &M, con
                 int e, k;
                 queue_item(M, E, q, e, k);
                 cand = cull_objects(Sc, M, e, k);
-            } else if (CULL == CULL_ACTIVE) {
-                int e, k;
-                queue_item(M, E, q, e, k);
-                cand = live[(size_t)e * M.K + k] > 0 ? 0xffu : 0u;
             } else {
                 cand = 0xffu;
             }
@@ -305,7 +302,7 @@ __device__ int next_batch(unsigned *counter, ItemBatch &B, const MeshDev &M, con
         const unsigned long long live = __ballot(cand != 0u);
         if (cand != 0u) {
             const int slot = (int)lanes_below(live);
-            B.item[slot] = q;
+            B.item[slot] = CULL == CULL_LIST ? list[q] : q;
             B.cand[slot] = (uint8_t)cand;
         }
         // identical values from every lane

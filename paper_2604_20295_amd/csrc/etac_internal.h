@@ -14,7 +14,8 @@ constexpr int kSavedWords = ETAC_SAVED_WORDS;   // pooling record per (env, patc
 constexpr int kMaxPatches = 1024;  // per-patch counters of the contact kernel live in LDS
 constexpr int kDefaultWgPerCu = 2;
 constexpr int kDefaultBatch = 4;   // work-queue positions claimed per atomic
-constexpr int kDefaultDecayWgPerCu = 3;   // workgroups per CU of the decay-adjoint kernel
+constexpr int kDefaultDecayWgPerCu = 3;
+constexpr int kDefaultNetBatch = 2;   // workgroups per CU of the decay-adjoint kernel
 
 // Device view of the plan's mesh copy.
 struct MeshDev {
@@ -66,6 +67,8 @@ struct BwdScratch {
     float *uhat_st;        // [3][E][N] u_hat of active nodes (step adjoint)
     float *gh_st;          // [3][E][N] dL/du_hat of active nodes after the decay adjoint
     int *m_st;             // [E*K]     active-node count of every item
+    int *live;             // [E*K]     queue positions of the items with contact, in queue order
+    int *seg_cnt;          // [n_seg + 1] items with contact per 1024 queue positions; [n_seg] = total
 };
 
 // Event pairs bracketing kernel launches (etac_plan_set_timing).
@@ -83,6 +86,7 @@ struct Plan {
     int batch;             // forward work-queue positions claimed per atomic (1 .. 64)
     int bwd_batch;         // adjoint work-queue positions claimed per atomic (1 .. 64)
     int decay_wg_per_cu;   // workgroups per CU of the decay-adjoint kernel (1 .. 8)
+    int net_batch;         // list positions per claim of the network-adjoint kernel (1 .. 64)
     int n_envs, max_obj, K, N, n_max;
     uint32_t flags;
     MeshDev mesh;

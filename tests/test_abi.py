@@ -95,7 +95,7 @@ def test_calls_reject_null_plan():
     assert lib.etac_plan_set_occupancy(None, 1) == -1
     assert lib.etac_plan_set_timing(None, 1) == -1
     assert lib.etac_plan_set_batch(None, 4) == -1
-    assert lib.etac_plan_set_launch(None, 0, 0, 0, 0) == -1
+    assert lib.etac_plan_set_launch(None, 0, 0, 0, 0, 0) == -1
     assert lib.etac_plan_get_launch(None, None) == -1
     assert lib.etac_plan_autotune(None, None, None, None, None, None, None, None, None, None, None, None, 1,
                                   None, None) == -1

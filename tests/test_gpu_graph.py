@@ -128,13 +128,14 @@ def test_autotune_picks_a_candidate_and_keeps_results(oracle_lib):
         return {k: v.cpu().numpy().copy() for k, v in outs.items()}
 
     log("[gpu] autotune")
-    assert plan.launch() == (2, 4, 4, 3)                     # built-in defaults
+    assert plan.launch() == (2, 4, 4, 3, 2)                  # built-in defaults
     ref = step()
     best = _native.etac_plan_autotune(plan, sc, md, outs["u"], outs["cobj"], outs["na"], gu, outs["grot"],
                                       outs["gt"], outs["ga"], outs["gp"], reps=2)
     log(f"[gpu]   chosen launch shape {best}")
     assert best == plan.launch()
     assert best[0] in (1, 2) and best[1] in (1, 2, 4, 8, 16) and best[2] in (2, 4, 8, 16) and best[3] in (2, 3, 4)
+    assert best[4] in (1, 2, 4)
     got = step()
     for k in ref:
         assert np.array_equal(got[k], ref[k]), k
