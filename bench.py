@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph", action="store_true", help="replay the step from a captured HIP graph")
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in launch shapes")
+    ap.add_argument("--launch", type=str, default=None,
+                    help="fixed launch shape a,b,c,d,e as in Plan.set_launch (no autotuning), e.g. for profiling")
     ap.add_argument("--rollout", action="store_true",
                     help="also run the graph-captured rollout: 16384 envs, 200 steps of smooth object motion")
     ap.add_argument("--rollout-envs", type=int, default=16384)
@@ -90,7 +92,9 @@ def rollout(args, mode):
     gal, gph = torch.empty((K,), device=dev), torch.empty((17411,), device=dev)
     saved = _native.saved_buffer(plan, E)
 
-    if not args.no_autotune:
+    if args.launch:
+        plan.set_launch(*[int(x) for x in args.launch.split(",")])
+    elif not args.no_autotune:
         _native.etac_plan_autotune(plan, sc, md, u, cobj, na, gu, grot, gtr, gal, gph, reps=2, saved=saved)
 
     def body(with_bwd):
@@ -280,7 +284,9 @@ def main():
         _native.etac_step_backward(plan, sc, md, grad_u, grot, gtr, gal, gph, saved=saved)
 
     # launch shapes chosen by the library's autotuner on this workload
-    if not args.no_autotune:
+    if args.launch:
+        plan.set_launch(*[int(x) for x in args.launch.split(",")])
+    elif not args.no_autotune:
         _native.etac_plan_autotune(plan, sc, md, u, cobj, na, grad_u, grot, gtr, gal, gph, reps=2, saved=saved)
     launch_shape = plan.launch()
 
@@ -400,7 +406,7 @@ def main():
                    "launch_shape": {"fwd_wg_per_cu": launch_shape[0], "fwd_batch": launch_shape[1],
                                     "bwd_batch": launch_shape[2], "decay_wg_per_cu": launch_shape[3],
                                     "net_batch": launch_shape[4],
-                                    "autotuned": not args.no_autotune}},
+                                    "autotuned": not (args.no_autotune or args.launch)}},
         "fwd_only": {"value": fwd_rate, "unit": "node-updates/s", "ms_per_step": fwd_only_ms,
                      "hbm_gbs": hbm_fwd_gbs, "hbm_frac": hbm_fwd_gbs / HBM_PEAK_GBS},
         "hbm_frac_step": hbm_step_gbs / HBM_PEAK_GBS,
