@@ -217,11 +217,12 @@ etac_status etac_plan_create(const etac_mesh *mesh, int32_t n_envs, int32_t max_
         const size_t items = (size_t)n_envs * K;
         etac::BwdScratch &b = p.bwd;
         e = plan_alloc(p, &b.guhat, G * 3 * (size_t)n_max);
-        if (e == hipSuccess) e = plan_alloc(p, &b.phi_part, items * ETAC_PHI_SIZE);
+        if (e == hipSuccess) e = plan_alloc(p, &b.phi_part, items * etac::kRecWords);
+        if (e == hipSuccess) e = plan_alloc(p, &b.rec_map, ETAC_PHI_SIZE);
         if (e == hipSuccess) e = plan_alloc(p, &b.alpha_part, items);
         if (e == hipSuccess) e = plan_alloc(p, &b.pose_part, items * (size_t)max_obj * 12);
         if (e == hipSuccess) e = plan_alloc(p, &b.item_flag, items);
-        if (e == hipSuccess) e = plan_alloc(p, &b.phi_seg, (size_t)64 * ETAC_PHI_SIZE);
+        if (e == hipSuccess) e = plan_alloc(p, &b.phi_seg, (size_t)64 * etac::kRedColsMax);
         const size_t EN = (size_t)n_envs * N;
         if (e == hipSuccess) e = plan_alloc(p, &b.cobj_st, EN);
         if (e == hipSuccess) e = plan_alloc(p, &b.uhat_st, 3 * EN);
@@ -229,6 +230,7 @@ etac_status etac_plan_create(const etac_mesh *mesh, int32_t n_envs, int32_t max_
         if (e == hipSuccess) e = plan_alloc(p, &b.m_st, items);
         if (e == hipSuccess) e = plan_alloc(p, &b.live, items);
         if (e == hipSuccess) e = plan_alloc(p, &b.seg_cnt, (items + 1023) / 1024 + 1);
+        if (e == hipSuccess) e = etac::init_record_map(p);
         p.has_bwd = (e == hipSuccess);
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();

@@ -48,7 +48,71 @@ struct BwdParams {
 };
 
 constexpr int kTrRow = 20;     // padded row of the block transpose buffer: conflict-free stores, aligned loads
-constexpr int kRedRegs = 32;   // accumulator registers per lane summed per pass of the item reduction
+// ---------------------------------------------------------------------------
+// item record of the parameter gradients
+//
+// For every item with contact k_bwd writes the four waves' summed
+// accumulators as 40 blocks of 16 x 16 in MFMA output order (block b at
+// floats [256 b, 256 b + 256), lane l's registers r at 256 b + 4 l + r):
+// dW4[:, :64] (blocks 0-15, row block ob, column block ib at 4 ob + ib), dW2
+// (16-31, same order), dW1 with db1 as input column 9 (32-35, row blocks) and
+// dW5 (36-39, column blocks, rows 0-2), then the vectors db2, db4 (= s4),
+// db3 (= dpre3), db5, g' and g.  The global-MLP weight gradients are rank one
+// per item, dW4[:, 64:] = s4 g'^T and dW3 = dpre3 g^T: only their factors are
+// stored and the reduction forms the products.
+// ---------------------------------------------------------------------------
+constexpr int kRecBlocks = 40;
+constexpr int kRecB2 = kRecBlocks * 256, kRecB4 = kRecB2 + 64, kRecB3 = kRecB4 + 64, kRecB5 = kRecB3 + 64,
+              kRecGp = kRecB5 + 4, kRecG = kRecGp + 64;
+static_assert(kRecWords == kRecG + 64, "record size");
+static_assert(kRecWords % 4 == 0, "16-byte aligned records");
+
+__host__ __device__ constexpr int rec_block_slot(int b, int row, int col) {
+    return b * 256 + (16 * (row >> 2) + col) * 4 + (row & 3);
+}
+
+// The parameter reduction sums "columns": record slots 0 .. kRecWords - 1
+// (padded to kRedPlain), then the 2 x 64 x 64 rank-one entries, column
+// kRedPlain + 4096 w + 64 o + i for w = 0 (dW4[o][64 + i] = s4[o] g'[i]) and
+// w = 1 (dW3[o][i] = dpre3[o] g[i]).
+constexpr int kRedPlain = (kRecWords + 63) / 64 * 64;
+constexpr int kRedCols = kRedPlain + 2 * 4096;
+static_assert(kRedCols == kRedColsMax, "reduction columns");
+
+// Reduction column of parameter c.
+__device__ int record_column(int c) {
+    if (c < kB1) {
+        const int o = c / 9, i = c % 9;
+        return rec_block_slot(32 + (o >> 4), o & 15, i);
+    }
+    if (c < kW2) {
+        const int o = c - kB1;
+        return rec_block_slot(32 + (o >> 4), o & 15, 9);
+    }
+    if (c < kB2) {
+        const int o = (c - kW2) >> 6, i = (c - kW2) & 63;
+        return rec_block_slot(16 + 4 * (o >> 4) + (i >> 4), o & 15, i & 15);
+    }
+    if (c < kW3) return kRecB2 + (c - kB2);
+    if (c < kB3) return kRedPlain + 4096 + (c - kW3);
+    if (c < kW4) return kRecB3 + (c - kB3);
+    if (c < kB4) {
+        const int o = (c - kW4) >> 7, i = (c - kW4) & 127;
+        if (i < 64) return rec_block_slot(4 * (o >> 4) + (i >> 4), o & 15, i & 15);
+        return kRedPlain + 64 * o + (i - 64);
+    }
+    if (c < kW5) return kRecB4 + (c - kB4);
+    if (c < kB5) {
+        const int row = (c - kW5) >> 6, i = (c - kW5) & 63;
+        return rec_block_slot(36 + (i >> 4), row, i & 15);
+    }
+    return kRecB5 + (c - kB5);
+}
+
+__global__ __launch_bounds__(256) void k_record_map(int *map) {
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c < kPhiN) map[c] = record_column(c);
+}
 
 // Staging area of the decay adjoint.
 struct DecayStage {
@@ -72,7 +136,7 @@ struct BwdLds {
     half8 w4th[4 * 2 * 64], w4tl[4 * 2 * 64];   // [it][s][lane] split fragments of W4[:, :64]^T
     float w1u[3][64];                           // W1[:, 6..8]: the u_hat inputs
     union {
-        float red[kWaves][kRedRegs][64];   // one chunk of every wave's gradient accumulators
+        floatx4 red[kWaves][8][64];        // eight record blocks of every wave's gradient accumulators
         StageBuf xs;                       // node inputs of the network passes
     } u;
     floatx4 acc15[kWaves][8 * 64]; // per-wave dW1 (blocks 0-3) and dW5 (4-7) accumulators [block][lane]
@@ -1014,46 +1078,36 @@ __device__ void contact_adjoint_item(const BwdParams &p, BwdLds &S, int e, int i
 
 // Sum accumulator chunk C over the four waves (in wave order) and store it
 // into the item's parameter-gradient partial.
+// Record blocks 8 C .. 8 C + 7 of the item: every wave puts its eight
+// accumulator blocks in LDS (one 16-byte store per lane and block), then each
+// thread sums two (block, lane) entries over the waves in wave order and
+// stores them with one 16-byte store each.  Every register is named
+// statically, so the accumulators never leave registers.
 template <int C>
-__device__ __forceinline__ void store_partials(BwdLds &S, const WGrad &G, float *out) {
+__device__ __forceinline__ void store_record_chunk(BwdLds &S, const WGrad &G, float *rec) {
     const int wave = threadIdx.x >> 6, lane = lane_id();
     __syncthreads();    // previous users of the buffer are done
-    // chunks 0-1: dW4[:, :64] row blocks 0-1 / 2-3; chunks 2-3: the same of
-    // dW2; chunk 4: dW1 then dW5 (every register named statically, so the
-    // accumulators never leave registers)
-#define ETAC_ST(j, blk)                                                          \
-    {                                                                            \
-        const floatx4 v_ = (blk);                                                \
-        for (int r = 0; r < 4; ++r) S.u.red[wave][4 * (j) + r][lane] = v_[r];    \
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        floatx4 v;
+        if (C == 0) v = G.w4[j >> 2][j & 3];
+        else if (C == 1) v = G.w4[2 + (j >> 2)][j & 3];
+        else if (C == 2) v = G.w2[j >> 2][j & 3];
+        else if (C == 3) v = G.w2[2 + (j >> 2)][j & 3];
+        else v = S.acc15[wave][j * 64 + lane];
+        S.u.red[wave][j][lane] = v;
     }
-#define ETAC_ST4(j0, arr) ETAC_ST(j0, arr[0]) ETAC_ST(j0 + 1, arr[1]) ETAC_ST(j0 + 2, arr[2]) ETAC_ST(j0 + 3, arr[3])
-    if (C == 0) { ETAC_ST4(0, G.w4[0]) ETAC_ST4(4, G.w4[1]) }
-    if (C == 1) { ETAC_ST4(0, G.w4[2]) ETAC_ST4(4, G.w4[3]) }
-    if (C == 2) { ETAC_ST4(0, G.w2[0]) ETAC_ST4(4, G.w2[1]) }
-    if (C == 3) { ETAC_ST4(0, G.w2[2]) ETAC_ST4(4, G.w2[3]) }
-    if (C == 4)
-        for (int j = 0; j < 8; ++j) ETAC_ST(j, S.acc15[wave][j * 64 + lane])
-#undef ETAC_ST4
-#undef ETAC_ST
     __syncthreads();
-    for (int idx = threadIdx.x; idx < kRedRegs * 64; idx += kWG) {
-        const int reg = idx >> 6, ln = idx & 63;
-        float v = S.u.red[0][reg][ln];
-        for (int w = 1; w < kWaves; ++w) v += S.u.red[w][reg][ln];
-        const int j = reg >> 2, r = reg & 3, cl = ln & 15;
-        const int lrow = 4 * (ln >> 4) + r;      // row within the 16 x 16 block
-        if (C < 4) {
-            const int ob = 2 * (C & 1) + (j >> 2), ib = j & 3;
-            const int o = 16 * ob + lrow, i = 16 * ib + cl;
-            if (C < 2) out[kW4 + o * 128 + i] = v;
-            else out[kW2 + o * 64 + i] = v;
-        } else if (j < 4) {
-            const int o = 16 * j + lrow;
-            if (cl < 9) out[kW1 + o * 9 + cl] = v;
-            else if (cl == 9) out[kB1 + o] = v;
-        } else if (lrow < 3) {
-            out[kW5 + lrow * 64 + 16 * (j - 4) + cl] = v;
+    for (int idx = threadIdx.x; idx < 8 * 64; idx += kWG) {
+        const int j = idx >> 6, ln = idx & 63;
+        floatx4 v = S.u.red[0][j][ln];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) {
+            const floatx4 x = S.u.red[w][j][ln];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] += x[r];
         }
+        *reinterpret_cast<floatx4 *>(&rec[(8 * C + j) * 256 + 4 * ln]) = v;
     }
 }
 
@@ -1150,7 +1204,7 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
     const size_t EN = (size_t)p.E * N;
     const size_t row = (size_t)e * N + base;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
-    float *out = p.bwd.phi_part + (size_t)item * kPhiN;
+    float *rec = p.bwd.phi_part + (size_t)item * kRecWords;
 
     // (a) max-pool with arg-max (lowest node on ties): from the forward's
     //     record, else an encoder pass over every node of the item
@@ -1266,13 +1320,13 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
         }
     }
 
-    // (e) item partial of every parameter gradient: the four waves'
-    //     accumulators summed in wave order, kRedRegs registers per pass
-    store_partials<0>(S, G, out);
-    store_partials<1>(S, G, out);
-    store_partials<2>(S, G, out);
-    store_partials<3>(S, G, out);
-    store_partials<4>(S, G, out);
+    // (e) the item's record of the parameter gradients: the four waves'
+    //     accumulators summed in wave order, eight blocks per pass
+    store_record_chunk<0>(S, G, rec);
+    store_record_chunk<1>(S, G, rec);
+    store_record_chunk<2>(S, G, rec);
+    store_record_chunk<3>(S, G, rec);
+    store_record_chunk<4>(S, G, rec);
     // db2 (passive sums plus the routed one-hots) and db5
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob) {
@@ -1292,20 +1346,20 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
         const int c = threadIdx.x;
         float t = S.vred[0][c];
         for (int w = 1; w < kWaves; ++w) t += S.vred[w][c];
-        out[kB2 + c] = t + S.vroute[c];
-        out[kB4 + c] = S.s4[c];
-        if (c < 3) {
-            float b = __int_as_float(S.ired[0][c]);
-            for (int w = 1; w < kWaves; ++w) b += __int_as_float(S.ired[w][c]);
-            out[kB5 + c] = b;
+        rec[kRecB2 + c] = t + S.vroute[c];
+        rec[kRecB4 + c] = S.s4[c];
+        rec[kRecB3 + c] = S.dpre3[c];
+        rec[kRecGp + c] = L.gp[c];     // dW4[:, 64:] = s4 (x) g'
+        rec[kRecG + c] = L.g[c];       // dW3 = dpre3 (x) g
+        if (c < 4) {
+            float b = 0.0f;
+            if (c < 3) {
+                b = __int_as_float(S.ired[0][c]);
+                for (int w = 1; w < kWaves; ++w) b += __int_as_float(S.ired[w][c]);
+            }
+            rec[kRecB5 + c] = b;
         }
     }
-    for (int idx = threadIdx.x; idx < 64 * 64; idx += kWG) {
-        const int o = idx >> 6, c = idx & 63;
-        out[kW4 + o * 128 + 64 + c] = S.s4[o] * L.gp[c];     // dW4[:, 64:] = s4 (x) g'
-        out[kW3 + o * 64 + c] = S.dpre3[o] * L.g[c];          // dW3 = dpre3 (x) g
-    }
-    if (threadIdx.x < 64) out[kB3 + threadIdx.x] = S.dpre3[threadIdx.x];
     __syncthreads();
 }
 
@@ -1581,64 +1635,93 @@ __global__ __launch_bounds__(kWG) void k_bwd(BwdParams p) {
 // fixed-order reductions of the per-item partials
 // ---------------------------------------------------------------------------
 
-// Segment sums of the parameter partials (FP64).  Segment s covers items
-// [s R, (s + 1) R), R = ceil(n_items / kPhiSegs), and adds the partials of
+// Segment sums of the reduction columns (FP64).  Segment s covers items
+// [s R, (s + 1) R), R = ceil(n_items / kPhiSegs), and adds the records of
 // the items that wrote one (flag set) in ascending item order.  The block
 // compacts its segment's flags into an LDS list 1024 items at a time (wave
 // ballots, waves in order), then every thread sums its column over the list
-// with four loads in flight.
+// with four items in flight.  Plain columns read one record word (record
+// order, so a wave reads 256 contiguous bytes); rank-one columns multiply two.
 __global__ __launch_bounds__(256) void k_phi_segments(const float *part, const int *flag, int n_items,
                                                       double *seg) {
     __shared__ int list[1024];
     __shared__ int wsum[kWaves];
-    const int c = blockIdx.x * 256 + threadIdx.x;
+    const int col = blockIdx.x * 256 + threadIdx.x;
     const int s = blockIdx.y;
     const int wave = threadIdx.x >> 6;
     const int per = (n_items + kPhiSegs - 1) / kPhiSegs;
     const int a = min(n_items, s * per), b = min(n_items, a + per);
-    const int cc = c < kPhiN ? c : 0;   // out-of-range columns read column 0, store nothing
+    // word(s) of this column (uniform per wave: both regions are 64-aligned);
+    // the padding words between kRecWords and kRedPlain add nothing
+    const bool rank1 = col >= kRedPlain;
+    const int k = col - kRedPlain, w = k >> 12, o = (k >> 6) & 63, i = k & 63;
+    const int sa = rank1 ? (w ? kRecB3 + o : kRecB4 + o) : (col < kRecWords ? col : 0);
+    const int sb = rank1 ? (w ? kRecG + i : kRecGp + i) : sa;
+    const bool live_col = col < kRedCols && (rank1 || col < kRecWords);
     double acc = 0.0;
     for (int c0 = a; c0 < b; c0 += 1024) {
         int cnt = 0;   // identical in every thread
         for (int j = 0; j < 4; ++j) {
-            const int i = c0 + j * 256 + threadIdx.x;
-            const bool f = i < b && flag[i] != 0;
+            const int it = c0 + j * 256 + threadIdx.x;
+            const bool f = it < b && flag[it] != 0;
             const unsigned long long bal = __ballot(f);
             __syncthreads();   // the previous round's wsum reads are done
             wsum[wave] = __popcll(bal);
             __syncthreads();
             int off = cnt, tot = 0;
-            for (int w = 0; w < kWaves; ++w) {
-                if (w < wave) off += wsum[w];
-                tot += wsum[w];
+            for (int v = 0; v < kWaves; ++v) {
+                if (v < wave) off += wsum[v];
+                tot += wsum[v];
             }
-            if (f) list[off + lanes_below(bal)] = i;
+            if (f) list[off + lanes_below(bal)] = it;
             cnt += uniform(tot);
         }
         __syncthreads();
-        int q = 0;
-        for (; q + 4 <= cnt; q += 4) {
-            const float v0 = part[(size_t)list[q] * kPhiN + cc];
-            const float v1 = part[(size_t)list[q + 1] * kPhiN + cc];
-            const float v2 = part[(size_t)list[q + 2] * kPhiN + cc];
-            const float v3 = part[(size_t)list[q + 3] * kPhiN + cc];
-            acc += (double)v0;
-            acc += (double)v1;
-            acc += (double)v2;
-            acc += (double)v3;
+        if (live_col) {
+            int q = 0;
+            if (rank1) {
+                for (; q + 4 <= cnt; q += 4) {
+                    double v[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const float *r = part + (size_t)list[q + u] * kRecWords;
+                        v[u] = (double)r[sa] * (double)r[sb];
+                    }
+                    acc += v[0];
+                    acc += v[1];
+                    acc += v[2];
+                    acc += v[3];
+                }
+                for (; q < cnt; ++q) {
+                    const float *r = part + (size_t)list[q] * kRecWords;
+                    acc += (double)r[sa] * (double)r[sb];
+                }
+            } else {
+                for (; q + 4 <= cnt; q += 4) {
+                    const float v0 = part[(size_t)list[q] * kRecWords + sa];
+                    const float v1 = part[(size_t)list[q + 1] * kRecWords + sa];
+                    const float v2 = part[(size_t)list[q + 2] * kRecWords + sa];
+                    const float v3 = part[(size_t)list[q + 3] * kRecWords + sa];
+                    acc += (double)v0;
+                    acc += (double)v1;
+                    acc += (double)v2;
+                    acc += (double)v3;
+                }
+                for (; q < cnt; ++q) acc += (double)part[(size_t)list[q] * kRecWords + sa];
+            }
         }
-        for (; q < cnt; ++q) acc += (double)part[(size_t)list[q] * kPhiN + cc];
         __syncthreads();   // the list is rewritten by the next chunk
     }
-    if (c < kPhiN) seg[(size_t)s * kPhiN + c] = acc;
+    if (col < kRedCols) seg[(size_t)s * kRedCols + col] = acc;
 }
 
-// dL/dphi: the segment sums added in segment order.
-__global__ __launch_bounds__(256) void k_phi_final(const double *seg, float *grad_phi) {
+// dL/dphi: each parameter's column of the segment sums added in segment order.
+__global__ __launch_bounds__(256) void k_phi_final(const double *seg, const int *map, float *grad_phi) {
     const int c = blockIdx.x * 256 + threadIdx.x;
     if (c >= kPhiN) return;
+    const int col = map[c];
     double acc = 0.0;
-    for (int s = 0; s < kPhiSegs; ++s) acc += seg[(size_t)s * kPhiN + c];
+    for (int s = 0; s < kPhiSegs; ++s) acc += seg[(size_t)s * kRedCols + col];
     grad_phi[c] = (float)acc;
 }
 
@@ -1712,9 +1795,10 @@ hipError_t launch_backward(const Plan &pl, const SceneDev *s, const ModelDev &m,
     if (e != hipSuccess) return e;
     slot = timer_begin(pl, ETAC_TIMER_REDUCE, st);
     if (grad_phi) {
-        hipLaunchKernelGGL(k_phi_segments, dim3((kPhiN + 255) / 256, kPhiSegs), dim3(256), 0, st, pl.bwd.phi_part,
+        hipLaunchKernelGGL(k_phi_segments, dim3((kRedCols + 255) / 256, kPhiSegs), dim3(256), 0, st, pl.bwd.phi_part,
                            pl.bwd.item_flag, p.n_items, pl.bwd.phi_seg);
-        hipLaunchKernelGGL(k_phi_final, dim3((kPhiN + 255) / 256), dim3(256), 0, st, pl.bwd.phi_seg, grad_phi);
+        hipLaunchKernelGGL(k_phi_final, dim3((kPhiN + 255) / 256), dim3(256), 0, st, pl.bwd.phi_seg,
+                           pl.bwd.rec_map, grad_phi);
     }
     if (grad_alpha) hipLaunchKernelGGL(k_alpha, dim3(pl.K), dim3(256), 0, st, pl.bwd.alpha_part, n_envs, pl.K, grad_alpha);
     if (s) {
@@ -1754,6 +1838,11 @@ hipError_t launch_contact_backward(const Plan &pl, const SceneDev &s, const floa
     const int nt = s.E * s.O * 12;
     hipLaunchKernelGGL(k_pose, dim3((nt + 255) / 256), dim3(256), 0, st, pl.bwd.pose_part, s.E, pl.K, s.O, grad_rot,
                        grad_trans);
+    return hipGetLastError();
+}
+
+hipError_t init_record_map(const Plan &pl) {
+    hipLaunchKernelGGL(k_record_map, dim3((kPhiN + 255) / 256), dim3(256), 0, 0, pl.bwd.rec_map);
     return hipGetLastError();
 }
 

@@ -11,6 +11,8 @@ namespace etac {
 constexpr int kWG = 256;           // threads per workgroup: 4 waves of 64
 constexpr int kWaves = kWG / 64;
 constexpr int kSavedWords = ETAC_SAVED_WORDS;   // pooling record per (env, patch) item
+constexpr int kRecWords = 10564;                  // parameter-gradient record per item with contact
+constexpr int kRedColsMax = 10624 + 8192;         // columns of the parameter reduction
 constexpr int kMaxPatches = 1024;  // per-patch counters of the contact kernel live in LDS
 constexpr int kDefaultWgPerCu = 2;
 constexpr int kDefaultBatch = 4;   // work-queue positions claimed per atomic
@@ -57,11 +59,12 @@ struct Scratch {
 // Backward scratch (plan flag ETAC_PLAN_BACKWARD).
 struct BwdScratch {
     float *guhat;          // [G][3][n_max]    dL/du_hat per node of the current item
-    float *phi_part;       // [E*K][17411]     per-item parameter-gradient partials
+    float *phi_part;       // [E*K][kRecWords] per-item parameter-gradient records
+    int *rec_map;          // [17411]          reduction column of every parameter
     float *alpha_part;     // [E*K]            per-item dL/dalpha partials
     float *pose_part;      // [E*K][O][12]     per-item pose-gradient partials
     int *item_flag;        // [E*K]            1 if the item wrote partials
-    double *phi_seg;       // [kPhiSegs][17411] segment sums of the parameter reduction
+    double *phi_seg;       // [64][kRedColsMax] segment sums of the parameter reduction
     // hand-over from the decay kernel to the network / contact kernel
     int8_t *cobj_st;       // [E][N]    contact winners of every candidate item (step adjoint)
     float *uhat_st;        // [3][E][N] u_hat of active nodes (step adjoint)
@@ -126,6 +129,7 @@ hipError_t launch_backward(const Plan &p, const SceneDev *s, const ModelDev &m, 
                            const int8_t *cobj_in, const float *uhat_in, const float *grad_u,
                            const uint32_t *saved, float *grad_uhat, float *grad_rot, float *grad_trans,
                            float *grad_alpha, float *grad_phi, hipStream_t st);
+hipError_t init_record_map(const Plan &p);
 hipError_t launch_contact_backward(const Plan &p, const SceneDev &s, const float *grad_uhat,
                                    float *grad_rot, float *grad_trans, hipStream_t st);
 
