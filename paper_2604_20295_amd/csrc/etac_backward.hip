@@ -694,8 +694,8 @@ __device__ void passive_tiles(BwdLds &S, WGrad &G, int cnt, const int (&t)[NT]) 
 
 // Max-pool routing for the wave's 16 channels c = 16 wave + j: the
 // gradient dL/dpre2 = vroute[c] e_c at the arg-max node of channel c.  Its
-// dL/dh1 = W2^T dpre2 comes from the W2^T fragments in both forms; adds the
-// dW2 rows, dW1 and db1 contributions and leaves dL/du_hat of each channel's
+// dL/dh1 = W2^T dpre2 is row c of W2 scaled, in both forms; adds the dW2
+// rows, dW1 and db1 contributions and leaves dL/du_hat of each channel's
 // node in S.dxs (identical in the four lane groups).
 __device__ void routing_tile(const BwdParams &p, BwdLds &S, WGrad &G, int k, int base, int n, const float *uhn) {
     const NetLds &L = S.net;
@@ -720,17 +720,18 @@ __device__ void routing_tile(const BwdParams &p, BwdLds &S, WGrad &G, int k, int
     load_x(M, k, base + (vT ? lnT : 0), vT, uhn, n_max, vT ? lnT : 0, xh, xl);
     floatx4 h1T[4], h1N[4];
     layer1_dual(L, xh, xl, h1T, h1N);
-    // one-hot dL/dpre2 in T form, then dL/dh1 in both forms
+    // dL/dpre2 is one-hot, vroute[c] e_c, so dL/dh1 = W2^T dpre2 is row c of
+    // W2 scaled by vroute[c], in both forms
     const float vt = vT ? S.vroute[cT] : 0.0f;
-    floatx4 d2T[4];
+    const float *w2 = p.model.phi + kW2;
+    floatx4 dh1T[4], dh1N[4];
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) d2T[ob][r] = (ob * 16 + 4 * gq + r == cT) ? vt : 0.0f;
-    half8 sh[2], sl[2];
-    split_chain(d2T, sh, sl);
-    floatx4 dh1T[4], dh1N[4];
-    layer64<true, true, false>(S.w2th, S.w2tl, sh, sl, nullptr, dh1T, dh1N);
+        for (int r = 0; r < 4; ++r) {
+            dh1T[ob][r] = vt * w2[cT * 64 + ob * 16 + 4 * gq + r];
+            dh1N[ob][r] = vn[r] * w2[(16 * wave + 4 * gq + r) * 64 + ob * 16 + col];
+        }
     // dL/du_hat of the channel's node: W1[:, 6..8]^T dpre1 in T form
     float du[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
