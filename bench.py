@@ -54,6 +54,8 @@ def parse():
                     help="also run the graph-captured rollout: 16384 envs, 200 steps of smooth object motion")
     ap.add_argument("--rollout-envs", type=int, default=16384)
     ap.add_argument("--rollout-steps", type=int, default=200)
+    ap.add_argument("--calib-steps", type=int, default=30,
+                    help="Adam iterations of the calibration loop (Eq. 3) timed on the same scenes (0: skip)")
     return ap.parse_args()
 
 
@@ -136,6 +138,43 @@ def rollout(args, mode):
         del g
     plan.close()
     return out
+
+
+def calibration(args, plan, mesh, scene, model, mode):
+    """The calibration loop (Eq. 3, Adam on alpha and Phi) on the benchmark's
+    scenes, with a teacher model's displacements as the targets: iterations/s
+    (one forward, adjoint and update each) and the loss over the run."""
+    import torch
+    import scenes
+    from paper_2604_20295_amd.calibrate import Calibrator, gpu_step_fn, teacher_targets
+    dev = torch.device("cuda", 0)
+
+    def t(a, dtype):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).to(dev)
+
+    n_obj, typ, shape = t(scene.n_obj, torch.int32), t(scene.type, torch.int32), t(scene.shape, torch.float32)
+    rot, trans = t(scene.rot, torch.float32), t(scene.trans, torch.float32)
+    teacher = scenes.draw_model(np.random.default_rng([0, 7]), mesh.pitch, mode)
+    target = teacher_targets(plan, n_obj, typ, shape, rot, trans, t(teacher.alpha, torch.float32),
+                             t(teacher.phi, torch.float32), mode)
+    cal = Calibrator(gpu_step_fn(plan, n_obj, typ, shape, rot, trans, mode), target, t(model.alpha, torch.float32),
+                     t(model.phi, torch.float32), lr_alpha=0.05, lr_phi=1e-3, lr_decay=0.97,
+                     fit_phi=mode != scenes.MODE_DECAY_ONLY)
+    cal.step()
+    torch.cuda.synchronize()
+    losses = []
+    t0 = time.perf_counter()
+    for _ in range(args.calib_steps):
+        losses.append(cal.step())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    losses = [float(x) for x in losses]
+    return {"what": "Adam on (log alpha, Phi) for the Eq. 3 passive-node L2 loss against a teacher model's "
+                    "displacements of the same scenes; each iteration = etac_step + etac_step_backward + update",
+            "iterations": args.calib_steps, "iterations_per_s": args.calib_steps / dt,
+            "ms_per_iteration": dt * 1e3 / args.calib_steps,
+            "node_updates_per_s": float(scene.n_envs) * mesh.n_nodes * args.calib_steps / dt,
+            "loss_first": losses[0], "loss_last": losses[-1]}
 
 
 def work_counts(mesh, n_active):
@@ -424,6 +463,9 @@ def main():
                               "k_bwd_decay": counts["pairs"] / (kernel_avg.get("k_bwd_decay", float("nan")) * 1e-3),
                               "transcendental_ceiling": TRANS_PAIR_CEILING},
     }
+
+    if args.calib_steps > 0:
+        line["calibration"] = calibration(args, plan, mesh, scene, model, mode)
 
     if not args.no_cpu_baseline:
         # the FP64 oracle (forward + adjoint) on blocks of the same envs until
