@@ -1726,6 +1726,10 @@ __global__ __launch_bounds__(256) void k_phi_final(const double *seg, const int 
     grad_phi[c] = (float)acc;
 }
 
+__global__ __launch_bounds__(256) void k_zero(float *x, int n) {
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) x[i] = 0.0f;
+}
+
 // dL/dalpha_k: sum over envs of item (e, k) partials, fixed tree.
 __global__ __launch_bounds__(256) void k_alpha(const float *part, int E, int K, float *grad_alpha) {
     __shared__ double red[256];
@@ -1757,7 +1761,12 @@ hipError_t launch_backward(const Plan &pl, const SceneDev *s, const ModelDev &m,
                            const float *uhat_in, const float *grad_u, const uint32_t *saved, float *grad_uhat,
                            float *grad_rot, float *grad_trans, float *grad_alpha, float *grad_phi,
                            hipStream_t st) {
-    if (n_envs == 0) return hipSuccess;
+    if (n_envs == 0) {
+        // sums over no env: zero parameter gradients
+        if (grad_alpha) hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, st, grad_alpha, pl.K);
+        if (grad_phi) hipLaunchKernelGGL(k_zero, dim3((kPhiN + 255) / 256), dim3(256), 0, st, grad_phi, kPhiN);
+        return hipGetLastError();
+    }
     BwdParams p;
     p.mesh = pl.mesh;
     p.scene = s ? *s : SceneDev{nullptr, nullptr, nullptr, nullptr, nullptr, 0, 1};
