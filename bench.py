@@ -27,6 +27,7 @@ F16_MFMA_PEAK_TFLOPS = 2500.0  # dense FP16 matrix (the MFMA the network kernels
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 MFMA_PASSES = 3                # split-FP16 products per FP32-equivalent product (hi*hi + hi*lo + lo*hi)
 ENC_MAC, DEC_MAC, GLOBAL_MAC = 9 * 64 + 64 * 64, 64 * 128 + 64 * 3, 2 * 64 * 64
+REC_WORDS = 10564      # floats of an item's parameter-gradient record (dense blocks + rank-one factors)
 PAIR_FLOP = 20                 # decay pair: 3 sub, 5 for the squared distance, sqrt, scale, exp, 6 for w*u
 PAIR_FLOP_BWD = 30             # adjoint pair: the above without u, plus d*w and the g.u_hat dot product
 PHI_SIZE = 17411
@@ -217,11 +218,12 @@ def algorithmic_work(kernel, counts, E, N, K, O, mode):
     # k_bwd, given the forward's pooling record: on the passive nodes of
     # contacted patches the network's forward is recomputed (encoder and
     # decoder) and both adjoint products run, 3x those forward flops; the
-    # global MLP likewise per item.  Reads the record (512 B per item).
+    # global MLP likewise per item.  Reads the pooling record (512 B per item)
+    # and writes the item's parameter-gradient record (REC_WORDS floats).
     bwd_flop = 3.0 * 2.0 * ((ENC_MAC + DEC_MAC) * counts["passive"] + GLOBAL_MAC * items)
     return dict(mfma_flop=bwd_flop if net else 0.0, valu_flop=0.0,
                 hbm_bytes=counts["contacted_nodes"] + 24.0 * counts["active"] + 48.0 * O * items
-                + ((4.0 * PHI_SIZE + 512.0) * items if net else 0.0))
+                + ((4.0 * REC_WORDS + 512.0) * items if net else 0.0))
 
 
 def source_digest():
