@@ -697,27 +697,52 @@ __device__ void passive_tiles(BwdLds &S, WGrad &G, int cnt, const int (&t)[NT]) 
 // dL/dh1 = W2^T dpre2 is row c of W2 scaled, in both forms; adds the dW2
 // rows, dW1 and db1 contributions and leaves dL/du_hat of each channel's
 // node in S.dxs (identical in the four lane groups).
-__device__ void routing_tile(const BwdParams &p, BwdLds &S, WGrad &G, int k, int base, int n, const float *uhn) {
-    const NetLds &L = S.net;
+// Network inputs of the wave's channels' arg-max nodes, loaded ahead of the
+// global-MLP adjoint so that their latency overlaps it: T form (this lane's
+// channel 16 wave + (l & 15)) and N form (channels 16 wave + 4 (l >> 4) + r).
+struct RouteIn {
+    float x[8];
+    floatx4 xn;
+};
+
+__device__ __forceinline__ void route_inputs(const BwdParams &p, const BwdLds &S, int k, int base, int n,
+                                             const float *uhn, RouteIn &in) {
     const MeshDev &M = p.mesh;
     const int lane = lane_id(), wave = threadIdx.x >> 6, gq = lane >> 4, col = lane & 15, n_max = p.scr.n_max;
+    const int lnT = S.argmax[16 * wave + col];
+    const bool vT = lnT < n;
+    int lnr[4];
+    bool vr[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        lnr[r] = S.argmax[16 * wave + 4 * gq + r];
+        vr[r] = lnr[r] < n;
+        if (!vr[r]) lnr[r] = 0;
+    }
+    load_x_raw(M, k, base + (vT ? lnT : 0), vT, uhn, n_max, vT ? lnT : 0, in.x);
+    in.xn = load_xn(M, k, base, lnr, vr, uhn, n_max);
+}
+
+__device__ void routing_tile(const BwdParams &p, BwdLds &S, WGrad &G, int n, const RouteIn &in) {
+    const NetLds &L = S.net;
+    const int lane = lane_id(), wave = threadIdx.x >> 6, gq = lane >> 4, col = lane & 15;
     // T form: channel 16 wave + col; N form: channels 16 wave + 4 gq + r
     const int cT = 16 * wave + col;
     const int lnT = S.argmax[cT];
     const bool vT = lnT < n;
-    int lnr[4];
-    bool vr[4];
     float vn[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int c = 16 * wave + 4 * gq + r;
-        lnr[r] = S.argmax[c];
-        vr[r] = lnr[r] < n;
-        if (!vr[r]) lnr[r] = 0;
-        vn[r] = vr[r] ? S.vroute[c] : 0.0f;
+        vn[r] = S.argmax[c] < n ? S.vroute[c] : 0.0f;
     }
     half8 xh, xl;
-    load_x(M, k, base + (vT ? lnT : 0), vT, uhn, n_max, vT ? lnT : 0, xh, xl);
+    {
+        float v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = in.x[e];
+        split8(v, xh, xl);
+    }
     floatx4 h1T[4], h1N[4];
     layer1_dual(L, xh, xl, h1T, h1N);
     // dL/dpre2 is one-hot, vroute[c] e_c, so dL/dh1 = W2^T dpre2 is row c of
@@ -762,7 +787,7 @@ __device__ void routing_tile(const BwdParams &p, BwdLds &S, WGrad &G, int k, int
     // dW1 += dpre1 (x) x (db1 through input 9)
     WOp<1, 4, true> A;
     WOp<1, 1, false> B;
-    B.set(0, 0, load_xn(M, k, base, lnr, vr, uhn, n_max));
+    B.set(0, 0, in.xn);
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob) {
         floatx4 d1;
@@ -1248,7 +1273,15 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
     }
 
     // (c) db4 = s4 = sum_i dpre4_i; global MLP adjoint: dg' = W4[:, 64:]^T s4,
-    //     dpre3 = dg' [g' > 0], dg = W3^T dpre3
+    //     dpre3 = dg' [g' > 0], dg = W3^T dpre3.  The wave's 16 rows of
+    //     W4[:, 64:] and of W3, and the routing pass's node inputs, are
+    //     loaded ahead of the reductions they feed, so their latency overlaps
+    //     the barriers.
+    RouteIn rin;
+    route_inputs(p, S, k, base, n, uhn, rin);
+    float w4g[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) w4g[q] = phi[kW4 + (16 * wave + q) * 128 + 64 + lane];
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob) {
         float v = G.b4[ob];
@@ -1267,9 +1300,12 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
         // each wave sums 16 of the 64 terms, the partials are added in wave order
         const int c = lane;
         float s = 0.0f;
-#pragma unroll 4
-        for (int o = 16 * wave; o < 16 * wave + 16; ++o) s += phi[kW4 + o * 128 + 64 + c] * S.s4[o];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) s += w4g[q] * S.s4[16 * wave + q];
         S.vred[wave][c] = s;
+        float w3r[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) w3r[q] = phi[kW3 + (16 * wave + q) * 64 + c];
         __syncthreads();
         if (threadIdx.x < 64) {
             float t = S.vred[0][c];
@@ -1279,8 +1315,8 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
         }
         __syncthreads();
         s = 0.0f;
-#pragma unroll 4
-        for (int o = 16 * wave; o < 16 * wave + 16; ++o) s += phi[kW3 + o * 64 + c] * S.dpre3[o];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) s += w3r[q] * S.dpre3[16 * wave + q];
         S.vred[wave][c] = s;
         __syncthreads();
         if (threadIdx.x < 64) {
@@ -1294,7 +1330,7 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
     }
 
     // (d) max-pool routing: wave w takes channels 16 w .. 16 w + 15
-    routing_tile(p, S, G, k, base, n, uhn);
+    routing_tile(p, S, G, n, rin);
     __syncthreads();
     // Routed dL/du_hat of active arg-max nodes: lane c of wave 0 owns channel
     // c's node if c is the lowest channel routed there; the owner sums the

@@ -524,11 +524,10 @@ __device__ __forceinline__ void split_chain(const floatx4 x[4], half8 bh[2], hal
 
 // Network input of this lane's node: lane group q = lane >> 4 supplies input
 // features 8 q .. 8 q + 7 of [p - o_k (3), n (3), U_hat (3)], zero padded to 32.
-__device__ __forceinline__ void load_x(const MeshDev &M, int k, int gnode, bool valid, const float *uhn, int n_max,
-                                       int lnode, half8 &xh, half8 &xl, float *xf = nullptr) {
+__device__ __forceinline__ void load_x_raw(const MeshDev &M, int k, int gnode, bool valid, const float *uhn,
+                                           int n_max, int lnode, float (&v)[8]) {
     const int q = lane_id() >> 4;
     const int N = M.N;
-    float v[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) v[e] = 0.0f;
     if (valid && q == 0) {
@@ -542,9 +541,12 @@ __device__ __forceinline__ void load_x(const MeshDev &M, int k, int gnode, bool 
     } else if (valid && q == 1) {
         v[0] = uhn[(size_t)2 * n_max + lnode];
     }
-    if (xf)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) xf[e] = v[e];
+}
+
+__device__ __forceinline__ void load_x(const MeshDev &M, int k, int gnode, bool valid, const float *uhn, int n_max,
+                                       int lnode, half8 &xh, half8 &xl) {
+    float v[8];
+    load_x_raw(M, k, gnode, valid, uhn, n_max, lnode, v);
     split8(v, xh, xl);
 }
 

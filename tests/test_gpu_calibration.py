@@ -40,7 +40,7 @@ def test_calibration_gradient_matches_oracle(oracle_lib):
     loss.backward()
     torch.cuda.synchronize()
     gu = u.grad.double().cpu().numpy()
-    log(f"[gpu] calibration gradient, loss {float(loss):.4e}, envs {n_clean}/8")
+    log(f"[gpu] calibration gradient, loss {float(loss.detach()):.4e}, envs {n_clean}/8")
     ref = oracle_lib.backward(mesh, sc, model, gu)
     _close(alpha.grad.cpu().numpy(), ref["grad_alpha"], "grad_alpha")
     _close(phi.grad.cpu().numpy(), ref["grad_phi"], "grad_phi")
