@@ -130,6 +130,9 @@ struct DecayLds {
     ItemBatch batch;
 };
 
+// Chunks of kWG nodes per pass of compact_given.
+constexpr int kGivenChunks = 4;
+
 struct BwdLds {
     NetLds net;
     half8 w2th[4 * 2 * 64], w2tl[4 * 2 * 64];   // [it][s][lane] split fragments of W2^T
@@ -149,7 +152,7 @@ struct BwdLds {
     int argmax[64];
     float dxs[64][3];             // dL/du_hat of the routed arg-max node of each channel
     double dred[kWaves][12];
-    int wcnt[2][kWaves];
+    int wcnt[kGivenChunks][2][kWaves];   // compaction counts, one set per chunk of a pass
     ItemBatch batch;
 };
 
@@ -1575,6 +1578,71 @@ __global__ __launch_bounds__(256) void k_live_list(BwdParams p) {
 // k_bwd: network and contact adjoint
 // ---------------------------------------------------------------------------
 
+// The active and passive node lists of one (env, patch) item from given
+// contact results (contact_obj and u_hat of a forward or contact pass), as
+// contact_and_compact does with FROM_INPUT, but kGivenChunks chunks of kWG
+// nodes per pair of barriers: the loads are cheap and their latencies overlap.
+// Lists in ascending node order (chunk, then wave, then lane).  Returns m.
+__device__ int compact_given(int E, int N, int n_max, const int8_t *cobj_in, const float *uhat_in,
+                             int (&wcnt)[kGivenChunks][2][kWaves], int e, int base, int n, float *uhn, int *alist,
+                             int *plist, int8_t *wobj) {
+    constexpr int G = kGivenChunks;
+    const size_t EN = (size_t)E * N;
+    const int wave = threadIdx.x >> 6;
+    int run_a = 0, run_p = 0;
+    for (int g0 = 0; g0 < n; g0 += G * kWG) {
+        bool act[G], pas[G];
+#pragma unroll
+        for (int c = 0; c < G; ++c) {
+            const int i = g0 + c * kWG + threadIdx.x;
+            const bool valid = i < n;
+            int best = -1;
+            float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f;
+            if (valid) {
+                const size_t en = (size_t)e * N + base + i;
+                best = cobj_in[en] >= 0 ? (int)cobj_in[en] : -1;
+                if (best >= 0) {
+                    u0 = uhat_in[en];
+                    u1 = uhat_in[EN + en];
+                    u2 = uhat_in[2 * EN + en];
+                }
+                uhn[i] = u0;
+                uhn[n_max + i] = u1;
+                uhn[2 * n_max + i] = u2;
+                if (wobj) wobj[i] = (int8_t)best;
+            }
+            act[c] = valid && best >= 0;
+            pas[c] = valid && best < 0;
+        }
+        unsigned long long ba[G], bp[G];
+#pragma unroll
+        for (int c = 0; c < G; ++c) {
+            ba[c] = __ballot(act[c]);
+            bp[c] = __ballot(pas[c]);
+            // every lane stores the same wave counts (no single-lane block next to the barrier)
+            wcnt[c][0][wave] = __popcll(ba[c]);
+            wcnt[c][1][wave] = __popcll(bp[c]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < G; ++c) {
+            const int i = g0 + c * kWG + threadIdx.x;
+            int oa = run_a, op = run_p, ta = 0, tp = 0;
+            for (int w = 0; w < kWaves; ++w) {
+                if (w < wave) { oa += wcnt[c][0][w]; op += wcnt[c][1][w]; }
+                ta += wcnt[c][0][w];
+                tp += wcnt[c][1][w];
+            }
+            if (act[c]) alist[oa + lanes_below(ba[c])] = i;
+            if (pas[c]) plist[op + lanes_below(bp[c])] = i;
+            run_a += uniform(ta);
+            run_p += uniform(tp);
+        }
+        __syncthreads();
+    }
+    return uniform(run_a);
+}
+
 // One item (item = e K + k indexes the partials).  Step / propagate adjoint:
 // only items with active nodes reach here; contact comes from the hand-over
 // (step) or the caller (propagate), dL/du_hat of active nodes from the decay
@@ -1591,8 +1659,12 @@ __device__ void process_item_bwd(const BwdParams &p, BwdLds &S, int item, int e,
     const size_t row = (size_t)e * N + base;
     const int8_t *cin = KIND == BWD_STEP ? p.bwd.cobj_st : p.cobj_in;
     const float *uin = KIND == BWD_STEP ? p.bwd.uhat_st : p.uhat_in;
-    const int m = contact_and_compact<KIND != BWD_CONTACT>(M, p.scene, p.E, n_max, cin, uin, nullptr, S.wcnt, e, k,
-                                                           base, n, cand, uhn, alist, plist, wobj);
+    int m;
+    if constexpr (KIND == BWD_CONTACT)
+        m = contact_and_compact<false>(M, p.scene, p.E, n_max, nullptr, nullptr, nullptr, S.wcnt[0], e, k, base, n,
+                                       cand, uhn, alist, plist, wobj);
+    else
+        m = compact_given(p.E, N, n_max, cin, uin, S.wcnt, e, base, n, uhn, alist, plist, wobj);
     if (m == 0) {
         // contact adjoint only: the other kinds never queue items without contact
         if (threadIdx.x < 64) p.bwd.item_flag[item] = 0;
