@@ -283,3 +283,46 @@ def twist_from_grad_rot(grad_rot, R):
         e[k] = 1.0
         out[k] = np.sum(G * (skew(e) @ R))
     return out
+
+
+# ----------------------------------------------------------------------------
+# triangle-mesh objects
+# ----------------------------------------------------------------------------
+
+def closest_point(q, a, b, c):
+    """Closest point of triangle (a, b, c) to q.  Returns (squared distance,
+    closest point [3], feature: 0 face, 1 edge ab, 2 bc, 3 ca, 4 vertex a, 5 b,
+    6 c)."""
+    lib = _load()
+    lib.oracle_closest_point.restype = C.c_double
+    cp = np.empty(3, np.float64)
+    feat = np.empty(1, np.int32)
+    s = lib.oracle_closest_point(*[_p(_f64(x)) for x in (q, a, b, c)], _p(cp), _p(feat))
+    return float(s), cp, int(feat[0])
+
+
+def mesh_pseudonormals(meshset, m):
+    """Pseudo-normals [T][7][3] of mesh m of a TriMeshSet (face, edges ab bc
+    ca, vertices a b c)."""
+    lib = _load()
+    t0, t1 = int(meshset.tri_offset[m]), int(meshset.tri_offset[m + 1])
+    pn = np.empty((t1 - t0, 7, 3), np.float64)
+    _call(lib.oracle_mesh_pseudonormals, C.c_int(meshset.n_verts), _f64(meshset.verts), _i32(meshset.tris),
+          C.c_int(t0), C.c_int(t1), pn)
+    return pn
+
+
+def contact_mesh(mesh, scene, meshset):
+    """Contact with primitives and triangle-mesh objects (type 3, shape[0] =
+    mesh index into `meshset`).  Returns contact_obj, uhat, n_active as
+    contact()."""
+    lib = _load()
+    K, N, off, pos, nrm, _ = _mesh_args(mesh)
+    E, O, n_obj, typ, shape, rot, trans = _scene_args(scene)
+    cobj = np.empty((E.value, N.value), np.int8)
+    uhat = np.empty((3, E.value, N.value), np.float64)
+    na = np.empty((E.value, K.value), np.int32)
+    _call(lib.oracle_contact_mesh, K, N, off, pos, nrm, E, O, n_obj, typ, shape, rot, trans,
+          C.c_int(meshset.n_meshes), _i32(meshset.tri_offset), C.c_int(meshset.n_verts), _f64(meshset.verts),
+          _i32(meshset.tris), cobj, uhat, na)
+    return cobj, uhat, na

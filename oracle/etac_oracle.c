@@ -50,7 +50,7 @@
 #define NIN 9        /* [p - o, n, u_hat] */
 #define PHI_N 17411
 
-enum { O_SPHERE = 0, O_BOX = 1, O_CAPSULE = 2 };
+enum { O_SPHERE = 0, O_BOX = 1, O_CAPSULE = 2, O_MESH = 3 };
 enum { O_FULL = 0, O_DECAY_ONLY = 1, O_RESIDUAL_ONLY = 2 };
 
 /* ------------------------------------------------------------------------ */
@@ -221,6 +221,7 @@ static void contact_env(const problem_t *P, int e, int8_t *cobj, double *uhat, i
             memset(&bh, 0, sizeof bh);
             for (int o = 0; o < P->n_obj[e]; ++o) {
                 size_t eo = (size_t)e * O + o;
+                if (P->type[eo] < O_SPHERE || P->type[eo] > O_CAPSULE) continue; /* meshes: contact_mesh_env */
                 hit_t h = penetrate(P->type[eo], P->shape + 4 * eo, P->rot + 9 * eo,
                                     P->trans + 3 * eo, p, n);
                 if (h.inside && (best < 0 || h.depth > bh.depth)) { best = o; bh = h; }
@@ -233,6 +234,281 @@ static void contact_env(const problem_t *P, int e, int8_t *cobj, double *uhat, i
                 *sig = fnv(*sig, best);
                 if (best >= 0) *sig = fnv(fnv(fnv(*sig, bh.face), bh.sign), bh.degenerate);
             }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* 1b. contact: point vs closed triangle mesh                               */
+/* ------------------------------------------------------------------------ */
+/*
+ * The paper's contact queries the signed distance field of each object's
+ * mesh (Sec. III-A, contact detection; the objects of Sec. IV are meshes).
+ * Here the SDF is evaluated exactly on the triangles: the distance is the
+ * minimum over the triangles of the point-triangle distance, and the sign
+ * comes from the angle-weighted pseudo-normal of the closest feature
+ * (face, edge or vertex), which is exact for a closed, consistently
+ * oriented mesh (Baerentzen and Aanaes, IEEE TVCG 2005).  The closest point
+ * on a triangle follows the Voronoi-region classification of Ericson
+ * ("Real-Time Collision Detection", 2005, Sec. 5.1.5).  Readings (listed in
+ * the design notes): the node is inside iff (q - c) . n < 0 for its closest
+ * point c and pseudo-normal n; depth = |q - c|; u_hat = R (c - q); the
+ * lowest triangle index wins distance ties; the deepest object (primitive
+ * or mesh) wins, lowest object index on ties.
+ *
+ * FP64 operation order (round to nearest-even, no FMA); dot(x, y) means
+ * (x0 y0 + x1 y1) + x2 y2 and vector +, - are componentwise:
+ *   q = R^T (p - t) as for the primitives;
+ *   ab = b - a, ac = c - a, ap = q - a, d1 = dot(ab, ap), d2 = dot(ac, ap)
+ *   d1 <= 0 and d2 <= 0                      -> vertex a
+ *   bp = q - b, d3 = dot(ab, bp), d4 = dot(ac, bp)
+ *   d3 >= 0 and d4 <= d3                     -> vertex b
+ *   vc = d1 d4 - d3 d2
+ *   vc <= 0 and d1 >= 0 and d3 <= 0          -> edge ab, v = d1 / (d1 - d3), c = a + v ab
+ *   cp = q - c, d5 = dot(ab, cp), d6 = dot(ac, cp)
+ *   d6 >= 0 and d5 <= d6                     -> vertex c
+ *   vb = d5 d2 - d1 d6
+ *   vb <= 0 and d2 >= 0 and d6 <= 0          -> edge ca, w = d2 / (d2 - d6), c = a + w ac
+ *   va = d3 d6 - d5 d4, e4 = d4 - d3, e5 = d5 - d6
+ *   va <= 0 and e4 >= 0 and e5 >= 0          -> edge bc, w = e4 / (e4 + e5), c = b + w (c - b)
+ *   otherwise face: den = (va + vb) + vc, v = vb / den, w = vc / den,
+ *                   c = (a + v ab) + w ac
+ *   s = dot(q - c, q - c); minimum over triangles with strict <.
+ * Pseudo-normals (from the FP32 vertices promoted to FP64):
+ *   face   : x = ab x ac = (ab1 ac2 - ab2 ac1, ab2 ac0 - ab0 ac2, ab0 ac1 - ab1 ac0),
+ *            n_f = x / sqrt(dot(x, x));
+ *   edge   : n_f + n_g, f and g the two faces sharing the edge;
+ *   vertex : sum over the faces f containing it, ascending f, of theta_f n_f,
+ *            theta = acos(clamp(dot(e1, e2) / (sqrt(dot(e1, e1)) sqrt(dot(e2, e2)), -1, 1)),
+ *            e1, e2 the edges leaving the vertex in the order (a: b - a, c - a;
+ *            b: c - b, a - b; c: a - c, b - c).
+ */
+enum { F_FACE = 0, F_EDGE_AB = 1, F_EDGE_BC = 2, F_EDGE_CA = 3, F_VERT_A = 4, F_VERT_B = 5, F_VERT_C = 6 };
+
+static inline double dot3(const double x[3], const double y[3]) {
+    return (x[0] * y[0] + x[1] * y[1]) + x[2] * y[2];
+}
+
+/* Closest point cp of triangle (a, b, c) to q; returns the squared distance
+ * and the feature holding cp. */
+static double closest_on_triangle(const double q[3], const double a[3], const double b[3],
+                                  const double c[3], double cp[3], int *feature) {
+    double ab[3], ac[3], ap[3], bp[3], cq[3], w[3];
+    for (int i = 0; i < 3; ++i) { ab[i] = b[i] - a[i]; ac[i] = c[i] - a[i]; ap[i] = q[i] - a[i]; }
+    double d1 = dot3(ab, ap), d2 = dot3(ac, ap);
+    if (d1 <= 0.0 && d2 <= 0.0) {
+        *feature = F_VERT_A;
+        for (int i = 0; i < 3; ++i) cp[i] = a[i];
+        goto done;
+    }
+    for (int i = 0; i < 3; ++i) bp[i] = q[i] - b[i];
+    double d3 = dot3(ab, bp), d4 = dot3(ac, bp);
+    if (d3 >= 0.0 && d4 <= d3) {
+        *feature = F_VERT_B;
+        for (int i = 0; i < 3; ++i) cp[i] = b[i];
+        goto done;
+    }
+    double vc = d1 * d4 - d3 * d2;
+    if (vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0) {
+        double v = d1 / (d1 - d3);
+        *feature = F_EDGE_AB;
+        for (int i = 0; i < 3; ++i) cp[i] = a[i] + v * ab[i];
+        goto done;
+    }
+    for (int i = 0; i < 3; ++i) cq[i] = q[i] - c[i];
+    double d5 = dot3(ab, cq), d6 = dot3(ac, cq);
+    if (d6 >= 0.0 && d5 <= d6) {
+        *feature = F_VERT_C;
+        for (int i = 0; i < 3; ++i) cp[i] = c[i];
+        goto done;
+    }
+    double vb = d5 * d2 - d1 * d6;
+    if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) {
+        double wv = d2 / (d2 - d6);
+        *feature = F_EDGE_CA;
+        for (int i = 0; i < 3; ++i) cp[i] = a[i] + wv * ac[i];
+        goto done;
+    }
+    double va = d3 * d6 - d5 * d4;
+    double e4 = d4 - d3, e5 = d5 - d6;
+    if (va <= 0.0 && e4 >= 0.0 && e5 >= 0.0) {
+        double wv = e4 / (e4 + e5);
+        *feature = F_EDGE_BC;
+        for (int i = 0; i < 3; ++i) cp[i] = b[i] + wv * (c[i] - b[i]);
+        goto done;
+    }
+    {
+        double den = (va + vb) + vc;
+        double v = vb / den, wv = vc / den;
+        *feature = F_FACE;
+        for (int i = 0; i < 3; ++i) cp[i] = (a[i] + v * ab[i]) + wv * ac[i];
+    }
+done:
+    for (int i = 0; i < 3; ++i) w[i] = q[i] - cp[i];
+    return dot3(w, w);
+}
+
+/* One mesh of a mesh set: corners and the seven pseudo-normals per triangle. */
+typedef struct {
+    int T;
+    double *corner; /* [T][3 corners][3] */
+    double *pn;     /* [T][7 features][3], feature order F_FACE .. F_VERT_C */
+} trimesh_t;
+
+static void trimesh_free(trimesh_t *m) {
+    free(m->corner);
+    free(m->pn);
+    m->corner = m->pn = NULL;
+}
+
+/* Build mesh `m` of a set: triangles tri_offset[m] .. tri_offset[m+1]-1 of
+ * `tris` (vertex indices into `verts` [V][3]).  Returns 0, or -2 when an
+ * edge is not shared by exactly one other triangle in reverse direction
+ * (the mesh is not closed and consistently oriented), or -3 for a zero-area
+ * triangle or a vertex index out of range. */
+static int trimesh_build(trimesh_t *out, int V, const double *verts, const int32_t *tris, int t0, int t1) {
+    const int T = t1 - t0;
+    out->T = T;
+    out->corner = (double *)calloc((size_t)T * 9 + 1, sizeof(double));
+    out->pn = (double *)calloc((size_t)T * 21 + 1, sizeof(double));
+    double *fn = (double *)calloc((size_t)T * 3 + 1, sizeof(double));
+    if (!out->corner || !out->pn || !fn) { free(fn); trimesh_free(out); return -3; }
+    int rc = 0;
+    for (int f = 0; f < T && rc == 0; ++f) {
+        const int32_t *tv = tris + 3 * (size_t)(t0 + f);
+        for (int k = 0; k < 3; ++k) {
+            if (tv[k] < 0 || tv[k] >= V) { rc = -3; break; }
+            for (int i = 0; i < 3; ++i) out->corner[f * 9 + k * 3 + i] = verts[3 * (size_t)tv[k] + i];
+        }
+        if (rc) break;
+        const double *a = out->corner + f * 9, *b = a + 3, *c = a + 6;
+        double ab[3], ac[3], x[3];
+        for (int i = 0; i < 3; ++i) { ab[i] = b[i] - a[i]; ac[i] = c[i] - a[i]; }
+        x[0] = ab[1] * ac[2] - ab[2] * ac[1];
+        x[1] = ab[2] * ac[0] - ab[0] * ac[2];
+        x[2] = ab[0] * ac[1] - ab[1] * ac[0];
+        double len = sqrt(dot3(x, x));
+        if (!(len > 0.0)) { rc = -3; break; }
+        for (int i = 0; i < 3; ++i) fn[f * 3 + i] = x[i] / len;
+    }
+    /* edges: the face across directed edge (u -> v) holds (v -> u) */
+    for (int f = 0; f < T && rc == 0; ++f) {
+        const int32_t *tv = tris + 3 * (size_t)(t0 + f);
+        for (int k = 0; k < 3 && rc == 0; ++k) {
+            int u = tv[k], v = tv[(k + 1) % 3], other = -1, cnt = 0;
+            for (int g = 0; g < T; ++g) {
+                const int32_t *gv = tris + 3 * (size_t)(t0 + g);
+                for (int l = 0; l < 3; ++l)
+                    if (gv[l] == v && gv[(l + 1) % 3] == u) { other = g; ++cnt; }
+                for (int l = 0; l < 3; ++l)
+                    if (g != f && gv[l] == u && gv[(l + 1) % 3] == v) cnt += 2; /* duplicated direction */
+            }
+            if (cnt != 1) { rc = -2; break; }
+            /* k = 0: edge ab, 1: bc, 2: ca */
+            for (int i = 0; i < 3; ++i) out->pn[f * 21 + (1 + k) * 3 + i] = fn[f * 3 + i] + fn[other * 3 + i];
+        }
+    }
+    /* vertices: angle-weighted sums over the incident faces, ascending face */
+    for (int f = 0; f < T && rc == 0; ++f) {
+        const int32_t *tv = tris + 3 * (size_t)(t0 + f);
+        for (int i = 0; i < 3; ++i) out->pn[f * 21 + i] = fn[f * 3 + i];
+        for (int k = 0; k < 3; ++k) {
+            double acc[3] = {0.0, 0.0, 0.0};
+            for (int g = 0; g < T; ++g) {
+                const int32_t *gv = tris + 3 * (size_t)(t0 + g);
+                for (int l = 0; l < 3; ++l) {
+                    if (gv[l] != tv[k]) continue;
+                    const double *P0 = out->corner + g * 9 + l * 3;
+                    const double *P1 = out->corner + g * 9 + ((l + 1) % 3) * 3;
+                    const double *P2 = out->corner + g * 9 + ((l + 2) % 3) * 3;
+                    double e1[3], e2[3];
+                    for (int i = 0; i < 3; ++i) { e1[i] = P1[i] - P0[i]; e2[i] = P2[i] - P0[i]; }
+                    double cs = dot3(e1, e2) / (sqrt(dot3(e1, e1)) * sqrt(dot3(e2, e2)));
+                    if (cs < -1.0) cs = -1.0;
+                    if (cs > 1.0) cs = 1.0;
+                    double th = acos(cs);
+                    for (int i = 0; i < 3; ++i) acc[i] = acc[i] + th * fn[g * 3 + i];
+                }
+            }
+            for (int i = 0; i < 3; ++i) out->pn[f * 21 + (4 + k) * 3 + i] = acc[i];
+        }
+    }
+    free(fn);
+    if (rc) trimesh_free(out);
+    return rc;
+}
+
+/* Penetration of point p into mesh object (R, t). */
+static hit_t mesh_penetrate(const trimesh_t *m, const double *R, const double *t, const double p[3]) {
+    hit_t h;
+    memset(&h, 0, sizeof h);
+    double d0 = p[0] - t[0], d1 = p[1] - t[1], d2 = p[2] - t[2];
+    double q[3];
+    for (int c = 0; c < 3; ++c) q[c] = (R[0 * 3 + c] * d0 + R[1 * 3 + c] * d1) + R[2 * 3 + c] * d2;
+    int bf = -1, bfeat = 0;
+    double bs = 0.0, bcp[3] = {0.0, 0.0, 0.0};
+    for (int f = 0; f < m->T; ++f) {
+        double cp[3];
+        int feat;
+        const double *a = m->corner + f * 9;
+        double s = closest_on_triangle(q, a, a + 3, a + 6, cp, &feat);
+        if (bf < 0 || s < bs) {
+            bf = f; bs = s; bfeat = feat;
+            for (int i = 0; i < 3; ++i) bcp[i] = cp[i];
+        }
+    }
+    if (bf < 0) return h;
+    double w[3] = {q[0] - bcp[0], q[1] - bcp[1], q[2] - bcp[2]};
+    if (!(dot3(w, m->pn + bf * 21 + bfeat * 3) < 0.0)) return h;
+    h.inside = 1;
+    h.face = bf;
+    h.sign = bfeat;
+    h.depth = sqrt(bs);
+    double v[3] = {bcp[0] - q[0], bcp[1] - q[1], bcp[2] - q[2]};
+    for (int a = 0; a < 3; ++a) h.u[a] = (R[a * 3 + 0] * v[0] + R[a * 3 + 1] * v[1]) + R[a * 3 + 2] * v[2];
+    return h;
+}
+
+/* Mesh index of an ETAC-mesh object, or -1 when shape[0] is not an integer
+ * in [0, n_meshes). */
+static int mesh_index(const double *shape, int n_meshes) {
+    double x = shape[0];
+    if (!(x >= 0.0) || !(x < (double)n_meshes) || x != floor(x)) return -1;
+    return (int)x;
+}
+
+/* Contact of env e with primitives and meshes: the deepest object wins,
+ * lowest object index on ties. */
+static void contact_mesh_env(const problem_t *P, const trimesh_t *meshes, int n_meshes, int e, int8_t *cobj,
+                             double *uhat, int32_t *n_active) {
+    const int N = P->N, E = P->E, O = P->O;
+    for (int k = 0; k < P->K; ++k) n_active[(size_t)e * P->K + k] = 0;
+    for (int k = 0; k < P->K; ++k) {
+        for (int i = P->offset[k]; i < P->offset[k + 1]; ++i) {
+            double p[3] = {P->pos[i], P->pos[N + i], P->pos[2 * N + i]};
+            double n[3] = {P->nrm[i], P->nrm[N + i], P->nrm[2 * N + i]};
+            int best = -1;
+            hit_t bh;
+            memset(&bh, 0, sizeof bh);
+            for (int o = 0; o < P->n_obj[e]; ++o) {
+                size_t eo = (size_t)e * O + o;
+                hit_t h;
+                int ty = P->type[eo];
+                if (ty >= O_SPHERE && ty <= O_CAPSULE) {
+                    h = penetrate(ty, P->shape + 4 * eo, P->rot + 9 * eo, P->trans + 3 * eo, p, n);
+                } else if (ty == O_MESH) {
+                    int mi = mesh_index(P->shape + 4 * eo, n_meshes);
+                    if (mi < 0) continue;
+                    h = mesh_penetrate(meshes + mi, P->rot + 9 * eo, P->trans + 3 * eo, p);
+                } else {
+                    continue;
+                }
+                if (h.inside && (best < 0 || h.depth > bh.depth)) { best = o; bh = h; }
+            }
+            size_t en = (size_t)e * N + i;
+            cobj[en] = (int8_t)best;
+            for (int a = 0; a < 3; ++a) uhat[(size_t)a * E * N + en] = best >= 0 ? bh.u[a] : 0.0;
+            if (best >= 0) n_active[(size_t)e * P->K + k] += 1;
         }
     }
 }
@@ -653,6 +929,7 @@ static void contact_env_backward(const problem_t *P, int e, const double *guhat,
         memset(&bh, 0, sizeof bh);
         for (int o = 0; o < P->n_obj[e]; ++o) {
             size_t eo = (size_t)e * O + o;
+            if (P->type[eo] < O_SPHERE || P->type[eo] > O_CAPSULE) continue;
             hit_t h = penetrate(P->type[eo], P->shape + 4 * eo, P->rot + 9 * eo, P->trans + 3 * eo, p, n);
             if (h.inside && (best < 0 || h.depth > bh.depth)) { best = o; bh = h; }
         }
@@ -817,4 +1094,54 @@ int oracle_backward(int K, int N, const int32_t *offset, const double *pos, cons
     free(uhat);
     free(na);
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* triangle-mesh contact entry points                                       */
+/* ------------------------------------------------------------------------ */
+
+/* Closest point of triangle (a, b, c) to q: returns the squared distance,
+ * writes cp[3] and the feature (0 face, 1 edge ab, 2 bc, 3 ca, 4 vertex a,
+ * 5 b, 6 c). */
+double oracle_closest_point(const double *q, const double *a, const double *b, const double *c, double *cp,
+                            int32_t *feature) {
+    int f;
+    double s = closest_on_triangle(q, a, b, c, cp, &f);
+    *feature = f;
+    return s;
+}
+
+/* Pseudo-normals of the triangles t0 .. t1-1 of a mesh: pn [T][7][3]
+ * (face, edges ab bc ca, vertices a b c).  Returns 0 or the trimesh_build
+ * error. */
+int oracle_mesh_pseudonormals(int V, const double *verts, const int32_t *tris, int t0, int t1, double *pn) {
+    trimesh_t m;
+    int rc = trimesh_build(&m, V, verts, tris, t0, t1);
+    if (rc) return rc;
+    memcpy(pn, m.pn, sizeof(double) * 21 * (size_t)m.T);
+    trimesh_free(&m);
+    return 0;
+}
+
+/* Contact with primitives and triangle meshes (type 3, shape[0] = mesh
+ * index).  Mesh m owns triangles tri_offset[m] .. tri_offset[m+1]-1 of
+ * tris [T][3] (indices into verts [V][3]).  Outputs as oracle_contact. */
+int oracle_contact_mesh(int K, int N, const int32_t *offset, const double *pos, const double *nrm, int E,
+                        int O, const int32_t *n_obj, const int32_t *type, const double *shape,
+                        const double *rot, const double *trans, int n_meshes, const int32_t *tri_offset,
+                        int V, const double *verts, const int32_t *tris, int8_t *cobj, double *uhat,
+                        int32_t *n_active) {
+    problem_t P = mkprob(K, N, offset, pos, nrm, NULL, E, O, n_obj, type, shape, rot, trans);
+    trimesh_t *ms = (trimesh_t *)calloc((size_t)n_meshes + 1, sizeof(trimesh_t));
+    if (!ms) return -3;
+    int rc = 0;
+    for (int m = 0; m < n_meshes && rc == 0; ++m) rc = trimesh_build(ms + m, V, verts, tris, tri_offset[m],
+                                                                     tri_offset[m + 1]);
+    if (rc == 0) {
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int e = 0; e < E; ++e) contact_mesh_env(&P, ms, n_meshes, e, cobj, uhat, n_active);
+    }
+    for (int m = 0; m < n_meshes; ++m) trimesh_free(ms + m);
+    free(ms);
+    return rc;
 }

@@ -15,6 +15,7 @@ import pytest
 import oracle
 from tests import test_oracle_adjoint as TA
 from tests import test_oracle_contact as TC
+from tests import test_oracle_mesh as TM
 from tests import test_oracle_propagate as TP
 
 SRC = oracle.SRC
@@ -26,8 +27,10 @@ MUTANTS = [
     ("box face tie to highest axis", "if (sl < best) { best = sl; cs = c; }\n        }\n        h.face = cs;",
      "if (sl <= best) { best = sl; cs = c; }\n        }\n        h.face = cs;"),
     ("capsule ignores clamp", "double v0 = q[0], v1 = q[1], v2 = q[2] - z;", "double v0 = q[0], v1 = q[1], v2 = q[2];"),
-    ("shallowest object wins", "if (h.inside && (best < 0 || h.depth > bh.depth)) { best = o; bh = h; }\n            }\n            size_t en",
-     "if (h.inside && (best < 0 || h.depth < bh.depth)) { best = o; bh = h; }\n            }\n            size_t en"),
+    ("shallowest object wins", "P->trans + 3 * eo, p, n);\n                if (h.inside && (best < 0 || h.depth > bh.depth))",
+     "P->trans + 3 * eo, p, n);\n                if (h.inside && (best < 0 || h.depth < bh.depth))"),
+    ("mesh contact: shallowest object wins", "continue;\n                }\n                if (h.inside && (best < 0 || h.depth > bh.depth))",
+     "continue;\n                }\n                if (h.inside && (best < 0 || h.depth < bh.depth))"),
     ("decay uses squared distance", "return exp(-alpha * d);", "return exp(-alpha * d * d);"),
     ("decay sums the passive node", "for (int a = 0; a < 3; ++a) acc[a] += w * uhat[(size_t)a * E * N + ej];",
      "for (int a = 0; a < 3; ++a) acc[a] += w * uhat[(size_t)a * E * N + (size_t)e * N + i];"),
@@ -47,6 +50,11 @@ MUTANTS = [
     ("max-pool routes to node 0", "S->df[(size_t)S->argmax[c] * NF + c] += dg[c];", "S->df[(size_t)0 * NF + c] += dg[c];"),
     ("decoder gradient misses W4 g' part", "dW->W4[o * 2 * NF + NF + c] += dh4[o] * S->gp[c];", "dW->W4[o * 2 * NF + NF + c] += dh4[o] * S->g[c];"),
     ("encoder gate uses h1 instead of pre1", "dpre1[c] = pre1[c] > 0.0 ? acc : 0.0;", "dpre1[c] = acc;"),
+    ("mesh sign from the face normal only", "if (!(dot3(w, m->pn + bf * 21 + bfeat * 3) < 0.0)) return h;",
+     "if (!(dot3(w, m->pn + bf * 21) < 0.0)) return h;"),
+    ("mesh edge ab parameter", "double v = d1 / (d1 - d3);", "double v = d3 / (d1 - d3);"),
+    ("mesh u_hat points inward", "double v[3] = {bcp[0] - q[0], bcp[1] - q[1], bcp[2] - q[2]};",
+     "double v[3] = {q[0] - bcp[0], q[1] - bcp[1], q[2] - bcp[2]};"),
     ("u_hat gradient from passive input", "if (cobj[ei] >= 0) { /* only active nodes carry u_hat into the input */",
      "if (cobj[ei] < 0) { /* only active nodes carry u_hat into the input */"),
 ]
@@ -69,6 +77,10 @@ def _pins():
         lambda o: TA.test_contact_adjoint_vs_torch_autograd(o),
         lambda o: [TA.test_propagation_adjoint_vs_torch_autograd(o, m) for m in (0, 1, 2)],
         lambda o: TA.test_raw_rotation_entries_vs_fd(o),
+        lambda o: TM.test_closest_point_vs_independent_and_sampling(o),
+        lambda o: TM.test_convex_hull_inside_and_depth_vs_qhull_planes(o),
+        lambda o: TM.test_triangulated_cube_matches_box_primitive(o),
+        lambda o: TM.test_deepest_object_wins_across_primitives_and_meshes(o),
     ]
 
 
