@@ -76,6 +76,10 @@ typedef int32_t etac_status;
 #define ETAC_SPHERE  0
 #define ETAC_BOX     1
 #define ETAC_CAPSULE 2
+#define ETAC_MESH    3          /* closed triangle mesh of an etac_meshset;
+                                   shape[0] = mesh index (an integer value);
+                                   only etac_contact_mesh tests these, every
+                                   other call ignores such objects          */
 
 #define ETAC_FULL          0    /* Eq. 2: decay + residual (Table 2, full)     */
 #define ETAC_DECAY_ONLY    1    /* Eq. 1 only (Table 2, linear decay only)     */
@@ -171,6 +175,41 @@ etac_status etac_propagate(etac_plan *plan, const etac_model *model, int32_t n_e
  * ETAC_SAVED_WORDS. */
 etac_status etac_step(etac_plan *plan, const etac_scene *scene, const etac_model *model,
                       float *u, int8_t *contact_obj, int32_t *n_active, void *saved, void *stream);
+
+/* Rigid objects given as closed triangle meshes (the paper's objects are
+ * meshes whose signed distance fields drive contact, Sec. III-A contact
+ * detection and Sec. IV).  A mesh set holds several meshes: mesh m owns
+ * triangles tri_offset[m] .. tri_offset[m+1]-1 of `tris` [T][3] (vertex
+ * indices into `verts` [n_verts][3], object-frame positions in mm, FP32),
+ * counter-clockwise seen from outside.  Every mesh must be closed and
+ * consistently oriented (each directed edge used once, its reverse once by
+ * another triangle), with no zero-area triangle: otherwise ETAC_ERR_VALUE.
+ * Limits: 1 <= n_meshes <= 65536, 4 <= triangles per mesh, T <= 2^24.
+ * All pointers HOST, read during the call.  The set computes the
+ * angle-weighted pseudo-normals of every face, edge and vertex in FP64,
+ * groups each mesh's triangles into clusters of at most 64 with bounding
+ * balls, and uploads everything to the current device (synchronous; not
+ * during stream capture: ETAC_ERR_CAPTURE).  *out is set only on success. */
+typedef struct etac_meshset etac_meshset;
+etac_status etac_meshset_create(int32_t n_meshes, const int32_t *tri_offset, int32_t n_verts,
+                                const float *verts, const int32_t *tris, etac_meshset **out);
+
+/* Free a mesh set and its device memory (synchronises the device). NULL is OK. */
+etac_status etac_meshset_destroy(etac_meshset *ms);
+
+/* Contact pass with primitives and triangle meshes (Sec. III-A contact
+ * detection and local displacement).  Objects of type ETAC_MESH name a mesh
+ * of `ms` by shape[0]; a value that is not an integer in [0, n_meshes) makes
+ * the object ignored.  A node is inside a mesh when (q - c) . n < 0 for its
+ * closest surface point c (minimum point-triangle distance, lowest triangle
+ * index on ties) and the pseudo-normal n of the face, edge or vertex holding
+ * c; its depth is |q - c| and u_hat = R (c - q).  The deepest object wins
+ * over primitives and meshes alike, lowest index on ties.  Same outputs and
+ * layouts as etac_contact (uhat may be NULL); the results feed
+ * etac_propagate.  `ms` must live on the plan's device (ETAC_ERR_VALUE
+ * otherwise).  No adjoint with respect to mesh poses is provided. */
+etac_status etac_contact_mesh(etac_plan *plan, const etac_meshset *ms, const etac_scene *scene,
+                              int8_t *contact_obj, float *uhat, int32_t *n_active, void *stream);
 
 /* Adjoint of the contact pass: given dL/du_hat [3][E][N] (DEVICE; read on
  * active nodes only) returns dL/dR [E][O][9] and dL/dt [E][O][3] (DEVICE,

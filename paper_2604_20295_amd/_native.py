@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libetac.so")
 
 ETAC_OK = 0
-ETAC_SPHERE, ETAC_BOX, ETAC_CAPSULE = 0, 1, 2
+ETAC_SPHERE, ETAC_BOX, ETAC_CAPSULE, ETAC_MESH = 0, 1, 2, 3
 ETAC_FULL, ETAC_DECAY_ONLY, ETAC_RESIDUAL_ONLY = 0, 1, 2
 ETAC_PHI_SIZE = 17411
 ETAC_SAVED_WORDS = 128     # 32-bit words of the pooling record per (env, patch) item
@@ -32,6 +32,7 @@ EXPORTED = (
     "etac_status_string", "etac_last_hip_error", "etac_plan_info", "etac_plan_set_occupancy",
     "etac_plan_set_timing", "etac_plan_kernel_time", "etac_plan_set_batch",
     "etac_plan_set_launch", "etac_plan_get_launch", "etac_plan_autotune",
+    "etac_meshset_create", "etac_meshset_destroy", "etac_contact_mesh",
 )
 
 
@@ -76,6 +77,9 @@ def lib():
             "etac_plan_create": ([P(etac_mesh), i32, i32, C.c_uint32, P(vp)], i32),
             "etac_plan_destroy": ([vp], i32),
             "etac_contact": ([vp, P(etac_scene), vp, vp, vp, vp], i32),
+            "etac_meshset_create": ([i32, vp, i32, vp, vp, P(vp)], i32),
+            "etac_meshset_destroy": ([vp], i32),
+            "etac_contact_mesh": ([vp, vp, P(etac_scene), vp, vp, vp, vp], i32),
             "etac_propagate": ([vp, P(etac_model), i32, vp, vp, vp, vp, vp], i32),
             "etac_step": ([vp, P(etac_scene), P(etac_model), vp, vp, vp, vp, vp], i32),
             "etac_contact_backward": ([vp, P(etac_scene), vp, vp, vp, vp], i32),
@@ -223,6 +227,54 @@ def etac_contact(plan, scene, contact_obj, uhat, n_active):
     _req(n_active, torch.int32, (E, plan.K), "n_active", plan.device)
     _check("etac_contact", lib().etac_contact(plan.handle, C.byref(scene), _ptr(contact_obj), _ptr(uhat),
                                               _ptr(n_active), _stream(plan.device)))
+
+
+class MeshSet:
+    """An etac_meshset on the current GPU: closed triangle meshes of rigid
+    objects (verts float32 [V][3], tris int32 [T][3], tri_offset int32
+    [M+1]; layout of scenes.trimeshes.TriMeshSet)."""
+
+    def __init__(self, verts, tris, tri_offset):
+        import torch
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        v = np.ascontiguousarray(verts, dtype=np.float32)
+        t = np.ascontiguousarray(tris, dtype=np.int32)
+        off = np.ascontiguousarray(tri_offset, dtype=np.int32)
+        if v.ndim != 2 or v.shape[1] != 3 or t.ndim != 2 or t.shape[1] != 3 or off.ndim != 1 or off.size < 2:
+            raise ValueError("verts [V][3], tris [T][3], tri_offset [M+1] expected")
+        if int(off[-1]) != t.shape[0]:
+            raise ValueError("tri_offset[-1] must equal the triangle count")
+        self.n_meshes = int(off.size - 1)
+        h = C.c_void_p()
+        _check("etac_meshset_create", lib().etac_meshset_create(self.n_meshes, off.ctypes.data, int(v.shape[0]),
+                                                                v.ctypes.data, t.ctypes.data, C.byref(h)))
+        self.handle = h
+
+    @classmethod
+    def from_set(cls, ms):
+        return cls(ms.verts, ms.tris, ms.tri_offset)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            lib().etac_meshset_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def etac_contact_mesh(plan, meshset, scene, contact_obj, uhat, n_active):
+    import torch
+    E = scene.n_envs
+    _req(contact_obj, torch.int8, (E, plan.N), "contact_obj", plan.device)
+    _req(uhat, torch.float32, (3, E, plan.N), "uhat", plan.device)
+    _req(n_active, torch.int32, (E, plan.K), "n_active", plan.device)
+    _check("etac_contact_mesh", lib().etac_contact_mesh(plan.handle, meshset.handle, C.byref(scene),
+                                                        _ptr(contact_obj), _ptr(uhat), _ptr(n_active),
+                                                        _stream(plan.device)))
 
 
 def saved_buffer(plan, n_envs):

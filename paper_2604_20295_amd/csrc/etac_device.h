@@ -148,13 +148,15 @@ __device__ __forceinline__ int contact_node(const SceneDev &S, int e, unsigned c
     return best;
 }
 
-// Objects of env e whose bounding ball may reach patch k's bounding sphere.
+// Primitives of env e whose bounding ball may reach patch k's bounding
+// sphere (objects of other types, triangle meshes included, are ignored).
 __device__ __forceinline__ unsigned cull_objects(const SceneDev &S, const MeshDev &M, int e, int k) {
     unsigned cand = 0;
     const int no = min(S.n_obj[e], S.O);
     const float4 b = M.bound[k];
     for (int o = 0; o < no; ++o) {
         const size_t eo = (size_t)e * S.O + o;
+        if ((unsigned)S.type[eo] > (unsigned)ETAC_CAPSULE) continue;
         const float *t = S.trans + 3 * eo;
         const float dx = b.x - t[0], dy = b.y - t[1], dz = b.z - t[2];
         const float reach = (b.w + bounding_radius(S.type[eo], S.shape + 4 * eo)) * 1.001f + 1e-3f;

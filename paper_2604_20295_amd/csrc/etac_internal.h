@@ -133,4 +133,29 @@ hipError_t init_record_map(const Plan &p);
 hipError_t launch_contact_backward(const Plan &p, const SceneDev &s, const float *grad_uhat,
                                    float *grad_rot, float *grad_trans, hipStream_t st);
 
+// Triangle meshes of rigid objects on the device (one etac_meshset).  The
+// triangles of each mesh are stored in cluster order (clusters of at most 64
+// spatially close triangles); `orig` keeps each triangle's index within its
+// mesh as given, which breaks distance ties.
+struct MeshSetDev {
+    const int4 *mesh;        // [M] first triangle, end triangle, first cluster, end cluster
+    const float *radius;     // [M] ball about the object origin holding the mesh (rounded up)
+    const float *corner;     // [9][T] a.x a.y a.z b.x b.y b.z c.x c.y c.z per triangle
+    const int *orig;         // [T] index of the triangle within its mesh, as given
+    const double *pn;        // [T][7][3] pseudo-normals: face, edges ab bc ca, vertices a b c
+    const double4 *ball;     // [C] cluster bounding ball: centre, radius (with margin)
+    const int2 *range;       // [C] cluster triangle range [first, end)
+    int M, T, C;
+};
+
+hipError_t launch_contact_mesh(const Plan &p, const MeshSetDev &ms, const SceneDev &s, int8_t *cobj, float *uhat,
+                               int32_t *n_active, hipStream_t st);
+
 }  // namespace etac
+
+struct etac_meshset {
+    int device;
+    etac::MeshSetDev d;
+    void *allocs[8];
+    int n_allocs;
+};

@@ -1,0 +1,550 @@
+// Contact with rigid objects given as closed triangle meshes (ETac, Sec. III-A
+// contact detection against object SDFs; the objects of Sec. IV are meshes).
+//
+//   host : etac_meshset_create validates the meshes, computes the FP64
+//          angle-weighted pseudo-normals (Baerentzen and Aanaes, IEEE TVCG
+//          2005) of every face, edge and vertex, splits each mesh into
+//          clusters of at most 64 triangles by recursive median splits of
+//          the triangle centroids, and uploads it all.
+//   k_contact_mesh : one workgroup per env, as the primitive contact pass.
+//          Primitives are tested one node per lane.  For a mesh object the
+//          nodes inside its bounding ball are queried one at a time by the
+//          whole wave: lanes take the clusters' lower bounds, then the
+//          triangles of the nearest unvisited cluster (one per lane), with
+//          wave reductions for the minimum; clusters whose lower bound
+//          exceeds the best distance so far are never opened.
+//
+// The closest point of a triangle follows the Voronoi-region classification
+// of Ericson ("Real-Time Collision Detection", 2005, Sec. 5.1.5).  All of it
+// runs in FP64 in a fixed operation order without contraction into FMA, the
+// divisions and square roots correctly rounded, so the inside set and the
+// deepest-object choice are reproducible bit for bit.  Cluster skipping
+// never changes the result: a cluster ball's radius carries a margin of
+// 1e-6 mm, far above the rounding of the distances compared, so a skipped
+// cluster's triangles are strictly farther than the best one.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <numeric>
+#include <utility>
+#include <vector>
+
+#include "etac_device.h"
+
+namespace etac {
+
+// ---------------------------------------------------------------------------
+// device
+// ---------------------------------------------------------------------------
+
+// Features of a triangle holding its closest point.
+enum { FEAT_FACE = 0, FEAT_AB = 1, FEAT_BC = 2, FEAT_CA = 3, FEAT_A = 4, FEAT_B = 5, FEAT_C = 6 };
+
+struct TriCorners {
+    double a0, a1, a2, b0, b1, b2, c0, c1, c2;
+};
+
+__device__ __forceinline__ TriCorners load_tri(const MeshSetDev &ms, int t) {
+    const size_t T = (size_t)ms.T;
+    const float *c = ms.corner + t;
+    return TriCorners{c[0], c[T], c[2 * T], c[3 * T], c[4 * T], c[5 * T], c[6 * T], c[7 * T], c[8 * T]};
+}
+
+// Closest point (x0, x1, x2) of the triangle to q, its feature, and the
+// squared distance.  Dot products are (x0 y0 + x1 y1) + x2 y2.
+__device__ __forceinline__ double closest_tri(double q0, double q1, double q2, const TriCorners &t, double &x0,
+                                              double &x1, double &x2, int &feat) {
+#pragma clang fp contract(off)
+    const double ab0 = t.b0 - t.a0, ab1 = t.b1 - t.a1, ab2 = t.b2 - t.a2;
+    const double ac0 = t.c0 - t.a0, ac1 = t.c1 - t.a1, ac2 = t.c2 - t.a2;
+    const double ap0 = q0 - t.a0, ap1 = q1 - t.a1, ap2 = q2 - t.a2;
+    const double d1 = (ab0 * ap0 + ab1 * ap1) + ab2 * ap2;
+    const double d2 = (ac0 * ap0 + ac1 * ap1) + ac2 * ap2;
+    const double bp0 = q0 - t.b0, bp1 = q1 - t.b1, bp2 = q2 - t.b2;
+    const double d3 = (ab0 * bp0 + ab1 * bp1) + ab2 * bp2;
+    const double d4 = (ac0 * bp0 + ac1 * bp1) + ac2 * bp2;
+    const double cq0 = q0 - t.c0, cq1 = q1 - t.c1, cq2 = q2 - t.c2;
+    const double d5 = (ab0 * cq0 + ab1 * cq1) + ab2 * cq2;
+    const double d6 = (ac0 * cq0 + ac1 * cq1) + ac2 * cq2;
+    const double vc = d1 * d4 - d3 * d2;
+    const double vb = d5 * d2 - d1 * d6;
+    const double va = d3 * d6 - d5 * d4;
+    const double e4 = d4 - d3, e5 = d5 - d6;
+    if (d1 <= 0.0 && d2 <= 0.0) {
+        feat = FEAT_A;
+        x0 = t.a0; x1 = t.a1; x2 = t.a2;
+    } else if (d3 >= 0.0 && d4 <= d3) {
+        feat = FEAT_B;
+        x0 = t.b0; x1 = t.b1; x2 = t.b2;
+    } else if (vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0) {
+        const double v = d1 / (d1 - d3);
+        feat = FEAT_AB;
+        x0 = t.a0 + v * ab0; x1 = t.a1 + v * ab1; x2 = t.a2 + v * ab2;
+    } else if (d6 >= 0.0 && d5 <= d6) {
+        feat = FEAT_C;
+        x0 = t.c0; x1 = t.c1; x2 = t.c2;
+    } else if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) {
+        const double w = d2 / (d2 - d6);
+        feat = FEAT_CA;
+        x0 = t.a0 + w * ac0; x1 = t.a1 + w * ac1; x2 = t.a2 + w * ac2;
+    } else if (va <= 0.0 && e4 >= 0.0 && e5 >= 0.0) {
+        const double w = e4 / (e4 + e5);
+        feat = FEAT_BC;
+        x0 = t.b0 + w * (t.c0 - t.b0); x1 = t.b1 + w * (t.c1 - t.b1); x2 = t.b2 + w * (t.c2 - t.b2);
+    } else {
+        const double den = (va + vb) + vc;
+        const double v = vb / den, w = vc / den;
+        feat = FEAT_FACE;
+        x0 = (t.a0 + v * ab0) + w * ac0;
+        x1 = (t.a1 + v * ab1) + w * ac1;
+        x2 = (t.a2 + v * ab2) + w * ac2;
+    }
+    const double w0 = q0 - x0, w1 = q1 - x1, w2 = q2 - x2;
+    return (w0 * w0 + w1 * w1) + w2 * w2;
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+    return v;
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off));
+    return v;
+}
+
+// Signed-distance query of one point q (object frame, the same value in
+// every lane of the wave) against mesh `mesh`; the whole wave takes part.
+// Returns the same result in every lane.
+__device__ Pen mesh_query(const MeshSetDev &ms, int mesh, double q0, double q1, double q2, const float *R) {
+#pragma clang fp contract(off)
+    const int lane = lane_id();
+    const int4 mr = ms.mesh[mesh];
+    const double kInf = __builtin_inf();
+    double best_s = kInf;
+    int best_o = 0x7fffffff, best_t = -1;
+    for (int cb = mr.z; cb < mr.w; cb += 64) {
+        const int c = cb + lane;
+        double lb = kInf;   // squared lower bound of the distance to cluster c
+        if (c < mr.w) {
+            const double4 b = ms.ball[c];
+            const double dx = q0 - b.x, dy = q1 - b.y, dz = q2 - b.z;
+            const double l = sqrt((dx * dx + dy * dy) + dz * dz) - b.w;
+            lb = l > 0.0 ? l * l : 0.0;
+        }
+        for (;;) {
+            const double m = wave_min(lb);
+            // every cluster left is strictly farther (or all visited); a NaN
+            // bound (non-finite pose) also ends the search, with no result
+            if (!(m < kInf) || !(m <= best_s)) break;
+            const int src = __ffsll((unsigned long long)__ballot(lb == m)) - 1;
+            if (lane == src) lb = kInf;
+            const int2 r = ms.range[cb + src];
+            const int t = r.x + lane;
+            double s = kInf;
+            int o = 0x7fffffff;
+            if (t < r.y) {
+                double x0, x1, x2;
+                int f;
+                s = closest_tri(q0, q1, q2, load_tri(ms, t), x0, x1, x2, f);
+                o = ms.orig[t];
+            }
+            const double sm = wave_min(s);
+            const int om = wave_min(s == sm ? o : 0x7fffffff);
+            if (sm < best_s || (sm == best_s && om < best_o)) {
+                best_s = sm;
+                best_o = om;
+                best_t = r.x + __ffsll((unsigned long long)__ballot(s == sm && o == om)) - 1;
+            }
+        }
+    }
+    Pen h;
+    h.inside = false;
+    h.depth = 0.0;
+    h.u0 = h.u1 = h.u2 = 0.0;
+    if (best_t < 0) return h;
+    double x0, x1, x2;
+    int f;
+    closest_tri(q0, q1, q2, load_tri(ms, best_t), x0, x1, x2, f);   // same inputs, same bits as in the search
+    const double *n = ms.pn + ((size_t)best_t * 7 + f) * 3;
+    const double w0 = q0 - x0, w1 = q1 - x1, w2 = q2 - x2;
+    if (!((w0 * n[0] + w1 * n[1]) + w2 * n[2] < 0.0)) return h;
+    h.inside = true;
+    h.depth = sqrt(best_s);
+    const double v0 = x0 - q0, v1 = x1 - q1, v2 = x2 - q2;
+    h.u0 = ((double)R[0] * v0 + (double)R[1] * v1) + (double)R[2] * v2;
+    h.u1 = ((double)R[3] * v0 + (double)R[4] * v1) + (double)R[5] * v2;
+    h.u2 = ((double)R[6] * v0 + (double)R[7] * v1) + (double)R[8] * v2;
+    return h;
+}
+
+// Mesh index named by a mesh object's shape[0], or -1.
+__device__ __forceinline__ int mesh_of(const float *sh, int M) {
+    const float x = sh[0];
+    return (x >= 0.0f && x < (float)M && x == floorf(x)) ? (int)x : -1;
+}
+
+struct MeshContactParams {
+    MeshDev mesh;
+    SceneDev scene;
+    MeshSetDev ms;
+    int8_t *cobj;      // [E][N]
+    float *uhat;       // [3][E][N] or null
+    int32_t *n_active; // [E][K]
+};
+
+// Candidate objects (primitives and valid meshes) of env e whose bounding
+// ball may reach patch k's bounding sphere.
+__device__ __forceinline__ unsigned cull_mesh_objects(const MeshContactParams &p, int e, int k) {
+    const SceneDev &S = p.scene;
+    unsigned cand = 0;
+    const int no = min(S.n_obj[e], S.O);
+    const float4 b = p.mesh.bound[k];
+    for (int o = 0; o < no; ++o) {
+        const size_t eo = (size_t)e * S.O + o;
+        const int ty = S.type[eo];
+        float rad;
+        if (ty >= ETAC_SPHERE && ty <= ETAC_CAPSULE) {
+            rad = bounding_radius(ty, S.shape + 4 * eo);
+        } else if (ty == ETAC_MESH) {
+            const int m = mesh_of(S.shape + 4 * eo, p.ms.M);
+            if (m < 0) continue;
+            rad = p.ms.radius[m];
+        } else {
+            continue;
+        }
+        const float *t = S.trans + 3 * eo;
+        const float dx = b.x - t[0], dy = b.y - t[1], dz = b.z - t[2];
+        const float reach = (b.w + rad) * 1.001f + 1e-3f;
+        if ((dx * dx + dy * dy + dz * dz) * (1.0f - 1e-5f) <= reach * reach) cand |= 1u << o;
+    }
+    return cand;
+}
+
+__global__ __launch_bounds__(kWG) void k_contact_mesh(MeshContactParams p) {
+    __shared__ int cnt[kMaxPatches];
+    __shared__ uint8_t cand[kMaxPatches];
+    const int e = blockIdx.x;
+    const MeshDev &M = p.mesh;
+    const SceneDev &S = p.scene;
+    const int N = M.N, K = M.K;
+    const size_t EN = (size_t)S.E * N;
+    for (int k = threadIdx.x; k < K; k += kWG) {
+        cnt[k] = 0;
+        cand[k] = (uint8_t)cull_mesh_objects(p, e, k);
+    }
+    __syncthreads();
+    const int lane = lane_id();
+    const int no = min(S.n_obj[e], S.O);
+    const size_t row = (size_t)e * N;
+    // whole waves step through the nodes: every lane reaches the wave-wide queries
+    for (int i0 = threadIdx.x - lane; i0 < N; i0 += kWG) {
+        const int i = i0 + lane;
+        const bool valid = i < N;
+        const int k = valid ? M.node_patch[i] : 0;
+        const unsigned c = valid ? cand[k] : 0u;
+        const float px = valid ? M.pos[i] : 0.0f, py = valid ? M.pos[N + i] : 0.0f;
+        const float pz = valid ? M.pos[2 * N + i] : 0.0f;
+        int best = -1;
+        double bd = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
+        if (__ballot(c != 0u)) {
+            for (int o = 0; o < no; ++o) {
+                const size_t eo = (size_t)e * S.O + o;
+                const int ty = S.type[eo];
+                const float *sh = S.shape + 4 * eo;
+                const float *R = S.rot + 9 * eo;
+                const float *t = S.trans + 3 * eo;
+                const bool take = (c >> o) & 1u;
+                const float dx = px - t[0], dy = py - t[1], dz = pz - t[2];
+                const float d2 = dx * dx + dy * dy + dz * dz;
+                if (ty >= ETAC_SPHERE && ty <= ETAC_CAPSULE) {
+                    const float rb = bounding_radius(ty, sh) * 1.001f + 1e-3f;
+                    if (!take || d2 > rb * rb) continue;
+                    const Pen h = penetrate(ty, sh, R, t, px, py, pz, M.nrm[i], M.nrm[N + i], M.nrm[2 * N + i]);
+                    if (h.inside && (best < 0 || h.depth > bd)) {
+                        best = o;
+                        bd = h.depth;
+                        b0 = h.u0; b1 = h.u1; b2 = h.u2;
+                    }
+                } else if (ty == ETAC_MESH) {
+                    const int m = mesh_of(sh, p.ms.M);
+                    if (m < 0) continue;
+                    const float rb = p.ms.radius[m] * 1.001f + 1e-3f;
+                    unsigned long long todo = __ballot(take && d2 <= rb * rb);
+                    const double t0 = t[0], t1 = t[1], t2 = t[2];
+                    const double r00 = R[0], r01 = R[1], r02 = R[2];
+                    const double r10 = R[3], r11 = R[4], r12 = R[5];
+                    const double r20 = R[6], r21 = R[7], r22 = R[8];
+                    while (todo) {
+                        const int src = __ffsll(todo) - 1;
+                        todo &= todo - 1;
+                        // the node of lane src, the same value in every lane
+                        const double d0 = (double)__shfl(px, src) - t0;
+                        const double d1 = (double)__shfl(py, src) - t1;
+                        const double e2 = (double)__shfl(pz, src) - t2;
+                        double q0, q1, q2;
+                        {
+#pragma clang fp contract(off)
+                            q0 = (r00 * d0 + r10 * d1) + r20 * e2;
+                            q1 = (r01 * d0 + r11 * d1) + r21 * e2;
+                            q2 = (r02 * d0 + r12 * d1) + r22 * e2;
+                        }
+                        const Pen h = mesh_query(p.ms, m, q0, q1, q2, R);
+                        if (lane == src && h.inside && (best < 0 || h.depth > bd)) {
+                            best = o;
+                            bd = h.depth;
+                            b0 = h.u0; b1 = h.u1; b2 = h.u2;
+                        }
+                    }
+                }
+            }
+        }
+        if (valid) {
+            p.cobj[row + i] = (int8_t)best;
+            if (p.uhat) {
+                p.uhat[row + i] = (float)b0;
+                p.uhat[EN + row + i] = (float)b1;
+                p.uhat[2 * EN + row + i] = (float)b2;
+            }
+            if (best >= 0) atomicAdd(&cnt[k], 1);
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < K; k += kWG) p.n_active[(size_t)e * K + k] = cnt[k];
+}
+
+hipError_t launch_contact_mesh(const Plan &p, const MeshSetDev &ms, const SceneDev &s, int8_t *cobj, float *uhat,
+                               int32_t *n_active, hipStream_t st) {
+    if (s.E == 0) return hipSuccess;
+    MeshContactParams cp{p.mesh, s, ms, cobj, uhat, n_active};
+    hipLaunchKernelGGL(k_contact_mesh, dim3(s.E), dim3(kWG), 0, st, cp);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// host: mesh-set construction
+// ---------------------------------------------------------------------------
+namespace {
+
+struct V3 {
+    double x, y, z;
+};
+
+#pragma clang fp contract(off)
+inline V3 sub(const V3 &a, const V3 &b) { return V3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline double dot(const V3 &a, const V3 &b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
+
+// Unit normal of triangle (a, b, c); false for zero area.
+bool face_normal(const V3 &a, const V3 &b, const V3 &c, V3 &n) {
+    const V3 ab = sub(b, a), ac = sub(c, a);
+    const V3 x{ab.y * ac.z - ab.z * ac.y, ab.z * ac.x - ab.x * ac.z, ab.x * ac.y - ab.y * ac.x};
+    const double len = std::sqrt(dot(x, x));
+    if (!(len > 0.0) || !std::isfinite(len)) return false;
+    n = V3{x.x / len, x.y / len, x.z / len};
+    return true;
+}
+
+// Interior angle at p0 of the triangle (p0, p1, p2).
+double corner_angle(const V3 &p0, const V3 &p1, const V3 &p2) {
+    const V3 e1 = sub(p1, p0), e2 = sub(p2, p0);
+    double cs = dot(e1, e2) / (std::sqrt(dot(e1, e1)) * std::sqrt(dot(e2, e2)));
+    cs = std::min(1.0, std::max(-1.0, cs));
+    return std::acos(cs);
+}
+
+struct BuiltMesh {
+    std::vector<int> order;              // triangles (index within the mesh) in cluster order
+    std::vector<std::pair<int, int>> clusters;   // ranges into `order`
+};
+
+// Recursive median split of the triangle centroids along the longest axis
+// of their bounding box, down to clusters of at most 64 triangles.
+void split(std::vector<int> &ids, int lo, int hi, const std::vector<V3> &cen, BuiltMesh &out) {
+    if (hi - lo <= 64) {
+        out.clusters.push_back({lo, hi});
+        return;
+    }
+    V3 mn = cen[ids[lo]], mx = mn;
+    for (int i = lo; i < hi; ++i) {
+        const V3 &c = cen[ids[i]];
+        mn = V3{std::min(mn.x, c.x), std::min(mn.y, c.y), std::min(mn.z, c.z)};
+        mx = V3{std::max(mx.x, c.x), std::max(mx.y, c.y), std::max(mx.z, c.z)};
+    }
+    const double ex = mx.x - mn.x, ey = mx.y - mn.y, ez = mx.z - mn.z;
+    const int axis = (ex >= ey && ex >= ez) ? 0 : (ey >= ez ? 1 : 2);
+    auto coord = [&](int t) { return axis == 0 ? cen[t].x : (axis == 1 ? cen[t].y : cen[t].z); };
+    const int mid = lo + (hi - lo) / 2;
+    std::nth_element(ids.begin() + lo, ids.begin() + mid, ids.begin() + hi, [&](int a, int b) {
+        const double ca = coord(a), cb = coord(b);
+        return ca < cb || (ca == cb && a < b);
+    });
+    split(ids, lo, mid, cen, out);
+    split(ids, mid, hi, cen, out);
+}
+
+}  // namespace
+}  // namespace etac
+
+extern "C" {
+
+etac_status etac_meshset_create(int32_t n_meshes, const int32_t *tri_offset, int32_t n_verts, const float *verts,
+                                const int32_t *tris, etac_meshset **out) {
+    using namespace etac;
+    if (!tri_offset || !verts || !tris || !out) return ETAC_ERR_NULL;
+    if (n_meshes < 1 || n_meshes > 65536 || n_verts < 3) return ETAC_ERR_SHAPE;
+    if (tri_offset[0] != 0) return ETAC_ERR_SHAPE;
+    for (int m = 0; m < n_meshes; ++m)
+        if (tri_offset[m + 1] - tri_offset[m] < 4) return ETAC_ERR_SHAPE;
+    const int T = tri_offset[n_meshes];
+    if (T > (1 << 24)) return ETAC_ERR_SHAPE;
+    for (size_t i = 0; i < (size_t)n_verts * 3; ++i)
+        if (!std::isfinite(verts[i])) return ETAC_ERR_VALUE;
+    for (size_t i = 0; i < (size_t)T * 3; ++i)
+        if (tris[i] < 0 || tris[i] >= n_verts) return ETAC_ERR_VALUE;
+    auto vtx = [&](int v) { return V3{verts[3 * (size_t)v], verts[3 * (size_t)v + 1], verts[3 * (size_t)v + 2]}; };
+
+    std::vector<float> corner((size_t)9 * T);
+    std::vector<int> orig(T);
+    std::vector<double> pn((size_t)21 * T);
+    std::vector<double4> ball;
+    std::vector<int2> range;
+    std::vector<int4> mesh(n_meshes);
+    std::vector<float> radius(n_meshes);
+    for (int m = 0; m < n_meshes; ++m) {
+        const int t0 = tri_offset[m], nt = tri_offset[m + 1] - t0;
+        const int32_t *tv = tris + 3 * (size_t)t0;
+        // closed and consistently oriented: every directed edge once, its reverse once
+        std::map<std::pair<int, int>, int> edge;   // directed edge -> triangle
+        for (int f = 0; f < nt; ++f)
+            for (int k = 0; k < 3; ++k) {
+                const std::pair<int, int> key{tv[3 * f + k], tv[3 * f + (k + 1) % 3]};
+                if (key.first == key.second || !edge.emplace(key, f).second) return ETAC_ERR_VALUE;
+            }
+        std::vector<V3> fn(nt), cen(nt);
+        for (int f = 0; f < nt; ++f) {
+            const V3 a = vtx(tv[3 * f]), b = vtx(tv[3 * f + 1]), c = vtx(tv[3 * f + 2]);
+            if (!face_normal(a, b, c, fn[f])) return ETAC_ERR_VALUE;
+            cen[f] = V3{(a.x + b.x + c.x) / 3.0, (a.y + b.y + c.y) / 3.0, (a.z + b.z + c.z) / 3.0};
+        }
+        // per-triangle pseudo-normals in the order given
+        std::vector<double> mpn((size_t)21 * nt);
+        std::map<int, V3> vsum;   // vertex -> angle-weighted normal sum, faces in ascending order
+        for (int f = 0; f < nt; ++f)
+            for (int k = 0; k < 3; ++k) {
+                const int v = tv[3 * f + k];
+                const double th = corner_angle(vtx(v), vtx(tv[3 * f + (k + 1) % 3]), vtx(tv[3 * f + (k + 2) % 3]));
+                V3 &acc = vsum.emplace(v, V3{0.0, 0.0, 0.0}).first->second;
+                acc = V3{acc.x + th * fn[f].x, acc.y + th * fn[f].y, acc.z + th * fn[f].z};
+            }
+        for (int f = 0; f < nt; ++f) {
+            double *o = mpn.data() + (size_t)21 * f;
+            o[0] = fn[f].x; o[1] = fn[f].y; o[2] = fn[f].z;
+            for (int k = 0; k < 3; ++k) {   // edges ab, bc, ca
+                auto it = edge.find({tv[3 * f + (k + 1) % 3], tv[3 * f + k]});
+                if (it == edge.end()) return ETAC_ERR_VALUE;   // open mesh
+                const V3 &g = fn[it->second];
+                o[3 + 3 * k] = fn[f].x + g.x;
+                o[4 + 3 * k] = fn[f].y + g.y;
+                o[5 + 3 * k] = fn[f].z + g.z;
+            }
+            for (int k = 0; k < 3; ++k) {   // vertices a, b, c
+                const V3 &s = vsum[tv[3 * f + k]];
+                o[12 + 3 * k] = s.x; o[13 + 3 * k] = s.y; o[14 + 3 * k] = s.z;
+            }
+        }
+        // clusters
+        BuiltMesh bm;
+        bm.order.resize(nt);
+        std::iota(bm.order.begin(), bm.order.end(), 0);
+        split(bm.order, 0, nt, cen, bm);
+        const int c_first = (int)ball.size();
+        double rmax = 0.0;
+        for (auto [lo, hi] : bm.clusters) {
+            V3 mn{INFINITY, INFINITY, INFINITY}, mx{-INFINITY, -INFINITY, -INFINITY};
+            for (int i = lo; i < hi; ++i)
+                for (int k = 0; k < 3; ++k) {
+                    const V3 p = vtx(tv[3 * bm.order[i] + k]);
+                    mn = V3{std::min(mn.x, p.x), std::min(mn.y, p.y), std::min(mn.z, p.z)};
+                    mx = V3{std::max(mx.x, p.x), std::max(mx.y, p.y), std::max(mx.z, p.z)};
+                }
+            const V3 cc{(mn.x + mx.x) / 2.0, (mn.y + mx.y) / 2.0, (mn.z + mx.z) / 2.0};
+            double r = 0.0;
+            for (int i = lo; i < hi; ++i)
+                for (int k = 0; k < 3; ++k) {
+                    const V3 d = sub(vtx(tv[3 * bm.order[i] + k]), cc);
+                    r = std::max(r, std::sqrt(dot(d, d)));
+                    const V3 p = vtx(tv[3 * bm.order[i] + k]);
+                    rmax = std::max(rmax, std::sqrt(dot(p, p)));
+                }
+            const double scale = std::sqrt(dot(cc, cc)) + r;
+            ball.push_back(make_double4(cc.x, cc.y, cc.z, r + 1e-6 + 1e-12 * scale));
+            range.push_back(make_int2(t0 + lo, t0 + hi));
+        }
+        for (int i = 0; i < nt; ++i) {
+            const int f = bm.order[i], slot = t0 + i;
+            for (int k = 0; k < 3; ++k) {
+                const V3 p = vtx(tv[3 * f + k]);
+                corner[(size_t)(3 * k) * T + slot] = (float)p.x;
+                corner[(size_t)(3 * k + 1) * T + slot] = (float)p.y;
+                corner[(size_t)(3 * k + 2) * T + slot] = (float)p.z;
+            }
+            orig[slot] = f;
+            std::copy(mpn.begin() + (size_t)21 * f, mpn.begin() + (size_t)21 * (f + 1), pn.begin() + (size_t)21 * slot);
+        }
+        mesh[m] = make_int4(t0, t0 + nt, c_first, (int)ball.size());
+        float rf = (float)rmax;
+        if ((double)rf < rmax) rf = std::nextafter(rf, INFINITY);
+        radius[m] = rf;
+    }
+
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(nullptr, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return ETAC_ERR_CAPTURE;
+    etac_meshset *ms = new (std::nothrow) etac_meshset();
+    if (!ms) return ETAC_ERR_HIP;
+    ms->n_allocs = 0;
+    if (hipGetDevice(&ms->device) != hipSuccess) {
+        delete ms;
+        return ETAC_ERR_HIP;
+    }
+    auto upload = [&](const void *src, size_t bytes, void **dst) -> hipError_t {
+        void *d = nullptr;
+        hipError_t e = hipMalloc(&d, bytes ? bytes : 1);
+        if (e != hipSuccess) return e;
+        ms->allocs[ms->n_allocs++] = d;
+        *dst = d;
+        return bytes ? hipMemcpy(d, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+    };
+    void *p[7];
+    hipError_t e = hipSuccess;
+    const void *src[7] = {mesh.data(), radius.data(), corner.data(), orig.data(), pn.data(), ball.data(),
+                          range.data()};
+    const size_t bytes[7] = {mesh.size() * sizeof(int4), radius.size() * sizeof(float), corner.size() * sizeof(float),
+                             orig.size() * sizeof(int), pn.size() * sizeof(double), ball.size() * sizeof(double4),
+                             range.size() * sizeof(int2)};
+    for (int i = 0; i < 7 && e == hipSuccess; ++i) e = upload(src[i], bytes[i], &p[i]);
+    if (e != hipSuccess) {
+        etac_meshset_destroy(ms);
+        return ETAC_ERR_HIP;
+    }
+    ms->d = MeshSetDev{(const int4 *)p[0], (const float *)p[1], (const float *)p[2], (const int *)p[3],
+                       (const double *)p[4], (const double4 *)p[5], (const int2 *)p[6], n_meshes, T,
+                       (int)ball.size()};
+    *out = ms;
+    return ETAC_OK;
+}
+
+etac_status etac_meshset_destroy(etac_meshset *ms) {
+    if (!ms) return ETAC_OK;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(ms->device);
+    (void)hipDeviceSynchronize();
+    for (int i = 0; i < ms->n_allocs; ++i) (void)hipFree(ms->allocs[i]);
+    (void)hipSetDevice(cur);
+    delete ms;
+    return ETAC_OK;
+}
+
+}  // extern "C"

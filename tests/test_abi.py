@@ -90,6 +90,8 @@ def test_calls_reject_null_plan():
     assert lib.etac_contact_backward(None, C.byref(sc), None, None, None, None) == -1
     assert lib.etac_propagate_backward(None, C.byref(md), 1, None, None, None, None, None, None, None, None) == -1
     assert lib.etac_step_backward(None, C.byref(sc), C.byref(md), None, None, None, None, None, None, None) == -1
+    assert lib.etac_contact_mesh(None, None, C.byref(sc), None, None, None, None) == -1
+    assert lib.etac_meshset_destroy(None) == 0
     assert lib.etac_plan_destroy(None) == 0
     assert lib.etac_plan_info(None, None, None, None) == -1
     assert lib.etac_plan_set_occupancy(None, 1) == -1
@@ -108,3 +110,30 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(_native, "LIB_PATH", str(tmp_path / "libetac.so"))
     with pytest.raises(ImportError):
         _native.lib()
+
+
+def test_meshset_validation_without_gpu():
+    """Mesh-set arguments are checked on the host before any device call."""
+    from scenes import trimeshes as tm
+    lib = _native.lib()
+    ms = tm.merge([tm.cube_mesh(half=4.0, n=1)], ("cube",))
+    v, t, off = ms.verts.copy(), ms.tris.copy(), ms.tri_offset.copy()
+
+    def create(v, t, off, M=None):
+        h = C.c_void_p()
+        M = off.size - 1 if M is None else M
+        return lib.etac_meshset_create(M, off.ctypes.data, v.shape[0], v.ctypes.data, t.ctypes.data, C.byref(h))
+
+    assert lib.etac_meshset_create(1, None, 3, None, None, None) == -1
+    assert create(v, t, off, M=0) == -2
+    assert create(v, t, np.array([1, 12], np.int32)) == -2                    # offsets must start at 0
+    assert create(v, t[:3], np.array([0, 3], np.int32)) == -2                 # fewer than 4 triangles
+    bad = t.copy(); bad[0, 0] = v.shape[0]
+    assert create(v, bad, off) == -3                                          # vertex index out of range
+    vn = v.copy(); vn[0, 0] = np.nan
+    assert create(vn, t, off) == -3                                           # non-finite vertex
+    assert create(v, np.ascontiguousarray(t[1:]), np.array([0, 11], np.int32)) == -3   # open mesh
+    flip = t.copy(); flip[0] = flip[0, [0, 2, 1]]
+    assert create(v, flip, off) == -3                                         # inconsistent orientation
+    deg = t.copy(); deg[0, 2] = deg[0, 1]
+    assert create(v, deg, off) == -3                                          # repeated vertex
