@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--rollout-steps", type=int, default=200)
     ap.add_argument("--calib-steps", type=int, default=30,
                     help="Adam iterations of the calibration loop (Eq. 3) timed on the same scenes (0: skip)")
+    ap.add_argument("--no-mesh", action="store_true",
+                    help="skip the triangle-mesh object contact measurement (etac_contact_mesh)")
     return ap.parse_args()
 
 
@@ -176,6 +178,56 @@ def calibration(args, plan, mesh, scene, model, mode):
             "ms_per_iteration": dt * 1e3 / args.calib_steps,
             "node_updates_per_s": float(scene.n_envs) * mesh.n_nodes * args.calib_steps / dt,
             "loss_first": losses[0], "loss_last": losses[-1]}
+
+
+def mesh_contact(args, plan, mesh, model, mode, reps=20):
+    """Contact with triangle-mesh objects on the same hand: every env holds
+    1-3 of four stand-in object meshes (egg, can, rock, cube; 768-1280
+    triangles), posed like the primitives.  Times etac_contact_mesh alone and
+    followed by etac_propagate (the forward with mesh objects)."""
+    import torch
+    from scenes import trimeshes as tm
+    from paper_2604_20295_amd import _native
+    dev = torch.device("cuda", 0)
+    E, N, K = plan.n_envs, plan.N, plan.K
+    ms = tm.object_set()
+    sc = tm.hand_mesh_scene(mesh, ms, E, seed=2, p_mesh=1.0)
+
+    def t(a, dtype):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).to(dev)
+
+    st = plan.scene_struct(t(sc.n_obj, torch.int32), t(sc.type, torch.int32), t(sc.shape, torch.float32),
+                           t(sc.rot, torch.float32), t(sc.trans, torch.float32))
+    md = plan.model_struct(mode, t(model.alpha, torch.float32), t(model.phi, torch.float32))
+    dms = _native.MeshSet.from_set(ms)
+    cobj = torch.empty((E, N), dtype=torch.int8, device=dev)
+    uhat = torch.empty((3, E, N), device=dev)
+    na = torch.empty((E, K), dtype=torch.int32, device=dev)
+    u = torch.empty((3, E, N), device=dev)
+
+    def timed(fn):
+        for _ in range(2):
+            fn()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(reps):
+            fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps
+
+    c_ms = timed(lambda: _native.etac_contact_mesh(plan, dms, st, cobj, uhat, na))
+    f_ms = timed(lambda: (_native.etac_contact_mesh(plan, dms, st, cobj, uhat, na),
+                          _native.etac_propagate(plan, md, E, cobj, uhat, u)))
+    active = float((cobj >= 0).float().mean())
+    dms.close()
+    return {"workload": f"{E} envs x 16-patch hand, 1-3 triangle-mesh objects per env "
+                        f"({ms.n_tris} triangles in {ms.n_meshes} meshes)",
+            "contact_ms": c_ms, "contact_value": E * N / (c_ms * 1e-3),
+            "forward_ms": f_ms, "forward_value": E * N / (f_ms * 1e-3), "unit": "node-updates/s",
+            "active_fraction": active,
+            "what": "etac_contact_mesh (exact triangle SDF, FP64); forward = etac_contact_mesh + etac_propagate"}
 
 
 def work_counts(mesh, n_active):
@@ -468,6 +520,8 @@ def main():
 
     if args.calib_steps > 0:
         line["calibration"] = calibration(args, plan, mesh, scene, model, mode)
+    if not args.no_mesh and args.workload == "hand":
+        line["mesh_contact"] = mesh_contact(args, plan, mesh, model, mode)
 
     if not args.no_cpu_baseline:
         # the FP64 oracle (forward + adjoint) on blocks of the same envs until

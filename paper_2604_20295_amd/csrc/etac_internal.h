@@ -145,6 +145,11 @@ struct MeshSetDev {
     const double *pn;        // [T][7][3] pseudo-normals: face, edges ab bc ca, vertices a b c
     const double4 *ball;     // [C] cluster bounding ball: centre, radius (with margin)
     const int2 *range;       // [C] cluster triangle range [first, end)
+    // occupancy grid per mesh over its bounding box: bit (i, j, k) is clear
+    // when every point of that cell is certainly outside the mesh
+    const float4 *grid_lo;   // [M] box corner (object frame), 1 / cell size
+    const int4 *grid_dim;    // [M] cells along x, y, z; first bit in grid_bits
+    const unsigned *grid_bits;
     int M, T, C;
 };
 
@@ -156,6 +161,6 @@ hipError_t launch_contact_mesh(const Plan &p, const MeshSetDev &ms, const SceneD
 struct etac_meshset {
     int device;
     etac::MeshSetDev d;
-    void *allocs[8];
+    void *allocs[16];
     int n_allocs;
 };

@@ -4,15 +4,18 @@
 //   host : etac_meshset_create validates the meshes, computes the FP64
 //          angle-weighted pseudo-normals (Baerentzen and Aanaes, IEEE TVCG
 //          2005) of every face, edge and vertex, splits each mesh into
-//          clusters of at most 64 triangles by recursive median splits of
-//          the triangle centroids, and uploads it all.
+//          clusters of 32 triangles by recursive splits of the triangle
+//          centroids, builds a conservative occupancy grid per mesh, and
+//          uploads it all.
 //   k_contact_mesh : one workgroup per env, as the primitive contact pass.
 //          Primitives are tested one node per lane.  For a mesh object the
-//          nodes inside its bounding ball are queried one at a time by the
-//          whole wave: lanes take the clusters' lower bounds, then the
-//          triangles of the nearest unvisited cluster (one per lane), with
-//          wave reductions for the minimum; clusters whose lower bound
-//          exceeds the best distance so far are never opened.
+//          nodes inside its bounding ball and not in a cell of the grid that
+//          is certainly outside are queried one at a time by the whole wave:
+//          lanes take the clusters' lower bounds, then the triangles of the
+//          two nearest unvisited clusters (one cluster per half-wave, one
+//          triangle per lane), with DPP wave reductions for the minimum;
+//          clusters whose lower bound exceeds the best distance so far are
+//          never opened.
 //
 // The closest point of a triangle follows the Voronoi-region classification
 // of Ericson ("Real-Time Collision Detection", 2005, Sec. 5.1.5).  All of it
@@ -26,6 +29,7 @@
 #include <cmath>
 #include <map>
 #include <numeric>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -52,8 +56,8 @@ __device__ __forceinline__ TriCorners load_tri(const MeshSetDev &ms, int t) {
 
 // Closest point (x0, x1, x2) of the triangle to q, its feature, and the
 // squared distance.  Dot products are (x0 y0 + x1 y1) + x2 y2.
-__device__ __forceinline__ double closest_tri(double q0, double q1, double q2, const TriCorners &t, double &x0,
-                                              double &x1, double &x2, int &feat) {
+__host__ __device__ __forceinline__ double closest_tri(double q0, double q1, double q2, const TriCorners &t,
+                                                       double &x0, double &x1, double &x2, int &feat) {
 #pragma clang fp contract(off)
     const double ab0 = t.b0 - t.a0, ab1 = t.b1 - t.a1, ab2 = t.b2 - t.a2;
     const double ac0 = t.c0 - t.a0, ac1 = t.c1 - t.a1, ac2 = t.c2 - t.a2;
@@ -103,16 +107,41 @@ __device__ __forceinline__ double closest_tri(double q0, double q1, double q2, c
     return (w0 * w0 + w1 * w1) + w2 * w2;
 }
 
+// Wave-wide minima through DPP row permutes (xor 1, xor 2, half-row and
+// row mirrors: every lane ends with its row's minimum), then the four row
+// minima read lane by lane.  Every lane of the wave must be active; every
+// lane gets the result.
+template <int CTRL>
+__device__ __forceinline__ int dpp(int v) {
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+    const int lo = dpp<CTRL>(__double2loint(v)), hi = dpp<CTRL>(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
 __device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off));
-    return v;
+    v = fmin(v, dpp<0xb1>(v));    // quad_perm [1, 0, 3, 2]
+    v = fmin(v, dpp<0x4e>(v));    // quad_perm [2, 3, 0, 1]
+    v = fmin(v, dpp<0x141>(v));   // row_half_mirror
+    v = fmin(v, dpp<0x140>(v));   // row_mirror
+    return fmin(fmin(read_lane(v, 0), read_lane(v, 16)), fmin(read_lane(v, 32), read_lane(v, 48)));
 }
 
 __device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off));
-    return v;
+    v = min(v, dpp<0xb1>(v));
+    v = min(v, dpp<0x4e>(v));
+    v = min(v, dpp<0x141>(v));
+    v = min(v, dpp<0x140>(v));
+    return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+               min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
 // Signed-distance query of one point q (object frame, the same value in
@@ -125,6 +154,7 @@ __device__ Pen mesh_query(const MeshSetDev &ms, int mesh, double q0, double q1, 
     const double kInf = __builtin_inf();
     double best_s = kInf;
     int best_o = 0x7fffffff, best_t = -1;
+    const int half = lane >> 5;
     for (int cb = mr.z; cb < mr.w; cb += 64) {
         const int c = cb + lane;
         double lb = kInf;   // squared lower bound of the distance to cluster c
@@ -134,30 +164,51 @@ __device__ Pen mesh_query(const MeshSetDev &ms, int mesh, double q0, double q1, 
             const double l = sqrt((dx * dx + dy * dy) + dz * dz) - b.w;
             lb = l > 0.0 ? l * l : 0.0;
         }
-        for (;;) {
-            const double m = wave_min(lb);
-            // every cluster left is strictly farther (or all visited); a NaN
-            // bound (non-finite pose) also ends the search, with no result
-            if (!(m < kInf) || !(m <= best_s)) break;
-            const int src = __ffsll((unsigned long long)__ballot(lb == m)) - 1;
-            if (lane == src) lb = kInf;
-            const int2 r = ms.range[cb + src];
-            const int t = r.x + lane;
+        // first the two clusters of least bound, then, two at a time, every
+        // cluster whose bound does not exceed the best distance so far
+        // (re-checked after each pass); each half-wave takes one cluster
+        const double m1 = wave_min(lb);
+        // every cluster of this pass strictly farther; a non-finite bound
+        // (non-finite pose) gives no result
+        if (!(m1 < kInf) || !(m1 <= best_s)) continue;
+        const int a0 = __ffsll((unsigned long long)__ballot(lb == m1)) - 1;
+        const double m2 = wave_min(lane == a0 ? kInf : lb);
+        int ca = a0, cbb = -1;
+        if (m2 < kInf && m2 <= best_s) cbb = __ffsll((unsigned long long)__ballot(lane != a0 && lb == m2)) - 1;
+        while (ca >= 0) {
+            if (lane == ca || lane == cbb) lb = kInf;
+            const int mine = half ? cbb : ca;
+            int t = -1;
             double s = kInf;
             int o = 0x7fffffff;
-            if (t < r.y) {
+            if (mine >= 0) {
+                const int2 r = ms.range[cb + mine];
+                if (r.x + (lane & 31) < r.y) t = r.x + (lane & 31);
+            }
+            if (t >= 0) {
                 double x0, x1, x2;
                 int f;
                 s = closest_tri(q0, q1, q2, load_tri(ms, t), x0, x1, x2, f);
                 o = ms.orig[t];
             }
             const double sm = wave_min(s);
-            const int om = wave_min(s == sm ? o : 0x7fffffff);
+            unsigned long long at = __ballot(s == sm);
+            int om;
+            if (__popcll(at) == 1) {
+                om = __builtin_amdgcn_readlane(o, __ffsll(at) - 1);
+            } else {   // equal distances: the lowest triangle index
+                om = wave_min(s == sm ? o : 0x7fffffff);
+                at = __ballot(s == sm && o == om);
+            }
             if (sm < best_s || (sm == best_s && om < best_o)) {
                 best_s = sm;
                 best_o = om;
-                best_t = r.x + __ffsll((unsigned long long)__ballot(s == sm && o == om)) - 1;
+                best_t = __builtin_amdgcn_readlane(t, __ffsll(at) - 1);
             }
+            unsigned long long todo = __ballot(lb <= best_s && lb < kInf);
+            ca = __ffsll(todo) - 1;
+            todo &= todo - 1;
+            cbb = __ffsll(todo) - 1;
         }
     }
     Pen h;
@@ -272,7 +323,24 @@ __global__ __launch_bounds__(kWG) void k_contact_mesh(MeshContactParams p) {
                     const int m = mesh_of(sh, p.ms.M);
                     if (m < 0) continue;
                     const float rb = p.ms.radius[m] * 1.001f + 1e-3f;
-                    unsigned long long todo = __ballot(take && d2 <= rb * rb);
+                    bool near = take && d2 <= rb * rb;
+                    if (near) {   // the occupancy grid rules out nodes certainly outside
+                        const float4 g = p.ms.grid_lo[m];
+                        const int4 gd = p.ms.grid_dim[m];
+                        const float qx = (R[0] * dx + R[3] * dy) + R[6] * dz;
+                        const float qy = (R[1] * dx + R[4] * dy) + R[7] * dz;
+                        const float qz = (R[2] * dx + R[5] * dy) + R[8] * dz;
+                        const float gx = (qx - g.x) * g.w, gy = (qy - g.y) * g.w, gz = (qz - g.z) * g.w;
+                        near = gx >= 0.0f && gy >= 0.0f && gz >= 0.0f && gx < (float)gd.x && gy < (float)gd.y &&
+                               gz < (float)gd.z;
+                        if (near) {
+                            const int ix = min((int)gx, gd.x - 1), iy = min((int)gy, gd.y - 1);
+                            const int iz = min((int)gz, gd.z - 1);
+                            const unsigned bit = (unsigned)gd.w + (unsigned)((iz * gd.y + iy) * gd.x + ix);
+                            near = (p.ms.grid_bits[bit >> 5] >> (bit & 31u)) & 1u;
+                        }
+                    }
+                    unsigned long long todo = __ballot(near);
                     const double t0 = t[0], t1 = t[1], t2 = t[2];
                     const double r00 = R[0], r01 = R[1], r02 = R[2];
                     const double r10 = R[3], r11 = R[4], r12 = R[5];
@@ -359,10 +427,15 @@ struct BuiltMesh {
     std::vector<std::pair<int, int>> clusters;   // ranges into `order`
 };
 
-// Recursive median split of the triangle centroids along the longest axis
-// of their bounding box, down to clusters of at most 64 triangles.
+// Triangles per cluster: one half-wave each.
+constexpr int kCluster = 32;
+
+// Recursive split of the triangle centroids along the longest axis of their
+// bounding box, down to clusters of kCluster triangles (the last one of a
+// mesh may hold fewer): the lower side takes kCluster times half the number
+// of clusters needed, rounded up.
 void split(std::vector<int> &ids, int lo, int hi, const std::vector<V3> &cen, BuiltMesh &out) {
-    if (hi - lo <= 64) {
+    if (hi - lo <= kCluster) {
         out.clusters.push_back({lo, hi});
         return;
     }
@@ -375,13 +448,93 @@ void split(std::vector<int> &ids, int lo, int hi, const std::vector<V3> &cen, Bu
     const double ex = mx.x - mn.x, ey = mx.y - mn.y, ez = mx.z - mn.z;
     const int axis = (ex >= ey && ex >= ez) ? 0 : (ey >= ez ? 1 : 2);
     auto coord = [&](int t) { return axis == 0 ? cen[t].x : (axis == 1 ? cen[t].y : cen[t].z); };
-    const int mid = lo + (hi - lo) / 2;
+    const int mid = lo + kCluster * (((hi - lo + kCluster - 1) / kCluster + 1) / 2);
     std::nth_element(ids.begin() + lo, ids.begin() + mid, ids.begin() + hi, [&](int a, int b) {
         const double ca = coord(a), cb = coord(b);
         return ca < cb || (ca == cb && a < b);
     });
     split(ids, lo, mid, cen, out);
     split(ids, mid, hi, cen, out);
+}
+
+// Signed distance of x to one mesh (negative inside), for the occupancy
+// grid only: the same closest-point rule, clusters visited by ascending
+// lower bound.
+struct HostMesh {
+    const int32_t *tv;                   // vertex indices of the mesh's triangles, as given
+    const float *verts;
+    const std::vector<int> *order;       // cluster order -> triangle
+    const std::vector<std::pair<int, int>> *clusters;
+    const double4 *ball;                 // this mesh's cluster balls
+    const double *pn;                    // [nt][21] pseudo-normals, as given
+};
+
+double host_sdf(const HostMesh &hm, double x0, double x1, double x2) {
+    const int nc = (int)hm.clusters->size();
+    std::vector<std::pair<double, int>> lb(nc);
+    for (int c = 0; c < nc; ++c) {
+        const double4 b = hm.ball[c];
+        const double dx = x0 - b.x, dy = x1 - b.y, dz = x2 - b.z;
+        const double l = std::sqrt((dx * dx + dy * dy) + dz * dz) - b.w;
+        lb[c] = {l > 0.0 ? l * l : 0.0, c};
+    }
+    std::sort(lb.begin(), lb.end());
+    double best = INFINITY, c0 = 0.0, c1 = 0.0, c2 = 0.0;
+    int bf = -1, bfeat = 0;
+    for (auto [l, c] : lb) {
+        if (l > best) break;
+        for (int i = (*hm.clusters)[c].first; i < (*hm.clusters)[c].second; ++i) {
+            const int f = (*hm.order)[i];
+            const float *a = hm.verts + 3 * (size_t)hm.tv[3 * f], *b = hm.verts + 3 * (size_t)hm.tv[3 * f + 1];
+            const float *cc = hm.verts + 3 * (size_t)hm.tv[3 * f + 2];
+            const TriCorners t{a[0], a[1], a[2], b[0], b[1], b[2], cc[0], cc[1], cc[2]};
+            double y0, y1, y2;
+            int ft;
+            const double sq = closest_tri(x0, x1, x2, t, y0, y1, y2, ft);
+            if (sq < best || (sq == best && f < bf)) {
+                best = sq; bf = f; bfeat = ft;
+                c0 = y0; c1 = y1; c2 = y2;
+            }
+        }
+    }
+    const double *n = hm.pn + (size_t)21 * bf + 3 * bfeat;
+    const double d = std::sqrt(best);
+    return ((x0 - c0) * n[0] + (x1 - c1) * n[1]) + (x2 - c2) * n[2] < 0.0 ? -d : d;
+}
+
+// Occupancy grid of one mesh: cubic cells, about kGridCells along the longest
+// side of the bounding box (padded by 0.01 mm).  A cell's bit is cleared when
+// its centre is outside by more than the half diagonal plus 0.01 mm: the
+// signed distance changes no faster than the distance moved, so every point
+// of the cell (and up to 0.01 mm beyond it) is outside.
+constexpr int kGridCells = 40;
+
+void build_grid(const HostMesh &hm, V3 lo, V3 hi, float4 &glo, int4 &gdim, std::vector<unsigned> &bits) {
+    const double pad = 0.01;
+    lo = V3{lo.x - pad, lo.y - pad, lo.z - pad};
+    hi = V3{hi.x + pad, hi.y + pad, hi.z + pad};
+    const double h = std::max({hi.x - lo.x, hi.y - lo.y, hi.z - lo.z}) / kGridCells;
+    const int nx = std::max(1, (int)std::ceil((hi.x - lo.x) / h)), ny = std::max(1, (int)std::ceil((hi.y - lo.y) / h));
+    const int nz = std::max(1, (int)std::ceil((hi.z - lo.z) / h));
+    const size_t ncell = (size_t)nx * ny * nz, base = bits.size() * 32;
+    bits.resize((base + ncell + 31) / 32, 0u);
+    std::vector<uint8_t> maybe(ncell, 1);
+    const double reach = h * std::sqrt(3.0) / 2.0 + 0.01;
+    const int nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (int w = 0; w < nth; ++w)
+        pool.emplace_back([&, w]() {
+            for (size_t c = w; c < ncell; c += nth) {
+                const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
+                const double sd = host_sdf(hm, lo.x + (i + 0.5) * h, lo.y + (j + 0.5) * h, lo.z + (k + 0.5) * h);
+                maybe[c] = !(sd > reach);
+            }
+        });
+    for (auto &t : pool) t.join();
+    for (size_t c = 0; c < ncell; ++c)
+        if (maybe[c]) bits[(base + c) / 32] |= 1u << ((base + c) % 32);
+    glo = make_float4((float)lo.x, (float)lo.y, (float)lo.z, (float)(1.0 / h));
+    gdim = make_int4(nx, ny, nz, (int)base);
 }
 
 }  // namespace
@@ -412,6 +565,9 @@ etac_status etac_meshset_create(int32_t n_meshes, const int32_t *tri_offset, int
     std::vector<int2> range;
     std::vector<int4> mesh(n_meshes);
     std::vector<float> radius(n_meshes);
+    std::vector<float4> grid_lo(n_meshes);
+    std::vector<int4> grid_dim(n_meshes);
+    std::vector<unsigned> grid_bits;
     for (int m = 0; m < n_meshes; ++m) {
         const int t0 = tri_offset[m], nt = tri_offset[m + 1] - t0;
         const int32_t *tv = tris + 3 * (size_t)t0;
@@ -494,6 +650,17 @@ etac_status etac_meshset_create(int32_t n_meshes, const int32_t *tri_offset, int
             std::copy(mpn.begin() + (size_t)21 * f, mpn.begin() + (size_t)21 * (f + 1), pn.begin() + (size_t)21 * slot);
         }
         mesh[m] = make_int4(t0, t0 + nt, c_first, (int)ball.size());
+        {
+            V3 lo{INFINITY, INFINITY, INFINITY}, hi{-INFINITY, -INFINITY, -INFINITY};
+            for (int f = 0; f < nt; ++f)
+                for (int k = 0; k < 3; ++k) {
+                    const V3 p = vtx(tv[3 * f + k]);
+                    lo = V3{std::min(lo.x, p.x), std::min(lo.y, p.y), std::min(lo.z, p.z)};
+                    hi = V3{std::max(hi.x, p.x), std::max(hi.y, p.y), std::max(hi.z, p.z)};
+                }
+            const HostMesh hm{tv, verts, &bm.order, &bm.clusters, ball.data() + c_first, mpn.data()};
+            build_grid(hm, lo, hi, grid_lo[m], grid_dim[m], grid_bits);
+        }
         float rf = (float)rmax;
         if ((double)rf < rmax) rf = std::nextafter(rf, INFINITY);
         radius[m] = rf;
@@ -510,27 +677,30 @@ etac_status etac_meshset_create(int32_t n_meshes, const int32_t *tri_offset, int
     }
     auto upload = [&](const void *src, size_t bytes, void **dst) -> hipError_t {
         void *d = nullptr;
+        if (ms->n_allocs >= (int)(sizeof(ms->allocs) / sizeof(ms->allocs[0]))) return hipErrorOutOfMemory;
         hipError_t e = hipMalloc(&d, bytes ? bytes : 1);
         if (e != hipSuccess) return e;
         ms->allocs[ms->n_allocs++] = d;
         *dst = d;
         return bytes ? hipMemcpy(d, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
     };
-    void *p[7];
+    void *p[10];
     hipError_t e = hipSuccess;
-    const void *src[7] = {mesh.data(), radius.data(), corner.data(), orig.data(), pn.data(), ball.data(),
-                          range.data()};
-    const size_t bytes[7] = {mesh.size() * sizeof(int4), radius.size() * sizeof(float), corner.size() * sizeof(float),
-                             orig.size() * sizeof(int), pn.size() * sizeof(double), ball.size() * sizeof(double4),
-                             range.size() * sizeof(int2)};
-    for (int i = 0; i < 7 && e == hipSuccess; ++i) e = upload(src[i], bytes[i], &p[i]);
+    const void *src[10] = {mesh.data(), radius.data(), corner.data(), orig.data(), pn.data(), ball.data(),
+                           range.data(), grid_lo.data(), grid_dim.data(), grid_bits.data()};
+    const size_t bytes[10] = {mesh.size() * sizeof(int4), radius.size() * sizeof(float),
+                              corner.size() * sizeof(float), orig.size() * sizeof(int), pn.size() * sizeof(double),
+                              ball.size() * sizeof(double4), range.size() * sizeof(int2),
+                              grid_lo.size() * sizeof(float4), grid_dim.size() * sizeof(int4),
+                              grid_bits.size() * sizeof(unsigned)};
+    for (int i = 0; i < 10 && e == hipSuccess; ++i) e = upload(src[i], bytes[i], &p[i]);
     if (e != hipSuccess) {
         etac_meshset_destroy(ms);
         return ETAC_ERR_HIP;
     }
     ms->d = MeshSetDev{(const int4 *)p[0], (const float *)p[1], (const float *)p[2], (const int *)p[3],
-                       (const double *)p[4], (const double4 *)p[5], (const int2 *)p[6], n_meshes, T,
-                       (int)ball.size()};
+                       (const double *)p[4], (const double4 *)p[5], (const int2 *)p[6], (const float4 *)p[7],
+                       (const int4 *)p[8], (const unsigned *)p[9], n_meshes, T, (int)ball.size()};
     *out = ms;
     return ETAC_OK;
 }
