@@ -144,7 +144,6 @@ struct MeshSetDev {
     const int *orig;         // [T] index of the triangle within its mesh, as given
     const double *pn;        // [T][7][3] pseudo-normals: face, edges ab bc ca, vertices a b c
     const double4 *ball;     // [C] cluster bounding ball: centre, radius (with margin)
-    const int2 *range;       // [C] cluster triangle range [first, end)
     // occupancy grid per mesh over its bounding box: bit (i, j, k) is clear
     // when every point of that cell is certainly outside the mesh
     const float4 *grid_lo;   // [M] box corner (object frame), 1 / cell size

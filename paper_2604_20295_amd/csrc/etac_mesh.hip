@@ -41,6 +41,10 @@ namespace etac {
 // device
 // ---------------------------------------------------------------------------
 
+// Triangles per cluster: one half-wave each.  Cluster c of a mesh holds
+// its triangles kCluster (c - first cluster) onwards, in cluster order.
+constexpr int kCluster = 32;
+
 // Features of a triangle holding its closest point.
 enum { FEAT_FACE = 0, FEAT_AB = 1, FEAT_BC = 2, FEAT_CA = 3, FEAT_A = 4, FEAT_B = 5, FEAT_C = 6 };
 
@@ -181,9 +185,9 @@ __device__ Pen mesh_query(const MeshSetDev &ms, int mesh, double q0, double q1, 
             int t = -1;
             double s = kInf;
             int o = 0x7fffffff;
-            if (mine >= 0) {
-                const int2 r = ms.range[cb + mine];
-                if (r.x + (lane & 31) < r.y) t = r.x + (lane & 31);
+            if (mine >= 0) {   // clusters hold kCluster triangles, the mesh's last one possibly fewer
+                const int tt = mr.x + kCluster * (cb + mine - mr.z) + (lane & 31);
+                if (tt < mr.y) t = tt;
             }
             if (t >= 0) {
                 double x0, x1, x2;
@@ -274,7 +278,8 @@ __device__ __forceinline__ unsigned cull_mesh_objects(const MeshContactParams &p
     return cand;
 }
 
-__global__ __launch_bounds__(kWG) void k_contact_mesh(MeshContactParams p) {
+// Four waves per SIMD (at most 128 registers): the queries are latency-bound.
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_contact_mesh(MeshContactParams p) {
     __shared__ int cnt[kMaxPatches];
     __shared__ uint8_t cand[kMaxPatches];
     const int e = blockIdx.x;
@@ -427,9 +432,6 @@ struct BuiltMesh {
     std::vector<std::pair<int, int>> clusters;   // ranges into `order`
 };
 
-// Triangles per cluster: one half-wave each.
-constexpr int kCluster = 32;
-
 // Recursive split of the triangle centroids along the longest axis of their
 // bounding box, down to clusters of kCluster triangles (the last one of a
 // mesh may hold fewer): the lower side takes kCluster times half the number
@@ -562,7 +564,6 @@ etac_status etac_meshset_create(int32_t n_meshes, const int32_t *tri_offset, int
     std::vector<int> orig(T);
     std::vector<double> pn((size_t)21 * T);
     std::vector<double4> ball;
-    std::vector<int2> range;
     std::vector<int4> mesh(n_meshes);
     std::vector<float> radius(n_meshes);
     std::vector<float4> grid_lo(n_meshes);
@@ -617,6 +618,10 @@ etac_status etac_meshset_create(int32_t n_meshes, const int32_t *tri_offset, int
         split(bm.order, 0, nt, cen, bm);
         const int c_first = (int)ball.size();
         double rmax = 0.0;
+        for (size_t ci = 0; ci < bm.clusters.size(); ++ci)   // the kernel derives the ranges
+            if (bm.clusters[ci].first != kCluster * (int)ci ||
+                bm.clusters[ci].second != std::min(nt, kCluster * (int)ci + kCluster))
+                return ETAC_ERR_VALUE;
         for (auto [lo, hi] : bm.clusters) {
             V3 mn{INFINITY, INFINITY, INFINITY}, mx{-INFINITY, -INFINITY, -INFINITY};
             for (int i = lo; i < hi; ++i)
@@ -636,7 +641,6 @@ etac_status etac_meshset_create(int32_t n_meshes, const int32_t *tri_offset, int
                 }
             const double scale = std::sqrt(dot(cc, cc)) + r;
             ball.push_back(make_double4(cc.x, cc.y, cc.z, r + 1e-6 + 1e-12 * scale));
-            range.push_back(make_int2(t0 + lo, t0 + hi));
         }
         for (int i = 0; i < nt; ++i) {
             const int f = bm.order[i], slot = t0 + i;
@@ -684,23 +688,22 @@ etac_status etac_meshset_create(int32_t n_meshes, const int32_t *tri_offset, int
         *dst = d;
         return bytes ? hipMemcpy(d, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
     };
-    void *p[10];
+    void *p[9];
     hipError_t e = hipSuccess;
-    const void *src[10] = {mesh.data(), radius.data(), corner.data(), orig.data(), pn.data(), ball.data(),
-                           range.data(), grid_lo.data(), grid_dim.data(), grid_bits.data()};
-    const size_t bytes[10] = {mesh.size() * sizeof(int4), radius.size() * sizeof(float),
-                              corner.size() * sizeof(float), orig.size() * sizeof(int), pn.size() * sizeof(double),
-                              ball.size() * sizeof(double4), range.size() * sizeof(int2),
-                              grid_lo.size() * sizeof(float4), grid_dim.size() * sizeof(int4),
-                              grid_bits.size() * sizeof(unsigned)};
-    for (int i = 0; i < 10 && e == hipSuccess; ++i) e = upload(src[i], bytes[i], &p[i]);
+    const void *src[9] = {mesh.data(), radius.data(), corner.data(), orig.data(), pn.data(), ball.data(),
+                          grid_lo.data(), grid_dim.data(), grid_bits.data()};
+    const size_t bytes[9] = {mesh.size() * sizeof(int4), radius.size() * sizeof(float),
+                             corner.size() * sizeof(float), orig.size() * sizeof(int), pn.size() * sizeof(double),
+                             ball.size() * sizeof(double4), grid_lo.size() * sizeof(float4),
+                             grid_dim.size() * sizeof(int4), grid_bits.size() * sizeof(unsigned)};
+    for (int i = 0; i < 9 && e == hipSuccess; ++i) e = upload(src[i], bytes[i], &p[i]);
     if (e != hipSuccess) {
         etac_meshset_destroy(ms);
         return ETAC_ERR_HIP;
     }
     ms->d = MeshSetDev{(const int4 *)p[0], (const float *)p[1], (const float *)p[2], (const int *)p[3],
-                       (const double *)p[4], (const double4 *)p[5], (const int2 *)p[6], (const float4 *)p[7],
-                       (const int4 *)p[8], (const unsigned *)p[9], n_meshes, T, (int)ball.size()};
+                       (const double *)p[4], (const double4 *)p[5], (const float4 *)p[6], (const int4 *)p[7],
+                       (const unsigned *)p[8], n_meshes, T, (int)ball.size()};
     *out = ms;
     return ETAC_OK;
 }
