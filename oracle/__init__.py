@@ -326,3 +326,31 @@ def contact_mesh(mesh, scene, meshset):
           C.c_int(meshset.n_meshes), _i32(meshset.tri_offset), C.c_int(meshset.n_verts), _f64(meshset.verts),
           _i32(meshset.tris), cobj, uhat, na)
     return cobj, uhat, na
+
+
+def contact_mesh_backward(mesh, scene, meshset, grad_uhat):
+    """Pose gradients of L = sum(grad_uhat * u_hat) with primitives and mesh
+    objects (contact recomputed; winner, triangle and feature held fixed).
+    Returns dict(grad_rot [E][O][9], grad_trans [E][O][3])."""
+    lib = _load()
+    K, N, off, pos, nrm, _ = _mesh_args(mesh)
+    E, O, n_obj, typ, shape, rot, trans = _scene_args(scene)
+    grot = np.empty((E.value, O.value, 9), np.float64)
+    gt = np.empty((E.value, O.value, 3), np.float64)
+    _call(lib.oracle_contact_mesh_backward, K, N, off, pos, nrm, E, O, n_obj, typ, shape, rot, trans,
+          C.c_int(meshset.n_meshes), _i32(meshset.tri_offset), C.c_int(meshset.n_verts), _f64(meshset.verts),
+          _i32(meshset.tris), _f64(grad_uhat), grot, gt)
+    return dict(grad_rot=grot, grad_trans=gt)
+
+
+def contact_mesh_features(mesh, scene, meshset):
+    """Test hook: the closest-point feature (0 face, 1-3 edges ab bc ca, 4-6
+    vertices a b c) of each node won by a mesh object, else -1.  int32 [E][N]."""
+    lib = _load()
+    K, N, off, pos, nrm, _ = _mesh_args(mesh)
+    E, O, n_obj, typ, shape, rot, trans = _scene_args(scene)
+    feat = np.empty((E.value, N.value), np.int32)
+    _call(lib.oracle_contact_mesh_features, K, N, off, pos, nrm, E, O, n_obj, typ, shape, rot, trans,
+          C.c_int(meshset.n_meshes), _i32(meshset.tri_offset), C.c_int(meshset.n_verts), _f64(meshset.verts),
+          _i32(meshset.tris), feat)
+    return feat

@@ -469,6 +469,61 @@ static hit_t mesh_penetrate(const trimesh_t *m, const double *R, const double *t
     return h;
 }
 
+/*
+ * Adjoint of one mesh node with respect to the pose (R, t), the winning
+ * triangle f and feature held fixed.  With d = p - t, q = R^T d, c(q) the
+ * closest point and w = c - q, u_hat = R w, and dw/dq = J:
+ *   vertex : J = -I
+ *   edge   : J = e e^T / |e|^2 - I   (e the edge direction)
+ *   face   : J = -n n^T              (n the unit face normal)
+ * J is symmetric.  For L = g . u_hat, with h = J R^T g:
+ *   dL/dR = g w^T + d h^T  (R's nine entries taken as free inputs)
+ *   dL/dt = -R h
+ */
+static void mesh_node_backward(const trimesh_t *m, const double *R, const double *t, const double p[3],
+                               const double g[3], double *gR, double *gt) {
+    double d[3] = {p[0] - t[0], p[1] - t[1], p[2] - t[2]};
+    double q[3];
+    for (int c = 0; c < 3; ++c) q[c] = (R[0 * 3 + c] * d[0] + R[1 * 3 + c] * d[1]) + R[2 * 3 + c] * d[2];
+    int bf = -1, bfeat = 0;
+    double bs = 0.0, bcp[3] = {0.0, 0.0, 0.0};
+    for (int f = 0; f < m->T; ++f) {
+        double cp[3];
+        int feat;
+        const double *a = m->corner + f * 9;
+        double sq = closest_on_triangle(q, a, a + 3, a + 6, cp, &feat);
+        if (bf < 0 || sq < bs) {
+            bf = f; bs = sq; bfeat = feat;
+            for (int i = 0; i < 3; ++i) bcp[i] = cp[i];
+        }
+    }
+    const double *A = m->corner + bf * 9, *B = A + 3, *C = A + 6;
+    double J[9];
+    for (int i = 0; i < 9; ++i) J[i] = 0.0;
+    if (bfeat == F_FACE) {
+        const double *n = m->pn + bf * 21;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) J[i * 3 + j] = -n[i] * n[j];
+    } else if (bfeat >= F_EDGE_AB && bfeat <= F_EDGE_CA) {
+        const double *e0 = bfeat == F_EDGE_AB ? A : (bfeat == F_EDGE_BC ? B : C);
+        const double *e1 = bfeat == F_EDGE_AB ? B : (bfeat == F_EDGE_BC ? C : A);
+        double e[3] = {e1[0] - e0[0], e1[1] - e0[1], e1[2] - e0[2]};
+        double ee = dot3(e, e);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) J[i * 3 + j] = e[i] * e[j] / ee - (i == j ? 1.0 : 0.0);
+    } else {
+        for (int i = 0; i < 3; ++i) J[i * 4] = -1.0;
+    }
+    double RTg[3], h[3], w[3];
+    for (int c = 0; c < 3; ++c) RTg[c] = R[0 * 3 + c] * g[0] + R[1 * 3 + c] * g[1] + R[2 * 3 + c] * g[2];
+    for (int i = 0; i < 3; ++i) h[i] = J[i * 3 + 0] * RTg[0] + J[i * 3 + 1] * RTg[1] + J[i * 3 + 2] * RTg[2];
+    for (int i = 0; i < 3; ++i) w[i] = bcp[i] - q[i];
+    for (int a = 0; a < 3; ++a) {
+        for (int b = 0; b < 3; ++b) gR[a * 3 + b] += g[a] * w[b] + d[a] * h[b];
+        gt[a] += -(R[a * 3 + 0] * h[0] + R[a * 3 + 1] * h[1] + R[a * 3 + 2] * h[2]);
+    }
+}
+
 /* Mesh index of an ETAC-mesh object, or -1 when shape[0] is not an integer
  * in [0, n_meshes). */
 static int mesh_index(const double *shape, int n_meshes) {
@@ -1141,6 +1196,112 @@ int oracle_contact_mesh(int K, int N, const int32_t *offset, const double *pos, 
 #pragma omp parallel for schedule(dynamic, 1)
         for (int e = 0; e < E; ++e) contact_mesh_env(&P, ms, n_meshes, e, cobj, uhat, n_active);
     }
+    for (int m = 0; m < n_meshes; ++m) trimesh_free(ms + m);
+    free(ms);
+    return rc;
+}
+
+/* Pose gradients of L = sum g . u_hat over the active nodes of every env,
+ * contact with primitives and meshes recomputed (winner, triangle, feature
+ * held fixed).  grad_uhat [3][E][N]; grad_rot [E][O][9], grad_trans
+ * [E][O][3] (zero for objects that win no node). */
+int oracle_contact_mesh_backward(int K, int N, const int32_t *offset, const double *pos, const double *nrm,
+                                 int E, int O, const int32_t *n_obj, const int32_t *type, const double *shape,
+                                 const double *rot, const double *trans, int n_meshes, const int32_t *tri_offset,
+                                 int V, const double *verts, const int32_t *tris, const double *guhat,
+                                 double *grot, double *gtrans) {
+    (void)K;
+    (void)offset;
+    trimesh_t *ms = (trimesh_t *)calloc((size_t)n_meshes + 1, sizeof(trimesh_t));
+    if (!ms) return -3;
+    int rc = 0;
+    for (int m = 0; m < n_meshes && rc == 0; ++m) rc = trimesh_build(ms + m, V, verts, tris, tri_offset[m],
+                                                                     tri_offset[m + 1]);
+    if (rc == 0) {
+        const size_t EN = (size_t)E * N;
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int e = 0; e < E; ++e) {
+            for (int o = 0; o < O; ++o) {
+                for (int c = 0; c < 9; ++c) grot[((size_t)e * O + o) * 9 + c] = 0.0;
+                for (int c = 0; c < 3; ++c) gtrans[((size_t)e * O + o) * 3 + c] = 0.0;
+            }
+            for (int i = 0; i < N; ++i) {
+                double p[3] = {pos[i], pos[N + i], pos[2 * N + i]};
+                double n[3] = {nrm[i], nrm[N + i], nrm[2 * N + i]};
+                int best = -1;
+                hit_t bh;
+                memset(&bh, 0, sizeof bh);
+                for (int o = 0; o < n_obj[e]; ++o) {
+                    size_t eo = (size_t)e * O + o;
+                    hit_t h;
+                    int ty = type[eo];
+                    if (ty >= O_SPHERE && ty <= O_CAPSULE) {
+                        h = penetrate(ty, shape + 4 * eo, rot + 9 * eo, trans + 3 * eo, p, n);
+                    } else if (ty == O_MESH) {
+                        int mi = mesh_index(shape + 4 * eo, n_meshes);
+                        if (mi < 0) continue;
+                        h = mesh_penetrate(ms + mi, rot + 9 * eo, trans + 3 * eo, p);
+                    } else {
+                        continue;
+                    }
+                    if (h.inside && (best < 0 || h.depth > bh.depth)) { best = o; bh = h; }
+                }
+                if (best < 0) continue;
+                size_t ei = (size_t)e * N + i, eo = (size_t)e * O + best;
+                double g[3] = {guhat[ei], guhat[EN + ei], guhat[2 * EN + ei]};
+                if (type[eo] == O_MESH)
+                    mesh_node_backward(ms + mesh_index(shape + 4 * eo, n_meshes), rot + 9 * eo, trans + 3 * eo, p,
+                                       g, grot + 9 * eo, gtrans + 3 * eo);
+                else if (!bh.degenerate)
+                    contact_node_backward(type[eo], shape + 4 * eo, rot + 9 * eo, trans + 3 * eo, p, g,
+                                          grot + 9 * eo, gtrans + 3 * eo);
+            }
+        }
+    }
+    for (int m = 0; m < n_meshes; ++m) trimesh_free(ms + m);
+    free(ms);
+    return rc;
+}
+
+/* Feature of the winning triangle per node (0 face, 1-3 edges, 4-6
+ * vertices) where a mesh object wins, else -1: a test hook that shows which
+ * closest-point cases an input exercises. */
+int oracle_contact_mesh_features(int K, int N, const int32_t *offset, const double *pos, const double *nrm, int E,
+                                 int O, const int32_t *n_obj, const int32_t *type, const double *shape,
+                                 const double *rot, const double *trans, int n_meshes, const int32_t *tri_offset,
+                                 int V, const double *verts, const int32_t *tris, int32_t *feature) {
+    (void)K;
+    (void)offset;
+    trimesh_t *ms = (trimesh_t *)calloc((size_t)n_meshes + 1, sizeof(trimesh_t));
+    if (!ms) return -3;
+    int rc = 0;
+    for (int m = 0; m < n_meshes && rc == 0; ++m) rc = trimesh_build(ms + m, V, verts, tris, tri_offset[m],
+                                                                     tri_offset[m + 1]);
+    for (int e = 0; e < E && rc == 0; ++e)
+        for (int i = 0; i < N; ++i) {
+            double p[3] = {pos[i], pos[N + i], pos[2 * N + i]};
+            double n[3] = {nrm[i], nrm[N + i], nrm[2 * N + i]};
+            int best = -1, bmesh = 0;
+            hit_t bh;
+            memset(&bh, 0, sizeof bh);
+            for (int o = 0; o < n_obj[e]; ++o) {
+                size_t eo = (size_t)e * O + o;
+                hit_t h;
+                int ty = type[eo], is_mesh = 0;
+                if (ty >= O_SPHERE && ty <= O_CAPSULE) {
+                    h = penetrate(ty, shape + 4 * eo, rot + 9 * eo, trans + 3 * eo, p, n);
+                } else if (ty == O_MESH) {
+                    int mi = mesh_index(shape + 4 * eo, n_meshes);
+                    if (mi < 0) continue;
+                    h = mesh_penetrate(ms + mi, rot + 9 * eo, trans + 3 * eo, p);
+                    is_mesh = 1;
+                } else {
+                    continue;
+                }
+                if (h.inside && (best < 0 || h.depth > bh.depth)) { best = o; bh = h; bmesh = is_mesh; }
+            }
+            feature[(size_t)e * N + i] = (best >= 0 && bmesh) ? bh.sign : -1;
+        }
     for (int m = 0; m < n_meshes; ++m) trimesh_free(ms + m);
     free(ms);
     return rc;

@@ -191,6 +191,25 @@ def cube_mesh(half=20.0, n=8):
     return v, _orient_outward(v, f)
 
 
+def l_prism_mesh(arm=4.0, width=2.0, half_height=3.0):
+    """An L-shaped prism along z (not convex): the L of two arms of length
+    `arm` and width `width` in the xy plane, centred on its bounding box,
+    extruded over z in [-half_height, half_height].  Its inner corner is a
+    reflex edge."""
+    L = np.array([[0, 0], [arm, 0], [arm, width], [width, width], [width, arm], [0, arm]], np.float64)
+    L -= L.max(0) / 2.0
+    n = len(L)
+    v = np.concatenate([np.c_[L, np.full(n, -half_height)], np.c_[L, np.full(n, half_height)]])
+    f = []
+    for k in range(1, n - 1):              # caps: fans from the outer corner (the L is star-shaped from it)
+        f.append([n + 0, n + k, n + k + 1])
+        f.append([0, k + 1, k])
+    for k in range(n):                     # sides, the polygon counter-clockwise seen from +z
+        k1 = (k + 1) % n
+        f += [[k, k1, n + k1], [k, n + k1, n + k]]
+    return v, np.asarray(f)
+
+
 def merge(meshes, names):
     """Concatenate (verts, tris) pairs into a TriMeshSet (vertices rounded to
     FP32 once)."""

@@ -273,3 +273,96 @@ def test_object_set_is_closed_and_oriented(oracle_lib):
         assert abs(winding_number(np.zeros(3), V) - 1.0) < 1e-9
         pn = oracle_lib.mesh_pseudonormals(ms, m)
         assert np.allclose(np.linalg.norm(pn[:, 0], axis=1), 1.0)
+
+
+# ---------------------------------------------------------------------------
+# adjoint with respect to the poses
+# ---------------------------------------------------------------------------
+
+def _fd_mesh(oracle_lib, mesh, scene, ms, g, e, o, h=1e-6):
+    """Central differences of L = sum(g * u_hat) in FP64 for the translation
+    and the twist (R' = exp([w]_x) R) of object o of env e.  Returns the six
+    values and whether the contact masks agreed on both sides of every step."""
+    S = oracle_lib._F64Scene(scene)
+    out, ok = [], True
+    for kind in ("t", "w"):
+        for c in range(3):
+            vals, masks = [], []
+            for sgn in (1, -1):
+                Sp = oracle_lib._F64Scene(S)
+                if kind == "t":
+                    Sp.trans[e, o, c] += sgn * h
+                else:
+                    w = np.zeros(3)
+                    w[c] = sgn * h
+                    Sp.rot[e, o] = (oracle_lib.expm_so3(w) @ S.rot[e, o].reshape(3, 3)).ravel()
+                cobj, uhat, _ = oracle_lib.contact_mesh(mesh, Sp, ms)
+                vals.append(float(np.sum(g * uhat)))
+                masks.append(cobj)
+            ok &= bool(np.array_equal(*masks))
+            out.append((vals[0] - vals[1]) / (2 * h))
+    return np.array(out), ok
+
+
+@pytest.mark.parametrize("mesh_idx", [0, 1, 2, 3, "L"])
+def test_mesh_pose_adjoint_vs_central_differences(oracle_lib, mesh_idx):
+    # each stand-in mesh, and an L-shaped prism whose reflex edge is the
+    # closest feature of some nodes (edge Jacobian), pressed into the pad at
+    # a random pose: the analytic translation and twist gradients against
+    # FP64 central differences
+    rng = np.random.default_rng(2 if mesh_idx == "L" else 40 + mesh_idx)
+    if mesh_idx == "L":
+        ms, mesh_idx = tm.merge([tm.l_prism_mesh()], ("L",)), 0
+        edge_case = True
+    else:
+        ms, edge_case = tm.object_set(scale=0.25), False
+    mesh = scenes.pad32_mesh()
+    R = scenes.random_rotation(rng)
+    h = ms.support_extent(mesh_idx, R, np.array([0.0, 0.0, -1.0]))
+    t = np.array([0.3, -0.2, h - 2.5]) if edge_case else np.array([rng.uniform(-2, 2), rng.uniform(-2, 2), h - 1.5])
+    scene = mesh_scene([(mesh_idx, R, t)])
+    if edge_case:
+        feat = oracle_lib.contact_mesh_features(mesh, scene, ms)
+        assert ((feat >= 1) & (feat <= 3)).sum() >= 2
+    g = rng.standard_normal((3, 1, mesh.n_nodes))
+    cobj, _, _ = oracle_lib.contact_mesh(mesh, scene, ms)
+    assert (cobj >= 0).sum() > 30
+    ref = oracle_lib.contact_mesh_backward(mesh, scene, ms, g)
+    fd, ok = _fd_mesh(oracle_lib, mesh, scene, ms, g, 0, 0)
+    assert ok
+    an = np.concatenate([ref["grad_trans"][0, 0],
+                         oracle_lib.twist_from_grad_rot(ref["grad_rot"][0, 0], scene.rot[0, 0].astype(np.float64))])
+    scale = np.max(np.abs(an))
+    assert np.allclose(an, fd, rtol=1e-5, atol=1e-6 * scale), (an, fd)
+
+
+def test_mesh_adjoint_with_a_primitive_and_raw_rotation_entries(oracle_lib):
+    # a triangulated cube at a random pose beside a sphere: the sphere's part
+    # equals the primitive adjoint, and the cube's rotation gradient matches
+    # differences along all nine entries of R taken as free inputs
+    rng = np.random.default_rng(7)
+    ms = tm.merge([tm.cube_mesh(half=3.0, n=2)], ("cube",))
+    mesh = scenes.pad32_mesh()
+    corner_down = scenes.random_rotation(rng)
+    objs = [(0, corner_down, (1.0, -1.5, ms.support_extent(0, corner_down, np.array([0, 0, -1.0])) - 1.0)),
+            ((SPHERE, (3.0, 0, 0, 0)), np.eye(3), (-4.0, 3.0, 2.2))]
+    scene = mesh_scene(objs)
+    g = rng.standard_normal((3, 1, mesh.n_nodes))
+    cobj, _, _ = oracle_lib.contact_mesh(mesh, scene, ms)
+    assert {0, 1} <= set(np.unique(cobj).tolist())
+    ref = oracle_lib.contact_mesh_backward(mesh, scene, ms, g)
+    # the sphere's part equals the primitive adjoint of a scene holding only the sphere's winners
+    only_sphere = g * (cobj == 1)[None]
+    prim = oracle_lib.contact_backward(mesh, scene, only_sphere)
+    assert np.allclose(ref["grad_trans"][0, 1], prim["grad_trans"][0, 1], rtol=1e-12, atol=1e-12)
+    # raw rotation entries of the cube by differences
+    S = oracle_lib._F64Scene(scene)
+    hstep = 1e-6
+    for k in range(9):
+        vals = []
+        for sgn in (1, -1):
+            Sp = oracle_lib._F64Scene(S)
+            Sp.rot[0, 0, k] += sgn * hstep
+            vals.append(float(np.sum(g * oracle_lib.contact_mesh(mesh, Sp, ms)[1])))
+        fd = (vals[0] - vals[1]) / (2 * hstep)
+        assert abs(fd - ref["grad_rot"][0, 0, k]) <= 1e-5 * (1 + abs(fd)), (k, fd, ref["grad_rot"][0, 0, k])

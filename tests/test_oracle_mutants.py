@@ -29,8 +29,9 @@ MUTANTS = [
     ("capsule ignores clamp", "double v0 = q[0], v1 = q[1], v2 = q[2] - z;", "double v0 = q[0], v1 = q[1], v2 = q[2];"),
     ("shallowest object wins", "P->trans + 3 * eo, p, n);\n                if (h.inside && (best < 0 || h.depth > bh.depth))",
      "P->trans + 3 * eo, p, n);\n                if (h.inside && (best < 0 || h.depth < bh.depth))"),
-    ("mesh contact: shallowest object wins", "continue;\n                }\n                if (h.inside && (best < 0 || h.depth > bh.depth))",
-     "continue;\n                }\n                if (h.inside && (best < 0 || h.depth < bh.depth))"),
+    ("mesh contact: shallowest object wins",
+     "continue;\n                }\n                if (h.inside && (best < 0 || h.depth > bh.depth)) { best = o; bh = h; }",
+     "continue;\n                }\n                if (h.inside && (best < 0 || h.depth < bh.depth)) { best = o; bh = h; }"),
     ("decay uses squared distance", "return exp(-alpha * d);", "return exp(-alpha * d * d);"),
     ("decay sums the passive node", "for (int a = 0; a < 3; ++a) acc[a] += w * uhat[(size_t)a * E * N + ej];",
      "for (int a = 0; a < 3; ++a) acc[a] += w * uhat[(size_t)a * E * N + (size_t)e * N + i];"),
@@ -55,6 +56,9 @@ MUTANTS = [
     ("mesh edge ab parameter", "double v = d1 / (d1 - d3);", "double v = d3 / (d1 - d3);"),
     ("mesh u_hat points inward", "double v[3] = {bcp[0] - q[0], bcp[1] - q[1], bcp[2] - q[2]};",
      "double v[3] = {q[0] - bcp[0], q[1] - bcp[1], q[2] - bcp[2]};"),
+    ("mesh adjoint drops the frame term", "gR[a * 3 + b] += g[a] * w[b] + d[a] * h[b];", "gR[a * 3 + b] += g[a] * w[b];"),
+    ("mesh edge Jacobian as a vertex", "J[i * 3 + j] = e[i] * e[j] / ee - (i == j ? 1.0 : 0.0);",
+     "J[i * 3 + j] = -(i == j ? 1.0 : 0.0);"),
     ("u_hat gradient from passive input", "if (cobj[ei] >= 0) { /* only active nodes carry u_hat into the input */",
      "if (cobj[ei] < 0) { /* only active nodes carry u_hat into the input */"),
 ]
@@ -81,6 +85,8 @@ def _pins():
         lambda o: TM.test_convex_hull_inside_and_depth_vs_qhull_planes(o),
         lambda o: TM.test_triangulated_cube_matches_box_primitive(o),
         lambda o: TM.test_deepest_object_wins_across_primitives_and_meshes(o),
+        lambda o: [TM.test_mesh_pose_adjoint_vs_central_differences(o, m) for m in (0, "L")],
+        lambda o: TM.test_mesh_adjoint_with_a_primitive_and_raw_rotation_entries(o),
     ]
 
 
