@@ -207,9 +207,23 @@ etac_status etac_meshset_destroy(etac_meshset *ms);
  * over primitives and meshes alike, lowest index on ties.  Same outputs and
  * layouts as etac_contact (uhat may be NULL); the results feed
  * etac_propagate.  `ms` must live on the plan's device (ETAC_ERR_VALUE
- * otherwise).  No adjoint with respect to mesh poses is provided. */
+ * otherwise); etac_contact_mesh_backward is its adjoint. */
 etac_status etac_contact_mesh(etac_plan *plan, const etac_meshset *ms, const etac_scene *scene,
                               int8_t *contact_obj, float *uhat, int32_t *n_active, void *stream);
+
+/* Adjoint of etac_contact_mesh with respect to the object poses (ETac is
+ * differentiable, Table 1): given dL/du_hat [3][E][N] (DEVICE; read on the
+ * active nodes), writes dL/dR [E][O][9] and dL/dt [E][O][3] (DEVICE) for
+ * primitives and meshes alike; contact is recomputed.  For a mesh node the
+ * winning triangle and the feature holding its closest point are held
+ * fixed: with w = c - q, u_hat = R w and dw/dq = J (face: -n n^T; edge of
+ * direction e: e e^T / |e|^2 - I; vertex: -I), and h = J R^T g,
+ * dL/dR = g w^T + d h^T (R's nine entries as free inputs, d = p - t) and
+ * dL/dt = -R h.  Objects that win no node get zeros.  Sums run in a fixed
+ * order: results do not depend on scheduling.  No plan scratch is used. */
+etac_status etac_contact_mesh_backward(etac_plan *plan, const etac_meshset *ms, const etac_scene *scene,
+                                       const float *grad_uhat, float *grad_rot, float *grad_trans,
+                                       void *stream);
 
 /* Adjoint of the contact pass: given dL/du_hat [3][E][N] (DEVICE; read on
  * active nodes only) returns dL/dR [E][O][9] and dL/dt [E][O][3] (DEVICE,

@@ -32,7 +32,7 @@ EXPORTED = (
     "etac_status_string", "etac_last_hip_error", "etac_plan_info", "etac_plan_set_occupancy",
     "etac_plan_set_timing", "etac_plan_kernel_time", "etac_plan_set_batch",
     "etac_plan_set_launch", "etac_plan_get_launch", "etac_plan_autotune",
-    "etac_meshset_create", "etac_meshset_destroy", "etac_contact_mesh",
+    "etac_meshset_create", "etac_meshset_destroy", "etac_contact_mesh", "etac_contact_mesh_backward",
 )
 
 
@@ -80,6 +80,7 @@ def lib():
             "etac_meshset_create": ([i32, vp, i32, vp, vp, P(vp)], i32),
             "etac_meshset_destroy": ([vp], i32),
             "etac_contact_mesh": ([vp, vp, P(etac_scene), vp, vp, vp, vp], i32),
+            "etac_contact_mesh_backward": ([vp, vp, P(etac_scene), vp, vp, vp, vp], i32),
             "etac_propagate": ([vp, P(etac_model), i32, vp, vp, vp, vp, vp], i32),
             "etac_step": ([vp, P(etac_scene), P(etac_model), vp, vp, vp, vp, vp], i32),
             "etac_contact_backward": ([vp, P(etac_scene), vp, vp, vp, vp], i32),
@@ -275,6 +276,17 @@ def etac_contact_mesh(plan, meshset, scene, contact_obj, uhat, n_active):
     _check("etac_contact_mesh", lib().etac_contact_mesh(plan.handle, meshset.handle, C.byref(scene),
                                                         _ptr(contact_obj), _ptr(uhat), _ptr(n_active),
                                                         _stream(plan.device)))
+
+
+def etac_contact_mesh_backward(plan, meshset, scene, grad_uhat, grad_rot, grad_trans):
+    import torch
+    E, O = scene.n_envs, scene.max_obj
+    _req(grad_uhat, torch.float32, (3, E, plan.N), "grad_uhat", plan.device)
+    _req(grad_rot, torch.float32, (E, O, 9), "grad_rot", plan.device)
+    _req(grad_trans, torch.float32, (E, O, 3), "grad_trans", plan.device)
+    _check("etac_contact_mesh_backward",
+           lib().etac_contact_mesh_backward(plan.handle, meshset.handle, C.byref(scene), _ptr(grad_uhat),
+                                            _ptr(grad_rot), _ptr(grad_trans), _stream(plan.device)))
 
 
 def saved_buffer(plan, n_envs):

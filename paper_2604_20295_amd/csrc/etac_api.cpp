@@ -375,6 +375,18 @@ etac_status etac_contact_mesh(etac_plan *plan, const etac_meshset *ms, const eta
     return e == hipSuccess ? ETAC_OK : hip_fail(e);
 }
 
+etac_status etac_contact_mesh_backward(etac_plan *plan, const etac_meshset *ms, const etac_scene *scene,
+                                       const float *grad_uhat, float *grad_rot, float *grad_trans, void *stream) {
+    if (!plan || !ms) return ETAC_ERR_NULL;
+    etac_status st = check_scene(plan->p, scene);
+    if (st != ETAC_OK) return st;
+    if (ms->device != plan->p.device) return ETAC_ERR_VALUE;
+    if (scene->n_envs > 0 && (!grad_uhat || !grad_rot || !grad_trans)) return ETAC_ERR_NULL;
+    hipError_t e = etac::launch_contact_mesh_backward(plan->p, ms->d, scene_dev(scene), grad_uhat, grad_rot,
+                                                      grad_trans, (hipStream_t)stream);
+    return e == hipSuccess ? ETAC_OK : hip_fail(e);
+}
+
 etac_status etac_propagate(etac_plan *plan, const etac_model *model, int32_t n_envs, const int8_t *contact_obj,
                            const float *uhat, float *u, void *saved, void *stream) {
     if (!plan) return ETAC_ERR_NULL;

@@ -148,6 +148,71 @@ __device__ __forceinline__ int contact_node(const SceneDev &S, int e, unsigned c
     return best;
 }
 
+// dL/d(R, t) contribution of one active node from dL/du_hat = g (FP64),
+// added to acc[0..8] (R, row-major) and acc[9..11] (t).
+// The face / clamp choice repeats the forward's operation order.
+__device__ inline void contact_adjoint_node(int type, const float *sh, const float *Rf, const float *tf, float px, float py,
+                                     float pz, const double g[3], double acc[12]) {
+#pragma clang fp contract(off)
+    const double d[3] = {(double)px - (double)tf[0], (double)py - (double)tf[1], (double)pz - (double)tf[2]};
+    double R[9];
+    for (int c = 0; c < 9; ++c) R[c] = Rf[c];
+    if (type == ETAC_SPHERE) {
+        const double r = sh[0];
+        const double s = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+        if (s == 0.0) return;
+        const double l = sqrt(s);
+        const double phi = r / l - 1.0, tphip = -r / (l * s);
+        const double gd = g[0] * d[0] + g[1] * d[1] + g[2] * d[2];
+        #pragma unroll
+        for (int a = 0; a < 3; ++a) acc[9 + a] -= phi * g[a] + tphip * gd * d[a];
+        return;
+    }
+    double q[3];
+    for (int c = 0; c < 3; ++c) q[c] = (R[0 * 3 + c] * d[0] + R[1 * 3 + c] * d[1]) + R[2 * 3 + c] * d[2];
+    if (type == ETAC_BOX) {
+        double best = (double)sh[0] - fabs(q[0]);
+        int cs = 0;
+        for (int c = 1; c < 3; ++c) {
+            const double sl = (double)sh[c] - fabs(q[c]);
+            if (sl < best) { best = sl; cs = c; }
+        }
+        const double sg = q[cs] >= 0.0 ? 1.0 : -1.0;
+        const double rc[3] = {R[cs], R[3 + cs], R[6 + cs]};
+        const double grc = g[0] * rc[0] + g[1] * rc[1] + g[2] * rc[2];
+        const double coef = sg * (double)sh[cs] - q[cs];
+        #pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            acc[9 + a] += grc * rc[a];
+            acc[a * 3 + cs] += coef * g[a] - grc * d[a];
+        }
+        return;
+    }
+    const double r = sh[0], L = sh[1];
+    double z = q[2];
+    bool clamped = false;
+    if (z < -L) { z = -L; clamped = true; }
+    else if (z > L) { z = L; clamped = true; }
+    const double v[3] = {q[0], q[1], q[2] - z};
+    const double s = (v[0] * v[0] + v[1] * v[1]) + v[2] * v[2];
+    if (s == 0.0) return;
+    const double l = sqrt(s);
+    const double phi = r / l - 1.0, tphip = -r / (l * s);
+    double Rv[3], RTg[3];
+    #pragma unroll
+    for (int a = 0; a < 3; ++a) Rv[a] = R[a * 3] * v[0] + R[a * 3 + 1] * v[1] + R[a * 3 + 2] * v[2];
+    for (int c = 0; c < 3; ++c) RTg[c] = R[c] * g[0] + R[3 + c] * g[1] + R[6 + c] * g[2];
+    const double gRv = g[0] * Rv[0] + g[1] * Rv[1] + g[2] * Rv[2];
+    double av[3];
+    for (int c = 0; c < 3; ++c) av[c] = tphip * gRv * v[c] + phi * RTg[c];
+    if (!clamped) av[2] = tphip * gRv * v[2];
+    #pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        for (int c = 0; c < 3; ++c) acc[a * 3 + c] += d[a] * av[c] + phi * g[a] * v[c];
+        acc[9 + a] -= R[a * 3] * av[0] + R[a * 3 + 1] * av[1] + R[a * 3 + 2] * av[2];
+    }
+}
+
 // Primitives of env e whose bounding ball may reach patch k's bounding
 // sphere (objects of other types, triangle meshes included, are ignored).
 __device__ __forceinline__ unsigned cull_objects(const SceneDev &S, const MeshDev &M, int e, int k) {

@@ -154,6 +154,8 @@ struct MeshSetDev {
 
 hipError_t launch_contact_mesh(const Plan &p, const MeshSetDev &ms, const SceneDev &s, int8_t *cobj, float *uhat,
                                int32_t *n_active, hipStream_t st);
+hipError_t launch_contact_mesh_backward(const Plan &p, const MeshSetDev &ms, const SceneDev &s,
+                                        const float *grad_uhat, float *grad_rot, float *grad_trans, hipStream_t st);
 
 }  // namespace etac
 

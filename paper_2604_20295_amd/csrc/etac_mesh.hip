@@ -148,10 +148,21 @@ __device__ __forceinline__ int wave_min(int v) {
                min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
+// Wave-wide sum in a fixed order (pairwise within rows, then the four row
+// sums), the same value in every lane.
+__device__ __forceinline__ double wave_sum(double v) {
+    v = v + dpp<0xb1>(v);
+    v = v + dpp<0x4e>(v);
+    v = v + dpp<0x141>(v);
+    v = v + dpp<0x140>(v);
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
 // Signed-distance query of one point q (object frame, the same value in
 // every lane of the wave) against mesh `mesh`; the whole wave takes part.
 // Returns the same result in every lane.
-__device__ Pen mesh_query(const MeshSetDev &ms, int mesh, double q0, double q1, double q2, const float *R) {
+__device__ Pen mesh_query(const MeshSetDev &ms, int mesh, double q0, double q1, double q2, const float *R,
+                          int &tri) {
 #pragma clang fp contract(off)
     const int lane = lane_id();
     const int4 mr = ms.mesh[mesh];
@@ -219,6 +230,7 @@ __device__ Pen mesh_query(const MeshSetDev &ms, int mesh, double q0, double q1, 
     h.inside = false;
     h.depth = 0.0;
     h.u0 = h.u1 = h.u2 = 0.0;
+    tri = best_t;
     if (best_t < 0) return h;
     double x0, x1, x2;
     int f;
@@ -235,6 +247,55 @@ __device__ Pen mesh_query(const MeshSetDev &ms, int mesh, double q0, double q1, 
     return h;
 }
 
+// dL/d(R, t) of one node won by a mesh object (triangle `tri`), from
+// dL/du_hat = g, added to acc[0..8] (R) and acc[9..11] (t).  With the
+// closest point c(q) on the triangle's winning feature held fixed,
+// w = c - q, u_hat = R w and dw/dq = J (face: -n n^T; edge with direction
+// e: e e^T / |e|^2 - I; vertex: -I; J symmetric): for h = J R^T g,
+// dL/dR = g w^T + d h^T and dL/dt = -R h.
+__device__ void mesh_adjoint_node(const MeshSetDev &ms, int tri, const float *Rf, const float *tf, float px,
+                                  float py, float pz, const double g[3], double acc[12]) {
+#pragma clang fp contract(off)
+    const double d0 = (double)px - (double)tf[0], d1 = (double)py - (double)tf[1], d2 = (double)pz - (double)tf[2];
+    double R[9];
+    for (int c = 0; c < 9; ++c) R[c] = Rf[c];
+    const double q0 = (R[0] * d0 + R[3] * d1) + R[6] * d2;
+    const double q1 = (R[1] * d0 + R[4] * d1) + R[7] * d2;
+    const double q2 = (R[2] * d0 + R[5] * d1) + R[8] * d2;
+    const TriCorners T = load_tri(ms, tri);
+    double x0, x1, x2;
+    int f;
+    closest_tri(q0, q1, q2, T, x0, x1, x2, f);
+    const double rg0 = (R[0] * g[0] + R[3] * g[1]) + R[6] * g[2];
+    const double rg1 = (R[1] * g[0] + R[4] * g[1]) + R[7] * g[2];
+    const double rg2 = (R[2] * g[0] + R[5] * g[1]) + R[8] * g[2];
+    double h0, h1, h2;
+    if (f == FEAT_FACE) {
+        const double *n = ms.pn + (size_t)tri * 21;
+        const double nd = (n[0] * rg0 + n[1] * rg1) + n[2] * rg2;
+        h0 = -n[0] * nd; h1 = -n[1] * nd; h2 = -n[2] * nd;
+    } else if (f == FEAT_AB || f == FEAT_BC || f == FEAT_CA) {
+        const double s0 = f == FEAT_AB ? T.a0 : (f == FEAT_BC ? T.b0 : T.c0);
+        const double s1 = f == FEAT_AB ? T.a1 : (f == FEAT_BC ? T.b1 : T.c1);
+        const double s2 = f == FEAT_AB ? T.a2 : (f == FEAT_BC ? T.b2 : T.c2);
+        const double e0 = (f == FEAT_AB ? T.b0 : (f == FEAT_BC ? T.c0 : T.a0)) - s0;
+        const double e1 = (f == FEAT_AB ? T.b1 : (f == FEAT_BC ? T.c1 : T.a1)) - s1;
+        const double e2 = (f == FEAT_AB ? T.b2 : (f == FEAT_BC ? T.c2 : T.a2)) - s2;
+        const double k = ((e0 * rg0 + e1 * rg1) + e2 * rg2) / ((e0 * e0 + e1 * e1) + e2 * e2);
+        h0 = e0 * k - rg0; h1 = e1 * k - rg1; h2 = e2 * k - rg2;
+    } else {
+        h0 = -rg0; h1 = -rg1; h2 = -rg2;
+    }
+    const double w0 = x0 - q0, w1 = x1 - q1, w2 = x2 - q2;
+    const double d[3] = {d0, d1, d2}, w[3] = {w0, w1, w2}, h[3] = {h0, h1, h2};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) acc[a * 3 + b] += g[a] * w[b] + d[a] * h[b];
+        acc[9 + a] -= (R[a * 3] * h0 + R[a * 3 + 1] * h1) + R[a * 3 + 2] * h2;
+    }
+}
+
 // Mesh index named by a mesh object's shape[0], or -1.
 __device__ __forceinline__ int mesh_of(const float *sh, int M) {
     const float x = sh[0];
@@ -248,6 +309,10 @@ struct MeshContactParams {
     int8_t *cobj;      // [E][N]
     float *uhat;       // [3][E][N] or null
     int32_t *n_active; // [E][K]
+    // adjoint
+    const float *grad_uhat;  // [3][E][N]
+    float *grad_rot;         // [E][O][9]
+    float *grad_trans;       // [E][O][3]
 };
 
 // Candidate objects (primitives and valid meshes) of env e whose bounding
@@ -279,9 +344,14 @@ __device__ __forceinline__ unsigned cull_mesh_objects(const MeshContactParams &p
 }
 
 // Four waves per SIMD (at most 128 registers): the queries are latency-bound.
+// ADJ: the adjoint (contact recomputed; every node's pose gradient added to
+// its winning object's sums: per wave in a fixed order, then over the waves
+// in wave order, so results do not depend on timing).
+template <bool ADJ>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_contact_mesh(MeshContactParams p) {
     __shared__ int cnt[kMaxPatches];
     __shared__ uint8_t cand[kMaxPatches];
+    __shared__ double sacc[ADJ ? kWaves : 1][ADJ ? ETAC_MAX_OBJ : 1][12];
     const int e = blockIdx.x;
     const MeshDev &M = p.mesh;
     const SceneDev &S = p.scene;
@@ -291,6 +361,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         cnt[k] = 0;
         cand[k] = (uint8_t)cull_mesh_objects(p, e, k);
     }
+    if (ADJ)
+        for (int c = threadIdx.x; c < kWaves * ETAC_MAX_OBJ * 12; c += kWG) (&sacc[0][0][0])[c] = 0.0;
     __syncthreads();
     const int lane = lane_id();
     const int no = min(S.n_obj[e], S.O);
@@ -303,7 +375,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         const unsigned c = valid ? cand[k] : 0u;
         const float px = valid ? M.pos[i] : 0.0f, py = valid ? M.pos[N + i] : 0.0f;
         const float pz = valid ? M.pos[2 * N + i] : 0.0f;
-        int best = -1;
+        int best = -1, btri = -1;   // btri: winning triangle when a mesh wins
         double bd = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
         if (__ballot(c != 0u)) {
             for (int o = 0; o < no; ++o) {
@@ -321,6 +393,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                     const Pen h = penetrate(ty, sh, R, t, px, py, pz, M.nrm[i], M.nrm[N + i], M.nrm[2 * N + i]);
                     if (h.inside && (best < 0 || h.depth > bd)) {
                         best = o;
+                        btri = -1;
                         bd = h.depth;
                         b0 = h.u0; b1 = h.u1; b2 = h.u2;
                     }
@@ -364,9 +437,11 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                             q1 = (r01 * d0 + r11 * d1) + r21 * e2;
                             q2 = (r02 * d0 + r12 * d1) + r22 * e2;
                         }
-                        const Pen h = mesh_query(p.ms, m, q0, q1, q2, R);
+                        int tri;
+                        const Pen h = mesh_query(p.ms, m, q0, q1, q2, R, tri);
                         if (lane == src && h.inside && (best < 0 || h.depth > bd)) {
                             best = o;
+                            btri = tri;
                             bd = h.depth;
                             b0 = h.u0; b1 = h.u1; b2 = h.u2;
                         }
@@ -374,7 +449,32 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
                 }
             }
         }
-        if (valid) {
+        if (ADJ) {
+            if (__ballot(best >= 0)) {
+                double acc[12];
+#pragma unroll
+                for (int q = 0; q < 12; ++q) acc[q] = 0.0;
+                if (best >= 0) {
+                    const size_t eo = (size_t)e * S.O + best;
+                    const double g[3] = {p.grad_uhat[row + i], p.grad_uhat[EN + row + i],
+                                         p.grad_uhat[2 * EN + row + i]};
+                    if (btri >= 0)
+                        mesh_adjoint_node(p.ms, btri, S.rot + 9 * eo, S.trans + 3 * eo, px, py, pz, g, acc);
+                    else
+                        contact_adjoint_node(S.type[eo], S.shape + 4 * eo, S.rot + 9 * eo, S.trans + 3 * eo, px, py,
+                                             pz, g, acc);
+                }
+                const int wave = threadIdx.x >> 6;
+                for (int o = 0; o < no; ++o) {
+                    if (!__ballot(best == o)) continue;
+#pragma unroll
+                    for (int q = 0; q < 12; ++q) {
+                        const double v = wave_sum(best == o ? acc[q] : 0.0);
+                        if (lane == 0) sacc[wave][o][q] += v;   // one writer per wave, chunks in order
+                    }
+                }
+            }
+        } else if (valid) {
             p.cobj[row + i] = (int8_t)best;
             if (p.uhat) {
                 p.uhat[row + i] = (float)b0;
@@ -385,14 +485,33 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < K; k += kWG) p.n_active[(size_t)e * K + k] = cnt[k];
+    if (ADJ) {
+        for (int c = threadIdx.x; c < S.O * 12; c += kWG) {
+            const int o = c / 12, q = c % 12;
+            double v = 0.0;
+            for (int w = 0; w < kWaves; ++w) v += sacc[w][o][q];
+            const size_t eo = (size_t)e * S.O + o;
+            if (q < 9) p.grad_rot[eo * 9 + q] = (float)v;
+            else p.grad_trans[eo * 3 + q - 9] = (float)v;
+        }
+    } else {
+        for (int k = threadIdx.x; k < K; k += kWG) p.n_active[(size_t)e * K + k] = cnt[k];
+    }
 }
 
 hipError_t launch_contact_mesh(const Plan &p, const MeshSetDev &ms, const SceneDev &s, int8_t *cobj, float *uhat,
                                int32_t *n_active, hipStream_t st) {
     if (s.E == 0) return hipSuccess;
-    MeshContactParams cp{p.mesh, s, ms, cobj, uhat, n_active};
-    hipLaunchKernelGGL(k_contact_mesh, dim3(s.E), dim3(kWG), 0, st, cp);
+    MeshContactParams cp{p.mesh, s, ms, cobj, uhat, n_active, nullptr, nullptr, nullptr};
+    hipLaunchKernelGGL(k_contact_mesh<false>, dim3(s.E), dim3(kWG), 0, st, cp);
+    return hipGetLastError();
+}
+
+hipError_t launch_contact_mesh_backward(const Plan &p, const MeshSetDev &ms, const SceneDev &s,
+                                        const float *grad_uhat, float *grad_rot, float *grad_trans, hipStream_t st) {
+    if (s.E == 0) return hipSuccess;
+    MeshContactParams cp{p.mesh, s, ms, nullptr, nullptr, nullptr, grad_uhat, grad_rot, grad_trans};
+    hipLaunchKernelGGL(k_contact_mesh<true>, dim3(s.E), dim3(kWG), 0, st, cp);
     return hipGetLastError();
 }
 

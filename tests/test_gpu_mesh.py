@@ -3,7 +3,9 @@ oracle: bit-exact contact masks and active counts, u_hat within the
 displacement bar, the results fed to etac_propagate, a full-size hand sampled
 env by env, and the edge cases (meshes of more than 64 clusters, a
 four-triangle mesh, invalid mesh indices, zero envs, mesh objects ignored by
-the primitive-only calls)."""
+the primitive-only calls); and the pose adjoint (etac_contact_mesh_backward)
+against the oracle's, with reflex-edge features and run-to-run identical
+results."""
 import numpy as np
 import pytest
 
@@ -150,3 +152,75 @@ def test_invalid_mesh_index_zero_envs_and_primitive_calls(oracle_lib):
                               torch.empty((3, 0, plan.N), device=dev),
                               torch.empty((0, plan.K), dtype=torch.int32, device=dev))
     torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------------------
+# adjoint with respect to the poses
+# ---------------------------------------------------------------------------
+
+def gpu_contact_mesh_backward(plan, meshset, scene, grad_uhat):
+    from paper_2604_20295_amd import _native
+    torch, dev = torch_dev()
+    ds = DevScene(scene)
+    E, O = scene.n_envs, scene.max_obj
+    grot = torch.full((E, O, 9), float("nan"), device=dev)
+    gt = torch.full((E, O, 3), float("nan"), device=dev)
+    _native.etac_contact_mesh_backward(plan, meshset, ds.struct(plan), to_dev(grad_uhat.astype(np.float32)), grot, gt)
+    torch.cuda.synchronize()
+    return grot.cpu().numpy().astype(np.float64), gt.cpu().numpy().astype(np.float64)
+
+
+def _compare_adjoint(tag, got, ref):
+    from tests.test_gpu_backward import _close
+    grot, gt = got
+    log(f"[gpu] {tag}: max|grad_trans| {np.abs(ref['grad_trans']).max():.3e}, "
+        f"max|d grad_trans| {np.abs(gt - ref['grad_trans']).max():.2e}, "
+        f"max|d grad_rot| {np.abs(grot - ref['grad_rot']).max():.2e}")
+    _close(gt, ref["grad_trans"], "grad_trans")
+    _close(grot, ref["grad_rot"], "grad_rot")
+
+
+def test_mesh_adjoint_small_hand(oracle_lib):
+    from paper_2604_20295_amd import _native
+    mesh = scenes.hand_mesh(0, sizes=SMALL["sizes"])
+    ms, scene = _mixed(mesh, 48, 5, p_mesh=0.7, scale=SMALL["scale"])
+    plan = make_plan(mesh, 48, 3)
+    dms = _native.MeshSet.from_set(ms)
+    g = np.random.default_rng(3).standard_normal((3, 48, plan.N)).astype(np.float32).astype(np.float64)
+    got = gpu_contact_mesh_backward(plan, dms, scene, g)
+    ref = oracle_lib.contact_mesh_backward(mesh, scene, ms, g)
+    _compare_adjoint("mesh pose adjoint, small hand 48 envs", got, ref)
+    again = gpu_contact_mesh_backward(plan, dms, scene, g)
+    assert np.array_equal(got[0], again[0]) and np.array_equal(got[1], again[1])   # fixed summation order
+
+
+def test_mesh_adjoint_reflex_edges(oracle_lib):
+    from paper_2604_20295_amd import _native
+    from tests.test_oracle_mesh import mesh_scene
+    ms = tm.merge([tm.l_prism_mesh()], ("L",))
+    mesh = scenes.pad32_mesh()
+    rng = np.random.default_rng(2)
+    R = scenes.random_rotation(rng)
+    h = ms.support_extent(0, R, np.array([0.0, 0.0, -1.0]))
+    scene = mesh_scene([(0, R, np.array([0.3, -0.2, h - 2.5]))])
+    feat = oracle_lib.contact_mesh_features(mesh, scene, ms)
+    assert ((feat >= 1) & (feat <= 3)).sum() >= 2
+    plan = make_plan(mesh, 1, 1)
+    dms = _native.MeshSet.from_set(ms)
+    g = np.random.default_rng(4).standard_normal((3, 1, plan.N)).astype(np.float32).astype(np.float64)
+    _compare_adjoint("mesh pose adjoint, L prism (reflex-edge features)", gpu_contact_mesh_backward(plan, dms, scene, g),
+                     oracle_lib.contact_mesh_backward(mesh, scene, ms, g))
+
+
+def test_mesh_adjoint_full_size_hand_sampled(oracle_lib):
+    from paper_2604_20295_amd import _native
+    mesh = scenes.hand_mesh(0)
+    ms = tm.object_set()
+    scene = tm.hand_mesh_scene(mesh, ms, 4096, seed=2, p_mesh=1.0)
+    plan = make_plan(mesh, 4096, 3)
+    dms = _native.MeshSet.from_set(ms)
+    g = np.random.default_rng(9).standard_normal((3, 4096, plan.N)).astype(np.float32)
+    grot, gt = gpu_contact_mesh_backward(plan, dms, scene, g.astype(np.float64))
+    envs = np.sort(np.random.default_rng(17).choice(4096, 16, replace=False))
+    ref = oracle_lib.contact_mesh_backward(mesh, scene.select(envs), ms, np.ascontiguousarray(g[:, envs]).astype(np.float64))
+    _compare_adjoint("mesh pose adjoint, hand 4096 envs, 16 sampled envs", (grot[envs], gt[envs]), ref)
