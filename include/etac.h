@@ -206,24 +206,34 @@ etac_status etac_meshset_destroy(etac_meshset *ms);
  * c; its depth is |q - c| and u_hat = R (c - q).  The deepest object wins
  * over primitives and meshes alike, lowest index on ties.  Same outputs and
  * layouts as etac_contact (uhat may be NULL); the results feed
- * etac_propagate.  `ms` must live on the plan's device (ETAC_ERR_VALUE
- * otherwise); etac_contact_mesh_backward is its adjoint. */
+ * etac_propagate.  hit (DEVICE [E][N] int32, may be NULL): a record for the
+ * adjoint, the winning triangle of each node a mesh object wins (an index
+ * into `ms`'s own triangle order), -1 for every other node.  `ms` must live
+ * on the plan's device (ETAC_ERR_VALUE otherwise); etac_contact_mesh_backward
+ * is its adjoint. */
 etac_status etac_contact_mesh(etac_plan *plan, const etac_meshset *ms, const etac_scene *scene,
-                              int8_t *contact_obj, float *uhat, int32_t *n_active, void *stream);
+                              int8_t *contact_obj, float *uhat, int32_t *n_active, int32_t *hit, void *stream);
 
 /* Adjoint of etac_contact_mesh with respect to the object poses (ETac is
  * differentiable, Table 1): given dL/du_hat [3][E][N] (DEVICE; read on the
  * active nodes), writes dL/dR [E][O][9] and dL/dt [E][O][3] (DEVICE) for
- * primitives and meshes alike; contact is recomputed.  For a mesh node the
+ * primitives and meshes alike.  For a mesh node the
  * winning triangle and the feature holding its closest point are held
  * fixed: with w = c - q, u_hat = R w and dw/dq = J (face: -n n^T; edge of
  * direction e: e e^T / |e|^2 - I; vertex: -I), and h = J R^T g,
  * dL/dR = g w^T + d h^T (R's nine entries as free inputs, d = p - t) and
  * dL/dt = -R h.  Objects that win no node get zeros.  Sums run in a fixed
- * order: results do not depend on scheduling.  No plan scratch is used. */
+ * order: results do not depend on scheduling.  No plan scratch is used.
+ * contact_obj and hit (DEVICE, both or neither): the records of the
+ * etac_contact_mesh call on the same scene and mesh set; given them, the
+ * call reads each node's winner and triangle instead of repeating the
+ * distance search (identical results, at a fraction of the cost); entries
+ * that cannot come from that call (an object index out of range, a
+ * triangle outside the object's mesh) are skipped.  Both NULL: contact is
+ * recomputed.  Only one of them NULL: ETAC_ERR_NULL. */
 etac_status etac_contact_mesh_backward(etac_plan *plan, const etac_meshset *ms, const etac_scene *scene,
-                                       const float *grad_uhat, float *grad_rot, float *grad_trans,
-                                       void *stream);
+                                       const float *grad_uhat, const int8_t *contact_obj, const int32_t *hit,
+                                       float *grad_rot, float *grad_trans, void *stream);
 
 /* Adjoint of the contact pass: given dL/du_hat [3][E][N] (DEVICE; read on
  * active nodes only) returns dL/dR [E][O][9] and dL/dt [E][O][3] (DEVICE,

@@ -79,8 +79,8 @@ def lib():
             "etac_contact": ([vp, P(etac_scene), vp, vp, vp, vp], i32),
             "etac_meshset_create": ([i32, vp, i32, vp, vp, P(vp)], i32),
             "etac_meshset_destroy": ([vp], i32),
-            "etac_contact_mesh": ([vp, vp, P(etac_scene), vp, vp, vp, vp], i32),
-            "etac_contact_mesh_backward": ([vp, vp, P(etac_scene), vp, vp, vp, vp], i32),
+            "etac_contact_mesh": ([vp, vp, P(etac_scene), vp, vp, vp, vp, vp], i32),
+            "etac_contact_mesh_backward": ([vp, vp, P(etac_scene), vp, vp, vp, vp, vp, vp], i32),
             "etac_propagate": ([vp, P(etac_model), i32, vp, vp, vp, vp, vp], i32),
             "etac_step": ([vp, P(etac_scene), P(etac_model), vp, vp, vp, vp, vp], i32),
             "etac_contact_backward": ([vp, P(etac_scene), vp, vp, vp, vp], i32),
@@ -267,26 +267,30 @@ class MeshSet:
             pass
 
 
-def etac_contact_mesh(plan, meshset, scene, contact_obj, uhat, n_active):
+def etac_contact_mesh(plan, meshset, scene, contact_obj, uhat, n_active, hit=None):
     import torch
     E = scene.n_envs
     _req(contact_obj, torch.int8, (E, plan.N), "contact_obj", plan.device)
     _req(uhat, torch.float32, (3, E, plan.N), "uhat", plan.device)
     _req(n_active, torch.int32, (E, plan.K), "n_active", plan.device)
+    _req(hit, torch.int32, (E, plan.N), "hit", plan.device)
     _check("etac_contact_mesh", lib().etac_contact_mesh(plan.handle, meshset.handle, C.byref(scene),
-                                                        _ptr(contact_obj), _ptr(uhat), _ptr(n_active),
+                                                        _ptr(contact_obj), _ptr(uhat), _ptr(n_active), _ptr(hit),
                                                         _stream(plan.device)))
 
 
-def etac_contact_mesh_backward(plan, meshset, scene, grad_uhat, grad_rot, grad_trans):
+def etac_contact_mesh_backward(plan, meshset, scene, grad_uhat, grad_rot, grad_trans, contact_obj=None, hit=None):
     import torch
     E, O = scene.n_envs, scene.max_obj
     _req(grad_uhat, torch.float32, (3, E, plan.N), "grad_uhat", plan.device)
     _req(grad_rot, torch.float32, (E, O, 9), "grad_rot", plan.device)
     _req(grad_trans, torch.float32, (E, O, 3), "grad_trans", plan.device)
+    _req(contact_obj, torch.int8, (E, plan.N), "contact_obj", plan.device)
+    _req(hit, torch.int32, (E, plan.N), "hit", plan.device)
     _check("etac_contact_mesh_backward",
            lib().etac_contact_mesh_backward(plan.handle, meshset.handle, C.byref(scene), _ptr(grad_uhat),
-                                            _ptr(grad_rot), _ptr(grad_trans), _stream(plan.device)))
+                                            _ptr(contact_obj), _ptr(hit), _ptr(grad_rot), _ptr(grad_trans),
+                                            _stream(plan.device)))
 
 
 def saved_buffer(plan, n_envs):

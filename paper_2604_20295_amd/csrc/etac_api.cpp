@@ -364,26 +364,28 @@ etac_status etac_contact(etac_plan *plan, const etac_scene *scene, int8_t *conta
 }
 
 etac_status etac_contact_mesh(etac_plan *plan, const etac_meshset *ms, const etac_scene *scene, int8_t *contact_obj,
-                              float *uhat, int32_t *n_active, void *stream) {
+                              float *uhat, int32_t *n_active, int32_t *hit, void *stream) {
     if (!plan || !ms) return ETAC_ERR_NULL;
     etac_status st = check_scene(plan->p, scene);
     if (st != ETAC_OK) return st;
     if (ms->device != plan->p.device) return ETAC_ERR_VALUE;
     if (scene->n_envs > 0 && (!contact_obj || !n_active)) return ETAC_ERR_NULL;
-    hipError_t e = etac::launch_contact_mesh(plan->p, ms->d, scene_dev(scene), contact_obj, uhat, n_active,
+    hipError_t e = etac::launch_contact_mesh(plan->p, ms->d, scene_dev(scene), contact_obj, uhat, n_active, hit,
                                              (hipStream_t)stream);
     return e == hipSuccess ? ETAC_OK : hip_fail(e);
 }
 
 etac_status etac_contact_mesh_backward(etac_plan *plan, const etac_meshset *ms, const etac_scene *scene,
-                                       const float *grad_uhat, float *grad_rot, float *grad_trans, void *stream) {
+                                       const float *grad_uhat, const int8_t *contact_obj, const int32_t *hit,
+                                       float *grad_rot, float *grad_trans, void *stream) {
     if (!plan || !ms) return ETAC_ERR_NULL;
     etac_status st = check_scene(plan->p, scene);
     if (st != ETAC_OK) return st;
     if (ms->device != plan->p.device) return ETAC_ERR_VALUE;
     if (scene->n_envs > 0 && (!grad_uhat || !grad_rot || !grad_trans)) return ETAC_ERR_NULL;
-    hipError_t e = etac::launch_contact_mesh_backward(plan->p, ms->d, scene_dev(scene), grad_uhat, grad_rot,
-                                                      grad_trans, (hipStream_t)stream);
+    if ((contact_obj == nullptr) != (hit == nullptr)) return ETAC_ERR_NULL;   // both records or neither
+    hipError_t e = etac::launch_contact_mesh_backward(plan->p, ms->d, scene_dev(scene), grad_uhat, contact_obj, hit,
+                                                      grad_rot, grad_trans, (hipStream_t)stream);
     return e == hipSuccess ? ETAC_OK : hip_fail(e);
 }
 

@@ -153,9 +153,10 @@ struct MeshSetDev {
 };
 
 hipError_t launch_contact_mesh(const Plan &p, const MeshSetDev &ms, const SceneDev &s, int8_t *cobj, float *uhat,
-                               int32_t *n_active, hipStream_t st);
+                               int32_t *n_active, int32_t *hit, hipStream_t st);
 hipError_t launch_contact_mesh_backward(const Plan &p, const MeshSetDev &ms, const SceneDev &s,
-                                        const float *grad_uhat, float *grad_rot, float *grad_trans, hipStream_t st);
+                                        const float *grad_uhat, const int8_t *cobj, const int32_t *hit,
+                                        float *grad_rot, float *grad_trans, hipStream_t st);
 
 }  // namespace etac
 

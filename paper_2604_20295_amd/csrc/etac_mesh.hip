@@ -309,10 +309,13 @@ struct MeshContactParams {
     int8_t *cobj;      // [E][N]
     float *uhat;       // [3][E][N] or null
     int32_t *n_active; // [E][K]
+    int32_t *hit;            // [E][N] or null: winning triangle (cluster order) of mesh-won nodes, else -1
     // adjoint
     const float *grad_uhat;  // [3][E][N]
     float *grad_rot;         // [E][O][9]
     float *grad_trans;       // [E][O][3]
+    const int8_t *cobj_in;   // [E][N] and
+    const int32_t *hit_in;   // [E][N]: the forward's records, or null (contact recomputed)
 };
 
 // Candidate objects (primitives and valid meshes) of env e whose bounding
@@ -377,7 +380,26 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         const float pz = valid ? M.pos[2 * N + i] : 0.0f;
         int best = -1, btri = -1;   // btri: winning triangle when a mesh wins
         double bd = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
-        if (__ballot(c != 0u)) {
+        if (ADJ && p.hit_in) {
+            // the forward's records; values that cannot come from it are skipped
+            if (valid && c != 0u) {
+                const int o = p.cobj_in[row + i];
+                if (o >= 0 && o < no) {
+                    const size_t eo = (size_t)e * S.O + o;
+                    const int ty = S.type[eo];
+                    const int h = p.hit_in[row + i];
+                    if (ty >= ETAC_SPHERE && ty <= ETAC_CAPSULE) {
+                        best = o;
+                    } else if (ty == ETAC_MESH) {
+                        const int m = mesh_of(S.shape + 4 * eo, p.ms.M);
+                        if (m >= 0 && h >= p.ms.mesh[m].x && h < p.ms.mesh[m].y) {
+                            best = o;
+                            btri = h;
+                        }
+                    }
+                }
+            }
+        } else if (__ballot(c != 0u)) {
             for (int o = 0; o < no; ++o) {
                 const size_t eo = (size_t)e * S.O + o;
                 const int ty = S.type[eo];
@@ -476,6 +498,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
             }
         } else if (valid) {
             p.cobj[row + i] = (int8_t)best;
+            if (p.hit) p.hit[row + i] = best >= 0 ? btri : -1;
             if (p.uhat) {
                 p.uhat[row + i] = (float)b0;
                 p.uhat[EN + row + i] = (float)b1;
@@ -500,17 +523,19 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
 }
 
 hipError_t launch_contact_mesh(const Plan &p, const MeshSetDev &ms, const SceneDev &s, int8_t *cobj, float *uhat,
-                               int32_t *n_active, hipStream_t st) {
+                               int32_t *n_active, int32_t *hit, hipStream_t st) {
     if (s.E == 0) return hipSuccess;
-    MeshContactParams cp{p.mesh, s, ms, cobj, uhat, n_active, nullptr, nullptr, nullptr};
+    MeshContactParams cp{p.mesh, s, ms, cobj, uhat, n_active, hit, nullptr, nullptr, nullptr, nullptr, nullptr};
     hipLaunchKernelGGL(k_contact_mesh<false>, dim3(s.E), dim3(kWG), 0, st, cp);
     return hipGetLastError();
 }
 
 hipError_t launch_contact_mesh_backward(const Plan &p, const MeshSetDev &ms, const SceneDev &s,
-                                        const float *grad_uhat, float *grad_rot, float *grad_trans, hipStream_t st) {
+                                        const float *grad_uhat, const int8_t *cobj, const int32_t *hit,
+                                        float *grad_rot, float *grad_trans, hipStream_t st) {
     if (s.E == 0) return hipSuccess;
-    MeshContactParams cp{p.mesh, s, ms, nullptr, nullptr, nullptr, grad_uhat, grad_rot, grad_trans};
+    MeshContactParams cp{p.mesh, s, ms, nullptr, nullptr, nullptr, nullptr, grad_uhat, grad_rot, grad_trans,
+                         hit ? cobj : nullptr, cobj ? hit : nullptr};
     hipLaunchKernelGGL(k_contact_mesh<true>, dim3(s.E), dim3(kWG), 0, st, cp);
     return hipGetLastError();
 }

@@ -90,8 +90,8 @@ def test_calls_reject_null_plan():
     assert lib.etac_contact_backward(None, C.byref(sc), None, None, None, None) == -1
     assert lib.etac_propagate_backward(None, C.byref(md), 1, None, None, None, None, None, None, None, None) == -1
     assert lib.etac_step_backward(None, C.byref(sc), C.byref(md), None, None, None, None, None, None, None) == -1
-    assert lib.etac_contact_mesh(None, None, C.byref(sc), None, None, None, None) == -1
-    assert lib.etac_contact_mesh_backward(None, None, C.byref(sc), None, None, None, None) == -1
+    assert lib.etac_contact_mesh(None, None, C.byref(sc), None, None, None, None, None) == -1
+    assert lib.etac_contact_mesh_backward(None, None, C.byref(sc), None, None, None, None, None, None) == -1
     assert lib.etac_meshset_destroy(None) == 0
     assert lib.etac_plan_destroy(None) == 0
     assert lib.etac_plan_info(None, None, None, None) == -1

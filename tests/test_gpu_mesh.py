@@ -224,3 +224,59 @@ def test_mesh_adjoint_full_size_hand_sampled(oracle_lib):
     envs = np.sort(np.random.default_rng(17).choice(4096, 16, replace=False))
     ref = oracle_lib.contact_mesh_backward(mesh, scene.select(envs), ms, np.ascontiguousarray(g[:, envs]).astype(np.float64))
     _compare_adjoint("mesh pose adjoint, hand 4096 envs, 16 sampled envs", (grot[envs], gt[envs]), ref)
+
+
+def test_mesh_adjoint_from_forward_records(oracle_lib):
+    # the forward's contact_obj + hit records give the same gradients as the
+    # recomputing adjoint, bit for bit; hit marks exactly the mesh-won nodes;
+    # record entries that cannot come from the forward are skipped
+    from paper_2604_20295_amd import _native
+    torch, dev = torch_dev()
+    mesh = scenes.hand_mesh(0, sizes=SMALL["sizes"])
+    ms, scene = _mixed(mesh, 32, 21, p_mesh=0.7, scale=SMALL["scale"])
+    plan = make_plan(mesh, 32, 3)
+    dms = _native.MeshSet.from_set(ms)
+    ds = DevScene(scene)
+    st = ds.struct(plan)
+    N, K, O = plan.N, plan.K, scene.max_obj
+    cobj = torch.empty((32, N), dtype=torch.int8, device=dev)
+    uhat = torch.empty((3, 32, N), device=dev)
+    na = torch.empty((32, K), dtype=torch.int32, device=dev)
+    hit = torch.full((32, N), 12345, dtype=torch.int32, device=dev)
+    _native.etac_contact_mesh(plan, dms, st, cobj, uhat, na, hit)
+    g = to_dev(np.random.default_rng(5).standard_normal((3, 32, N)).astype(np.float32))
+    out = {}
+    for tag, rec in (("recompute", (None, None)), ("records", (cobj, hit))):
+        gr = torch.empty((32, O, 9), device=dev)
+        gt = torch.empty((32, O, 3), device=dev)
+        _native.etac_contact_mesh_backward(plan, dms, st, g, gr, gt, *rec)
+        out[tag] = (gr.cpu().numpy(), gt.cpu().numpy())
+    torch.cuda.synchronize()
+    assert np.array_equal(out["recompute"][0], out["records"][0])
+    assert np.array_equal(out["recompute"][1], out["records"][1])
+    c, h = cobj.cpu().numpy(), hit.cpu().numpy()
+    won_by_mesh = np.zeros_like(c, dtype=bool)
+    for e in range(32):
+        for o in range(scene.n_obj[e]):
+            if scene.type[e, o] == tm.MESH:
+                won_by_mesh[e] |= c[e] == o
+    assert np.array_equal(h >= 0, won_by_mesh) and (h[~won_by_mesh] == -1).all()
+    assert won_by_mesh.sum() > 100
+    ref = oracle_lib.contact_mesh_backward(mesh, scene, ms, g.cpu().numpy().astype(np.float64))
+    _compare_adjoint("mesh pose adjoint from records, small hand 32 envs", (out["records"][0].astype(np.float64),
+                                                                            out["records"][1].astype(np.float64)), ref)
+    # corrupt a third of the mesh-won nodes' records: they drop out, as if their dL/du_hat were 0
+    bad = np.flatnonzero(won_by_mesh.ravel())[::3]
+    h2 = h.ravel().copy()
+    h2[bad[0::2]] = -5
+    h2[bad[1::2]] = 1 << 30
+    g0 = g.cpu().numpy().reshape(3, -1).copy()
+    g0[:, bad] = 0.0
+    gr = torch.empty((32, O, 9), device=dev)
+    gt = torch.empty((32, O, 3), device=dev)
+    _native.etac_contact_mesh_backward(plan, dms, st, g, gr, gt, cobj, to_dev(h2.reshape(32, N)))
+    gr0 = torch.empty((32, O, 9), device=dev)
+    gt0 = torch.empty((32, O, 3), device=dev)
+    _native.etac_contact_mesh_backward(plan, dms, st, to_dev(g0.reshape(3, 32, N)), gr0, gt0, cobj, hit)
+    torch.cuda.synchronize()
+    assert np.array_equal(gr.cpu().numpy(), gr0.cpu().numpy()) and np.array_equal(gt.cpu().numpy(), gt0.cpu().numpy())
