@@ -5,7 +5,8 @@ returns (u [3][E][N], contact_obj [E][N], n_active [E][K]); gradients flow to
 rot [E][O][9], trans [E][O][3], alpha [K] and phi [17411].  The forward runs
 etac_step, the backward runs etac_step_backward, which recomputes the contact
 pass; besides the inputs only the network's pooling record (pooled features
-and their arg-max nodes, 512 bytes per (env, patch) item) is saved.  Argument
+and their arg-max nodes, 512 bytes per (env, patch) item) is saved.
+ETacMeshStep does the same for scenes with triangle-mesh objects.  Argument
 marshalling only.
 """
 import torch
@@ -49,6 +50,56 @@ class ETacStep(torch.autograd.Function):
 
 def etac_step(plan, n_obj, type_, shape, rot, trans, alpha, phi, mode=_native.ETAC_FULL):
     return ETacStep.apply(plan, n_obj, type_, shape, rot, trans, alpha, phi, mode)
+
+
+class ETacMeshStep(torch.autograd.Function):
+    """The step with triangle-mesh objects (and primitives) in the scene:
+    etac_contact_mesh then etac_propagate forward; etac_propagate_backward
+    then etac_contact_mesh_backward (reading the forward's contact_obj and
+    winning-triangle records) backward.  Saved: contact_obj, u_hat, the hit
+    record and the pooling record.  The plan needs ETAC_PLAN_BACKWARD."""
+
+    @staticmethod
+    def forward(ctx, plan, meshset, n_obj, type_, shape, rot, trans, alpha, phi, mode):
+        rot, trans = rot.contiguous(), trans.contiguous()
+        alpha, phi = alpha.contiguous(), phi.contiguous()
+        sc = plan.scene_struct(n_obj, type_, shape, rot, trans)
+        md = plan.model_struct(mode, alpha, phi)
+        E = int(type_.shape[0])
+        dev = rot.device
+        cobj = torch.empty((E, plan.N), dtype=torch.int8, device=dev)
+        uhat = torch.empty((3, E, plan.N), dtype=torch.float32, device=dev)
+        na = torch.empty((E, plan.K), dtype=torch.int32, device=dev)
+        hit = torch.empty((E, plan.N), dtype=torch.int32, device=dev)
+        u = torch.empty((3, E, plan.N), dtype=torch.float32, device=dev)
+        saved = _native.saved_buffer(plan, E)
+        _native.etac_contact_mesh(plan, meshset, sc, cobj, uhat, na, hit)
+        _native.etac_propagate(plan, md, E, cobj, uhat, u, saved=saved)
+        ctx.plan, ctx.meshset, ctx.mode = plan, meshset, int(mode)
+        ctx.save_for_backward(n_obj, type_, shape, rot, trans, alpha, phi, cobj, uhat, hit, saved)
+        ctx.mark_non_differentiable(cobj, na)
+        return u, cobj, na
+
+    @staticmethod
+    def backward(ctx, grad_u, _grad_cobj, _grad_na):
+        n_obj, type_, shape, rot, trans, alpha, phi, cobj, uhat, hit, saved = ctx.saved_tensors
+        plan = ctx.plan
+        sc = plan.scene_struct(n_obj, type_, shape, rot, trans)
+        md = plan.model_struct(ctx.mode, alpha, phi)
+        E = int(type_.shape[0])
+        gu = grad_u.to(torch.float32).contiguous()
+        guhat = torch.empty_like(uhat)
+        gal = torch.empty_like(alpha)
+        gph = torch.empty_like(phi)
+        _native.etac_propagate_backward(plan, md, E, cobj, uhat, gu, guhat, gal, gph, saved=saved)
+        grot = torch.empty_like(rot)
+        gtr = torch.empty_like(trans)
+        _native.etac_contact_mesh_backward(plan, ctx.meshset, sc, guhat, grot, gtr, cobj, hit)
+        return None, None, None, None, None, grot, gtr, gal, gph, None
+
+
+def etac_mesh_step(plan, meshset, n_obj, type_, shape, rot, trans, alpha, phi, mode=_native.ETAC_FULL):
+    return ETacMeshStep.apply(plan, meshset, n_obj, type_, shape, rot, trans, alpha, phi, mode)
 
 
 def rotation_from_axis_angle(w):

@@ -280,3 +280,38 @@ def test_mesh_adjoint_from_forward_records(oracle_lib):
     _native.etac_contact_mesh_backward(plan, dms, st, to_dev(g0.reshape(3, 32, N)), gr0, gt0, cobj, hit)
     torch.cuda.synchronize()
     assert np.array_equal(gr.cpu().numpy(), gr0.cpu().numpy()) and np.array_equal(gt.cpu().numpy(), gt0.cpu().numpy())
+
+
+def test_mesh_step_autograd_against_oracle(oracle_lib):
+    # ETacMeshStep: gradients of L = sum(w * U) with respect to the poses and
+    # alpha against the oracle's propagation adjoint composed with its
+    # mesh-contact adjoint (decay-only model: no network decisions near
+    # margins; the network's adjoint is covered by the propagation tests)
+    from paper_2604_20295_amd import _native
+    from paper_2604_20295_amd.autograd import etac_mesh_step
+    from scenes import MODE_DECAY_ONLY
+    torch, dev = torch_dev()
+    mesh = scenes.hand_mesh(0, sizes=SMALL["sizes"])
+    ms, scene = _mixed(mesh, 24, 31, p_mesh=0.7, scale=SMALL["scale"])
+    model = scenes.draw_model(np.random.default_rng([0, 1]), mesh.pitch, MODE_DECAY_ONLY)
+    plan = make_plan(mesh, 24, 3, backward=True)
+    dms = _native.MeshSet.from_set(ms)
+    ds, dm = DevScene(scene), DevModel(model)
+    rot = ds.rot.clone().requires_grad_(True)
+    trans = ds.trans.clone().requires_grad_(True)
+    alpha = dm.alpha.clone().requires_grad_(True)
+    u, cobj, na = etac_mesh_step(plan, dms, ds.n_obj, ds.type, ds.shape, rot, trans, alpha, dm.phi, MODE_DECAY_ONLY)
+    w = np.random.default_rng(6).standard_normal((3, 24, plan.N)).astype(np.float32)
+    (u * to_dev(w)).sum().backward()
+    torch.cuda.synchronize()
+    rc, ru, _ = oracle_lib.contact_mesh(mesh, scene, ms)
+    assert np.array_equal(cobj.cpu().numpy(), rc)
+    ref_u = oracle_lib.propagate(mesh, model, rc, ru)
+    assert max_err(u.detach().cpu().numpy(), ref_u) <= TOL_U
+    pb = oracle_lib.propagate_backward(mesh, model, rc, ru, w.astype(np.float64))
+    cb = oracle_lib.contact_mesh_backward(mesh, scene, ms, pb["grad_uhat"])
+    from tests.test_gpu_backward import _close
+    log("[gpu] mesh step autograd (decay-only), 24 envs")
+    _close(alpha.grad.cpu().numpy(), pb["grad_alpha"], "grad_alpha")
+    _close(trans.grad.cpu().numpy(), cb["grad_trans"], "grad_trans")
+    _close(rot.grad.cpu().numpy(), cb["grad_rot"], "grad_rot")
