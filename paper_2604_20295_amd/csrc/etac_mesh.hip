@@ -347,10 +347,11 @@ __device__ __forceinline__ unsigned cull_mesh_objects(const MeshContactParams &p
 }
 
 // Four waves per SIMD (at most 128 registers): the queries are latency-bound.
-// ADJ: the adjoint (contact recomputed; every node's pose gradient added to
-// its winning object's sums: per wave in a fixed order, then over the waves
-// in wave order, so results do not depend on timing).
-template <bool ADJ>
+// ADJ: the adjoint (every node's pose gradient added to its winning object's
+// sums: per wave in a fixed order, then over the waves in wave order, so
+// results do not depend on timing), with contact recomputed or, REC, read
+// from the forward's records.
+template <bool ADJ, bool REC>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_contact_mesh(MeshContactParams p) {
     __shared__ int cnt[kMaxPatches];
     __shared__ uint8_t cand[kMaxPatches];
@@ -380,7 +381,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         const float pz = valid ? M.pos[2 * N + i] : 0.0f;
         int best = -1, btri = -1;   // btri: winning triangle when a mesh wins
         double bd = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
-        if (ADJ && p.hit_in) {
+        if (REC) {
             // the forward's records; values that cannot come from it are skipped
             if (valid && c != 0u) {
                 const int o = p.cobj_in[row + i];
@@ -526,7 +527,7 @@ hipError_t launch_contact_mesh(const Plan &p, const MeshSetDev &ms, const SceneD
                                int32_t *n_active, int32_t *hit, hipStream_t st) {
     if (s.E == 0) return hipSuccess;
     MeshContactParams cp{p.mesh, s, ms, cobj, uhat, n_active, hit, nullptr, nullptr, nullptr, nullptr, nullptr};
-    hipLaunchKernelGGL(k_contact_mesh<false>, dim3(s.E), dim3(kWG), 0, st, cp);
+    hipLaunchKernelGGL((k_contact_mesh<false, false>), dim3(s.E), dim3(kWG), 0, st, cp);
     return hipGetLastError();
 }
 
@@ -536,7 +537,8 @@ hipError_t launch_contact_mesh_backward(const Plan &p, const MeshSetDev &ms, con
     if (s.E == 0) return hipSuccess;
     MeshContactParams cp{p.mesh, s, ms, nullptr, nullptr, nullptr, nullptr, grad_uhat, grad_rot, grad_trans,
                          hit ? cobj : nullptr, cobj ? hit : nullptr};
-    hipLaunchKernelGGL(k_contact_mesh<true>, dim3(s.E), dim3(kWG), 0, st, cp);
+    if (cp.hit_in) hipLaunchKernelGGL((k_contact_mesh<true, true>), dim3(s.E), dim3(kWG), 0, st, cp);
+    else hipLaunchKernelGGL((k_contact_mesh<true, false>), dim3(s.E), dim3(kWG), 0, st, cp);
     return hipGetLastError();
 }
 
