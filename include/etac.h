@@ -187,8 +187,9 @@ etac_status etac_step(etac_plan *plan, const etac_scene *scene, const etac_model
  * Limits: 1 <= n_meshes <= 65536, 4 <= triangles per mesh, T <= 2^24.
  * All pointers HOST, read during the call.  The set computes the
  * angle-weighted pseudo-normals of every face, edge and vertex in FP64,
- * groups each mesh's triangles into clusters of 32 with bounding
- * balls, and uploads everything to the current device (synchronous; not
+ * groups each mesh's triangles into clusters of 32 with oriented bounding
+ * boxes, classifies the cells of a grid over each mesh as certainly outside
+ * or not, and uploads everything to the current device (synchronous; not
  * during stream capture: ETAC_ERR_CAPTURE).  *out is set only on success. */
 typedef struct etac_meshset etac_meshset;
 etac_status etac_meshset_create(int32_t n_meshes, const int32_t *tri_offset, int32_t n_verts,

@@ -143,7 +143,7 @@ struct MeshSetDev {
     const float *corner;     // [9][T] a.x a.y a.z b.x b.y b.z c.x c.y c.z per triangle
     const int *orig;         // [T] index of the triangle within its mesh, as given
     const double *pn;        // [T][7][3] pseudo-normals: face, edges ab bc ca, vertices a b c
-    const double4 *ball;     // [C] cluster bounding ball: centre, radius (with margin)
+    const double *box;       // [C][16] cluster bounding box: centre, three unit axes, half extents (with margin)
     // occupancy grid per mesh over its bounding box: bit (i, j, k) is clear
     // when every point of that cell is certainly outside the mesh
     const float4 *grid_lo;   // [M] box corner (object frame), 1 / cell size

@@ -22,9 +22,10 @@
 // runs in FP64 in a fixed operation order without contraction into FMA, the
 // divisions and square roots correctly rounded, so the inside set and the
 // deepest-object choice are reproducible bit for bit.  Cluster skipping
-// never changes the result: a cluster ball's radius carries a margin of
-// 1e-6 mm, far above the rounding of the distances compared, so a skipped
-// cluster's triangles are strictly farther than the best one.
+// never changes the result: a cluster's oriented bounding box carries a
+// margin of 1e-6 mm on every half extent, far above the rounding of the
+// distances compared, so a skipped cluster's triangles are strictly farther
+// than the best one.
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -172,12 +173,17 @@ __device__ Pen mesh_query(const MeshSetDev &ms, int mesh, double q0, double q1, 
     const int half = lane >> 5;
     for (int cb = mr.z; cb < mr.w; cb += 64) {
         const int c = cb + lane;
-        double lb = kInf;   // squared lower bound of the distance to cluster c
+        double lb = kInf;   // squared distance to cluster c's box: a lower bound for its triangles
         if (c < mr.w) {
-            const double4 b = ms.ball[c];
-            const double dx = q0 - b.x, dy = q1 - b.y, dz = q2 - b.z;
-            const double l = sqrt((dx * dx + dy * dy) + dz * dz) - b.w;
-            lb = l > 0.0 ? l * l : 0.0;
+            const double *b = ms.box + 16 * (size_t)c;
+            const double dx = q0 - b[0], dy = q1 - b[1], dz = q2 - b[2];
+            double e0 = fabs((dx * b[3] + dy * b[4]) + dz * b[5]) - b[12];
+            double e1 = fabs((dx * b[6] + dy * b[7]) + dz * b[8]) - b[13];
+            double e2 = fabs((dx * b[9] + dy * b[10]) + dz * b[11]) - b[14];
+            e0 = e0 > 0.0 ? e0 : 0.0;
+            e1 = e1 > 0.0 ? e1 : 0.0;
+            e2 = e2 > 0.0 ? e2 : 0.0;
+            lb = (e0 * e0 + e1 * e1) + e2 * e2;
         }
         // first the two clusters of least bound, then, two at a time, every
         // cluster whose bound does not exceed the best distance so far
@@ -709,7 +715,8 @@ etac_status etac_meshset_create(int32_t n_meshes, const int32_t *tri_offset, int
     std::vector<float> corner((size_t)9 * T);
     std::vector<int> orig(T);
     std::vector<double> pn((size_t)21 * T);
-    std::vector<double4> ball;
+    std::vector<double4> ball;   // cluster balls, for the host-side grid classification
+    std::vector<double> box;     // [C][16] cluster boxes: centre, three axes, half extents (with margin)
     std::vector<int4> mesh(n_meshes);
     std::vector<float> radius(n_meshes);
     std::vector<float4> grid_lo(n_meshes);
@@ -787,6 +794,63 @@ etac_status etac_meshset_create(int32_t n_meshes, const int32_t *tri_offset, int
                 }
             const double scale = std::sqrt(dot(cc, cc)) + r;
             ball.push_back(make_double4(cc.x, cc.y, cc.z, r + 1e-6 + 1e-12 * scale));
+            // oriented box: one axis along the area-weighted mean normal (thin
+            // for a surface patch), one towards the farthest vertex in the
+            // plane across it, the third their cross product
+            V3 nsum{0.0, 0.0, 0.0};
+            for (int i = lo; i < hi; ++i) {
+                const int f = bm.order[i];
+                const V3 a = vtx(tv[3 * f]), b = vtx(tv[3 * f + 1]), c = vtx(tv[3 * f + 2]);
+                const V3 ab = sub(b, a), ac = sub(c, a);
+                nsum = V3{nsum.x + (ab.y * ac.z - ab.z * ac.y), nsum.y + (ab.z * ac.x - ab.x * ac.z),
+                          nsum.z + (ab.x * ac.y - ab.y * ac.x)};
+            }
+            auto unit = [](V3 v, V3 fallback) {
+                const double l = std::sqrt(dot(v, v));
+                return l > 1e-12 ? V3{v.x / l, v.y / l, v.z / l} : fallback;
+            };
+            const V3 ax0 = unit(nsum, V3{0.0, 0.0, 1.0});
+            V3 far{0.0, 0.0, 0.0};
+            double fl = -1.0;
+            for (int i = lo; i < hi; ++i)
+                for (int k = 0; k < 3; ++k) {
+                    const V3 d = sub(vtx(tv[3 * bm.order[i] + k]), cc);
+                    const double dn = dot(d, ax0);
+                    const V3 u{d.x - dn * ax0.x, d.y - dn * ax0.y, d.z - dn * ax0.z};
+                    if (dot(u, u) > fl) { fl = dot(u, u); far = u; }
+                }
+            const V3 any = std::fabs(ax0.x) < 0.9 ? V3{1.0, 0.0, 0.0} : V3{0.0, 1.0, 0.0};
+            const V3 anyp{any.y * ax0.z - any.z * ax0.y, any.z * ax0.x - any.x * ax0.z, any.x * ax0.y - any.y * ax0.x};
+            V3 ax1 = unit(far, unit(anyp, V3{0.0, 1.0, 0.0}));
+            const double p1 = dot(ax1, ax0);   // re-orthogonalise against rounding
+            ax1 = unit(V3{ax1.x - p1 * ax0.x, ax1.y - p1 * ax0.y, ax1.z - p1 * ax0.z}, ax1);
+            const V3 ax2 = unit(V3{ax0.y * ax1.z - ax0.z * ax1.y, ax0.z * ax1.x - ax0.x * ax1.z,
+                                   ax0.x * ax1.y - ax0.y * ax1.x}, V3{0.0, 0.0, 1.0});
+            const V3 ax[3] = {ax0, ax1, ax2};
+            double lo_k[3] = {INFINITY, INFINITY, INFINITY}, hi_k[3] = {-INFINITY, -INFINITY, -INFINITY};
+            for (int i = lo; i < hi; ++i)
+                for (int k = 0; k < 3; ++k) {
+                    const V3 d = sub(vtx(tv[3 * bm.order[i] + k]), cc);
+                    for (int j = 0; j < 3; ++j) {
+                        lo_k[j] = std::min(lo_k[j], dot(d, ax[j]));
+                        hi_k[j] = std::max(hi_k[j], dot(d, ax[j]));
+                    }
+                }
+            V3 bc = cc;
+            for (int j = 0; j < 3; ++j) {
+                const double mid = (lo_k[j] + hi_k[j]) / 2.0;
+                bc = V3{bc.x + mid * ax[j].x, bc.y + mid * ax[j].y, bc.z + mid * ax[j].z};
+            }
+            double half[3] = {0.0, 0.0, 0.0};
+            for (int i = lo; i < hi; ++i)
+                for (int k = 0; k < 3; ++k) {
+                    const V3 d = sub(vtx(tv[3 * bm.order[i] + k]), bc);
+                    for (int j = 0; j < 3; ++j) half[j] = std::max(half[j], std::fabs(dot(d, ax[j])));
+                }
+            const double bx[16] = {bc.x, bc.y, bc.z, ax0.x, ax0.y, ax0.z, ax1.x, ax1.y, ax1.z, ax2.x, ax2.y, ax2.z,
+                                   half[0] + 1e-6 + 1e-12 * scale, half[1] + 1e-6 + 1e-12 * scale,
+                                   half[2] + 1e-6 + 1e-12 * scale, 0.0};
+            box.insert(box.end(), bx, bx + 16);
         }
         for (int i = 0; i < nt; ++i) {
             const int f = bm.order[i], slot = t0 + i;
@@ -836,11 +900,11 @@ etac_status etac_meshset_create(int32_t n_meshes, const int32_t *tri_offset, int
     };
     void *p[9];
     hipError_t e = hipSuccess;
-    const void *src[9] = {mesh.data(), radius.data(), corner.data(), orig.data(), pn.data(), ball.data(),
+    const void *src[9] = {mesh.data(), radius.data(), corner.data(), orig.data(), pn.data(), box.data(),
                           grid_lo.data(), grid_dim.data(), grid_bits.data()};
     const size_t bytes[9] = {mesh.size() * sizeof(int4), radius.size() * sizeof(float),
                              corner.size() * sizeof(float), orig.size() * sizeof(int), pn.size() * sizeof(double),
-                             ball.size() * sizeof(double4), grid_lo.size() * sizeof(float4),
+                             box.size() * sizeof(double), grid_lo.size() * sizeof(float4),
                              grid_dim.size() * sizeof(int4), grid_bits.size() * sizeof(unsigned)};
     for (int i = 0; i < 9 && e == hipSuccess; ++i) e = upload(src[i], bytes[i], &p[i]);
     if (e != hipSuccess) {
@@ -848,7 +912,7 @@ etac_status etac_meshset_create(int32_t n_meshes, const int32_t *tri_offset, int
         return ETAC_ERR_HIP;
     }
     ms->d = MeshSetDev{(const int4 *)p[0], (const float *)p[1], (const float *)p[2], (const int *)p[3],
-                       (const double *)p[4], (const double4 *)p[5], (const float4 *)p[6], (const int4 *)p[7],
+                       (const double *)p[4], (const double *)p[5], (const float4 *)p[6], (const int4 *)p[7],
                        (const unsigned *)p[8], n_meshes, T, (int)ball.size()};
     *out = ms;
     return ETAC_OK;
