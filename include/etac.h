@@ -184,7 +184,7 @@ etac_status etac_step(etac_plan *plan, const etac_scene *scene, const etac_model
  * counter-clockwise seen from outside.  Every mesh must be closed and
  * consistently oriented (each directed edge used once, its reverse once by
  * another triangle), with no zero-area triangle: otherwise ETAC_ERR_VALUE.
- * Limits: 1 <= n_meshes <= 65536, 4 <= triangles per mesh, T <= 2^24.
+ * Limits: 1 <= n_meshes <= 4096, 4 <= triangles per mesh, T <= 2^24.
  * All pointers HOST, read during the call.  The set computes the
  * angle-weighted pseudo-normals of every face, edge and vertex in FP64,
  * groups each mesh's triangles into clusters of 32 with oriented bounding

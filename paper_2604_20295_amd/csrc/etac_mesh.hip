@@ -700,7 +700,8 @@ etac_status etac_meshset_create(int32_t n_meshes, const int32_t *tri_offset, int
                                 const int32_t *tris, etac_meshset **out) {
     using namespace etac;
     if (!tri_offset || !verts || !tris || !out) return ETAC_ERR_NULL;
-    if (n_meshes < 1 || n_meshes > 65536 || n_verts < 3) return ETAC_ERR_SHAPE;
+    // at most 4096 meshes: their occupancy grids (at most 41^3 cells each) keep 32-bit bit offsets
+    if (n_meshes < 1 || n_meshes > 4096 || n_verts < 3) return ETAC_ERR_SHAPE;
     if (tri_offset[0] != 0) return ETAC_ERR_SHAPE;
     for (int m = 0; m < n_meshes; ++m)
         if (tri_offset[m + 1] - tri_offset[m] < 4) return ETAC_ERR_SHAPE;

@@ -127,6 +127,7 @@ def test_meshset_validation_without_gpu():
 
     assert lib.etac_meshset_create(1, None, 3, None, None, None) == -1
     assert create(v, t, off, M=0) == -2
+    assert create(v, t, off, M=4097) == -2                                     # more meshes than the grids allow
     assert create(v, t, np.array([1, 12], np.int32)) == -2                    # offsets must start at 0
     assert create(v, t[:3], np.array([0, 3], np.int32)) == -2                 # fewer than 4 triangles
     bad = t.copy(); bad[0, 0] = v.shape[0]
