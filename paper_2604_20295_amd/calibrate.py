@@ -37,6 +37,18 @@ def gpu_step_fn(plan, n_obj, type_, shape, rot, trans, mode):
     return step
 
 
+def gpu_mesh_step_fn(plan, meshset, n_obj, type_, shape, rot, trans, mode):
+    """(alpha, phi) -> (U, contact_obj) through the library for scenes with
+    triangle-mesh objects (autograd.ETacMeshStep), differentiable in alpha
+    and phi."""
+    from .autograd import ETacMeshStep
+
+    def step(alpha, phi):
+        u, cobj, _ = ETacMeshStep.apply(plan, meshset, n_obj, type_, shape, rot, trans, alpha, phi, mode)
+        return u, cobj
+    return step
+
+
 class Calibrator:
     """Adam on (log alpha, phi) for the Eq. 3 loss of one fixed batch of
     scenes, learning rates multiplied by `lr_decay` after every step.

@@ -80,3 +80,37 @@ def test_calibration_full_model_reduces_loss(oracle_lib):
     log(f"[gpu] calibration full model: loss {hist[0]:.4e} -> {hist[-1]:.4e}")
     assert all(np.isfinite(hist))
     assert hist[-1] < 0.5 * hist[0]
+
+
+def test_calibration_with_mesh_objects_recovers_decay_rate(oracle_lib):
+    # the loop on a small hand pressed by triangle-mesh objects (and
+    # primitives), through ETacMeshStep: a teacher's alpha is recovered
+    import torch
+    from paper_2604_20295_amd import _native
+    from paper_2604_20295_amd.calibrate import Calibrator, gpu_mesh_step_fn
+    from scenes import trimeshes as tm
+    mesh = scenes.hand_mesh(0, sizes=SMALL["sizes"])
+    ms = tm.object_set(scale=SMALL["scale"])
+    scene = tm.hand_mesh_scene(mesh, ms, 48, seed=6, p_mesh=0.8, scale=SMALL["scale"])
+    model = scenes.draw_model(np.random.default_rng([0, 1]), mesh.pitch, MODE_DECAY_ONLY)
+    ds, dm = DevScene(scene), DevModel(model)
+    plan = make_plan(mesh, 48, 3, backward=True)
+    dms = _native.MeshSet.from_set(ms)
+    fn = gpu_mesh_step_fn(plan, dms, ds.n_obj, ds.type, ds.shape, ds.rot, ds.trans, MODE_DECAY_ONLY)
+    with torch.no_grad():
+        target, cobj = fn(dm.alpha, dm.phi)
+        target = target.clone()
+    # patches some object touches in the batch: only their alpha gets a gradient
+    act = (cobj >= 0).any(0).cpu().numpy()
+    touched = np.array([act[a:b].any() for a, b in zip(mesh.patch_offset[:-1], mesh.patch_offset[1:])])
+    assert touched.sum() >= 8
+    cal = Calibrator(fn, target, dm.alpha * 1.3, dm.phi, lr_alpha=0.05, fit_phi=False, lr_decay=0.95)
+    l0 = cal.loss()
+    for _ in range(120):
+        cal.step()
+    torch.cuda.synchronize()
+    rel = float(torch.max((torch.abs(cal.alpha - dm.alpha) / dm.alpha)[torch.from_numpy(touched).to(dm.alpha.device)]))
+    log(f"[gpu] calibration with mesh objects: loss {l0:.3e} -> {cal.loss():.3e}, alpha max rel err {rel:.2e} "
+        f"over the {int(touched.sum())} touched patches")
+    assert cal.loss() < 1e-2 * l0
+    assert rel < 1e-2
