@@ -315,3 +315,54 @@ def test_mesh_step_autograd_against_oracle(oracle_lib):
     _close(alpha.grad.cpu().numpy(), pb["grad_alpha"], "grad_alpha")
     _close(trans.grad.cpu().numpy(), cb["grad_trans"], "grad_trans")
     _close(rot.grad.cpu().numpy(), cb["grad_rot"], "grad_rot")
+
+
+def test_mesh_contact_eight_objects_and_largest_patch(oracle_lib):
+    # ETAC_MAX_OBJ objects per env, meshes and primitives mixed, and one patch
+    # of ETAC_MAX_PATCH_NODES nodes; contact and the adjoint from records
+    from paper_2604_20295_amd import _native
+    from tests.test_gpu_edges import _largest_patch_mesh
+    torch, dev = torch_dev()
+    mesh = _largest_patch_mesh()
+    ms = tm.object_set(scale=0.2)
+    E = 3
+    scene = scenes._empty_scene(E, 8)
+    rng = np.random.default_rng(12)
+    for e in range(E):
+        scene.n_obj[e] = 8
+        for o in range(8):
+            R = scenes.random_rotation(rng)
+            if o % 3 == 2:
+                ptype, shape, R = scenes.draw_primitive(rng, 0.15)
+                scene.type[e, o] = ptype
+                scene.shape[e, o] = shape
+                h = scenes.support_extent(ptype, shape, R, np.array([0.0, 0.0, 1.0]))
+            else:
+                m = int(rng.integers(0, 4))
+                scene.type[e, o] = tm.MESH
+                scene.shape[e, o] = (float(m), 0, 0, 0)
+                h = ms.support_extent(m, R, np.array([0.0, 0.0, -1.0]))
+            scene.rot[e, o] = R.ravel()
+            scene.trans[e, o] = (rng.uniform(-12, 12), rng.uniform(-12, 12), h - rng.uniform(0.3, 2.0))
+    plan = make_plan(mesh, E, 8)
+    dms = _native.MeshSet.from_set(ms)
+    ds = DevScene(scene)
+    st = ds.struct(plan)
+    N, K = plan.N, plan.K
+    cobj = torch.empty((E, N), dtype=torch.int8, device=dev)
+    uhat = torch.empty((3, E, N), device=dev)
+    na = torch.empty((E, K), dtype=torch.int32, device=dev)
+    hit = torch.empty((E, N), dtype=torch.int32, device=dev)
+    _native.etac_contact_mesh(plan, dms, st, cobj, uhat, na, hit)
+    g = np.random.default_rng(2).standard_normal((3, E, N)).astype(np.float32)
+    gr = torch.empty((E, 8, 9), device=dev)
+    gt = torch.empty((E, 8, 3), device=dev)
+    _native.etac_contact_mesh_backward(plan, dms, st, to_dev(g), gr, gt, cobj, hit)
+    torch.cuda.synchronize()
+    ref = oracle_lib.contact_mesh(mesh, scene, ms)
+    _compare("mesh contact, 8 objects per env on a 65536-node patch",
+             (cobj.cpu().numpy(), uhat.cpu().numpy().astype(np.float64), na.cpu().numpy()), ref)
+    assert len(np.unique(ref[0][ref[0] >= 0])) >= 6
+    _compare_adjoint("mesh pose adjoint, 8 objects per env on a 65536-node patch",
+                     (gr.cpu().numpy().astype(np.float64), gt.cpu().numpy().astype(np.float64)),
+                     oracle_lib.contact_mesh_backward(mesh, scene, ms, g.astype(np.float64)))
