@@ -696,8 +696,8 @@ void build_grid(const HostMesh &hm, V3 lo, V3 hi, float4 &glo, int4 &gdim, std::
 
 extern "C" {
 
-etac_status etac_meshset_create(int32_t n_meshes, const int32_t *tri_offset, int32_t n_verts, const float *verts,
-                                const int32_t *tris, etac_meshset **out) {
+static etac_status meshset_create(int32_t n_meshes, const int32_t *tri_offset, int32_t n_verts, const float *verts,
+                                  const int32_t *tris, etac_meshset **out) {
     using namespace etac;
     if (!tri_offset || !verts || !tris || !out) return ETAC_ERR_NULL;
     // at most 4096 meshes: their occupancy grids (at most 41^3 cells each) keep 32-bit bit offsets
@@ -917,6 +917,15 @@ etac_status etac_meshset_create(int32_t n_meshes, const int32_t *tri_offset, int
                        (const unsigned *)p[8], n_meshes, T, (int)ball.size()};
     *out = ms;
     return ETAC_OK;
+}
+
+etac_status etac_meshset_create(int32_t n_meshes, const int32_t *tri_offset, int32_t n_verts, const float *verts,
+                                const int32_t *tris, etac_meshset **out) {
+    try {   // host containers and worker threads may throw; no exception crosses the C ABI
+        return meshset_create(n_meshes, tri_offset, n_verts, verts, tris, out);
+    } catch (...) {
+        return ETAC_ERR_HIP;
+    }
 }
 
 etac_status etac_meshset_destroy(etac_meshset *ms) {
