@@ -366,3 +366,31 @@ def test_mesh_contact_eight_objects_and_largest_patch(oracle_lib):
     _compare_adjoint("mesh pose adjoint, 8 objects per env on a 65536-node patch",
                      (gr.cpu().numpy().astype(np.float64), gt.cpu().numpy().astype(np.float64)),
                      oracle_lib.contact_mesh_backward(mesh, scene, ms, g.astype(np.float64)))
+
+
+def test_mesh_contact_ties_and_surface_points(oracle_lib):
+    # nodes exactly on a cube's vertices, edge midpoints and face centres
+    # (passive), and inside nodes on its diagonal planes |x| = |y| etc., where
+    # two faces are exactly equidistant (the lowest triangle index wins):
+    # masks and u_hat must match the oracle bit for bit
+    from paper_2604_20295_amd import _native
+    from tests.test_oracle_contact import points_mesh
+    from tests.test_oracle_mesh import corners, mesh_scene
+    ms = tm.merge([tm.cube_mesh(half=4.0, n=2)], ("cube",))
+    V = corners(ms, 0)
+    surf = np.concatenate([V[:, 0], (V[:, 0] + V[:, 1]) / 2, V.mean(1)])
+    g = np.array([-3.5, -2.0, -1.0, -0.25, 0.0, 0.25, 1.0, 2.0, 3.5])
+    diag = np.array([[a, a * s, b] for a in g for s in (1, -1) for b in g] +
+                    [[a, b, a * s] for a in g for s in (1, -1) for b in g] +
+                    [[b, a, a * s] for a in g for s in (1, -1) for b in g])
+    pts = np.concatenate([surf, diag]).astype(np.float32)
+    mesh = points_mesh(pts.T)
+    scene = mesh_scene([(0, np.eye(3), (0.0, 0.0, 0.0))])
+    plan = make_plan(mesh, 1, 1)
+    dms = _native.MeshSet.from_set(ms)
+    cobj, uhat, na = gpu_contact_mesh(plan, dms, scene)
+    rc, ru, rn = oracle_lib.contact_mesh(mesh, scene, ms)
+    assert (rc[0, :len(surf)] == -1).all()
+    assert np.array_equal(cobj, rc) and np.array_equal(na, rn)
+    assert np.array_equal(uhat.astype(np.float32), ru.astype(np.float32))
+    assert (rc >= 0).sum() > 200
