@@ -169,7 +169,8 @@ __device__ Pen mesh_query(const MeshSetDev &ms, int mesh, double q0, double q1, 
     const int4 mr = ms.mesh[mesh];
     const double kInf = __builtin_inf();
     double best_s = kInf;
-    int best_o = 0x7fffffff, best_t = -1;
+    int best_o = 0x7fffffff, best_t = -1, best_f = 0;
+    double bx0 = 0.0, bx1 = 0.0, bx2 = 0.0;   // the winning closest point, read from its lane
     const int half = lane >> 5;
     for (int cb = mr.z; cb < mr.w; cb += 64) {
         const int c = cb + lane;
@@ -206,9 +207,9 @@ __device__ Pen mesh_query(const MeshSetDev &ms, int mesh, double q0, double q1, 
                 const int tt = mr.x + kCluster * (cb + mine - mr.z) + (lane & 31);
                 if (tt < mr.y) t = tt;
             }
+            double x0 = 0.0, x1 = 0.0, x2 = 0.0;
+            int f = 0;
             if (t >= 0) {
-                double x0, x1, x2;
-                int f;
                 s = closest_tri(q0, q1, q2, load_tri(ms, t), x0, x1, x2, f);
                 o = ms.orig[t];
             }
@@ -222,9 +223,14 @@ __device__ Pen mesh_query(const MeshSetDev &ms, int mesh, double q0, double q1, 
                 at = __ballot(s == sm && o == om);
             }
             if (sm < best_s || (sm == best_s && om < best_o)) {
+                const int wl = __ffsll(at) - 1;
                 best_s = sm;
                 best_o = om;
-                best_t = __builtin_amdgcn_readlane(t, __ffsll(at) - 1);
+                best_t = __builtin_amdgcn_readlane(t, wl);
+                best_f = __builtin_amdgcn_readlane(f, wl);
+                bx0 = read_lane(x0, wl);
+                bx1 = read_lane(x1, wl);
+                bx2 = read_lane(x2, wl);
             }
             unsigned long long todo = __ballot(lb <= best_s && lb < kInf);
             ca = __ffsll(todo) - 1;
@@ -238,9 +244,8 @@ __device__ Pen mesh_query(const MeshSetDev &ms, int mesh, double q0, double q1, 
     h.u0 = h.u1 = h.u2 = 0.0;
     tri = best_t;
     if (best_t < 0) return h;
-    double x0, x1, x2;
-    int f;
-    closest_tri(q0, q1, q2, load_tri(ms, best_t), x0, x1, x2, f);   // same inputs, same bits as in the search
+    const double x0 = bx0, x1 = bx1, x2 = bx2;
+    const int f = best_f;
     const double *n = ms.pn + ((size_t)best_t * 7 + f) * 3;
     const double w0 = q0 - x0, w1 = q1 - x1, w2 = q2 - x2;
     if (!((w0 * n[0] + w1 * n[1]) + w2 * n[2] < 0.0)) return h;
