@@ -21,7 +21,9 @@
  *      passive nodes;
  *   4. Eq. 2: U_p = Omega U_a + Phi_p; active nodes keep u_hat.
  * and the reverse-mode adjoint of all of it with respect to object poses
- * (R, t), alpha and the network parameters.
+ * (R, t), alpha and the network parameters.  Objects are primitives
+ * (sphere, box, capsule) or closed triangle meshes (1b below: the exact
+ * triangle SDF with pseudo-normal signs, and its pose adjoint).
  *
  * Readings where the paper is silent (all listed in the design notes):
  *   - contact displacement = closest-point penetration vector; strict inside;
