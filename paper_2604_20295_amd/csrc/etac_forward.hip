@@ -48,11 +48,12 @@ __global__ __launch_bounds__(kWG) void k_contact(ContactParams p) {
                                 M.nrm[2 * N + i], u0, u1, u2);
             if (best >= 0) atomicAdd(&cnt[k], 1);
         }
-        p.cobj[row + i] = (int8_t)best;
+        // results stream out: non-temporal stores keep them from displacing cached inputs
+        __builtin_nontemporal_store((int8_t)best, p.cobj + row + i);
         if (p.uhat) {
-            p.uhat[row + i] = u0;
-            p.uhat[EN + row + i] = u1;
-            p.uhat[2 * EN + row + i] = u2;
+            __builtin_nontemporal_store(u0, p.uhat + row + i);
+            __builtin_nontemporal_store(u1, p.uhat + EN + row + i);
+            __builtin_nontemporal_store(u2, p.uhat + 2 * EN + row + i);
         }
     }
     __syncthreads();
@@ -128,10 +129,10 @@ __device__ __forceinline__ void write_zero_item(const StepParams &p, int e, int 
     const size_t EN = (size_t)p.E * p.mesh.N;
     const size_t row = (size_t)e * p.mesh.N + base;
     for (int i = threadIdx.x; i < n; i += kWG) {
-        p.u[row + i] = 0.0f;
-        p.u[EN + row + i] = 0.0f;
-        p.u[2 * EN + row + i] = 0.0f;
-        if (write_cobj) p.cobj_out[row + i] = -1;
+        __builtin_nontemporal_store(0.0f, p.u + row + i);
+        __builtin_nontemporal_store(0.0f, p.u + EN + row + i);
+        __builtin_nontemporal_store(0.0f, p.u + 2 * EN + row + i);
+        if (write_cobj) __builtin_nontemporal_store((int8_t)-1, p.cobj_out + row + i);
     }
 }
 
@@ -151,10 +152,10 @@ __device__ void zero_fill_batch(const StepParams &p, const ItemBatch &B, int b0)
         const int base = M.offset[k], n = M.offset[k + 1] - base;
         const size_t row = (size_t)e * M.N + base;
         for (int i = lane; i < n; i += 64) {
-            p.u[row + i] = 0.0f;
-            p.u[EN + row + i] = 0.0f;
-            p.u[2 * EN + row + i] = 0.0f;
-            p.cobj_out[row + i] = -1;
+            __builtin_nontemporal_store(0.0f, p.u + row + i);
+            __builtin_nontemporal_store(0.0f, p.u + EN + row + i);
+            __builtin_nontemporal_store(0.0f, p.u + 2 * EN + row + i);
+            __builtin_nontemporal_store((int8_t)-1, p.cobj_out + row + i);
         }
         p.n_active[(size_t)e * M.K + k] = 0;
     }
@@ -398,9 +399,9 @@ __device__ void decay_item(const StepParams &p, StepLds &S, int base, int m, int
                     const int i = ii[a];
                     if (use_res)
                         for (int c = 0; c < 3; ++c) acc[a][c] += (double)resid[c * n_max + i];
-                    p.u[row + i] = (float)acc[a][0];
-                    p.u[EN + row + i] = (float)acc[a][1];
-                    p.u[2 * EN + row + i] = (float)acc[a][2];
+                    __builtin_nontemporal_store((float)acc[a][0], p.u + row + i);
+                    __builtin_nontemporal_store((float)acc[a][1], p.u + EN + row + i);
+                    __builtin_nontemporal_store((float)acc[a][2], p.u + 2 * EN + row + i);
                 }
     }
 }
@@ -443,9 +444,9 @@ __device__ void process_item(const StepParams &p, StepLds &S, int e, int k, unsi
     // active nodes keep their contact displacement
     for (int t = threadIdx.x; t < m; t += kWG) {
         const int i = alist[t];
-        p.u[row + i] = uhn[i];
-        p.u[EN + row + i] = uhn[n_max + i];
-        p.u[2 * EN + row + i] = uhn[2 * n_max + i];
+        __builtin_nontemporal_store(uhn[i], p.u + row + i);
+        __builtin_nontemporal_store(uhn[n_max + i], p.u + EN + row + i);
+        __builtin_nontemporal_store(uhn[2 * n_max + i], p.u + 2 * EN + row + i);
     }
     const bool use_res = mode != ETAC_DECAY_ONLY, use_dec = mode != ETAC_RESIDUAL_ONLY;
     const int np = n - m;
