@@ -1072,7 +1072,8 @@ __device__ __forceinline__ void store_record_chunk(BwdLds &S, const WGrad &G, fl
 #pragma unroll
             for (int r = 0; r < 4; ++r) v[r] += x[r];
         }
-        *reinterpret_cast<floatx4 *>(&rec[(8 * C + j) * 256 + 4 * ln]) = v;
+        // the record streams to HBM for the reduction kernels: non-temporal
+        __builtin_nontemporal_store(v, reinterpret_cast<floatx4 *>(&rec[(8 * C + j) * 256 + 4 * ln]));
     }
 }
 
