@@ -3,10 +3,15 @@
 
 One step = the whole hot path over one batch: the fused contact + propagation
 forward (etac_step) and its adjoint (etac_step_backward, which recomputes
-contact) for every env of the workload.  Workload: 4096 envs of a 16-patch
-hand (7232 surface nodes per env, patch sizes 64..1024) with 1-3 rigid
-primitives per env, FP32 with the FP64 contact predicate; inputs are resident
-in HBM before the timed region.
+contact) for every env of the workload, replayed from one HIP graph.
+Workload: 4096 envs of a 16-patch hand (7232 surface nodes per env, patch
+sizes 64..1024) with 1-3 rigid primitives per env covering 5-30 % of the
+nodes, FP32 with the FP64 contact predicate; inputs are resident in HBM
+before the timed region.  Also reported: an eager pass with per-kernel
+device times and their rooflines, the forward alone, the contact pass alone,
+the high-resolution pads (4096 envs x 4 x 128^2 nodes), the graph-captured
+rollout (16384 envs x 200 steps, p50/p99), the calibration loop, mesh
+objects, and the FP64 oracle on the host's cores.
 
 Prints one JSON line (metric: sensor node-updates/s = envs x nodes / step time).
 """
@@ -24,14 +29,23 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 F16_MFMA_PEAK_TFLOPS = 2500.0  # dense FP16 matrix (the MFMA the network kernels issue)
-FP32_VECTOR_PEAK_TFLOPS = 157.3
 MFMA_PASSES = 3                # split-FP16 products per FP32-equivalent product (hi*hi + hi*lo + lo*hi)
-ENC_MAC, DEC_MAC, GLOBAL_MAC = 9 * 64 + 64 * 64, 64 * 128 + 64 * 3, 2 * 64 * 64
-REC_WORDS = 10564      # floats of an item's parameter-gradient record (dense blocks + rank-one factors)
-PAIR_FLOP = 20                 # decay pair: 3 sub, 5 for the squared distance, sqrt, scale, exp, 6 for w*u
-PAIR_FLOP_BWD = 30             # adjoint pair: the above without u, plus d*w and the g.u_hat dot product
+# network multiply-adds: encoder per node (9 -> 64 -> 64), decoder per passive
+# node (the per-node half of W4, 64 -> 64, and W5, 64 -> 3; the g' half of W4
+# is one vector per item), global MLP per item (W3 and the g' half of W4)
+ENC_MAC, DEC_MAC, GLOBAL_MAC = 9 * 64 + 64 * 64, 64 * 64 + 64 * 3, 2 * 64 * 64
 PHI_SIZE = 17411
-TRANS_PAIR_CEILING = 4.9e12    # pairs/s: two quarter-rate transcendentals per pair (256 CU x 64 lanes x 2.4 GHz / 4 / 2)
+# VALU issue: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz = 39.3e12 lane slots/s
+# (78.6 TFLOP/s of unpacked FP32 FMA; packed FP32 is not used); exp2 and sqrt
+# issue at quarter rate (4 slots).  A decay pair of Eq. 1 takes, in the
+# kernels' inner loops, 10 full-rate operations (3 differences, squared
+# distance in 3, exponent scale, w u in 3) and the two transcendentals: 18
+# slots; an adjoint pair 14 full-rate (w g in 3, the dL/dalpha term in 4) and
+# the two: 22 slots.
+VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+PAIR_SLOTS, PAIR_SLOTS_BWD = 18, 22
+PAIR_CEILING = VALU_SLOTS_PER_S / PAIR_SLOTS          # 2.18e12 pairs/s
+PAIR_CEILING_BWD = VALU_SLOTS_PER_S / PAIR_SLOTS_BWD  # 1.79e12 pairs/s
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -47,12 +61,16 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="time budget of the CPU oracle baseline (envs are added in blocks until it is spent)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--graph", action="store_true", help="replay the step from a captured HIP graph")
+    ap.add_argument("--eager", action="store_true",
+                    help="time the headline steps as eager calls instead of replays of one captured HIP graph")
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in launch shapes")
     ap.add_argument("--launch", type=str, default=None,
                     help="fixed launch shape a,b,c,d,e as in Plan.set_launch (no autotuning), e.g. for profiling")
-    ap.add_argument("--rollout", action="store_true",
-                    help="also run the graph-captured rollout: 16384 envs, 200 steps of smooth object motion")
+    ap.add_argument("--no-rollout", action="store_true",
+                    help="skip the graph-captured rollout (16384 envs, 200 steps of smooth object motion)")
+    ap.add_argument("--no-hires", action="store_true",
+                    help="skip the high-resolution pads (4096 envs x 4 x 128^2 nodes)")
+    ap.add_argument("--hires-steps", type=int, default=3)
     ap.add_argument("--rollout-envs", type=int, default=16384)
     ap.add_argument("--rollout-steps", type=int, default=200)
     ap.add_argument("--calib-steps", type=int, default=30,
@@ -242,7 +260,8 @@ def mesh_contact(args, plan, mesh, model, mode, reps=20):
 
 
 def work_counts(mesh, n_active):
-    """Algorithmic work of one forward given the active counts [E][K]."""
+    """Algorithmic work of one forward given the active counts [E][K], and the
+    distribution of the envs' active fractions."""
     n = mesh.patch_sizes()[None, :].astype(np.float64)
     m = n_active.astype(np.float64)
     hit = m > 0
@@ -251,42 +270,42 @@ def work_counts(mesh, n_active):
     dec_nodes = float(np.sum(np.where(hit, n - m, 0.0)))
     items = float(np.sum(hit))
     mlp_flop = 2.0 * (ENC_MAC * enc_nodes + DEC_MAC * dec_nodes + GLOBAL_MAC * items)
+    frac = m.sum(axis=1) / mesh.n_nodes
+    edges = [0.0, 0.05, 0.10, 0.15, 0.20, 0.25, 0.30, 1.0]
+    dist = {"mean": float(frac.mean()), "median": float(np.median(frac)), "p5": float(np.percentile(frac, 5)),
+            "p95": float(np.percentile(frac, 95)), "in_5_30_pct": float(np.mean((frac >= 0.05) & (frac <= 0.30))),
+            "hist_edges": edges, "hist_envs": [int(x) for x in np.histogram(frac, bins=edges)[0]]}
     return dict(pairs=pairs, mlp_flop=mlp_flop, contacted_items=items, contacted_nodes=enc_nodes,
-                active=float(m.sum()), passive=dec_nodes)
+                active=float(m.sum()), passive=dec_nodes, active_fraction=dist)
 
 
 def algorithmic_work(kernel, counts, E, N, K, O, mode):
     """Algorithmic work of one launch of a kernel: FP32-equivalent network
-    flops (2 per multiply-add), decay-pair flops and the HBM bytes that must
-    move (inputs read once, outputs written once).  The adjoint reads dL/dU
-    only on patches in contact (elsewhere U = 0 whatever the inputs)."""
+    flops (2 per multiply-add), decay pairs of Eq. 1, and the HBM bytes its
+    inputs and outputs must move (each once; the plan's scratch, such as the
+    adjoint's hand-over between its kernels and its per-item gradient
+    records, is not counted).  The adjoint reads dL/dU only on patches in
+    contact (elsewhere U = 0 whatever the inputs)."""
     nodes = float(E) * N
     items = counts["contacted_items"]
     decay = mode != 2     # not residual-only
     net = mode != 1       # not decay-only
     if kernel == "k_contact":
         # contact winner (1 B) and u_hat (12 B) per node, active count per item
-        return dict(mfma_flop=0.0, valu_flop=0.0, hbm_bytes=13.0 * nodes + 4.0 * E * K)
+        return dict(mfma_flop=0.0, pairs=0.0, hbm_bytes=13.0 * nodes + 4.0 * E * K)
     if kernel == "k_step":
-        return dict(mfma_flop=counts["mlp_flop"] if net else 0.0,
-                    valu_flop=PAIR_FLOP * counts["pairs"] if decay else 0.0,
+        return dict(mfma_flop=counts["mlp_flop"] if net else 0.0, pairs=counts["pairs"] if decay else 0.0,
                     hbm_bytes=13.0 * nodes + 4.0 * E * K)
     if kernel == "k_bwd_decay":
-        # dL/dU of contacted patches in; alpha partials, active counts and, for
-        # contacted items, winners (1 B per node) and u_hat, dL/du_hat (24 B per
-        # active node) handed to k_bwd
-        return dict(mfma_flop=0.0, valu_flop=PAIR_FLOP_BWD * counts["pairs"] if decay else 0.0,
-                    hbm_bytes=12.0 * counts["contacted_nodes"] + 8.0 * E * K
-                    + counts["contacted_nodes"] + 24.0 * counts["active"])
-    # k_bwd, given the forward's pooling record: on the passive nodes of
-    # contacted patches the network's forward is recomputed (encoder and
-    # decoder) and both adjoint products run, 3x those forward flops; the
-    # global MLP likewise per item.  Reads the pooling record (512 B per item)
-    # and writes the item's parameter-gradient record (REC_WORDS floats).
+        # dL/dU of contacted patches in, dL/dalpha partial per item out
+        return dict(mfma_flop=0.0, pairs=counts["pairs"] if decay else 0.0,
+                    hbm_bytes=12.0 * counts["contacted_nodes"] + 4.0 * E * K)
+    # k_bwd: on the passive nodes of contacted patches the network's forward
+    # is recomputed (encoder and decoder) and both adjoint products run, 3x
+    # those forward flops; the global MLP likewise per item.  dL/dU of the
+    # passive nodes of contacted patches in.
     bwd_flop = 3.0 * 2.0 * ((ENC_MAC + DEC_MAC) * counts["passive"] + GLOBAL_MAC * items)
-    return dict(mfma_flop=bwd_flop if net else 0.0, valu_flop=0.0,
-                hbm_bytes=counts["contacted_nodes"] + 24.0 * counts["active"] + 48.0 * O * items
-                + ((4.0 * REC_WORDS + 512.0) * items if net else 0.0))
+    return dict(mfma_flop=bwd_flop if net else 0.0, pairs=0.0, hbm_bytes=12.0 * counts["passive"])
 
 
 def source_digest():
@@ -322,26 +341,130 @@ def measured_traffic(kernel, workload):
 
 
 def roofline_of(kernel, avg_ms, work, workload="hand"):
-    """Roofline of the dominant kernel: the resource whose lower-bound time
-    (work / peak) is largest names the bound; achieved = algorithmic work of
-    one launch / its average device time."""
+    """Roofline of a kernel: the resource whose lower-bound time (work /
+    peak) is largest names the bound; achieved = algorithmic work of one
+    launch / its average device time.  mfma: FP32-equivalent flops of the
+    network, three split-FP16 passes each, against the dense FP16 peak; alu:
+    decay pairs against the VALU issue ceiling (PAIR_CEILING); hbm: bytes
+    against 8 TB/s."""
     t = avg_ms * 1e-3
+    ceiling = PAIR_CEILING_BWD if kernel == "k_bwd_decay" else PAIR_CEILING
     lb = {"mfma": MFMA_PASSES * work["mfma_flop"] / (F16_MFMA_PEAK_TFLOPS * 1e12),
-          "alu": work["valu_flop"] / (FP32_VECTOR_PEAK_TFLOPS * 1e12),
+          "alu": work["pairs"] / ceiling,
           "hbm": work["hbm_bytes"] / (HBM_PEAK_GBS * 1e9)}
     bound = max(lb, key=lb.get)
     if bound == "mfma":
         achieved, peak, unit = work["mfma_flop"] / t / 1e12, F16_MFMA_PEAK_TFLOPS, "TFLOP/s"
     elif bound == "alu":
-        achieved, peak, unit = work["valu_flop"] / t / 1e12, FP32_VECTOR_PEAK_TFLOPS, "TFLOP/s"
+        achieved, peak, unit = work["pairs"] / t / 1e9, ceiling / 1e9, "Gpairs/s"
     else:
         achieved, peak, unit = work["hbm_bytes"] / t / 1e9, HBM_PEAK_GBS, "GB/s"
     traffic = measured_traffic(kernel, workload)
-    return {"bound": bound, "kernel": kernel, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+    return {"bound": bound, "kernel": kernel, "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": unit,
             "frac": round(achieved / peak, 5), "traffic": traffic, "avg_ms": round(avg_ms, 4),
             "mfma_passes": MFMA_PASSES if bound == "mfma" else None,
             "lower_bound_ms": {k: round(v * 1e3, 4) for k, v in lb.items()},
             "work_per_launch": work}
+
+
+def hires(args, mode):
+    """High-resolution pads: 4096 envs x 4 flat 128x128 pads at 0.125 mm, one
+    sphere or box per pad pressed 0.1-2 mm.  Forward and forward + adjoint
+    (eager calls, per-kernel device times), steps/s and node-updates/s."""
+    import torch
+    import scenes
+    from paper_2604_20295_amd import _native
+    dev = torch.device("cuda", 0)
+    mesh, scene, model = scenes.config4(n_envs=args.envs, mode=mode)
+    E, O, N, K = scene.n_envs, scene.max_obj, mesh.n_nodes, mesh.n_patches
+
+    def t(a, dtype):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).to(dev)
+
+    plan = _native.Plan.from_mesh(mesh, E, O, backward=True)
+    sc = plan.scene_struct(t(scene.n_obj, torch.int32), t(scene.type, torch.int32), t(scene.shape, torch.float32),
+                           t(scene.rot, torch.float32), t(scene.trans, torch.float32))
+    md = plan.model_struct(mode, t(model.alpha, torch.float32), t(model.phi, torch.float32))
+    gu = torch.randn((3, E, N), generator=torch.Generator(device=dev).manual_seed(7), device=dev)
+    u = torch.empty((3, E, N), device=dev)
+    cobj = torch.empty((E, N), dtype=torch.int8, device=dev)
+    na = torch.empty((E, K), dtype=torch.int32, device=dev)
+    grot, gtr = torch.empty((E, O, 9), device=dev), torch.empty((E, O, 3), device=dev)
+    gal, gph = torch.empty((K,), device=dev), torch.empty((PHI_SIZE,), device=dev)
+    saved = _native.saved_buffer(plan, E)
+    if args.launch:
+        plan.set_launch(*[int(x) for x in args.launch.split(",")])
+    elif not args.no_autotune:
+        _native.etac_plan_autotune(plan, sc, md, u, cobj, na, gu, grot, gtr, gal, gph, reps=1, saved=saved)
+    _native.etac_step(plan, sc, md, u, cobj, na, saved=saved)
+    _native.etac_step_backward(plan, sc, md, gu, grot, gtr, gal, gph, saved=saved)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(args.hires_steps):
+        _native.etac_step(plan, sc, md, u, cobj, na)
+    torch.cuda.synchronize()
+    fwd_ms = (time.perf_counter() - t0) * 1e3 / args.hires_steps
+    _, _ = plan.kernel_time(_native.ETAC_TIMER_STEP)    # forward-only launches are not part of the step averages
+    t0 = time.perf_counter()
+    for _ in range(args.hires_steps):
+        _native.etac_step(plan, sc, md, u, cobj, na, saved=saved)
+        _native.etac_step_backward(plan, sc, md, gu, grot, gtr, gal, gph, saved=saved)
+    torch.cuda.synchronize()
+    step_ms = (time.perf_counter() - t0) * 1e3 / args.hires_steps
+    kern = {}
+    for name, tid in (("k_step", _native.ETAC_TIMER_STEP), ("k_bwd_decay", _native.ETAC_TIMER_BWD_DECAY),
+                      ("k_bwd", _native.ETAC_TIMER_BACKWARD), ("bwd_reductions", _native.ETAC_TIMER_REDUCE)):
+        n, ms = plan.kernel_time(tid)
+        kern[name + "_avg"] = ms / n if n else float("nan")
+    plan.set_timing(False)
+    counts = work_counts(mesh, na.cpu().numpy())
+    plan.close()
+    nodes = float(E) * N
+    return {"workload": f"{E} envs x 4 pads of 128x128 nodes at 0.125 mm ({N} nodes/env), one sphere or box per "
+                        f"pad pressed 0.1-2 mm, mode full",
+            "fwd": {"ms_per_step": fwd_ms, "steps_per_s": 1e3 / fwd_ms, "node_updates_per_s": nodes / (fwd_ms * 1e-3)},
+            "fwd_bwd": {"ms_per_step": step_ms, "steps_per_s": 1e3 / step_ms,
+                        "node_updates_per_s": nodes / (step_ms * 1e-3)},
+            "kernel_ms": kern, "decay_pairs": counts["pairs"],
+            "decay_pairs_per_s_k_step": counts["pairs"] / (kern["k_step_avg"] * 1e-3),
+            "steps": args.hires_steps, "launch_shape": None}
+
+
+def cpu_baseline(mesh, scene, model, grad_u, budget):
+    """The FP64 oracle (forward + adjoint) on consecutive blocks of the same
+    envs until the time budget is spent, on every host thread and on one."""
+    import oracle
+    E, N = scene.n_envs, mesh.n_nodes
+    cpu = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                cpu = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    out = {}
+    all_threads = oracle.num_threads()
+    for threads, share in ((all_threads, 0.7), (1, 0.3)):
+        oracle.set_num_threads(threads)
+        ne, dt, block = 0, 0.0, (256 if threads > 1 else 16)
+        while ne < E and dt < budget * share:
+            envs = np.arange(ne, min(E, ne + block))
+            sub = scene.select(envs)
+            tc = time.perf_counter()
+            oracle.forward(mesh, sub, model)
+            oracle.backward(mesh, sub, model, np.ascontiguousarray(grad_u[:, envs]))
+            dt += time.perf_counter() - tc
+            ne += len(envs)
+        out[threads] = (ne * N / dt, ne, dt)
+    oracle.set_num_threads(all_threads)
+    v, ne, dt = out[all_threads]
+    v1, ne1, dt1 = out[1]
+    return {"value": v, "unit": "node-updates/s", "cores": all_threads, "kind": "oracle",
+            "sample": f"first {ne} of {E} envs, FP64 forward + adjoint, {dt:.1f} s on {all_threads} threads; "
+                      f"first {ne1} envs, {dt1:.1f} s on 1 thread",
+            "cpu_model": cpu, "value_1_thread": v1}
 
 
 def main():
@@ -370,18 +493,18 @@ def main():
     sc = plan.scene_struct(t(scene.n_obj, torch.int32), t(scene.type, torch.int32), t(scene.shape, torch.float32),
                            t(scene.rot, torch.float32), t(scene.trans, torch.float32))
     md = plan.model_struct(mode, t(model.alpha, torch.float32), t(model.phi, torch.float32))
-    grad_u = t(np.random.default_rng(7).standard_normal((3, E, N)), torch.float32)
+    grad_u_host = np.random.default_rng(7).standard_normal((3, E, N))
+    grad_u = t(grad_u_host, torch.float32)
     u = torch.empty((3, E, N), dtype=torch.float32, device=dev)
     cobj = torch.empty((E, N), dtype=torch.int8, device=dev)
     na = torch.empty((E, K), dtype=torch.int32, device=dev)
     grot = torch.empty((E, O, 9), dtype=torch.float32, device=dev)
     gtr = torch.empty((E, O, 3), dtype=torch.float32, device=dev)
     gal = torch.empty((K,), dtype=torch.float32, device=dev)
-    gph = torch.empty((17411,), dtype=torch.float32, device=dev)
+    gph = torch.empty((PHI_SIZE,), dtype=torch.float32, device=dev)
     # the forward's pooling record, handed to the adjoint (as the autograd
     # binding does); the forward-only figure is taken without it
     saved = _native.saved_buffer(plan, E)
-    stream = torch.cuda.current_stream(dev)
 
     def fwd(rec=saved):
         _native.etac_step(plan, sc, md, u, cobj, na, saved=rec)
@@ -395,52 +518,64 @@ def main():
     elif not args.no_autotune:
         _native.etac_plan_autotune(plan, sc, md, u, cobj, na, grad_u, grot, gtr, gal, gph, reps=2, saved=saved)
     launch_shape = plan.launch()
+    stream = torch.cuda.current_stream(dev)
 
-    graph = None
-    if args.graph:
+    # eager pass: the same steps as separate calls, each kernel bracketed by
+    # the library's HIP event pairs on its launch stream (per-kernel device
+    # times for the rooflines)
+    for _ in range(args.warmup):
         fwd(); bwd()
+    torch.cuda.synchronize()
+    counts = work_counts(mesh, na.cpu().numpy())
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    plan.set_timing(True)
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        ev[s][0].record(stream); fwd(); ev[s][1].record(stream); bwd(); ev[s][2].record(stream)
+    torch.cuda.synchronize()
+    eager_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    kernel_avg = {}
+    for name, tid in (("k_step", _native.ETAC_TIMER_STEP), ("k_bwd_decay", _native.ETAC_TIMER_BWD_DECAY),
+                      ("k_bwd", _native.ETAC_TIMER_BACKWARD), ("bwd_reductions", _native.ETAC_TIMER_REDUCE)):
+        n, ms = plan.kernel_time(tid)
+        kernel_avg[name] = ms / n if n else float("nan")
+    plan.set_timing(False)
+    fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    bwd_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+
+    # headline: the whole step (forward + adjoint) replayed from one HIP graph
+    graph = None
+    if not args.eager:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            fwd(); bwd()
+        torch.cuda.current_stream().wait_stream(side)
         torch.cuda.synchronize()
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
             fwd()
             bwd()
-        stream = torch.cuda.current_stream(dev)
-
     for _ in range(args.warmup):
         if graph is not None:
             graph.replay()
         else:
             fwd(); bwd()
+    hev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
-    counts = work_counts(mesh, na.cpu().numpy())
-
-    # forward + backward steps: HIP events around each call on the launch
-    # stream, and the library's per-kernel event pairs (same stream)
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    if graph is None:
-        plan.set_timing(True)
     t0 = time.perf_counter()
+    hev[0].record(stream)
     for s in range(args.steps):
         if graph is not None:
-            ev[s][0].record(stream); graph.replay(); ev[s][2].record(stream)
+            graph.replay()
         else:
-            ev[s][0].record(stream); fwd(); ev[s][1].record(stream); bwd(); ev[s][2].record(stream)
+            fwd(); bwd()
+        hev[s + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     step_ms = wall * 1e3 / args.steps
-    kernel_avg = {}
-    if graph is None:
-        fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
-        bwd_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
-        for name, tid in (("k_step", _native.ETAC_TIMER_STEP), ("k_bwd_decay", _native.ETAC_TIMER_BWD_DECAY),
-                          ("k_bwd", _native.ETAC_TIMER_BACKWARD), ("bwd_reductions", _native.ETAC_TIMER_REDUCE)):
-            n, ms = plan.kernel_time(tid)
-            kernel_avg[name] = ms / n if n else float("nan")
-        plan.set_timing(False)
-    else:
-        fwd_ms = bwd_ms = float("nan")
-    step_ev_ms = float(np.mean([e[0].elapsed_time(e[2]) for e in ev]))
+    lat = np.array([hev[s].elapsed_time(hev[s + 1]) for s in range(args.steps)])
+    del graph
 
     # forward-only throughput
     torch.cuda.synchronize()
@@ -483,13 +618,12 @@ def main():
     hbm_fwd_gbs = 13.0 * nodes / (fwd_only_ms * 1e-3) / 1e9
     hbm_step_gbs = 25.0 * nodes / (step_ms * 1e-3) / 1e9
 
-    roofline, by_kernel = None, {}
-    if "k_step" in kernel_avg:
-        for kern in ("k_contact", "k_step", "k_bwd_decay", "k_bwd"):
-            by_kernel[kern] = roofline_of(kern, kernel_avg[kern], algorithmic_work(kern, counts, E, N, K, O, mode),
-                                          args.workload)
-        kernel = max(("k_step", "k_bwd_decay", "k_bwd"), key=lambda k: kernel_avg[k])
-        roofline = dict(by_kernel[kernel])
+    by_kernel = {}
+    for kern in ("k_contact", "k_step", "k_bwd_decay", "k_bwd"):
+        by_kernel[kern] = roofline_of(kern, kernel_avg[kern], algorithmic_work(kern, counts, E, N, K, O, mode),
+                                      args.workload)
+    dominant = max(("k_step", "k_bwd_decay", "k_bwd"), key=lambda k: kernel_avg[k])
+    roofline = dict(by_kernel[dominant])
 
     line = {
         "metric": "sensor node-updates/s at 4096 envs, fwd and fwd+bwd; % of HBM roofline",
@@ -503,59 +637,56 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
+        "precision": {"contact": "FP64 predicate and penetration, FP32 results",
+                      "decay": "FP32 terms, FP64 block sums",
+                      "network": "FP32 operands as FP16 hi+lo pairs with power-of-two range scaling "
+                                 "(hi*hi + hi*lo + lo*hi on FP16 MFMA, 22-bit operands), FP32 accumulation"},
         "data": "synthetic",
         "config": {"workload": (f"{E} envs x 16-patch hand ({N} nodes/env, patches 64-1024 nodes), "
-                                f"1-3 sphere/box/capsule per env, mode {args.mode}") if args.workload == "hand" else
-                               (f"{E} envs x 4 pads of 128x128 nodes at 0.125 mm ({N} nodes/env), one sphere or box "
-                                f"per pad, mode {args.mode}"),
-                   "envs": E, "nodes_per_env": N, "patches": K, "graph": bool(args.graph),
+                                f"1-3 sphere/box/capsule per env on 5-30 % of the nodes, mode {args.mode}")
+                   if args.workload == "hand" else
+                   (f"{E} envs x 4 pads of 128x128 nodes at 0.125 mm ({N} nodes/env), one sphere or box "
+                    f"per pad, mode {args.mode}"),
+                   "envs": E, "nodes_per_env": N, "patches": K, "graph": not args.eager,
                    "launch_shape": {"fwd_wg_per_cu": launch_shape[0], "fwd_batch": launch_shape[1],
                                     "bwd_batch": launch_shape[2], "decay_wg_per_cu": launch_shape[3],
                                     "net_batch": launch_shape[4],
                                     "autotuned": not (args.no_autotune or args.launch)}},
+        "step_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "eager": {"ms_per_step": eager_ms, "value": nodes / (eager_ms * 1e-3), "unit": "node-updates/s",
+                  "what": "the same steps as separate calls, with the per-kernel device times below"},
         "fwd_only": {"value": fwd_rate, "unit": "node-updates/s", "ms_per_step": fwd_only_ms,
                      "hbm_gbs": hbm_fwd_gbs, "hbm_frac": hbm_fwd_gbs / HBM_PEAK_GBS},
         "hbm_frac_step": hbm_step_gbs / HBM_PEAK_GBS,
-        "kernel_ms": {"etac_step": fwd_ms, "etac_step_backward": bwd_ms, "step_events": step_ev_ms,
+        "kernel_ms": {"etac_step": fwd_ms, "etac_step_backward": bwd_ms,
                       **{f"{k}_avg": v for k, v in kernel_avg.items()}},
         "work": counts,
         "roofline": roofline,
         "roofline_by_kernel": by_kernel,
-        "contact_only": {"value": nodes / (kernel_avg.get("k_contact", float("nan")) * 1e-3), "unit": "node-updates/s",
-                         "ms": kernel_avg.get("k_contact")},
+        "contact_only": {"value": nodes / (kernel_avg["k_contact"] * 1e-3), "unit": "node-updates/s",
+                         "ms": kernel_avg["k_contact"]},
         "plain_forward": {"ms_per_step": plain_fwd_ms, "value": nodes / (plain_fwd_ms * 1e-3),
                           "unit": "node-updates/s", "what": "etac_contact then etac_propagate (two launches)",
                           "fwd_bwd_over_plain_forward": step_ms / plain_fwd_ms},
-        "decay_pairs_per_s": {"k_step": counts["pairs"] / (kernel_avg.get("k_step", float("nan")) * 1e-3),
-                              "k_bwd_decay": counts["pairs"] / (kernel_avg.get("k_bwd_decay", float("nan")) * 1e-3),
-                              "transcendental_ceiling": TRANS_PAIR_CEILING},
+        "decay_pairs_per_s": {"k_step": counts["pairs"] / (kernel_avg["k_step"] * 1e-3),
+                              "k_bwd_decay": counts["pairs"] / (kernel_avg["k_bwd_decay"] * 1e-3),
+                              "issue_ceiling_fwd": PAIR_CEILING, "issue_ceiling_bwd": PAIR_CEILING_BWD},
     }
 
     if args.calib_steps > 0:
         line["calibration"] = calibration(args, plan, mesh, scene, model, mode)
     if not args.no_mesh and args.workload == "hand":
         line["mesh_contact"] = mesh_contact(args, plan, mesh, model, mode)
-
-    if not args.no_cpu_baseline:
-        # the FP64 oracle (forward + adjoint) on blocks of the same envs until
-        # the time budget is spent
-        import oracle
-        gu_host = grad_u.cpu().numpy().astype(np.float64)
-        ne, dt, block = 0, 0.0, (256 if N < 20000 else 1)
-        while ne < E and dt < args.cpu_seconds:
-            envs = np.arange(ne, min(E, ne + block))
-            sub = scene.select(envs)
-            tc = time.perf_counter()
-            oracle.forward(mesh, sub, model)
-            oracle.backward(mesh, sub, model, np.ascontiguousarray(gu_host[:, envs]))
-            dt += time.perf_counter() - tc
-            ne += len(envs)
-        line["cpu_baseline"] = {"value": ne * N / dt, "unit": "node-updates/s", "cores": oracle.num_threads(),
-                                "kind": "oracle",
-                                "sample": f"first {ne} of {E} envs, FP64 forward + adjoint, {dt:.1f} s"}
     plan.close()
-    if args.rollout:
+    del saved, grad_u, u, cobj, uhat, uo
+    torch.cuda.empty_cache()
+    if not args.no_hires and args.workload == "hand":
+        line["hires"] = hires(args, mode)
+        torch.cuda.empty_cache()
+    if not args.no_rollout and args.workload == "hand":
         line["rollout"] = rollout(args, mode)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(mesh, scene, model, grad_u_host, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 

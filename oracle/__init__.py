@@ -65,6 +65,11 @@ def num_threads():
     return int(_load().oracle_num_threads())
 
 
+def set_num_threads(n):
+    """Threads of the oracle's parallel loops from here on."""
+    _load().oracle_set_num_threads(C.c_int(int(n)))
+
+
 def _mesh_args(mesh):
     return (C.c_int(mesh.n_patches), C.c_int(mesh.n_nodes), _i32(mesh.patch_offset),
             _f64(mesh.pos), _f64(mesh.nrm), _f64(mesh.origin))
@@ -127,6 +132,24 @@ def forward(mesh, scene, model, with_sig=False):
     if with_sig:
         out.update(sig=sig, margin=margin)
     return out
+
+
+def item_margins(mesh, scene, model):
+    """Decision margin of every (env, patch) item [E][K]: the smallest distance
+    of a ReLU input or max-pool runner-up gap from its decision boundary
+    (inf for items that evaluate no network), and the forward's outputs."""
+    lib = _load()
+    K, N, off, pos, nrm, origin = _mesh_args(mesh)
+    E, O, n_obj, typ, shape, rot, trans = _scene_args(scene)
+    e, n = E.value, N.value
+    U = np.empty((3, e, n), np.float64)
+    cobj = np.empty((e, n), np.int8)
+    uhat = np.empty((3, e, n), np.float64)
+    na = np.empty((e, K.value), np.int32)
+    margin = np.empty((e, K.value), np.float64)
+    _call(lib.oracle_item_margins, K, N, off, pos, nrm, origin, E, O, n_obj, typ, shape, rot, trans,
+          C.c_int(model.mode), _f64(model.alpha), _f64(model.phi), U, cobj, uhat, na, margin)
+    return dict(u=U, contact_obj=cobj, uhat=uhat, n_active=na, margin=margin)
 
 
 def propagate_backward(mesh, model, contact_obj, uhat, grad_u):
@@ -223,11 +246,13 @@ def fd_gradients(mesh, scene, model, w, env=0, obj=0, h=1e-4, phi_idx=(), shrink
     pattern, arg-max) is not a derivative.  Such a difference is retaken with
     the smaller steps in `shrink`; if every step straddles a decision the
     result is flagged.  Returns (dict of FD values, ok) where ok is False if
-    any entry stayed flagged."""
+    any entry stayed flagged; the dict's "ok_each" holds the flag of every
+    entry (same keys and shapes)."""
     S = _F64Scene(scene)
     M = _F64Model(model)
     ok = True
     res = {}
+    flags = []
 
     def central(perturb):
         nonlocal ok
@@ -239,8 +264,10 @@ def fd_gradients(mesh, scene, model, w, env=0, obj=0, h=1e-4, phi_idx=(), shrink
             lp, sp = loss_and_sig(mesh, Sp, Mp, w)
             lm, sm = loss_and_sig(mesh, Sm, Mm, w)
             if np.array_equal(sp, sm):
+                flags.append(True)
                 return (lp - lm) / (2 * step)
         ok = False
+        flags.append(False)
         return (lp - lm) / (2 * step)
 
     def shift_t(c):
@@ -266,10 +293,14 @@ def fd_gradients(mesh, scene, model, w, env=0, obj=0, h=1e-4, phi_idx=(), shrink
             M_.phi[i] += s
         return f
 
-    res["trans"] = np.array([central(shift_t(c)) for c in range(3)])
-    res["twist"] = np.array([central(twist(c)) for c in range(3)])
-    res["alpha"] = np.array([central(shift_alpha(k)) for k in range(mesh.n_patches)])
-    res["phi"] = np.array([central(shift_phi(i)) for i in phi_idx])
+    each = {}
+    for key, fns in (("trans", [shift_t(c) for c in range(3)]), ("twist", [twist(c) for c in range(3)]),
+                     ("alpha", [shift_alpha(k) for k in range(mesh.n_patches)]),
+                     ("phi", [shift_phi(i) for i in phi_idx])):
+        flags.clear()
+        res[key] = np.array([central(f) for f in fns])
+        each[key] = np.array(flags, dtype=bool)
+    res["ok_each"] = each
     return res, ok
 
 

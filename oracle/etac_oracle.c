@@ -1016,6 +1016,15 @@ int oracle_num_threads(void) {
 #endif
 }
 
+/* Threads of the following parallel loops (timing of the CPU baseline). */
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Contact only.  Outputs contact_obj [E][N], uhat [3][E][N], n_active [E][K]. */
 int oracle_contact(int K, int N, const int32_t *offset, const double *pos, const double *nrm, int E,
                    int O, const int32_t *n_obj, const int32_t *type, const double *shape,
@@ -1069,6 +1078,37 @@ int oracle_forward(int K, int N, const int32_t *offset, const double *pos, const
                                 sig ? &h : NULL);
             if (sig) sig[e] = h;
             if (margin) margin[e] = mg;
+        }
+        scratch_free(&S);
+    }
+    return 0;
+}
+
+/* Whole forward step with the decision margin of every (env, patch) item:
+ * margin [E][K] is the smallest distance of a ReLU input or max-pool
+ * runner-up gap of the item from its decision boundary (INFINITY when the
+ * item evaluates no network).  A diagnostic for the parity checks: an item
+ * whose margin exceeds the FP32 rounding of the pre-activations takes the
+ * same discrete decisions in FP32 as here. */
+int oracle_item_margins(int K, int N, const int32_t *offset, const double *pos, const double *nrm,
+                        const double *origin, int E, int O, const int32_t *n_obj, const int32_t *type,
+                        const double *shape, const double *rot, const double *trans, int mode,
+                        const double *alpha, const double *phi, double *U, int8_t *cobj, double *uhat,
+                        int32_t *n_active, double *margin) {
+    problem_t P = mkprob(K, N, offset, pos, nrm, origin, E, O, n_obj, type, shape, rot, trans);
+    net_t W = net_view(phi);
+    int nmax = max_patch(&P);
+#pragma omp parallel
+    {
+        scratch_t S = scratch_new(nmax);
+#pragma omp for schedule(static)
+        for (int e = 0; e < E; ++e) {
+            contact_env(&P, e, cobj, uhat, n_active, NULL);
+            for (int k = 0; k < K; ++k) {
+                double mg = INFINITY;
+                propagate_patch(&P, &W, mode, alpha, e, k, cobj, uhat, U, &S, &mg, NULL);
+                margin[(size_t)e * K + k] = mg;
+            }
         }
         scratch_free(&S);
     }

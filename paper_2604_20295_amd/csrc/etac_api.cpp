@@ -152,6 +152,7 @@ etac_status etac_plan_create(const etac_mesh *mesh, int32_t n_envs, int32_t max_
     std::vector<float4> bound(K);
     std::vector<int16_t> node_patch(N);
     std::vector<int> order(K);
+    std::vector<float> xbound(K);
     for (int k = 0; k < K; ++k) {
         const int o0 = mesh->patch_offset[k], o1 = mesh->patch_offset[k + 1];
         double lo[3], hi[3];
@@ -177,6 +178,14 @@ etac_status etac_plan_create(const etac_mesh *mesh, int32_t n_envs, int32_t max_
             node_patch[i] = (int16_t)k;
         }
         bound[k] = make_float4(cf[0], cf[1], cf[2], round_up_float(rad * (1.0 + 1e-6) + 1e-4));
+        // bound of the geometric network inputs of the patch (the scale of its split operands)
+        double xb = 0.0;
+        for (int i = o0; i < o1; ++i)
+            for (int a = 0; a < 3; ++a) {
+                xb = std::max(xb, std::fabs((double)mesh->pos[(size_t)a * N + i] - (double)mesh->origin[3 * k + a]));
+                xb = std::max(xb, std::fabs((double)mesh->nrm[(size_t)a * N + i]));
+            }
+        xbound[k] = round_up_float(xb * (1.0 + 1e-6));
         order[k] = k;
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
@@ -186,6 +195,7 @@ etac_status etac_plan_create(const etac_mesh *mesh, int32_t n_envs, int32_t max_
     float *pos = nullptr, *nrm = nullptr, *origin = nullptr;
     int *offset = nullptr, *ord = nullptr;
     float4 *bnd = nullptr;
+    float *xbd = nullptr;
     int16_t *np = nullptr;
     e = plan_alloc(p, &pos, 3 * (size_t)N);
     if (e == hipSuccess) e = plan_alloc(p, &nrm, 3 * (size_t)N);
@@ -194,6 +204,7 @@ etac_status etac_plan_create(const etac_mesh *mesh, int32_t n_envs, int32_t max_
     if (e == hipSuccess) e = plan_alloc(p, &ord, (size_t)K);
     if (e == hipSuccess) e = plan_alloc(p, &bnd, (size_t)K);
     if (e == hipSuccess) e = plan_alloc(p, &np, (size_t)N);
+    if (e == hipSuccess) e = plan_alloc(p, &xbd, (size_t)K);
     if (e == hipSuccess) e = hipMemcpy(pos, mesh->pos, 3 * (size_t)N * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(nrm, mesh->nrm, 3 * (size_t)N * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(origin, mesh->origin, 3 * (size_t)K * sizeof(float), hipMemcpyHostToDevice);
@@ -201,7 +212,8 @@ etac_status etac_plan_create(const etac_mesh *mesh, int32_t n_envs, int32_t max_
     if (e == hipSuccess) e = hipMemcpy(ord, order.data(), (size_t)K * sizeof(int), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(bnd, bound.data(), (size_t)K * sizeof(float4), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(np, node_patch.data(), (size_t)N * sizeof(int16_t), hipMemcpyHostToDevice);
-    p.mesh = etac::MeshDev{pos, nrm, origin, offset, bnd, np, ord, K, N, n_max};
+    if (e == hipSuccess) e = hipMemcpy(xbd, xbound.data(), (size_t)K * sizeof(float), hipMemcpyHostToDevice);
+    p.mesh = etac::MeshDev{pos, nrm, origin, offset, bnd, np, ord, xbd, K, N, n_max};
 
     // forward scratch, one slice per persistent workgroup
     const size_t G = (size_t)p.cu_count * 8;  // enough for any occupancy override

@@ -126,8 +126,19 @@ struct DecayStage {
 struct DecayLds {
     DecayStage st;
     double dred[kWaves][12];
-    int wcnt[2][kWaves];
+    int wcnt[3][kWaves];
     ItemBatch batch;
+};
+
+// Power-of-two scales of one item's adjoint: the activations' as in the
+// forward (ItemScale) and the gradients': dL/dU of the passive nodes staged
+// at 2^dre (dre from their largest |component|), which puts dL/dpre4 at
+// 2^d4 = 2^(dre + c5t), dL/dpre2 at 2^d2 = 2^(d4 + s4t) and dL/dpre1 at
+// 2^d1 = 2^(d2 + s2t), each below T (see stage_net).  In LDS, read into
+// scalar registers where used.
+struct BwdScale {
+    float fone;          // the constant input 1 of the N-form inputs at the inputs' scale (2^ax)
+    int dre, d4, d2, d1;
 };
 
 // Chunks of kWG nodes per pass of compact_given.
@@ -138,6 +149,7 @@ struct BwdLds {
     half8 w2th[4 * 2 * 64], w2tl[4 * 2 * 64];   // [it][s][lane] split fragments of W2^T
     half8 w4th[4 * 2 * 64], w4tl[4 * 2 * 64];   // [it][s][lane] split fragments of W4[:, :64]^T
     float w1u[3][64];                           // W1[:, 6..8]: the u_hat inputs
+    float w5t[3 * 64];                          // W5 2^c5t (dL/dpre4 = W5^T dL/dr)
     union {
         floatx4 red[kWaves][8][64];        // eight record blocks of every wave's gradient accumulators
         StageBuf xs;                       // node inputs of the network passes
@@ -153,6 +165,8 @@ struct BwdLds {
     float dxs[64][3];             // dL/du_hat of the routed arg-max node of each channel
     double dred[kWaves][12];
     int wcnt[kGivenChunks][2][kWaves];   // compaction counts, one set per chunk of a pass
+    int wmx[2][kWaves];           // per-wave largest |u_hat| and passive |dL/dU| components (float bits)
+    BwdScale bsc;                 // the current item's adjoint scales
     ItemBatch batch;
 };
 
@@ -163,9 +177,12 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // Transposed weight fragments for the adjoint layers, in the chain order of
-// etac_device.h (K step s, lane group q, element e <-> output chain_k(s, q, e)).
+// etac_device.h (K step s, lane group q, element e <-> output chain_k(s, q, e)),
+// scaled by 2^s2t and 2^s4t, and W5 scaled by 2^c5t (after stage_net).
 __device__ void stage_net_t(BwdLds &S, const float *phi) {
     const int tid = threadIdx.x;
+    const float s2 = pow2(uniform(S.net.s2t)), s4 = pow2(uniform(S.net.s4t)), s5 = pow2(uniform(S.net.c5t));
+    for (int i = tid; i < 192; i += kWG) S.w5t[i] = phi[kW5 + i] * s5;
     for (int idx = tid; idx < 4 * 2 * 64; idx += kWG) {
         const int lane = idx & 63, s = (idx >> 6) & 1, it = idx >> 7, q = lane >> 4;
         const int in = it * 16 + (lane & 15);
@@ -173,8 +190,8 @@ __device__ void stage_net_t(BwdLds &S, const float *phi) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int out = chain_k(s, q, e);
-            a[e] = phi[kW2 + out * 64 + in];
-            b[e] = phi[kW4 + out * 128 + in];
+            a[e] = phi[kW2 + out * 64 + in] * s2;
+            b[e] = phi[kW4 + out * 128 + in] * s4;
         }
         split8(a, S.w2th[idx], S.w2tl[idx]);
         split8(b, S.w4th[idx], S.w4tl[idx]);
@@ -228,8 +245,8 @@ __device__ __forceinline__ void layer1_dual(const NetLds &L, const half8 &xh, co
     for (int ob = 0; ob < 4; ++ob) {
         wh[ob] = L.w1h[ob * 64 + lane];
         wl[ob] = L.w1l[ob * 64 + lane];
-        h1T[ob] = *reinterpret_cast<const floatx4 *>(&L.b1[ob * 16 + 4 * gq]);
-        const float bn = L.b1[ob * 16 + col];
+        h1T[ob] = *reinterpret_cast<const floatx4 *>(&L.b1s[ob * 16 + 4 * gq]);
+        const float bn = L.b1s[ob * 16 + col];
         h1N[ob] = floatx4{bn, bn, bn, bn};
     }
 #pragma unroll
@@ -344,12 +361,13 @@ __device__ __forceinline__ void wgrad_tiles(const WOp<NT, NO, true> &A, const WO
         for (int i = 0; i < NI; ++i) acc[o][i] = mfma16(A.l[o], B.h[i], acc[o][i]);
 }
 
-// acc15[wave][blk0 + o NI + i] += sum over the tiles' nodes of A[o] (x) B[i]
-// (NO x NI = 4 blocks): products from fresh accumulators, then one LDS
-// read-modify-write per block.
-template <int NT, int NO, int NI>
+// acc15[wave][blk0 + o NI + i] += post * sum over the tiles' nodes of
+// A[o] (x) B[i] (NO x NI = 4 blocks; post a power of two that brings the
+// products to the accumulator's scale, used only if SCALED): products from
+// fresh accumulators, then one LDS read-modify-write per block.
+template <int NT, int NO, int NI, bool SCALED = false>
 __device__ __forceinline__ void acc15_add(floatx4 *acc, int blk0, const WOp<NT, NO, true> &A,
-                                          const WOp<NT, NI, false> &B) {
+                                          const WOp<NT, NI, false> &B, float post = 1.0f) {
     static_assert(NO * NI == 4, "four blocks");
     const int lane = lane_id();
     floatx4 t[NO][NI];
@@ -365,16 +383,17 @@ __device__ __forceinline__ void acc15_add(floatx4 *acc, int blk0, const WOp<NT, 
             const int j = blk0 + o * NI + i;
             floatx4 v = acc[j * 64 + lane];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) v[r] += t[o][i][r];
+            for (int r = 0; r < 4; ++r) v[r] += SCALED ? t[o][i][r] * post : t[o][i][r];
             acc[j * 64 + lane] = v;
         }
 }
 
-// Network inputs in N form: lane l supplies input feature (l & 15) of nodes
-// 4 (l >> 4) + r: [p - o_k (3), n (3), U_hat (3)], a constant 1 at input 9
-// (its weight-gradient column is the bias gradient db1), zeros above.
+// Network inputs in N form, scaled by xmul: lane l supplies input feature
+// (l & 15) of nodes 4 (l >> 4) + r: [p - o_k (3), n (3), U_hat (3)], a
+// constant 1 at input 9 (its weight-gradient column is the bias gradient
+// db1), zeros above.
 __device__ __forceinline__ floatx4 load_xn(const MeshDev &M, int k, int base, const int ln[4], const bool v[4],
-                                           const float *uhn, int n_max) {
+                                           const float *uhn, int n_max, float xmul) {
     const int col = lane_id() & 15, N = M.N;
     floatx4 x;
 #pragma unroll
@@ -387,7 +406,7 @@ __device__ __forceinline__ floatx4 load_xn(const MeshDev &M, int k, int base, co
             else if (col < 9) val = uhn[(size_t)(col - 6) * n_max + ln[r]];
             else if (col == 9) val = 1.0f;
         }
-        x[r] = val;
+        x[r] = val * xmul;
     }
     return x;
 }
@@ -448,7 +467,7 @@ __device__ __forceinline__ void layer1_tiles(const NetLds &L, const half8 (&xh)[
     for (int ob = 0; ob < 4; ++ob) {
         wh[ob] = L.w1h[ob * 64 + lane];
         wl[ob] = L.w1l[ob * 64 + lane];
-        const floatx4 b = *reinterpret_cast<const floatx4 *>(&L.b1[ob * 16 + 4 * gq]);
+        const floatx4 b = *reinterpret_cast<const floatx4 *>(&L.b1s[ob * 16 + 4 * gq]);
 #pragma unroll
         for (int u = 0; u < NT; ++u) h1[u][ob] = b;
     }
@@ -543,9 +562,12 @@ __device__ __forceinline__ void layer64_tiles_n(const half8 *wh, const half8 *wl
 // Adjoint of NT tiles of 16 passive nodes (staged nodes 16 t[u] .. 16 t[u] +
 // 15 of the current chunk of cnt): forward recomputation, decoder and encoder
 // adjoints, all accumulated into this wave's parameter gradients.  Passive
-// nodes have U_hat = 0 and need no dL/du_hat; the stage holds dL/dU in its
-// third triple.  Every layer runs in T form on MFMA; the N forms the weight
-// gradients need are block transposes of the T-form values.
+// nodes have U_hat = 0 and need no dL/du_hat; the stage holds dL/dU (at
+// 2^dre) in its third triple.  Every layer runs in T form on MFMA; the N
+// forms the weight gradients need are block transposes of the T-form values.
+// dW5 (three output rows) accumulates in FP32 on the VALU, so h4 is never
+// split.  Accumulator scales: dW5 2^(dre + a4), db5 2^dre, dW4 2^(d4 + af),
+// db4 2^d4, dW2 2^(d2 + a1), db2 2^d2, dW1 2^(d1 + ax).
 template <int NT>
 __device__ void passive_tiles(BwdLds &S, WGrad &G, int cnt, const int (&t)[NT]) {
     const NetLds &L = S.net;
@@ -563,7 +585,7 @@ __device__ void passive_tiles(BwdLds &S, WGrad &G, int cnt, const int (&t)[NT]) 
     // 1).  Reads stay inside the stage (tile rows < kStage) and are masked
     // afterwards, so no lane branches.
     const int fcol = col < 6 ? col : 0;
-    const float fsel = col < 6 ? 1.0f : 0.0f, fone = col == 9 ? 1.0f : 0.0f;
+    const float fsel = col < 6 ? 1.0f : 0.0f, fone = col == 9 ? uniform(S.bsc.fone) : 0.0f;
 #pragma unroll
     for (int u = 0; u < NT; ++u) {
         const int li = 16 * t[u] + col;
@@ -588,7 +610,7 @@ __device__ void passive_tiles(BwdLds &S, WGrad &G, int cnt, const int (&t)[NT]) 
     layer1_tiles<NT>(L, xh, xl, h1T);
 #pragma unroll
     for (int u = 0; u < NT; ++u) split_chain(h1T[u], sh[u], sl[u]);
-    layer64_tiles<NT, true>(L.w2h, L.w2l, sh, sl, L.b2, fT);
+    layer64_tiles<NT, true>(L.w2h, L.w2l, sh, sl, L.b2s, fT);
 #pragma unroll
     for (int u = 0; u < NT; ++u) split_chain(fT[u], sh[u], sl[u]);
     layer64_tiles<NT, true>(L.w4h, L.w4l, sh, sl, L.c4, h4T);
@@ -599,34 +621,41 @@ __device__ void passive_tiles(BwdLds &S, WGrad &G, int cnt, const int (&t)[NT]) 
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int ft = ob * 16 + 4 * gq + r;
-            const float w0 = L.w5[ft], w1 = L.w5[64 + ft], w2 = L.w5[128 + ft];
+            const float w0 = S.w5t[ft], w1 = S.w5t[64 + ft], w2 = S.w5t[128 + ft];
 #pragma unroll
             for (int u = 0; u < NT; ++u) {
                 const float vt = w0 * dr[u][0] + w1 * dr[u][1] + w2 * dr[u][2];
                 d4T[u][ob][r] = h4T[u][ob][r] > 0.0f ? vt : 0.0f;
             }
         }
-    // dW5 += dr (x) h4 (lane col < 3 supplies output col), db5
+    // dW5 += dr (x) h4 in FP32: lane l adds, for feature 16 ib + (l & 15),
+    // its four nodes 4 gq + r into acc15[4 + ib] (components 0..2; the lane
+    // groups are summed when the record is written); db5
     {
-        WOp<NT, 1, true> A;
-        WOp<NT, 4, false> B;
         const int ccol = col < 3 ? col : 0;
+        floatx4 *a5 = S.acc15[wave] + 4 * 64;
 #pragma unroll
         for (int u = 0; u < NT; ++u) {
             floatx4 h4N[4];
             to_n_form(tb, h4T[u], h4N);
-            floatx4 a;
+            float d[4][3];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float v = xs[6 + ccol][lj[u][r]];
-                a[r] = (vr[u][r] && col < 3) ? v : 0.0f;
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float v = xs[6 + c][lj[u][r]];
+                    d[r][c] = vr[u][r] ? v : 0.0f;
+                }
+            G.b5 += col < 3 ? (d[0][ccol] + d[1][ccol]) + (d[2][ccol] + d[3][ccol]) : 0.0f;
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib) {
+                floatx4 v = a5[ib * 64 + lane];
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    v[c] += (d[0][c] * h4N[ib][0] + d[1][c] * h4N[ib][1]) + (d[2][c] * h4N[ib][2] + d[3][c] * h4N[ib][3]);
+                a5[ib * 64 + lane] = v;
             }
-            G.b5 += (a[0] + a[1]) + (a[2] + a[3]);
-            A.set(u, 0, a);
-#pragma unroll
-            for (int ib = 0; ib < 4; ++ib) B.set(u, ib, h4N[ib]);
         }
-        acc15_add<NT, 1, 4>(S.acc15[wave], 4, A, B);
     }
     // dW4[:, :64] += dpre4 (x) f, db4; f > 0 kept as bits (4 block + register)
     unsigned fmask[NT];
@@ -709,7 +738,7 @@ struct RouteIn {
 };
 
 __device__ __forceinline__ void route_inputs(const BwdParams &p, const BwdLds &S, int k, int base, int n,
-                                             const float *uhn, RouteIn &in) {
+                                             const float *uhn, float xmul, RouteIn &in) {
     const MeshDev &M = p.mesh;
     const int lane = lane_id(), wave = threadIdx.x >> 6, gq = lane >> 4, col = lane & 15, n_max = p.scr.n_max;
     const int lnT = S.argmax[16 * wave + col];
@@ -722,13 +751,21 @@ __device__ __forceinline__ void route_inputs(const BwdParams &p, const BwdLds &S
         vr[r] = lnr[r] < n;
         if (!vr[r]) lnr[r] = 0;
     }
-    load_x_raw(M, k, base + (vT ? lnT : 0), vT, uhn, n_max, vT ? lnT : 0, in.x);
-    in.xn = load_xn(M, k, base, lnr, vr, uhn, n_max);
+    load_x_raw(M, k, base + (vT ? lnT : 0), vT, uhn, n_max, vT ? lnT : 0, xmul, in.x);
+    in.xn = load_xn(M, k, base, lnr, vr, uhn, n_max, xmul);
 }
 
+// vroute is unscaled and h1 at 2^a1: 2^d2 brings the routed dL/dpre2 (x) h1
+// to dW2's accumulator scale 2^(d2 + a1); the routed dL/dpre1 (unscaled) is
+// split at its own scale 2^drt from a bound max |vroute| max |W2|, and its
+// dW1 products are brought to the accumulator's scale 2^(d1 + ax) by
+// 2^(d1 - drt).
 __device__ void routing_tile(const BwdParams &p, BwdLds &S, WGrad &G, int n, const RouteIn &in) {
     const NetLds &L = S.net;
     const int lane = lane_id(), wave = threadIdx.x >> 6, gq = lane >> 4, col = lane & 15;
+    const int drt = uniform(range_exp(wave_max(fabsf(S.vroute[lane])) * S.net.mw2));   // same in every wave
+    const float drt_mul = uniform(pow2(drt)), post = uniform(pow2(uniform(S.bsc.d1) - drt));
+    const float d2mul = uniform(pow2(uniform(S.bsc.d2)));
     // T form: channel 16 wave + col; N form: channels 16 wave + 4 gq + r
     const int cT = 16 * wave + col;
     const int lnT = S.argmax[cT];
@@ -785,7 +822,7 @@ __device__ void routing_tile(const BwdParams &p, BwdLds &S, WGrad &G, int n, con
 #pragma unroll
         for (int ib = 0; ib < 4; ++ib)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) G.w2[ob][ib][r] += (mine ? vn[r] : 0.0f) * h1N[ib][r];
+            for (int r = 0; r < 4; ++r) G.w2[ob][ib][r] += (mine ? vn[r] * d2mul : 0.0f) * h1N[ib][r];
     }
     // dW1 += dpre1 (x) x (db1 through input 9)
     WOp<1, 4, true> A;
@@ -795,10 +832,10 @@ __device__ void routing_tile(const BwdParams &p, BwdLds &S, WGrad &G, int n, con
     for (int ob = 0; ob < 4; ++ob) {
         floatx4 d1;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) d1[r] = h1N[ob][r] > 0.0f ? dh1N[ob][r] : 0.0f;
+        for (int r = 0; r < 4; ++r) d1[r] = h1N[ob][r] > 0.0f ? dh1N[ob][r] * drt_mul : 0.0f;
         A.set(0, ob, d1);
     }
-    acc15_add<1, 4, 1>(S.acc15[wave], 0, A, B);
+    acc15_add<1, 4, 1, true>(S.acc15[wave], 0, A, B, post);
 }
 
 // ---------------------------------------------------------------------------
@@ -1041,15 +1078,17 @@ __device__ void contact_adjoint_item(const BwdParams &p, BwdLds &S, int e, int i
     }
 }
 
-// Sum accumulator chunk C over the four waves (in wave order) and store it
-// into the item's parameter-gradient partial.
+// Sum accumulator chunk C over the four waves (in wave order), unscale it
+// (blocks 0-3 of the chunk by mul_lo, 4-7 by mul_hi) and store it into the
+// item's parameter-gradient partial.
 // Record blocks 8 C .. 8 C + 7 of the item: every wave puts its eight
 // accumulator blocks in LDS (one 16-byte store per lane and block), then each
 // thread sums two (block, lane) entries over the waves in wave order and
 // stores them with one 16-byte store each.  Every register is named
 // statically, so the accumulators never leave registers.
 template <int C>
-__device__ __forceinline__ void store_record_chunk(BwdLds &S, const WGrad &G, float *rec) {
+__device__ __forceinline__ void store_record_chunk(BwdLds &S, const WGrad &G, float *rec, float mul_lo,
+                                                   float mul_hi) {
     const int wave = threadIdx.x >> 6, lane = lane_id();
     __syncthreads();    // previous users of the buffer are done
 #pragma unroll
@@ -1072,13 +1111,34 @@ __device__ __forceinline__ void store_record_chunk(BwdLds &S, const WGrad &G, fl
 #pragma unroll
             for (int r = 0; r < 4; ++r) v[r] += x[r];
         }
+        if (C == 4 && j >= 4) {
+            // dW5: FP32 partials of the four lane groups, summed into the
+            // MFMA output layout of the record (output c at lane (l & 15),
+            // register c of lane group 0)
+            if (ln < 16) {
+#pragma unroll
+                for (int q = 1; q < 4; ++q)
+#pragma unroll
+                    for (int w = 0; w < kWaves; ++w) {
+                        const floatx4 x = S.u.red[w][j][ln + 16 * q];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) v[r] += x[r];
+                    }
+            } else {
+                v = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            }
+        }
+        const float mul = j < 4 ? mul_lo : mul_hi;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] *= mul;
         // the record streams to HBM for the reduction kernels: non-temporal
         __builtin_nontemporal_store(v, reinterpret_cast<floatx4 *>(&rec[(8 * C + j) * 256 + 4 * ln]));
     }
 }
 
 // Max-pool of the item's encoder features with, per channel, the arg-max
-// node (lowest index on ties) recomputed over every node: L.g, S.argmax.
+// node (lowest index on ties) recomputed over every node: L.g (unscaled),
+// S.argmax.
 __device__ void pool_argmax(const BwdParams &p, BwdLds &S, int k, int base, int n, const float *uhn) {
     NetLds &L = S.net;
     const MeshDev &M = p.mesh;
@@ -1093,7 +1153,8 @@ __device__ void pool_argmax(const BwdParams &p, BwdLds &S, int k, int base, int 
     for (int c0 = 0; c0 < n; c0 += kStage) {
         const int cnt = min(kStage, n - c0);
         __syncthreads();
-        stage_nodes(M, k, base, nullptr, c0, cnt, uhn, n_max, 0, S.u.xs);
+        const float xmul = uniform(L.isc.xmul);
+        stage_nodes(M, k, base, nullptr, c0, cnt, uhn, n_max, 0, xmul, xmul, S.u.xs);
         __syncthreads();
         // two tiles per wave step (t and t + kWaves); the second may be padding
         const int ntl = (cnt + 15) >> 4;
@@ -1153,16 +1214,19 @@ __device__ void pool_argmax(const BwdParams &p, BwdLds &S, int k, int base, int 
             const int i2 = S.ired[w][c];
             if (v2 > v || (v2 == v && i2 < ix)) { v = v2; ix = i2; }
         }
-        L.g[c] = v;
+        L.g[c] = v * pow2(-L.isc.af);   // unscaled
         S.argmax[c] = ix;
     }
     __syncthreads();
 }
 
 // Residual-network adjoint of one item; writes its parameter-gradient
-// partial and adds dL/du_hat of active arg-max nodes into gh.
+// partial and adds dL/du_hat of active arg-max nodes into gh.  umax: the
+// largest |u_hat| component of the item's nodes; gmax: the largest |dL/dU|
+// component of its passive nodes (they set the range scales).
 __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, int item, int base, int n, int np,
-                                 const int *plist, const float *uhn, const int8_t *wobj, float *gh) {
+                                 const int *plist, const float *uhn, const int8_t *wobj, float *gh, float umax,
+                                 float gmax) {
     NetLds &L = S.net;
     const MeshDev &M = p.mesh;
     const float *phi = p.model.phi;
@@ -1171,6 +1235,7 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
     const size_t row = (size_t)e * N + base;
     const int lane = lane_id(), wave = threadIdx.x >> 6;
     float *rec = p.bwd.phi_part + (size_t)item * kRecWords;
+    item_biases(L, item_scale(L, item_xbound(M, k, umax)));   // published by the next barrier
 
     // (a) max-pool with arg-max (lowest node on ties): from the forward's
     //     record, else an encoder pass over every node of the item
@@ -1187,7 +1252,17 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
     } else {
         pool_argmax(p, S, k, base, n, uhn);
     }
-    global_mlp(L, phi);
+    global_mlp(L, phi, item_scale_lds(L));
+    // gradient scales: dL/dU staged at 2^dre, dre from gmax (see BwdScale)
+    if (threadIdx.x < 64) {   // wave 0, identical values; published by the stage barrier
+        BwdScale bs;
+        bs.fone = L.isc.xmul;
+        bs.dre = range_exp(gmax);
+        bs.d4 = bs.dre + L.c5t;
+        bs.d2 = bs.d4 + L.s4t;
+        bs.d1 = bs.d2 + L.s2t;
+        S.bsc = bs;
+    }
 
     // (b) decoder and encoder adjoints over the passive nodes, tile t on wave t % 4
     WGrad G;
@@ -1196,7 +1271,8 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
     for (int c0 = 0; c0 < np; c0 += kStage) {
         const int cnt = min(kStage, np - c0);
         __syncthreads();
-        stage_nodes(M, k, base, plist, c0, cnt, p.grad_u, EN, row, S.u.xs);
+        stage_nodes(M, k, base, plist, c0, cnt, p.grad_u, EN, row, uniform(L.isc.xmul),
+                    pow2(uniform(S.bsc.dre)), S.u.xs);
         __syncthreads();
         // pairs of tiles (t, t + 4) per wave while every wave gets a pair,
         // then single tiles
@@ -1218,7 +1294,7 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
     //     loaded ahead of the reductions they feed, so their latency overlaps
     //     the barriers.
     RouteIn rin;
-    route_inputs(p, S, k, base, n, uhn, rin);
+    route_inputs(p, S, k, base, n, uhn, uniform(L.isc.xmul), rin);
     float w4g[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) w4g[q] = phi[kW4 + (16 * wave + q) * 128 + 64 + lane];
@@ -1233,7 +1309,7 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
     if (threadIdx.x < 64) {
         float t = S.vred[0][threadIdx.x];
         for (int w = 1; w < kWaves; ++w) t += S.vred[w][threadIdx.x];
-        S.s4[threadIdx.x] = t;
+        S.s4[threadIdx.x] = t * pow2(-S.bsc.d4);     // unscaled from here on
     }
     __syncthreads();
     {
@@ -1299,11 +1375,14 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
 
     // (e) the item's record of the parameter gradients: the four waves'
     //     accumulators summed in wave order, eight blocks per pass
-    store_record_chunk<0>(S, G, rec);
-    store_record_chunk<1>(S, G, rec);
-    store_record_chunk<2>(S, G, rec);
-    store_record_chunk<3>(S, G, rec);
-    store_record_chunk<4>(S, G, rec);
+    const ItemScale isc = item_scale_lds(L);
+    const int dre = uniform(S.bsc.dre), d4 = uniform(S.bsc.d4), d2 = uniform(S.bsc.d2), d1 = uniform(S.bsc.d1);
+    const float m4 = pow2(-(d4 + isc.af)), m2 = pow2(-(d2 + isc.a1));
+    store_record_chunk<0>(S, G, rec, m4, m4);
+    store_record_chunk<1>(S, G, rec, m4, m4);
+    store_record_chunk<2>(S, G, rec, m2, m2);
+    store_record_chunk<3>(S, G, rec, m2, m2);
+    store_record_chunk<4>(S, G, rec, pow2(-(d1 + isc.ax)), pow2(-(dre + isc.a4)));
     // db2 (passive sums plus the routed one-hots) and db5
 #pragma unroll
     for (int ob = 0; ob < 4; ++ob) {
@@ -1323,7 +1402,7 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
         const int c = threadIdx.x;
         float t = S.vred[0][c];
         for (int w = 1; w < kWaves; ++w) t += S.vred[w][c];
-        rec[kRecB2 + c] = t + S.vroute[c];
+        rec[kRecB2 + c] = t * pow2(-d2) + S.vroute[c];
         rec[kRecB4 + c] = S.s4[c];
         rec[kRecB3 + c] = S.dpre3[c];
         rec[kRecGp + c] = L.gp[c];     // dW4[:, 64:] = s4 (x) g'
@@ -1334,7 +1413,7 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
                 b = __int_as_float(S.ired[0][c]);
                 for (int w = 1; w < kWaves; ++w) b += __int_as_float(S.ired[w][c]);
             }
-            rec[kRecB5 + c] = b;
+            rec[kRecB5 + c] = b * pow2(-dre);
         }
     }
     __syncthreads();
@@ -1377,9 +1456,10 @@ __device__ void decay_item_bwd(const BwdParams &p, DecayLds &S, int item, int e,
     const int base = M.offset[k];
     const int n = M.offset[k + 1] - base;
     const size_t row = (size_t)e * N + base;
+    float umax;
     const int m = contact_and_compact<KIND == BWD_PROP>(M, p.scene, p.E, n_max, p.cobj_in, p.uhat_in,
                                                         KIND == BWD_STEP ? p.bwd.cobj_st : nullptr, S.wcnt, e, k,
-                                                        base, n, cand, uhn, alist, plist, nullptr);
+                                                        base, n, cand, uhn, alist, plist, nullptr, umax);
     if (threadIdx.x < 64) p.bwd.m_st[item] = m;     // identical stores
     if (m == 0) {
         if (threadIdx.x < 64) {
@@ -1519,14 +1599,18 @@ __global__ __launch_bounds__(256) void k_live_list(BwdParams p) {
 // contact results (contact_obj and u_hat of a forward or contact pass), as
 // contact_and_compact does with FROM_INPUT, but kGivenChunks chunks of kWG
 // nodes per pair of barriers: the loads are cheap and their latencies overlap.
-// Lists in ascending node order (chunk, then wave, then lane).  Returns m.
+// Lists in ascending node order (chunk, then wave, then lane).  Returns m;
+// umax / gmax: the largest |u_hat| component over the item's nodes and the
+// largest |dL/dU| component (grad_u) over its passive nodes.
 __device__ int compact_given(int E, int N, int n_max, const int8_t *cobj_in, const float *uhat_in,
-                             int (&wcnt)[kGivenChunks][2][kWaves], int e, int base, int n, float *uhn, int *alist,
-                             int *plist, int8_t *wobj) {
+                             const float *grad_u, int (&wcnt)[kGivenChunks][2][kWaves], int (&wmx)[2][kWaves],
+                             int e, int base, int n, float *uhn, int *alist, int *plist, int8_t *wobj, float &umax,
+                             float &gmax) {
     constexpr int G = kGivenChunks;
     const size_t EN = (size_t)E * N;
     const int wave = threadIdx.x >> 6;
     int run_a = 0, run_p = 0;
+    int ubits = 0, gbits = 0;   // bits of non-negative floats: integer order is float order
     for (int g0 = 0; g0 < n; g0 += G * kWG) {
         bool act[G], pas[G];
 #pragma unroll
@@ -1542,6 +1626,10 @@ __device__ int compact_given(int E, int N, int n_max, const int8_t *cobj_in, con
                     u0 = uhat_in[en];
                     u1 = uhat_in[EN + en];
                     u2 = uhat_in[2 * EN + en];
+                    ubits = max(ubits, __float_as_int(fmaxf(fmaxf(fabsf(u0), fabsf(u1)), fabsf(u2))));
+                } else {
+                    const float g0 = grad_u[en], g1 = grad_u[EN + en], g2 = grad_u[2 * EN + en];
+                    gbits = max(gbits, __float_as_int(fmaxf(fmaxf(fabsf(g0), fabsf(g1)), fabsf(g2))));
                 }
                 uhn[i] = u0;
                 uhn[n_max + i] = u1;
@@ -1551,6 +1639,8 @@ __device__ int compact_given(int E, int N, int n_max, const int8_t *cobj_in, con
             act[c] = valid && best >= 0;
             pas[c] = valid && best < 0;
         }
+        wmx[0][wave] = wave_max_int(ubits);
+        wmx[1][wave] = wave_max_int(gbits);
         unsigned long long ba[G], bp[G];
 #pragma unroll
         for (int c = 0; c < G; ++c) {
@@ -1575,6 +1665,15 @@ __device__ int compact_given(int E, int N, int n_max, const int8_t *cobj_in, con
             run_a += uniform(ta);
             run_p += uniform(tp);
         }
+        if (g0 + G * kWG >= n) {   // last pass: the wave maxima cover every node of the item
+            int ub = 0, gb = 0;
+            for (int w = 0; w < kWaves; ++w) {
+                ub = max(ub, wmx[0][w]);
+                gb = max(gb, wmx[1][w]);
+            }
+            umax = __int_as_float(uniform(ub));
+            gmax = __int_as_float(uniform(gb));
+        }
         __syncthreads();
     }
     return uniform(run_a);
@@ -1597,11 +1696,14 @@ __device__ void process_item_bwd(const BwdParams &p, BwdLds &S, int item, int e,
     const int8_t *cin = KIND == BWD_STEP ? p.bwd.cobj_st : p.cobj_in;
     const float *uin = KIND == BWD_STEP ? p.bwd.uhat_st : p.uhat_in;
     int m;
+    float umax = 0.0f, gmax = 0.0f;
     if constexpr (KIND == BWD_CONTACT)
-        m = contact_and_compact<false>(M, p.scene, p.E, n_max, nullptr, nullptr, nullptr, S.wcnt[0], e, k, base, n,
-                                       cand, uhn, alist, plist, wobj);
+        m = contact_and_compact<false>(M, p.scene, p.E, n_max, nullptr, nullptr, nullptr,
+                                       *reinterpret_cast<int (*)[3][kWaves]>(&S.wcnt[0][0][0]), e, k, base, n,
+                                       cand, uhn, alist, plist, wobj, umax);
     else
-        m = compact_given(p.E, N, n_max, cin, uin, S.wcnt, e, base, n, uhn, alist, plist, wobj);
+        m = compact_given(p.E, N, n_max, cin, uin, p.grad_u, S.wcnt, S.wmx, e, base, n, uhn, alist, plist, wobj,
+                          umax, gmax);
     if (m == 0) {
         // contact adjoint only: the other kinds never queue items without contact
         if (threadIdx.x < 64) p.bwd.item_flag[item] = 0;
@@ -1617,7 +1719,8 @@ __device__ void process_item_bwd(const BwdParams &p, BwdLds &S, int item, int e,
         gh[2 * n_max + j] = g0[2 * EN + row + j];
     }
     __syncthreads();
-    if (KIND != BWD_CONTACT && uses_residual(p)) residual_adjoint(p, S, e, k, item, base, n, n - m, plist, uhn, wobj, gh);
+    if (KIND != BWD_CONTACT && uses_residual(p))
+        residual_adjoint(p, S, e, k, item, base, n, n - m, plist, uhn, wobj, gh, umax, gmax);
     if (threadIdx.x < 64) p.bwd.item_flag[item] = (KIND != BWD_CONTACT && uses_residual(p)) ? 1 : 0;
     __syncthreads();
     if (KIND == BWD_PROP) {

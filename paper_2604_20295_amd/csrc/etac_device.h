@@ -243,10 +243,25 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 // re-enter the barrier and read stale LDS).
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ unsigned uniform(unsigned v) { return (unsigned)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ float uniform(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
 
 __device__ __forceinline__ unsigned lanes_below(unsigned long long mask) {
     return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
                                      __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+// Maximum over the wave, returned in every lane.
+__device__ __forceinline__ int wave_max_int(int v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+    return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -389,13 +404,14 @@ __device__ int next_batch(unsigned *counter, ItemBatch &B, const MeshDev &M, con
 // contact_obj into `cobj_out` when computing contact.  Returns m.
 template <bool FROM_INPUT>
 __device__ int contact_and_compact(const MeshDev &M, const SceneDev &Sc, int E, int n_max, const int8_t *cobj_in,
-                                   const float *uhat_in, int8_t *cobj_out, int (&wcnt)[2][kWaves], int e, int k,
+                                   const float *uhat_in, int8_t *cobj_out, int (&wcnt)[3][kWaves], int e, int k,
                                    int base, int n, unsigned cand, float *uhn, int *alist, int *plist,
-                                   int8_t *wobj) {
+                                   int8_t *wobj, float &umax) {
     const int N = M.N;
     const size_t EN = (size_t)E * N;
     const int wave = threadIdx.x >> 6;
     int run_a = 0, run_p = 0;
+    int ubits = 0;   // largest |u_hat| component of this thread's nodes (bits of a non-negative float)
     for (int i0 = 0; i0 < n; i0 += kWG) {
         const int i = i0 + threadIdx.x;
         const bool valid = i < n;
@@ -420,12 +436,14 @@ __device__ int contact_and_compact(const MeshDev &M, const SceneDev &Sc, int E, 
             uhn[n_max + i] = u1;
             uhn[2 * n_max + i] = u2;
             if (wobj) wobj[i] = (int8_t)best;
+            ubits = max(ubits, __float_as_int(fmaxf(fmaxf(fabsf(u0), fabsf(u1)), fabsf(u2))));
         }
         const bool act = valid && best >= 0, pas = valid && best < 0;
         const unsigned long long ba = __ballot(act), bp = __ballot(pas);
         // every lane stores the same wave counts (no single-lane block next to the barrier)
         wcnt[0][wave] = __popcll(ba);
         wcnt[1][wave] = __popcll(bp);
+        wcnt[2][wave] = wave_max_int(ubits);
         __syncthreads();
         int oa = run_a, op = run_p, ta = 0, tp = 0;
         for (int w = 0; w < kWaves; ++w) {
@@ -437,6 +455,11 @@ __device__ int contact_and_compact(const MeshDev &M, const SceneDev &Sc, int E, 
         if (pas) plist[op + lanes_below(bp)] = i;
         run_a += uniform(ta);
         run_p += uniform(tp);
+        if (i0 + kWG >= n) {   // last chunk: the wave maxima cover every node of the item
+            int ub = 0;
+            for (int w = 0; w < kWaves; ++w) ub = max(ub, wcnt[2][w]);
+            umax = __int_as_float(uniform(ub));
+        }
         __syncthreads();
     }
     return uniform(run_a);
@@ -451,6 +474,21 @@ __device__ int contact_and_compact(const MeshDev &M, const SceneDev &Sc, int E, 
 // The dropped lo*lo term is ~2^-22 relative, so a layer keeps FP32-level
 // accuracy at the FP16 matrix rate (about 5x the FP32 matrix rate).
 //
+// Range.  The pair keeps 22 bits only while |x| lies in [2^-3, 2^15]: above
+// 65504 hi overflows, below 2^-3 lo is subnormal (absolute floor 2^-25).  So
+// every split operand carries a power-of-two scale that keeps it below 2^15
+// (T) with its bound within a factor two of T; a block's small elements then
+// lose relative precision only below 2^-40 of that bound.  The node inputs
+// are scaled per item (2^ax from X, the largest |component| of the item's
+// inputs, at least 1).  The weights are scaled per launch by constants
+// chosen from their infinity norms (largest row sum of |w|, or column sum
+// for a transposed use) so that the products land below T without a
+// rescale: |h1| <= (||W1|| + 2 max|b1|) T 2^s1 < T for inputs below T, and so
+// on through the layers.  The biases follow the item's scales.  Powers of
+// two are exact: the scaling changes no value beyond the rounding of the
+// splits.  (A weight block whose scaled maximum falls below 2^-3 keeps
+// 2^-25 absolute accuracy, about 2^-19 of its largest element at worst.)
+//
 // A 16-node tile is processed by one wave in transposed form, Y^T = W X^T:
 // the MFMA's M dimension is the layer's output features, N the 16 nodes, K the
 // input features.  Lane l holds node (l & 15).  After a layer it holds output
@@ -463,16 +501,47 @@ __device__ int contact_and_compact(const MeshDev &M, const SceneDev &Sc, int E, 
 // ---------------------------------------------------------------------------
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 
+constexpr int kTopExp = 15;   // scaled operand bounds lie in [2^14, 2^15): T = 2^15
+constexpr float kTop = 32768.0f;
+
+// Exponent s of the scale 2^s that puts `bound` in [2^(kTopExp-1), 2^kTopExp);
+// 0 for a zero or non-finite bound; clamped to [-100, 100].
+__device__ __forceinline__ int range_exp(float bound) {
+    if (!(bound > 0.0f) || !(bound <= 3.0e38f)) return 0;
+    int e;
+    (void)frexpf(bound, &e);   // bound = m 2^e, m in [0.5, 1)
+    return max(-100, min(100, kTopExp - e));
+}
+
+// 2^s, exact for -149 <= s <= 127 (subnormal below -126).
+__device__ __forceinline__ float pow2(int s) { return ldexpf(1.0f, s); }
+
+// Scales of one item's activations (uniform; every thread computes the same
+// values).  X bounds every component of the item's node inputs.
+// Scales of one item's activations: x at 2^ax, h1 at 2^a1 = 2^(s1 + ax),
+// f at 2^af = 2^(s2 + a1), h4 at 2^a4 = 2^(s4 + af).
+struct ItemScale {
+    int ax, a1, af, a4;
+    float xmul;          // 2^ax
+};
+
 struct NetLds {
-    half8 w1h[4 * 64], w1l[4 * 64];          // [ot][lane]    W1, inputs padded 9 -> 32 (one K step)
-    half8 w2h[4 * 2 * 64], w2l[4 * 2 * 64];  // [ot2][s][lane] W2
-    half8 w4h[4 * 2 * 64], w4l[4 * 2 * 64];  // [ot2][s][lane] W4 columns 0..63 (per-node part)
+    half8 w1h[4 * 64], w1l[4 * 64];          // [ot][lane]    W1 2^s1, inputs padded 9 -> 32 (one K step)
+    half8 w2h[4 * 2 * 64], w2l[4 * 2 * 64];  // [ot2][s][lane] W2 2^s2
+    half8 w4h[4 * 2 * 64], w4l[4 * 2 * 64];  // [ot2][s][lane] W4 columns 0..63 (per-node part) 2^s4
     float b1[64], b2[64];
-    float c4[64];                            // W4[:, 64:] g' + b4, per item
+    float b1s[64], b2s[64];                  // per item: b1 2^a1, b2 2^af
+    float c4[64];                            // per item: (W4[:, 64:] g' + b4) 2^a4
     float w5[3 * 64];
     float b5[4];
-    float g[64], gp[64];                     // pooled feature and global MLP output
+    float g[64], gp[64];                     // pooled feature and global MLP output (unscaled)
     float part[kWaves][64];                  // per-wave partials
+    // per launch: scale exponents of the staged weights (W1 2^s1, W2 2^s2,
+    // W4[:, :64] 2^s4) and of the adjoint's transposed uses (W5^T 2^c5t,
+    // W4[:, :64]^T 2^s4t, W2^T 2^s2t)
+    int s1, s2, s4, c5t, s4t, s2t;
+    float mw2;               // max |W2|
+    ItemScale isc;           // per item: the activation scales (a copy for readers that re-read them)
 };
 
 typedef _Float16 half2t __attribute__((ext_vector_type(2)));
@@ -515,18 +584,75 @@ __device__ __forceinline__ void split8(const float v[8], half8 &hi, half8 &lo) {
 // Input feature of K step s, lane group q, element e of a 64 -> 64 layer.
 __device__ __forceinline__ int chain_k(int s, int q, int e) { return 16 * (2 * s + (e >> 2)) + 4 * q + (e & 3); }
 
-// Stage the network into LDS in fragment order (whole workgroup).
+// Per-launch quantities of the range scaling (whole workgroup; the caller
+// brackets it with barriers).  Wave w takes rows (or columns) 16 w + (l & 15);
+// lane group q = l >> 4 sums a quarter of each, the quarters are added with
+// two shuffles and the wave's largest sum goes to L.part.
+__device__ void net_norms(NetLds &L, const float *phi) {
+    const int lane = lane_id(), wave = threadIdx.x >> 6, q = lane >> 4;
+    const int r = 16 * wave + (lane & 15);
+    float s1 = 0.0f, s2 = 0.0f, s4 = 0.0f, t2 = 0.0f, t4 = 0.0f, t5 = 0.0f;
+    float m2 = 0.0f, m4 = 0.0f, mb1 = 0.0f, mb2 = 0.0f;
+    for (int c = 16 * q; c < 16 * q + 16; ++c) {
+        const float a = fabsf(phi[kW2 + r * 64 + c]), b = fabsf(phi[kW4 + r * 128 + c]);
+        s2 += a; s4 += b;
+        m2 = fmaxf(m2, a); m4 = fmaxf(m4, b);
+        t2 += fabsf(phi[kW2 + c * 64 + r]);
+        t4 += fabsf(phi[kW4 + c * 128 + r]);
+    }
+    if (q == 0) {
+        for (int c = 0; c < 9; ++c) s1 += fabsf(phi[kW1 + r * 9 + c]);
+        for (int c = 0; c < 3; ++c) t5 += fabsf(phi[kW5 + c * 64 + r]);
+        mb1 = fabsf(phi[kB1 + r]);
+        mb2 = fabsf(phi[kB2 + r]);
+    }
+    float v[10] = {s1, s2, s4, t2, t4, t5, m2, m4, mb1, mb2};
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {   // sums over the four quarters
+        v[j] += __shfl_xor(v[j], 16);
+        v[j] += __shfl_xor(v[j], 32);
+    }
+#pragma unroll
+    for (int j = 0; j < 10; ++j) {
+        v[j] = wave_max(v[j]);
+        L.part[wave][j] = v[j];      // identical in every lane
+    }
+}
+
+// Stage the network into LDS in fragment order (whole workgroup), each
+// weight matrix scaled by its per-launch power of two, and set the scale
+// exponents.  With inputs x 2^ax below T (X at least 1, so 2^ax <= 2T):
+//   h1 = W1 2^s1 x + b1 2^a1:  |h1| <= (||W1|| + 2 max|b1|) T 2^s1 < T,
+//   f  = W2 2^s2 h1 + b2 2^af: |f| <= (||W2|| T + 2 max|b2| T 2^s1) 2^s2 < T,
+//   h4 = W4 2^s4 f + c4 2^a4 with s4 from max |W4[:, :64]| (h4 is never split).
+// Adjoint, with dL/dU 2^dre below T: W5^T 2^c5t, W4[:, :64]^T 2^s4t and W2^T
+// 2^s2t by their column norms keep dL/dpre4, dL/dpre2 and dL/dpre1 below T.
+// Ends with a barrier.
 __device__ void stage_net(NetLds &L, const float *phi) {
     const int tid = threadIdx.x;
+    net_norms(L, phi);
+    __syncthreads();
+    float v[10];
+#pragma unroll
+    for (int j = 0; j < 10; ++j) {
+        v[j] = L.part[0][j];
+        for (int w = 1; w < kWaves; ++w) v[j] = fmaxf(v[j], L.part[w][j]);
+    }
+    const float n1 = v[0], n2 = v[1], n4t = v[4], n2t = v[3], n5t = v[5];
+    const float mw2 = v[6], mw4 = v[7], mb1 = v[8], mb2 = v[9];
+    const int s1 = range_exp((n1 + 2.0f * mb1) * kTop);
+    const int s2 = range_exp((n2 * kTop + 2.0f * mb2 * kTop * pow2(s1)));
+    const int s4 = range_exp(mw4);
+    const float e1 = pow2(s1), e2 = pow2(s2), e4 = pow2(s4);
     for (int idx = tid; idx < 4 * 64; idx += kWG) {
         const int lane = idx & 63, ot = idx >> 6, q = lane >> 4;
-        float v[8];
+        float x[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int in = 8 * q + e;
-            v[e] = in < 9 ? phi[kW1 + (ot * 16 + (lane & 15)) * 9 + in] : 0.0f;
+            x[e] = in < 9 ? phi[kW1 + (ot * 16 + (lane & 15)) * 9 + in] * e1 : 0.0f;
         }
-        split8(v, L.w1h[idx], L.w1l[idx]);
+        split8(x, L.w1h[idx], L.w1l[idx]);
     }
     for (int idx = tid; idx < 4 * 2 * 64; idx += kWG) {
         const int lane = idx & 63, s = (idx >> 6) & 1, ot2 = idx >> 7, q = lane >> 4;
@@ -535,8 +661,8 @@ __device__ void stage_net(NetLds &L, const float *phi) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int in = chain_k(s, q, e);
-            a[e] = phi[kW2 + out * 64 + in];
-            b[e] = phi[kW4 + out * 128 + in];
+            a[e] = phi[kW2 + out * 64 + in] * e2;
+            b[e] = phi[kW4 + out * 128 + in] * e4;
         }
         split8(a, L.w2h[idx], L.w2l[idx]);
         split8(b, L.w4h[idx], L.w4l[idx]);
@@ -547,6 +673,53 @@ __device__ void stage_net(NetLds &L, const float *phi) {
     }
     for (int i = tid; i < 192; i += kWG) L.w5[i] = phi[kW5 + i];
     for (int i = tid; i < 4; i += kWG) L.b5[i] = i < 3 ? phi[kB5 + i] : 0.0f;
+    if (tid < 64) {   // wave 0, identical values
+        L.s1 = s1; L.s2 = s2; L.s4 = s4;
+        L.c5t = range_exp(n5t * kTop);
+        L.s4t = range_exp(n4t * kTop);
+        L.s2t = range_exp(n2t * kTop);
+        L.mw2 = mw2;
+    }
+    __syncthreads();
+}
+
+// Scales of the activations of an item whose inputs are bounded by X
+// (uniform; every thread computes the same values, kept in scalar registers).
+__device__ __forceinline__ ItemScale item_scale(const NetLds &L, float X) {
+    ItemScale s;
+    s.ax = uniform(range_exp(fmaxf(X, 1.0f)));
+    s.a1 = uniform(L.s1) + s.ax;
+    s.af = uniform(L.s2) + s.a1;
+    s.a4 = uniform(L.s4) + s.af;
+    s.xmul = uniform(pow2(s.ax));
+    return s;
+}
+
+// Scaled biases of the item's encoder layers and a copy of the scales in
+// L.isc (threads < 64; the caller's next barrier publishes them).
+__device__ __forceinline__ void item_biases(NetLds &L, const ItemScale &s) {
+    if (threadIdx.x < 64) {
+        const int i = threadIdx.x;
+        L.b1s[i] = L.b1[i] * pow2(s.a1);
+        L.b2s[i] = L.b2[i] * pow2(s.af);
+        L.isc = s;   // identical values from every lane
+    }
+}
+
+// The item's scales as published by item_biases, in scalar registers.
+__device__ __forceinline__ ItemScale item_scale_lds(const NetLds &L) {
+    ItemScale s;
+    s.ax = uniform(L.isc.ax);
+    s.a1 = uniform(L.isc.a1);
+    s.af = uniform(L.isc.af);
+    s.a4 = uniform(L.isc.a4);
+    s.xmul = uniform(L.isc.xmul);
+    return s;
+}
+
+// Input bound of item (patch k) given the largest |u_hat| component of its nodes.
+__device__ __forceinline__ float item_xbound(const MeshDev &M, int k, float umax) {
+    return fmaxf(M.xbound[k], umax);
 }
 
 // Keeps the compiler from hoisting the (loop-invariant) LDS weight-fragment
@@ -589,10 +762,11 @@ __device__ __forceinline__ void split_chain(const floatx4 x[4], half8 bh[2], hal
     }
 }
 
-// Network input of this lane's node: lane group q = lane >> 4 supplies input
-// features 8 q .. 8 q + 7 of [p - o_k (3), n (3), U_hat (3)], zero padded to 32.
+// Network input of this lane's node, scaled by xmul: lane group q = lane >> 4
+// supplies input features 8 q .. 8 q + 7 of [p - o_k (3), n (3), U_hat (3)],
+// zero padded to 32.
 __device__ __forceinline__ void load_x_raw(const MeshDev &M, int k, int gnode, bool valid, const float *uhn,
-                                           int n_max, int lnode, float (&v)[8]) {
+                                           int n_max, int lnode, float xmul, float (&v)[8]) {
     const int q = lane_id() >> 4;
     const int N = M.N;
 #pragma unroll
@@ -600,21 +774,14 @@ __device__ __forceinline__ void load_x_raw(const MeshDev &M, int k, int gnode, b
     if (valid && q == 0) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            v[a] = M.pos[(size_t)a * N + gnode] - M.origin[3 * k + a];
-            v[3 + a] = M.nrm[(size_t)a * N + gnode];
+            v[a] = (M.pos[(size_t)a * N + gnode] - M.origin[3 * k + a]) * xmul;
+            v[3 + a] = M.nrm[(size_t)a * N + gnode] * xmul;
         }
-        v[6] = uhn[lnode];
-        v[7] = uhn[(size_t)n_max + lnode];
+        v[6] = uhn[lnode] * xmul;
+        v[7] = uhn[(size_t)n_max + lnode] * xmul;
     } else if (valid && q == 1) {
-        v[0] = uhn[(size_t)2 * n_max + lnode];
+        v[0] = uhn[(size_t)2 * n_max + lnode] * xmul;
     }
-}
-
-__device__ __forceinline__ void load_x(const MeshDev &M, int k, int gnode, bool valid, const float *uhn, int n_max,
-                                       int lnode, half8 &xh, half8 &xl) {
-    float v[8];
-    load_x_raw(M, k, gnode, valid, uhn, n_max, lnode, v);
-    split8(v, xh, xl);
 }
 
 // y = W x + acc over the two K steps of a 64 -> 64 layer in T form; the three
@@ -651,25 +818,27 @@ __device__ __forceinline__ void layer64_t(const half8 *wh, const half8 *wl, cons
 constexpr int kStage = 1024;
 typedef float StageBuf[9][kStage];
 
-// Stage nodes c0 + j (list == nullptr) or list[c0 + j], j < cnt; the third
-// triple is third[c * stride + off + node] (zeros when third is null).
+// Stage nodes c0 + j (list == nullptr) or list[c0 + j], j < cnt; the
+// geometric features are multiplied by xmul, the third triple
+// third[c * stride + off + node] by tmul (zeros when third is null).
 // Whole workgroup; the caller brackets it with barriers.
 __device__ __forceinline__ void stage_nodes(const MeshDev &M, int k, int base, const int *list, int c0, int cnt,
-                                            const float *third, size_t stride, size_t off, StageBuf &xs) {
+                                            const float *third, size_t stride, size_t off, float xmul, float tmul,
+                                            StageBuf &xs) {
     const int N = M.N;
     const float o0 = M.origin[3 * k], o1 = M.origin[3 * k + 1], o2 = M.origin[3 * k + 2];
     for (int j = threadIdx.x; j < cnt; j += kWG) {
         const int i = list ? list[c0 + j] : c0 + j;
         const int g = base + i;
-        xs[0][j] = M.pos[g] - o0;
-        xs[1][j] = M.pos[N + g] - o1;
-        xs[2][j] = M.pos[2 * N + g] - o2;
-        xs[3][j] = M.nrm[g];
-        xs[4][j] = M.nrm[N + g];
-        xs[5][j] = M.nrm[2 * N + g];
-        xs[6][j] = third ? third[off + i] : 0.0f;
-        xs[7][j] = third ? third[stride + off + i] : 0.0f;
-        xs[8][j] = third ? third[2 * stride + off + i] : 0.0f;
+        xs[0][j] = (M.pos[g] - o0) * xmul;
+        xs[1][j] = (M.pos[N + g] - o1) * xmul;
+        xs[2][j] = (M.pos[2 * N + g] - o2) * xmul;
+        xs[3][j] = M.nrm[g] * xmul;
+        xs[4][j] = M.nrm[N + g] * xmul;
+        xs[5][j] = M.nrm[2 * N + g] * xmul;
+        xs[6][j] = third ? third[off + i] * tmul : 0.0f;
+        xs[7][j] = third ? third[stride + off + i] * tmul : 0.0f;
+        xs[8][j] = third ? third[2 * stride + off + i] * tmul : 0.0f;
     }
 }
 
@@ -693,7 +862,8 @@ __device__ __forceinline__ void stage_x(const StageBuf &xs, int j, bool valid, h
     split8(v, xh, xl);
 }
 
-// Encoder: h1 = relu(W1 x + b1), f = relu(W2 h1 + b2) for a 16-node tile.
+// Encoder: h1 = relu(W1 x + b1), f = relu(W2 h1 + b2) for a 16-node tile of
+// scaled inputs (2^ax x); h1 and f come out at the item's scales 2^a1, 2^af.
 __device__ __forceinline__ void encoder_tile(const NetLds &L, const half8 &xh, const half8 &xl, floatx4 h1[4],
                                              floatx4 f[4]) {
     reload_fence();
@@ -703,7 +873,7 @@ __device__ __forceinline__ void encoder_tile(const NetLds &L, const half8 &xh, c
     for (int ot = 0; ot < 4; ++ot) {
         wh[ot] = L.w1h[ot * 64 + lane];
         wl[ot] = L.w1l[ot * 64 + lane];
-        h1[ot] = *reinterpret_cast<const floatx4 *>(&L.b1[ot * 16 + 4 * gq]);
+        h1[ot] = *reinterpret_cast<const floatx4 *>(&L.b1s[ot * 16 + 4 * gq]);
     }
 #pragma unroll
     for (int ot = 0; ot < 4; ++ot) h1[ot] = mfma16(wh[ot], xh, h1[ot]);
@@ -714,7 +884,7 @@ __device__ __forceinline__ void encoder_tile(const NetLds &L, const half8 &xh, c
     half8 bh[2], bl[2];
     split_chain(h1, bh, bl);
 #pragma unroll
-    for (int ot = 0; ot < 4; ++ot) f[ot] = *reinterpret_cast<const floatx4 *>(&L.b2[ot * 16 + 4 * gq]);
+    for (int ot = 0; ot < 4; ++ot) f[ot] = *reinterpret_cast<const floatx4 *>(&L.b2s[ot * 16 + 4 * gq]);
     layer64_t(L.w2h, L.w2l, bh, bl, f);
 #pragma unroll
     for (int ot = 0; ot < 4; ++ot) f[ot] = relu4(f[ot]);
@@ -733,7 +903,7 @@ __device__ __forceinline__ void encoder_tile2(const NetLds &L, const half8 (&xh)
         for (int ot = 0; ot < 4; ++ot) {
             wh[ot] = L.w1h[ot * 64 + lane];
             wl[ot] = L.w1l[ot * 64 + lane];
-            const floatx4 b = *reinterpret_cast<const floatx4 *>(&L.b1[ot * 16 + 4 * gq]);
+            const floatx4 b = *reinterpret_cast<const floatx4 *>(&L.b1s[ot * 16 + 4 * gq]);
             h1[0][ot] = b;
             h1[1][ot] = b;
         }
@@ -755,7 +925,7 @@ __device__ __forceinline__ void encoder_tile2(const NetLds &L, const half8 (&xh)
     for (int u = 0; u < 2; ++u) split_chain(h1[u], bh[u], bl[u]);
 #pragma unroll
     for (int ot = 0; ot < 4; ++ot) {
-        const floatx4 b = *reinterpret_cast<const floatx4 *>(&L.b2[ot * 16 + 4 * gq]);
+        const floatx4 b = *reinterpret_cast<const floatx4 *>(&L.b2s[ot * 16 + 4 * gq]);
         f[0][ot] = b;
         f[1][ot] = b;
     }
@@ -787,8 +957,10 @@ __device__ __forceinline__ void encoder_tile2(const NetLds &L, const half8 (&xh)
 }
 
 // Decoder: h4 = relu(W4 [f; g'] + b4) with the g' part folded into c4, then
-// r = W5 h4 + b5.  Every lane returns r of its node (lane & 15).
-__device__ __forceinline__ void decoder_tile(const NetLds &L, const floatx4 f[4], floatx4 h4[4], float r_out[3]) {
+// r = W5 h4 + b5.  h4 comes out at 2^a4 and r_mul = 2^-a4 unscales the W5
+// sum.  Every lane returns r of its node (lane & 15).
+__device__ __forceinline__ void decoder_tile(const NetLds &L, const floatx4 f[4], float r_mul, floatx4 h4[4],
+                                             float r_out[3]) {
     reload_fence();
     const int lane = lane_id(), gq = lane >> 4;
     half8 bh[2], bl[2];
@@ -808,14 +980,15 @@ __device__ __forceinline__ void decoder_tile(const NetLds &L, const floatx4 f[4]
         }
         s += __shfl_xor(s, 16);
         s += __shfl_xor(s, 32);
-        r_out[c] = s + L.b5[c];
+        r_out[c] = s * r_mul + L.b5[c];
     }
 }
 
-// Global MLP of one item from the pooled feature in L.g:
-// g' = relu(W3 g + b3) and c4 = W4[:, 64:] g' + b4.  Whole workgroup; each
-// wave sums 16 input features and the four partials are added in wave order.
-__device__ void global_mlp(NetLds &L, const float *phi) {
+// Global MLP of one item from the (unscaled) pooled feature in L.g:
+// g' = relu(W3 g + b3) and c4 = W4[:, 64:] g' + b4, stored at h4's scale
+// 2^a4.  Whole workgroup; each wave sums 16 input features and the four
+// partials are added in wave order.
+__device__ void global_mlp(NetLds &L, const float *phi, const ItemScale &sc) {
     const int tid = threadIdx.x, o = tid & 63, w = tid >> 6;
     float acc = 0.0f;
     for (int c = 16 * w; c < 16 * w + 16; ++c) acc += phi[kW3 + o * 64 + c] * L.g[c];
@@ -834,7 +1007,7 @@ __device__ void global_mlp(NetLds &L, const float *phi) {
     if (tid < 64) {
         float s = phi[kB4 + o];
         for (int q = 0; q < kWaves; ++q) s += L.part[q][o];
-        L.c4[o] = s;
+        L.c4[o] = s * pow2(sc.a4);
     }
     __syncthreads();
 }

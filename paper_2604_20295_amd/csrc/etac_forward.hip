@@ -100,7 +100,7 @@ struct StepLds {
         };
         StageBuf xs;                 // node inputs of the network passes (before the decay)
     };
-    int wcnt[2][kWaves];
+    int wcnt[3][kWaves];
     ItemBatch batch;
 };
 
@@ -165,12 +165,15 @@ __device__ void zero_fill_batch(const StepParams &p, const ItemBatch &B, int b0)
 // global MLP, then the decoder pass writing r into `resid` ([3][n_max]) for
 // the passive nodes (plist[0 .. np)), the only ones whose residual is used.
 // The encoder is recomputed in the decoder pass instead of keeping n x 64
-// features.
+// features.  umax: the largest |u_hat| component of the item's nodes (with
+// the patch's geometry it bounds the network inputs: the range scaling).
 __device__ void residual_item(const StepParams &p, StepLds &S, int item, int k, int base, int n, const float *uhn,
-                              const int *plist, int np, float *resid) {
+                              const int *plist, int np, float *resid, float umax) {
     NetLds &L = S.net;
     const int lane = lane_id(), wave = threadIdx.x >> 6, gq = lane >> 4;
     const int n_max = p.scr.n_max;
+    const ItemScale sc = item_scale(L, item_xbound(p.mesh, k, umax));
+    item_biases(L, sc);    // published by the first stage barrier
     // max-pool with arg-max (lowest node on ties); f >= 0 beats the initial -1
     floatx4 mx[4];
     int mi[4][4];
@@ -181,7 +184,7 @@ __device__ void residual_item(const StepParams &p, StepLds &S, int item, int k, 
     for (int c0 = 0; c0 < n; c0 += kStage) {
         const int cnt = min(kStage, n - c0);
         __syncthreads();
-        stage_nodes(p.mesh, k, base, nullptr, c0, cnt, uhn, n_max, 0, S.xs);
+        stage_nodes(p.mesh, k, base, nullptr, c0, cnt, uhn, n_max, 0, sc.xmul, sc.xmul, S.xs);
         __syncthreads();
         // two tiles per wave step (t and t + kWaves); the second may be padding
         const int ntl = (cnt + 15) >> 4;
@@ -245,6 +248,7 @@ __device__ void residual_item(const StepParams &p, StepLds &S, int item, int k, 
             const int i2 = ipart[w][c];
             if (v2 > v || (v2 == v && i2 < ix)) { v = v2; ix = i2; }
         }
+        v *= pow2(-sc.af);    // the pooled feature, unscaled
         L.g[c] = v;
         if (p.saved) {
             uint32_t *rec = p.saved + (size_t)item * kSavedWords;
@@ -253,11 +257,12 @@ __device__ void residual_item(const StepParams &p, StepLds &S, int item, int k, 
         }
     }
     __syncthreads();
-    global_mlp(L, p.model.phi);
+    global_mlp(L, p.model.phi, sc);
+    const float r_mul = pow2(-sc.a4);
     for (int c0 = 0; c0 < np; c0 += kStage) {
         const int cnt = min(kStage, np - c0);
         __syncthreads();
-        stage_nodes(p.mesh, k, base, plist, c0, cnt, nullptr, 0, 0, S.xs);   // passive: U_hat = 0
+        stage_nodes(p.mesh, k, base, plist, c0, cnt, nullptr, 0, 0, sc.xmul, 0.0f, S.xs);   // passive: U_hat = 0
         __syncthreads();
         const int ptl = (cnt + 15) >> 4;
         for (int t = wave; t < ptl; t += kWaves) {
@@ -268,7 +273,7 @@ __device__ void residual_item(const StepParams &p, StepLds &S, int item, int k, 
             floatx4 h1[4], f[4], h4[4];
             encoder_tile(L, xh, xl, h1, f);
             float r[3];
-            decoder_tile(L, f, h4, r);
+            decoder_tile(L, f, r_mul, h4, r);
             if (valid && gq < 3) resid[gq * n_max + plist[c0 + lj]] = r[gq];
         }
     }
@@ -432,8 +437,9 @@ __device__ void process_item(const StepParams &p, StepLds &S, int e, int k, unsi
     const int base = M.offset[k];
     const int n = M.offset[k + 1] - base;
     const int mode = p.model.mode;
+    float umax;
     const int m = contact_and_compact<FROM_INPUT>(M, p.scene, p.E, p.scr.n_max, p.cobj_in, p.uhat_in, p.cobj_out,
-                                                  S.wcnt, e, k, base, n, cand, uhn, alist, plist, nullptr);
+                                                  S.wcnt, e, k, base, n, cand, uhn, alist, plist, nullptr, umax);
     if (!FROM_INPUT && threadIdx.x < 64) p.n_active[(size_t)e * M.K + k] = m;
     if (m == 0) {
         write_zero_item(p, e, base, n, false);
@@ -450,7 +456,7 @@ __device__ void process_item(const StepParams &p, StepLds &S, int e, int k, unsi
     }
     const bool use_res = mode != ETAC_DECAY_ONLY, use_dec = mode != ETAC_RESIDUAL_ONLY;
     const int np = n - m;
-    if (use_res) residual_item(p, S, e * M.K + k, k, base, n, uhn, plist, np, resid);
+    if (use_res) residual_item(p, S, e * M.K + k, k, base, n, uhn, plist, np, resid, umax);
     // exp(-alpha d) = exp2(-alpha log2(e) d)
     const float nbeta = (float)(-(double)p.model.alpha[k] * 1.4426950408889634);
     float cut2 = cutoff_d2(p.model.alpha[k]);

@@ -28,6 +28,7 @@ struct MeshDev {
     const float4 *bound;   // [K] conservative bounding sphere (cx, cy, cz, radius)
     const int16_t *node_patch;  // [N] patch of each node
     const int *order;      // [K] patches sorted by node count, largest first
+    const float *xbound;   // [K] largest |component| of p - o_k and of n over the patch's nodes (rounded up)
     int K, N, n_max;
 };
 

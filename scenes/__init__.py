@@ -227,9 +227,10 @@ def config1(seed=0, centred=False, mode=MODE_FULL):
     return mesh, scene, model
 
 
-def config3(seeds=range(8), mode=MODE_FULL, loss_seed=1234):
-    """Config 1 pads for seeds 0..7 as 8 envs sharing the pad and the model,
-    plus loss weights w ~ N(0,1) of shape [3][E][N]."""
+def config3(seeds=range(8), mode=MODE_FULL, loss_seed=1234, model_seed=None):
+    """Config 1 pads for the given seeds (default 0..7) as envs sharing the pad
+    and the model (drawn as config 1's for model_seed, default the first
+    seed), plus loss weights w ~ N(0,1) of shape [3][E][N]."""
     mesh = pad32_mesh()
     seeds = list(seeds)
     scene = _empty_scene(len(seeds), 1)
@@ -239,7 +240,7 @@ def config3(seeds=range(8), mode=MODE_FULL, loss_seed=1234):
         scene.type[e, 0] = SPHERE
         scene.shape[e, 0, 0] = r
         scene.trans[e, 0] = (x0, y0, z0)
-    model = draw_model(np.random.default_rng([seeds[0], 1]), mesh.pitch, mode)
+    model = draw_model(np.random.default_rng([seeds[0] if model_seed is None else model_seed, 1]), mesh.pitch, mode)
     w = np.random.default_rng(loss_seed).standard_normal((3, len(seeds), mesh.n_nodes))
     return mesh, scene, model, w
 
@@ -311,19 +312,127 @@ def place_primitive(rng, mesh, ptype, shape, R, offset=HAND_OFFSET):
     return p + (h - s) * n
 
 
-def hand_scene(mesh, n_envs, seed=1, max_obj=3, offset=HAND_OFFSET, scale=1.0):
+# Footprint placement: the env's objects together cover a drawn fraction of
+# its nodes.  FOOT_GOAL is the range of that fraction; an object covers at
+# most FOOT_CAP of its patch, and its node is drawn inside the patch inset by
+# FOOT_INSET of the patch's half-extent on each side.
+FOOT_GOAL = (0.08, 0.24)
+FOOT_CAP = 0.85
+FOOT_INSET = 0.35
+# a curved patch bends away from a flat footprint: its area target is
+# enlarged by this factor
+FOOT_CURVED = 1.6
+
+
+def _frame(n, rng):
+    """Orthonormal tangent vectors (t1, t2) of unit normal n, rotated by a
+    uniform in-plane angle."""
+    a = np.array([1.0, 0.0, 0.0]) if abs(n[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    t1 = np.cross(n, a)
+    t1 /= np.linalg.norm(t1)
+    t2 = np.cross(n, t1)
+    phi = rng.uniform(0.0, 2.0 * np.pi)
+    return np.cos(phi) * t1 + np.sin(phi) * t2, -np.sin(phi) * t1 + np.cos(phi) * t2
+
+
+def _tilt(R, n, rng, max_deg=2.0):
+    """R rotated about a random tangent axis by up to max_deg degrees."""
+    t1, _ = _frame(n, rng)
+    return _rodrigues_batch(t1 * np.deg2rad(rng.uniform(-max_deg, max_deg)))[...] @ R
+
+
+def footprint_primitive(rng, n, area, scale=1.0, span=np.inf):
+    """A primitive, its rotation and its press depth along -n such that the
+    part below the tangent plane has the given cross-section area (mm^2), by
+    the closed forms of its shape (the patch's curvature is ignored):
+    sphere (r U(10, 40)) pressed d deep: pi (2 r d - d^2); capsule (r U(8, 20),
+    length U(30, 80)) with its axis in the tangent plane: a stadium of half
+    width w = sqrt(2 r d - d^2), 4 w L + pi w^2 with L at most `span` / 2 (the
+    part of the stadium over the patch); box with a face on the tangent
+    plane: the face, whose sides are set to the area (the third side
+    U(20, 60)), pressed U(1, 3) mm.  Boxes and capsules get a uniform in-plane
+    rotation and a tilt of up to 2 degrees about their centre.  Returns (type,
+    shape[4], R, depth, ext): ext is the untilted extent of the object from
+    its centre towards the surface, so the centre goes ext - depth above the
+    pressed node along its normal."""
+    ptype = int(rng.integers(0, 3))
+    shape = np.zeros(4)
+    if ptype == SPHERE:
+        r = rng.uniform(10.0, 40.0) * scale
+        r = max(r, np.sqrt(area / (0.8 * np.pi)))          # the disc must be able to reach the area
+        d = r - np.sqrt(max(r * r - area / np.pi, 0.0))
+        shape[0] = r
+        return ptype, shape, np.eye(3), d, r
+    t1, t2 = _frame(n, rng)
+    if ptype == CAPSULE:
+        r = rng.uniform(8.0, 20.0) * scale
+        L = rng.uniform(30.0, 80.0) / 2.0 * scale
+        Le = min(L, 0.5 * span)
+        # 4 w Le + pi w^2 = area  ->  w
+        w = (-4.0 * Le + np.sqrt(16.0 * Le * Le + 4.0 * np.pi * area)) / (2.0 * np.pi)
+        w = min(w, 0.95 * r)
+        d = r - np.sqrt(r * r - w * w)
+        shape[0], shape[1] = r, L
+        R = np.stack([t2, n, t1], axis=1)      # object z (the axis) along t1
+        return ptype, shape, _tilt(R, n, rng), d, r
+    a = np.sqrt(area) * np.exp(rng.uniform(-0.3, 0.3))   # face sides a x area / a
+    b = area / a
+    shape[0], shape[1], shape[2] = a / 2.0, b / 2.0, rng.uniform(20.0, 60.0) / 2.0 * scale
+    R = np.stack([t1, t2, n], axis=1)          # object z along the normal: face on the tangent plane
+    return ptype, shape, _tilt(R, n, rng), rng.uniform(1.0, 3.0) * scale, shape[2]
+
+
+def _footprint_env(rng, mesh, cnt, scale):
+    """Objects of one env placed by footprint (see FOOT_GOAL)."""
+    sizes = mesh.patch_sizes().astype(np.float64)
+    pitch = mesh.pitch
+    goal = rng.uniform(*FOOT_GOAL) * mesh.n_nodes
+    share = goal / cnt
+    fits = np.nonzero(FOOT_CAP * sizes >= share)[0]
+    if fits.size < cnt:                    # not enough patches that hold the share: the largest ones
+        fits = np.argsort(-sizes)[:max(cnt, fits.size)]
+    w = sizes[fits] / sizes[fits].sum()
+    patches = rng.choice(fits, size=cnt, replace=False, p=w)
+    out = []
+    for k in patches:
+        k = int(k)
+        nodes = min(share, FOOT_CAP * sizes[k])
+        nx, ny, rc = mesh.grid[k]
+        area = nodes * pitch[k] ** 2 * (FOOT_CURVED if rc > 0 else 1.0)
+        i = int(np.clip(np.round(rng.uniform(FOOT_INSET, 1.0 - FOOT_INSET) * (nx - 1)), 0, nx - 1))
+        j = int(np.clip(np.round(rng.uniform(FOOT_INSET, 1.0 - FOOT_INSET) * (ny - 1)), 0, ny - 1))
+        node = int(mesh.patch_offset[k]) + j * nx + i
+        p = mesh.pos[:, node].astype(np.float64)
+        n = mesh.nrm[:, node].astype(np.float64)
+        n /= np.linalg.norm(n)
+        ptype, shape, R, d, ext = footprint_primitive(rng, n, area, scale, span=min(nx, ny) * pitch[k])
+        out.append((ptype, shape, R, p + (ext - d) * n))
+    return out
+
+
+def hand_scene(mesh, n_envs, seed=1, max_obj=3, offset=HAND_OFFSET, scale=1.0, placement="footprint"):
     """Per env: object count U{1,2,3}, then per object type/shape/rotation and
     placement.  Env e draws from its own stream (seed, e) so that any subset
-    of envs can be regenerated alone.  `scale` shrinks objects and press
-    depths together (small-patch hands)."""
+    of envs can be regenerated alone.  placement "footprint" (the benchmark
+    hand): the objects cover FOOT_GOAL of the env's nodes together, each
+    pressed along the normal of a node of its own patch (footprint_primitive);
+    "press": each object's extreme point `offset` mm below a uniformly drawn
+    node in the approach direction -z, orientation uniform on SO(3).  `scale`
+    shrinks objects and press depths together (small-patch hands)."""
     scene = _empty_scene(n_envs, max_obj)
     for e in range(n_envs):
         rng = np.random.default_rng([seed, e])
         cnt = int(rng.integers(1, max_obj + 1))
         scene.n_obj[e] = cnt
-        for o in range(cnt):
-            ptype, shape, R = draw_primitive(rng, scale)
-            t = place_primitive(rng, mesh, ptype, shape, R, (offset[0] * scale, offset[1] * scale))
+        if placement == "footprint":
+            objs = _footprint_env(rng, mesh, cnt, scale)
+        else:
+            objs = []
+            for o in range(cnt):
+                ptype, shape, R = draw_primitive(rng, scale)
+                t = place_primitive(rng, mesh, ptype, shape, R, (offset[0] * scale, offset[1] * scale))
+                objs.append((ptype, shape, R, t))
+        for o, (ptype, shape, R, t) in enumerate(objs):
             scene.type[e, o] = ptype
             scene.shape[e, o] = shape
             scene.rot[e, o] = R.ravel()
@@ -331,12 +440,14 @@ def hand_scene(mesh, n_envs, seed=1, max_obj=3, offset=HAND_OFFSET, scale=1.0):
     return scene
 
 
-def config2(n_envs=4096, hand_seed=0, env_seed=1, mode=MODE_FULL, sizes=HAND_SIZES, scale=1.0):
-    """Batched forward: n_envs envs of a 16-patch hand with 1-3 primitives.
+def config2(n_envs=4096, hand_seed=0, env_seed=1, mode=MODE_FULL, sizes=HAND_SIZES, scale=1.0,
+            placement="footprint"):
+    """Batched forward: n_envs envs of a 16-patch hand with 1-3 primitives,
+    placed by footprint (the benchmark's contact band) or by press depth.
     `sizes` narrows the patch-size draw (small-patch hands for the gradient
     checks)."""
     mesh = hand_mesh(hand_seed, sizes=sizes)
-    scene = hand_scene(mesh, n_envs, env_seed, scale=scale)
+    scene = hand_scene(mesh, n_envs, env_seed, scale=scale, placement=placement)
     model = draw_model(np.random.default_rng([hand_seed, 1]), mesh.pitch, mode)
     return mesh, scene, model
 

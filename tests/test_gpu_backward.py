@@ -22,7 +22,7 @@ from tests.gpu_util import DevModel, DevScene, log, make_plan, to_dev, torch_dev
 pytestmark = pytest.mark.gpu
 
 MARGIN = 5e-6
-SMALL = dict(sizes=(64, 128, 256), scale=0.2)   # small-patch hand: many envs clear the margin
+SMALL = dict(sizes=(64, 128, 256), scale=0.2, placement="press")   # small-patch hand: many envs clear the margin
 
 
 def _close(gpu, ref, name, rel=1e-4, atol=1e-6):

@@ -55,7 +55,7 @@ def test_config3_adjoint_vs_central_fd(oracle_lib, mode):
 def test_pose_gradients_vs_fd_rotated_primitives(oracle_lib, ptype):
     # boxes and capsules in arbitrary orientation on the config-2 hand
     mesh = scenes.hand_mesh(0)
-    full = scenes.hand_scene(mesh, 64, 1)
+    full = scenes.hand_scene(mesh, 64, 1, placement="press")
     cands = [(e, o) for e in range(64) for o in range(full.n_obj[e]) if full.type[e, o] == ptype]
     model = scenes.draw_model(np.random.default_rng([0, 1]), mesh.pitch, MODE_FULL)
     rng = np.random.default_rng(5)
@@ -76,7 +76,7 @@ def test_raw_rotation_entries_vs_fd(oracle_lib):
     # grad_rot is the derivative with respect to the nine entries of R taken as
     # free inputs of the implemented function (R need not stay orthonormal).
     mesh = scenes.hand_mesh(0)
-    full = scenes.hand_scene(mesh, 64, 1)
+    full = scenes.hand_scene(mesh, 64, 1, placement="press")
     model = scenes.draw_model(np.random.default_rng([0, 1]), mesh.pitch, MODE_DECAY_ONLY)
     rng = np.random.default_rng(3)
     done = set()
