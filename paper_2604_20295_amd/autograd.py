@@ -55,12 +55,15 @@ def etac_step(plan, n_obj, type_, shape, rot, trans, alpha, phi, mode=_native.ET
 class ETacMeshStep(torch.autograd.Function):
     """The step with triangle-mesh objects (and primitives) in the scene:
     etac_contact_mesh then etac_propagate forward; etac_propagate_backward
-    then etac_contact_mesh_backward (reading the forward's contact_obj and
-    winning-triangle records) backward.  Saved: contact_obj, u_hat, the hit
-    record and the pooling record.  The plan needs ETAC_PLAN_BACKWARD."""
+    then etac_contact_mesh_backward (reading contact_obj and the
+    winning-triangle records) backward.  By default the backward runs the
+    contact pass again, so that only the inputs and the pooling record are
+    saved, as for ETacStep; with keep_contact=True the forward's contact_obj,
+    u_hat and hit record (17 bytes per node) are saved instead and the
+    backward skips that launch.  The plan needs ETAC_PLAN_BACKWARD."""
 
     @staticmethod
-    def forward(ctx, plan, meshset, n_obj, type_, shape, rot, trans, alpha, phi, mode):
+    def forward(ctx, plan, meshset, n_obj, type_, shape, rot, trans, alpha, phi, mode, keep_contact=False):
         rot, trans = rot.contiguous(), trans.contiguous()
         alpha, phi = alpha.contiguous(), phi.contiguous()
         sc = plan.scene_struct(n_obj, type_, shape, rot, trans)
@@ -75,18 +78,30 @@ class ETacMeshStep(torch.autograd.Function):
         saved = _native.saved_buffer(plan, E)
         _native.etac_contact_mesh(plan, meshset, sc, cobj, uhat, na, hit)
         _native.etac_propagate(plan, md, E, cobj, uhat, u, saved=saved)
-        ctx.plan, ctx.meshset, ctx.mode = plan, meshset, int(mode)
-        ctx.save_for_backward(n_obj, type_, shape, rot, trans, alpha, phi, cobj, uhat, hit, saved)
+        ctx.plan, ctx.meshset, ctx.mode, ctx.keep = plan, meshset, int(mode), bool(keep_contact)
+        if ctx.keep:
+            ctx.save_for_backward(n_obj, type_, shape, rot, trans, alpha, phi, saved, cobj, uhat, hit)
+        else:
+            ctx.save_for_backward(n_obj, type_, shape, rot, trans, alpha, phi, saved)
         ctx.mark_non_differentiable(cobj, na)
         return u, cobj, na
 
     @staticmethod
     def backward(ctx, grad_u, _grad_cobj, _grad_na):
-        n_obj, type_, shape, rot, trans, alpha, phi, cobj, uhat, hit, saved = ctx.saved_tensors
+        n_obj, type_, shape, rot, trans, alpha, phi, saved = ctx.saved_tensors[:8]
         plan = ctx.plan
         sc = plan.scene_struct(n_obj, type_, shape, rot, trans)
         md = plan.model_struct(ctx.mode, alpha, phi)
         E = int(type_.shape[0])
+        if ctx.keep:
+            cobj, uhat, hit = ctx.saved_tensors[8:]
+        else:
+            dev = rot.device
+            cobj = torch.empty((E, plan.N), dtype=torch.int8, device=dev)
+            uhat = torch.empty((3, E, plan.N), dtype=torch.float32, device=dev)
+            na = torch.empty((E, plan.K), dtype=torch.int32, device=dev)
+            hit = torch.empty((E, plan.N), dtype=torch.int32, device=dev)
+            _native.etac_contact_mesh(plan, ctx.meshset, sc, cobj, uhat, na, hit)
         gu = grad_u.to(torch.float32).contiguous()
         guhat = torch.empty_like(uhat)
         gal = torch.empty_like(alpha)
@@ -95,11 +110,12 @@ class ETacMeshStep(torch.autograd.Function):
         grot = torch.empty_like(rot)
         gtr = torch.empty_like(trans)
         _native.etac_contact_mesh_backward(plan, ctx.meshset, sc, guhat, grot, gtr, cobj, hit)
-        return None, None, None, None, None, grot, gtr, gal, gph, None
+        return None, None, None, None, None, grot, gtr, gal, gph, None, None
 
 
-def etac_mesh_step(plan, meshset, n_obj, type_, shape, rot, trans, alpha, phi, mode=_native.ETAC_FULL):
-    return ETacMeshStep.apply(plan, meshset, n_obj, type_, shape, rot, trans, alpha, phi, mode)
+def etac_mesh_step(plan, meshset, n_obj, type_, shape, rot, trans, alpha, phi, mode=_native.ETAC_FULL,
+                   keep_contact=False):
+    return ETacMeshStep.apply(plan, meshset, n_obj, type_, shape, rot, trans, alpha, phi, mode, keep_contact)
 
 
 def rotation_from_axis_angle(w):

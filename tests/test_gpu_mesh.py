@@ -282,11 +282,14 @@ def test_mesh_adjoint_from_forward_records(oracle_lib):
     assert np.array_equal(gr.cpu().numpy(), gr0.cpu().numpy()) and np.array_equal(gt.cpu().numpy(), gt0.cpu().numpy())
 
 
-def test_mesh_step_autograd_against_oracle(oracle_lib):
+@pytest.mark.parametrize("keep_contact", [False, True])
+def test_mesh_step_autograd_against_oracle(oracle_lib, keep_contact):
     # ETacMeshStep: gradients of L = sum(w * U) with respect to the poses and
     # alpha against the oracle's propagation adjoint composed with its
     # mesh-contact adjoint (decay-only model: no network decisions near
-    # margins; the network's adjoint is covered by the propagation tests)
+    # margins; the network's adjoint is covered by the propagation tests);
+    # the backward either runs the contact pass again (default) or reads the
+    # forward's contact records
     from paper_2604_20295_amd import _native
     from paper_2604_20295_amd.autograd import etac_mesh_step
     from scenes import MODE_DECAY_ONLY
@@ -300,7 +303,8 @@ def test_mesh_step_autograd_against_oracle(oracle_lib):
     rot = ds.rot.clone().requires_grad_(True)
     trans = ds.trans.clone().requires_grad_(True)
     alpha = dm.alpha.clone().requires_grad_(True)
-    u, cobj, na = etac_mesh_step(plan, dms, ds.n_obj, ds.type, ds.shape, rot, trans, alpha, dm.phi, MODE_DECAY_ONLY)
+    u, cobj, na = etac_mesh_step(plan, dms, ds.n_obj, ds.type, ds.shape, rot, trans, alpha, dm.phi, MODE_DECAY_ONLY,
+                                 keep_contact=keep_contact)
     w = np.random.default_rng(6).standard_normal((3, 24, plan.N)).astype(np.float32)
     (u * to_dev(w)).sum().backward()
     torch.cuda.synchronize()
@@ -311,7 +315,7 @@ def test_mesh_step_autograd_against_oracle(oracle_lib):
     pb = oracle_lib.propagate_backward(mesh, model, rc, ru, w.astype(np.float64))
     cb = oracle_lib.contact_mesh_backward(mesh, scene, ms, pb["grad_uhat"])
     from tests.test_gpu_backward import _close
-    log("[gpu] mesh step autograd (decay-only), 24 envs")
+    log(f"[gpu] mesh step autograd (decay-only), 24 envs, keep_contact={keep_contact}")
     _close(alpha.grad.cpu().numpy(), pb["grad_alpha"], "grad_alpha")
     _close(trans.grad.cpu().numpy(), cb["grad_trans"], "grad_trans")
     _close(rot.grad.cpu().numpy(), cb["grad_rot"], "grad_rot")
