@@ -176,6 +176,24 @@ etac_status etac_propagate(etac_plan *plan, const etac_model *model, int32_t n_e
 etac_status etac_step(etac_plan *plan, const etac_scene *scene, const etac_model *model,
                       float *u, int8_t *contact_obj, int32_t *n_active, void *saved, void *stream);
 
+/* The fused step for callers that cannot allocate device memory or may not
+ * call hipMalloc (code under stream capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, outputs and errors as etac_step,
+ * identical results; it allocates and frees nothing.  The per-workgroup
+ * scratch of its kernel (u_hat, residuals and node lists of the current
+ * item, work-queue counters) is a library-owned 64 MiB device array, which
+ * every device the library runs on holds until the process ends, instead of
+ * the plan's scratch.  All calls on one device share that array: calls that
+ * could run at the same time on one device (different streams without
+ * ordering between them) race and must not be made.  A workgroup needs
+ * 32 n_max bytes of it (n_max: the plan's largest patch); when the plan's
+ * persistent grid needs more than the array holds, fewer workgroups run.
+ * ETAC_ERR_SHAPE if one workgroup's slice does not fit; ETAC_ERR_WORKSPACE if
+ * the array's address on the plan's device is not known (it is looked up
+ * when a plan is created on that device). */
+etac_status etac_step_static(etac_plan *plan, const etac_scene *scene, const etac_model *model, float *u,
+                             int8_t *contact_obj, int32_t *n_active, void *saved, void *stream);
+
 /* Rigid objects given as closed triangle meshes (the paper's objects are
  * meshes whose signed distance fields drive contact, Sec. III-A contact
  * detection and Sec. IV).  A mesh set holds several meshes: mesh m owns

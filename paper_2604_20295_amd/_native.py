@@ -27,7 +27,7 @@ ETAC_TIMER_CONTACT, ETAC_TIMER_STEP, ETAC_TIMER_BACKWARD, ETAC_TIMER_REDUCE, ETA
 ETAC_TIMER_SLOTS = 256
 
 EXPORTED = (
-    "etac_plan_create", "etac_plan_destroy", "etac_contact", "etac_propagate", "etac_step",
+    "etac_plan_create", "etac_plan_destroy", "etac_contact", "etac_propagate", "etac_step", "etac_step_static",
     "etac_contact_backward", "etac_propagate_backward", "etac_step_backward",
     "etac_status_string", "etac_last_hip_error", "etac_plan_info", "etac_plan_set_occupancy",
     "etac_plan_set_timing", "etac_plan_kernel_time", "etac_plan_set_batch",
@@ -83,6 +83,7 @@ def lib():
             "etac_contact_mesh_backward": ([vp, vp, P(etac_scene), vp, vp, vp, vp, vp, vp], i32),
             "etac_propagate": ([vp, P(etac_model), i32, vp, vp, vp, vp, vp], i32),
             "etac_step": ([vp, P(etac_scene), P(etac_model), vp, vp, vp, vp, vp], i32),
+            "etac_step_static": ([vp, P(etac_scene), P(etac_model), vp, vp, vp, vp, vp], i32),
             "etac_contact_backward": ([vp, P(etac_scene), vp, vp, vp, vp], i32),
             "etac_propagate_backward": ([vp, P(etac_model), i32, vp, vp, vp, vp, vp, vp, vp, vp], i32),
             "etac_step_backward": ([vp, P(etac_scene), P(etac_model), vp, vp, vp, vp, vp, vp, vp], i32),
@@ -320,6 +321,20 @@ def etac_step(plan, scene, model, u, contact_obj, n_active, saved=None):
     _req(saved, torch.int32, (E * plan.K, ETAC_SAVED_WORDS), "saved", plan.device)
     _check("etac_step", lib().etac_step(plan.handle, C.byref(scene), C.byref(model), _ptr(u), _ptr(contact_obj),
                                         _ptr(n_active), _ptr(saved), _stream(plan.device)))
+
+
+def etac_step_static(plan, scene, model, u, contact_obj, n_active, saved=None):
+    """etac_step without allocation: the kernel's scratch is the library's
+    static device array (see include/etac.h)."""
+    import torch
+    E = scene.n_envs
+    _req(u, torch.float32, (3, E, plan.N), "u", plan.device)
+    _req(contact_obj, torch.int8, (E, plan.N), "contact_obj", plan.device)
+    _req(n_active, torch.int32, (E, plan.K), "n_active", plan.device)
+    _req(saved, torch.int32, (E * plan.K, ETAC_SAVED_WORDS), "saved", plan.device)
+    _check("etac_step_static", lib().etac_step_static(plan.handle, C.byref(scene), C.byref(model), _ptr(u),
+                                                      _ptr(contact_obj), _ptr(n_active), _ptr(saved),
+                                                      _stream(plan.device)))
 
 
 def etac_contact_backward(plan, scene, grad_uhat, grad_rot, grad_trans):

@@ -142,6 +142,8 @@ etac_status etac_plan_create(const etac_mesh *mesh, int32_t n_envs, int32_t max_
     p.net_batch = etac::kDefaultNetBatch;
     hipError_t e = hipGetDevice(&p.device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&p.cu_count, hipDeviceAttributeMultiprocessorCount, p.device);
+    // the device address of the static scratch of etac_step_static, once per device
+    if (e == hipSuccess) e = etac::static_scratch_init(p.device);
     if (e != hipSuccess) {
         delete h;
         return hip_fail(e);
@@ -424,6 +426,23 @@ etac_status etac_step(etac_plan *plan, const etac_scene *scene, const etac_model
     const etac::SceneDev sd = scene_dev(scene);
     hipError_t e = etac::launch_step(plan->p, &sd, model_dev(model), scene->n_envs, nullptr, nullptr, u,
                                      contact_obj, n_active, static_cast<uint32_t *>(saved), (hipStream_t)stream);
+    return e == hipSuccess ? ETAC_OK : hip_fail(e);
+}
+
+etac_status etac_step_static(etac_plan *plan, const etac_scene *scene, const etac_model *model, float *u,
+                             int8_t *contact_obj, int32_t *n_active, void *saved, void *stream) {
+    if (!plan) return ETAC_ERR_NULL;
+    etac_status st = check_scene(plan->p, scene);
+    if (st != ETAC_OK) return st;
+    st = check_model(model);
+    if (st != ETAC_OK) return st;
+    if (scene->n_envs > 0 && (!u || !contact_obj || !n_active)) return ETAC_ERR_NULL;
+    // one workgroup's slice plus the counters must fit the array
+    if (etac::static_scratch_per_wg(plan->p.n_max) + 256 > etac::kStaticScratchBytes) return ETAC_ERR_SHAPE;
+    const etac::SceneDev sd = scene_dev(scene);
+    const hipError_t e = etac::launch_step_static(plan->p, sd, model_dev(model), u, contact_obj, n_active,
+                                                  static_cast<uint32_t *>(saved), (hipStream_t)stream);
+    if (e == hipErrorNotInitialized) return ETAC_ERR_WORKSPACE;
     return e == hipSuccess ? ETAC_OK : hip_fail(e);
 }
 

@@ -4,6 +4,8 @@
 //               at a time per workgroup, items taken from a device work queue
 //               in longest-patch-first order.  The same kernel, templated,
 //               propagates given contact results (etac_propagate).
+#include <mutex>
+
 #include "etac_device.h"
 
 namespace etac {
@@ -536,6 +538,98 @@ hipError_t launch_step(const Plan &pl, const SceneDev *s, const ModelDev &m, int
     if (s) hipLaunchKernelGGL(k_step<false>, dim3(grid), dim3(kWG), 0, st, p);
     else hipLaunchKernelGGL(k_step<true>, dim3(grid), dim3(kWG), 0, st, p);
     const hipError_t e = hipGetLastError();
+    timer_end(pl, ETAC_TIMER_STEP, slot, st);
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// the fused step with its scratch in a file-scope device array
+//
+// For callers that cannot allocate (code under stream capture, serving
+// loops): the per-workgroup slices of the fused step (u_hat, residuals and
+// node lists of the current item) and the work-queue counters live in
+// `scratch`, which every device the library runs on holds until the process
+// ends.  Host code uses only the array's device address, looked up once per
+// device by static_scratch_init (at plan creation, with that device
+// current); the array's name is never used as an address on the host.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_static_mu;
+static void *g_static_ptr[kMaxDevices];
+
+hipError_t static_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (g_static_ptr[device]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e == hipSuccess) g_static_ptr[device] = ptr;
+    if (cur != device) {
+        const hipError_t e2 = hipSetDevice(cur);
+        if (e == hipSuccess) e = e2;
+    }
+    return e;
+}
+
+// Bytes of the array one persistent workgroup's slice needs: u_hat and
+// residuals [3][n_max] floats, active and passive lists [n_max] ints.
+size_t static_scratch_per_wg(int n_max) { return ((size_t)32 * (size_t)n_max + 255) / 256 * 256; }
+
+// The work-queue counters start at zero (a fill kernel, not a memset, so that
+// a captured graph replays it reliably).
+__global__ __launch_bounds__(64) void k_clear_counters(unsigned *c) {
+    if (threadIdx.x < 4) c[threadIdx.x] = 0u;
+}
+
+hipError_t launch_step_static(const Plan &pl, const SceneDev &s, const ModelDev &m, float *u, int8_t *cobj_out,
+                              int32_t *n_active, uint32_t *saved, hipStream_t st) {
+    void *base = nullptr;
+    if (pl.device >= 0 && pl.device < kMaxDevices) {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        base = g_static_ptr[pl.device];
+    }
+    if (!base) return hipErrorNotInitialized;
+    if (s.E == 0) return hipSuccess;
+    const size_t per_wg = static_scratch_per_wg(pl.n_max);
+    const int n_items = s.E * pl.K;
+    int grid = (int)std::min<size_t>((size_t)pl.grid, (kStaticScratchBytes - 256) / per_wg);
+    grid = std::min(grid, n_items);
+    if (grid < 1) return hipErrorInvalidValue;      // the caller checks the size first
+    const size_t nm = (size_t)pl.n_max, g = (size_t)grid;
+    char *b = static_cast<char *>(base);
+    Scratch scr;
+    scr.counter = reinterpret_cast<unsigned *>(b);
+    scr.uhat_node = reinterpret_cast<float *>(b + 256);
+    scr.resid = scr.uhat_node + g * 3 * nm;
+    scr.alist = reinterpret_cast<int *>(scr.resid + g * 3 * nm);
+    scr.plist = scr.alist + g * nm;
+    scr.n_max = pl.n_max;
+    StepParams p;
+    p.mesh = pl.mesh;
+    p.scene = s;
+    p.model = m;
+    p.scr = scr;
+    p.E = s.E;
+    p.n_items = n_items;
+    p.batch = pl.batch;
+    p.cobj_in = nullptr;
+    p.uhat_in = nullptr;
+    p.u = u;
+    p.cobj_out = cobj_out;
+    p.n_active = n_active;
+    p.saved = saved;
+    hipLaunchKernelGGL(k_clear_counters, dim3(1), dim3(64), 0, st, scr.counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int slot = timer_begin(pl, ETAC_TIMER_STEP, st);
+    hipLaunchKernelGGL(k_step<false>, dim3(grid), dim3(kWG), 0, st, p);
+    e = hipGetLastError();
     timer_end(pl, ETAC_TIMER_STEP, slot, st);
     return e;
 }

@@ -131,6 +131,15 @@ hipError_t launch_backward(const Plan &p, const SceneDev *s, const ModelDev &m, 
                            const uint32_t *saved, float *grad_uhat, float *grad_rot, float *grad_trans,
                            float *grad_alpha, float *grad_phi, hipStream_t st);
 hipError_t init_record_map(const Plan &p);
+
+// The fused step with its scratch in the library's file-scope device array
+// (etac_step_static): size of the array, the slice one persistent workgroup
+// needs, the once-per-device lookup of the array's address, and the launch.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+size_t static_scratch_per_wg(int n_max);
+hipError_t static_scratch_init(int device);
+hipError_t launch_step_static(const Plan &p, const SceneDev &s, const ModelDev &m, float *u, int8_t *cobj,
+                              int32_t *n_active, uint32_t *saved, hipStream_t st);
 hipError_t launch_contact_backward(const Plan &p, const SceneDev &s, const float *grad_uhat,
                                    float *grad_rot, float *grad_trans, hipStream_t st);
 
