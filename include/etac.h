@@ -71,7 +71,7 @@ typedef int32_t etac_status;
 #define ETAC_ERR_VALUE     -3   /* bad mode / flags / primitive type           */
 #define ETAC_ERR_WORKSPACE -4   /* plan was created without what this call needs */
 #define ETAC_ERR_HIP       -5   /* HIP runtime error                           */
-#define ETAC_ERR_CAPTURE   -6   /* plan creation attempted during stream capture */
+#define ETAC_ERR_CAPTURE   -6   /* plan creation or autotuning during stream capture */
 
 #define ETAC_SPHERE  0
 #define ETAC_BOX     1
@@ -257,7 +257,9 @@ etac_status etac_contact_mesh_backward(etac_plan *plan, const etac_meshset *ms, 
 /* Adjoint of the contact pass: given dL/du_hat [3][E][N] (DEVICE; read on
  * active nodes only) returns dL/dR [E][O][9] and dL/dt [E][O][3] (DEVICE,
  * overwritten, zero for absent objects).  dL/dR treats the nine entries of R
- * as free inputs of the displacement formula.  Recomputes the contact pass. */
+ * as free inputs of the displacement formula.  Recomputes the contact pass.
+ * Needs a plan created with ETAC_PLAN_BACKWARD (its per-item pose partials
+ * live in the backward scratch). */
 etac_status etac_contact_backward(etac_plan *plan, const etac_scene *scene, const float *grad_uhat,
                                   float *grad_rot, float *grad_trans, void *stream);
 

@@ -93,7 +93,7 @@ const char *etac_status_string(etac_status s) {
         case ETAC_ERR_VALUE: return "invalid mode, flags or value";
         case ETAC_ERR_WORKSPACE: return "plan lacks the scratch this call needs (create it with ETAC_PLAN_BACKWARD)";
         case ETAC_ERR_HIP: return "HIP runtime error (see etac_last_hip_error)";
-        case ETAC_ERR_CAPTURE: return "plan creation is not allowed during stream capture";
+        case ETAC_ERR_CAPTURE: return "plan creation or autotuning is not allowed during stream capture";
         default: return "unknown status";
     }
 }
