@@ -385,3 +385,115 @@ def contact_mesh_features(mesh, scene, meshset):
           C.c_int(meshset.n_meshes), _i32(meshset.tri_offset), C.c_int(meshset.n_verts), _f64(meshset.verts),
           _i32(meshset.tris), feat)
     return feat
+
+
+# ----------------------------------------------------------------------------
+# articulated hand (link frames, self-contact, contact reward)
+# ----------------------------------------------------------------------------
+
+def _hand_args(hand, links, rel32):
+    return (C.c_int(int(hand.n_links)), _i32(hand.patch_link), np.ascontiguousarray(hand.collide, np.uint32),
+            _i32(hand.prim_type), _f64(hand.prim_shape), _f64(hand.prim_rot), _f64(hand.prim_trans),
+            _f64(links.rot), _f64(links.trans), C.c_int(1 if rel32 else 0))
+
+
+def hand_forward(mesh, hand, scene, links, model, omega_a=1.0, rel32=True, with_sig=False):
+    """Articulated-hand step: contact of every patch in its link frame against
+    the env's objects and the other links' collision primitives, then Eqs.
+    1-2 in the link frames, and the contact-reward terms.  Returns dict(u,
+    uhat, contact_obj (object o, O + j for link j), n_active, n_touch, n_a,
+    link_mask, r_contact[, sig])."""
+    lib = _load()
+    K, N, off, pos, nrm, origin = _mesh_args(mesh)
+    E, O, n_obj, typ, shape, rot, trans = _scene_args(scene)
+    e, n, k = E.value, N.value, K.value
+    out = dict(u=np.empty((3, e, n)), uhat=np.empty((3, e, n)), contact_obj=np.empty((e, n), np.int8),
+               n_active=np.empty((e, k), np.int32), n_touch=np.empty((e, k), np.int32),
+               n_a=np.empty(e, np.int32), link_mask=np.empty(e, np.uint32), r_contact=np.empty(e))
+    sig = np.empty(e, np.uint64) if with_sig else None
+    _call(lib.oracle_hand_forward, K, N, off, pos, nrm, origin, E, O, n_obj, typ, shape, rot, trans,
+          *_hand_args(hand, links, rel32), C.c_int(model.mode), _f64(model.alpha), _f64(model.phi),
+          C.c_double(float(omega_a)), out["u"], out["contact_obj"], out["uhat"], out["n_active"], out["n_touch"],
+          out["n_a"], out["link_mask"], out["r_contact"], sig)
+    if with_sig:
+        out["sig"] = sig
+    return out
+
+
+def hand_backward(mesh, hand, scene, links, model, grad_u, rel32=True):
+    """Adjoint of L = sum(grad_u * U) of the hand step with respect to object
+    poses, link poses, alpha and phi."""
+    lib = _load()
+    K, N, off, pos, nrm, origin = _mesh_args(mesh)
+    E, O, n_obj, typ, shape, rot, trans = _scene_args(scene)
+    e, o, L = E.value, O.value, int(hand.n_links)
+    res = dict(grad_rot=np.empty((e, o, 9)), grad_trans=np.empty((e, o, 3)), grad_link_rot=np.empty((e, L, 9)),
+               grad_link_trans=np.empty((e, L, 3)), grad_alpha=np.empty(K.value), grad_phi=np.empty(PHI_SIZE),
+               grad_uhat=np.empty((3, e, N.value)))
+    _call(lib.oracle_hand_backward, K, N, off, pos, nrm, origin, E, O, n_obj, typ, shape, rot, trans,
+          *_hand_args(hand, links, rel32), C.c_int(model.mode), _f64(model.alpha), _f64(model.phi), _f64(grad_u),
+          res["grad_rot"], res["grad_trans"], res["grad_link_rot"], res["grad_link_trans"], res["grad_alpha"],
+          res["grad_phi"], res["grad_uhat"])
+    return res
+
+
+class _F64Links:
+    def __init__(self, lk):
+        self.rot = lk.rot.astype(np.float64)
+        self.trans = lk.trans.astype(np.float64)
+
+
+def hand_fd_gradients(mesh, hand, scene, links, model, w, env=0, link=None, obj=None, h=1e-4,
+                      shrink=(1e-5, 1e-6)):
+    """Central differences of L = sum(w * U) of the hand step in FP64 (relative
+    poses kept in FP64) for the 3 translations and 3 twists (R' = exp([+-h
+    e_k]_x) R) of link `link` or object `obj` of env `env`.  A difference whose
+    two sides take different discrete decisions is retaken with the smaller
+    steps; returns (dict(trans, twist, ok_each), ok)."""
+    S0, M0, L0 = _F64Scene(scene), _F64Model(model), _F64Links(links)
+    flags = []
+
+    def loss(S_, L_):
+        out = hand_forward(mesh, hand, S_, L_, M0, rel32=False, with_sig=True)
+        return float(np.sum(out["u"] * w)), out["sig"]
+
+    def central(perturb):
+        for step in (h,) + tuple(shrink):
+            Sp, Lp, Sm, Lm = _F64Scene(S0), _F64Links(L0), _F64Scene(S0), _F64Links(L0)
+            for A, B in ((Sp, Lp), (Sm, Lm)):
+                A.n_obj, A.type, A.shape = S0.n_obj, S0.type, S0.shape
+            perturb(Sp, Lp, step)
+            perturb(Sm, Lm, -step)
+            lp, sp = loss(Sp, Lp)
+            lm, sm = loss(Sm, Lm)
+            if np.array_equal(sp, sm):
+                flags.append(True)
+                return (lp - lm) / (2 * step)
+        flags.append(False)
+        return (lp - lm) / (2 * step)
+
+    def target(S_, L_):
+        if link is not None:
+            return L_.rot[env, link], L_.trans[env, link]
+        return S_.rot[env, obj], S_.trans[env, obj]
+
+    def shift_t(c):
+        def f(S_, L_, s):
+            target(S_, L_)[1][c] += s
+        return f
+
+    def twist(c):
+        def f(S_, L_, s):
+            e = np.zeros(3)
+            e[c] = s
+            R = target(S_, L_)[0]
+            R[:] = (expm_so3(e) @ R.reshape(3, 3)).ravel()
+        return f
+
+    res, each = {}, {}
+    for key, fns in (("trans", [shift_t(c) for c in range(3)]), ("twist", [twist(c) for c in range(3)])):
+        flags.clear()
+        res[key] = np.array([central(f) for f in fns])
+        each[key] = np.array(flags, dtype=bool)
+    res["ok_each"] = each
+    return res, all(bool(v.all()) for v in each.values())

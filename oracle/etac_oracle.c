@@ -1348,3 +1348,323 @@ int oracle_contact_mesh_features(int K, int N, const int32_t *offset, const doub
     free(ms);
     return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* 1c. articulated hand: link frames and self-contact                       */
+/* ------------------------------------------------------------------------ */
+/*
+ * The paper's contact detection covers the hand's own links as well as the
+ * external objects (Sec. III-A, contact detection), and its contact reward
+ * counts active nodes and touched links (Sec. IV-B, contact reward).
+ * Readings (listed in the design notes):
+ *   - every patch is rigidly attached to one link; its node positions,
+ *     normals and origin are given in that link's frame, and its outputs
+ *     u_hat and U are expressed in that frame;
+ *   - contact of patch k on link l is evaluated in link l's frame against
+ *     the env's objects (ids 0 .. O-1) and against the collision primitive
+ *     of every link j whose bit is set in collide[l] (j != l; id O + j);
+ *     candidates are ordered objects first, then links by index; the
+ *     deepest penetration wins, the first candidate on ties;
+ *   - an object of world pose (R_w, t_w) appears in link l's frame (pose
+ *     R_l, t_l) as R' = R_l^T R_w, t' = R_l^T (t_w - t_l); link j's primitive,
+ *     of pose (C_R, C_t) in its link frame, has world pose R_w = R_j C_R,
+ *     t_w = R_j C_t + t_j.  Evaluated in FP64 in this order (each sum of three
+ *     products as (x0 y0 + x1 y1) + x2 y2, then the translation added or
+ *     subtracted), no FMA; with `rel32` the relative pose is rounded to FP32
+ *     before the contact test (the GPU library stores it so), else it stays
+ *     in FP64 (for finite differences);
+ *   - reward: n_touch[e][k] counts the nodes of patch k whose winner is an
+ *     object; n_a = sum over k; bit l of S_cr is set when some patch on link
+ *     l has n_touch > 0; r_contact = popcount(S_cr) / L + omega_a (n_a / N
+ *     if n_a > 0, else -0.1), N the hand's node count.
+ * The adjoint holds every discrete choice fixed and chains dL/d(R', t') to
+ * the world poses: dL/dR_w = R_l G', dL/dt_w = R_l g'; for the frame link
+ * dL/dR_l += R_w G'^T + (t_w - t_l) g'^T, dL/dt_l -= R_l g'; for a link
+ * primitive dL/dR_j += (dL/dR_w) C_R^T + (dL/dt_w) C_t^T, dL/dt_j += dL/dt_w.
+ */
+typedef struct {
+    int L;
+    const int32_t *patch_link;   /* [K] */
+    const uint32_t *collide;     /* [L] */
+    const int32_t *ptype;        /* [L] primitive type or -1 */
+    const double *pshape;        /* [L][4] */
+    const double *prot;          /* [L][9] primitive pose in its link frame */
+    const double *ptrans;        /* [L][3] */
+    const double *lrot;          /* [E][L][9] link poses */
+    const double *ltrans;        /* [E][L][3] */
+    int rel32;
+} hand_t;
+
+#define HAND_MAX_CAND 64
+
+typedef struct {
+    int n;
+    int id[HAND_MAX_CAND];          /* object o, or O + j for link j */
+    int type[HAND_MAX_CAND];
+    double shape[HAND_MAX_CAND][4];
+    double R[HAND_MAX_CAND][9];     /* relative pose (link frame) */
+    double t[HAND_MAX_CAND][3];
+    double Rw[HAND_MAX_CAND][9];    /* world pose (FP64, unrounded) */
+    double tw[HAND_MAX_CAND][3];
+} hand_cand_t;
+
+static inline double sum3(double a, double b, double c) { return (a + b) + c; }
+
+static void rel_pose(const double *Rl, const double *tl, const double *Rw, const double *tw, int rel32,
+                     double *Rr, double *tr) {
+    double d[3] = {tw[0] - tl[0], tw[1] - tl[1], tw[2] - tl[2]};
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 3; ++c)
+            Rr[a * 3 + c] = sum3(Rl[0 * 3 + a] * Rw[0 * 3 + c], Rl[1 * 3 + a] * Rw[1 * 3 + c],
+                                 Rl[2 * 3 + a] * Rw[2 * 3 + c]);
+    for (int c = 0; c < 3; ++c) tr[c] = sum3(Rl[0 * 3 + c] * d[0], Rl[1 * 3 + c] * d[1], Rl[2 * 3 + c] * d[2]);
+    if (rel32) {
+        for (int i = 0; i < 9; ++i) Rr[i] = (double)(float)Rr[i];
+        for (int i = 0; i < 3; ++i) tr[i] = (double)(float)tr[i];
+    }
+}
+
+/* candidates of item (e, k) in contact order */
+static void hand_candidates(const problem_t *P, const hand_t *H, int e, int k, hand_cand_t *C) {
+    const int L = H->L, O = P->O, l = H->patch_link[k];
+    const double *Rl = H->lrot + ((size_t)e * L + l) * 9, *tl = H->ltrans + ((size_t)e * L + l) * 3;
+    C->n = 0;
+    for (int o = 0; o < P->n_obj[e] && C->n < HAND_MAX_CAND; ++o) {
+        size_t eo = (size_t)e * O + o;
+        if (P->type[eo] < O_SPHERE || P->type[eo] > O_CAPSULE) continue;
+        int s = C->n++;
+        C->id[s] = o;
+        C->type[s] = P->type[eo];
+        for (int i = 0; i < 4; ++i) C->shape[s][i] = P->shape[4 * eo + i];
+        for (int i = 0; i < 9; ++i) C->Rw[s][i] = P->rot[9 * eo + i];
+        for (int i = 0; i < 3; ++i) C->tw[s][i] = P->trans[3 * eo + i];
+        rel_pose(Rl, tl, C->Rw[s], C->tw[s], H->rel32, C->R[s], C->t[s]);
+    }
+    for (int j = 0; j < L && C->n < HAND_MAX_CAND; ++j) {
+        if (j == l || !((H->collide[l] >> j) & 1u)) continue;
+        if (H->ptype[j] < O_SPHERE || H->ptype[j] > O_CAPSULE) continue;
+        const double *Rj = H->lrot + ((size_t)e * L + j) * 9, *tj = H->ltrans + ((size_t)e * L + j) * 3;
+        const double *CR = H->prot + 9 * j, *Ct = H->ptrans + 3 * j;
+        int s = C->n++;
+        C->id[s] = O + j;
+        C->type[s] = H->ptype[j];
+        for (int i = 0; i < 4; ++i) C->shape[s][i] = H->pshape[4 * j + i];
+        for (int a = 0; a < 3; ++a) {
+            for (int c = 0; c < 3; ++c)
+                C->Rw[s][a * 3 + c] = sum3(Rj[a * 3 + 0] * CR[0 * 3 + c], Rj[a * 3 + 1] * CR[1 * 3 + c],
+                                           Rj[a * 3 + 2] * CR[2 * 3 + c]);
+            C->tw[s][a] = sum3(Rj[a * 3 + 0] * Ct[0], Rj[a * 3 + 1] * Ct[1], Rj[a * 3 + 2] * Ct[2]) + tj[a];
+        }
+        rel_pose(Rl, tl, C->Rw[s], C->tw[s], H->rel32, C->R[s], C->t[s]);
+    }
+}
+
+/* winner slot of one node among the item's candidates (-1: passive) */
+static int hand_winner(const hand_cand_t *C, const double p[3], const double n[3], hit_t *bh) {
+    int best = -1;
+    memset(bh, 0, sizeof *bh);
+    for (int s = 0; s < C->n; ++s) {
+        hit_t h = penetrate(C->type[s], C->shape[s], C->R[s], C->t[s], p, n);
+        if (h.inside && (best < 0 || h.depth > bh->depth)) { best = s; *bh = h; }
+    }
+    return best;
+}
+
+static void hand_contact_env(const problem_t *P, const hand_t *H, int e, int8_t *cobj, double *uhat,
+                             int32_t *n_active, int32_t *n_touch, uint64_t *sig) {
+    const int N = P->N, E = P->E, O = P->O;
+    hand_cand_t *C = malloc(sizeof *C);
+    for (int k = 0; k < P->K; ++k) {
+        hand_candidates(P, H, e, k, C);
+        int na = 0, nt = 0;
+        for (int i = P->offset[k]; i < P->offset[k + 1]; ++i) {
+            double p[3] = {P->pos[i], P->pos[N + i], P->pos[2 * N + i]};
+            double n[3] = {P->nrm[i], P->nrm[N + i], P->nrm[2 * N + i]};
+            hit_t bh;
+            int s = hand_winner(C, p, n, &bh);
+            size_t en = (size_t)e * N + i;
+            cobj[en] = (int8_t)(s >= 0 ? C->id[s] : -1);
+            for (int a = 0; a < 3; ++a) uhat[(size_t)a * E * N + en] = s >= 0 ? bh.u[a] : 0.0;
+            if (s >= 0) {
+                ++na;
+                if (C->id[s] < O) ++nt;
+            }
+            if (sig) {
+                *sig = fnv(*sig, s >= 0 ? C->id[s] : -1);
+                if (s >= 0) *sig = fnv(fnv(fnv(*sig, bh.face), bh.sign), bh.degenerate);
+            }
+        }
+        n_active[(size_t)e * P->K + k] = na;
+        n_touch[(size_t)e * P->K + k] = nt;
+    }
+    free(C);
+}
+
+static void hand_reward(const problem_t *P, const hand_t *H, int e, const int32_t *n_touch, double omega_a,
+                        int32_t *n_a, uint32_t *link_mask, double *r_contact) {
+    int64_t s = 0;
+    uint32_t mask = 0;
+    for (int k = 0; k < P->K; ++k) {
+        int32_t t = n_touch[(size_t)e * P->K + k];
+        s += t;
+        if (t > 0) mask |= 1u << H->patch_link[k];
+    }
+    int links = 0;
+    for (int l = 0; l < H->L; ++l) links += (mask >> l) & 1u;
+    n_a[e] = (int32_t)s;
+    link_mask[e] = mask;
+    double ra = s > 0 ? (double)s / (double)P->N : -0.1;
+    r_contact[e] = (double)links / (double)H->L + omega_a * ra;
+}
+
+static hand_t mkhand(int L, const int32_t *patch_link, const uint32_t *collide, const int32_t *ptype,
+                     const double *pshape, const double *prot, const double *ptrans, const double *lrot,
+                     const double *ltrans, int rel32) {
+    hand_t H = {L, patch_link, collide, ptype, pshape, prot, ptrans, lrot, ltrans, rel32};
+    return H;
+}
+
+/* Articulated-hand forward step.  Outputs: U [3][E][N] and uhat [3][E][N]
+ * in each patch's link frame, contact_obj [E][N] (object o, O + j for link
+ * j, -1 passive), n_active and n_touch [E][K], n_a [E], link_mask [E],
+ * r_contact [E]; sig [E] (may be NULL) fingerprints every discrete choice. */
+int oracle_hand_forward(int K, int N, const int32_t *offset, const double *pos, const double *nrm,
+                        const double *origin, int E, int O, const int32_t *n_obj, const int32_t *type,
+                        const double *shape, const double *rot, const double *trans, int L,
+                        const int32_t *patch_link, const uint32_t *collide, const int32_t *ptype,
+                        const double *pshape, const double *prot, const double *ptrans, const double *lrot,
+                        const double *ltrans, int rel32, int mode, const double *alpha, const double *phi,
+                        double omega_a, double *U, int8_t *cobj, double *uhat, int32_t *n_active,
+                        int32_t *n_touch, int32_t *n_a, uint32_t *link_mask, double *r_contact, uint64_t *sig) {
+    if (L < 1 || L > 32) return 1;
+    for (int k = 0; k < K; ++k)
+        if (patch_link[k] < 0 || patch_link[k] >= L) return 2;
+    problem_t P = mkprob(K, N, offset, pos, nrm, origin, E, O, n_obj, type, shape, rot, trans);
+    hand_t H = mkhand(L, patch_link, collide, ptype, pshape, prot, ptrans, lrot, ltrans, rel32);
+    net_t W = net_view(phi);
+    int nmax = max_patch(&P);
+#pragma omp parallel
+    {
+        scratch_t S = scratch_new(nmax);
+#pragma omp for schedule(static)
+        for (int e = 0; e < E; ++e) {
+            uint64_t h = 1469598103934665603ULL;
+            hand_contact_env(&P, &H, e, cobj, uhat, n_active, n_touch, sig ? &h : NULL);
+            hand_reward(&P, &H, e, n_touch, omega_a, n_a, link_mask, r_contact);
+            for (int k = 0; k < K; ++k)
+                propagate_patch(&P, &W, mode, alpha, e, k, cobj, uhat, U, &S, NULL, sig ? &h : NULL);
+            if (sig) sig[e] = h;
+        }
+        scratch_free(&S);
+    }
+    return 0;
+}
+
+/* pose gradients of env e from dL/du_hat of its active nodes (hand) */
+static void hand_contact_env_backward(const problem_t *P, const hand_t *H, int e, const double *guhat,
+                                      double *grot, double *gtrans, double *glrot, double *gltrans) {
+    const int N = P->N, E = P->E, O = P->O, L = H->L;
+    const size_t EN = (size_t)E * N;
+    for (int i = 0; i < O * 9; ++i) grot[(size_t)e * O * 9 + i] = 0.0;
+    for (int i = 0; i < O * 3; ++i) gtrans[(size_t)e * O * 3 + i] = 0.0;
+    for (int i = 0; i < L * 9; ++i) glrot[(size_t)e * L * 9 + i] = 0.0;
+    for (int i = 0; i < L * 3; ++i) gltrans[(size_t)e * L * 3 + i] = 0.0;
+    hand_cand_t *C = malloc(sizeof *C);
+    double (*gR)[9] = malloc(sizeof(double) * 9 * HAND_MAX_CAND);
+    double (*gt)[3] = malloc(sizeof(double) * 3 * HAND_MAX_CAND);
+    for (int k = 0; k < P->K; ++k) {
+        hand_candidates(P, H, e, k, C);
+        for (int s = 0; s < C->n; ++s) {
+            for (int i = 0; i < 9; ++i) gR[s][i] = 0.0;
+            for (int i = 0; i < 3; ++i) gt[s][i] = 0.0;
+        }
+        for (int i = P->offset[k]; i < P->offset[k + 1]; ++i) {
+            double p[3] = {P->pos[i], P->pos[N + i], P->pos[2 * N + i]};
+            double n[3] = {P->nrm[i], P->nrm[N + i], P->nrm[2 * N + i]};
+            hit_t bh;
+            int s = hand_winner(C, p, n, &bh);
+            if (s < 0 || bh.degenerate) continue;
+            size_t ei = (size_t)e * N + i;
+            double g[3] = {guhat[ei], guhat[EN + ei], guhat[2 * EN + ei]};
+            contact_node_backward(C->type[s], C->shape[s], C->R[s], C->t[s], p, g, gR[s], gt[s]);
+        }
+        /* chain rule from the relative poses to the world poses */
+        const int l = H->patch_link[k];
+        const double *Rl = H->lrot + ((size_t)e * L + l) * 9, *tl = H->ltrans + ((size_t)e * L + l) * 3;
+        double *gRl = glrot + ((size_t)e * L + l) * 9, *gtl = gltrans + ((size_t)e * L + l) * 3;
+        for (int s = 0; s < C->n; ++s) {
+            double GRw[9], gtw[3], d[3];
+            for (int a = 0; a < 3; ++a) {
+                for (int c = 0; c < 3; ++c)
+                    GRw[a * 3 + c] = Rl[a * 3 + 0] * gR[s][0 * 3 + c] + Rl[a * 3 + 1] * gR[s][1 * 3 + c] +
+                                     Rl[a * 3 + 2] * gR[s][2 * 3 + c];
+                gtw[a] = Rl[a * 3 + 0] * gt[s][0] + Rl[a * 3 + 1] * gt[s][1] + Rl[a * 3 + 2] * gt[s][2];
+                d[a] = C->tw[s][a] - tl[a];
+            }
+            /* frame link: R_w G'^T + d g'^T, and -R_l g' */
+            for (int a = 0; a < 3; ++a) {
+                for (int b = 0; b < 3; ++b) {
+                    double v = C->Rw[s][a * 3 + 0] * gR[s][b * 3 + 0] + C->Rw[s][a * 3 + 1] * gR[s][b * 3 + 1] +
+                               C->Rw[s][a * 3 + 2] * gR[s][b * 3 + 2];
+                    gRl[a * 3 + b] += v + d[a] * gt[s][b];
+                }
+                gtl[a] -= gtw[a];
+            }
+            const int id = C->id[s];
+            if (id < O) {
+                double *go = grot + ((size_t)e * O + id) * 9, *gto = gtrans + ((size_t)e * O + id) * 3;
+                for (int i = 0; i < 9; ++i) go[i] += GRw[i];
+                for (int i = 0; i < 3; ++i) gto[i] += gtw[i];
+            } else {
+                const int j = id - O;
+                const double *CR = H->prot + 9 * j, *Ct = H->ptrans + 3 * j;
+                double *gRj = glrot + ((size_t)e * L + j) * 9, *gtj = gltrans + ((size_t)e * L + j) * 3;
+                for (int a = 0; a < 3; ++a) {
+                    for (int b = 0; b < 3; ++b)
+                        gRj[a * 3 + b] += GRw[a * 3 + 0] * CR[b * 3 + 0] + GRw[a * 3 + 1] * CR[b * 3 + 1] +
+                                          GRw[a * 3 + 2] * CR[b * 3 + 2] + gtw[a] * Ct[b];
+                    gtj[a] += gtw[a];
+                }
+            }
+        }
+    }
+    free(C);
+    free(gR);
+    free(gt);
+}
+
+/* Adjoint of L = sum g . U for the articulated hand: recomputes contact,
+ * then the propagation adjoint (link frames), then the contact adjoint with
+ * the chain rule to object poses grot [E][O][9], gtrans [E][O][3] and link
+ * poses glrot [E][L][9], gltrans [E][L][3]; galpha [K], gphi [PHI_N]. */
+int oracle_hand_backward(int K, int N, const int32_t *offset, const double *pos, const double *nrm,
+                         const double *origin, int E, int O, const int32_t *n_obj, const int32_t *type,
+                         const double *shape, const double *rot, const double *trans, int L,
+                         const int32_t *patch_link, const uint32_t *collide, const int32_t *ptype,
+                         const double *pshape, const double *prot, const double *ptrans, const double *lrot,
+                         const double *ltrans, int rel32, int mode, const double *alpha, const double *phi,
+                         const double *gu, double *grot, double *gtrans, double *glrot, double *gltrans,
+                         double *galpha, double *gphi, double *guhat_out) {
+    if (L < 1 || L > 32) return 1;
+    for (int k = 0; k < K; ++k)
+        if (patch_link[k] < 0 || patch_link[k] >= L) return 2;
+    size_t EN = (size_t)E * N;
+    problem_t P = mkprob(K, N, offset, pos, nrm, origin, E, O, n_obj, type, shape, rot, trans);
+    hand_t H = mkhand(L, patch_link, collide, ptype, pshape, prot, ptrans, lrot, ltrans, rel32);
+    int8_t *cobj = malloc(EN);
+    double *uhat = malloc(sizeof(double) * 3 * EN);
+    int32_t *na = malloc(sizeof(int32_t) * (size_t)E * K), *nt = malloc(sizeof(int32_t) * (size_t)E * K);
+    double *guhat = guhat_out ? guhat_out : malloc(sizeof(double) * 3 * EN);
+#pragma omp parallel for schedule(static)
+    for (int e = 0; e < E; ++e) hand_contact_env(&P, &H, e, cobj, uhat, na, nt, NULL);
+    oracle_propagate_backward(K, N, offset, pos, nrm, origin, E, mode, alpha, phi, cobj, uhat, gu, guhat, galpha,
+                              gphi);
+#pragma omp parallel for schedule(static)
+    for (int e = 0; e < E; ++e) hand_contact_env_backward(&P, &H, e, guhat, grot, gtrans, glrot, gltrans);
+    if (!guhat_out) free(guhat);
+    free(cobj);
+    free(uhat);
+    free(na);
+    free(nt);
+    return 0;
+}

@@ -15,6 +15,7 @@ import pytest
 import oracle
 from tests import test_oracle_adjoint as TA
 from tests import test_oracle_contact as TC
+from tests import test_oracle_hand as TH
 from tests import test_oracle_mesh as TM
 from tests import test_oracle_propagate as TP
 
@@ -61,6 +62,24 @@ MUTANTS = [
      "J[i * 3 + j] = -(i == j ? 1.0 : 0.0);"),
     ("u_hat gradient from passive input", "if (cobj[ei] >= 0) { /* only active nodes carry u_hat into the input */",
      "if (cobj[ei] < 0) { /* only active nodes carry u_hat into the input */"),
+    ("hand: relative rotation without the transpose",
+     "Rr[a * 3 + c] = sum3(Rl[0 * 3 + a] * Rw[0 * 3 + c], Rl[1 * 3 + a] * Rw[1 * 3 + c],\n                                 Rl[2 * 3 + a] * Rw[2 * 3 + c]);",
+     "Rr[a * 3 + c] = sum3(Rl[a * 3 + 0] * Rw[0 * 3 + c], Rl[a * 3 + 1] * Rw[1 * 3 + c],\n                                 Rl[a * 3 + 2] * Rw[2 * 3 + c]);"),
+    ("hand: translation not taken relative to the link", "double d[3] = {tw[0] - tl[0], tw[1] - tl[1], tw[2] - tl[2]};",
+     "double d[3] = {tw[0], tw[1], tw[2]};"),
+    ("hand: link primitive offset ignored",
+     "C->tw[s][a] = sum3(Rj[a * 3 + 0] * Ct[0], Rj[a * 3 + 1] * Ct[1], Rj[a * 3 + 2] * Ct[2]) + tj[a];",
+     "C->tw[s][a] = tj[a];"),
+    ("hand: frame-link translation gradient sign", "gtl[a] -= gtw[a];", "gtl[a] += gtw[a];"),
+    ("hand: frame-link rotation gradient drops the lever term", "gRl[a * 3 + b] += v + d[a] * gt[s][b];",
+     "gRl[a * 3 + b] += v;"),
+    ("hand: object gradient left in the link frame", "for (int i = 0; i < 9; ++i) go[i] += GRw[i];",
+     "for (int i = 0; i < 9; ++i) go[i] += gR[s][i];"),
+    ("hand: link primitive gradient drops its offset", "GRw[a * 3 + 2] * CR[b * 3 + 2] + gtw[a] * Ct[b];",
+     "GRw[a * 3 + 2] * CR[b * 3 + 2];"),
+    ("hand: reward counts self-contact", "if (C->id[s] < O) ++nt;", "++nt;"),
+    ("hand: reward without the empty-contact penalty", "double ra = s > 0 ? (double)s / (double)P->N : -0.1;",
+     "double ra = s > 0 ? (double)s / (double)P->N : 0.0;"),
 ]
 
 
@@ -87,6 +106,13 @@ def _pins():
         lambda o: TM.test_deepest_object_wins_across_primitives_and_meshes(o),
         lambda o: [TM.test_mesh_pose_adjoint_vs_central_differences(o, m) for m in (0, "L")],
         lambda o: TM.test_mesh_adjoint_with_a_primitive_and_raw_rotation_entries(o),
+        lambda o: TH.test_identity_links_reduce_to_the_plain_step(o),
+        lambda o: TH.test_link_frame_contact_equals_world_frame_contact(o),
+        lambda o: TH.test_self_contact_sphere_closed_form(o),
+        lambda o: TH.test_rigid_motion_of_everything_changes_nothing(o),
+        lambda o: TH.test_adjoint_translation_and_rotation_sums_vanish(o),
+        lambda o: TH.test_contact_reward_worked_example(o),
+        lambda o: [TH.test_hand_pose_adjoint_vs_central_differences(o, m) for m in (1, 0)],
     ]
 
 
