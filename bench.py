@@ -77,6 +77,9 @@ def parse():
                     help="Adam iterations of the calibration loop (Eq. 3) timed on the same scenes (0: skip)")
     ap.add_argument("--no-mesh", action="store_true",
                     help="skip the triangle-mesh object contact measurement (etac_contact_mesh)")
+    ap.add_argument("--no-articulated", action="store_true",
+                    help="skip the articulated hand with self-contact and the contact reward (4096 envs)")
+    ap.add_argument("--articulated-steps", type=int, default=10)
     return ap.parse_args()
 
 
@@ -431,6 +434,92 @@ def hires(args, mode):
             "steps": args.hires_steps, "launch_shape": None}
 
 
+def articulated(args, mode):
+    """The 16-link articulated hand (palm + three phalanges per finger, one
+    patch per link given in its link frame), 4096 grasp scenes: contact with
+    the objects and with the other links' primitives, the contact reward,
+    the fused step and its adjoint to object and link poses.  Eager calls on
+    one stream, bracketed by HIP events; kernel times from the library's
+    timers."""
+    import torch
+    from scenes import articulated as art
+    from paper_2604_20295_amd import _native
+    dev = torch.device("cuda", 0)
+    h, mesh, scene, links, model = art.config_hand(n_envs=args.envs, mode=mode)
+    E, O, N, K, L = scene.n_envs, scene.max_obj, mesh.n_nodes, mesh.n_patches, h.n_links
+
+    def t(a, dtype):
+        return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).to(dev)
+
+    plan = _native.Plan.from_mesh(mesh, E, O, backward=True)
+    plan.set_hand(h)
+    sc = plan.scene_struct(t(scene.n_obj, torch.int32), t(scene.type, torch.int32), t(scene.shape, torch.float32),
+                           t(scene.rot, torch.float32), t(scene.trans, torch.float32))
+    lk = plan.links_struct(t(links.rot, torch.float32), t(links.trans, torch.float32))
+    md = plan.model_struct(mode, t(model.alpha, torch.float32), t(model.phi, torch.float32))
+    u = torch.empty((3, E, N), device=dev)
+    uhat = torch.empty((3, E, N), device=dev)
+    cobj = torch.empty((E, N), dtype=torch.int8, device=dev)
+    na = torch.empty((E, K), dtype=torch.int32, device=dev)
+    touch = torch.empty((E, K), dtype=torch.int32, device=dev)
+    n_a = torch.empty((E,), dtype=torch.int32, device=dev)
+    mask = torch.empty((E,), dtype=torch.int32, device=dev)
+    r = torch.empty((E,), device=dev)
+    rw = plan.reward_struct(E, 1.0, touch, n_a, mask, r)
+    gu = torch.randn((3, E, N), generator=torch.Generator(device=dev).manual_seed(7), device=dev)
+    g = [torch.empty(s, device=dev) for s in ((E, O, 9), (E, O, 3), (E, L, 9), (E, L, 3), (K,), (PHI_SIZE,))]
+    saved = _native.saved_buffer(plan, E)
+    if args.launch:
+        plan.set_launch(*[int(x) for x in args.launch.split(",")])
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn, reps):
+        for _ in range(2):
+            fn()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(reps):
+            fn()
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps
+
+    reps = args.articulated_steps
+    contact_ms = timed(lambda: _native.etac_hand_contact(plan, sc, lk, cobj, uhat, na, rw), reps)
+    fwd_ms = timed(lambda: _native.etac_hand_step(plan, sc, lk, md, u, cobj, na, rw), reps)
+
+    def step():
+        _native.etac_hand_step(plan, sc, lk, md, u, cobj, na, rw, saved=saved)
+        _native.etac_hand_step_backward(plan, sc, lk, md, gu, *g, saved=saved)
+
+    step()
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    step_ms = timed(step, reps)
+    kern = {}
+    for name, tid in (("k_step", _native.ETAC_TIMER_STEP), ("k_bwd_decay", _native.ETAC_TIMER_BWD_DECAY),
+                      ("k_bwd", _native.ETAC_TIMER_BACKWARD), ("reductions", _native.ETAC_TIMER_REDUCE)):
+        n, ms = plan.kernel_time(tid)
+        kern[name + "_avg"] = ms / n if n else float("nan")
+    plan.set_timing(False)
+    c = cobj.cpu().numpy()
+    counts = work_counts(mesh, na.cpu().numpy())
+    nodes = float(E) * N
+    plan.close()
+    return {"workload": f"{E} envs x 16-link articulated hand ({N} nodes/env: palm 32x32 at 2.5 mm, phalanges "
+                        f"512/256/128 nodes), grasp scenes with 1-2 primitives, fingers closed on the first, "
+                        f"self-contact with every non-adjacent link, mode {args.mode}",
+            "active_fraction_mean": float((c >= 0).mean()),
+            "self_contact_share_of_active": float((c >= O).sum() / max(1, (c >= 0).sum())),
+            "links_touched_mean": float(np.mean([bin(int(v) & 0xffffffff).count("1") for v in mask.cpu().numpy()])),
+            "r_contact_mean": float(r.cpu().numpy().mean()),
+            "contact_with_reward": {"ms": contact_ms, "node_updates_per_s": nodes / (contact_ms * 1e-3)},
+            "fwd": {"ms_per_step": fwd_ms, "node_updates_per_s": nodes / (fwd_ms * 1e-3)},
+            "fwd_bwd": {"ms_per_step": step_ms, "node_updates_per_s": nodes / (step_ms * 1e-3)},
+            "kernel_ms": kern, "decay_pairs": counts["pairs"], "steps": reps}
+
+
 def cpu_baseline(mesh, scene, model, grad_u, budget):
     """The FP64 oracle (forward + adjoint) on consecutive blocks of the same
     envs until the time budget is spent, on every host thread and on one."""
@@ -685,6 +774,10 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_rollout and args.workload == "hand":
         line["rollout"] = rollout(args, mode)
+        torch.cuda.empty_cache()
+    if not args.no_articulated and args.workload == "hand":
+        line["articulated"] = articulated(args, mode)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(mesh, scene, model, grad_u_host, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -358,6 +358,93 @@ etac_status etac_plan_set_timing(etac_plan *plan, int32_t enable);
  * never turned on. */
 etac_status etac_plan_kernel_time(etac_plan *plan, int32_t timer, int32_t *launches, double *total_ms);
 
+/* ------------------------------------------------------------------------
+ * Articulated hand and self-contact.  The paper's contact detection covers
+ * the hand's own links besides the external objects (Sec. III-A, contact
+ * detection), and its contact reward counts active nodes and touched links
+ * (Sec. IV-B, contact-reward equation).  Here every patch rides on one link
+ * of the hand: the plan's mesh gives patch k's node positions, normals and
+ * origin in the frame of link patch_link[k], and the hand calls return u_hat
+ * and U in that frame.  Contact of patch k on link l is evaluated in link
+ * l's frame against
+ *   - the env's objects (contact_obj ids 0 .. O-1, O = scene max_obj), and
+ *   - the collision primitive of every link j with bit j of collide[l] set,
+ *     j != l (id O + j),
+ * each at its relative pose R' = R_l^T R_w, t' = R_l^T (t_w - t_l), formed in
+ * FP64 (every entry (a0 b0 + a1 b1) + a2 b2, no fused multiply-add) and
+ * rounded to FP32; link j's primitive has world pose R_w = R_j C_R,
+ * t_w = R_j C_t + t_j for its pose (C_R, C_t) in link j's frame.  Candidates
+ * are ordered objects first, then links by index; the deepest penetration
+ * wins, the first candidate on ties.  Triangle-mesh objects are ignored by
+ * the hand calls.
+ * ------------------------------------------------------------------------ */
+#define ETAC_MAX_LINKS 24
+
+/* The hand's links.  All pointers HOST; etac_plan_set_hand copies them. */
+typedef struct {
+    int32_t n_links;              /* L, 1 .. ETAC_MAX_LINKS                     */
+    const int32_t *patch_link;    /* [K] link carrying each patch, 0 .. L-1     */
+    const uint32_t *collide;      /* [L] bit j: link j's primitive is tested
+                                     against the patches on this link (bit of
+                                     the link itself ignored)                   */
+    const int32_t *prim_type;     /* [L] ETAC_SPHERE / BOX / CAPSULE, or -1 for
+                                     a link without a collision primitive       */
+    const float *prim_shape;      /* [L][4] as etac_scene shapes                 */
+    const float *prim_rot;        /* [L][9] primitive pose in its link frame     */
+    const float *prim_trans;      /* [L][3]                                      */
+} etac_hand;
+
+/* Link poses of every env (world x = R q + t for a link-frame point q).
+ * DEVICE [E][L][9] and [E][L][3]. */
+typedef struct {
+    const float *rot;
+    const float *trans;
+} etac_links;
+
+/* Contact-reward outputs (DEVICE; each pointer may be NULL to skip it).
+ * n_touch[e][k]: nodes of patch k won by an object (not by a link);
+ * n_a[e] = sum over k of n_touch; link_mask[e] bit l: some patch on link l
+ * has n_touch > 0 (the paper's S_cr); r_contact[e] = popcount(link_mask) / L
+ * + omega_a (n_a / N if n_a > 0, else -0.1), N the plan's node count. */
+typedef struct {
+    float omega_a;
+    int32_t *n_touch;             /* [E][K] */
+    int32_t *n_a;                 /* [E]    */
+    uint32_t *link_mask;          /* [E]    */
+    float *r_contact;             /* [E]    */
+} etac_reward;
+
+/* Attach a hand to a plan (replaces a previous one).  Validates it (every
+ * patch_link in range, primitive types, positive shapes; the largest
+ * candidate set max_obj + popcount(collide[l]) at most 32: ETAC_ERR_SHAPE
+ * beyond), uploads it and allocates the per-item candidate table (and the
+ * adjoint's partials with ETAC_PLAN_BACKWARD).  Synchronous; not during
+ * stream capture (ETAC_ERR_CAPTURE). */
+etac_status etac_plan_set_hand(etac_plan *plan, const etac_hand *hand);
+
+/* Contact pass of the hand: contact_obj [E][N] (ids as above, -1 passive),
+ * uhat [3][E][N] (link frames; may be NULL), n_active [E][K], and the reward
+ * outputs (reward may be NULL).  ETAC_ERR_WORKSPACE without a hand. */
+etac_status etac_hand_contact(etac_plan *plan, const etac_scene *scene, const etac_links *links,
+                              int8_t *contact_obj, float *uhat, int32_t *n_active, const etac_reward *reward,
+                              void *stream);
+
+/* Fused step of the hand (contact as above, then Eqs. 1-2 in the link
+ * frames): u [3][E][N], contact_obj, n_active, reward (may be NULL), saved
+ * (may be NULL: the pooling record, see ETAC_SAVED_WORDS). */
+etac_status etac_hand_step(etac_plan *plan, const etac_scene *scene, const etac_links *links,
+                           const etac_model *model, float *u, int8_t *contact_obj, int32_t *n_active,
+                           const etac_reward *reward, void *saved, void *stream);
+
+/* Adjoint of L = sum g . U of the hand step: dL/dR [E][O][9], dL/dt [E][O][3]
+ * of the objects, dL/dR [E][L][9], dL/dt [E][L][3] of the links (rotation
+ * entries as free inputs), dL/dalpha, dL/dphi (may be NULL).  Recomputes
+ * contact; saved as for etac_step_backward.  Needs ETAC_PLAN_BACKWARD. */
+etac_status etac_hand_step_backward(etac_plan *plan, const etac_scene *scene, const etac_links *links,
+                                    const etac_model *model, const float *grad_u, const void *saved,
+                                    float *grad_rot, float *grad_trans, float *grad_link_rot,
+                                    float *grad_link_trans, float *grad_alpha, float *grad_phi, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -397,12 +397,13 @@ def _hand_args(hand, links, rel32):
             _f64(links.rot), _f64(links.trans), C.c_int(1 if rel32 else 0))
 
 
-def hand_forward(mesh, hand, scene, links, model, omega_a=1.0, rel32=True, with_sig=False):
+def hand_forward(mesh, hand, scene, links, model, omega_a=1.0, rel32=True, with_sig=False, with_margin=False):
     """Articulated-hand step: contact of every patch in its link frame against
     the env's objects and the other links' collision primitives, then Eqs.
     1-2 in the link frames, and the contact-reward terms.  Returns dict(u,
     uhat, contact_obj (object o, O + j for link j), n_active, n_touch, n_a,
-    link_mask, r_contact[, sig])."""
+    link_mask, r_contact[, sig][, margin [E][K]: each item's decision margin
+    as in item_margins])."""
     lib = _load()
     K, N, off, pos, nrm, origin = _mesh_args(mesh)
     E, O, n_obj, typ, shape, rot, trans = _scene_args(scene)
@@ -411,12 +412,15 @@ def hand_forward(mesh, hand, scene, links, model, omega_a=1.0, rel32=True, with_
                n_active=np.empty((e, k), np.int32), n_touch=np.empty((e, k), np.int32),
                n_a=np.empty(e, np.int32), link_mask=np.empty(e, np.uint32), r_contact=np.empty(e))
     sig = np.empty(e, np.uint64) if with_sig else None
+    margin = np.empty((e, k)) if with_margin else None
     _call(lib.oracle_hand_forward, K, N, off, pos, nrm, origin, E, O, n_obj, typ, shape, rot, trans,
           *_hand_args(hand, links, rel32), C.c_int(model.mode), _f64(model.alpha), _f64(model.phi),
           C.c_double(float(omega_a)), out["u"], out["contact_obj"], out["uhat"], out["n_active"], out["n_touch"],
-          out["n_a"], out["link_mask"], out["r_contact"], sig)
+          out["n_a"], out["link_mask"], out["r_contact"], sig, margin)
     if with_sig:
         out["sig"] = sig
+    if with_margin:
+        out["margin"] = margin
     return out
 
 

@@ -1527,7 +1527,9 @@ static hand_t mkhand(int L, const int32_t *patch_link, const uint32_t *collide, 
 /* Articulated-hand forward step.  Outputs: U [3][E][N] and uhat [3][E][N]
  * in each patch's link frame, contact_obj [E][N] (object o, O + j for link
  * j, -1 passive), n_active and n_touch [E][K], n_a [E], link_mask [E],
- * r_contact [E]; sig [E] (may be NULL) fingerprints every discrete choice. */
+ * r_contact [E]; sig [E] (may be NULL) fingerprints every discrete choice;
+ * margin [E][K] (may be NULL) is each item's decision margin as in
+ * oracle_item_margins. */
 int oracle_hand_forward(int K, int N, const int32_t *offset, const double *pos, const double *nrm,
                         const double *origin, int E, int O, const int32_t *n_obj, const int32_t *type,
                         const double *shape, const double *rot, const double *trans, int L,
@@ -1535,7 +1537,8 @@ int oracle_hand_forward(int K, int N, const int32_t *offset, const double *pos, 
                         const double *pshape, const double *prot, const double *ptrans, const double *lrot,
                         const double *ltrans, int rel32, int mode, const double *alpha, const double *phi,
                         double omega_a, double *U, int8_t *cobj, double *uhat, int32_t *n_active,
-                        int32_t *n_touch, int32_t *n_a, uint32_t *link_mask, double *r_contact, uint64_t *sig) {
+                        int32_t *n_touch, int32_t *n_a, uint32_t *link_mask, double *r_contact, uint64_t *sig,
+                        double *margin) {
     if (L < 1 || L > 32) return 1;
     for (int k = 0; k < K; ++k)
         if (patch_link[k] < 0 || patch_link[k] >= L) return 2;
@@ -1551,8 +1554,11 @@ int oracle_hand_forward(int K, int N, const int32_t *offset, const double *pos, 
             uint64_t h = 1469598103934665603ULL;
             hand_contact_env(&P, &H, e, cobj, uhat, n_active, n_touch, sig ? &h : NULL);
             hand_reward(&P, &H, e, n_touch, omega_a, n_a, link_mask, r_contact);
-            for (int k = 0; k < K; ++k)
-                propagate_patch(&P, &W, mode, alpha, e, k, cobj, uhat, U, &S, NULL, sig ? &h : NULL);
+            for (int k = 0; k < K; ++k) {
+                double mg = INFINITY;
+                propagate_patch(&P, &W, mode, alpha, e, k, cobj, uhat, U, &S, margin ? &mg : NULL, sig ? &h : NULL);
+                if (margin) margin[(size_t)e * K + k] = mg;
+            }
             if (sig) sig[e] = h;
         }
         scratch_free(&S);

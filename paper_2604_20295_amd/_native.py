@@ -28,6 +28,7 @@ ETAC_TIMER_SLOTS = 256
 
 EXPORTED = (
     "etac_plan_create", "etac_plan_destroy", "etac_contact", "etac_propagate", "etac_step", "etac_step_static",
+    "etac_plan_set_hand", "etac_hand_contact", "etac_hand_step", "etac_hand_step_backward",
     "etac_contact_backward", "etac_propagate_backward", "etac_step_backward",
     "etac_status_string", "etac_last_hip_error", "etac_plan_info", "etac_plan_set_occupancy",
     "etac_plan_set_timing", "etac_plan_kernel_time", "etac_plan_set_batch",
@@ -48,6 +49,21 @@ class etac_scene(C.Structure):
 
 class etac_model(C.Structure):
     _fields_ = [("mode", C.c_int32), ("alpha", C.c_void_p), ("phi", C.c_void_p)]
+
+
+class etac_hand(C.Structure):
+    _fields_ = [("n_links", C.c_int32), ("patch_link", C.c_void_p), ("collide", C.c_void_p),
+                ("prim_type", C.c_void_p), ("prim_shape", C.c_void_p), ("prim_rot", C.c_void_p),
+                ("prim_trans", C.c_void_p)]
+
+
+class etac_links(C.Structure):
+    _fields_ = [("rot", C.c_void_p), ("trans", C.c_void_p)]
+
+
+class etac_reward(C.Structure):
+    _fields_ = [("omega_a", C.c_float), ("n_touch", C.c_void_p), ("n_a", C.c_void_p), ("link_mask", C.c_void_p),
+                ("r_contact", C.c_void_p)]
 
 
 class EtacError(RuntimeError):
@@ -98,6 +114,12 @@ def lib():
             "etac_plan_autotune": ([vp, P(etac_scene), P(etac_model), vp, vp, vp, vp, vp, vp, vp, vp, vp, i32,
                                     P(i32), vp], i32),
             "etac_plan_kernel_time": ([vp, i32, P(i32), P(C.c_double)], i32),
+            "etac_plan_set_hand": ([vp, P(etac_hand)], i32),
+            "etac_hand_contact": ([vp, P(etac_scene), P(etac_links), vp, vp, vp, P(etac_reward), vp], i32),
+            "etac_hand_step": ([vp, P(etac_scene), P(etac_links), P(etac_model), vp, vp, vp, P(etac_reward), vp,
+                                vp], i32),
+            "etac_hand_step_backward": ([vp, P(etac_scene), P(etac_links), P(etac_model), vp, vp, vp, vp, vp, vp,
+                                         vp, vp, vp], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -210,6 +232,43 @@ class Plan:
         _req(trans, torch.float32, (E, O, 3), "trans", self.device)
         st = etac_scene(E, O, _ptr(n_obj), _ptr(type_), _ptr(shape), _ptr(rot), _ptr(trans))
         st._keep = (n_obj, type_, shape, rot, trans)   # the struct holds raw pointers: keep the tensors alive
+        return st
+
+    def set_hand(self, hand):
+        """Attach an articulated hand (scenes.articulated.Hand layout: n_links,
+        patch_link, collide, prim_type, prim_shape, prim_rot, prim_trans)."""
+        self._hand_host = (np.ascontiguousarray(hand.patch_link, np.int32),
+                           np.ascontiguousarray(hand.collide, np.uint32),
+                           np.ascontiguousarray(hand.prim_type, np.int32),
+                           np.ascontiguousarray(hand.prim_shape, np.float32),
+                           np.ascontiguousarray(hand.prim_rot, np.float32),
+                           np.ascontiguousarray(hand.prim_trans, np.float32))
+        pl, co, pt, ps, pr, pp = self._hand_host
+        if pl.shape != (self.K,):
+            raise ValueError(f"patch_link: expected ({self.K},), got {pl.shape}")
+        self.L = int(hand.n_links)
+        h = etac_hand(self.L, pl.ctypes.data, co.ctypes.data, pt.ctypes.data, ps.ctypes.data, pr.ctypes.data,
+                      pp.ctypes.data)
+        _check("etac_plan_set_hand", lib().etac_plan_set_hand(self.handle, C.byref(h)))
+
+    def links_struct(self, rot, trans):
+        import torch
+        E = int(rot.shape[0])
+        _req(rot, torch.float32, (E, self.L, 9), "link rot", self.device)
+        _req(trans, torch.float32, (E, self.L, 3), "link trans", self.device)
+        st = etac_links(_ptr(rot), _ptr(trans))
+        st._keep = (rot, trans)
+        return st
+
+    def reward_struct(self, n_envs, omega_a=1.0, n_touch=None, n_a=None, link_mask=None, r_contact=None):
+        import torch
+        E = int(n_envs)
+        _req(n_touch, torch.int32, (E, self.K), "n_touch", self.device)
+        _req(n_a, torch.int32, (E,), "n_a", self.device)
+        _req(link_mask, torch.int32, (E,), "link_mask (bits as int32)", self.device)
+        _req(r_contact, torch.float32, (E,), "r_contact", self.device)
+        st = etac_reward(float(omega_a), _ptr(n_touch), _ptr(n_a), _ptr(link_mask), _ptr(r_contact))
+        st._keep = (n_touch, n_a, link_mask, r_contact)
         return st
 
     def model_struct(self, mode, alpha, phi):
@@ -403,3 +462,47 @@ def etac_plan_autotune(plan, scene, model, u, contact_obj, n_active, grad_u=None
                                     _ptr(contact_obj), _ptr(n_active), _ptr(saved), _ptr(grad_rot), _ptr(grad_trans),
                                     _ptr(grad_alpha), _ptr(grad_phi), int(reps), best, _stream(plan.device)))
     return tuple(best)
+
+
+def etac_hand_contact(plan, scene, links, contact_obj, uhat, n_active, reward=None):
+    import torch
+    E = scene.n_envs
+    _req(contact_obj, torch.int8, (E, plan.N), "contact_obj", plan.device)
+    _req(uhat, torch.float32, (3, E, plan.N), "uhat", plan.device)
+    _req(n_active, torch.int32, (E, plan.K), "n_active", plan.device)
+    _check("etac_hand_contact", lib().etac_hand_contact(plan.handle, C.byref(scene), C.byref(links), _ptr(contact_obj),
+                                                        _ptr(uhat), _ptr(n_active),
+                                                        C.byref(reward) if reward is not None else None,
+                                                        _stream(plan.device)))
+
+
+def etac_hand_step(plan, scene, links, model, u, contact_obj, n_active, reward=None, saved=None):
+    import torch
+    E = scene.n_envs
+    _req(u, torch.float32, (3, E, plan.N), "u", plan.device)
+    _req(contact_obj, torch.int8, (E, plan.N), "contact_obj", plan.device)
+    _req(n_active, torch.int32, (E, plan.K), "n_active", plan.device)
+    _req(saved, torch.int32, (E * plan.K, ETAC_SAVED_WORDS), "saved", plan.device)
+    _check("etac_hand_step", lib().etac_hand_step(plan.handle, C.byref(scene), C.byref(links), C.byref(model),
+                                                  _ptr(u), _ptr(contact_obj), _ptr(n_active),
+                                                  C.byref(reward) if reward is not None else None, _ptr(saved),
+                                                  _stream(plan.device)))
+
+
+def etac_hand_step_backward(plan, scene, links, model, grad_u, grad_rot, grad_trans, grad_link_rot, grad_link_trans,
+                            grad_alpha, grad_phi, saved=None):
+    import torch
+    E, O = scene.n_envs, scene.max_obj
+    _req(saved, torch.int32, (E * plan.K, ETAC_SAVED_WORDS), "saved", plan.device)
+    _req(grad_u, torch.float32, (3, E, plan.N), "grad_u", plan.device)
+    _req(grad_rot, torch.float32, (E, O, 9), "grad_rot", plan.device)
+    _req(grad_trans, torch.float32, (E, O, 3), "grad_trans", plan.device)
+    _req(grad_link_rot, torch.float32, (E, plan.L, 9), "grad_link_rot", plan.device)
+    _req(grad_link_trans, torch.float32, (E, plan.L, 3), "grad_link_trans", plan.device)
+    _req(grad_alpha, torch.float32, (plan.K,), "grad_alpha", plan.device)
+    _req(grad_phi, torch.float32, (ETAC_PHI_SIZE,), "grad_phi", plan.device)
+    _check("etac_hand_step_backward",
+           lib().etac_hand_step_backward(plan.handle, C.byref(scene), C.byref(links), C.byref(model), _ptr(grad_u),
+                                         _ptr(saved), _ptr(grad_rot), _ptr(grad_trans), _ptr(grad_link_rot),
+                                         _ptr(grad_link_trans), _ptr(grad_alpha), _ptr(grad_phi),
+                                         _stream(plan.device)))

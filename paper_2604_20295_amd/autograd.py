@@ -6,8 +6,9 @@ rot [E][O][9], trans [E][O][3], alpha [K] and phi [17411].  The forward runs
 etac_step, the backward runs etac_step_backward, which recomputes the contact
 pass; besides the inputs only the network's pooling record (pooled features
 and their arg-max nodes, 512 bytes per (env, patch) item) is saved.
-ETacMeshStep does the same for scenes with triangle-mesh objects.  Argument
-marshalling only.
+ETacMeshStep does the same for scenes with triangle-mesh objects, and
+ETacHandStep for the articulated hand (gradients also to the link poses).
+Argument marshalling only.
 """
 import torch
 
@@ -116,6 +117,54 @@ class ETacMeshStep(torch.autograd.Function):
 def etac_mesh_step(plan, meshset, n_obj, type_, shape, rot, trans, alpha, phi, mode=_native.ETAC_FULL,
                    keep_contact=False):
     return ETacMeshStep.apply(plan, meshset, n_obj, type_, shape, rot, trans, alpha, phi, mode, keep_contact)
+
+
+class ETacHandStep(torch.autograd.Function):
+    """The articulated-hand step (plan with etac_plan_set_hand): contact with
+    the objects and the other links in each patch's link frame, then Eqs.
+    1-2.  Returns (u [3][E][N] in the link frames, contact_obj, n_active,
+    r_contact [E]); gradients flow to the object poses, the link poses
+    [E][L][9], [E][L][3], alpha and phi.  The backward recomputes contact and
+    reads the forward's pooling record."""
+
+    @staticmethod
+    def forward(ctx, plan, n_obj, type_, shape, rot, trans, link_rot, link_trans, alpha, phi, mode, omega_a=1.0):
+        rot, trans = rot.contiguous(), trans.contiguous()
+        link_rot, link_trans = link_rot.contiguous(), link_trans.contiguous()
+        alpha, phi = alpha.contiguous(), phi.contiguous()
+        sc = plan.scene_struct(n_obj, type_, shape, rot, trans)
+        lk = plan.links_struct(link_rot, link_trans)
+        md = plan.model_struct(mode, alpha, phi)
+        E = int(type_.shape[0])
+        dev = rot.device
+        u = torch.empty((3, E, plan.N), dtype=torch.float32, device=dev)
+        cobj = torch.empty((E, plan.N), dtype=torch.int8, device=dev)
+        na = torch.empty((E, plan.K), dtype=torch.int32, device=dev)
+        r = torch.empty((E,), dtype=torch.float32, device=dev)
+        rw = plan.reward_struct(E, omega_a, r_contact=r)
+        saved = _native.saved_buffer(plan, E)
+        _native.etac_hand_step(plan, sc, lk, md, u, cobj, na, rw, saved=saved)
+        ctx.plan, ctx.mode = plan, int(mode)
+        ctx.save_for_backward(n_obj, type_, shape, rot, trans, link_rot, link_trans, alpha, phi, saved)
+        ctx.mark_non_differentiable(cobj, na, r)
+        return u, cobj, na, r
+
+    @staticmethod
+    def backward(ctx, grad_u, _grad_cobj, _grad_na, _grad_r):
+        n_obj, type_, shape, rot, trans, link_rot, link_trans, alpha, phi, saved = ctx.saved_tensors
+        plan = ctx.plan
+        sc = plan.scene_struct(n_obj, type_, shape, rot, trans)
+        lk = plan.links_struct(link_rot, link_trans)
+        md = plan.model_struct(ctx.mode, alpha, phi)
+        gu = grad_u.to(torch.float32).contiguous()
+        g = [torch.empty_like(x) for x in (rot, trans, link_rot, link_trans, alpha, phi)]
+        _native.etac_hand_step_backward(plan, sc, lk, md, gu, *g, saved=saved)
+        return (None, None, None, None) + tuple(g) + (None, None)
+
+
+def etac_hand_step(plan, n_obj, type_, shape, rot, trans, link_rot, link_trans, alpha, phi, mode=_native.ETAC_FULL,
+                   omega_a=1.0):
+    return ETacHandStep.apply(plan, n_obj, type_, shape, rot, trans, link_rot, link_trans, alpha, phi, mode, omega_a)
 
 
 def rotation_from_axis_angle(w):

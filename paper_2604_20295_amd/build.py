@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libetac.so")
-SOURCES = ["etac_api.cpp", "etac_forward.hip", "etac_backward.hip", "etac_mesh.hip"]
+SOURCES = ["etac_api.cpp", "etac_forward.hip", "etac_backward.hip", "etac_mesh.hip", "etac_hand.hip"]
 # The adjoint kernel keeps ~500 registers per lane live (one wave per SIMD);
 # letting MFMA results live in VGPRs as well as AGPRs avoids spills there.
 EXTRA = {"etac_backward.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}

@@ -42,6 +42,10 @@ hipError_t plan_alloc(etac::Plan &p, T **ptr, size_t count) {
 void plan_free_all(etac::Plan &p) {
     for (int i = 0; i < p.n_allocs; ++i) (void)hipFree(p.allocs[i]);
     p.n_allocs = 0;
+    if (p.hand_mem) (void)hipFree(p.hand_mem);
+    p.hand_mem = nullptr;
+    delete p.hand;
+    p.hand = nullptr;
     if (p.timers) {
         for (int k = 0; k < ETAC_TIMER_COUNT; ++k)
             for (int i = 0; i < ETAC_TIMER_SLOTS; ++i)
@@ -80,6 +84,25 @@ etac::SceneDev scene_dev(const etac_scene *s) {
 }
 
 etac::ModelDev model_dev(const etac_model *m) { return etac::ModelDev{m->mode, m->alpha, m->phi}; }
+
+etac_status check_hand_call(const etac::Plan &p, const etac_scene *scene, const etac_links *links) {
+    etac_status st = check_scene(p, scene);
+    if (st != ETAC_OK) return st;
+    if (!links) return ETAC_ERR_NULL;
+    if (scene->n_envs > 0 && (!links->rot || !links->trans)) return ETAC_ERR_NULL;
+    if (!p.hand) return ETAC_ERR_WORKSPACE;
+    return ETAC_OK;
+}
+
+int32_t *touch_buffer(const etac::Plan &p, const etac_reward *r) {
+    return (r && r->n_touch) ? r->n_touch : p.hand->n_touch;
+}
+
+hipError_t hand_reward(const etac::Plan &p, int E, const int32_t *touch, const etac_reward *r, hipStream_t st) {
+    if (!r) return hipSuccess;
+    return etac::launch_hand_reward(p, E, touch, r->omega_a, r->n_a, r->link_mask, r->r_contact, st);
+}
+
 
 }  // namespace
 
@@ -580,6 +603,174 @@ etac_status etac_plan_autotune(etac_plan *plan, const etac_scene *scene, const e
         best[4] = p.net_batch;
     }
     return out;
+}
+
+
+// ---------------------------------------------------------------------------
+// articulated hand
+// ---------------------------------------------------------------------------
+etac_status etac_plan_set_hand(etac_plan *plan, const etac_hand *hand) {
+    if (!plan || !hand) return ETAC_ERR_NULL;
+    if (!hand->patch_link || !hand->collide || !hand->prim_type || !hand->prim_shape || !hand->prim_rot ||
+        !hand->prim_trans)
+        return ETAC_ERR_NULL;
+    etac::Plan &p = plan->p;
+    const int L = hand->n_links, K = p.K;
+    if (L < 1 || L > ETAC_MAX_LINKS) return ETAC_ERR_SHAPE;
+    for (int k = 0; k < K; ++k)
+        if (hand->patch_link[k] < 0 || hand->patch_link[k] >= L) return ETAC_ERR_VALUE;
+    unsigned with_prim = 0;
+    for (int l = 0; l < L; ++l) {
+        const int ty = hand->prim_type[l];
+        if (ty < -1 || ty > ETAC_CAPSULE) return ETAC_ERR_VALUE;
+        for (int i = 0; i < 4; ++i)
+            if (!std::isfinite(hand->prim_shape[4 * l + i])) return ETAC_ERR_VALUE;
+        for (int i = 0; i < 9; ++i)
+            if (!std::isfinite(hand->prim_rot[9 * l + i])) return ETAC_ERR_VALUE;
+        for (int i = 0; i < 3; ++i)
+            if (!std::isfinite(hand->prim_trans[3 * l + i])) return ETAC_ERR_VALUE;
+        if (ty < 0) continue;
+        const float *sh = hand->prim_shape + 4 * l;
+        if (!(sh[0] > 0.0f)) return ETAC_ERR_VALUE;
+        if (ty == ETAC_BOX && !(sh[1] > 0.0f && sh[2] > 0.0f)) return ETAC_ERR_VALUE;
+        if (ty == ETAC_CAPSULE && !(sh[1] >= 0.0f)) return ETAC_ERR_VALUE;
+        with_prim |= 1u << l;
+    }
+    int most = 0;
+    for (int l = 0; l < L; ++l)
+        most = std::max(most, __builtin_popcount(hand->collide[l] & ~(1u << l) & with_prim));
+    const int cap = std::max(1, p.max_obj + most);
+    if (cap > etac::kMaxRowObj) return ETAC_ERR_SHAPE;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(nullptr, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return ETAC_ERR_CAPTURE;
+
+    // one device block, carved at 256-byte boundaries
+    const size_t rows = (size_t)p.n_envs * K, rc = rows * (size_t)cap;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { const size_t o = off; off += (bytes + 255) / 256 * 256; return o; };
+    const size_t o_pl = take(K * sizeof(int)), o_co = take(L * sizeof(unsigned)), o_pt = take(L * sizeof(int));
+    const size_t o_ps = take(4 * L * sizeof(float)), o_pr = take(9 * L * sizeof(float)), o_pp = take(3 * L * sizeof(float));
+    const size_t o_no = take(rows * sizeof(int)), o_ne = take(rows * sizeof(int)), o_ty = take(rc * sizeof(int));
+    const size_t o_sh = take(4 * rc * sizeof(float)), o_ro = take(9 * rc * sizeof(float));
+    const size_t o_tr = take(3 * rc * sizeof(float)), o_sr = take(rc), o_nt = take(rows * sizeof(int));
+    const size_t o_pa = p.has_bwd ? take(12 * rc * sizeof(float)) : 0;
+    void *mem = nullptr;
+    hipError_t e = hipMalloc(&mem, off);
+    if (e != hipSuccess) return hip_fail(e);
+    char *b = static_cast<char *>(mem);
+    etac::HandDev *h = new (std::nothrow) etac::HandDev();
+    if (!h) {
+        (void)hipFree(mem);
+        return ETAC_ERR_SHAPE;
+    }
+    h->L = L;
+    h->cap = cap;
+    h->patch_link = reinterpret_cast<int *>(b + o_pl);
+    h->collide = reinterpret_cast<unsigned *>(b + o_co);
+    h->ptype = reinterpret_cast<int *>(b + o_pt);
+    h->pshape = reinterpret_cast<float *>(b + o_ps);
+    h->prot = reinterpret_cast<float *>(b + o_pr);
+    h->ptrans = reinterpret_cast<float *>(b + o_pp);
+    h->n_obj = reinterpret_cast<int *>(b + o_no);
+    h->n_ext = reinterpret_cast<int *>(b + o_ne);
+    h->type = reinterpret_cast<int *>(b + o_ty);
+    h->shape = reinterpret_cast<float *>(b + o_sh);
+    h->rot = reinterpret_cast<float *>(b + o_ro);
+    h->trans = reinterpret_cast<float *>(b + o_tr);
+    h->src = reinterpret_cast<int8_t *>(b + o_sr);
+    h->n_touch = reinterpret_cast<int *>(b + o_nt);
+    h->pose_part = p.has_bwd ? reinterpret_cast<float *>(b + o_pa) : nullptr;
+    std::vector<unsigned> collide(L);
+    for (int l = 0; l < L; ++l) collide[l] = hand->collide[l] & ~(1u << l) & with_prim & (L < 32 ? (1u << L) - 1u : ~0u);
+    e = hipMemcpy(b + o_pl, hand->patch_link, K * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b + o_co, collide.data(), L * sizeof(unsigned), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b + o_pt, hand->prim_type, L * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b + o_ps, hand->prim_shape, 4 * L * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b + o_pr, hand->prim_rot, 9 * L * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b + o_pp, hand->prim_trans, 3 * L * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(b + o_no, 0, rows * sizeof(int));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        delete h;
+        (void)hipFree(mem);
+        return hip_fail(e);
+    }
+    (void)hipDeviceSynchronize();
+    if (p.hand_mem) (void)hipFree(p.hand_mem);
+    delete p.hand;
+    p.hand = h;
+    p.hand_mem = mem;
+    return ETAC_OK;
+}
+
+etac_status etac_hand_contact(etac_plan *plan, const etac_scene *scene, const etac_links *links,
+                              int8_t *contact_obj, float *uhat, int32_t *n_active, const etac_reward *reward,
+                              void *stream) {
+    if (!plan) return ETAC_ERR_NULL;
+    const etac::Plan &p = plan->p;
+    etac_status st = check_hand_call(p, scene, links);
+    if (st != ETAC_OK) return st;
+    if (scene->n_envs > 0 && (!contact_obj || !n_active)) return ETAC_ERR_NULL;
+    if (scene->n_envs == 0) return ETAC_OK;
+    const hipStream_t s = (hipStream_t)stream;
+    const etac::LinksDev lk{links->rot, links->trans};
+    etac::SceneDev rows;
+    hipError_t e = etac::launch_hand_scene(p, scene_dev(scene), lk, &rows, s);
+    int32_t *touch = touch_buffer(p, reward);
+    if (e == hipSuccess) e = etac::launch_contact_rows(p, rows, contact_obj, uhat, n_active, touch, s);
+    if (e == hipSuccess) e = hand_reward(p, scene->n_envs, touch, reward, s);
+    return e == hipSuccess ? ETAC_OK : hip_fail(e);
+}
+
+etac_status etac_hand_step(etac_plan *plan, const etac_scene *scene, const etac_links *links,
+                           const etac_model *model, float *u, int8_t *contact_obj, int32_t *n_active,
+                           const etac_reward *reward, void *saved, void *stream) {
+    if (!plan) return ETAC_ERR_NULL;
+    const etac::Plan &p = plan->p;
+    etac_status st = check_hand_call(p, scene, links);
+    if (st != ETAC_OK) return st;
+    st = check_model(model);
+    if (st != ETAC_OK) return st;
+    if (scene->n_envs > 0 && (!u || !contact_obj || !n_active)) return ETAC_ERR_NULL;
+    if (scene->n_envs == 0) return ETAC_OK;
+    const hipStream_t s = (hipStream_t)stream;
+    const etac::LinksDev lk{links->rot, links->trans};
+    etac::SceneDev rows;
+    hipError_t e = etac::launch_hand_scene(p, scene_dev(scene), lk, &rows, s);
+    int32_t *touch = touch_buffer(p, reward);
+    if (e == hipSuccess)
+        e = etac::launch_step(p, &rows, model_dev(model), scene->n_envs, nullptr, nullptr, u, contact_obj, n_active,
+                              static_cast<uint32_t *>(saved), s, touch);
+    if (e == hipSuccess) e = hand_reward(p, scene->n_envs, touch, reward, s);
+    return e == hipSuccess ? ETAC_OK : hip_fail(e);
+}
+
+etac_status etac_hand_step_backward(etac_plan *plan, const etac_scene *scene, const etac_links *links,
+                                    const etac_model *model, const float *grad_u, const void *saved,
+                                    float *grad_rot, float *grad_trans, float *grad_link_rot,
+                                    float *grad_link_trans, float *grad_alpha, float *grad_phi, void *stream) {
+    if (!plan) return ETAC_ERR_NULL;
+    const etac::Plan &p = plan->p;
+    etac_status st = check_hand_call(p, scene, links);
+    if (st != ETAC_OK) return st;
+    st = check_model(model);
+    if (st != ETAC_OK) return st;
+    if (!p.has_bwd) return ETAC_ERR_WORKSPACE;
+    if (scene->n_envs > 0 && (!grad_u || !grad_rot || !grad_trans || !grad_link_rot || !grad_link_trans))
+        return ETAC_ERR_NULL;
+    const hipStream_t s = (hipStream_t)stream;
+    const etac::SceneDev world = scene_dev(scene);
+    const etac::LinksDev lk{links->rot, links->trans};
+    etac::SceneDev rows;
+    hipError_t e = etac::launch_hand_scene(p, world, lk, &rows, s);
+    // the adjoint hands winners over as row slots: no id mapping, no reward counts
+    rows.src = nullptr;
+    rows.n_ext = nullptr;
+    if (e == hipSuccess)
+        e = etac::launch_backward(p, &rows, model_dev(model), scene->n_envs, nullptr, nullptr, grad_u,
+                                  static_cast<const uint32_t *>(saved), nullptr, grad_rot, grad_trans, grad_alpha,
+                                  grad_phi, s, &world, &lk, grad_link_rot, grad_link_trans);
+    return e == hipSuccess ? ETAC_OK : hip_fail(e);
 }
 
 }  // extern "C"

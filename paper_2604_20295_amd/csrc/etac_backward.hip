@@ -1042,27 +1042,29 @@ __device__ void contact_adjoint_item(const BwdParams &p, BwdLds &S, int e, int i
                                      const int *alist, const int8_t *wobj, const float *gh) {
     const MeshDev &M = p.mesh;
     const int N = M.N, n_max = p.scr.n_max, O = p.scene.O;
-    const int no = min(p.scene.n_obj[e], O);
+    // the item's scene row: its env, or the item itself for a row per item
+    const size_t row = p.scene.rows_per_env ? (size_t)item : (size_t)e;
+    const int no = min(p.scene.n_obj[row], O);
     float *out = p.bwd.pose_part + (size_t)item * O * 12;
     // objects present among the active nodes (an OR, independent of order)
-    int mask = 0;
-    for (int q = threadIdx.x; q < m; q += kWG) mask |= 1 << wobj[alist[q]];
+    unsigned mask = 0;
+    for (int q = threadIdx.x; q < m; q += kWG) mask |= 1u << wobj[alist[q]];
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) mask |= __shfl_xor(mask, off);
-    S.ired[threadIdx.x >> 6][lane_id()] = mask;     // identical in every lane of the wave
+    for (int off = 32; off >= 1; off >>= 1) mask |= (unsigned)__shfl_xor((int)mask, off);
+    S.ired[threadIdx.x >> 6][lane_id()] = (int)mask;     // identical in every lane of the wave
     __syncthreads();
-    int present = 0;
-    for (int w = 0; w < kWaves; ++w) present |= S.ired[w][0];
+    unsigned present = 0;
+    for (int w = 0; w < kWaves; ++w) present |= (unsigned)S.ired[w][0];
     present = uniform(present);
     __syncthreads();
     for (int o = 0; o < O; ++o) {
-        if (!((present >> o) & 1) || o >= no) {
+        if (!((present >> o) & 1u) || o >= no) {
             if (threadIdx.x < 64 && lane_id() < 12) out[o * 12 + lane_id()] = 0.0f;
             continue;
         }
         double acc[12];
         for (int c = 0; c < 12; ++c) acc[c] = 0.0;
-        const size_t eo = (size_t)e * O + o;
+        const size_t eo = row * O + o;
         const int ty = p.scene.type[eo];
         const float *sh = p.scene.shape + 4 * eo, *R = p.scene.rot + 9 * eo, *t = p.scene.trans + 3 * eo;
         for (int q = threadIdx.x; q < m; q += kWG) {
@@ -1457,9 +1459,10 @@ __device__ void decay_item_bwd(const BwdParams &p, DecayLds &S, int item, int e,
     const int n = M.offset[k + 1] - base;
     const size_t row = (size_t)e * N + base;
     float umax;
+    int touch;
     const int m = contact_and_compact<KIND == BWD_PROP>(M, p.scene, p.E, n_max, p.cobj_in, p.uhat_in,
                                                         KIND == BWD_STEP ? p.bwd.cobj_st : nullptr, S.wcnt, e, k,
-                                                        base, n, cand, uhn, alist, plist, nullptr, umax);
+                                                        base, n, cand, uhn, alist, plist, nullptr, umax, touch);
     if (threadIdx.x < 64) p.bwd.m_st[item] = m;     // identical stores
     if (m == 0) {
         if (threadIdx.x < 64) {
@@ -1525,9 +1528,11 @@ __global__ __launch_bounds__(kWG) void k_bwd_decay(BwdParams p) {
         const int nb = uniform(S.batch.n);
         for (int q = 0; q < nb; ++q) {
             const int pos = uniform(S.batch.item[q]);
-            const unsigned cand = uniform((unsigned)S.batch.cand[q]);
             int e, k;
             queue_item(p.mesh, p.E, pos, e, k);
+            const unsigned cand = KIND == BWD_PROP
+                                      ? 0xffffffffu
+                                      : item_cand(p.scene, e, k, uniform((unsigned)S.batch.cand[q]));
             decay_item_bwd<KIND>(p, S, e * p.mesh.K + k, e, k, cand, uhn, gh, alist, plist);
         }
     }
@@ -1697,10 +1702,11 @@ __device__ void process_item_bwd(const BwdParams &p, BwdLds &S, int item, int e,
     const float *uin = KIND == BWD_STEP ? p.bwd.uhat_st : p.uhat_in;
     int m;
     float umax = 0.0f, gmax = 0.0f;
+    int touch;
     if constexpr (KIND == BWD_CONTACT)
         m = contact_and_compact<false>(M, p.scene, p.E, n_max, nullptr, nullptr, nullptr,
                                        *reinterpret_cast<int (*)[3][kWaves]>(&S.wcnt[0][0][0]), e, k, base, n,
-                                       cand, uhn, alist, plist, wobj, umax);
+                                       cand, uhn, alist, plist, wobj, umax, touch);
     else
         m = compact_given(p.E, N, n_max, cin, uin, p.grad_u, S.wcnt, S.wmx, e, base, n, uhn, alist, plist, wobj,
                           umax, gmax);
@@ -1764,9 +1770,11 @@ __global__ __launch_bounds__(kWG) void k_bwd(BwdParams p) {
         const int nb = uniform(S.batch.n);
         for (int q = 0; q < nb; ++q) {
             const int pos = uniform(S.batch.item[q]);
-            const unsigned cand = uniform((unsigned)S.batch.cand[q]);
             int e, k;
             queue_item(p.mesh, p.E, pos, e, k);
+            const unsigned cand = KIND == BWD_CONTACT
+                                      ? item_cand(p.scene, e, k, uniform((unsigned)S.batch.cand[q]))
+                                      : 0xffffffffu;
             process_item_bwd<KIND>(p, S, e * p.mesh.K + k, e, k, cand, uhn, gh, alist, plist, wobj);
         }
     }
@@ -1908,7 +1916,8 @@ __global__ __launch_bounds__(256) void k_pose(const float *part, int E, int K, i
 hipError_t launch_backward(const Plan &pl, const SceneDev *s, const ModelDev &m, int n_envs, const int8_t *cobj_in,
                            const float *uhat_in, const float *grad_u, const uint32_t *saved, float *grad_uhat,
                            float *grad_rot, float *grad_trans, float *grad_alpha, float *grad_phi,
-                           hipStream_t st) {
+                           hipStream_t st, const SceneDev *world, const LinksDev *links, float *grad_link_rot,
+                           float *grad_link_trans) {
     if (n_envs == 0) {
         // sums over no env: zero parameter gradients
         if (grad_alpha) hipLaunchKernelGGL(k_zero, dim3(1), dim3(256), 0, st, grad_alpha, pl.K);
@@ -1921,6 +1930,8 @@ hipError_t launch_backward(const Plan &pl, const SceneDev *s, const ModelDev &m,
     p.model = m;
     p.scr = pl.scr;
     p.bwd = pl.bwd;
+    // the hand's rows hold up to cap candidates: their own pose partials
+    if (links) p.bwd.pose_part = pl.hand->pose_part;
     p.E = n_envs;
     p.n_items = n_envs * pl.K;
     p.batch = pl.bwd_batch;
@@ -1959,12 +1970,15 @@ hipError_t launch_backward(const Plan &pl, const SceneDev *s, const ModelDev &m,
                            pl.bwd.rec_map, grad_phi);
     }
     if (grad_alpha) hipLaunchKernelGGL(k_alpha, dim3(pl.K), dim3(256), 0, st, pl.bwd.alpha_part, n_envs, pl.K, grad_alpha);
-    if (s) {
+    e = hipSuccess;
+    if (s && links) {
+        e = launch_pose_hand(pl, *world, *links, grad_rot, grad_trans, grad_link_rot, grad_link_trans, st);
+    } else if (s) {
         const int nt = n_envs * s->O * 12;
         hipLaunchKernelGGL(k_pose, dim3((nt + 255) / 256), dim3(256), 0, st, pl.bwd.pose_part, n_envs, pl.K, s->O,
                            grad_rot, grad_trans);
     }
-    e = hipGetLastError();
+    if (e == hipSuccess) e = hipGetLastError();
     timer_end(pl, ETAC_TIMER_REDUCE, slot, st);
     return e;
 }

@@ -116,20 +116,20 @@ __device__ __forceinline__ float bounding_radius(int type, const float *sh) {
     return sh[0] + sh[1];
 }
 
-// Contact of one node with the candidate objects of env e (bit o of `cand`).
-// A cheap FP32 ball test with a relative margin of 1e-3 (far above FP32
-// rounding) skips objects that cannot contain the node; survivors take the
-// exact FP64 test.  Deepest penetration wins, lowest index on ties.
-// Returns the winning object or -1; u is the winner's u_hat rounded to FP32.
-__device__ __forceinline__ int contact_node(const SceneDev &S, int e, unsigned cand, float px, float py,
+// Contact of one node with the candidate objects of scene row `row` (bit o
+// of `cand`).  A cheap FP32 ball test with a relative margin of 1e-3 (far
+// above FP32 rounding) skips objects that cannot contain the node; survivors
+// take the exact FP64 test.  Deepest penetration wins, lowest index on ties.
+// Returns the winning slot or -1; u is the winner's u_hat rounded to FP32.
+__device__ __forceinline__ int contact_node(const SceneDev &S, size_t row, unsigned cand, float px, float py,
                                             float pz, float nx, float ny, float nz, float &u0, float &u1,
                                             float &u2) {
     int best = -1;
     double bd = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
-    const int no = min(S.n_obj[e], S.O);   // device contents are not validated on the host
+    const int no = min(S.n_obj[row], S.O);   // device contents are not validated on the host
     for (int o = 0; o < no; ++o) {
         if (!((cand >> o) & 1u)) continue;
-        const size_t eo = (size_t)e * S.O + o;
+        const size_t eo = row * S.O + o;
         const int ty = S.type[eo];
         const float *sh = S.shape + 4 * eo;
         const float *R = S.rot + 9 * eo;
@@ -213,20 +213,28 @@ __device__ inline void contact_adjoint_node(int type, const float *sh, const flo
     }
 }
 
-// Primitives of env e whose bounding ball may reach patch k's bounding
-// sphere (objects of other types, triangle meshes included, are ignored).
+// Conservative test that a primitive's bounding ball (centre t) may reach the
+// ball b = (centre, radius): relative margins of 1e-3 and 1e-5, far above
+// FP32 rounding.
+__device__ __forceinline__ bool ball_reaches(const float4 &b, int type, const float *shape, const float *t) {
+    const float dx = b.x - t[0], dy = b.y - t[1], dz = b.z - t[2];
+    const float reach = (b.w + bounding_radius(type, shape)) * 1.001f + 1e-3f;
+    const float d2 = dx * dx + dy * dy + dz * dz;
+    return d2 * (1.0f - 1e-5f) <= reach * reach;
+}
+
+// Primitives of item (e, k)'s scene row whose bounding ball may reach patch
+// k's bounding sphere (objects of other types, triangle meshes included, are
+// ignored).
 __device__ __forceinline__ unsigned cull_objects(const SceneDev &S, const MeshDev &M, int e, int k) {
     unsigned cand = 0;
-    const int no = min(S.n_obj[e], S.O);
+    const size_t row = scene_row(S, e, k);
+    const int no = min(S.n_obj[row], S.O);
     const float4 b = M.bound[k];
     for (int o = 0; o < no; ++o) {
-        const size_t eo = (size_t)e * S.O + o;
+        const size_t eo = row * S.O + o;
         if ((unsigned)S.type[eo] > (unsigned)ETAC_CAPSULE) continue;
-        const float *t = S.trans + 3 * eo;
-        const float dx = b.x - t[0], dy = b.y - t[1], dz = b.z - t[2];
-        const float reach = (b.w + bounding_radius(S.type[eo], S.shape + 4 * eo)) * 1.001f + 1e-3f;
-        const float d2 = dx * dx + dy * dy + dz * dz;
-        if (d2 * (1.0f - 1e-5f) <= reach * reach) cand |= 1u << o;
+        if (ball_reaches(b, S.type[eo], S.shape + 4 * eo, S.trans + 3 * eo)) cand |= 1u << o;
     }
     return cand;
 }
@@ -385,7 +393,8 @@ __device__ int next_batch(unsigned *counter, ItemBatch &B, const MeshDev &M, con
         if (cand != 0u) {
             const int slot = (int)lanes_below(live);
             B.item[slot] = CULL == CULL_LIST ? list[q] : q;
-            B.cand[slot] = (uint8_t)cand;
+            // a row scene's mask may use all 32 bits: the item recomputes it (item_cand)
+            B.cand[slot] = (uint8_t)(Sc.rows_per_env ? 1u : cand);
         }
         // identical values from every lane
         B.mask_lo = (unsigned)live;
@@ -397,20 +406,36 @@ __device__ int next_batch(unsigned *counter, ItemBatch &B, const MeshDev &M, con
     return uniform(B.b0);
 }
 
+// Candidate mask of an item taken from a batch: the batch keeps 8 bits per
+// item, enough for env rows (at most ETAC_MAX_OBJ objects).  An item row of
+// the hand holds only candidates that passed the same ball test when the row
+// was filled, so its mask is every slot of the row.
+__device__ __forceinline__ unsigned item_cand(const SceneDev &S, int e, int k, unsigned stored) {
+    if (!S.rows_per_env) return stored;
+    const int n = min(S.n_obj[scene_row(S, e, k)], S.O);
+    return uniform(n >= 32 ? ~0u : (1u << n) - 1u);
+}
+
 // Contact (or given contact results) for every node of one (env, patch)
 // item, then the active and passive node lists in ascending node order
 // (wave ballots, prefix over waves).  Writes u_hat of every node into `uhn`
-// ([3][n_max], 0 on passive nodes), the winner into `wobj` when given, and
-// contact_obj into `cobj_out` when computing contact.  Returns m.
-template <bool FROM_INPUT>
+// ([3][n_max], 0 on passive nodes), the winner's slot into `wobj` when
+// given, and contact_obj into `cobj_out` when computing contact (the
+// winner's source id for a row scene with `src`).  Returns m; `touch`
+// counts the active nodes won by external objects (slots below the row's
+// n_ext; 0 without n_ext).  IDS = false (the adjoint's hand-over) skips the
+// id mapping and the touch count.
+template <bool FROM_INPUT, bool IDS = false>
 __device__ int contact_and_compact(const MeshDev &M, const SceneDev &Sc, int E, int n_max, const int8_t *cobj_in,
                                    const float *uhat_in, int8_t *cobj_out, int (&wcnt)[3][kWaves], int e, int k,
                                    int base, int n, unsigned cand, float *uhn, int *alist, int *plist,
-                                   int8_t *wobj, float &umax) {
+                                   int8_t *wobj, float &umax, int &touch) {
     const int N = M.N;
     const size_t EN = (size_t)E * N;
     const int wave = threadIdx.x >> 6;
-    int run_a = 0, run_p = 0;
+    const size_t srow = FROM_INPUT ? 0 : scene_row(Sc, e, k);
+    const int n_ext = (IDS && !FROM_INPUT && Sc.n_ext) ? uniform(Sc.n_ext[srow]) : 0;
+    int run_a = 0, run_p = 0, run_t = 0;
     int ubits = 0;   // largest |u_hat| component of this thread's nodes (bits of a non-negative float)
     for (int i0 = 0; i0 < n; i0 += kWG) {
         const int i = i0 + threadIdx.x;
@@ -428,9 +453,10 @@ __device__ int contact_and_compact(const MeshDev &M, const SceneDev &Sc, int E, 
                     u2 = uhat_in[2 * EN + en];
                 }
             } else {
-                best = contact_node(Sc, e, cand, M.pos[gi], M.pos[N + gi], M.pos[2 * N + gi], M.nrm[gi],
+                best = contact_node(Sc, srow, cand, M.pos[gi], M.pos[N + gi], M.pos[2 * N + gi], M.nrm[gi],
                                     M.nrm[N + gi], M.nrm[2 * N + gi], u0, u1, u2);
-                if (cobj_out) cobj_out[en] = (int8_t)best;
+                if (cobj_out)
+                    cobj_out[en] = (IDS && best >= 0 && Sc.src) ? Sc.src[srow * Sc.O + best] : (int8_t)best;
             }
             uhn[i] = u0;
             uhn[n_max + i] = u1;
@@ -439,22 +465,26 @@ __device__ int contact_and_compact(const MeshDev &M, const SceneDev &Sc, int E, 
             ubits = max(ubits, __float_as_int(fmaxf(fmaxf(fabsf(u0), fabsf(u1)), fabsf(u2))));
         }
         const bool act = valid && best >= 0, pas = valid && best < 0;
-        const unsigned long long ba = __ballot(act), bp = __ballot(pas);
-        // every lane stores the same wave counts (no single-lane block next to the barrier)
-        wcnt[0][wave] = __popcll(ba);
+        const unsigned long long ba = __ballot(act), bp = __ballot(pas), bt = IDS ? __ballot(act && best < n_ext) : 0ull;
+        // every lane stores the same wave counts (no single-lane block next to
+        // the barrier); external-object touches ride in the upper half-word
+        wcnt[0][wave] = __popcll(ba) | (__popcll(bt) << 16);
         wcnt[1][wave] = __popcll(bp);
         wcnt[2][wave] = wave_max_int(ubits);
         __syncthreads();
-        int oa = run_a, op = run_p, ta = 0, tp = 0;
+        int oa = run_a, op = run_p, ta = 0, tp = 0, tt = 0;
         for (int w = 0; w < kWaves; ++w) {
-            if (w < wave) { oa += wcnt[0][w]; op += wcnt[1][w]; }
-            ta += wcnt[0][w];
+            const int ca = wcnt[0][w] & 0xffff;
+            if (w < wave) { oa += ca; op += wcnt[1][w]; }
+            ta += ca;
             tp += wcnt[1][w];
+            tt += wcnt[0][w] >> 16;
         }
         if (act) alist[oa + lanes_below(ba)] = i;
         if (pas) plist[op + lanes_below(bp)] = i;
         run_a += uniform(ta);
         run_p += uniform(tp);
+        run_t += uniform(tt);
         if (i0 + kWG >= n) {   // last chunk: the wave maxima cover every node of the item
             int ub = 0;
             for (int w = 0; w < kWaves; ++w) ub = max(ub, wcnt[2][w]);
@@ -462,6 +492,7 @@ __device__ int contact_and_compact(const MeshDev &M, const SceneDev &Sc, int E, 
         }
         __syncthreads();
     }
+    touch = run_t;
     return uniform(run_a);
 }
 

@@ -21,6 +21,7 @@ struct ContactParams {
     int8_t *cobj;      // [E][N]
     float *uhat;       // [3][E][N] or null
     int32_t *n_active; // [E][K]
+    int32_t *n_touch;  // [E][K] active nodes won by external objects, or null
 };
 
 // One workgroup per env.  The patches' candidate objects are culled first
@@ -29,14 +30,17 @@ struct ContactParams {
 // consecutive threads on consecutive nodes.
 __global__ __launch_bounds__(kWG) void k_contact(ContactParams p) {
     __shared__ int cnt[kMaxPatches];
-    __shared__ uint8_t cand[kMaxPatches];
+    __shared__ int tcnt[kMaxPatches];
+    __shared__ unsigned cand[kMaxPatches];
     const int e = blockIdx.x;
     const MeshDev &M = p.mesh;
+    const SceneDev &S = p.scene;
     const int N = M.N, K = M.K;
-    const size_t EN = (size_t)p.scene.E * N;
+    const size_t EN = (size_t)S.E * N;
     for (int k = threadIdx.x; k < K; k += kWG) {
         cnt[k] = 0;
-        cand[k] = (uint8_t)cull_objects(p.scene, M, e, k);
+        tcnt[k] = 0;
+        cand[k] = cull_objects(S, M, e, k);
     }
     __syncthreads();
     const size_t row = (size_t)e * N;
@@ -45,13 +49,19 @@ __global__ __launch_bounds__(kWG) void k_contact(ContactParams p) {
         float u0 = 0.0f, u1 = 0.0f, u2 = 0.0f;
         const int k = M.node_patch[i];
         const unsigned c = cand[k];
+        int8_t id = -1;
         if (c) {
-            best = contact_node(p.scene, e, c, M.pos[i], M.pos[N + i], M.pos[2 * N + i], M.nrm[i], M.nrm[N + i],
+            const size_t srow = scene_row(S, e, k);
+            best = contact_node(S, srow, c, M.pos[i], M.pos[N + i], M.pos[2 * N + i], M.nrm[i], M.nrm[N + i],
                                 M.nrm[2 * N + i], u0, u1, u2);
-            if (best >= 0) atomicAdd(&cnt[k], 1);
+            if (best >= 0) {
+                atomicAdd(&cnt[k], 1);
+                if (S.n_ext && best < S.n_ext[srow]) atomicAdd(&tcnt[k], 1);
+                id = S.src ? S.src[srow * S.O + best] : (int8_t)best;
+            }
         }
         // results stream out: non-temporal stores keep them from displacing cached inputs
-        __builtin_nontemporal_store((int8_t)best, p.cobj + row + i);
+        __builtin_nontemporal_store(id, p.cobj + row + i);
         if (p.uhat) {
             __builtin_nontemporal_store(u0, p.uhat + row + i);
             __builtin_nontemporal_store(u1, p.uhat + EN + row + i);
@@ -59,13 +69,21 @@ __global__ __launch_bounds__(kWG) void k_contact(ContactParams p) {
         }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < K; k += kWG) p.n_active[(size_t)e * K + k] = cnt[k];
+    for (int k = threadIdx.x; k < K; k += kWG) {
+        p.n_active[(size_t)e * K + k] = cnt[k];
+        if (p.n_touch) p.n_touch[(size_t)e * K + k] = tcnt[k];
+    }
 }
 
 hipError_t launch_contact(const Plan &p, const SceneDev &s, int8_t *cobj, float *uhat, int32_t *n_active,
                           hipStream_t st) {
+    return launch_contact_rows(p, s, cobj, uhat, n_active, nullptr, st);
+}
+
+hipError_t launch_contact_rows(const Plan &p, const SceneDev &s, int8_t *cobj, float *uhat, int32_t *n_active,
+                               int32_t *n_touch, hipStream_t st) {
     if (s.E == 0) return hipSuccess;
-    ContactParams cp{p.mesh, s, cobj, uhat, n_active};
+    ContactParams cp{p.mesh, s, cobj, uhat, n_active, n_touch};
     const int slot = timer_begin(p, ETAC_TIMER_CONTACT, st);
     hipLaunchKernelGGL(k_contact, dim3(s.E), dim3(kWG), 0, st, cp);
     const hipError_t e = hipGetLastError();
@@ -89,6 +107,7 @@ struct StepParams {
     float *u;                // [3][E][N]
     int8_t *cobj_out;        // [E][N] (fused step)
     int32_t *n_active;       // [E][K] (fused step)
+    int32_t *n_touch;        // [E][K] active nodes won by external objects (hand), or null
     uint32_t *saved;         // [E K][kSavedWords] pooling record for the adjoint, or null
 };
 
@@ -160,6 +179,7 @@ __device__ void zero_fill_batch(const StepParams &p, const ItemBatch &B, int b0)
             __builtin_nontemporal_store((int8_t)-1, p.cobj_out + row + i);
         }
         p.n_active[(size_t)e * M.K + k] = 0;
+        if (p.n_touch) p.n_touch[(size_t)e * M.K + k] = 0;
     }
 }
 
@@ -440,9 +460,14 @@ __device__ void process_item(const StepParams &p, StepLds &S, int e, int k, unsi
     const int n = M.offset[k + 1] - base;
     const int mode = p.model.mode;
     float umax;
-    const int m = contact_and_compact<FROM_INPUT>(M, p.scene, p.E, p.scr.n_max, p.cobj_in, p.uhat_in, p.cobj_out,
-                                                  S.wcnt, e, k, base, n, cand, uhn, alist, plist, nullptr, umax);
-    if (!FROM_INPUT && threadIdx.x < 64) p.n_active[(size_t)e * M.K + k] = m;
+    int touch;
+    const int m = contact_and_compact<FROM_INPUT, true>(M, p.scene, p.E, p.scr.n_max, p.cobj_in, p.uhat_in, p.cobj_out,
+                                                  S.wcnt, e, k, base, n, cand, uhn, alist, plist, nullptr, umax,
+                                                  touch);
+    if (!FROM_INPUT && threadIdx.x < 64) {
+        p.n_active[(size_t)e * M.K + k] = m;
+        if (p.n_touch) p.n_touch[(size_t)e * M.K + k] = touch;
+    }
     if (m == 0) {
         write_zero_item(p, e, base, n, false);
         __syncthreads();
@@ -505,9 +530,10 @@ __global__ __launch_bounds__(kWG) void k_step(StepParams p) {
         const int nb = uniform(S.batch.n);
         for (int q = 0; q < nb; ++q) {
             const int item = uniform(S.batch.item[q]);
-            const unsigned cand = uniform((unsigned)S.batch.cand[q]);
             int e, k;
             queue_item(p.mesh, p.E, item, e, k);
+            const unsigned cand = FROM_INPUT ? 0xffffffffu
+                                             : item_cand(p.scene, e, k, uniform((unsigned)S.batch.cand[q]));
             process_item<FROM_INPUT>(p, S, e, k, cand, uhn, resid, alist, plist);
         }
     }
@@ -516,7 +542,7 @@ __global__ __launch_bounds__(kWG) void k_step(StepParams p) {
 
 hipError_t launch_step(const Plan &pl, const SceneDev *s, const ModelDev &m, int n_envs,
                        const int8_t *cobj_in, const float *uhat_in, float *u, int8_t *cobj_out,
-                       int32_t *n_active, uint32_t *saved, hipStream_t st) {
+                       int32_t *n_active, uint32_t *saved, hipStream_t st, int32_t *n_touch) {
     if (n_envs == 0) return hipSuccess;
     StepParams p;
     p.mesh = pl.mesh;
@@ -532,6 +558,7 @@ hipError_t launch_step(const Plan &pl, const SceneDev *s, const ModelDev &m, int
     p.u = u;
     p.cobj_out = cobj_out;
     p.n_active = n_active;
+    p.n_touch = n_touch;
     p.saved = saved;
     const int grid = p.n_items < pl.grid ? p.n_items : pl.grid;
     const int slot = timer_begin(pl, ETAC_TIMER_STEP, st);
@@ -623,6 +650,7 @@ hipError_t launch_step_static(const Plan &pl, const SceneDev &s, const ModelDev 
     p.u = u;
     p.cobj_out = cobj_out;
     p.n_active = n_active;
+    p.n_touch = nullptr;
     p.saved = saved;
     hipLaunchKernelGGL(k_clear_counters, dim3(1), dim3(64), 0, st, scr.counter);
     hipError_t e = hipGetLastError();

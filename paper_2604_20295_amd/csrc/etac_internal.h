@@ -32,13 +32,58 @@ struct MeshDev {
     int K, N, n_max;
 };
 
+// Objects the contact test sees, in rows of O candidates: one row per env
+// (rows_per_env = 0), or one row per (env, patch) item (rows_per_env = K:
+// the articulated hand, whose rows hold each patch's candidates in its link
+// frame).  With `src`, contact_obj reports src[row][winner] instead of the
+// winner's slot; with `n_ext`, slots below n_ext[row] are external objects
+// (their nodes count towards the contact reward).
 struct SceneDev {
-    const int *n_obj;      // [E]
-    const int *type;       // [E][O]
-    const float *shape;    // [E][O][4]
-    const float *rot;      // [E][O][9]
-    const float *trans;    // [E][O][3]
+    const int *n_obj;      // [rows]
+    const int *type;       // [rows][O]
+    const float *shape;    // [rows][O][4]
+    const float *rot;      // [rows][O][9]
+    const float *trans;    // [rows][O][3]
     int E, O;
+    int rows_per_env = 0;
+    const int8_t *src = nullptr;   // [rows][O]
+    const int *n_ext = nullptr;    // [rows]
+};
+
+__host__ __device__ inline size_t scene_row(const SceneDev &S, int e, int k) {
+    return S.rows_per_env ? (size_t)e * S.rows_per_env + k : (size_t)e;
+}
+
+// Articulated hand (etac_plan_set_hand): the link description on the device
+// and the per-item candidate table its pre-pass fills.
+constexpr int kMaxLinks = 24;
+constexpr int kMaxRowObj = 32;     // candidates per item row (one bit each in a 32-bit mask)
+
+struct HandDev {
+    int L;
+    int cap;                       // row capacity: plan max_obj + largest self-contact set
+    const int *patch_link;         // [K]
+    const unsigned *collide;       // [L]
+    const int *ptype;              // [L] primitive type or -1
+    const float *pshape;           // [L][4]
+    const float *prot;             // [L][9] primitive pose in its link frame
+    const float *ptrans;           // [L][3]
+    // candidate table, one row per (env, patch) item
+    int *n_obj;                    // [E K]
+    int *n_ext;                    // [E K]
+    int *type;                     // [E K][cap]
+    float *shape;                  // [E K][cap][4]
+    float *rot;                    // [E K][cap][9]
+    float *trans;                  // [E K][cap][3]
+    int8_t *src;                   // [E K][cap]
+    float *pose_part;              // [E K][cap][12] relative-pose gradient partials (backward)
+    int *n_touch;                  // [E K] reward counts when the caller passes none
+};
+
+// Per-step inputs of the hand: link poses.
+struct LinksDev {
+    const float *rot;              // [E][L][9]
+    const float *trans;            // [E][L][3]
 };
 
 struct ModelDev {
@@ -102,6 +147,8 @@ struct Plan {
     int n_allocs;
     int64_t scratch_bytes;
     Timers *timers;        // null until timing is first turned on
+    HandDev *hand;         // null until etac_plan_set_hand (host copy of the device view)
+    void *hand_mem;        // the hand's device block (one allocation)
 };
 
 // Open a timed span of timer k on stream st; returns the slot, or -1 when
@@ -123,13 +170,27 @@ inline void timer_end(const Plan &p, int k, int slot, hipStream_t st) {
 // Launchers (return hipError_t of the launch).
 hipError_t launch_contact(const Plan &p, const SceneDev &s, int8_t *cobj, float *uhat, int32_t *n_active,
                           hipStream_t st);
+hipError_t launch_contact_rows(const Plan &p, const SceneDev &s, int8_t *cobj, float *uhat, int32_t *n_active,
+                               int32_t *n_touch, hipStream_t st);
 hipError_t launch_step(const Plan &p, const SceneDev *s, const ModelDev &m, int n_envs,
                        const int8_t *cobj_in, const float *uhat_in, float *u, int8_t *cobj_out,
-                       int32_t *n_active, uint32_t *saved, hipStream_t st);
+                       int32_t *n_active, uint32_t *saved, hipStream_t st, int32_t *n_touch = nullptr);
+// hand: with `links`, pose partials are relative-pose gradients of the hand's
+// candidate rows, chained to object and link poses (grad_link_rot/trans).
 hipError_t launch_backward(const Plan &p, const SceneDev *s, const ModelDev &m, int n_envs,
                            const int8_t *cobj_in, const float *uhat_in, const float *grad_u,
                            const uint32_t *saved, float *grad_uhat, float *grad_rot, float *grad_trans,
-                           float *grad_alpha, float *grad_phi, hipStream_t st);
+                           float *grad_alpha, float *grad_phi, hipStream_t st, const SceneDev *world = nullptr,
+                           const LinksDev *links = nullptr, float *grad_link_rot = nullptr,
+                           float *grad_link_trans = nullptr);
+// hand pre-pass: fills the candidate rows of every (env, patch) item from the
+// world scene and the link poses; returns the row view in *rows.
+hipError_t launch_hand_scene(const Plan &p, const SceneDev &world, const LinksDev &links, SceneDev *rows,
+                             hipStream_t st);
+hipError_t launch_hand_reward(const Plan &p, int n_envs, const int32_t *n_touch, float omega_a, int32_t *n_a,
+                              uint32_t *link_mask, float *r_contact, hipStream_t st);
+hipError_t launch_pose_hand(const Plan &p, const SceneDev &world, const LinksDev &links, float *grad_rot,
+                            float *grad_trans, float *grad_link_rot, float *grad_link_trans, hipStream_t st);
 hipError_t init_record_map(const Plan &p);
 
 // The fused step with its scratch in the library's file-scope device array
