@@ -27,10 +27,12 @@ struct ContactParams {
 // One workgroup per env.  The patches' candidate objects are culled first
 // (one mask per patch in LDS), so nodes of patches no object reaches only
 // store their empty result; the others are tested one node per thread,
-// consecutive threads on consecutive nodes.
+// consecutive threads on consecutive nodes.  ROWS: the hand's candidate rows
+// (ids mapped through src, object-won nodes counted).
+template <bool ROWS>
 __global__ __launch_bounds__(kWG) void k_contact(ContactParams p) {
     __shared__ int cnt[kMaxPatches];
-    __shared__ int tcnt[kMaxPatches];
+    __shared__ int tcnt[ROWS ? kMaxPatches : 1];
     __shared__ unsigned cand[kMaxPatches];
     const int e = blockIdx.x;
     const MeshDev &M = p.mesh;
@@ -39,7 +41,7 @@ __global__ __launch_bounds__(kWG) void k_contact(ContactParams p) {
     const size_t EN = (size_t)S.E * N;
     for (int k = threadIdx.x; k < K; k += kWG) {
         cnt[k] = 0;
-        tcnt[k] = 0;
+        if (ROWS) tcnt[k] = 0;
         cand[k] = cull_objects(S, M, e, k);
     }
     __syncthreads();
@@ -56,8 +58,11 @@ __global__ __launch_bounds__(kWG) void k_contact(ContactParams p) {
                                 M.nrm[2 * N + i], u0, u1, u2);
             if (best >= 0) {
                 atomicAdd(&cnt[k], 1);
-                if (S.n_ext && best < S.n_ext[srow]) atomicAdd(&tcnt[k], 1);
-                id = S.src ? S.src[srow * S.O + best] : (int8_t)best;
+                id = (int8_t)best;
+                if (ROWS) {
+                    if (S.n_ext && best < S.n_ext[srow]) atomicAdd(&tcnt[k], 1);
+                    if (S.src) id = S.src[srow * S.O + best];
+                }
             }
         }
         // results stream out: non-temporal stores keep them from displacing cached inputs
@@ -71,7 +76,7 @@ __global__ __launch_bounds__(kWG) void k_contact(ContactParams p) {
     __syncthreads();
     for (int k = threadIdx.x; k < K; k += kWG) {
         p.n_active[(size_t)e * K + k] = cnt[k];
-        if (p.n_touch) p.n_touch[(size_t)e * K + k] = tcnt[k];
+        if (ROWS && p.n_touch) p.n_touch[(size_t)e * K + k] = tcnt[k];
     }
 }
 
@@ -85,7 +90,8 @@ hipError_t launch_contact_rows(const Plan &p, const SceneDev &s, int8_t *cobj, f
     if (s.E == 0) return hipSuccess;
     ContactParams cp{p.mesh, s, cobj, uhat, n_active, n_touch};
     const int slot = timer_begin(p, ETAC_TIMER_CONTACT, st);
-    hipLaunchKernelGGL(k_contact, dim3(s.E), dim3(kWG), 0, st, cp);
+    if (s.rows_per_env) hipLaunchKernelGGL(k_contact<true>, dim3(s.E), dim3(kWG), 0, st, cp);
+    else hipLaunchKernelGGL(k_contact<false>, dim3(s.E), dim3(kWG), 0, st, cp);
     const hipError_t e = hipGetLastError();
     timer_end(p, ETAC_TIMER_CONTACT, slot, st);
     return e;
