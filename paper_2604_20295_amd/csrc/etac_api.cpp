@@ -265,6 +265,7 @@ etac_status etac_plan_create(const etac_mesh *mesh, int32_t n_envs, int32_t max_
         if (e == hipSuccess) e = plan_alloc(p, &b.uhat_st, 3 * EN);
         if (e == hipSuccess) e = plan_alloc(p, &b.gh_st, 3 * EN);
         if (e == hipSuccess) e = plan_alloc(p, &b.m_st, items);
+        if (e == hipSuccess) e = plan_alloc(p, &b.gmax_st, items);
         if (e == hipSuccess) e = plan_alloc(p, &b.live, items);
         if (e == hipSuccess) e = plan_alloc(p, &b.seg_cnt, (items + 1023) / 1024 + 1);
         if (e == hipSuccess) e = etac::init_record_map(p);

@@ -127,6 +127,7 @@ struct DecayLds {
     DecayStage st;
     double dred[kWaves][12];
     int wcnt[3][kWaves];
+    int gmx[kWaves];
     ItemBatch batch;
 };
 
@@ -165,7 +166,7 @@ struct BwdLds {
     float dxs[64][3];             // dL/du_hat of the routed arg-max node of each channel
     double dred[kWaves][12];
     int wcnt[kGivenChunks][2][kWaves];   // compaction counts, one set per chunk of a pass
-    int wmx[2][kWaves];           // per-wave largest |u_hat| and passive |dL/dU| components (float bits)
+    int wmx[2][kWaves];           // per-wave largest |u_hat| component (float bits; row 1 unused)
     BwdScale bsc;                 // the current item's adjoint scales
     ItemBatch batch;
 };
@@ -1224,14 +1225,19 @@ __device__ void pool_argmax(const BwdParams &p, BwdLds &S, int k, int base, int 
 
 // Residual-network adjoint of one item; writes its parameter-gradient
 // partial and adds dL/du_hat of active arg-max nodes into gh.  umax: the
-// largest |u_hat| component of the item's nodes; gmax: the largest |dL/dU|
-// component of its passive nodes (they set the range scales).
+// largest |u_hat| component of the item's nodes; with the largest |dL/dU|
+// component of its passive nodes (k_bwd_decay's gmax_st) it sets the range
+// scales.
 __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, int item, int base, int n, int np,
-                                 const int *plist, const float *uhn, const int8_t *wobj, float *gh, float umax,
-                                 float gmax) {
+                                 const int *plist, const float *uhn, const int8_t *wobj, float *gh, float umax) {
     NetLds &L = S.net;
     const MeshDev &M = p.mesh;
+    // Opaque per item: keeps the compiler from hoisting the per-lane row
+    // addresses of the W4 / W3 loads below out of the item loop, where they
+    // would hold 64-bit addresses in ~60 registers (and spill) for the whole
+    // kernel instead of being formed where they are used.
     const float *phi = p.model.phi;
+    asm volatile("" : "+s"(phi));
     const int N = M.N, n_max = p.scr.n_max;
     const size_t EN = (size_t)p.E * N;
     const size_t row = (size_t)e * N + base;
@@ -1259,7 +1265,7 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
     if (threadIdx.x < 64) {   // wave 0, identical values; published by the stage barrier
         BwdScale bs;
         bs.fone = L.isc.xmul;
-        bs.dre = range_exp(gmax);
+        bs.dre = range_exp(p.bwd.gmax_st[item]);
         bs.d4 = bs.dre + L.c5t;
         bs.d2 = bs.d4 + L.s4t;
         bs.d1 = bs.d2 + L.s2t;
@@ -1499,6 +1505,24 @@ __device__ void decay_item_bwd(const BwdParams &p, DecayLds &S, int item, int e,
         wg_sum12(S.dred, v);
         if (threadIdx.x < 64) p.bwd.alpha_part[item] = (float)v[0];
     }
+    // the largest |dL/dU| component over the passive nodes: the scale of the
+    // network adjoint's gradient operands in k_bwd (these values were just
+    // read by the decay adjoint, so they come from the cache)
+    if (uses_residual(p)) {
+        int gbits = 0;   // bits of a non-negative float: integer order is float order
+        for (int t = threadIdx.x; t < np; t += kWG) {
+            const int i = plist[t];
+            const float g0 = p.grad_u[row + i], g1 = p.grad_u[EN + row + i], g2 = p.grad_u[2 * EN + row + i];
+            gbits = max(gbits, __float_as_int(fmaxf(fmaxf(fabsf(g0), fabsf(g1)), fabsf(g2))));
+        }
+        S.gmx[threadIdx.x >> 6] = wave_max_int(gbits);   // identical in every lane of the wave
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            int g = 0;
+            for (int w = 0; w < kWaves; ++w) g = max(g, S.gmx[w]);
+            p.bwd.gmax_st[item] = __int_as_float(g);
+        }
+    }
     // hand-over of the active nodes to k_bwd
     for (int q = threadIdx.x; q < m; q += kWG) {
         const int j = alist[q];
@@ -1605,17 +1629,15 @@ __global__ __launch_bounds__(256) void k_live_list(BwdParams p) {
 // contact_and_compact does with FROM_INPUT, but kGivenChunks chunks of kWG
 // nodes per pair of barriers: the loads are cheap and their latencies overlap.
 // Lists in ascending node order (chunk, then wave, then lane).  Returns m;
-// umax / gmax: the largest |u_hat| component over the item's nodes and the
-// largest |dL/dU| component (grad_u) over its passive nodes.
+// umax: the largest |u_hat| component over the item's nodes.
 __device__ int compact_given(int E, int N, int n_max, const int8_t *cobj_in, const float *uhat_in,
-                             const float *grad_u, int (&wcnt)[kGivenChunks][2][kWaves], int (&wmx)[2][kWaves],
-                             int e, int base, int n, float *uhn, int *alist, int *plist, int8_t *wobj, float &umax,
-                             float &gmax) {
+                             int (&wcnt)[kGivenChunks][2][kWaves], int (&wmx)[2][kWaves], int e, int base, int n,
+                             float *uhn, int *alist, int *plist, int8_t *wobj, float &umax) {
     constexpr int G = kGivenChunks;
     const size_t EN = (size_t)E * N;
     const int wave = threadIdx.x >> 6;
     int run_a = 0, run_p = 0;
-    int ubits = 0, gbits = 0;   // bits of non-negative floats: integer order is float order
+    int ubits = 0;   // bits of a non-negative float: integer order is float order
     for (int g0 = 0; g0 < n; g0 += G * kWG) {
         bool act[G], pas[G];
 #pragma unroll
@@ -1632,9 +1654,6 @@ __device__ int compact_given(int E, int N, int n_max, const int8_t *cobj_in, con
                     u1 = uhat_in[EN + en];
                     u2 = uhat_in[2 * EN + en];
                     ubits = max(ubits, __float_as_int(fmaxf(fmaxf(fabsf(u0), fabsf(u1)), fabsf(u2))));
-                } else {
-                    const float g0 = grad_u[en], g1 = grad_u[EN + en], g2 = grad_u[2 * EN + en];
-                    gbits = max(gbits, __float_as_int(fmaxf(fmaxf(fabsf(g0), fabsf(g1)), fabsf(g2))));
                 }
                 uhn[i] = u0;
                 uhn[n_max + i] = u1;
@@ -1645,7 +1664,6 @@ __device__ int compact_given(int E, int N, int n_max, const int8_t *cobj_in, con
             pas[c] = valid && best < 0;
         }
         wmx[0][wave] = wave_max_int(ubits);
-        wmx[1][wave] = wave_max_int(gbits);
         unsigned long long ba[G], bp[G];
 #pragma unroll
         for (int c = 0; c < G; ++c) {
@@ -1671,13 +1689,9 @@ __device__ int compact_given(int E, int N, int n_max, const int8_t *cobj_in, con
             run_p += uniform(tp);
         }
         if (g0 + G * kWG >= n) {   // last pass: the wave maxima cover every node of the item
-            int ub = 0, gb = 0;
-            for (int w = 0; w < kWaves; ++w) {
-                ub = max(ub, wmx[0][w]);
-                gb = max(gb, wmx[1][w]);
-            }
+            int ub = 0;
+            for (int w = 0; w < kWaves; ++w) ub = max(ub, wmx[0][w]);
             umax = __int_as_float(uniform(ub));
-            gmax = __int_as_float(uniform(gb));
         }
         __syncthreads();
     }
@@ -1701,15 +1715,14 @@ __device__ void process_item_bwd(const BwdParams &p, BwdLds &S, int item, int e,
     const int8_t *cin = KIND == BWD_STEP ? p.bwd.cobj_st : p.cobj_in;
     const float *uin = KIND == BWD_STEP ? p.bwd.uhat_st : p.uhat_in;
     int m;
-    float umax = 0.0f, gmax = 0.0f;
+    float umax = 0.0f;
     int touch;
     if constexpr (KIND == BWD_CONTACT)
         m = contact_and_compact<false>(M, p.scene, p.E, n_max, nullptr, nullptr, nullptr,
                                        *reinterpret_cast<int (*)[3][kWaves]>(&S.wcnt[0][0][0]), e, k, base, n,
                                        cand, uhn, alist, plist, wobj, umax, touch);
     else
-        m = compact_given(p.E, N, n_max, cin, uin, p.grad_u, S.wcnt, S.wmx, e, base, n, uhn, alist, plist, wobj,
-                          umax, gmax);
+        m = compact_given(p.E, N, n_max, cin, uin, S.wcnt, S.wmx, e, base, n, uhn, alist, plist, wobj, umax);
     if (m == 0) {
         // contact adjoint only: the other kinds never queue items without contact
         if (threadIdx.x < 64) p.bwd.item_flag[item] = 0;
@@ -1726,7 +1739,7 @@ __device__ void process_item_bwd(const BwdParams &p, BwdLds &S, int item, int e,
     }
     __syncthreads();
     if (KIND != BWD_CONTACT && uses_residual(p))
-        residual_adjoint(p, S, e, k, item, base, n, n - m, plist, uhn, wobj, gh, umax, gmax);
+        residual_adjoint(p, S, e, k, item, base, n, n - m, plist, uhn, wobj, gh, umax);
     if (threadIdx.x < 64) p.bwd.item_flag[item] = (KIND != BWD_CONTACT && uses_residual(p)) ? 1 : 0;
     __syncthreads();
     if (KIND == BWD_PROP) {

@@ -226,9 +226,8 @@ __device__ __forceinline__ bool ball_reaches(const float4 &b, int type, const fl
 // Primitives of item (e, k)'s scene row whose bounding ball may reach patch
 // k's bounding sphere (objects of other types, triangle meshes included, are
 // ignored).
-__device__ __forceinline__ unsigned cull_objects(const SceneDev &S, const MeshDev &M, int e, int k) {
+__device__ __forceinline__ unsigned cull_objects(const SceneDev &S, const MeshDev &M, int e, int k, size_t row) {
     unsigned cand = 0;
-    const size_t row = scene_row(S, e, k);
     const int no = min(S.n_obj[row], S.O);
     const float4 b = M.bound[k];
     for (int o = 0; o < no; ++o) {
@@ -237,6 +236,10 @@ __device__ __forceinline__ unsigned cull_objects(const SceneDev &S, const MeshDe
         if (ball_reaches(b, S.type[eo], S.shape + 4 * eo, S.trans + 3 * eo)) cand |= 1u << o;
     }
     return cand;
+}
+
+__device__ __forceinline__ unsigned cull_objects(const SceneDev &S, const MeshDev &M, int e, int k) {
+    return cull_objects(S, M, e, k, scene_row(S, e, k));
 }
 
 // ---------------------------------------------------------------------------

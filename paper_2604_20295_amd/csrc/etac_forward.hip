@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kWG) void k_contact(ContactParams p) {
     for (int k = threadIdx.x; k < K; k += kWG) {
         cnt[k] = 0;
         if (ROWS) tcnt[k] = 0;
-        cand[k] = cull_objects(S, M, e, k);
+        cand[k] = ROWS ? cull_objects(S, M, e, k) : cull_objects(S, M, e, k, (size_t)e);
     }
     __syncthreads();
     const size_t row = (size_t)e * N;
@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kWG) void k_contact(ContactParams p) {
         const unsigned c = cand[k];
         int8_t id = -1;
         if (c) {
-            const size_t srow = scene_row(S, e, k);
+            const size_t srow = ROWS ? scene_row(S, e, k) : (size_t)e;
             best = contact_node(S, srow, c, M.pos[i], M.pos[N + i], M.pos[2 * N + i], M.nrm[i], M.nrm[N + i],
                                 M.nrm[2 * N + i], u0, u1, u2);
             if (best >= 0) {

@@ -116,6 +116,7 @@ struct BwdScratch {
     float *uhat_st;        // [3][E][N] u_hat of active nodes (step adjoint)
     float *gh_st;          // [3][E][N] dL/du_hat of active nodes after the decay adjoint
     int *m_st;             // [E*K]     active-node count of every item
+    float *gmax_st;        // [E*K]     largest |dL/dU| component over each contacted item's passive nodes
     int *live;             // [E*K]     queue positions of the items with contact, in queue order
     int *seg_cnt;          // [n_seg + 1] items with contact per 1024 queue positions; [n_seg] = total
 };
