@@ -9,10 +9,21 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libetac.so")
-SOURCES = ["etac_api.cpp", "etac_forward.hip", "etac_backward.hip", "etac_mesh.hip", "etac_hand.hip"]
-# The adjoint kernel keeps ~500 registers per lane live (one wave per SIMD);
-# letting MFMA results live in VGPRs as well as AGPRs avoids spills there.
-EXTRA = {"etac_backward.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+# (source, object name, extra flags).  The network-adjoint kernel keeps ~450
+# registers per lane live (one wave per SIMD): letting MFMA results live in
+# VGPRs as well as AGPRs, and sinking loop-invariant address computations
+# into the loops that use them, keeps it free of spills.  It is built from
+# etac_backward.hip on its own (ETAC_BWD_NET_ONLY); the decay adjoint, which
+# runs three or four workgroups per CU, is better off without the sinking.
+SOURCES = [
+    ("etac_api.cpp", "etac_api", []),
+    ("etac_forward.hip", "etac_forward", []),
+    ("etac_backward.hip", "etac_backward", ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]),
+    ("etac_backward.hip", "etac_backward_net", ["-DETAC_BWD_NET_ONLY", "-mllvm", "-amdgpu-mfma-vgpr-form=1",
+                                                "-mllvm", "-sink-insts-to-avoid-spills"]),
+    ("etac_mesh.hip", "etac_mesh", []),
+    ("etac_hand.hip", "etac_hand", []),
+]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -25,10 +36,10 @@ FLAGS = [
 
 def build(verbose=False):
     objs = []
-    for src in SOURCES:
+    for src, name, extra in SOURCES:
         path = os.path.join(CSRC, src)
-        obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
-        cmd = [HIPCC, "-x", "hip", *FLAGS, *EXTRA.get(src, []), "-c", path, "-o", obj]
+        obj = os.path.join(CSRC, name + ".o")
+        cmd = [HIPCC, "-x", "hip", *FLAGS, *extra, "-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)

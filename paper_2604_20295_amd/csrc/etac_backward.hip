@@ -109,10 +109,12 @@ __device__ int record_column(int c) {
     return kRecB5 + (c - kB5);
 }
 
+#ifndef ETAC_BWD_NET_ONLY
 __global__ __launch_bounds__(256) void k_record_map(int *map) {
     const int c = blockIdx.x * 256 + threadIdx.x;
     if (c < kPhiN) map[c] = record_column(c);
 }
+#endif
 
 // Staging area of the decay adjoint.
 struct DecayStage {
@@ -1583,6 +1585,7 @@ __device__ __forceinline__ bool item_live(const BwdParams &p, int q) {
     return p.bwd.m_st[(size_t)e * p.mesh.K + k] > 0;
 }
 
+#ifndef ETAC_BWD_NET_ONLY
 __global__ __launch_bounds__(256) void k_live_count(BwdParams p) {
     __shared__ int wsum[kWaves];
     const int s = blockIdx.x, wave = threadIdx.x >> 6;
@@ -1619,6 +1622,8 @@ __global__ __launch_bounds__(256) void k_live_list(BwdParams p) {
     }
     if (s == (int)gridDim.x - 1 && threadIdx.x < 64) p.bwd.seg_cnt[gridDim.x] = run;
 }
+
+#endif
 
 // ---------------------------------------------------------------------------
 // k_bwd: network and contact adjoint
@@ -1801,6 +1806,20 @@ __global__ __launch_bounds__(kWG) void k_bwd(BwdParams p) {
     }
 }
 
+// The network-adjoint kernel is built in a translation unit of its own
+// (this file with ETAC_BWD_NET_ONLY), with instruction sinking so that its
+// loop-invariant per-lane addresses are formed where used instead of held
+// across the item loop: one wave per SIMD leaves no room for them.
+#ifdef ETAC_BWD_NET_ONLY
+hipError_t launch_bwd_net(const BwdParams &p, int kind, int grid, hipStream_t st) {
+    if (kind == BWD_STEP) hipLaunchKernelGGL(k_bwd<BWD_STEP>, dim3(grid), dim3(kWG), 0, st, p);
+    else if (kind == BWD_PROP) hipLaunchKernelGGL(k_bwd<BWD_PROP>, dim3(grid), dim3(kWG), 0, st, p);
+    else hipLaunchKernelGGL(k_bwd<BWD_CONTACT>, dim3(grid), dim3(kWG), 0, st, p);
+    return hipGetLastError();
+}
+#else
+hipError_t launch_bwd_net(const BwdParams &p, int kind, int grid, hipStream_t st);
+
 // ---------------------------------------------------------------------------
 // fixed-order reductions of the per-item partials
 // ---------------------------------------------------------------------------
@@ -1970,9 +1989,7 @@ hipError_t launch_backward(const Plan &pl, const SceneDev *s, const ModelDev &m,
     // network and contact adjoint of the contacted items, one workgroup per CU
     const int grid = min(p.n_items, pl.cu_count);
     slot = timer_begin(pl, ETAC_TIMER_BACKWARD, st);
-    if (s) hipLaunchKernelGGL(k_bwd<BWD_STEP>, dim3(grid), dim3(kWG), 0, st, p);
-    else hipLaunchKernelGGL(k_bwd<BWD_PROP>, dim3(grid), dim3(kWG), 0, st, p);
-    e = hipGetLastError();
+    e = launch_bwd_net(p, s ? BWD_STEP : BWD_PROP, grid, st);
     timer_end(pl, ETAC_TIMER_BACKWARD, slot, st);
     if (e != hipSuccess) return e;
     slot = timer_begin(pl, ETAC_TIMER_REDUCE, st);
@@ -2017,8 +2034,7 @@ hipError_t launch_contact_backward(const Plan &pl, const SceneDev &s, const floa
     p.net_batch = pl.net_batch;
     p.n_seg = (p.n_items + 1023) / 1024;
     const int grid = min(p.n_items, pl.cu_count);
-    hipLaunchKernelGGL(k_bwd<BWD_CONTACT>, dim3(grid), dim3(kWG), 0, st, p);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_bwd_net(p, BWD_CONTACT, grid, st);
     if (e != hipSuccess) return e;
     const int nt = s.E * s.O * 12;
     hipLaunchKernelGGL(k_pose, dim3((nt + 255) / 256), dim3(256), 0, st, pl.bwd.pose_part, s.E, pl.K, s.O, grad_rot,
@@ -2030,5 +2046,7 @@ hipError_t init_record_map(const Plan &pl) {
     hipLaunchKernelGGL(k_record_map, dim3((kPhiN + 255) / 256), dim3(256), 0, 0, pl.bwd.rec_map);
     return hipGetLastError();
 }
+
+#endif  // ETAC_BWD_NET_ONLY
 
 }  // namespace etac
