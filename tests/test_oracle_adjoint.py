@@ -15,7 +15,7 @@ from scenes import SPHERE, BOX, CAPSULE, MODE_FULL, MODE_DECAY_ONLY, MODE_RESIDU
 from tests.torch_ref import primitive_disp, propagate_env, t64
 
 
-def _fd_check(oracle_lib, mesh, scene, model, w, env_obj_list, phi_idx, rtol=2e-5):
+def _fd_check(oracle_lib, mesh, scene, model, w, env_obj_list, phi_idx, rtol=1e-6):
     g = oracle_lib.backward(mesh, scene, model, w)
     checked = 0
     for (e, o) in env_obj_list:
