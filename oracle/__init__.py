@@ -501,3 +501,35 @@ def hand_fd_gradients(mesh, hand, scene, links, model, w, env=0, link=None, obj=
         each[key] = np.array(flags, dtype=bool)
     res["ok_each"] = each
     return res, all(bool(v.all()) for v in each.values())
+
+
+# ----------------------------------------------------------------------------
+# real-sensor regressor (inference)
+# ----------------------------------------------------------------------------
+
+REG_SIZE = 88204
+REG_LAYERS = (("E1", 64, 6), ("e1", 64, 1), ("E2", 64, 64), ("e2", 64, 1), ("E3", 256, 64), ("e3", 256, 1),
+              ("A1", 128, 256), ("a1", 128, 1), ("a2", 128, 1), ("a0", 4, 1), ("D1", 128, 256), ("d1", 128, 1),
+              ("D2", 8, 128), ("d2", 8, 1))
+
+
+def reg_offsets():
+    """Offset and shape of every block of the packed regressor parameters."""
+    out, off = {}, 0
+    for name, o, i in REG_LAYERS:
+        out[name] = (off, (o, i) if i > 1 else (o,))
+        off += o * i
+    assert off == REG_SIZE
+    return out
+
+
+def regress(mesh, reg, u):
+    """Taxel outputs y [E][K][8] of the attention-pooled PointNet regressor
+    for displacements u [3][E][N] (FP64)."""
+    lib = _load()
+    K, N, off, pos, _, origin = _mesh_args(mesh)
+    uu = _f64(u)
+    E = uu.shape[1]
+    y = np.empty((E, K.value, 8))
+    _call(lib.oracle_regress, K, N, off, pos, origin, C.c_int(E), _f64(reg), uu, y)
+    return y

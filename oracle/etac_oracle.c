@@ -1674,3 +1674,135 @@ int oracle_hand_backward(int K, int N, const int32_t *offset, const double *pos,
     free(nt);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* 4. real-sensor regressor (inference)                                     */
+/* ------------------------------------------------------------------------ */
+/*
+ * The paper maps simulated surface displacements to the outputs of a real
+ * sensor's eight pressure taxels with a PointNet-based regressor that has
+ * residual connections and pools its per-node features with attention
+ * instead of a max (appendix, "Modeling Real Sensors"); the attention is an
+ * MLP [256, 128, 1] with tanh whose scores are normalised by a softmax.  The
+ * rest of the architecture is in a figure that is not available.  Reading
+ * (listed in the design notes), per (env, patch) item:
+ *   x_i  = [p_i - o_k, U_i]                      (6; U the step's output)
+ *   h1_i = relu(E1 x_i + e1)                     (64)
+ *   h2_i = relu(E2 h1_i + e2) + h1_i             (64, residual)
+ *   f_i  = relu(E3 h2_i + e3)                    (256)
+ *   s_i  = a2 . tanh(A1 f_i + a1) + a0           (128 -> 1)
+ *   w    = softmax(s) over the item's nodes      (max subtracted first)
+ *   g    = sum_i w_i f_i                         (256)
+ *   y    = D2 relu(D1 g + d1) + d2               (128 -> 8 taxels)
+ * Packed parameters (FP32): E1[64][6] e1[64] E2[64][64] e2[64] E3[256][64]
+ * e3[256] A1[128][256] a1[128] a2[128] a0[4] (a0[0] used) D1[128][256] d1[128]
+ * D2[8][128] d2[8]: REG_N = 88204 values.
+ */
+#define REG_N 88204
+typedef struct {
+    const double *E1, *e1, *E2, *e2, *E3, *e3, *A1, *a1, *a2, *a0, *D1, *d1, *D2, *d2;
+} reg_t;
+
+static reg_t reg_view(const double *r) {
+    reg_t R;
+    R.E1 = r; r += 64 * 6;
+    R.e1 = r; r += 64;
+    R.E2 = r; r += 64 * 64;
+    R.e2 = r; r += 64;
+    R.E3 = r; r += 256 * 64;
+    R.e3 = r; r += 256;
+    R.A1 = r; r += 128 * 256;
+    R.a1 = r; r += 128;
+    R.a2 = r; r += 128;
+    R.a0 = r; r += 4;
+    R.D1 = r; r += 128 * 256;
+    R.d1 = r; r += 128;
+    R.D2 = r; r += 8 * 128;
+    R.d2 = r;
+    return R;
+}
+
+/* per-node feature f (256) and attention score of node input x (6) */
+static double reg_node(const reg_t *R, const double x[6], double f[256]) {
+    double h1[64], h2[64], t[128];
+    for (int o = 0; o < 64; ++o) {
+        double a = R->e1[o];
+        for (int c = 0; c < 6; ++c) a += R->E1[o * 6 + c] * x[c];
+        h1[o] = relu(a);
+    }
+    for (int o = 0; o < 64; ++o) {
+        double a = R->e2[o];
+        for (int c = 0; c < 64; ++c) a += R->E2[o * 64 + c] * h1[c];
+        h2[o] = relu(a) + h1[o];
+    }
+    for (int o = 0; o < 256; ++o) {
+        double a = R->e3[o];
+        for (int c = 0; c < 64; ++c) a += R->E3[o * 64 + c] * h2[c];
+        f[o] = relu(a);
+    }
+    double s = R->a0[0];
+    for (int o = 0; o < 128; ++o) {
+        double a = R->a1[o];
+        for (int c = 0; c < 256; ++c) a += R->A1[o * 256 + c] * f[c];
+        t[o] = tanh(a);
+        s += R->a2[o] * t[o];
+    }
+    return s;
+}
+
+/* Taxel outputs of every (env, patch) item: y [E][K][8]; u [3][E][N] the
+ * displacements (link frames for the articulated hand). */
+int oracle_regress(int K, int N, const int32_t *offset, const double *pos, const double *origin, int E,
+                   const double *reg, const double *u, double *y) {
+    reg_t R = reg_view(reg);
+    int nmax = 0;
+    for (int k = 0; k < K; ++k)
+        if (offset[k + 1] - offset[k] > nmax) nmax = offset[k + 1] - offset[k];
+#pragma omp parallel
+    {
+        double *F = malloc(sizeof(double) * (size_t)nmax * 256);
+        double *S = malloc(sizeof(double) * (size_t)nmax);
+#pragma omp for schedule(static)
+        for (int e = 0; e < E; ++e)
+            for (int k = 0; k < K; ++k) {
+                const int n = offset[k + 1] - offset[k];
+                double smax = -INFINITY;
+                for (int j = 0; j < n; ++j) {
+                    const int i = offset[k] + j;
+                    const size_t ei = (size_t)e * N + i;
+                    double x[6];
+                    for (int a = 0; a < 3; ++a) {
+                        x[a] = pos[(size_t)a * N + i] - origin[3 * k + a];
+                        x[3 + a] = u[(size_t)a * E * N + ei];
+                    }
+                    S[j] = reg_node(&R, x, F + (size_t)j * 256);
+                    if (S[j] > smax) smax = S[j];
+                }
+                double z = 0.0;
+                for (int j = 0; j < n; ++j) {
+                    S[j] = exp(S[j] - smax);
+                    z += S[j];
+                }
+                double g[256], h[128];
+                for (int c = 0; c < 256; ++c) {
+                    double a = 0.0;
+                    for (int j = 0; j < n; ++j) a += S[j] * F[(size_t)j * 256 + c];
+                    g[c] = a / z;
+                }
+                for (int o = 0; o < 128; ++o) {
+                    double a = R.d1[o];
+                    for (int c = 0; c < 256; ++c) a += R.D1[o * 256 + c] * g[c];
+                    h[o] = relu(a);
+                }
+                double *yo = y + ((size_t)e * K + k) * 8;
+                for (int o = 0; o < 8; ++o) {
+                    double a = R.d2[o];
+                    for (int c = 0; c < 128; ++c) a += R.D2[o * 128 + c] * h[c];
+                    yo[o] = a;
+                }
+            }
+        free(F);
+        free(S);
+    }
+    return 0;
+}

@@ -180,6 +180,30 @@ def draw_phi(rng):
     return phi
 
 
+REG_LAYERS = (("E1", 64, 6), ("e1", 64, 1), ("E2", 64, 64), ("e2", 64, 1), ("E3", 256, 64), ("e3", 256, 1),
+              ("A1", 128, 256), ("a1", 128, 1), ("a2", 128, 1), ("a0", 4, 1), ("D1", 128, 256), ("d1", 128, 1),
+              ("D2", 8, 128), ("d2", 8, 1))
+REG_SIZE = sum(o * i for _, o, i in REG_LAYERS)
+
+
+def draw_regressor(rng):
+    """Real-sensor regressor parameters (packed as REG_LAYERS): every weight
+    and bias U(+-1/sqrt(fan_in)) of its layer; a0 (the attention score's
+    offset, softmax-invariant) is 0."""
+    fan = {"e1": 6, "e2": 64, "e3": 64, "a1": 256, "a2": 128, "d1": 256, "d2": 128}
+    parts = []
+    for name, o, i in REG_LAYERS:
+        n = fan.get(name, i)
+        lim = 1.0 / np.sqrt(n)
+        if name == "a0":
+            parts.append(np.zeros(o * i))
+        else:
+            parts.append(rng.uniform(-lim, lim, size=o * i))
+    reg = np.concatenate(parts).astype(np.float32)
+    assert reg.size == REG_SIZE
+    return reg
+
+
 def draw_model(rng, pitches, mode=MODE_FULL):
     """alpha_k = kappa_k / pitch_k with kappa ~ U(1.5, 3)."""
     kappa = rng.uniform(1.5, 3.0, size=len(pitches))

@@ -18,6 +18,7 @@ from tests import test_oracle_contact as TC
 from tests import test_oracle_hand as TH
 from tests import test_oracle_mesh as TM
 from tests import test_oracle_propagate as TP
+from tests import test_oracle_regress as TR
 
 SRC = oracle.SRC
 
@@ -80,6 +81,13 @@ MUTANTS = [
     ("hand: reward counts self-contact", "if (C->id[s] < O) ++nt;", "++nt;"),
     ("hand: reward without the empty-contact penalty", "double ra = s > 0 ? (double)s / (double)P->N : -0.1;",
      "double ra = s > 0 ? (double)s / (double)P->N : 0.0;"),
+    ("regressor: no residual connection", "h2[o] = relu(a) + h1[o];", "h2[o] = relu(a);"),
+    ("regressor: attention weights not normalised", "g[c] = a / z;", "g[c] = a;"),
+    ("regressor: relu instead of tanh in the attention", "t[o] = tanh(a);", "t[o] = relu(a);"),
+    ("regressor: positions not relative to the origin", "x[a] = pos[(size_t)a * N + i] - origin[3 * k + a];",
+     "x[a] = pos[(size_t)a * N + i];"),
+    ("regressor: head without its hidden relu", "h[o] = relu(a);\n                }\n                double *yo",
+     "h[o] = a;\n                }\n                double *yo"),
 ]
 
 
@@ -113,6 +121,10 @@ def _pins():
         lambda o: TH.test_adjoint_translation_and_rotation_sums_vanish(o),
         lambda o: TH.test_contact_reward_worked_example(o),
         lambda o: [TH.test_hand_pose_adjoint_vs_central_differences(o, m) for m in (1, 0)],
+        lambda o: TR.test_closed_form_softmax_weighted_mean(o),
+        lambda o: TR.test_single_node_and_uniform_attention(o),
+        lambda o: TR.test_node_order_duplication_and_score_shift_change_nothing(o),
+        lambda o: TR.test_residual_connection(o),
     ]
 
 
