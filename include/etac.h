@@ -343,7 +343,8 @@ typedef enum {
     ETAC_TIMER_BACKWARD = 2,  /* k_bwd: network and contact adjoint of contacted items   */
     ETAC_TIMER_REDUCE = 3,    /* the fixed-order reductions that follow k_bwd, as one span */
     ETAC_TIMER_BWD_DECAY = 4, /* k_bwd_decay: contact and Eq. 1 adjoint, before k_bwd     */
-    ETAC_TIMER_COUNT = 5
+    ETAC_TIMER_REGRESS = 5,   /* k_regress: the real-sensor regressor (etac_regress)      */
+    ETAC_TIMER_COUNT = 6
 } etac_timer;
 
 /* Turn timing on (enable != 0) or off.  The first call that turns it on
@@ -444,6 +445,38 @@ etac_status etac_hand_step_backward(etac_plan *plan, const etac_scene *scene, co
                                     const etac_model *model, const float *grad_u, const void *saved,
                                     float *grad_rot, float *grad_trans, float *grad_link_rot,
                                     float *grad_link_trans, float *grad_alpha, float *grad_phi, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Real-sensor regressor (appendix, "Modeling Real Sensors"): the displacement
+ * field of each (env, patch) item is mapped to the eight pressure-taxel
+ * outputs of a real sensor by a PointNet-style network with a residual layer
+ * whose per-node features are pooled with attention (an MLP [256, 128, 1]
+ * with tanh, normalised by a softmax over the item's nodes).  Per node i of
+ * patch k:
+ *   x_i  = [p_i - o_k, U_i]                  (6)
+ *   h1_i = relu(E1 x_i + e1)                 (64)
+ *   h2_i = relu(E2 h1_i + e2) + h1_i         (64, residual)
+ *   f_i  = relu(E3 h2_i + e3)                (256)
+ *   s_i  = a2 . tanh(A1 f_i + a1) + a0       (scalar score)
+ * per item: w = softmax(s), g = sum_i w_i f_i, y = D2 relu(D1 g + d1) + d2.
+ * reg: packed FP32, ETAC_REG_SIZE floats: E1[64][6] e1[64] E2[64][64] e2[64]
+ * E3[256][64] e3[256] A1[128][256] a1[128] a2[128] a0[4] (a0[0] used; the
+ * softmax does not depend on it) D1[128][256] d1[128] D2[8][128] d2[8].
+ * Arithmetic: E1 and E2 at FP32 level (split FP16 operands), E3 and A1 on FP16
+ * operands with FP32 accumulation, softmax, pooling and head in FP32.
+ * ------------------------------------------------------------------------ */
+#define ETAC_REG_SIZE 88204
+#define ETAC_TAXELS 8
+
+/* taxels [E][K][8] (DEVICE, overwritten) from u [3][E][N] and n_active [E][K]
+ * (DEVICE, as written by a step call with the same n_envs = E; items with
+ * n_active 0 must have U = 0 on their patch, as every step leaves them: they
+ * take the patch's output at U = 0, evaluated once per call).  reg DEVICE
+ * [ETAC_REG_SIZE].  0 <= n_envs <= the plan's n_envs (ETAC_ERR_SHAPE).  Uses
+ * the plan's own scratch (a [K][8] table and a work counter), so calls on one
+ * plan must not overlap; non-finite parameters propagate to the outputs. */
+etac_status etac_regress(etac_plan *plan, const float *reg, int32_t n_envs, const float *u,
+                         const int32_t *n_active, float *taxels, void *stream);
 
 #ifdef __cplusplus
 }

@@ -24,6 +24,9 @@ ETAC_SAVED_WORDS = 128     # 32-bit words of the pooling record per (env, patch)
 ETAC_MAX_OBJ = 8
 ETAC_PLAN_BACKWARD = 1
 ETAC_TIMER_CONTACT, ETAC_TIMER_STEP, ETAC_TIMER_BACKWARD, ETAC_TIMER_REDUCE, ETAC_TIMER_BWD_DECAY = 0, 1, 2, 3, 4
+ETAC_TIMER_REGRESS = 5
+ETAC_REG_SIZE = 88204      # packed regressor parameters
+ETAC_TAXELS = 8
 ETAC_TIMER_SLOTS = 256
 
 EXPORTED = (
@@ -34,6 +37,7 @@ EXPORTED = (
     "etac_plan_set_timing", "etac_plan_kernel_time", "etac_plan_set_batch",
     "etac_plan_set_launch", "etac_plan_get_launch", "etac_plan_autotune",
     "etac_meshset_create", "etac_meshset_destroy", "etac_contact_mesh", "etac_contact_mesh_backward",
+    "etac_regress",
 )
 
 
@@ -120,6 +124,7 @@ def lib():
                                 vp], i32),
             "etac_hand_step_backward": ([vp, P(etac_scene), P(etac_links), P(etac_model), vp, vp, vp, vp, vp, vp,
                                          vp, vp, vp], i32),
+            "etac_regress": ([vp, vp, i32, vp, vp, vp, vp], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -506,3 +511,16 @@ def etac_hand_step_backward(plan, scene, links, model, grad_u, grad_rot, grad_tr
                                          _ptr(saved), _ptr(grad_rot), _ptr(grad_trans), _ptr(grad_link_rot),
                                          _ptr(grad_link_trans), _ptr(grad_alpha), _ptr(grad_phi),
                                          _stream(plan.device)))
+
+
+def etac_regress(plan, reg, u, n_active, taxels):
+    """Real-sensor taxel outputs taxels [E][K][8] of the displacement field u
+    [3][E][N] (n_active [E][K] from the same step)."""
+    import torch
+    E = u.shape[1] if u is not None and u.dim() == 3 else 0
+    _req(reg, torch.float32, (ETAC_REG_SIZE,), "reg", plan.device)
+    _req(u, torch.float32, (3, E, plan.N), "u", plan.device)
+    _req(n_active, torch.int32, (E, plan.K), "n_active", plan.device)
+    _req(taxels, torch.float32, (E, plan.K, ETAC_TAXELS), "taxels", plan.device)
+    _check("etac_regress", lib().etac_regress(plan.handle, _ptr(reg), int(E), _ptr(u), _ptr(n_active), _ptr(taxels),
+                                              _stream(plan.device)))

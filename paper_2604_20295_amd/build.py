@@ -23,6 +23,7 @@ SOURCES = [
                                                 "-mllvm", "-sink-insts-to-avoid-spills"]),
     ("etac_mesh.hip", "etac_mesh", []),
     ("etac_hand.hip", "etac_hand", []),
+    ("etac_regress.hip", "etac_regress", []),
 ]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -247,8 +247,13 @@ etac_status etac_plan_create(const etac_mesh *mesh, int32_t n_envs, int32_t max_
     if (e == hipSuccess) e = plan_alloc(p, &p.scr.resid, G * 3 * n_max);
     if (e == hipSuccess) e = plan_alloc(p, &p.scr.alist, G * n_max);
     if (e == hipSuccess) e = plan_alloc(p, &p.scr.plist, G * n_max);
-    if (e == hipSuccess) e = plan_alloc(p, &p.scr.counter, 4);
-    if (e == hipSuccess) e = hipMemset(p.scr.counter, 0, 4 * sizeof(unsigned));
+    // work counters: [0..1] forward, [2..3] adjoint, [4..5] regressor
+    if (e == hipSuccess) e = plan_alloc(p, &p.scr.counter, 8);
+    if (e == hipSuccess) e = hipMemset(p.scr.counter, 0, 8 * sizeof(unsigned));
+    // regressor: rest outputs, and a pooled-feature row per item it may process
+    if (e == hipSuccess) e = plan_alloc(p, &p.reg_rest, 8 * (size_t)K);
+    if (e == hipSuccess) e = plan_alloc(p, &p.reg_pooled, ((size_t)n_envs * K + K) * 256);
+    if (e == hipSuccess) e = plan_alloc(p, &p.reg_row, (size_t)n_envs * K + K);
 
     if (e == hipSuccess && (flags & ETAC_PLAN_BACKWARD)) {
         const size_t items = (size_t)n_envs * K;
@@ -771,6 +776,16 @@ etac_status etac_hand_step_backward(etac_plan *plan, const etac_scene *scene, co
         e = etac::launch_backward(p, &rows, model_dev(model), scene->n_envs, nullptr, nullptr, grad_u,
                                   static_cast<const uint32_t *>(saved), nullptr, grad_rot, grad_trans, grad_alpha,
                                   grad_phi, s, &world, &lk, grad_link_rot, grad_link_trans);
+    return e == hipSuccess ? ETAC_OK : hip_fail(e);
+}
+
+etac_status etac_regress(etac_plan *plan, const float *reg, int32_t n_envs, const float *u,
+                         const int32_t *n_active, float *taxels, void *stream) {
+    if (!plan) return ETAC_ERR_NULL;
+    const etac::Plan &p = plan->p;
+    if (n_envs < 0 || n_envs > p.n_envs) return ETAC_ERR_SHAPE;
+    if (n_envs > 0 && (!reg || !u || !n_active || !taxels)) return ETAC_ERR_NULL;
+    const hipError_t e = etac::launch_regress(p, reg, n_envs, u, n_active, taxels, (hipStream_t)stream);
     return e == hipSuccess ? ETAC_OK : hip_fail(e);
 }
 

@@ -98,7 +98,7 @@ struct Scratch {
     float *resid;          // [G][3][n_max] residual-network output
     int *alist;            // [G][n_max]    active node indices (patch-local, ascending)
     int *plist;            // [G][n_max]    passive node indices (patch-local, ascending)
-    unsigned *counter;     // [4]           work-queue counters (self-resetting)
+    unsigned *counter;     // [8]           work-queue counters (self-resetting)
     int n_max;
 };
 
@@ -144,12 +144,15 @@ struct Plan {
     BwdScratch bwd;
     bool has_bwd;
     // device allocations owned by the plan
-    void *allocs[32];
+    void *allocs[48];
     int n_allocs;
     int64_t scratch_bytes;
     Timers *timers;        // null until timing is first turned on
     HandDev *hand;         // null until etac_plan_set_hand (host copy of the device view)
     void *hand_mem;        // the hand's device block (one allocation)
+    float *reg_rest;       // [K][8] regressor outputs of the patches at U = 0
+    float *reg_pooled;     // [E K + K][256] regressor pooled features, one row per processed item
+    int *reg_row;          // [E K + K] the item of each row
 };
 
 // Open a timed span of timer k on stream st; returns the slot, or -1 when
@@ -169,6 +172,9 @@ inline void timer_end(const Plan &p, int k, int slot, hipStream_t st) {
 }
 
 // Launchers (return hipError_t of the launch).
+// Real-sensor regressor: taxels [E][K][8] from u [3][E][N] (n_envs = E).
+hipError_t launch_regress(const Plan &p, const float *reg, int n_envs, const float *u, const int32_t *n_active,
+                          float *taxels, hipStream_t st);
 hipError_t launch_contact(const Plan &p, const SceneDev &s, int8_t *cobj, float *uhat, int32_t *n_active,
                           hipStream_t st);
 hipError_t launch_contact_rows(const Plan &p, const SceneDev &s, int8_t *cobj, float *uhat, int32_t *n_active,
