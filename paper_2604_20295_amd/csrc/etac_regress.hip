@@ -21,12 +21,13 @@
 //            -> s = a2 . tanh(A1 f + a1) + a0.
 // Per item:  w = softmax(s), g = sum w f, y = D2 relu(D1 g + d1) + d2 (8).
 //
-// Precision: E1 and E2 (the layers that see positions and displacements) use
-// split-FP16 operands (hi + lo, FP32-level); E3 and A1 (49k of the 54k
-// multiply-adds per node) take FP16 operands with FP32 accumulation; the
-// pooled features are the FP16 operands of A1 (so f is held once, in 32
-// registers); softmax weights, pooling sums and the head are FP32.  FP16
-// rounding is relative 2^-11 at most.
+// Precision: E1, the layer that sees positions and displacements, uses
+// split-FP16 operands (hi + lo, FP32-level), so that displacements well
+// below the position scale keep their bits; E2, E3 and A1 take FP16
+// operands with FP32 accumulation; the pooled features are the FP16
+// operands of A1 (f is held once, in 32 registers per tile); softmax
+// weights, pooling sums and the head are FP32.  FP16 rounding is relative
+// 2^-11 at most.
 #include "etac_device.h"
 
 namespace etac {
@@ -45,7 +46,7 @@ constexpr float kTwoLog2e = 2.8853900817779268f;
 
 struct RegLds {
     half8 e1h[4 * 64], e1l[4 * 64];              // [E1 | e1] split, inputs padded 7 -> 32 (x_6 = 1 carries e1)
-    half8 e2h[4 * 2 * 64], e2l[4 * 2 * 64];      // E2 split, [ot][s][lane], chain order
+    half8 e2[4 * 2 * 64];                        // E2 FP16, [ot][s][lane], chain order
     half8 e3[16 * 2 * 64];                       // E3 FP16, [ot][s][lane], 256 outputs
     half8 a1[8 * 8 * 64];                        // 2 log2(e) A1 in FP16, [ot][s][lane], 128 outputs over 256 inputs
     float be2[64], be3[256], ba1[128], wa2[128]; // e2, e3, 2 log2(e) a1, -2 a2
@@ -76,10 +77,10 @@ __device__ void stage_regressor(RegLds &L, const float *R) {
     }
     for (int idx = tid; idx < 4 * 2 * 64; idx += kRegWG) {
         const int lane = idx & 63, s = (idx >> 6) & 1, ot = idx >> 7, q = lane >> 4;
-        float x[8];
+        half8 h;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) x[e] = R[kRE2 + (ot * 16 + (lane & 15)) * 64 + chain_k(s, q, e)];
-        split8(x, L.e2h[idx], L.e2l[idx]);
+        for (int e = 0; e < 8; ++e) h[e] = (_Float16)R[kRE2 + (ot * 16 + (lane & 15)) * 64 + chain_k(s, q, e)];
+        L.e2[idx] = h;
     }
     for (int idx = tid; idx < 16 * 2 * 64; idx += kRegWG) {
         const int lane = idx & 63, s = (idx >> 6) & 1, ot = idx >> 7, q = lane >> 4;
@@ -132,13 +133,15 @@ __device__ __forceinline__ float fma_half(float w, unsigned h, float acc) {
 // tile's features f (256) as FP16 B operands of A1 (element e is feature
 // chain_k(s, l >> 4, e) of node l & 15), and sc[i], the attention score of
 // the lane's node up to a constant (the same in the four lanes of a node).
-// Each weight fragment is read from LDS once per pass and used by every tile.
+// Each weight fragment is read from LDS once per pass and used by every
+// tile; A1 runs output block by output block so that the tanh of one block
+// overlaps the MFMAs of the next.
 __device__ __forceinline__ void regress_tiles(const RegLds &L, const half8 (&xh)[kRegNT], const half8 (&xl)[kRegNT],
                                               half8 (&fb)[kRegNT][8], float (&sc)[kRegNT]) {
     constexpr int NT = kRegNT;
     reload_fence();
     const int lane = lane_id(), gq = lane >> 4;
-    floatx4 h1[NT][4], h2[NT][4];
+    floatx4 h1[NT][4];
     {
         const floatx4 z = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -148,102 +151,77 @@ __device__ __forceinline__ void regress_tiles(const RegLds &L, const half8 (&xh)
             for (int i = 0; i < NT; ++i) h1[i][ot] = relu4(mfma_split(wh, wl, xh[i], xl[i], z));
         }
     }
+    half8 b0[NT], b1[NT];   // h2 as FP16 B operands of E3
     {
-        half8 bh[NT][2], bl[NT][2];
+        half8 c0[NT], c1[NT];   // h1 as FP16 B operands of E2
 #pragma unroll
         for (int i = 0; i < NT; ++i) {
-            split_chain(h1[i], bh[i], bl[i]);
-#pragma unroll
-            for (int ot = 0; ot < 4; ++ot) h2[i][ot] = *reinterpret_cast<const floatx4 *>(&L.be2[ot * 16 + 4 * gq]);
+            c0[i] = chain_f16(h1[i], 0);
+            c1[i] = chain_f16(h1[i], 1);
         }
+        floatx4 h2[NT][4];
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            half8 wh[4], wl[4];
+        for (int ot = 0; ot < 4; ++ot) {
+            const floatx4 bias = *reinterpret_cast<const floatx4 *>(&L.be2[ot * 16 + 4 * gq]);
+            const half8 w0 = L.e2[(ot * 2 + 0) * 64 + lane], w1 = L.e2[(ot * 2 + 1) * 64 + lane];
 #pragma unroll
-            for (int ot = 0; ot < 4; ++ot) {
-                wh[ot] = L.e2h[(ot * 2 + s) * 64 + lane];
-                wl[ot] = L.e2l[(ot * 2 + s) * 64 + lane];
-            }
-#pragma unroll
-            for (int i = 0; i < NT; ++i)
-#pragma unroll
-                for (int ot = 0; ot < 4; ++ot) h2[i][ot] = mfma16(wh[ot], bh[i][s], h2[i][ot]);
-#pragma unroll
-            for (int i = 0; i < NT; ++i)
-#pragma unroll
-                for (int ot = 0; ot < 4; ++ot) h2[i][ot] = mfma16(wh[ot], bl[i][s], h2[i][ot]);
-#pragma unroll
-            for (int i = 0; i < NT; ++i)
-#pragma unroll
-                for (int ot = 0; ot < 4; ++ot) h2[i][ot] = mfma16(wl[ot], bh[i][s], h2[i][ot]);
-        }
-#pragma unroll
-        for (int i = 0; i < NT; ++i)
-#pragma unroll
-            for (int ot = 0; ot < 4; ++ot) {
-                h2[i][ot] = relu4(h2[i][ot]);
+            for (int i = 0; i < NT; ++i) {
+                h2[i][ot] = relu4(mfma16(w1, c1[i], mfma16(w0, c0[i], bias)));
 #pragma unroll
                 for (int r = 0; r < 4; ++r) h2[i][ot][r] += h1[i][ot][r];
             }
-    }
-    reload_fence();
-    {
-        half8 b0[NT], b1[NT];
+        }
 #pragma unroll
         for (int i = 0; i < NT; ++i) {
             b0[i] = chain_f16(h2[i], 0);
             b1[i] = chain_f16(h2[i], 1);
         }
+    }
+    reload_fence();
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            floatx4 f[NT][2];
+    for (int s = 0; s < 8; ++s) {
+        floatx4 f[NT][2];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int ot = 2 * s + j;
-                const floatx4 bias = *reinterpret_cast<const floatx4 *>(&L.be3[ot * 16 + 4 * gq]);
-                const half8 w0 = L.e3[(ot * 2 + 0) * 64 + lane], w1 = L.e3[(ot * 2 + 1) * 64 + lane];
+        for (int j = 0; j < 2; ++j) {
+            const int ot = 2 * s + j;
+            const floatx4 bias = *reinterpret_cast<const floatx4 *>(&L.be3[ot * 16 + 4 * gq]);
+            const half8 w0 = L.e3[(ot * 2 + 0) * 64 + lane], w1 = L.e3[(ot * 2 + 1) * 64 + lane];
 #pragma unroll
-                for (int i = 0; i < NT; ++i) f[i][j] = mfma16(w1, b1[i], mfma16(w0, b0[i], bias));
-            }
+            for (int i = 0; i < NT; ++i) f[i][j] = mfma16(w1, b1[i], mfma16(w0, b0[i], bias));
+        }
 #pragma unroll
-            for (int i = 0; i < NT; ++i) {
-                uint4t v;
-                v[0] = pack_relu(f[i][0][0], f[i][0][1]);
-                v[1] = pack_relu(f[i][0][2], f[i][0][3]);
-                v[2] = pack_relu(f[i][1][0], f[i][1][1]);
-                v[3] = pack_relu(f[i][1][2], f[i][1][3]);
-                fb[i][s] = __builtin_bit_cast(half8, v);
-            }
+        for (int i = 0; i < NT; ++i) {
+            uint4t v;
+            v[0] = pack_relu(f[i][0][0], f[i][0][1]);
+            v[1] = pack_relu(f[i][0][2], f[i][0][3]);
+            v[2] = pack_relu(f[i][1][0], f[i][1][1]);
+            v[3] = pack_relu(f[i][1][2], f[i][1][3]);
+            fb[i][s] = __builtin_bit_cast(half8, v);
         }
     }
     reload_fence();
-    floatx4 t[NT][8];
-#pragma unroll
-    for (int ot = 0; ot < 8; ++ot) {
-        const floatx4 bias = *reinterpret_cast<const floatx4 *>(&L.ba1[ot * 16 + 4 * gq]);
-#pragma unroll
-        for (int i = 0; i < NT; ++i) t[i][ot] = bias;
-    }
-#pragma unroll
-    for (int s = 0; s < 8; ++s)
-#pragma unroll
-        for (int ot = 0; ot < 8; ++ot) {
-            const half8 w = L.a1[(ot * 8 + s) * 64 + lane];
-#pragma unroll
-            for (int i = 0; i < NT; ++i) t[i][ot] = mfma16(w, fb[i][s], t[i][ot]);
-        }
     // a2 . tanh(z) = sum(a2) - 2 a2 . 1 / (1 + e^(2 z)); the constant sum(a2)
     // (like a0) cancels in the softmax
 #pragma unroll
     for (int i = 0; i < NT; ++i) sc[i] = 0.0f;
 #pragma unroll
     for (int ot = 0; ot < 8; ++ot) {
+        const floatx4 bias = *reinterpret_cast<const floatx4 *>(&L.ba1[ot * 16 + 4 * gq]);
+        floatx4 t[NT];
+#pragma unroll
+        for (int i = 0; i < NT; ++i) t[i] = bias;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const half8 w = L.a1[(ot * 8 + s) * 64 + lane];
+#pragma unroll
+            for (int i = 0; i < NT; ++i) t[i] = mfma16(w, fb[i][s], t[i]);
+        }
         const floatx4 c = *reinterpret_cast<const floatx4 *>(&L.wa2[ot * 16 + 4 * gq]);
 #pragma unroll
         for (int i = 0; i < NT; ++i)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                sc[i] += c[r] * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(t[i][ot][r]));
+                sc[i] += c[r] * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(t[i][r]));
     }
 #pragma unroll
     for (int i = 0; i < NT; ++i) {
