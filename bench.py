@@ -34,6 +34,8 @@ MFMA_PASSES = 3                # split-FP16 products per FP32-equivalent product
 # node (the per-node half of W4, 64 -> 64, and W5, 64 -> 3; the g' half of W4
 # is one vector per item), global MLP per item (W3 and the g' half of W4)
 ENC_MAC, DEC_MAC, GLOBAL_MAC = 9 * 64 + 64 * 64, 64 * 64 + 64 * 3, 2 * 64 * 64
+# real-sensor regressor: multiply-adds per node (E1, E2, E3, A1) and per item (head)
+REG_NODE_MAC, REG_HEAD_MAC = 6 * 64 + 64 * 64 + 64 * 256 + 256 * 128, 256 * 128 + 128 * 8
 PHI_SIZE = 17411
 # VALU issue: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz = 39.3e12 lane slots/s
 # (78.6 TFLOP/s of unpacked FP32 FMA; packed FP32 is not used); exp2 and sqrt
@@ -80,6 +82,9 @@ def parse():
     ap.add_argument("--no-articulated", action="store_true",
                     help="skip the articulated hand with self-contact and the contact reward (4096 envs)")
     ap.add_argument("--articulated-steps", type=int, default=10)
+    ap.add_argument("--no-regressor", action="store_true",
+                    help="skip the real-sensor regressor on the step's displacements (etac_regress)")
+    ap.add_argument("--regressor-steps", type=int, default=10)
     return ap.parse_args()
 
 
@@ -311,14 +316,22 @@ def algorithmic_work(kernel, counts, E, N, K, O, mode):
     return dict(mfma_flop=bwd_flop if net else 0.0, pairs=0.0, hbm_bytes=12.0 * counts["passive"])
 
 
-def source_digest():
-    """Digest of the sources the step's kernels are built from (the mesh-object
-    contact file does not enter them)."""
+REGRESSOR_SOURCES = ("etac_regress.hip", "etac_device.h", "etac_internal.h")
+
+
+def source_digest(kernel=None):
+    """Digest of the sources a kernel is built from: the real-sensor regressor's
+    file and its headers for k_regress, every other file of the step for the
+    step's kernels (the mesh-object contact and the regressor do not enter
+    them)."""
     import hashlib
     h = hashlib.sha256()
     src = os.path.join(ROOT, "paper_2604_20295_amd", "csrc")
     for f in sorted(os.listdir(src)):
-        if f.endswith((".hip", ".h", ".cpp")) and f != "etac_mesh.hip":
+        if not f.endswith((".hip", ".h", ".cpp")) or f == "etac_mesh.hip":
+            continue
+        use = f in REGRESSOR_SOURCES if kernel == "k_regress" else f != "etac_regress.hip"
+        if use:
             h.update(open(os.path.join(src, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -335,7 +348,7 @@ def measured_traffic(kernel, workload):
         if ":" in ln and not ln.startswith("#"):
             a, b = ln.split(":", 1)
             kv[a.strip()] = b.strip()
-    if kv.get("source_digest") != source_digest():
+    if kv.get("source_digest") != source_digest(kernel):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -518,6 +531,58 @@ def articulated(args, mode):
             "fwd": {"ms_per_step": fwd_ms, "node_updates_per_s": nodes / (fwd_ms * 1e-3)},
             "fwd_bwd": {"ms_per_step": step_ms, "node_updates_per_s": nodes / (step_ms * 1e-3)},
             "kernel_ms": kern, "decay_pairs": counts["pairs"], "steps": reps}
+
+
+def regressor(args, plan, mesh, u, na):
+    """The real-sensor regressor (eight taxels per patch) on the displacements
+    of the headline step: items in contact through the per-node layers, one
+    rest item per patch for the others.  k_regress time from the library's
+    timer; the whole call (with the head and the fill) bracketed by events."""
+    import torch
+    import scenes
+    from paper_2604_20295_amd import _native
+    dev = u.device
+    E, K = na.shape
+    reg = torch.from_numpy(scenes.draw_regressor(np.random.default_rng(21))).to(dev)
+    y = torch.empty((E, K, _native.ETAC_TAXELS), device=dev)
+    stream = torch.cuda.current_stream(dev)
+    for _ in range(2):
+        _native.etac_regress(plan, reg, u, na, y)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for _ in range(args.regressor_steps):
+        _native.etac_regress(plan, reg, u, na, y)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    n, ms = plan.kernel_time(_native.ETAC_TIMER_REGRESS)
+    plan.set_timing(False)
+    call_ms = ev[0].elapsed_time(ev[1]) / args.regressor_steps
+    k_ms = ms / n
+    sizes = np.diff(mesh.patch_offset).astype(np.float64)
+    live = na.cpu().numpy() > 0
+    nodes = float((live * sizes[None, :]).sum() + sizes.sum())
+    items = float(live.sum() + K)
+    tiles = float((live * np.ceil(sizes / 16)[None, :]).sum() + np.ceil(sizes / 16).sum())
+    flop = 2.0 * REG_NODE_MAC * nodes
+    achieved = flop / (k_ms * 1e-3) / 1e12
+    return {"what": "taxels [E][K][8] from the step's U: attention-pooled PointNet with a residual layer "
+                    "(per node 6-64-64(+res)-256, attention 256-128-1 with tanh, head 256-128-8)",
+            "precision": "E1 split-FP16 (FP32-level), E2/E3/A1 FP16 operands with FP32 accumulation, "
+                         "softmax, pooling and head FP32",
+            "items_in_contact": int(live.sum()), "rest_items": K, "nodes_processed": nodes,
+            "tiles_16_nodes": tiles, "call_ms": call_ms, "k_regress_ms": k_ms,
+            "nodes_per_s": nodes / (k_ms * 1e-3),
+            "taxel_items_per_s": E * K / (call_ms * 1e-3),
+            "roofline": {"bound": "mfma", "kernel": "k_regress", "achieved": round(achieved, 3),
+                         "peak": F16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(achieved / F16_MFMA_PEAK_TFLOPS, 5),
+                         "traffic": measured_traffic("k_regress", "hand"), "avg_ms": round(k_ms, 4),
+                         "work_per_launch": {"mfma_flop": flop, "flop_per_node": 2.0 * REG_NODE_MAC,
+                                             "head_flop": 2.0 * REG_HEAD_MAC * items,
+                                             "hbm_bytes": 12.0 * (nodes - sizes.sum()) + 1024.0 * items}},
+            "steps": args.regressor_steps}
 
 
 def cpu_baseline(mesh, scene, model, grad_u, budget):
@@ -766,6 +831,9 @@ def main():
         line["calibration"] = calibration(args, plan, mesh, scene, model, mode)
     if not args.no_mesh and args.workload == "hand":
         line["mesh_contact"] = mesh_contact(args, plan, mesh, model, mode)
+    if not args.no_regressor and args.workload == "hand":
+        fwd(None)
+        line["regressor"] = regressor(args, plan, mesh, u, na)
     plan.close()
     del saved, grad_u, u, cobj, uhat, uo
     torch.cuda.empty_cache()
