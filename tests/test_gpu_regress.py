@@ -197,3 +197,60 @@ def test_regress_validation():
     assert lib.etac_regress(plan.handle, p(reg), 2, p(u), p(na), None, None) == -1
     assert lib.etac_regress(None, p(reg), 2, p(u), p(na), p(y), None) == -1
     assert lib.etac_regress(plan.handle, None, 0, None, None, None, None) == 0
+
+
+def test_regress_graph_replay():
+    """The step and the regressor captured in one HIP graph replay
+    bit-identically to eager calls, with eager work between the replays and
+    after new poses are written into the captured buffers."""
+    from paper_2604_20295_amd import _native
+    from tests.gpu_util import DevModel, DevScene
+    torch, dev = torch_dev()
+    mesh, scene, model = scenes.config2(n_envs=32, env_seed=3)
+    E, O, N, K = 32, 3, mesh.n_nodes, mesh.n_patches
+    plan = make_plan(mesh, E, O)
+    ds, dm = DevScene(scene), DevModel(model)
+    sc, md = ds.struct(plan), dm.struct(plan)
+    reg = to_dev(_reg(19))
+    u = torch.empty((3, E, N), device=dev)
+    cobj = torch.empty((E, N), dtype=torch.int8, device=dev)
+    na = torch.empty((E, K), dtype=torch.int32, device=dev)
+    y = torch.empty((E, K, 8), device=dev)
+
+    def step():
+        _native.etac_step(plan, sc, md, u, cobj, na)
+        _native.etac_regress(plan, reg, u, na, y)
+
+    def snap():
+        torch.cuda.synchronize()
+        return y.cpu().numpy().copy()
+
+    step()
+    eager = snap()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for rep in range(3):
+        y.zero_()
+        g.replay()
+        assert np.array_equal(snap(), eager), rep
+        _ = (torch.randn(1000, device=dev) * 2).sum().item()   # eager work between replays
+    traj_rot, traj_trans = scenes.trajectory(scene, 2, seed=4)
+    ds.rot.copy_(to_dev(traj_rot[1]))
+    ds.trans.copy_(to_dev(traj_trans[1]))
+    g.replay()
+    got = snap()
+    step()
+    assert np.array_equal(got, snap())
+    # and the replayed taxels against the oracle on the oracle's own step at the new poses
+    s2 = scene.copy()
+    s2.rot, s2.trans = traj_rot[1], traj_trans[1]
+    ref = oracle.forward(mesh, s2, model)
+    yr = oracle.regress(mesh, _reg(19).astype(np.float64), ref["u"].astype(np.float32).astype(np.float64))
+    _check(got, yr, "graph replay at new poses")
