@@ -462,8 +462,9 @@ etac_status etac_hand_step_backward(etac_plan *plan, const etac_scene *scene, co
  * reg: packed FP32, ETAC_REG_SIZE floats: E1[64][6] e1[64] E2[64][64] e2[64]
  * E3[256][64] e3[256] A1[128][256] a1[128] a2[128] a0[4] (a0[0] used; the
  * softmax does not depend on it) D1[128][256] d1[128] D2[8][128] d2[8].
- * Arithmetic: E1 and E2 at FP32 level (split FP16 operands), E3 and A1 on FP16
- * operands with FP32 accumulation, softmax, pooling and head in FP32.
+ * Arithmetic: E1 at FP32 level (split FP16 operands); E2, E3 and A1 on FP16
+ * operands with FP32 accumulation, the pooled features as those FP16 values;
+ * softmax weights, pooling sums and the head in FP32.
  * ------------------------------------------------------------------------ */
 #define ETAC_REG_SIZE 88204
 #define ETAC_TAXELS 8
