@@ -104,6 +104,7 @@ def test_calls_reject_null_plan():
                                   None, None) == -1
     n, ms = C.c_int32(), C.c_double()
     assert lib.etac_plan_kernel_time(None, 0, C.byref(n), C.byref(ms)) == -1
+    assert lib.etac_regress(None, None, 0, None, None, None, None) == -1
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
@@ -139,3 +140,15 @@ def test_meshset_validation_without_gpu():
     assert create(v, flip, off) == -3                                         # inconsistent orientation
     deg = t.copy(); deg[0, 2] = deg[0, 1]
     assert create(v, deg, off) == -3                                          # repeated vertex
+
+
+def test_regressor_constants_match_the_layer_table():
+    """The C ABI's regressor sizes and the benchmark's flop accounting follow
+    the packed layer table the oracle and the input generator use."""
+    import bench
+    import scenes
+    sizes = {name: o * i for name, o, i in scenes.REG_LAYERS}
+    assert _native.ETAC_REG_SIZE == scenes.REG_SIZE == sum(sizes.values())
+    assert _native.ETAC_TAXELS == dict((n, o) for n, o, _ in scenes.REG_LAYERS)["d2"]
+    assert bench.REG_NODE_MAC == sizes["E1"] + sizes["E2"] + sizes["E3"] + sizes["A1"]
+    assert bench.REG_HEAD_MAC == sizes["D1"] + sizes["D2"]
