@@ -218,7 +218,7 @@ __device__ void stage_net_t(BwdLds &S, const float *phi) {
 // whose K = 32 runs over the tile's 16 nodes twice (hi and lo parts).
 // Every accumulator here sees only that one MFMA shape: chaining an
 // accumulator from the 16x16x32 shape into the 16x16x16 one gave wrong
-// gradients in this build, so the 16x16x16 shape is not used.
+// gradients with ROCm 7.2 hipcc for gfx950, so the 16x16x16 shape is not used.
 // ---------------------------------------------------------------------------
 typedef _Float16 half4 __attribute__((ext_vector_type(4)));
 
@@ -322,8 +322,8 @@ __device__ __forceinline__ void layer64(const half8 *wh, const half8 *wl, const 
 //   NT = 1: A operand h = [hi hi], l = [lo 0]; B operand h = [hi lo]; then
 //           A.h B.h = hi*hi + hi*lo and A.l B.h = lo*hi.
 // Every accumulator sees only the 16x16x32 MFMA shape: chaining an
-// accumulator from that shape into the 16x16x16 one gave wrong gradients in
-// this build, so the 16x16x16 shape is not used.
+// accumulator from that shape into the 16x16x16 one gave wrong gradients
+// with ROCm 7.2 hipcc for gfx950, so the 16x16x16 shape is not used.
 template <int NT, int NB, bool A_ROLE>
 struct WOp {
     static_assert(NT == 1 || NT == 2, "one or two tiles");
