@@ -930,8 +930,10 @@ __device__ double decay_adjoint_grid(const BwdParams &p, DecayStage &st, int e, 
                 float sx[A], sy[A], sz[A], q[A];
 #pragma unroll
                 for (int a = 0; a < A; ++a) sx[a] = sy[a] = sz[a] = q[a] = 0.0f;
-#pragma unroll 2
-                for (int i = i0; i < i1; ++i) {
+                // the run's bounds are wave-uniform (segments are whole waves): scalar loop control
+                const int ie = uniform(i1);
+#pragma unroll 4
+                for (int i = uniform(i0); i < ie; ++i) {
                     const float4 pa = st.a[i];
                     const float2 pb = st.b[i];
 #pragma unroll

@@ -347,7 +347,10 @@ __device__ __forceinline__ void decay_range(const StepLds &S, const float4 *bb, 
         float sx[P], sy[P], sz[P];
 #pragma unroll
         for (int a = 0; a < P; ++a) sx[a] = sy[a] = sz[a] = 0.0f;
-        for (int j = j0; j < j1; ++j) {
+        // the run's bounds are wave-uniform (segments are whole waves): scalar loop control
+        const int je = uniform(j1);
+#pragma unroll 4
+        for (int j = uniform(j0); j < je; ++j) {
             const float4 pa = S.act_a[j];
             const float2 pb = S.act_b[j];
 #pragma unroll
