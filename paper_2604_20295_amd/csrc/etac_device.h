@@ -286,6 +286,9 @@ __device__ __forceinline__ float wave_max(float v) {
 // below FP32 rounding of the sums themselves.
 // ---------------------------------------------------------------------------
 constexpr double kCutLog2 = 50.0;
+// The cutoff in units of the decay's exponent (positions scaled by
+// |alpha| log2(e)): kCutLog2^2, rounded up.
+constexpr float kCut2Scaled = (float)(kCutLog2 * kCutLog2 * (1.0 + 1e-6));
 
 // D^2 for the item's alpha, rounded up (no cutoff when alpha <= 0).
 __device__ __forceinline__ float cutoff_d2(float alpha) {

@@ -308,28 +308,32 @@ __device__ void residual_item(const StepParams &p, StepLds &S, int item, int k, 
     __syncthreads();
 }
 
-// Stage active nodes [c0, c0 + cnt) of the item into LDS.
+// Stage active nodes [c0, c0 + cnt) of the item into LDS, positions times
+// sc (|alpha| log2(e): distances then come out in units of the decay's
+// exponent, see decay_range).
 __device__ __forceinline__ void stage_active(const StepParams &p, StepLds &S, int base, const int *alist,
-                                             const float *uhn, int c0, int cnt) {
+                                             const float *uhn, int c0, int cnt, float sc) {
     const MeshDev &M = p.mesh;
     const int N = M.N, n_max = p.scr.n_max;
     for (int t = threadIdx.x; t < cnt; t += kWG) {
         const int j = alist[c0 + t];
         const int gj = base + j;
-        S.act_a[t] = make_float4(M.pos[gj], M.pos[N + gj], M.pos[2 * N + gj], uhn[j]);
+        S.act_a[t] = make_float4(M.pos[gj] * sc, M.pos[N + gj] * sc, M.pos[2 * N + gj] * sc, uhn[j]);
         S.act_b[t] = make_float2(uhn[n_max + j], uhn[2 * n_max + j]);
     }
 }
 
 // Eq. 1 over staged active nodes [lo, hi) for P passive nodes per thread.
+// Positions come scaled by |alpha| log2(e), so a pair's scaled distance d
+// gives its weight exp(-alpha |p_j - p_i|) as 2^-d (2^d for alpha < 0: GROW).
 // FP32 terms are summed in blocks of 32 and the block sums are accumulated
 // in FP64.
 // Runs of 32 staged actives that no valid passive node of the wave can reach
 // within the cutoff are skipped (a run overlaps at most two boxes); cut2 < 0
 // turns the cutoff off.
-template <int P>
+template <int P, bool GROW>
 __device__ __forceinline__ void decay_range(const StepLds &S, const float4 *bb, float cut2, int lo, int hi,
-                                            float nbeta, const bool (&v)[P], const float (&px)[P],
+                                            const bool (&v)[P], const float (&px)[P],
                                             const float (&py)[P], const float (&pz)[P], double (&acc)[P][3]) {
     for (int j0 = lo; j0 < hi; j0 += 32) {
         const int j1 = min(hi, j0 + 32);
@@ -357,7 +361,7 @@ __device__ __forceinline__ void decay_range(const StepLds &S, const float4 *bb, 
             for (int a = 0; a < P; ++a) {
                 const float dx = pa.x - px[a], dy = pa.y - py[a], dz = pa.z - pz[a];
                 const float d = __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
-                const float w = __builtin_amdgcn_exp2f(nbeta * d);
+                const float w = __builtin_amdgcn_exp2f(GROW ? d : -d);
                 sx[a] += w * pa.w; sy[a] += w * pb.x; sz[a] += w * pb.y;
             }
         }
@@ -374,7 +378,7 @@ __device__ __forceinline__ void decay_range(const StepLds &S, const float4 *bb, 
 template <int SLOTS, int P>
 __device__ void decay_item(const StepParams &p, StepLds &S, int base, int m, int np, const int *alist,
                            const int *plist, const float *uhn, const float *resid, bool use_dec, bool use_res,
-                           float nbeta, float cut2, size_t row) {
+                           float sc, bool grow, float cut2, size_t row) {
     const MeshDev &M = p.mesh;
     const int N = M.N, n_max = p.scr.n_max;
     const size_t EN = (size_t)p.E * N;
@@ -393,25 +397,27 @@ __device__ void decay_item(const StepParams &p, StepLds &S, int base, int m, int
             v[a] = t < np;
             ii[a] = v[a] ? plist[t] : 0;
             const int g = base + ii[a];
-            px[a] = M.pos[g]; py[a] = M.pos[N + g]; pz[a] = M.pos[2 * N + g];
+            px[a] = M.pos[g] * sc; py[a] = M.pos[N + g] * sc; pz[a] = M.pos[2 * N + g] * sc;
             acc[a][0] = acc[a][1] = acc[a][2] = 0.0;
         }
         if (use_dec) {
             if (one_chunk) {
                 const int per = (m + nseg - 1) / nseg, lo = seg * per;
-                decay_range<P>(S, bb, cut2, lo, min(m, lo + per), nbeta, v, px, py, pz, acc);
+                if (grow) decay_range<P, true>(S, bb, cut2, lo, min(m, lo + per), v, px, py, pz, acc);
+                else decay_range<P, false>(S, bb, cut2, lo, min(m, lo + per), v, px, py, pz, acc);
             } else {
                 for (int c0 = 0; c0 < m; c0 += kChunk) {
                     const int cnt = min(kChunk, m - c0);
                     __syncthreads();
-                    stage_active(p, S, base, alist, uhn, c0, cnt);
+                    stage_active(p, S, base, alist, uhn, c0, cnt, sc);
                     __syncthreads();
                     if (cut2 >= 0.0f) {
                         block_boxes(S.act_a, cnt, reinterpret_cast<float4 *>(&S.net.part[0][0]));
                         __syncthreads();
                     }
                     const int per = (cnt + nseg - 1) / nseg, lo = seg * per;
-                    decay_range<P>(S, bb, cut2, lo, min(cnt, lo + per), nbeta, v, px, py, pz, acc);
+                    if (grow) decay_range<P, true>(S, bb, cut2, lo, min(cnt, lo + per), v, px, py, pz, acc);
+                    else decay_range<P, false>(S, bb, cut2, lo, min(cnt, lo + per), v, px, py, pz, acc);
                 }
             }
             if (nseg > 1) {
@@ -493,12 +499,14 @@ __device__ void process_item(const StepParams &p, StepLds &S, int e, int k, unsi
     const bool use_res = mode != ETAC_DECAY_ONLY, use_dec = mode != ETAC_RESIDUAL_ONLY;
     const int np = n - m;
     if (use_res) residual_item(p, S, e * M.K + k, k, base, n, uhn, plist, np, resid, umax);
-    // exp(-alpha d) = exp2(-alpha log2(e) d)
-    const float nbeta = (float)(-(double)p.model.alpha[k] * 1.4426950408889634);
-    float cut2 = cutoff_d2(p.model.alpha[k]);
-    if (!cutoff_useful(M, k, cut2)) cut2 = -1.0f;     // off: no boxes, no tests
+    // exp(-alpha d) = 2^-(alpha log2(e) d): positions are scaled by
+    // sc = |alpha| log2(e), the cutoff D by the same factor (sc D = kCutLog2)
+    const float alpha = p.model.alpha[k];
+    const float sc = (float)(fabs((double)alpha) * 1.4426950408889634);
+    const bool grow = alpha < 0.0f;
+    const float cut2 = cutoff_useful(M, k, cutoff_d2(alpha)) ? kCut2Scaled : -1.0f;   // off: no boxes, no tests
     if (use_dec && m <= kChunk) {
-        stage_active(p, S, base, alist, uhn, 0, m);
+        stage_active(p, S, base, alist, uhn, 0, m, sc);
         __syncthreads();
         if (cut2 >= 0.0f) {
             block_boxes(S.act_a, m, reinterpret_cast<float4 *>(&S.net.part[0][0]));
@@ -508,12 +516,12 @@ __device__ void process_item(const StepParams &p, StepLds &S, int e, int k, unsi
     // with the decay off (residual only) every shape does the same work
     const int shape = use_dec ? uniform(decay_grid_shape(np, m)) : 5;
     switch (shape) {
-        case 0: decay_item<64, 1>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, nbeta, cut2, row); break;
-        case 1: decay_item<128, 1>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, nbeta, cut2, row); break;
-        case 2: decay_item<256, 1>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, nbeta, cut2, row); break;
-        case 3: decay_item<64, 2>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, nbeta, cut2, row); break;
-        case 4: decay_item<128, 2>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, nbeta, cut2, row); break;
-        default: decay_item<256, 2>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, nbeta, cut2, row); break;
+        case 0: decay_item<64, 1>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, sc, grow, cut2, row); break;
+        case 1: decay_item<128, 1>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, sc, grow, cut2, row); break;
+        case 2: decay_item<256, 1>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, sc, grow, cut2, row); break;
+        case 3: decay_item<64, 2>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, sc, grow, cut2, row); break;
+        case 4: decay_item<128, 2>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, sc, grow, cut2, row); break;
+        default: decay_item<256, 2>(p, S, base, m, np, alist, plist, uhn, resid, use_dec, use_res, sc, grow, cut2, row); break;
     }
     __syncthreads();
 }
