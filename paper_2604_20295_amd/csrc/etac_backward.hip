@@ -1360,23 +1360,41 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
     // (d) max-pool routing: wave w takes channels 16 w .. 16 w + 15
     routing_tile(p, S, G, n, rin);
     __syncthreads();
-    // Routed dL/du_hat of active arg-max nodes: lane c of wave 0 owns channel
-    // c's node if c is the lowest channel routed there; the owner sums the
-    // node's channels in channel order and updates gh once.
-    if (threadIdx.x < 64) {
-        const int c = threadIdx.x;
+    // Routed dL/du_hat of active arg-max nodes: channel c owns its node if c
+    // is the lowest channel routed there; the owner adds the node's channels
+    // (c and the higher ones routed there) to gh once.  Wave w scans channels
+    // 16 w .. 16 w + 15 for every c (lane c); wave 0 adds the four partial
+    // sums in wave order.  The per-wave transpose buffers are free here.
+    {
+        const int c = lane;
         const int ln = S.argmax[c];
         const float x0 = S.dxs[c][0], x1 = S.dxs[c][1], x2 = S.dxs[c][2];
-        bool owner = ln < n;
+        bool lower = false;
         float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
-        for (int c2 = 0; c2 < 64; ++c2) {   // channel c2's node and values, read from its lane
+        const int cb = uniform(16 * wave);
+#pragma unroll 4
+        for (int c2 = cb; c2 < cb + 16; ++c2) {   // channel c2's node and values, read from its lane
             const int l2 = __builtin_amdgcn_readlane(ln, c2);
             const float y0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x0), c2));
             const float y1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x1), c2));
             const float y2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x2), c2));
             const bool same = l2 == ln;
-            owner = owner && !(same && c2 < c);
+            lower = lower || (same && c2 < c);
             if (same && c2 >= c) { s0 += y0; s1 += y1; s2 += y2; }
+        }
+        *reinterpret_cast<floatx4 *>(reinterpret_cast<float *>(&S.tr[wave][0]) + 4 * c) =
+            floatx4{s0, s1, s2, lower ? 1.0f : 0.0f};
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int c = threadIdx.x;
+        const int ln = S.argmax[c];
+        bool owner = ln < n;
+        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+        for (int w = 0; w < kWaves; ++w) {
+            const floatx4 q = *reinterpret_cast<const floatx4 *>(reinterpret_cast<const float *>(&S.tr[w][0]) + 4 * c);
+            s0 += q[0]; s1 += q[1]; s2 += q[2];
+            owner = owner && q[3] == 0.0f;
         }
         if (owner && wobj[ln] >= 0) {
             gh[ln] += s0;
