@@ -1021,32 +1021,60 @@ __device__ __forceinline__ void decoder_tile(const NetLds &L, const floatx4 f[4]
     }
 }
 
+// The global MLP's weights this thread uses (row tid & 63, input features
+// 16 (tid >> 6) .. + 15 of W3 and of W4[:, 64:], and the row's biases): the
+// persistent forward loads them once and keeps them in registers across its
+// items instead of reading them for every item.
+struct GmlpW {
+    float w3[16], w4[16], b3, b4;
+};
+
+__device__ __forceinline__ GmlpW load_gmlp(const float *phi) {
+    const int tid = threadIdx.x, o = tid & 63, w = tid >> 6;
+    GmlpW g;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        g.w3[c] = phi[kW3 + o * 64 + 16 * w + c];
+        g.w4[c] = phi[kW4 + o * 128 + 64 + 16 * w + c];
+    }
+    g.b3 = phi[kB3 + o];
+    g.b4 = phi[kB4 + o];
+    return g;
+}
+
 // Global MLP of one item from the (unscaled) pooled feature in L.g:
 // g' = relu(W3 g + b3) and c4 = W4[:, 64:] g' + b4, stored at h4's scale
 // 2^a4.  Whole workgroup; each wave sums 16 input features and the four
 // partials are added in wave order.
-__device__ void global_mlp(NetLds &L, const float *phi, const ItemScale &sc) {
+__device__ void global_mlp(NetLds &L, const GmlpW &gw, const ItemScale &sc) {
     const int tid = threadIdx.x, o = tid & 63, w = tid >> 6;
     float acc = 0.0f;
-    for (int c = 16 * w; c < 16 * w + 16; ++c) acc += phi[kW3 + o * 64 + c] * L.g[c];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) acc += gw.w3[c] * L.g[16 * w + c];
     L.part[w][o] = acc;
     __syncthreads();
     if (tid < 64) {
-        float s = phi[kB3 + o];
+        float s = gw.b3;
         for (int q = 0; q < kWaves; ++q) s += L.part[q][o];
         L.gp[o] = fmaxf(s, 0.0f);
     }
     __syncthreads();
     acc = 0.0f;
-    for (int c = 16 * w; c < 16 * w + 16; ++c) acc += phi[kW4 + o * 128 + 64 + c] * L.gp[c];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) acc += gw.w4[c] * L.gp[16 * w + c];
     L.part[w][o] = acc;
     __syncthreads();
     if (tid < 64) {
-        float s = phi[kB4 + o];
+        float s = gw.b4;
         for (int q = 0; q < kWaves; ++q) s += L.part[q][o];
         L.c4[o] = s * pow2(sc.a4);
     }
     __syncthreads();
+}
+
+// The same, its weights read for this item.
+__device__ __forceinline__ void global_mlp(NetLds &L, const float *phi, const ItemScale &sc) {
+    global_mlp(L, load_gmlp(phi), sc);
 }
 
 }  // namespace etac

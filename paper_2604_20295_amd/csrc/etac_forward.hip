@@ -195,8 +195,8 @@ __device__ void zero_fill_batch(const StepParams &p, const ItemBatch &B, int b0)
 // The encoder is recomputed in the decoder pass instead of keeping n x 64
 // features.  umax: the largest |u_hat| component of the item's nodes (with
 // the patch's geometry it bounds the network inputs: the range scaling).
-__device__ void residual_item(const StepParams &p, StepLds &S, int item, int k, int base, int n, const float *uhn,
-                              const int *plist, int np, float *resid, float umax) {
+__device__ void residual_item(const StepParams &p, StepLds &S, const GmlpW &gw, int item, int k, int base, int n,
+                              const float *uhn, const int *plist, int np, float *resid, float umax) {
     NetLds &L = S.net;
     const int lane = lane_id(), wave = threadIdx.x >> 6, gq = lane >> 4;
     const int n_max = p.scr.n_max;
@@ -285,7 +285,7 @@ __device__ void residual_item(const StepParams &p, StepLds &S, int item, int k, 
         }
     }
     __syncthreads();
-    global_mlp(L, p.model.phi, sc);
+    global_mlp(L, gw, sc);
     const float r_mul = pow2(-sc.a4);
     for (int c0 = 0; c0 < np; c0 += kStage) {
         const int cnt = min(kStage, np - c0);
@@ -466,7 +466,7 @@ __device__ __forceinline__ int decay_grid_shape(int np, int m) {
 // One item with at least one candidate object (cand: objects that may reach
 // the patch; all bits set when contact results are given).
 template <bool FROM_INPUT>
-__device__ void process_item(const StepParams &p, StepLds &S, int e, int k, unsigned cand, float *uhn,
+__device__ void process_item(const StepParams &p, StepLds &S, const GmlpW &gw, int e, int k, unsigned cand, float *uhn,
                              float *resid, int *alist, int *plist) {
     const MeshDev &M = p.mesh;
     const int N = M.N, n_max = p.scr.n_max;
@@ -498,7 +498,7 @@ __device__ void process_item(const StepParams &p, StepLds &S, int e, int k, unsi
     }
     const bool use_res = mode != ETAC_DECAY_ONLY, use_dec = mode != ETAC_RESIDUAL_ONLY;
     const int np = n - m;
-    if (use_res) residual_item(p, S, e * M.K + k, k, base, n, uhn, plist, np, resid, umax);
+    if (use_res) residual_item(p, S, gw, e * M.K + k, k, base, n, uhn, plist, np, resid, umax);
     // exp(-alpha d) = 2^-(alpha log2(e) d): positions are scaled by
     // sc = |alpha| log2(e), the cutoff D by the same factor (sc D = kCutLog2)
     const float alpha = p.model.alpha[k];
@@ -535,8 +535,10 @@ __global__ __launch_bounds__(kWG) void k_step(StepParams p) {
     float *resid = p.scr.resid + (size_t)wg * 3 * n_max;
     int *alist = p.scr.alist + (size_t)wg * n_max;
     int *plist = p.scr.plist + (size_t)wg * n_max;
+    GmlpW gw{};   // the global MLP's weights, held in registers across the items
     if (p.model.mode != ETAC_DECAY_ONLY) {
         stage_net(S.net, p.model.phi);
+        gw = load_gmlp(p.model.phi);
         __syncthreads();
     }
     for (;;) {
@@ -551,7 +553,7 @@ __global__ __launch_bounds__(kWG) void k_step(StepParams p) {
             queue_item(p.mesh, p.E, item, e, k);
             const unsigned cand = FROM_INPUT ? 0xffffffffu
                                              : item_cand(p.scene, e, k, uniform((unsigned)S.batch.cand[q]));
-            process_item<FROM_INPUT>(p, S, e, k, cand, uhn, resid, alist, plist);
+            process_item<FROM_INPUT>(p, S, gw, e, k, cand, uhn, resid, alist, plist);
         }
     }
     retire(p.scr.counter);
