@@ -168,7 +168,7 @@ struct BwdLds {
     float dxs[64][3];             // dL/du_hat of the routed arg-max node of each channel
     double dred[kWaves][12];
     int wcnt[kGivenChunks][2][kWaves];   // compaction counts, one set per chunk of a pass
-    int wmx[2][kWaves];           // per-wave largest |u_hat| component (float bits; row 1 unused)
+    int wmx[2][kWaves];           // per-wave largest |u_hat| component (float bits), objects present (bits)
     BwdScale bsc;                 // the current item's adjoint scales
     ItemBatch batch;
 };
@@ -1042,9 +1042,11 @@ __device__ void wg_sum12(double (&dred)[kWaves][12], double v[12]) {
 
 // Pose partials of one item: for every object, the sum over its active
 // nodes.  Objects that win no active node of the item get exact zeros
-// without a reduction (usually one object reaches a patch).
+// without a reduction (usually one object reaches a patch).  known: the
+// caller's mask of the objects present among the active nodes (bit o for
+// object o), or 0 to find it here.
 __device__ void contact_adjoint_item(const BwdParams &p, BwdLds &S, int e, int item, int base, int m,
-                                     const int *alist, const int8_t *wobj, const float *gh) {
+                                     const int *alist, const int8_t *wobj, const float *gh, unsigned known) {
     const MeshDev &M = p.mesh;
     const int N = M.N, n_max = p.scr.n_max, O = p.scene.O;
     // the item's scene row: its env, or the item itself for a row per item
@@ -1052,16 +1054,17 @@ __device__ void contact_adjoint_item(const BwdParams &p, BwdLds &S, int e, int i
     const int no = min(p.scene.n_obj[row], O);
     float *out = p.bwd.pose_part + (size_t)item * O * 12;
     // objects present among the active nodes (an OR, independent of order)
-    unsigned mask = 0;
-    for (int q = threadIdx.x; q < m; q += kWG) mask |= 1u << wobj[alist[q]];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) mask |= (unsigned)__shfl_xor((int)mask, off);
-    S.ired[threadIdx.x >> 6][lane_id()] = (int)mask;     // identical in every lane of the wave
-    __syncthreads();
-    unsigned present = 0;
-    for (int w = 0; w < kWaves; ++w) present |= (unsigned)S.ired[w][0];
-    present = uniform(present);
-    __syncthreads();
+    unsigned present = known;
+    if (present == 0) {
+        unsigned mask = 0;
+        for (int q = threadIdx.x; q < m; q += kWG) mask |= 1u << wobj[alist[q]];
+        mask = wave_or(mask);
+        S.ired[threadIdx.x >> 6][lane_id()] = (int)mask;     // identical in every lane of the wave
+        __syncthreads();
+        for (int w = 0; w < kWaves; ++w) present |= (unsigned)S.ired[w][0];
+        present = uniform(present);
+        __syncthreads();
+    }
     for (int o = 0; o < O; ++o) {
         if (!((present >> o) & 1u) || o >= no) {
             if (threadIdx.x < 64 && lane_id() < 12) out[o * 12 + lane_id()] = 0.0f;
@@ -1654,15 +1657,20 @@ __global__ __launch_bounds__(256) void k_live_list(BwdParams p) {
 // contact_and_compact does with FROM_INPUT, but kGivenChunks chunks of kWG
 // nodes per pair of barriers: the loads are cheap and their latencies overlap.
 // Lists in ascending node order (chunk, then wave, then lane).  Returns m;
-// umax: the largest |u_hat| component over the item's nodes.
+// umax: the largest |u_hat| component over the item's nodes; present: the
+// objects that win an active node (bit o for object o).  dL/du_hat of the
+// active nodes is read from gsrc into gh in the same pass, so its loads
+// overlap those of u_hat.
 __device__ int compact_given(int E, int N, int n_max, const int8_t *cobj_in, const float *uhat_in,
-                             int (&wcnt)[kGivenChunks][2][kWaves], int (&wmx)[2][kWaves], int e, int base, int n,
-                             float *uhn, int *alist, int *plist, int8_t *wobj, float &umax) {
+                             const float *gsrc, int (&wcnt)[kGivenChunks][2][kWaves], int (&wmx)[2][kWaves], int e,
+                             int base, int n, float *uhn, float *gh, int *alist, int *plist, int8_t *wobj,
+                             float &umax, unsigned &present) {
     constexpr int G = kGivenChunks;
     const size_t EN = (size_t)E * N;
     const int wave = threadIdx.x >> 6;
     int run_a = 0, run_p = 0;
     int ubits = 0;   // bits of a non-negative float: integer order is float order
+    unsigned omask = 0;
     for (int g0 = 0; g0 < n; g0 += G * kWG) {
         bool act[G], pas[G];
 #pragma unroll
@@ -1678,7 +1686,12 @@ __device__ int compact_given(int E, int N, int n_max, const int8_t *cobj_in, con
                     u0 = uhat_in[en];
                     u1 = uhat_in[EN + en];
                     u2 = uhat_in[2 * EN + en];
+                    const float g0v = gsrc[en], g1v = gsrc[EN + en], g2v = gsrc[2 * EN + en];
+                    gh[i] = g0v;
+                    gh[n_max + i] = g1v;
+                    gh[2 * n_max + i] = g2v;
                     ubits = max(ubits, __float_as_int(fmaxf(fmaxf(fabsf(u0), fabsf(u1)), fabsf(u2))));
+                    omask |= 1u << (best & 31);
                 }
                 uhn[i] = u0;
                 uhn[n_max + i] = u1;
@@ -1689,6 +1702,7 @@ __device__ int compact_given(int E, int N, int n_max, const int8_t *cobj_in, con
             pas[c] = valid && best < 0;
         }
         wmx[0][wave] = wave_max_int(ubits);
+        wmx[1][wave] = (int)wave_or(omask);
         unsigned long long ba[G], bp[G];
 #pragma unroll
         for (int c = 0; c < G; ++c) {
@@ -1715,8 +1729,13 @@ __device__ int compact_given(int E, int N, int n_max, const int8_t *cobj_in, con
         }
         if (g0 + G * kWG >= n) {   // last pass: the wave maxima cover every node of the item
             int ub = 0;
-            for (int w = 0; w < kWaves; ++w) ub = max(ub, wmx[0][w]);
+            unsigned ob = 0;
+            for (int w = 0; w < kWaves; ++w) {
+                ub = max(ub, wmx[0][w]);
+                ob |= (unsigned)wmx[1][w];
+            }
             umax = __int_as_float(uniform(ub));
+            present = uniform(ob);
         }
         __syncthreads();
     }
@@ -1742,12 +1761,14 @@ __device__ void process_item_bwd(const BwdParams &p, BwdLds &S, int item, int e,
     int m;
     float umax = 0.0f;
     int touch;
+    unsigned present = 0;   // found by contact_adjoint_item for the contact adjoint
     if constexpr (KIND == BWD_CONTACT)
         m = contact_and_compact<false>(M, p.scene, p.E, n_max, nullptr, nullptr, nullptr,
                                        *reinterpret_cast<int (*)[3][kWaves]>(&S.wcnt[0][0][0]), e, k, base, n,
                                        cand, uhn, alist, plist, wobj, umax, touch);
     else
-        m = compact_given(p.E, N, n_max, cin, uin, S.wcnt, S.wmx, e, base, n, uhn, alist, plist, wobj, umax);
+        m = compact_given(p.E, N, n_max, cin, uin, p.bwd.gh_st, S.wcnt, S.wmx, e, base, n, uhn, gh, alist, plist,
+                          wobj, umax, present);
     if (m == 0) {
         // contact adjoint only: the other kinds never queue items without contact
         if (threadIdx.x < 64) p.bwd.item_flag[item] = 0;
@@ -1755,14 +1776,15 @@ __device__ void process_item_bwd(const BwdParams &p, BwdLds &S, int item, int e,
         __syncthreads();
         return;
     }
-    const float *g0 = KIND == BWD_CONTACT ? p.grad_uhat_in : p.bwd.gh_st;
-    for (int q = threadIdx.x; q < m; q += kWG) {
-        const int j = alist[q];
-        gh[j] = g0[row + j];
-        gh[n_max + j] = g0[EN + row + j];
-        gh[2 * n_max + j] = g0[2 * EN + row + j];
+    if constexpr (KIND == BWD_CONTACT) {   // the other kinds read dL/du_hat during compaction
+        for (int q = threadIdx.x; q < m; q += kWG) {
+            const int j = alist[q];
+            gh[j] = p.grad_uhat_in[row + j];
+            gh[n_max + j] = p.grad_uhat_in[EN + row + j];
+            gh[2 * n_max + j] = p.grad_uhat_in[2 * EN + row + j];
+        }
+        __syncthreads();
     }
-    __syncthreads();
     if (KIND != BWD_CONTACT && uses_residual(p))
         residual_adjoint(p, S, e, k, item, base, n, n - m, plist, uhn, wobj, gh, umax);
     if (threadIdx.x < 64) p.bwd.item_flag[item] = (KIND != BWD_CONTACT && uses_residual(p)) ? 1 : 0;
@@ -1775,7 +1797,7 @@ __device__ void process_item_bwd(const BwdParams &p, BwdLds &S, int item, int e,
             p.grad_uhat_out[2 * EN + row + i] = act ? gh[2 * n_max + i] : 0.0f;
         }
     } else {
-        contact_adjoint_item(p, S, e, item, base, m, alist, wobj, gh);
+        contact_adjoint_item(p, S, e, item, base, m, alist, wobj, gh, present);
     }
     __syncthreads();
 }

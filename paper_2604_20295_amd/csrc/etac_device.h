@@ -264,6 +264,11 @@ __device__ __forceinline__ unsigned lanes_below(unsigned long long mask) {
 }
 
 // Maximum over the wave, returned in every lane.
+__device__ __forceinline__ unsigned wave_or(unsigned v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v |= (unsigned)__shfl_xor((int)v, off);
+    return v;
+}
 __device__ __forceinline__ int wave_max_int(int v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off));
