@@ -1075,12 +1075,27 @@ __device__ void contact_adjoint_item(const BwdParams &p, BwdLds &S, int e, int i
         const size_t eo = row * O + o;
         const int ty = p.scene.type[eo];
         const float *sh = p.scene.shape + 4 * eo, *R = p.scene.rot + 9 * eo, *t = p.scene.trans + 3 * eo;
-        for (int q = threadIdx.x; q < m; q += kWG) {
-            const int j = alist[q];
-            if (wobj[j] != o) continue;
-            const int gj = base + j;
-            const double g[3] = {gh[j], gh[n_max + j], gh[2 * n_max + j]};
-            contact_adjoint_node(ty, sh, R, t, M.pos[gj], M.pos[N + gj], M.pos[2 * N + gj], g, acc);
+        // list positions q and q + kWG per pass: both nodes' loads are issued
+        // before either is used (the same nodes, in the same order, as one
+        // position per pass)
+        for (int q = threadIdx.x; q < m; q += 2 * kWG) {
+            const bool two = q + kWG < m;
+            const int j0 = alist[q];
+            const int j1 = two ? alist[q + kWG] : j0;
+            const bool h0 = wobj[j0] == o, h1 = two && wobj[j1] == o;
+            const int gj0 = base + j0, gj1 = base + j1;
+            const float g0[3] = {gh[j0], gh[n_max + j0], gh[2 * n_max + j0]};
+            const float g1[3] = {gh[j1], gh[n_max + j1], gh[2 * n_max + j1]};
+            const float x0[3] = {M.pos[gj0], M.pos[N + gj0], M.pos[2 * N + gj0]};
+            const float x1[3] = {M.pos[gj1], M.pos[N + gj1], M.pos[2 * N + gj1]};
+            if (h0) {
+                const double g[3] = {g0[0], g0[1], g0[2]};
+                contact_adjoint_node(ty, sh, R, t, x0[0], x0[1], x0[2], g, acc);
+            }
+            if (h1) {
+                const double g[3] = {g1[0], g1[1], g1[2]};
+                contact_adjoint_node(ty, sh, R, t, x1[0], x1[1], x1[2], g, acc);
+            }
         }
         wg_sum12(S.dred, acc);
         if (threadIdx.x < 12) out[o * 12 + threadIdx.x] = (float)acc[threadIdx.x];
@@ -1254,7 +1269,9 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
 
     // (a) max-pool with arg-max (lowest node on ties): from the forward's
     //     record, else an encoder pass over every node of the item
+    GmlpW gw;
     if (p.saved) {
+        gw = load_gmlp(phi);   // issued before the record's loads, used after the barrier
         if (threadIdx.x < 64) {
             const uint32_t *rec = p.saved + (size_t)item * kSavedWords;
             L.g[threadIdx.x] = __uint_as_float(rec[threadIdx.x]);
@@ -1266,8 +1283,9 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
         __syncthreads();
     } else {
         pool_argmax(p, S, k, base, n, uhn);
+        gw = load_gmlp(phi);
     }
-    global_mlp(L, phi, item_scale_lds(L));
+    global_mlp(L, gw, item_scale_lds(L));
     // gradient scales: dL/dU staged at 2^dre, dre from gmax (see BwdScale)
     if (threadIdx.x < 64) {   // wave 0, identical values; published by the stage barrier
         BwdScale bs;
