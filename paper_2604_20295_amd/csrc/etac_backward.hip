@@ -459,7 +459,9 @@ __device__ __forceinline__ void to_n_form(floatx4 *buf, const floatx4 t[4], floa
 
 // T-form layers over NT tiles; each weight fragment is read from LDS once
 // for all tiles.  Per tile and block the MFMA sequence is that of layer64:
-// per K step hi*hi, hi*lo, lo*hi.
+// per K step hi*hi, hi*lo, lo*hi.  A tile's MFMAs of a K step are issued
+// together, so the first tile's output is complete while the next tile's
+// MFMAs still run and its ReLU and split overlap them.
 template <int NT>
 __device__ __forceinline__ void layer1_tiles(const NetLds &L, const half8 (&xh)[NT], const half8 (&xl)[NT],
                                              floatx4 (&h1)[NT][4]) {
@@ -475,17 +477,14 @@ __device__ __forceinline__ void layer1_tiles(const NetLds &L, const half8 (&xh)[
         for (int u = 0; u < NT; ++u) h1[u][ob] = b;
     }
 #pragma unroll
-    for (int ob = 0; ob < 4; ++ob)
+    for (int u = 0; u < NT; ++u) {
 #pragma unroll
-        for (int u = 0; u < NT; ++u) h1[u][ob] = mfma16(wh[ob], xh[u], h1[u][ob]);
+        for (int ob = 0; ob < 4; ++ob) h1[u][ob] = mfma16(wh[ob], xh[u], h1[u][ob]);
 #pragma unroll
-    for (int ob = 0; ob < 4; ++ob)
+        for (int ob = 0; ob < 4; ++ob) h1[u][ob] = mfma16(wh[ob], xl[u], h1[u][ob]);
 #pragma unroll
-        for (int u = 0; u < NT; ++u) h1[u][ob] = mfma16(wh[ob], xl[u], h1[u][ob]);
-#pragma unroll
-    for (int ob = 0; ob < 4; ++ob)
-#pragma unroll
-        for (int u = 0; u < NT; ++u) h1[u][ob] = relu4(mfma16(wl[ob], xh[u], h1[u][ob]));
+        for (int ob = 0; ob < 4; ++ob) h1[u][ob] = relu4(mfma16(wl[ob], xh[u], h1[u][ob]));
+    }
 }
 
 // y[u] = W x[u] (+ bias), relu if RELU (T form in and out).
@@ -510,17 +509,14 @@ __device__ __forceinline__ void layer64_tiles(const half8 *wh, const half8 *wl, 
             l[ob] = wl[(ob * 2 + s) * 64 + lane];
         }
 #pragma unroll
-        for (int ob = 0; ob < 4; ++ob)
+        for (int u = 0; u < NT; ++u) {
 #pragma unroll
-            for (int u = 0; u < NT; ++u) y[u][ob] = mfma16(h[ob], xh[u][s], y[u][ob]);
+            for (int ob = 0; ob < 4; ++ob) y[u][ob] = mfma16(h[ob], xh[u][s], y[u][ob]);
 #pragma unroll
-        for (int ob = 0; ob < 4; ++ob)
+            for (int ob = 0; ob < 4; ++ob) y[u][ob] = mfma16(h[ob], xl[u][s], y[u][ob]);
 #pragma unroll
-            for (int u = 0; u < NT; ++u) y[u][ob] = mfma16(h[ob], xl[u][s], y[u][ob]);
-#pragma unroll
-        for (int ob = 0; ob < 4; ++ob)
-#pragma unroll
-            for (int u = 0; u < NT; ++u) y[u][ob] = mfma16(l[ob], xh[u][s], y[u][ob]);
+            for (int ob = 0; ob < 4; ++ob) y[u][ob] = mfma16(l[ob], xh[u][s], y[u][ob]);
+        }
     }
     if (RELU)
 #pragma unroll
@@ -548,17 +544,14 @@ __device__ __forceinline__ void layer64_tiles_n(const half8 *wh, const half8 *wl
             l[ob] = wl[(ob * 2 + s) * 64 + lane];
         }
 #pragma unroll
-        for (int ob = 0; ob < 4; ++ob)
+        for (int u = 0; u < NT; ++u) {
 #pragma unroll
-            for (int u = 0; u < NT; ++u) y[u][ob] = mfma16(xh[u][s], h[ob], y[u][ob]);
+            for (int ob = 0; ob < 4; ++ob) y[u][ob] = mfma16(xh[u][s], h[ob], y[u][ob]);
 #pragma unroll
-        for (int ob = 0; ob < 4; ++ob)
+            for (int ob = 0; ob < 4; ++ob) y[u][ob] = mfma16(xh[u][s], l[ob], y[u][ob]);
 #pragma unroll
-            for (int u = 0; u < NT; ++u) y[u][ob] = mfma16(xh[u][s], l[ob], y[u][ob]);
-#pragma unroll
-        for (int ob = 0; ob < 4; ++ob)
-#pragma unroll
-            for (int u = 0; u < NT; ++u) y[u][ob] = mfma16(xl[u][s], h[ob], y[u][ob]);
+            for (int ob = 0; ob < 4; ++ob) y[u][ob] = mfma16(xl[u][s], h[ob], y[u][ob]);
+        }
     }
 }
 
