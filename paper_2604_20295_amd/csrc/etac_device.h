@@ -933,7 +933,8 @@ __device__ __forceinline__ void encoder_tile(const NetLds &L, const half8 &xh, c
 }
 
 // Encoder of two independent 16-node tiles at once: the weight fragments are
-// read once and the two tiles' MFMA chains interleave.
+// read once for both.  Each tile's MFMAs of a K step are issued together, so
+// the first tile's ReLU and split overlap the second tile's MFMAs.
 __device__ __forceinline__ void encoder_tile2(const NetLds &L, const half8 (&xh)[2], const half8 (&xl)[2],
                                               floatx4 (&f)[2][4]) {
     reload_fence();
@@ -950,17 +951,14 @@ __device__ __forceinline__ void encoder_tile2(const NetLds &L, const half8 (&xh)
             h1[1][ot] = b;
         }
 #pragma unroll
-        for (int ot = 0; ot < 4; ++ot)
+        for (int u = 0; u < 2; ++u) {
 #pragma unroll
-            for (int u = 0; u < 2; ++u) h1[u][ot] = mfma16(wh[ot], xh[u], h1[u][ot]);
+            for (int ot = 0; ot < 4; ++ot) h1[u][ot] = mfma16(wh[ot], xh[u], h1[u][ot]);
 #pragma unroll
-        for (int ot = 0; ot < 4; ++ot)
+            for (int ot = 0; ot < 4; ++ot) h1[u][ot] = mfma16(wh[ot], xl[u], h1[u][ot]);
 #pragma unroll
-            for (int u = 0; u < 2; ++u) h1[u][ot] = mfma16(wh[ot], xl[u], h1[u][ot]);
-#pragma unroll
-        for (int ot = 0; ot < 4; ++ot)
-#pragma unroll
-            for (int u = 0; u < 2; ++u) h1[u][ot] = relu4(mfma16(wl[ot], xh[u], h1[u][ot]));
+            for (int ot = 0; ot < 4; ++ot) h1[u][ot] = relu4(mfma16(wl[ot], xh[u], h1[u][ot]));
+        }
     }
     half8 bh[2][2], bl[2][2];
 #pragma unroll
@@ -980,17 +978,14 @@ __device__ __forceinline__ void encoder_tile2(const NetLds &L, const half8 (&xh)
             l[ot] = L.w2l[(ot * 2 + s) * 64 + lane];
         }
 #pragma unroll
-        for (int ot = 0; ot < 4; ++ot)
+        for (int u = 0; u < 2; ++u) {
 #pragma unroll
-            for (int u = 0; u < 2; ++u) f[u][ot] = mfma16(h[ot], bh[u][s], f[u][ot]);
+            for (int ot = 0; ot < 4; ++ot) f[u][ot] = mfma16(h[ot], bh[u][s], f[u][ot]);
 #pragma unroll
-        for (int ot = 0; ot < 4; ++ot)
+            for (int ot = 0; ot < 4; ++ot) f[u][ot] = mfma16(h[ot], bl[u][s], f[u][ot]);
 #pragma unroll
-            for (int u = 0; u < 2; ++u) f[u][ot] = mfma16(h[ot], bl[u][s], f[u][ot]);
-#pragma unroll
-        for (int ot = 0; ot < 4; ++ot)
-#pragma unroll
-            for (int u = 0; u < 2; ++u) f[u][ot] = mfma16(l[ot], bh[u][s], f[u][ot]);
+            for (int ot = 0; ot < 4; ++ot) f[u][ot] = mfma16(l[ot], bh[u][s], f[u][ot]);
+        }
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u)
