@@ -1021,6 +1021,60 @@ __device__ __forceinline__ void decoder_tile(const NetLds &L, const floatx4 f[4]
     }
 }
 
+// Decoder of two independent tiles at once (each tile's results identical to
+// decoder_tile's): the W4 fragments are read once for both, and each tile's
+// MFMAs of a K step are issued together.
+__device__ __forceinline__ void decoder_tile2(const NetLds &L, const floatx4 (&f)[2][4], float r_mul,
+                                              float (&r_out)[2][3]) {
+    reload_fence();
+    const int lane = lane_id(), gq = lane >> 4;
+    half8 bh[2][2], bl[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) split_chain(f[u], bh[u], bl[u]);
+    floatx4 h4[2][4];
+#pragma unroll
+    for (int ot = 0; ot < 4; ++ot) {
+        const floatx4 b = *reinterpret_cast<const floatx4 *>(&L.c4[ot * 16 + 4 * gq]);
+        h4[0][ot] = b;
+        h4[1][ot] = b;
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        half8 h[4], l[4];
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot) {
+            h[ot] = L.w4h[(ot * 2 + s) * 64 + lane];
+            l[ot] = L.w4l[(ot * 2 + s) * 64 + lane];
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+#pragma unroll
+            for (int ot = 0; ot < 4; ++ot) h4[u][ot] = mfma16(h[ot], bh[u][s], h4[u][ot]);
+#pragma unroll
+            for (int ot = 0; ot < 4; ++ot) h4[u][ot] = mfma16(h[ot], bl[u][s], h4[u][ot]);
+#pragma unroll
+            for (int ot = 0; ot < 4; ++ot) h4[u][ot] = mfma16(l[ot], bh[u][s], h4[u][ot]);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+#pragma unroll
+        for (int ot = 0; ot < 4; ++ot) h4[u][ot] = relu4(h4[u][ot]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float s = 0.0f;
+#pragma unroll
+            for (int ot = 0; ot < 4; ++ot) {
+                const floatx4 w = *reinterpret_cast<const floatx4 *>(&L.w5[c * 64 + ot * 16 + 4 * gq]);
+                s += w[0] * h4[u][ot][0] + w[1] * h4[u][ot][1] + w[2] * h4[u][ot][2] + w[3] * h4[u][ot][3];
+            }
+            s += __shfl_xor(s, 16);
+            s += __shfl_xor(s, 32);
+            r_out[u][c] = s * r_mul + L.b5[c];
+        }
+    }
+}
+
 // The global MLP's weights this thread uses (row tid & 63, input features
 // 16 (tid >> 6) .. + 15 of W3 and of W4[:, 64:], and the row's biases): the
 // persistent forward loads them once and keeps them in registers across its

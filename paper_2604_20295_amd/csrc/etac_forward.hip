@@ -292,8 +292,29 @@ __device__ void residual_item(const StepParams &p, StepLds &S, const GmlpW &gw, 
         __syncthreads();
         stage_nodes(p.mesh, k, base, plist, c0, cnt, nullptr, 0, 0, sc.xmul, 0.0f, S.xs);   // passive: U_hat = 0
         __syncthreads();
+        // pairs of tiles (t, t + 4) per wave while every wave gets a pair,
+        // then single tiles (the same residuals either way)
         const int ptl = (cnt + 15) >> 4;
-        for (int t = wave; t < ptl; t += kWaves) {
+        int t0 = 0;
+        for (; ptl - t0 >= 2 * kWaves; t0 += 2 * kWaves) {
+            int lj[2];
+            bool valid[2];
+            half8 xh[2], xl[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                lj[u] = (t0 + u * kWaves + wave) * 16 + (lane & 15);
+                valid[u] = lj[u] < cnt;     // the chunk's last tile may be ragged
+                stage_x<true>(S.xs, lj[u], valid[u], xh[u], xl[u]);
+            }
+            floatx4 f[2][4];
+            encoder_tile2(L, xh, xl, f);
+            float r[2][3];
+            decoder_tile2(L, f, r_mul, r);
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (valid[u] && gq < 3) resid[gq * n_max + plist[c0 + lj[u]]] = r[u][gq];
+        }
+        for (int t = t0 + wave; t < ptl; t += kWaves) {
             const int lj = t * 16 + (lane & 15);
             const bool valid = lj < cnt;
             half8 xh, xl;
