@@ -1882,7 +1882,7 @@ hipError_t launch_bwd_net(const BwdParams &p, int kind, int grid, hipStream_t st
 // the items that wrote one (flag set) in ascending item order.  The block
 // compacts its segment's flags into an LDS list 1024 items at a time (wave
 // ballots, waves in order), then every thread sums its column over the list
-// with four items in flight.  Plain columns read one record word (record
+// with eight items in flight.  Plain columns read one record word (record
 // order, so a wave reads 256 contiguous bytes); rank-one columns multiply two.
 __global__ __launch_bounds__(256) void k_phi_segments(const float *part, const int *flag, int n_items,
                                                       double *seg) {
@@ -1922,32 +1922,27 @@ __global__ __launch_bounds__(256) void k_phi_segments(const float *part, const i
         if (live_col) {
             int q = 0;
             if (rank1) {
-                for (; q + 4 <= cnt; q += 4) {
-                    double v[4];
+                for (; q + 8 <= cnt; q += 8) {
+                    double v[8];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
+                    for (int u = 0; u < 8; ++u) {
                         const float *r = part + (size_t)list[q + u] * kRecWords;
                         v[u] = (double)r[sa] * (double)r[sb];
                     }
-                    acc += v[0];
-                    acc += v[1];
-                    acc += v[2];
-                    acc += v[3];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) acc += v[u];
                 }
                 for (; q < cnt; ++q) {
                     const float *r = part + (size_t)list[q] * kRecWords;
                     acc += (double)r[sa] * (double)r[sb];
                 }
             } else {
-                for (; q + 4 <= cnt; q += 4) {
-                    const float v0 = part[(size_t)list[q] * kRecWords + sa];
-                    const float v1 = part[(size_t)list[q + 1] * kRecWords + sa];
-                    const float v2 = part[(size_t)list[q + 2] * kRecWords + sa];
-                    const float v3 = part[(size_t)list[q + 3] * kRecWords + sa];
-                    acc += (double)v0;
-                    acc += (double)v1;
-                    acc += (double)v2;
-                    acc += (double)v3;
+                for (; q + 8 <= cnt; q += 8) {
+                    float v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) v[u] = part[(size_t)list[q + u] * kRecWords + sa];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) acc += (double)v[u];
                 }
                 for (; q < cnt; ++q) acc += (double)part[(size_t)list[q] * kRecWords + sa];
             }
