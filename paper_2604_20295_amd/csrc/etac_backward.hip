@@ -1103,29 +1103,36 @@ __device__ void contact_adjoint_item(const BwdParams &p, BwdLds &S, int e, int i
 // accumulator blocks in LDS (one 16-byte store per lane and block), then each
 // thread sums two (block, lane) entries over the waves in wave order and
 // stores them with one 16-byte store each.  Every register is named
-// statically, so the accumulators never leave registers.
+// statically, so the accumulators never leave registers.  Chunk 4 (dW1,
+// dW5) is summed straight from the waves' LDS accumulators, which are
+// complete and published by the barrier after the routing pass.
 template <int C>
 __device__ __forceinline__ void store_record_chunk(BwdLds &S, const WGrad &G, float *rec, float mul_lo,
                                                    float mul_hi) {
-    const int wave = threadIdx.x >> 6, lane = lane_id();
-    __syncthreads();    // previous users of the buffer are done
+    if constexpr (C < 4) {
+        const int wave = threadIdx.x >> 6, lane = lane_id();
+        __syncthreads();    // previous users of the buffer are done
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        floatx4 v;
-        if (C == 0) v = G.w4[j >> 2][j & 3];
-        else if (C == 1) v = G.w4[2 + (j >> 2)][j & 3];
-        else if (C == 2) v = G.w2[j >> 2][j & 3];
-        else if (C == 3) v = G.w2[2 + (j >> 2)][j & 3];
-        else v = S.acc15[wave][j * 64 + lane];
-        S.u.red[wave][j][lane] = v;
+        for (int j = 0; j < 8; ++j) {
+            floatx4 v;
+            if (C == 0) v = G.w4[j >> 2][j & 3];
+            else if (C == 1) v = G.w4[2 + (j >> 2)][j & 3];
+            else if (C == 2) v = G.w2[j >> 2][j & 3];
+            else v = G.w2[2 + (j >> 2)][j & 3];
+            S.u.red[wave][j][lane] = v;
+        }
+        __syncthreads();
     }
-    __syncthreads();
+    // wave w's entry (block j, lane ln) of this chunk
+    auto part = [&](int w, int j, int ln) -> floatx4 {
+        return C < 4 ? S.u.red[w][j][ln] : S.acc15[w][j * 64 + ln];
+    };
     for (int idx = threadIdx.x; idx < 8 * 64; idx += kWG) {
         const int j = idx >> 6, ln = idx & 63;
-        floatx4 v = S.u.red[0][j][ln];
+        floatx4 v = part(0, j, ln);
 #pragma unroll
         for (int w = 1; w < kWaves; ++w) {
-            const floatx4 x = S.u.red[w][j][ln];
+            const floatx4 x = part(w, j, ln);
 #pragma unroll
             for (int r = 0; r < 4; ++r) v[r] += x[r];
         }
@@ -1138,7 +1145,7 @@ __device__ __forceinline__ void store_record_chunk(BwdLds &S, const WGrad &G, fl
                 for (int q = 1; q < 4; ++q)
 #pragma unroll
                     for (int w = 0; w < kWaves; ++w) {
-                        const floatx4 x = S.u.red[w][j][ln + 16 * q];
+                        const floatx4 x = part(w, j, ln + 16 * q);
 #pragma unroll
                         for (int r = 0; r < 4; ++r) v[r] += x[r];
                     }
