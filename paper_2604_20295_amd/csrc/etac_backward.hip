@@ -163,6 +163,8 @@ struct BwdLds {
     float dgp[64], dpre3[64], dg[64];
     float vroute[64];             // dL/dpre2 routed to the arg-max node of channel c: dg[c] [g[c] > 0]
     float vred[kWaves][64];
+    float vred2[kWaves][64];      // second partial-sum buffer of the global-MLP adjoint
+    float vrw[kWaves][64];        // each wave's copy of vroute for its routing pass
     int ired[kWaves][64];
     int argmax[64];
     float dxs[64][3];             // dL/du_hat of the routed arg-max node of each channel
@@ -759,7 +761,8 @@ __device__ __forceinline__ void route_inputs(const BwdParams &p, const BwdLds &S
 __device__ void routing_tile(const BwdParams &p, BwdLds &S, WGrad &G, int n, const RouteIn &in) {
     const NetLds &L = S.net;
     const int lane = lane_id(), wave = threadIdx.x >> 6, gq = lane >> 4, col = lane & 15;
-    const int drt = uniform(range_exp(wave_max(fabsf(S.vroute[lane])) * S.net.mw2));   // same in every wave
+    const float *vroute = S.vrw[wave];   // this wave's copy (identical in every wave)
+    const int drt = uniform(range_exp(wave_max(fabsf(vroute[lane])) * S.net.mw2));   // same in every wave
     const float drt_mul = uniform(pow2(drt)), post = uniform(pow2(uniform(S.bsc.d1) - drt));
     const float d2mul = uniform(pow2(uniform(S.bsc.d2)));
     // T form: channel 16 wave + col; N form: channels 16 wave + 4 gq + r
@@ -770,7 +773,7 @@ __device__ void routing_tile(const BwdParams &p, BwdLds &S, WGrad &G, int n, con
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int c = 16 * wave + 4 * gq + r;
-        vn[r] = S.argmax[c] < n ? S.vroute[c] : 0.0f;
+        vn[r] = S.argmax[c] < n ? vroute[c] : 0.0f;
     }
     half8 xh, xl;
     {
@@ -783,7 +786,7 @@ __device__ void routing_tile(const BwdParams &p, BwdLds &S, WGrad &G, int n, con
     layer1_dual(L, xh, xl, h1T, h1N);
     // dL/dpre2 is one-hot, vroute[c] e_c, so dL/dh1 = W2^T dpre2 is row c of
     // W2 scaled by vroute[c], in both forms
-    const float vt = vT ? S.vroute[cT] : 0.0f;
+    const float vt = vT ? vroute[cT] : 0.0f;
     const float *w2 = p.model.phi + kW2;
     floatx4 dh1T[4], dh1N[4];
 #pragma unroll
@@ -1339,43 +1342,51 @@ __device__ void residual_adjoint(const BwdParams &p, BwdLds &S, int e, int k, in
         S.vred[wave][ob * 16 + (lane & 15)] = v;     // identical in the 4 lane groups
     }
     __syncthreads();
-    if (threadIdx.x < 64) {
-        float t = S.vred[0][threadIdx.x];
-        for (int w = 1; w < kWaves; ++w) t += S.vred[w][threadIdx.x];
-        S.s4[threadIdx.x] = t * pow2(-S.bsc.d4);     // unscaled from here on
-    }
-    __syncthreads();
     {
-        // each wave sums 16 of the 64 terms, the partials are added in wave order
-        const int c = lane;
+        // Each wave sums 16 of the 64 terms of a product, the partials are
+        // added in wave order.  A wave forms the sums its own next product
+        // needs (its 16 rows; all 64 for the routing pass) from the four
+        // partials itself, so only the partials cross waves: one barrier per
+        // product, with two partial buffers in turn.
+        const int c = lane, o = 16 * wave + (lane & 15);   // o: identical in the 4 lane groups
+        {
+            float t = S.vred[0][o];
+            for (int w = 1; w < kWaves; ++w) t += S.vred[w][o];
+            S.s4[o] = t * pow2(-S.bsc.d4);     // unscaled from here on
+        }
+        wave_sync();
         float s = 0.0f;
 #pragma unroll
         for (int q = 0; q < 16; ++q) s += w4g[q] * S.s4[16 * wave + q];
-        S.vred[wave][c] = s;
+        S.vred2[wave][c] = s;
         float w3r[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) w3r[q] = phi[kW3 + (16 * wave + q) * 64 + c];
         __syncthreads();
-        if (threadIdx.x < 64) {
-            float t = S.vred[0][c];
-            for (int w = 1; w < kWaves; ++w) t += S.vred[w][c];
-            S.dgp[c] = t;
-            S.dpre3[c] = L.gp[c] > 0.0f ? t : 0.0f;
+        {
+            float t = S.vred2[0][o];
+            for (int w = 1; w < kWaves; ++w) t += S.vred2[w][o];
+            S.dgp[o] = t;
+            S.dpre3[o] = L.gp[o] > 0.0f ? t : 0.0f;
         }
-        __syncthreads();
+        wave_sync();
         s = 0.0f;
 #pragma unroll
         for (int q = 0; q < 16; ++q) s += w3r[q] * S.dpre3[16 * wave + q];
-        S.vred[wave][c] = s;
+        S.vred[wave][c] = s;     // every wave read vred before the barrier above
         __syncthreads();
-        if (threadIdx.x < 64) {
+        {
             float t = S.vred[0][c];
             for (int w = 1; w < kWaves; ++w) t += S.vred[w][c];
-            S.dg[c] = t;
             // f = relu(pre2) >= 0 and f at the arg-max node is g, so its gate is g > 0
-            S.vroute[c] = L.g[c] > 0.0f ? t : 0.0f;
+            const float vr = L.g[c] > 0.0f ? t : 0.0f;
+            S.vrw[wave][c] = vr;
+            if (wave == 0) {
+                S.dg[c] = t;
+                S.vroute[c] = vr;
+            }
         }
-        __syncthreads();
+        wave_sync();
     }
 
     // (d) max-pool routing: wave w takes channels 16 w .. 16 w + 15
